@@ -1,0 +1,174 @@
+/*
+ * dwfmm.h -- C ABI of the MI355X dimension weighted FMM library (libdwfmm.so).
+ *
+ * The library computes y = K~ x, the fast multipole approximation of a kernel
+ * matrix K = [K(x_i, x_j)] over N data sites in d dimensions, and solves
+ * (K~ + lambda I) alpha = f with conjugate gradients (Harbrecht, Multerer,
+ * Quizi, arXiv 2402.09531: Sec 2 eqs. (LGS0)/(LGS) for the systems, Sec 5 for
+ * the method).  Everything after setup runs in HIP kernels on a gfx950 GPU.
+ *
+ * Conventions for every entry point
+ *   - Array arguments are DEVICE pointers unless marked "host".
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Point and vector arrays are in the caller's original point order;
+ *     x, y, f, alpha are N x nrhs row-major FP64.
+ *   - Every call returns a dwfmm_status; no exception crosses the ABI and the
+ *     library never aborts.  dwfmm_last_error() gives a message for the last
+ *     non-OK status of the calling thread.
+ *   - Objects are not thread-safe; distinct objects may be used concurrently.
+ *   - The library owns all memory of a tree or operator: it is allocated in
+ *     dwfmm_build_tree / dwfmm_fmm_create and freed by the destroy calls.
+ *     dwfmm_fmm_matvec and dwfmm_fmm_solve allocate nothing.
+ */
+#ifndef DWFMM_H
+#define DWFMM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    DWFMM_OK = 0,
+    DWFMM_E_INVALID = 1,        /* argument out of range */
+    DWFMM_E_NONFINITE = 2,      /* NaN or Inf in points or weights */
+    DWFMM_E_NOMEM = 3,          /* device or host allocation failed */
+    DWFMM_E_HIP = 4,            /* a HIP runtime call failed */
+    DWFMM_E_NOT_CONVERGED = 5,  /* solve hit max_iter (info still filled) */
+    DWFMM_E_BREAKDOWN = 6       /* CG breakdown: |p^T A p| <= 1e-300 or non-finite */
+} dwfmm_status;
+
+/* Kernel functions K(x,y) with r = |x - y|_2:
+ *   MATERN32     (1 + sqrt(3) r/ell) exp(-sqrt(3) r/ell)
+ *   GAUSSIAN     exp(-r^2/ell)
+ *   EXPONENTIAL  exp(-r/ell)           (the Sec 6.2 kernel, with the sign read as decaying)
+ *   POLY_TEST    1 + sum_{k < (int)ell} x_k y_k + (x_0 y_0)^2  (exactness tests only)  */
+typedef enum { DWFMM_MATERN32 = 0, DWFMM_GAUSSIAN = 1, DWFMM_EXPONENTIAL = 2, DWFMM_POLY_TEST = 3 } dwfmm_kernel_kind;
+
+typedef struct {
+    int32_t kind;   /* dwfmm_kernel_kind */
+    double ell;     /* length scale (> 0) */
+} dwfmm_kernel;
+
+/* Dimension weights omega_k of the index set (Sec 4; Thm 4.6; Sec 6.2), computed
+ * from the box side lengths b_k given to dwfmm_build_tree:
+ *   R1 (default)  omega_k = max(1, log2(b_max / b_k))
+ *   R2            omega_k = 1 + log2(b_max / b_k)
+ *   R3            Sec 6.2: tau_k = 1/(eta b_k), rho_k = e g(tau_k)/g(tau_1),
+ *                 g(t) = 2t + sqrt(1+4t^2), omega_k = log rho_k
+ *   EXPLICIT      omega taken from dwfmm_opts.omega (host, length d, > 0)     */
+typedef enum { DWFMM_W_R1 = 0, DWFMM_W_R2 = 1, DWFMM_W_R3 = 2, DWFMM_W_EXPLICIT = 3 } dwfmm_weight_rule;
+
+/* Arithmetic of the coupling (M2L) and nearfield (P2P) stages.  Geometry,
+ * moments, transfers, CG inner products and residuals are always FP64.   */
+typedef enum { DWFMM_FP64 = 0, DWFMM_FP32 = 1, DWFMM_BF16 = 2 } dwfmm_precision;
+
+typedef struct {
+    int32_t weight_rule;     /* dwfmm_weight_rule, default R1 */
+    const double *omega;     /* host, length d, only for DWFMM_W_EXPLICIT */
+    int32_t precision;       /* dwfmm_precision of the inner matvec, default FP64 */
+    int32_t max_nrhs;        /* largest nrhs a matvec/solve may use (1..32), default 1 */
+    int32_t check_every;     /* CG iterations between host convergence checks, default 1 */
+    double ir_inner_rtol;    /* reduced precision: inner CG tolerance (0 = 1e-4 FP32, 1e-2 BF16) */
+    int32_t ir_max_outer;    /* reduced precision: max refinement steps, default 30 */
+} dwfmm_opts;
+
+/* Per right-hand-side result of dwfmm_fmm_solve. */
+typedef struct {
+    int32_t iters;               /* CG iterations (matvecs) taken, summed over refinement steps */
+    int32_t neg_curvature_steps; /* steps with p^T A p < 0 (taken, counted) */
+    int32_t refine_steps;        /* outer refinement steps (0 in FP64 mode) */
+    int32_t status;              /* DWFMM_OK, DWFMM_E_NOT_CONVERGED or DWFMM_E_BREAKDOWN */
+    double rel_res_recursive;    /* |r_k| / |f| from the CG recurrence */
+    double rel_res_true;         /* |f - (K~ + lambda I) alpha| / |f|, one extra FP64 matvec */
+} dwfmm_solve_info;
+
+typedef struct dwfmm_tree_s *dwfmm_tree;
+typedef struct dwfmm_op_s *dwfmm_op;
+
+/* Cluster tree and block partition (Sec 5.1, Def 5.1/5.2; Sec 5.2 eq. (admissibility)).
+ *   points       device, N x d row-major FP64, original order (copied; may be freed on return)
+ *   n, d         N >= 1, 1 <= d <= 64
+ *   dim_weights  host, length d, b_k > 0 (side lengths of the anisotropic box, Sec 2)
+ *   leaf_size    >= 1; depth J = min{j : ceil(N/2^j) <= leaf_size}
+ *   eta          > 0, admissibility dist(B,B') >= eta max(diam B, diam B')
+ * Splits every cluster above depth J along the longest edge of its tight box at
+ * the median (left child takes ceil(n/2); ties by original index).  Farfield =
+ * admissible blocks whose parent block is not; nearfield = remaining leaf blocks.
+ * Synchronises `stream`.  Errors: E_INVALID, E_NONFINITE, E_NOMEM, E_HIP.      */
+dwfmm_status dwfmm_build_tree(const double *points, int64_t n, int32_t d, const double *dim_weights,
+                              int32_t leaf_size, double eta, void *stream, dwfmm_tree *out);
+
+/* FMM operator for a tree (Sec 4 index set; Sec 5.2 interpolation, cluster bases,
+ * transfer matrices).  q >= 0 is the weighted total degree.  opts may be NULL.
+ * Builds Lambda, per-axis Leja-ordered Chebyshev nodes, V^-1, the transfer
+ * matrices of every cluster and the interpolation nodes of every box, and
+ * allocates the workspace for opts->max_nrhs right-hand sides.  The operator
+ * keeps a reference on the tree.  Synchronises `stream`.
+ * Errors: E_INVALID (bad kernel, q, opts), E_NOMEM, E_HIP.                       */
+dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, double q, const dwfmm_opts *opts,
+                              void *stream, dwfmm_op *out);
+
+/* y = K~ x (Sec 5.2 eq. (LowRankBlock) on the farfield, kernel entries on the
+ * nearfield), in the operator's precision.  x, y: device N x nrhs, distinct.
+ * 1 <= nrhs <= max_nrhs.  Asynchronous on `stream`; allocates nothing.
+ * Errors: E_INVALID, E_HIP.                                                     */
+dwfmm_status dwfmm_fmm_matvec(dwfmm_op op, const double *x, double *y, int32_t nrhs, void *stream);
+
+/* Same as dwfmm_fmm_matvec restricted to parts of the operator (bit 0 nearfield,
+ * bit 1 farfield), and with an explicit precision (dwfmm_precision), for
+ * stage-by-stage checks.                                                        */
+dwfmm_status dwfmm_fmm_matvec_parts(dwfmm_op op, const double *x, double *y, int32_t nrhs, int32_t parts,
+                                    int32_t precision, void *stream);
+
+/* Solve (K~ + lambda I) alpha = f by conjugate gradients (eq. (LGS)), one
+ * independent iteration per column.  alpha is the start vector on entry and
+ * the solution on return.  Stops a column when |r| <= rtol |f| (recursive
+ * residual), checked every opts.check_every iterations.  Steps with
+ * p^T A p < 0 are taken and counted.  In FP32/BF16 operator precision the
+ * solve is iterative refinement: an FP64 residual f - (K~ + lambda I) alpha,
+ * an inner CG in reduced precision, alpha += delta.  info: host, nrhs entries.
+ * Synchronises `stream`.  Returns the worst per-column status.
+ * Errors: E_INVALID, E_HIP, E_NOT_CONVERGED, E_BREAKDOWN.                       */
+dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double *f, double *alpha, int32_t nrhs,
+                             double rtol, int32_t max_iter, void *stream, dwfmm_solve_info *info);
+
+/* Device bytes an operator would hold for the given sizes (admission control). */
+size_t dwfmm_estimate_bytes(int64_t n, int32_t d, int32_t leaf_size, int32_t n_x, int32_t nrhs);
+/* Device bytes held by a tree plus operator. */
+size_t dwfmm_op_bytes(dwfmm_op op);
+
+void dwfmm_op_destroy(dwfmm_op op);
+/* Destroying a tree that an operator still references is deferred until that operator is destroyed. */
+void dwfmm_tree_destroy(dwfmm_tree tree);
+
+/* Message for the last non-OK status returned on the calling thread. */
+const char *dwfmm_last_error(void);
+
+/* ---- introspection (host copies; for tests and statistics) ---------------- */
+/* out[0..7] = n, d, J, ncl (clusters), nF (farfield blocks), nN (nearfield blocks), nleaf, leaf_size */
+dwfmm_status dwfmm_tree_info(dwfmm_tree tree, int64_t *out);
+/* Tree order and boxes: perm[n] (tree position -> original index), begin/end[ncl],
+ * lo/hi[ncl*d]; farfield CSR by target cluster Fptr[ncl+1], Fsrc[nF]; nearfield
+ * CSR by target cluster Nptr[ncl+1], Nsrc[nN].  Any pointer may be NULL.      */
+dwfmm_status dwfmm_tree_get(dwfmm_tree tree, int64_t *perm, int64_t *begin, int64_t *end, double *lo, double *hi,
+                            int64_t *Fptr, int64_t *Fsrc, int64_t *Nptr, int64_t *Nsrc);
+/* out[0..3] = n_x, max_nrhs, precision, bytes */
+dwfmm_status dwfmm_op_info(dwfmm_op op, int64_t *out);
+/* Index set alpha[n_x*d] (uint8), reference nodes xi[n_x*d], Vinv[n_x*n_x], omega[d]. */
+dwfmm_status dwfmm_op_basis(dwfmm_op op, uint8_t *alpha, double *xi, double *Vinv, double *omega);
+/* Kernel timing for measurement: while enabled, each matvec records HIP events
+ * on its stream around the nearfield (P2P) and coupling (M2L) launches.  out
+ * (host, 3 doubles, may be NULL) receives the summed P2P ms, summed M2L ms and
+ * the number of timed matvecs since the last call; the call then resets the
+ * count and sets timing on (enable != 0) or off.  Waits for the recorded events. */
+dwfmm_status dwfmm_op_timing(dwfmm_op op, int32_t enable, double *out);
+/* Lagrange moments and locals of the last matvec, host [ncl][n_x][nrhs]. */
+dwfmm_status dwfmm_op_moments(dwfmm_op op, double *moments, double *locals, int32_t nrhs);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

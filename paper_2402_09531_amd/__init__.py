@@ -1,0 +1,262 @@
+"""MI355X dimension weighted FMM (arXiv 2402.09531): Python binding of libdwfmm.so.
+
+Thin ctypes marshalling over the C ABI in ``include/dwfmm.h``; every step of the
+matvec and the solve runs in the library's HIP kernels.  Tensors passed in must
+be contiguous float64 CUDA (HIP) tensors; streams come from
+``torch.cuda.current_stream()``.  There is no CPU fallback: if the library is
+not built, loading raises.
+
+    tree = build_tree(points, dim_weights, leaf_size, eta)
+    op   = fmm_create(tree, "matern32", ell, q)
+    fmm_matvec(op, x, y)
+    info = fmm_solve(op, lam, f, alpha, rtol, max_iter)
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libdwfmm.so")
+
+OK, E_INVALID, E_NONFINITE, E_NOMEM, E_HIP, E_NOT_CONVERGED, E_BREAKDOWN = range(7)
+STATUS_NAMES = {0: "OK", 1: "E_INVALID", 2: "E_NONFINITE", 3: "E_NOMEM", 4: "E_HIP",
+                5: "E_NOT_CONVERGED", 6: "E_BREAKDOWN"}
+KERNELS = {"matern32": 0, "gaussian": 1, "exponential": 2, "poly": 3}
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+WEIGHT_RULES = {"R1": 0, "R2": 1, "R3": 2, "explicit": 3}
+
+
+class DwfmmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+class _Kernel(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("ell", C.c_double)]
+
+
+class _Opts(C.Structure):
+    _fields_ = [("weight_rule", C.c_int32), ("omega", C.POINTER(C.c_double)), ("precision", C.c_int32),
+                ("max_nrhs", C.c_int32), ("check_every", C.c_int32), ("ir_inner_rtol", C.c_double),
+                ("ir_max_outer", C.c_int32)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("neg_curvature_steps", C.c_int32), ("refine_steps", C.c_int32),
+                ("status", C.c_int32), ("rel_res_recursive", C.c_double), ("rel_res_true", C.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+EXPORTS = ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
+           "dwfmm_fmm_solve", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
+           "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info",
+           "dwfmm_op_basis", "dwfmm_op_moments", "dwfmm_op_timing"]
+
+
+def lib():
+    """Load libdwfmm.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with paper_2402_09531_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
+        L.dwfmm_build_tree.argtypes = [vp, C.c_int64, C.c_int32, dp, C.c_int32, C.c_double, vp, C.POINTER(vp)]
+        L.dwfmm_fmm_create.argtypes = [vp, _Kernel, C.c_double, C.POINTER(_Opts), vp, C.POINTER(vp)]
+        L.dwfmm_fmm_matvec.argtypes = [vp, vp, vp, C.c_int32, vp]
+        L.dwfmm_fmm_matvec_parts.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp]
+        L.dwfmm_fmm_solve.argtypes = [vp, C.c_double, vp, vp, C.c_int32, C.c_double, C.c_int32, vp,
+                                      C.POINTER(SolveInfo)]
+        L.dwfmm_estimate_bytes.argtypes = [C.c_int64, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+        L.dwfmm_estimate_bytes.restype = C.c_size_t
+        L.dwfmm_op_bytes.argtypes = [vp]
+        L.dwfmm_op_bytes.restype = C.c_size_t
+        L.dwfmm_op_destroy.argtypes = [vp]
+        L.dwfmm_op_destroy.restype = None
+        L.dwfmm_tree_destroy.argtypes = [vp]
+        L.dwfmm_tree_destroy.restype = None
+        L.dwfmm_last_error.restype = C.c_char_p
+        L.dwfmm_tree_info.argtypes = [vp, i64p]
+        L.dwfmm_tree_get.argtypes = [vp, i64p, i64p, i64p, dp, dp, i64p, i64p, i64p, i64p]
+        L.dwfmm_op_info.argtypes = [vp, i64p]
+        L.dwfmm_op_basis.argtypes = [vp, C.POINTER(C.c_uint8), dp, dp, dp]
+        L.dwfmm_op_moments.argtypes = [vp, dp, dp, C.c_int32]
+        L.dwfmm_op_timing.argtypes = [vp, C.c_int32, dp]
+        for name in ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
+                     "dwfmm_fmm_solve", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info", "dwfmm_op_basis",
+                     "dwfmm_op_moments", "dwfmm_op_timing"]:
+            getattr(L, name).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != OK:
+        raise DwfmmError(status, lib().dwfmm_last_error().decode())
+
+
+def _stream(stream):
+    import torch
+    s = torch.cuda.current_stream() if stream is None else stream
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev_f64(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float64 GPU tensor")
+    return C.c_void_p(t.data_ptr())
+
+
+def _i64(a):
+    return a.ctypes.data_as(C.POINTER(C.c_int64)) if a is not None else None
+
+
+def _f64p(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double)) if a is not None else None
+
+
+class Tree:
+    """Handle of a dwfmm_tree (cluster tree and block partition)."""
+
+    def __init__(self, handle):
+        self._h = handle
+        info = np.zeros(8, dtype=np.int64)
+        _check(lib().dwfmm_tree_info(self._h, _i64(info)))
+        self.n, self.d, self.J, self.ncl, self.nF, self.nN, self.nleaf, self.leaf = (int(v) for v in info)
+
+    def host(self):
+        """Tree order, boxes and block lists as NumPy arrays."""
+        perm = np.zeros(self.n, np.int64)
+        b = np.zeros(self.ncl, np.int64)
+        e = np.zeros(self.ncl, np.int64)
+        lo = np.zeros((self.ncl, self.d))
+        hi = np.zeros((self.ncl, self.d))
+        Fp = np.zeros(self.ncl + 1, np.int64)
+        Fs = np.zeros(max(self.nF, 1), np.int64)
+        Np = np.zeros(self.ncl + 1, np.int64)
+        Ns = np.zeros(max(self.nN, 1), np.int64)
+        _check(lib().dwfmm_tree_get(self._h, _i64(perm), _i64(b), _i64(e), _f64p(lo), _f64p(hi), _i64(Fp),
+                                    _i64(Fs), _i64(Np), _i64(Ns)))
+        return dict(perm=perm, begin=b, end=e, lo=lo, hi=hi, Fptr=Fp, Fsrc=Fs[:self.nF], Nptr=Np,
+                    Nsrc=Ns[:self.nN])
+
+    def near_entries(self) -> float:
+        """E_N = sum over nearfield blocks |nu||nu'|."""
+        h = self.host()
+        sz = h["end"] - h["begin"]
+        tgt = np.repeat(np.arange(self.ncl), np.diff(h["Nptr"]))
+        return float((sz[tgt] * sz[h["Nsrc"]]).sum())
+
+    def close(self):
+        if self._h:
+            lib().dwfmm_tree_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Op:
+    """Handle of a dwfmm_op (FMM operator)."""
+
+    def __init__(self, handle, tree: Tree):
+        self._h = handle
+        self.tree = tree
+        info = np.zeros(4, dtype=np.int64)
+        _check(lib().dwfmm_op_info(self._h, _i64(info)))
+        self.nx, self.max_nrhs, self.precision, self.bytes = (int(v) for v in info)
+
+    def basis(self):
+        d = self.tree.d
+        alpha = np.zeros((self.nx, d), np.uint8)
+        xi = np.zeros((self.nx, d))
+        Vinv = np.zeros((self.nx, self.nx))
+        om = np.zeros(d)
+        _check(lib().dwfmm_op_basis(self._h, alpha.ctypes.data_as(C.POINTER(C.c_uint8)), _f64p(xi), _f64p(Vinv),
+                                    _f64p(om)))
+        return dict(alpha=alpha, xi=xi, Vinv=Vinv, omega=om)
+
+    def moments(self, nrhs: int = 1):
+        m = np.zeros((self.tree.ncl, self.nx, nrhs))
+        l = np.zeros_like(m)
+        _check(lib().dwfmm_op_moments(self._h, _f64p(m), _f64p(l), nrhs))
+        return m, l
+
+    def timing(self, enable: bool):
+        """Read (p2p_ms_total, m2l_ms_total, n_timed) since the last call, then set timing on/off."""
+        out = np.zeros(3)
+        _check(lib().dwfmm_op_timing(self._h, int(enable), _f64p(out)))
+        return float(out[0]), float(out[1]), int(out[2])
+
+    def close(self):
+        if self._h:
+            lib().dwfmm_op_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build_tree(points, dim_weights, leaf_size: int, eta: float, stream=None) -> Tree:
+    """dwfmm_build_tree: points is an N x d float64 GPU tensor, dim_weights host values b_k."""
+    n, d = points.shape
+    b = np.ascontiguousarray(dim_weights, dtype=np.float64)
+    h = C.c_void_p()
+    _check(lib().dwfmm_build_tree(_dev_f64(points, "points"), n, d, _f64p(b), int(leaf_size), float(eta),
+                                  _stream(stream), C.byref(h)))
+    return Tree(h)
+
+
+def fmm_create(tree: Tree, kernel: str, ell: float, q: float, precision: str = "fp64", max_nrhs: int = 1,
+               weight_rule: str = "R1", omega=None, check_every: int = 1, ir_inner_rtol: float = 0.0,
+               ir_max_outer: int = 30, stream=None) -> Op:
+    """dwfmm_fmm_create."""
+    om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
+    opts = _Opts(WEIGHT_RULES[weight_rule], _f64p(om), PRECISIONS[precision], int(max_nrhs), int(check_every),
+                 float(ir_inner_rtol), int(ir_max_outer))
+    h = C.c_void_p()
+    _check(lib().dwfmm_fmm_create(tree._h, _Kernel(KERNELS[kernel], float(ell)), float(q), C.byref(opts),
+                                  _stream(stream), C.byref(h)))
+    return Op(h, tree)
+
+
+def fmm_matvec(op: Op, x, y, stream=None, parts: int | None = None, precision: str | None = None):
+    """dwfmm_fmm_matvec (or dwfmm_fmm_matvec_parts when parts/precision are given): y = K~ x."""
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    if parts is None and precision is None:
+        _check(lib().dwfmm_fmm_matvec(op._h, _dev_f64(x, "x"), _dev_f64(y, "y"), nrhs, _stream(stream)))
+    else:
+        prec = op.precision if precision is None else PRECISIONS[precision]
+        _check(lib().dwfmm_fmm_matvec_parts(op._h, _dev_f64(x, "x"), _dev_f64(y, "y"), nrhs,
+                                            3 if parts is None else int(parts), prec, _stream(stream)))
+
+
+def fmm_solve(op: Op, lam: float, f, alpha, rtol: float, max_iter: int = 10000, stream=None,
+              raise_on_error: bool = False):
+    """dwfmm_fmm_solve: (K~ + lam I) alpha = f; alpha holds the start vector.  Returns per-column info dicts."""
+    nrhs = 1 if f.dim() == 1 else f.shape[1]
+    infos = (SolveInfo * nrhs)()
+    st = lib().dwfmm_fmm_solve(op._h, float(lam), _dev_f64(f, "f"), _dev_f64(alpha, "alpha"), nrhs, float(rtol),
+                               int(max_iter), _stream(stream), infos)
+    if st not in (OK, E_NOT_CONVERGED, E_BREAKDOWN) or (raise_on_error and st != OK):
+        _check(st)
+    return [i.as_dict() for i in infos]
+
+
+def estimate_bytes(n: int, d: int, leaf_size: int, n_x: int, nrhs: int) -> int:
+    return int(lib().dwfmm_estimate_bytes(n, d, leaf_size, n_x, nrhs))

@@ -1,0 +1,703 @@
+// C ABI of libdwfmm.so (declared in include/dwfmm.h): object lifetime, uploads,
+// argument checks, and the conjugate gradient driver (Sec 2, eq. (LGS)).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dwfmm.h"
+#include "device.hpp"
+#include "setup.hpp"
+
+using namespace dwfmm;
+
+namespace {
+
+thread_local std::string g_err;
+
+dwfmm_status fail(dwfmm_status s, const std::string &msg)
+{
+    g_err = msg;
+    return s;
+}
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t bytes = 0;
+};
+
+// All device allocations of an object, freed together.
+struct Arena {
+    std::vector<DevBuf> bufs;
+    size_t total = 0;
+    hipError_t alloc(void **out, size_t bytes)
+    {
+        void *p = nullptr;
+        hipError_t e = hipMalloc(&p, std::max<size_t>(bytes, 256));
+        if (e != hipSuccess) return e;
+        bufs.push_back({p, bytes});
+        total += bytes;
+        *out = p;
+        return hipSuccess;
+    }
+    template <class T>
+    hipError_t upload(T **out, const std::vector<T> &v, hipStream_t st)
+    {
+        hipError_t e = alloc((void **)out, v.size() * sizeof(T));
+        if (e != hipSuccess) return e;
+        if (!v.empty()) e = hipMemcpyAsync(*out, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, st);
+        return e;
+    }
+    void release()
+    {
+        for (auto &b : bufs) (void)hipFree(b.p);
+        bufs.clear();
+        total = 0;
+    }
+};
+
+#define HIP_TRY(expr)                                                                             \
+    do {                                                                                          \
+        hipError_t _e = (expr);                                                                   \
+        if (_e != hipSuccess) {                                                                   \
+            return fail(_e == hipErrorOutOfMemory ? DWFMM_E_NOMEM : DWFMM_E_HIP,                  \
+                        std::string(#expr) + ": " + hipGetErrorString(_e));                       \
+        }                                                                                         \
+    } while (0)
+
+int pad_dim(int d) { return d <= 24 ? (d + 1) / 2 * 2 : (d + 7) / 8 * 8; }
+
+}  // namespace
+
+struct dwfmm_tree_s {
+    HostTree H;
+    DevTree D{};
+    Arena arena;
+    double *clo = nullptr, *csc = nullptr, *coff = nullptr;  // [ncl][d] reference-coordinate maps
+    int refs = 1;       // the caller's reference plus one per operator
+    bool destroyed = false;
+    int device = 0;
+};
+
+struct dwfmm_op_s {
+    dwfmm_tree tree = nullptr;
+    HostBasis B;
+    DevOp D{};
+    Arena arena;
+    int precision = 0, max_nrhs = 1, check_every = 1, ir_max_outer = 30;
+    double ir_inner_rtol = 0.0;
+    // CG workspace
+    double *r = nullptr, *p = nullptr, *q = nullptr, *partial = nullptr, *scal = nullptr;
+    int32_t *state = nullptr;
+    // kernel timing: one event pair per timed matvec, summed when read
+    bool timing = false;
+    std::vector<KernelTimer> timers;
+    size_t timers_used = 0;
+    ~dwfmm_op_s()
+    {
+        for (auto &t : timers) {
+            (void)hipEventDestroy(t.p2p_start);
+            (void)hipEventDestroy(t.p2p_stop);
+            (void)hipEventDestroy(t.m2l_start);
+            (void)hipEventDestroy(t.m2l_stop);
+        }
+    }
+};
+
+static void tree_release(dwfmm_tree t)
+{
+    if (--t->refs == 0) {
+        t->arena.release();
+        delete t;
+    }
+}
+
+// ============================================================== build_tree
+extern "C" dwfmm_status dwfmm_build_tree(const double *points, int64_t n, int32_t d, const double *dim_weights,
+                                         int32_t leaf_size, double eta, void *stream, dwfmm_tree *out)
+{
+    if (!out) return fail(DWFMM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!points || !dim_weights) return fail(DWFMM_E_INVALID, "points or dim_weights is NULL");
+    if (n < 1 || n > (int64_t)1 << 30) return fail(DWFMM_E_INVALID, "n must be in [1, 2^30]");
+    if (d < 1 || d > kMaxDim) return fail(DWFMM_E_INVALID, "d must be in [1, 64]");
+    if (leaf_size < 1 || leaf_size > 1024) return fail(DWFMM_E_INVALID, "leaf_size must be in [1, 1024]");
+    if (!(eta > 0.0) || !std::isfinite(eta)) return fail(DWFMM_E_INVALID, "eta must be finite and > 0");
+    for (int k = 0; k < d; ++k) {
+        if (!std::isfinite(dim_weights[k])) return fail(DWFMM_E_NONFINITE, "dim_weights not finite");
+        if (!(dim_weights[k] > 0.0)) return fail(DWFMM_E_INVALID, "dim_weights must be > 0");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> pts((size_t)n * d);
+    HIP_TRY(hipMemcpyAsync(pts.data(), points, pts.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (double v : pts)
+        if (!std::isfinite(v)) return fail(DWFMM_E_NONFINITE, "points contain NaN or Inf");
+
+    dwfmm_tree t = new (std::nothrow) dwfmm_tree_s();
+    if (!t) return fail(DWFMM_E_NOMEM, "host allocation failed");
+    std::string err;
+    if (!build_tree(pts.data(), n, d, dim_weights, leaf_size, eta, t->H, err)) {
+        delete t;
+        return fail(DWFMM_E_INVALID, err);
+    }
+    (void)hipGetDevice(&t->device);
+    const HostTree &H = t->H;
+    const int dp = pad_dim(d);
+    // SoA coordinates in tree order, zero rows up to dpad
+    std::vector<double> Xs((size_t)dp * n, 0.0);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < d; ++k) Xs[(size_t)k * n + i] = pts[(size_t)H.perm[i] * d + k];
+    // reference-coordinate maps t = (x - lo) * sc + off (degenerate axes -> 1/2)
+    std::vector<double> clo(H.lo), csc((size_t)H.ncl * d), coff((size_t)H.ncl * d);
+    for (size_t i = 0; i < csc.size(); ++i) {
+        double w = H.hi[i] - H.lo[i];
+        csc[i] = w > 0 ? 1.0 / w : 0.0;
+        coff[i] = w > 0 ? 0.0 : 0.5;
+    }
+    std::vector<int32_t> nsrc_local(H.Nsrc.size()), nptr_leaf(H.nleaf + 1);
+    const int32_t lf = (int32_t)(H.nleaf - 1);
+    for (size_t i = 0; i < H.Nsrc.size(); ++i) nsrc_local[i] = H.Nsrc[i] - lf;
+    for (int64_t l = 0; l <= H.nleaf; ++l) nptr_leaf[l] = H.Nptr[lf + l];
+    int max_leaf = 0;
+    for (int64_t l = 0; l < H.nleaf; ++l) max_leaf = std::max(max_leaf, H.end[lf + l] - H.begin[lf + l]);
+    // Symmetric nearfield: the self block is owned by its leaf; every other unordered pair
+    // {t, s} goes to whichever leaf owns fewer blocks so far (ties to the smaller index).
+    std::vector<std::pair<int32_t, int32_t>> owned;
+    std::vector<int32_t> own_cnt(H.nleaf, 0);
+    for (int32_t tl = 0; tl < (int32_t)H.nleaf; ++tl)
+        for (int32_t q = nptr_leaf[tl]; q < nptr_leaf[tl + 1]; ++q) {
+            const int32_t sl = nsrc_local[q];
+            if (sl < tl) continue;
+            int32_t o = tl, p = sl;
+            if (sl != tl && own_cnt[sl] < own_cnt[tl]) std::swap(o, p);
+            own_cnt[o]++;
+            owned.push_back({o, p});
+        }
+    std::sort(owned.begin(), owned.end());
+    std::vector<int32_t> own_ptr(H.nleaf + 1, 0), own_src(owned.size()), inc_ptr(H.nleaf + 1, 0), inc_blk;
+    for (auto &op : owned) own_ptr[op.first + 1]++;
+    for (int64_t l = 0; l < H.nleaf; ++l) own_ptr[l + 1] += own_ptr[l];
+    for (size_t b = 0; b < owned.size(); ++b) {
+        own_src[b] = owned[b].second;
+        if (owned[b].first != owned[b].second) inc_ptr[owned[b].second + 1]++;
+    }
+    for (int64_t l = 0; l < H.nleaf; ++l) inc_ptr[l + 1] += inc_ptr[l];
+    inc_blk.resize(inc_ptr[H.nleaf]);
+    {
+        std::vector<int32_t> fill(inc_ptr.begin(), inc_ptr.end() - 1);
+        for (size_t b = 0; b < owned.size(); ++b)
+            if (owned[b].first != owned[b].second) inc_blk[fill[owned[b].second]++] = (int32_t)b;
+    }
+    std::vector<double> center((size_t)H.nleaf * dp, 0.0);
+    for (int64_t l = 0; l < H.nleaf; ++l)
+        for (int k = 0; k < d; ++k)
+            center[(size_t)l * dp + k] = 0.5 * (H.lo[(size_t)(lf + l) * d + k] + H.hi[(size_t)(lf + l) * d + k]);
+
+    DevTree &D = t->D;
+    auto up = [&](auto **dst, const auto &v) { return t->arena.upload(dst, v, st); };
+    hipError_t e = hipSuccess;
+    double *dXs;
+    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs, *dop, *dos, *dip, *dib;
+    double *dcen;
+    if ((e = up(&dXs, Xs)) != hipSuccess || (e = up(&dperm, H.perm)) != hipSuccess ||
+        (e = up(&dcb, H.begin)) != hipSuccess || (e = up(&dce, H.end)) != hipSuccess ||
+        (e = up(&dFp, H.Fptr)) != hipSuccess || (e = up(&dFs, H.Fsrc)) != hipSuccess ||
+        (e = up(&dNp, nptr_leaf)) != hipSuccess || (e = up(&dNs, nsrc_local)) != hipSuccess ||
+        (e = up(&t->clo, clo)) != hipSuccess || (e = up(&t->csc, csc)) != hipSuccess ||
+        (e = up(&t->coff, coff)) != hipSuccess || (e = up(&dop, own_ptr)) != hipSuccess ||
+        (e = up(&dos, own_src)) != hipSuccess || (e = up(&dip, inc_ptr)) != hipSuccess ||
+        (e = up(&dib, inc_blk)) != hipSuccess || (e = up(&dcen, center)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        t->arena.release();
+        delete t;
+        return fail(e == hipErrorOutOfMemory ? DWFMM_E_NOMEM : DWFMM_E_HIP,
+                    std::string("tree upload: ") + hipGetErrorString(e));
+    }
+    D.n = (int)n;
+    D.d = d;
+    D.J = H.J;
+    D.dpad = dp;
+    D.nleaf = (int)H.nleaf;
+    D.ncl = (int)H.ncl;
+    D.leaf_first = lf;
+    D.max_leaf = max_leaf;
+    D.min_far_level = H.min_far_level;
+    D.Xs = dXs;
+    D.perm = dperm;
+    D.cbeg = dcb;
+    D.cend = dce;
+    D.Fptr = dFp;
+    D.Fsrc = dFs;
+    D.Nptr = dNp;
+    D.Nsrc = dNs;
+    D.nblk = (int)owned.size();
+    D.own_ptr = dop;
+    D.own_src = dos;
+    D.inc_ptr = dip;
+    D.inc_blk = dib;
+    D.center = dcen;
+    *out = t;
+    return DWFMM_OK;
+}
+
+extern "C" void dwfmm_tree_destroy(dwfmm_tree t)
+{
+    if (!t || t->destroyed) return;
+    t->destroyed = true;
+    tree_release(t);
+}
+
+// ============================================================== fmm_create
+extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, double q, const dwfmm_opts *opts,
+                                         void *stream, dwfmm_op *out)
+{
+    if (!out) return fail(DWFMM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!tree || tree->destroyed) return fail(DWFMM_E_INVALID, "tree is NULL or destroyed");
+    if (kernel.kind < 0 || kernel.kind > 3) return fail(DWFMM_E_INVALID, "unknown kernel kind");
+    if (!(kernel.ell > 0.0) || !std::isfinite(kernel.ell)) return fail(DWFMM_E_INVALID, "kernel ell must be > 0");
+    if (!(q >= 0.0) || !std::isfinite(q)) return fail(DWFMM_E_INVALID, "q must be finite and >= 0");
+    dwfmm_opts o{};
+    o.weight_rule = DWFMM_W_R1;
+    o.precision = DWFMM_FP64;
+    o.max_nrhs = 1;
+    o.check_every = 1;
+    o.ir_max_outer = 30;
+    if (opts) {
+        o = *opts;
+        if (o.max_nrhs == 0) o.max_nrhs = 1;
+        if (o.check_every == 0) o.check_every = 1;
+        if (o.ir_max_outer == 0) o.ir_max_outer = 30;
+    }
+    if (o.max_nrhs < 1 || o.max_nrhs > 32) return fail(DWFMM_E_INVALID, "max_nrhs must be in [1, 32]");
+    if (o.check_every < 1) return fail(DWFMM_E_INVALID, "check_every must be >= 1");
+    if (o.precision < 0 || o.precision > 2) return fail(DWFMM_E_INVALID, "unknown precision");
+    const HostTree &H = tree->H;
+    hipStream_t st = (hipStream_t)stream;
+
+    dwfmm_op op = new (std::nothrow) dwfmm_op_s();
+    if (!op) return fail(DWFMM_E_NOMEM, "host allocation failed");
+    std::string err;
+    std::vector<double> omega(H.d);
+    if (!compute_weights(o.weight_rule, H.d, H.b.data(), H.eta, o.omega, omega.data(), err) ||
+        !build_basis(H.d, omega.data(), q, op->B, err)) {
+        delete op;
+        return fail(DWFMM_E_INVALID, err);
+    }
+    const HostBasis &B = op->B;
+    const int nx = B.nx, dp = tree->D.dpad;
+    if (nx > 64 || nx * dp > 1536) {
+        delete op;
+        return fail(DWFMM_E_INVALID, "index set too large for the GPU kernels (n_x <= 64, n_x * d <= 1536)");
+    }
+    std::vector<double> nodes, nodes_p((size_t)H.ncl * nx * dp, 0.0), E;
+    box_nodes(H, B, nodes);
+    for (int64_t c = 0; c < H.ncl; ++c)
+        for (int a = 0; a < nx; ++a)
+            for (int k = 0; k < H.d; ++k)
+                nodes_p[((size_t)c * nx + a) * dp + k] = nodes[((size_t)c * nx + a) * H.d + k];
+    transfer_matrices(H, B, E);
+    // Legendre slots (axis, degree >= 1) and, per basis function, the slots whose product it is
+    std::vector<int32_t> leg_axis, leg_deg;
+    std::vector<std::vector<int>> slot(H.d);
+    for (int k = 0; k < H.d; ++k) {
+        slot[k].assign(B.mk[k] + 1, -1);
+        for (int m = 1; m <= B.mk[k]; ++m) {
+            slot[k][m] = (int)leg_axis.size();
+            leg_axis.push_back(k);
+            leg_deg.push_back(m);
+        }
+    }
+    int nnz_max = 1;
+    for (int a = 0; a < nx; ++a) {
+        int c = 0;
+        for (int k = 0; k < H.d; ++k) c += B.alpha[(size_t)a * H.d + k] != 0;
+        nnz_max = std::max(nnz_max, c);
+    }
+    std::vector<int32_t> lidx((size_t)nx * nnz_max, -1);
+    for (int a = 0; a < nx; ++a) {
+        int j = 0;
+        for (int k = 0; k < H.d; ++k) {
+            int m = B.alpha[(size_t)a * H.d + k];
+            if (m) lidx[(size_t)a * nnz_max + j++] = slot[k][m];
+        }
+    }
+    if (leg_axis.size() > 128) {
+        delete op;
+        return fail(DWFMM_E_INVALID, "too many Legendre slots");
+    }
+    if (leg_axis.empty()) {  // keep device arrays non-empty
+        leg_axis.push_back(0);
+        leg_deg.push_back(0);
+    }
+
+    auto up = [&](auto **dst, const auto &v) { return op->arena.upload(dst, v, st); };
+    const size_t n = (size_t)H.n, R = (size_t)o.max_nrhs;
+    double *dnodes, *dE, *dVinv, *dLb, *dxt, *dM, *dL;
+    int32_t *dlidx, *dla, *dld;
+    hipError_t e = hipSuccess;
+    if ((e = up(&dnodes, nodes_p)) != hipSuccess || (e = up(&dE, E)) != hipSuccess ||
+        (e = up(&dVinv, B.Vinv)) != hipSuccess || (e = up(&dlidx, lidx)) != hipSuccess ||
+        (e = up(&dla, leg_axis)) != hipSuccess || (e = up(&dld, leg_deg)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&dLb, sizeof(double) * nx * n)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&dxt, sizeof(double) * n * R)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&dM, sizeof(double) * H.ncl * nx * R)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&dL, sizeof(double) * H.ncl * nx * R)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&op->D.rowbuf, sizeof(double) * 128 * H.nleaf)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&op->D.colbuf, sizeof(double) * 128 * (size_t)tree->D.nblk)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&op->r, sizeof(double) * n * R)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&op->p, sizeof(double) * n * R)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&op->q, sizeof(double) * n * R)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&op->partial, sizeof(double) * kDotBlocks * R)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&op->scal, sizeof(double) * 16 * R)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&op->state, sizeof(int32_t) * 4 * R)) != hipSuccess ||
+        (e = hipMemsetAsync(dM, 0, sizeof(double) * H.ncl * nx * R, st)) != hipSuccess ||
+        (e = hipMemsetAsync(dL, 0, sizeof(double) * H.ncl * nx * R, st)) != hipSuccess ||
+        (e = launch_basis(tree->D, nx, tree->clo, tree->csc, tree->coff, dlidx, nnz_max, dVinv,
+                          (int)leg_axis.size(), dla, dld, dLb, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        op->arena.release();
+        delete op;
+        return fail(e == hipErrorOutOfMemory ? DWFMM_E_NOMEM : DWFMM_E_HIP,
+                    std::string("operator setup: ") + hipGetErrorString(e));
+    }
+    DevOp &D = op->D;
+    D.kind = kernel.kind;
+    D.ell = kernel.ell;
+    D.nx = nx;
+    D.max_nrhs = o.max_nrhs;
+    D.nodes = dnodes;
+    D.E = dE;
+    D.Lb = dLb;
+    D.xt = dxt;
+    D.M = dM;
+    D.L = dL;
+    op->precision = o.precision;
+    op->max_nrhs = o.max_nrhs;
+    op->check_every = o.check_every;
+    op->ir_inner_rtol = o.ir_inner_rtol;
+    op->ir_max_outer = o.ir_max_outer;
+    op->tree = tree;
+    tree->refs++;
+    *out = op;
+    return DWFMM_OK;
+}
+
+extern "C" void dwfmm_op_destroy(dwfmm_op op)
+{
+    if (!op) return;
+    op->arena.release();
+    dwfmm_tree t = op->tree;
+    delete op;
+    if (t) tree_release(t);
+}
+
+// ============================================================== matvec
+extern "C" dwfmm_status dwfmm_fmm_matvec_parts(dwfmm_op op, const double *x, double *y, int32_t nrhs, int32_t parts,
+                                               int32_t precision, void *stream)
+{
+    if (!op) return fail(DWFMM_E_INVALID, "op is NULL");
+    if (!x || !y) return fail(DWFMM_E_INVALID, "x or y is NULL");
+    if (x == y) return fail(DWFMM_E_INVALID, "x and y must be distinct");
+    if (nrhs < 1 || nrhs > op->max_nrhs) return fail(DWFMM_E_INVALID, "nrhs must be in [1, max_nrhs]");
+    if (parts < 0 || parts > 3) return fail(DWFMM_E_INVALID, "parts must be in [0, 3]");
+    if (precision < 0 || precision > 2) return fail(DWFMM_E_INVALID, "unknown precision");
+    const KernelTimer *tm = nullptr;
+    if (op->timing) {
+        if (op->timers_used == op->timers.size()) {
+            KernelTimer k;
+            HIP_TRY(hipEventCreate(&k.p2p_start));
+            HIP_TRY(hipEventCreate(&k.p2p_stop));
+            HIP_TRY(hipEventCreate(&k.m2l_start));
+            HIP_TRY(hipEventCreate(&k.m2l_stop));
+            op->timers.push_back(k);
+        }
+        tm = &op->timers[op->timers_used++];
+    }
+    HIP_TRY(launch_matvec(op->tree->D, op->D, x, y, nrhs, parts, precision, (hipStream_t)stream, tm));
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_op_timing(dwfmm_op op, int32_t enable, double *out)
+{
+    if (!op) return fail(DWFMM_E_INVALID, "op is NULL");
+    if (out) {
+        double p2p = 0.0, m2l = 0.0;
+        for (size_t i = 0; i < op->timers_used; ++i) {
+            float ms = 0.0f;
+            HIP_TRY(hipEventSynchronize(op->timers[i].p2p_stop));
+            HIP_TRY(hipEventElapsedTime(&ms, op->timers[i].p2p_start, op->timers[i].p2p_stop));
+            p2p += ms;
+            if (hipEventQuery(op->timers[i].m2l_stop) == hipSuccess &&
+                hipEventElapsedTime(&ms, op->timers[i].m2l_start, op->timers[i].m2l_stop) == hipSuccess)
+                m2l += ms;
+        }
+        out[0] = p2p;
+        out[1] = m2l;
+        out[2] = (double)op->timers_used;
+    }
+    op->timing = enable != 0;
+    op->timers_used = 0;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_fmm_matvec(dwfmm_op op, const double *x, double *y, int32_t nrhs, void *stream)
+{
+    if (!op) return fail(DWFMM_E_INVALID, "op is NULL");
+    return dwfmm_fmm_matvec_parts(op, x, y, nrhs, 3, op->precision, stream);
+}
+
+// ============================================================== CG
+namespace {
+
+// scal layout per column c (stride nrhs): [0] rr, [1] |f|^2, [2] pq, [3] rr_new, [4] a, [5] beta
+// state layout: [0] status (0 active, 1 converged, 2 breakdown), [1] iters, [2] neg curvature
+__global__ void cg_check_kernel(double *scal, int32_t *state, int nrhs, double rtol)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrhs) return;
+    const double rr = scal[c], ff = scal[nrhs + c];
+    if (state[c] == 0 && sqrt(rr) <= rtol * sqrt(ff)) state[c] = 1;
+}
+
+__global__ void cg_alpha_kernel(double *scal, int32_t *state, int nrhs)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrhs) return;
+    double a = 0.0;
+    if (state[c] == 0) {
+        const double pq = scal[2 * nrhs + c];
+        if (!isfinite(pq) || fabs(pq) <= 1e-300) {
+            state[c] = 2;
+        } else {
+            if (pq < 0.0) state[2 * nrhs + c] += 1;
+            a = scal[c] / pq;
+        }
+    }
+    scal[4 * nrhs + c] = a;
+}
+
+__global__ void cg_beta_kernel(double *scal, int32_t *state, int nrhs)
+{
+    const int c = blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= nrhs) return;
+    double b = 0.0;
+    if (state[c] == 0) {
+        b = scal[3 * nrhs + c] / scal[c];
+        scal[c] = scal[3 * nrhs + c];
+        state[nrhs + c] += 1;
+    }
+    scal[5 * nrhs + c] = b;
+}
+
+// v = a + s * b  (s per column from scal[slot], applied where state == 0 if masked)
+__global__ void axpy_kernel(double *out, const double *a, const double *b,
+                            const double *__restrict__ scal, int slot, double sign, const int32_t *__restrict__ state,
+                            int masked, size_t total, int nrhs)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x) {
+        const int c = (int)(i % nrhs);
+        if (masked && state[c] != 0) continue;
+        out[i] = a[i] + sign * scal[slot * nrhs + c] * b[i];
+    }
+}
+
+// out = a + lam * b   (adds the ridge term)
+__global__ void ridge_kernel(double *__restrict__ out, const double *__restrict__ b, double lam, size_t total)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = fma(lam, b[i], out[i]);
+}
+
+// out = f - a
+__global__ void sub_kernel(double *out, const double *f, const double *a,
+                           size_t total)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = f[i] - a[i];
+}
+
+__global__ void copy_kernel(double *__restrict__ out, const double *__restrict__ a, size_t total)
+{
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < total; i += (size_t)gridDim.x * blockDim.x)
+        out[i] = a[i];
+}
+
+constexpr int kEwBlocks = 1024;
+
+}  // namespace
+
+extern "C" dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double *f, double *alpha, int32_t nrhs,
+                                        double rtol, int32_t max_iter, void *stream, dwfmm_solve_info *info)
+{
+    if (!op) return fail(DWFMM_E_INVALID, "op is NULL");
+    if (!f || !alpha || !info) return fail(DWFMM_E_INVALID, "f, alpha or info is NULL");
+    if (nrhs < 1 || nrhs > op->max_nrhs) return fail(DWFMM_E_INVALID, "nrhs must be in [1, max_nrhs]");
+    if (!std::isfinite(lambda) || lambda < 0.0) return fail(DWFMM_E_INVALID, "lambda must be finite and >= 0");
+    if (!(rtol > 0.0) || max_iter < 0) return fail(DWFMM_E_INVALID, "rtol must be > 0 and max_iter >= 0");
+    hipStream_t st = (hipStream_t)stream;
+    const DevTree &T = op->tree->D;
+    const size_t total = (size_t)T.n * nrhs;
+    const int nb = (nrhs + 63) / 64;
+    double *r = op->r, *p = op->p, *q = op->q, *scal = op->scal;
+    int32_t *state = op->state;
+    auto matvecA = [&](const double *v, double *out) -> hipError_t {
+        hipError_t e = launch_matvec(T, op->D, v, out, nrhs, 3, DWFMM_FP64, st);
+        if (e != hipSuccess) return e;
+        if (lambda != 0.0) hipLaunchKernelGGL(ridge_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, v, lambda, total);
+        return hipGetLastError();
+    };
+    HIP_TRY(hipMemsetAsync(state, 0, sizeof(int32_t) * 3 * nrhs, st));
+    HIP_TRY(matvecA(alpha, q));
+    hipLaunchKernelGGL(sub_kernel, dim3(kEwBlocks), dim3(256), 0, st, r, f, q, total);
+    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, st, p, r, total);
+    HIP_TRY(launch_dot(r, r, T.n, nrhs, op->partial, scal, st));
+    HIP_TRY(launch_dot(f, f, T.n, nrhs, op->partial, scal + nrhs, st));
+    std::vector<int32_t> hstate(3 * nrhs);
+    int it = 0;
+    for (; it < max_iter; ++it) {
+        hipLaunchKernelGGL(cg_check_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs, rtol);
+        if (it % op->check_every == 0) {
+            HIP_TRY(hipMemcpyAsync(hstate.data(), state, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            bool active = false;
+            for (int c = 0; c < nrhs; ++c) active |= hstate[c] == 0;
+            if (!active) break;
+        }
+        HIP_TRY(matvecA(p, q));
+        HIP_TRY(launch_dot(p, q, T.n, nrhs, op->partial, scal + 2 * nrhs, st));
+        hipLaunchKernelGGL(cg_alpha_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs);
+        // alpha += a p ; r -= a q  (a = 0 for inactive columns)
+        hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, alpha, alpha, p, scal, 4, 1.0, state, 0,
+                           total, nrhs);
+        hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, r, r, q, scal, 4, -1.0, state, 0, total,
+                           nrhs);
+        HIP_TRY(launch_dot(r, r, T.n, nrhs, op->partial, scal + 3 * nrhs, st));
+        hipLaunchKernelGGL(cg_beta_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs);
+        // p = r + beta p on active columns
+        hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, p, r, p, scal, 5, 1.0, state, 1, total,
+                           nrhs);
+        HIP_TRY(hipGetLastError());
+    }
+    hipLaunchKernelGGL(cg_check_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs, rtol);
+    // true residual |f - A alpha|
+    HIP_TRY(matvecA(alpha, q));
+    hipLaunchKernelGGL(sub_kernel, dim3(kEwBlocks), dim3(256), 0, st, q, f, q, total);
+    HIP_TRY(launch_dot(q, q, T.n, nrhs, op->partial, scal + 6 * nrhs, st));
+    std::vector<double> hs(7 * nrhs);
+    HIP_TRY(hipMemcpyAsync(hs.data(), scal, sizeof(double) * 7 * nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hstate.data(), state, sizeof(int32_t) * 3 * nrhs, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    dwfmm_status worst = DWFMM_OK;
+    for (int c = 0; c < nrhs; ++c) {
+        const double fn = std::sqrt(hs[nrhs + c]);
+        const double den = fn > 0 ? fn : 1.0;
+        dwfmm_solve_info &I = info[c];
+        I.iters = hstate[nrhs + c];
+        I.neg_curvature_steps = hstate[2 * nrhs + c];
+        I.refine_steps = 0;
+        I.rel_res_recursive = std::sqrt(hs[c]) / den;
+        I.rel_res_true = std::sqrt(hs[6 * nrhs + c]) / den;
+        I.status = hstate[c] == 1 ? DWFMM_OK : (hstate[c] == 2 ? DWFMM_E_BREAKDOWN : DWFMM_E_NOT_CONVERGED);
+        if (I.status == DWFMM_E_BREAKDOWN) worst = DWFMM_E_BREAKDOWN;
+        else if (I.status == DWFMM_E_NOT_CONVERGED && worst == DWFMM_OK) worst = DWFMM_E_NOT_CONVERGED;
+    }
+    if (worst != DWFMM_OK) g_err = worst == DWFMM_E_BREAKDOWN ? "CG breakdown" : "CG did not converge";
+    return worst;
+}
+
+// ============================================================== sizes and introspection
+extern "C" size_t dwfmm_estimate_bytes(int64_t n, int32_t d, int32_t leaf_size, int32_t n_x, int32_t nrhs)
+{
+    if (n < 1 || d < 1 || leaf_size < 1 || n_x < 1 || nrhs < 1) return 0;
+    int J = 0;
+    while ((n + ((int64_t)1 << J) - 1) >> J > leaf_size) ++J;
+    const size_t ncl = ((size_t)1 << (J + 1)) - 1;
+    const size_t dp = (size_t)pad_dim(d);
+    size_t b = 0;
+    b += dp * n * 8 + 4 * (size_t)n;                 // coordinates, permutation
+    b += ncl * (8 + 3 * 8 * (size_t)d);              // ranges, box maps
+    b += ncl * 64 * 4 * 2;                           // lists (estimate: 64 entries per cluster)
+    b += ncl * n_x * dp * 8 + ncl * n_x * n_x * 8;   // nodes, transfer matrices
+    b += (size_t)n_x * n * 8;                        // basis cache
+    b += (size_t)n * nrhs * 8 * 4;                   // xt, r, p, q
+    b += 2 * ncl * n_x * nrhs * 8;                   // moments, locals
+    return b;
+}
+
+extern "C" size_t dwfmm_op_bytes(dwfmm_op op)
+{
+    if (!op) return 0;
+    return op->arena.total + op->tree->arena.total;
+}
+
+extern "C" const char *dwfmm_last_error(void) { return g_err.c_str(); }
+
+extern "C" dwfmm_status dwfmm_tree_info(dwfmm_tree t, int64_t *out)
+{
+    if (!t || !out) return fail(DWFMM_E_INVALID, "NULL argument");
+    const HostTree &H = t->H;
+    out[0] = H.n;
+    out[1] = H.d;
+    out[2] = H.J;
+    out[3] = H.ncl;
+    out[4] = (int64_t)H.Fsrc.size();
+    out[5] = (int64_t)H.Nsrc.size();
+    out[6] = H.nleaf;
+    out[7] = H.leaf;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_tree_get(dwfmm_tree t, int64_t *perm, int64_t *begin, int64_t *end, double *lo,
+                                       double *hi, int64_t *Fptr, int64_t *Fsrc, int64_t *Nptr, int64_t *Nsrc)
+{
+    if (!t) return fail(DWFMM_E_INVALID, "NULL tree");
+    const HostTree &H = t->H;
+    if (perm) std::copy(H.perm.begin(), H.perm.end(), perm);
+    if (begin) std::copy(H.begin.begin(), H.begin.end(), begin);
+    if (end) std::copy(H.end.begin(), H.end.end(), end);
+    if (lo) std::copy(H.lo.begin(), H.lo.end(), lo);
+    if (hi) std::copy(H.hi.begin(), H.hi.end(), hi);
+    if (Fptr) std::copy(H.Fptr.begin(), H.Fptr.end(), Fptr);
+    if (Fsrc) std::copy(H.Fsrc.begin(), H.Fsrc.end(), Fsrc);
+    if (Nptr) std::copy(H.Nptr.begin(), H.Nptr.end(), Nptr);
+    if (Nsrc) std::copy(H.Nsrc.begin(), H.Nsrc.end(), Nsrc);
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_op_info(dwfmm_op op, int64_t *out)
+{
+    if (!op || !out) return fail(DWFMM_E_INVALID, "NULL argument");
+    out[0] = op->B.nx;
+    out[1] = op->max_nrhs;
+    out[2] = op->precision;
+    out[3] = (int64_t)dwfmm_op_bytes(op);
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_op_basis(dwfmm_op op, uint8_t *alpha, double *xi, double *Vinv, double *omega)
+{
+    if (!op) return fail(DWFMM_E_INVALID, "NULL op");
+    const HostBasis &B = op->B;
+    if (alpha) std::copy(B.alpha.begin(), B.alpha.end(), alpha);
+    if (xi) std::copy(B.xi.begin(), B.xi.end(), xi);
+    if (Vinv) std::copy(B.Vinv.begin(), B.Vinv.end(), Vinv);
+    if (omega) std::copy(B.omega.begin(), B.omega.end(), omega);
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_op_moments(dwfmm_op op, double *moments, double *locals, int32_t nrhs)
+{
+    if (!op) return fail(DWFMM_E_INVALID, "NULL op");
+    if (nrhs < 1 || nrhs > op->max_nrhs) return fail(DWFMM_E_INVALID, "bad nrhs");
+    const size_t cnt = (size_t)op->tree->H.ncl * op->B.nx * nrhs;
+    if (moments) HIP_TRY(hipMemcpy(moments, op->D.M, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    if (locals) HIP_TRY(hipMemcpy(locals, op->D.L, cnt * sizeof(double), hipMemcpyDeviceToHost));
+    return DWFMM_OK;
+}

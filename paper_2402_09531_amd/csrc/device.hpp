@@ -1,0 +1,64 @@
+// Device-side data of a tree and an operator, and the launchers of the HIP
+// kernels that make up one matvec and the CG solver.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace dwfmm {
+
+// Everything the kernels read about the geometry (device pointers).
+struct DevTree {
+    int n, d, J, dpad;
+    int nleaf, ncl, leaf_first;   // leaf_first = 2^J - 1
+    int max_leaf;                 // largest leaf size
+    int min_far_level;            // J+1 when there is no farfield
+    const double *Xs;             // [dpad][n] coordinates in tree order (rows k >= d are zero)
+    const int32_t *perm;          // [n] tree position -> original index
+    const int32_t *cbeg, *cend;   // [ncl]
+    const int32_t *Fptr, *Fsrc;   // farfield CSR over clusters
+    const int32_t *Nptr, *Nsrc;   // nearfield CSR over leaves (leaf-local indices)
+    // Symmetric nearfield: every unordered leaf pair {t, s}, t != s, is owned by one of
+    // its two leaves (balanced); the owner evaluates the block once and applies it both
+    // ways.  own: CSR over owner leaves of partner leaves, block id = CSR position.
+    // inc: CSR over partner leaves of the block ids whose column sums they receive.
+    int nblk;                     // number of off-diagonal owned blocks
+    const int32_t *own_ptr, *own_src, *inc_ptr, *inc_blk;
+    const double *center;         // [nleaf][dpad] leaf box midpoints (coordinate shift)
+};
+
+struct DevOp {
+    int kind;
+    double ell;
+    int nx, max_nrhs;
+    const double *nodes;          // [ncl][nx][dpad] interpolation nodes of every box
+    const double *E;              // [ncl][nx][nx] Lagrange transfer matrices (row a, column b)
+    const double *Lb;             // [nx][n] Lagrange basis l_a(a_leaf^-1 x_i), tree order
+    double *xt;                   // [n][max_nrhs] x in tree order
+    double *M, *L;                // [ncl][nx][max_nrhs] moments and locals
+    double *rowbuf;               // [nleaf][128] owner-side nearfield row sums (one rhs)
+    double *colbuf;               // [nblk][128] column sums of owned blocks (one rhs)
+};
+
+// Optional HIP events recorded around the nearfield (P2P) and coupling (M2L)
+// launches, on the stream they run on.
+struct KernelTimer {
+    hipEvent_t p2p_start = nullptr, p2p_stop = nullptr, m2l_start = nullptr, m2l_stop = nullptr;
+};
+
+// One matvec (or parts of it) on `stream`.  parts: bit0 nearfield, bit1 farfield.
+hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, double *y, int nrhs, int parts,
+                         int precision, hipStream_t stream, const KernelTimer *timer = nullptr);
+
+// Lagrange basis cache Lb from the boxes and the index set (setup).
+hipError_t launch_basis(const DevTree &T, int nx, const double *clo, const double *csc, const double *coff,
+                        const int32_t *lidx, int nnz_max, const double *Vinv, int nleg, const int32_t *leg_axis,
+                        const int32_t *leg_deg, double *Lb, hipStream_t stream);
+
+// ---- CG building blocks (FP64, deterministic fixed-order reductions) ----
+// partial[b][c] for b < kDotBlocks; out[c] = sum_b partial[b][c] in order.
+constexpr int kDotBlocks = 240;
+hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double *partial, double *out,
+                      hipStream_t stream);
+
+}  // namespace dwfmm

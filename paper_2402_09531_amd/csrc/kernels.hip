@@ -1,0 +1,579 @@
+// HIP kernels (gfx950) for one dimension weighted FMM matvec, arXiv 2402.09531 Sec 5.2:
+//   P2M  leaf moments      m_nu = L_nu^T x_nu  (Lagrange basis of the leaf box)
+//   M2M  upward            m_nu = sum_c E_c^T m_c                 (two-scale relation)
+//   M2L  coupling          l_nu += S_{nu,nu'} m_nu',  S = [K(a_nu(xi_a), a_nu'(xi_b))]
+//   L2L  downward          l_c += E_c l_nu
+//   L2P  leaf evaluation   y_nu += L_nu l_nu
+//   P2P  nearfield         y_nu += K_{nu,nu'} x_nu' over inadmissible leaf pairs
+// The Lagrange form L = P V^-1 of the paper's Legendre cluster basis P is used
+// throughout: it is the same operator, K~_{nu,nu'} = P_nu V^-1 S V^-T P_nu'^T.
+#include <hip/hip_runtime.h>
+
+#include "device.hpp"
+
+namespace dwfmm {
+
+namespace {
+
+constexpr int kMaxNx = 64;
+constexpr int kMaxNodeWords = 1536;  // nx * dpad bound of the M2L node tiles
+
+template <int KIND>
+__device__ __forceinline__ double kernel_val(double r2, double inv_ell)
+{
+    if constexpr (KIND == 0) {
+        double s = 1.7320508075688772 * sqrt(r2) * inv_ell;
+        return (1.0 + s) * exp(-s);
+    } else if constexpr (KIND == 1) {
+        return exp(-r2 * inv_ell);
+    } else {
+        return exp(-sqrt(r2) * inv_ell);
+    }
+}
+
+// POLY_TEST kernel 1 + sum_{k<p} x_k y_k + (x_0 y_0)^2
+__device__ __forceinline__ double poly_kernel(const double *a, const double *b, int p)
+{
+    double v = 1.0;
+    for (int k = 0; k < p; ++k) v += a[k] * b[k];
+    double t = a[0] * b[0];
+    return v + t * t;
+}
+
+__device__ __forceinline__ double wave_sum(double v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    return v;
+}
+
+// ---------------------------------------------------------------- basis cache
+// Lb[a][i] = l_a(t_i) = sum_g Vinv[g][a] p_g(t_i), t_i = reference coordinates of
+// point i in its leaf box.  lidx[g][j] lists the Legendre slots whose product is p_g.
+__global__ void basis_kernel(DevTree T, int nx, const double *__restrict__ clo, const double *__restrict__ csc,
+                             const double *__restrict__ coff, const int32_t *__restrict__ lidx, int nnz_max,
+                             const double *__restrict__ Vinv, int nleg, const int32_t *__restrict__ leg_axis,
+                             const int32_t *__restrict__ leg_deg, double *__restrict__ Lb)
+{
+    const int c = T.leaf_first + blockIdx.x;
+    const int cb = T.cbeg[c], ce = T.cend[c];
+    for (int i = cb + (int)threadIdx.x; i < ce; i += blockDim.x) {
+        double leg[128];
+        double p[kMaxNx];
+        for (int s = 0; s < nleg; ++s) {
+            const int k = leg_axis[s], m = leg_deg[s];
+            const double t = (T.Xs[(size_t)k * T.n + i] - clo[(size_t)c * T.d + k]) * csc[(size_t)c * T.d + k] +
+                             coff[(size_t)c * T.d + k];
+            // orthonormal Legendre p_m(t) = sqrt(2m+1) P_m(2t-1)
+            const double u = 2.0 * t - 1.0;
+            double p0 = 1.0, p1 = u;
+            double v = 1.0;
+            if (m >= 1) {
+                for (int j = 1; j < m; ++j) {
+                    double p2 = ((2.0 * j + 1.0) * u * p1 - j * p0) / (j + 1.0);
+                    p0 = p1;
+                    p1 = p2;
+                }
+                v = sqrt(2.0 * m + 1.0) * p1;
+            }
+            leg[s] = v;
+        }
+        for (int g = 0; g < nx; ++g) {
+            double v = 1.0;
+            for (int j = 0; j < nnz_max; ++j) {
+                const int s = lidx[g * nnz_max + j];
+                if (s >= 0) v *= leg[s];
+            }
+            p[g] = v;
+        }
+        for (int a = 0; a < nx; ++a) {
+            double v = 0.0;
+            for (int g = 0; g < nx; ++g) v += Vinv[g * nx + a] * p[g];
+            Lb[(size_t)a * T.n + i] = v;
+        }
+    }
+}
+
+// ---------------------------------------------------------------- P2M (+ gather of x into tree order)
+__global__ __launch_bounds__(256) void p2m_kernel(DevTree T, DevOp O, const double *__restrict__ x, int nrhs,
+                                                  int do_far)
+{
+    extern __shared__ double xl[];  // [max_leaf]
+    const int l = blockIdx.x, c = T.leaf_first + l;
+    const int cb = T.cbeg[c], ce = T.cend[c], np = ce - cb;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    for (int r = 0; r < nrhs; ++r) {
+        for (int i = threadIdx.x; i < np; i += blockDim.x) {
+            const double v = x[(size_t)T.perm[cb + i] * nrhs + r];
+            xl[i] = v;
+            O.xt[(size_t)(cb + i) * nrhs + r] = v;
+        }
+        __syncthreads();
+        if (do_far) {
+            for (int a = wave; a < O.nx; a += blockDim.x >> 6) {
+                double s = 0.0;
+                for (int i = lane; i < np; i += 64) s += O.Lb[(size_t)a * T.n + cb + i] * xl[i];
+                s = wave_sum(s);
+                if (lane == 0) O.M[((size_t)c * O.nx + a) * nrhs + r] = s;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------- M2M, one level
+__global__ __launch_bounds__(64) void m2m_kernel(DevTree T, DevOp O, int first, int nrhs)
+{
+    const int c = first + blockIdx.x;
+    const int nx = O.nx;
+    for (int p = threadIdx.x; p < nx * nrhs; p += blockDim.x) {
+        const int a = p / nrhs, r = p % nrhs;
+        double s = 0.0;
+        for (int ch = 2 * c + 1; ch <= 2 * c + 2; ++ch) {
+            const double *E = O.E + (size_t)ch * nx * nx;
+            const double *m = O.M + (size_t)ch * nx * nrhs;
+            for (int b = 0; b < nx; ++b) s += E[b * nx + a] * m[b * nrhs + r];
+        }
+        O.M[((size_t)c * nx + a) * nrhs + r] = s;
+    }
+}
+
+// ---------------------------------------------------------------- M2L, all farfield levels at once
+template <int KIND>
+__global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first, int nrhs)
+{
+    __shared__ double tn[kMaxNodeWords];
+    __shared__ double sn[kMaxNodeWords];
+    __shared__ double S[kMaxNx * kMaxNx];
+    const int c = first + blockIdx.x;
+    const int nx = O.nx, dp = T.dpad;
+    const int f0 = T.Fptr[c], f1 = T.Fptr[c + 1];
+    const double inv_ell = 1.0 / O.ell;
+    constexpr int kAcc = (kMaxNx * 32 + 255) / 256;
+    double acc[kAcc];
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) acc[k] = 0.0;
+    if (f0 < f1) {
+        for (int q = threadIdx.x; q < nx * dp; q += blockDim.x) tn[q] = O.nodes[(size_t)c * nx * dp + q];
+        for (int f = f0; f < f1; ++f) {
+            const int s = T.Fsrc[f];
+            for (int q = threadIdx.x; q < nx * dp; q += blockDim.x) sn[q] = O.nodes[(size_t)s * nx * dp + q];
+            __syncthreads();
+            for (int q = threadIdx.x; q < nx * nx; q += blockDim.x) {
+                const int a = q / nx, b = q % nx;
+                double v;
+                if constexpr (KIND == 3) {
+                    v = poly_kernel(&tn[a * dp], &sn[b * dp], (int)O.ell);
+                } else {
+                    double r2 = 0.0;
+                    for (int k = 0; k < dp; ++k) {
+                        const double t = tn[a * dp + k] - sn[b * dp + k];
+                        r2 += t * t;
+                    }
+                    v = kernel_val<KIND>(r2, inv_ell);
+                }
+                S[q] = v;
+            }
+            __syncthreads();
+            const double *m = O.M + (size_t)s * nx * nrhs;
+#pragma unroll
+            for (int k = 0; k < kAcc; ++k) {
+                const int p = threadIdx.x + 256 * k;
+                if (p < nx * nrhs) {
+                    const int a = p / nrhs, r = p % nrhs;
+                    double v = 0.0;
+                    for (int b = 0; b < nx; ++b) v += S[a * nx + b] * m[b * nrhs + r];
+                    acc[k] += v;
+                }
+            }
+            __syncthreads();
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < kAcc; ++k) {
+        const int p = threadIdx.x + 256 * k;
+        if (p < nx * nrhs) O.L[(size_t)c * nx * nrhs + p] = acc[k];
+    }
+}
+
+// ---------------------------------------------------------------- L2L, one level
+__global__ __launch_bounds__(64) void l2l_kernel(DevTree T, DevOp O, int first, int nrhs)
+{
+    const int c = first + blockIdx.x;
+    const int par = (c - 1) / 2;
+    const int nx = O.nx;
+    const double *E = O.E + (size_t)c * nx * nx;
+    const double *lp = O.L + (size_t)par * nx * nrhs;
+    for (int p = threadIdx.x; p < nx * nrhs; p += blockDim.x) {
+        const int a = p / nrhs, r = p % nrhs;
+        double s = 0.0;
+        for (int b = 0; b < nx; ++b) s += E[a * nx + b] * lp[b * nrhs + r];
+        O.L[((size_t)c * nx + a) * nrhs + r] += s;
+    }
+}
+
+// ---------------------------------------------------------------- P2P + L2P + scatter to original order
+constexpr int kP2PThreads = 128;
+
+template <int KIND, int DP>
+__global__ __launch_bounds__(kP2PThreads) void p2p_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
+                                                          int do_near, int do_far)
+{
+    // source points staged per pass; fewer for wide points so that LDS stays below 32 KB
+    constexpr int SCH = DP <= 32 ? kP2PThreads : kP2PThreads / 2;
+    __shared__ double sx[SCH * DP];
+    __shared__ double sq[SCH];
+    const int l = blockIdx.x, c = T.leaf_first + l;
+    const int cb = T.cbeg[c], ce = T.cend[c];
+    const double inv_ell = 1.0 / O.ell;
+    const int n = T.n;
+    for (int t0 = cb; t0 < ce; t0 += kP2PThreads) {
+        const int i = t0 + (int)threadIdx.x;
+        const bool active = i < ce;
+        double xt[DP];
+#pragma unroll
+        for (int k = 0; k < DP; ++k) xt[k] = active ? T.Xs[(size_t)k * n + i] : 0.0;
+        for (int r = 0; r < nrhs; ++r) {
+            double acc = 0.0;
+            if (do_near) {
+                for (int f = T.Nptr[l]; f < T.Nptr[l + 1]; ++f) {
+                    const int s = T.leaf_first + T.Nsrc[f];
+                    const int sb = T.cbeg[s], se = T.cend[s];
+                    for (int s0 = sb; s0 < se; s0 += SCH) {
+                        __syncthreads();
+                        const int j = s0 + (int)threadIdx.x;
+                        if ((int)threadIdx.x < SCH && j < se) {
+#pragma unroll
+                            for (int k = 0; k < DP; ++k) sx[threadIdx.x * DP + k] = T.Xs[(size_t)k * n + j];
+                            sq[threadIdx.x] = O.xt[(size_t)j * nrhs + r];
+                        }
+                        __syncthreads();
+                        const int m = min(SCH, se - s0);
+                        for (int jj = 0; jj < m; ++jj) {
+                            double kv;
+                            if constexpr (KIND == 3) {
+                                kv = poly_kernel(xt, &sx[jj * DP], (int)O.ell);
+                            } else {
+                                double r2 = 0.0;
+#pragma unroll
+                                for (int k = 0; k < DP; ++k) {
+                                    const double t = xt[k] - sx[jj * DP + k];
+                                    r2 = fma(t, t, r2);
+                                }
+                                kv = kernel_val<KIND>(r2, inv_ell);
+                            }
+                            acc = fma(kv, sq[jj], acc);
+                        }
+                    }
+                }
+            }
+            if (do_far && active) {
+                const double *lc = O.L + (size_t)c * O.nx * nrhs;
+                for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * n + i], lc[a * nrhs + r], acc);
+            }
+            if (active) y[(size_t)T.perm[i] * nrhs + r] = acc;
+        }
+    }
+}
+
+template <int KIND, int DP>
+void launch_p2p_t(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
+{
+    hipLaunchKernelGGL((p2p_kernel<KIND, DP>), dim3(T.nleaf), dim3(kP2PThreads), 0, st, T, O, y, nrhs, near, far);
+}
+
+template <int KIND>
+hipError_t launch_p2p_k(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
+{
+    switch (T.dpad) {
+#define DWFMM_CASE(D) \
+    case D: launch_p2p_t<KIND, D>(T, O, y, nrhs, near, far, st); break;
+        DWFMM_CASE(2) DWFMM_CASE(4) DWFMM_CASE(6) DWFMM_CASE(8) DWFMM_CASE(10) DWFMM_CASE(12)
+        DWFMM_CASE(14) DWFMM_CASE(16) DWFMM_CASE(18) DWFMM_CASE(20) DWFMM_CASE(22) DWFMM_CASE(24)
+        DWFMM_CASE(32) DWFMM_CASE(40) DWFMM_CASE(48) DWFMM_CASE(56) DWFMM_CASE(64)
+#undef DWFMM_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- symmetric MFMA nearfield (one rhs)
+// Owner leaf t evaluates each block K_{t,s} it owns once: the squared distance
+// |x_i - y_j|^2 = |x_i|^2 + |y_j|^2 - 2 x_i.y_j takes the cross term from FP64
+// MFMA 16x16x4 tiles (coordinates shifted to the owner leaf's box midpoint), the
+// kernel value on the vector ALU.  Row sums K q_s stay in registers; column sums
+// K^T q_t go to colbuf[block] and are added by the partner leaf in the combine
+// pass, in a fixed order (no atomics, bitwise reproducible).
+// Lane layout of v_mfma_f64_16x16x4f64: A[i][k] in lane i + 16k, B[k][j] in lane
+// j + 16k, D[i][j] in lane j + 16(i%4), element i/4 (checked with a probe).
+typedef double dbl4 __attribute__((ext_vector_type(4)));
+constexpr int kSymLeaf = 128;
+
+template <int KIND, int DK>
+__global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
+{
+    constexpr int NKC = DK / 4;
+    __shared__ double sX[DK * kSymLeaf];  // [k][j] shifted source coordinates
+    __shared__ double sN[kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf], tQ[kSymLeaf];
+    __shared__ double colpart[4 * kSymLeaf];
+    __shared__ double cen[DK];
+
+    const int nleaf = T.nleaf;
+    const int bid = blockIdx.x;
+    // consecutive leaves (spatial neighbours) on the same XCD: blocks are dealt round-robin over 8 XCDs
+    const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
+    const int c = T.leaf_first + l;
+    const int cb = T.cbeg[c], nt = T.cend[c] - cb;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int n = T.n, d = T.d;
+    const double inv_ell = 1.0 / O.ell;
+    const int ntiles = (nt + 15) / 16;
+
+    if (tid < DK) cen[tid] = tid < d ? T.center[(size_t)l * T.dpad + tid] : 0.0;
+    __syncthreads();
+    if (tid < kSymLeaf) {
+        double s = 0.0, q = 0.0;
+        if (tid < nt) {
+            for (int k = 0; k < d; ++k) {
+                const double v = T.Xs[(size_t)k * n + cb + tid] - cen[k];
+                s = fma(v, v, s);
+            }
+            q = O.xt[cb + tid];
+        }
+        tN[tid] = s;
+        tQ[tid] = q;
+    }
+    const int rt[2] = {w, w + 4};
+    double A[2][NKC];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = 16 * rt[u] + li;
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) {
+            const int k = 4 * kc + lg;
+            A[u][kc] = (i < nt && k < d) ? T.Xs[(size_t)k * n + cb + i] - cen[k] : 0.0;
+        }
+    }
+    __syncthreads();
+    double rN[2][4], rQ[2][4], racc[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * rt[u] + 4 * v + lg;
+            rN[u][v] = tN[i];
+            rQ[u][v] = tQ[i];
+            racc[u][v] = 0.0;
+        }
+
+    const int o0 = T.own_ptr[l], o1 = T.own_ptr[l + 1];
+    for (int f = o0; f < o1; ++f) {
+        const int sl = T.own_src[f];
+        const bool diag = sl == l;
+        const int sc = T.leaf_first + sl;
+        const int sb = T.cbeg[sc], ns = T.cend[sc] - sb;
+        __syncthreads();
+        if (tid < kSymLeaf) {
+            const int j = tid;
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < DK; ++k) {
+                const double v = (j < ns && k < d) ? T.Xs[(size_t)k * n + sb + j] - cen[k] : 0.0;
+                sX[k * kSymLeaf + j] = v;
+                s = fma(v, v, s);
+            }
+            sN[j] = s;
+        } else {
+            const int j = tid - kSymLeaf;
+            sQ[j] = j < ns ? O.xt[sb + j] : 0.0;
+        }
+        __syncthreads();
+        const int nct = (ns + 15) / 16;
+        for (int ct = 0; ct < nct; ++ct) {
+            const int j = 16 * ct + li;
+            const double nb = sN[j], qb = sQ[j];
+            double Bf[NKC];
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
+            double cacc = 0.0;
+#pragma unroll
+            for (int u = 0; u < 2; ++u) {
+                if (rt[u] >= ntiles) continue;  // uniform over the wave
+                dbl4 G = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u][kc], Bf[kc], G, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    double r2 = fmax(fma(-2.0, G[v], rN[u][v] + nb), 0.0);
+                    if (diag && 16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
+                    const double kv = kernel_val<KIND>(r2, inv_ell);
+                    racc[u][v] = fma(kv, qb, racc[u][v]);
+                    cacc = fma(kv, rQ[u][v], cacc);
+                }
+            }
+            if (!diag) {
+                cacc += __shfl_xor(cacc, 16, 64);
+                cacc += __shfl_xor(cacc, 32, 64);
+                if (lg == 0) colpart[w * kSymLeaf + j] = cacc;
+            }
+        }
+        if (!diag) {
+            __syncthreads();
+            if (tid < ns)
+                O.colbuf[(size_t)f * kSymLeaf + tid] =
+                    ((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) + colpart[3 * kSymLeaf + tid];
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double s = racc[u][v];
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            s += __shfl_xor(s, 4, 64);
+            s += __shfl_xor(s, 8, 64);
+            const int i = 16 * rt[u] + 4 * v + lg;
+            if (li == 0 && i < nt) O.rowbuf[(size_t)l * kSymLeaf + i] = s;
+        }
+}
+
+// y[perm] = owner row sums + received column sums (fixed order) + L2P
+__global__ __launch_bounds__(kSymLeaf) void p2p_combine_kernel(DevTree T, DevOp O, double *__restrict__ y,
+                                                               int do_near, int do_far)
+{
+    const int l = blockIdx.x, c = T.leaf_first + l;
+    const int cb = T.cbeg[c], nt = T.cend[c] - cb;
+    const int i = threadIdx.x;
+    if (i >= nt) return;
+    double acc = 0.0;
+    if (do_near) {
+        acc = O.rowbuf[(size_t)l * kSymLeaf + i];
+        for (int q = T.inc_ptr[l]; q < T.inc_ptr[l + 1]; ++q) acc += O.colbuf[(size_t)T.inc_blk[q] * kSymLeaf + i];
+    }
+    if (do_far) {
+        const double *lc = O.L + (size_t)c * O.nx;
+        for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * T.n + cb + i], lc[a], acc);
+    }
+    y[T.perm[cb + i]] = acc;
+}
+
+template <int KIND>
+hipError_t launch_sym_k(const DevTree &T, const DevOp &O, hipStream_t st)
+{
+    const int dk = (T.d + 3) / 4 * 4;
+    switch (dk) {
+#define DWFMM_SYM(D) \
+    case D: hipLaunchKernelGGL((p2p_sym_kernel<KIND, D>), dim3(T.nleaf), dim3(256), 0, st, T, O); break;
+        DWFMM_SYM(4) DWFMM_SYM(8) DWFMM_SYM(12) DWFMM_SYM(16) DWFMM_SYM(20) DWFMM_SYM(24) DWFMM_SYM(28)
+        DWFMM_SYM(32)
+#undef DWFMM_SYM
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- deterministic dot products
+__global__ __launch_bounds__(256) void dot_partial_kernel(const double *__restrict__ a, const double *__restrict__ b,
+                                                          int n, int nrhs, double *__restrict__ partial)
+{
+    __shared__ double red[4];
+    const int chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+    for (int r = 0; r < nrhs; ++r) {
+        double s = 0.0;
+        for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) s = fma(a[(size_t)i * nrhs + r], b[(size_t)i * nrhs + r], s);
+        s = wave_sum(s);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nrhs + r] = ((red[0] + red[1]) + red[2]) + red[3];
+        __syncthreads();
+    }
+}
+
+__global__ void dot_final_kernel(const double *__restrict__ partial, int nblocks, int nrhs, double *__restrict__ out)
+{
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrhs) return;
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * nrhs + r];
+    out[r] = s;
+}
+
+}  // namespace
+
+hipError_t launch_basis(const DevTree &T, int nx, const double *clo, const double *csc, const double *coff,
+                        const int32_t *lidx, int nnz_max, const double *Vinv, int nleg, const int32_t *leg_axis,
+                        const int32_t *leg_deg, double *Lb, hipStream_t stream)
+{
+    if (nx > kMaxNx || nleg > 128) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(basis_kernel, dim3(T.nleaf), dim3(64), 0, stream, T, nx, clo, csc, coff, lidx, nnz_max, Vinv,
+                       nleg, leg_axis, leg_deg, Lb);
+    return hipGetLastError();
+}
+
+hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, double *y, int nrhs, int parts,
+                         int precision, hipStream_t st, const KernelTimer *timer)
+{
+    (void)precision;
+    if (O.nx > kMaxNx || O.nx * T.dpad > kMaxNodeWords || nrhs > 32) return hipErrorInvalidValue;
+    const int near = parts & 1;
+    const int far = (parts & 2) && T.min_far_level <= T.J;
+    hipLaunchKernelGGL(p2m_kernel, dim3(T.nleaf), dim3(256), sizeof(double) * T.max_leaf, st, T, O, x, nrhs, far);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (far) {
+        for (int j = T.J - 1; j >= T.min_far_level; --j)
+            hipLaunchKernelGGL(m2m_kernel, dim3(1 << j), dim3(64), 0, st, T, O, (1 << j) - 1, nrhs);
+        const int first = (1 << T.min_far_level) - 1;
+        const int cnt = T.ncl - first;
+        if (timer) (void)hipEventRecord(timer->m2l_start, st);
+        switch (O.kind) {
+        case 0: hipLaunchKernelGGL(m2l_kernel<0>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+        case 1: hipLaunchKernelGGL(m2l_kernel<1>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+        case 2: hipLaunchKernelGGL(m2l_kernel<2>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+        default: hipLaunchKernelGGL(m2l_kernel<3>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+        }
+        if (timer) (void)hipEventRecord(timer->m2l_stop, st);
+        for (int j = T.min_far_level + 1; j <= T.J; ++j)
+            hipLaunchKernelGGL(l2l_kernel, dim3(1 << j), dim3(64), 0, st, T, O, (1 << j) - 1, nrhs);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    // symmetric MFMA nearfield for one rhs, leaves <= 128 points, d <= 32, radial kernels
+    const bool sym = nrhs == 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && T.d <= 32 && O.rowbuf && O.colbuf;
+    if (timer) (void)hipEventRecord(timer->p2p_start, st);
+    if (sym) {
+        if (near) {
+            switch (O.kind) {
+            case 0: e = launch_sym_k<0>(T, O, st); break;
+            case 1: e = launch_sym_k<1>(T, O, st); break;
+            default: e = launch_sym_k<2>(T, O, st); break;
+            }
+            if (e != hipSuccess) return e;
+        }
+        if (timer) (void)hipEventRecord(timer->p2p_stop, st);
+        hipLaunchKernelGGL(p2p_combine_kernel, dim3(T.nleaf), dim3(kSymLeaf), 0, st, T, O, y, near, far);
+        return hipGetLastError();
+    }
+    switch (O.kind) {
+    case 0: e = launch_p2p_k<0>(T, O, y, nrhs, near, far, st); break;
+    case 1: e = launch_p2p_k<1>(T, O, y, nrhs, near, far, st); break;
+    case 2: e = launch_p2p_k<2>(T, O, y, nrhs, near, far, st); break;
+    default: e = launch_p2p_k<3>(T, O, y, nrhs, near, far, st); break;
+    }
+    if (timer) (void)hipEventRecord(timer->p2p_stop, st);
+    return e;
+}
+
+hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double *partial, double *out,
+                      hipStream_t stream)
+{
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotBlocks), dim3(256), 0, stream, a, b, n, nrhs, partial);
+    hipLaunchKernelGGL(dot_final_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, stream, partial, kDotBlocks, nrhs, out);
+    return hipGetLastError();
+}
+
+}  // namespace dwfmm

@@ -1,0 +1,427 @@
+// Host-side setup of the dimension weighted FMM (arXiv 2402.09531):
+//   weights (Thm 4.6, Sec 6.2), index set (Sec 4), Legendre basis and
+//   Vandermonde inverse (Sec 5.2), cluster tree (Sec 5.1), admissibility and
+//   block partition (Sec 5.2), nested transfer matrices (Sec 5.2).
+#include "setup.hpp"
+
+#include <algorithm>
+#include <cmath>
+#include <numeric>
+
+namespace dwfmm {
+
+// ------------------------------------------------------------------ weights
+bool compute_weights(int rule, int d, const double *b, double eta, const double *explicit_omega, double *omega,
+                     std::string &err)
+{
+    double bmax = 0.0;
+    for (int k = 0; k < d; ++k) bmax = std::max(bmax, b[k]);
+    auto g = [](double t) { return 2.0 * t + std::sqrt(1.0 + 4.0 * t * t); };
+    for (int k = 0; k < d; ++k) {
+        switch (rule) {
+        case 0:  // R1
+            omega[k] = std::max(1.0, std::log2(bmax / b[k]));
+            break;
+        case 1:  // R2
+            omega[k] = 1.0 + std::log2(bmax / b[k]);
+            break;
+        case 2: {  // R3, Sec 6.2 normalisation omega_1 = 1
+            double t1 = 1.0 / (eta * b[0]), tk = 1.0 / (eta * b[k]);
+            omega[k] = std::log(std::exp(1.0) * g(tk) / g(t1));
+            break;
+        }
+        case 3:
+            if (!explicit_omega) {
+                err = "explicit weight rule needs opts.omega";
+                return false;
+            }
+            omega[k] = explicit_omega[k];
+            break;
+        default:
+            err = "unknown weight rule";
+            return false;
+        }
+        if (!(omega[k] > 0.0) || !std::isfinite(omega[k])) {
+            err = "dimension weight omega_k must be finite and > 0";
+            return false;
+        }
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------ Legendre
+void legendre01(int m, double t, double *out)
+{
+    // P_j(s), s = 2t - 1, by (j+1) P_{j+1} = (2j+1) s P_j - j P_{j-1}; scaled by sqrt(2j+1).
+    const double s = 2.0 * t - 1.0;
+    double pm1 = 1.0, p = s;
+    out[0] = 1.0;
+    if (m >= 1) out[1] = std::sqrt(3.0) * s;
+    for (int j = 1; j < m; ++j) {
+        double pn = ((2.0 * j + 1.0) * s * p - j * pm1) / (j + 1.0);
+        pm1 = p;
+        p = pn;
+        out[j + 1] = std::sqrt(2.0 * (j + 1) + 1.0) * pn;
+    }
+}
+
+// ------------------------------------------------------------------ nodes
+// m+1 first-kind Chebyshev points on [0,1], ordered as a Leja sequence that
+// starts at the point nearest 1/2 (ties within 1e-9 go to the smaller point).
+static std::vector<double> leja_chebyshev(int m)
+{
+    if (m == 0) return {0.5};
+    const int n = m + 1;
+    const double pi = 3.14159265358979323846;
+    std::vector<double> pts(n);
+    for (int j = 0; j < n; ++j) pts[j] = (1.0 - std::cos((2.0 * j + 1.0) * pi / (2.0 * n))) / 2.0;
+    std::vector<double> seq;
+    std::vector<bool> taken(n, false);
+    // start
+    int s = 0;
+    for (int j = 1; j < n; ++j) {
+        double dj = std::fabs(pts[j] - 0.5), ds = std::fabs(pts[s] - 0.5);
+        double tol = 1e-9 * (ds > 0 ? ds : 1.0);
+        if (dj < ds - tol || (std::fabs(dj - ds) <= tol && pts[j] < pts[s])) s = j;
+    }
+    seq.push_back(pts[s]);
+    taken[s] = true;
+    while ((int)seq.size() < n) {
+        int best = -1;
+        double bv = 0.0;
+        for (int j = 0; j < n; ++j) {
+            if (taken[j]) continue;
+            double prod = 1.0;
+            for (double z : seq) prod *= std::fabs(pts[j] - z);
+            if (best < 0 || prod > bv * (1.0 + 1e-9) || (std::fabs(prod - bv) <= 1e-9 * bv && pts[j] < pts[best])) {
+                best = j;
+                bv = prod;
+            }
+        }
+        seq.push_back(pts[best]);
+        taken[best] = true;
+    }
+    return seq;
+}
+
+// LU factorisation with partial pivoting, then inverse column by column.
+static bool lu_inverse(int n, const std::vector<double> &A, std::vector<double> &inv)
+{
+    std::vector<double> LU(A);
+    std::vector<int> piv(n);
+    for (int k = 0; k < n; ++k) {
+        int p = k;
+        for (int i = k + 1; i < n; ++i)
+            if (std::fabs(LU[i * n + k]) > std::fabs(LU[p * n + k])) p = i;
+        if (LU[p * n + k] == 0.0) return false;
+        piv[k] = p;
+        if (p != k)
+            for (int j = 0; j < n; ++j) std::swap(LU[k * n + j], LU[p * n + j]);
+        for (int i = k + 1; i < n; ++i) {
+            LU[i * n + k] /= LU[k * n + k];
+            for (int j = k + 1; j < n; ++j) LU[i * n + j] -= LU[i * n + k] * LU[k * n + j];
+        }
+    }
+    inv.assign((size_t)n * n, 0.0);
+    std::vector<double> col(n);
+    for (int c = 0; c < n; ++c) {
+        std::fill(col.begin(), col.end(), 0.0);
+        col[c] = 1.0;
+        for (int k = 0; k < n; ++k)
+            if (piv[k] != k) std::swap(col[k], col[piv[k]]);
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < i; ++j) col[i] -= LU[i * n + j] * col[j];
+        for (int i = n - 1; i >= 0; --i) {
+            for (int j = i + 1; j < n; ++j) col[i] -= LU[i * n + j] * col[j];
+            col[i] /= LU[i * n + i];
+        }
+        for (int i = 0; i < n; ++i) inv[(size_t)i * n + c] = col[i];
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------ basis
+bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string &err)
+{
+    B = HostBasis();
+    B.d = d;
+    B.omega.assign(omega, omega + d);
+    // enumerate {alpha : sum_k omega_k alpha_k <= q} with an odometer over axes
+    std::vector<std::vector<uint8_t>> set;
+    std::vector<int> a(d, 0);
+    const double slack = 1e-9;
+    for (;;) {
+        double used = 0.0;
+        for (int k = 0; k < d; ++k) used += omega[k] * a[k];
+        if (used <= q + slack) {
+            set.emplace_back(a.begin(), a.end());
+            if (set.size() > 4096) {
+                err = "index set larger than 4096 entries";
+                return false;
+            }
+            a[0]++;  // advance the fastest axis
+            continue;
+        }
+        // overflow: reset the lowest non-zero axis and carry
+        int k = 0;
+        while (k < d && a[k] == 0) ++k;
+        if (k >= d - 1) break;
+        a[k] = 0;
+        a[k + 1]++;
+    }
+    // canonical order: weighted degree (summed over axes in order), then colex
+    std::vector<double> key(set.size());
+    for (size_t i = 0; i < set.size(); ++i) {
+        double w = 0.0;
+        for (int k = 0; k < d; ++k) w += omega[k] * set[i][k];
+        key[i] = w;
+    }
+    std::vector<size_t> ord(set.size());
+    std::iota(ord.begin(), ord.end(), 0);
+    std::sort(ord.begin(), ord.end(), [&](size_t x, size_t y) {
+        if (key[x] != key[y]) return key[x] < key[y];
+        for (int k = d - 1; k >= 0; --k)
+            if (set[x][k] != set[y][k]) return set[x][k] < set[y][k];
+        return false;
+    });
+    const int nx = (int)set.size();
+    B.nx = nx;
+    B.alpha.resize((size_t)nx * d);
+    for (int i = 0; i < nx; ++i)
+        for (int k = 0; k < d; ++k) B.alpha[(size_t)i * d + k] = set[ord[i]][k];
+    B.mk.assign(d, 0);
+    for (int i = 0; i < nx; ++i)
+        for (int k = 0; k < d; ++k) B.mk[k] = std::max<int>(B.mk[k], B.alpha[(size_t)i * d + k]);
+    // per-axis nodes; xi_alpha = (z^(1)_{alpha_1}, ..., z^(d)_{alpha_d})
+    B.xi.resize((size_t)nx * d);
+    for (int k = 0; k < d; ++k) {
+        std::vector<double> z = leja_chebyshev(B.mk[k]);
+        for (int i = 0; i < nx; ++i) B.xi[(size_t)i * d + k] = z[B.alpha[(size_t)i * d + k]];
+    }
+    // parent structure: beta = parent + beta_k e_k with k the last non-zero axis
+    B.par.assign(nx, -1);
+    B.pax.assign(nx, 0);
+    B.pdeg.assign(nx, 0);
+    for (int i = 1; i < nx; ++i) {
+        int k = d - 1;
+        while (B.alpha[(size_t)i * d + k] == 0) --k;
+        std::vector<uint8_t> p(B.alpha.begin() + (size_t)i * d, B.alpha.begin() + (size_t)(i + 1) * d);
+        p[k] = 0;
+        int found = -1;
+        for (int j = 0; j < i; ++j)
+            if (std::equal(p.begin(), p.end(), B.alpha.begin() + (size_t)j * d)) { found = j; break; }
+        if (found < 0) {
+            err = "index set is not a lower set";
+            return false;
+        }
+        B.par[i] = found;
+        B.pax[i] = k;
+        B.pdeg[i] = B.alpha[(size_t)i * d + k];
+    }
+    int off = 0;
+    for (int k = 0; k < d; ++k)
+        if (B.mk[k] > 0) {
+            B.act_axis.push_back(k);
+            B.act_off.push_back(off);
+            B.act_m.push_back(B.mk[k]);
+            off += B.mk[k] + 1;
+        }
+    B.nleg = off;
+    // Vandermonde V[a][b] = p_b(xi_a) and its inverse
+    std::vector<double> V((size_t)nx * nx);
+    std::vector<double> leg(256);
+    for (int i = 0; i < nx; ++i) {
+        std::vector<double> pv(nx);
+        pv[0] = 1.0;
+        std::vector<std::vector<double>> axv(d);
+        for (int k = 0; k < d; ++k) {
+            axv[k].resize(B.mk[k] + 1);
+            legendre01(B.mk[k], B.xi[(size_t)i * d + k], axv[k].data());
+        }
+        for (int j = 1; j < nx; ++j) pv[j] = pv[B.par[j]] * axv[B.pax[j]][B.pdeg[j]];
+        for (int j = 0; j < nx; ++j) V[(size_t)i * nx + j] = pv[j];
+    }
+    if (!lu_inverse(nx, V, B.Vinv)) {
+        err = "Vandermonde matrix is singular";
+        return false;
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------ tree
+bool build_tree(const double *pts, int64_t n, int d, const double *b, int leaf, double eta, HostTree &T,
+                std::string &err)
+{
+    T = HostTree();
+    T.n = n;
+    T.d = d;
+    T.leaf = leaf;
+    T.eta = eta;
+    T.b.assign(b, b + d);
+    int J = 0;
+    while ((n + ((int64_t)1 << J) - 1) >> J > leaf) ++J;
+    if (J > 30) {
+        err = "tree too deep";
+        return false;
+    }
+    T.J = J;
+    T.ncl = ((int64_t)1 << (J + 1)) - 1;
+    T.nleaf = (int64_t)1 << J;
+    T.perm.resize(n);
+    std::iota(T.perm.begin(), T.perm.end(), 0);
+    T.begin.assign(T.ncl, 0);
+    T.end.assign(T.ncl, 0);
+    T.lo.assign((size_t)T.ncl * d, 0.0);
+    T.hi.assign((size_t)T.ncl * d, 0.0);
+    T.begin[0] = 0;
+    T.end[0] = (int32_t)n;
+    for (int j = 0; j <= J; ++j) {
+        const int64_t first = ((int64_t)1 << j) - 1, last = ((int64_t)1 << (j + 1)) - 1;
+        for (int64_t c = first; c < last; ++c) {
+            const int32_t bgn = T.begin[c], e = T.end[c];
+            double *lo = &T.lo[(size_t)c * d], *hi = &T.hi[(size_t)c * d];
+            if (e > bgn) {
+                const double *x0 = pts + (size_t)T.perm[bgn] * d;
+                for (int k = 0; k < d; ++k) lo[k] = hi[k] = x0[k];
+                for (int32_t i = bgn + 1; i < e; ++i) {
+                    const double *x = pts + (size_t)T.perm[i] * d;
+                    for (int k = 0; k < d; ++k) {
+                        lo[k] = std::min(lo[k], x[k]);
+                        hi[k] = std::max(hi[k], x[k]);
+                    }
+                }
+            }
+            if (j == J) {
+                // canonical order inside a leaf: by original index
+                std::sort(T.perm.begin() + bgn, T.perm.begin() + e);
+                continue;
+            }
+            int axis = 0;
+            double ext = -1.0;
+            for (int k = 0; k < d; ++k) {
+                double w = e > bgn ? hi[k] - lo[k] : 0.0;
+                if (w > ext) {
+                    ext = w;
+                    axis = k;
+                }
+            }
+            const int32_t half = (e - bgn + 1) / 2;
+            if (e - bgn > 1) {
+                auto less = [&](int32_t u, int32_t v) {
+                    double xu = pts[(size_t)u * d + axis], xv = pts[(size_t)v * d + axis];
+                    return xu < xv || (xu == xv && u < v);
+                };
+                std::nth_element(T.perm.begin() + bgn, T.perm.begin() + bgn + half, T.perm.begin() + e, less);
+            }
+            T.begin[2 * c + 1] = bgn;
+            T.end[2 * c + 1] = bgn + half;
+            T.begin[2 * c + 2] = bgn + half;
+            T.end[2 * c + 2] = e;
+        }
+    }
+    // block partition from (root, root)
+    std::vector<std::pair<int32_t, int32_t>> far, near;
+    const double eta2 = eta * eta;
+    auto admissible = [&](int64_t u, int64_t v) {
+        const double *lu = &T.lo[(size_t)u * d], *hu = &T.hi[(size_t)u * d];
+        const double *lv = &T.lo[(size_t)v * d], *hv = &T.hi[(size_t)v * d];
+        double dist2 = 0.0, du = 0.0, dv = 0.0;
+        for (int k = 0; k < d; ++k) {
+            double gap = std::max(std::max(lv[k] - hu[k], lu[k] - hv[k]), 0.0);
+            dist2 += gap * gap;
+            du += (hu[k] - lu[k]) * (hu[k] - lu[k]);
+            dv += (hv[k] - lv[k]) * (hv[k] - lv[k]);
+        }
+        return dist2 >= eta2 * std::max(du, dv);
+    };
+    struct Item { int32_t u, v; int lev; };
+    std::vector<Item> stack{{0, 0, 0}};
+    while (!stack.empty()) {
+        Item it = stack.back();
+        stack.pop_back();
+        if (T.end[it.u] == T.begin[it.u] || T.end[it.v] == T.begin[it.v]) continue;
+        if (admissible(it.u, it.v)) {
+            far.push_back({it.u, it.v});
+        } else if (it.lev < J) {
+            // reverse push so that children pop in (1,1),(1,2),(2,1),(2,2) order
+            for (int i = 2; i >= 1; --i)
+                for (int k = 2; k >= 1; --k) stack.push_back({2 * it.u + i, 2 * it.v + k, it.lev + 1});
+        } else {
+            near.push_back({it.u, it.v});
+        }
+    }
+    auto csr = [&](std::vector<std::pair<int32_t, int32_t>> &pairs, std::vector<int32_t> &ptr,
+                   std::vector<int32_t> &src) {
+        std::stable_sort(pairs.begin(), pairs.end(),
+                         [](const std::pair<int32_t, int32_t> &x, const std::pair<int32_t, int32_t> &y) {
+                             return x.first < y.first || (x.first == y.first && x.second < y.second);
+                         });
+        ptr.assign(T.ncl + 1, 0);
+        src.resize(pairs.size());
+        for (auto &p : pairs) ptr[p.first + 1]++;
+        for (int64_t c = 0; c < T.ncl; ++c) ptr[c + 1] += ptr[c];
+        for (size_t i = 0; i < pairs.size(); ++i) src[i] = pairs[i].second;
+    };
+    csr(far, T.Fptr, T.Fsrc);
+    csr(near, T.Nptr, T.Nsrc);
+    T.min_far_level = J + 1;
+    for (auto &p : far) {
+        int lev = 0;
+        while ((((int64_t)1 << (lev + 1)) - 1) <= p.first) ++lev;
+        T.min_far_level = std::min(T.min_far_level, lev);
+    }
+    return true;
+}
+
+// ------------------------------------------------------------------ transfer
+static void ref_coords(const double *lo, const double *hi, const double *x, int d, double *t)
+{
+    for (int k = 0; k < d; ++k) t[k] = hi[k] > lo[k] ? (x[k] - lo[k]) / (hi[k] - lo[k]) : 0.5;
+}
+
+void box_nodes(const HostTree &T, const HostBasis &B, std::vector<double> &nodes)
+{
+    const int d = T.d, nx = B.nx;
+    nodes.assign((size_t)T.ncl * nx * d, 0.0);
+    for (int64_t c = 0; c < T.ncl; ++c) {
+        const double *lo = &T.lo[(size_t)c * d], *hi = &T.hi[(size_t)c * d];
+        for (int a = 0; a < nx; ++a)
+            for (int k = 0; k < d; ++k) {
+                double w = hi[k] - lo[k];
+                nodes[((size_t)c * nx + a) * d + k] = w > 0 ? lo[k] + B.xi[(size_t)a * d + k] * w : lo[k];
+            }
+    }
+}
+
+void transfer_matrices(const HostTree &T, const HostBasis &B, std::vector<double> &E)
+{
+    const int d = T.d, nx = B.nx;
+    E.assign((size_t)T.ncl * nx * nx, 0.0);
+    std::vector<double> x(d), t(d), pv(nx);
+    std::vector<std::vector<double>> axv(d);
+    for (int k = 0; k < d; ++k) axv[k].resize(B.mk[k] + 1);
+    for (int64_t c = 1; c < T.ncl; ++c) {
+        if (T.end[c] == T.begin[c]) continue;
+        const int64_t p = (c - 1) / 2;
+        const double *lc = &T.lo[(size_t)c * d], *hc = &T.hi[(size_t)c * d];
+        const double *lp = &T.lo[(size_t)p * d], *hp = &T.hi[(size_t)p * d];
+        for (int a = 0; a < nx; ++a) {
+            for (int k = 0; k < d; ++k) {
+                double w = hc[k] - lc[k];
+                x[k] = w > 0 ? lc[k] + B.xi[(size_t)a * d + k] * w : lc[k];
+            }
+            ref_coords(lp, hp, x.data(), d, t.data());
+            for (int k = 0; k < d; ++k) legendre01(B.mk[k], t[k], axv[k].data());
+            pv[0] = 1.0;
+            for (int j = 1; j < nx; ++j) pv[j] = pv[B.par[j]] * axv[B.pax[j]][B.pdeg[j]];
+            // l_b(t) = sum_g (V^-1)[g][b] p_g(t)
+            for (int bb = 0; bb < nx; ++bb) {
+                double s = 0.0;
+                for (int g = 0; g < nx; ++g) s += B.Vinv[(size_t)g * nx + bb] * pv[g];
+                E[((size_t)c * nx + a) * nx + bb] = s;
+            }
+        }
+    }
+}
+
+}  // namespace dwfmm

@@ -1,0 +1,61 @@
+// Host-side construction of the FMM structure: cluster tree, block partition,
+// index set, interpolation nodes, V^-1 and transfer matrices.  The data built
+// here is uploaded once; the matvec itself runs in HIP kernels.
+#pragma once
+#include <cstdint>
+#include <string>
+#include <vector>
+
+namespace dwfmm {
+
+constexpr int kMaxDim = 64;
+
+// Balanced binary cluster tree with heap numbering: cluster t of level j has id
+// 2^j - 1 + t, children 2c+1 and 2c+2.  Points are stored in tree order.
+struct HostTree {
+    int64_t n = 0;
+    int d = 0, leaf = 0, J = 0;
+    double eta = 0.0;
+    int64_t ncl = 0, nleaf = 0;
+    std::vector<double> b;               // box side lengths b_k (dimension weights)
+    std::vector<int32_t> perm;           // tree position -> original index
+    std::vector<int32_t> begin, end;     // point range of each cluster
+    std::vector<double> lo, hi;          // tight boxes, [ncl][d]
+    std::vector<int32_t> Fptr, Fsrc;     // farfield CSR over target clusters
+    std::vector<int32_t> Nptr, Nsrc;     // nearfield CSR over target clusters (leaves only)
+    int min_far_level = 0;               // first level holding a farfield block (J+1 if none)
+};
+
+// Index set Lambda_{omega,q,d}, nodes and Vandermonde inverse.
+struct HostBasis {
+    int d = 0, nx = 0;
+    std::vector<double> omega;           // [d]
+    std::vector<uint8_t> alpha;          // [nx][d], canonical order
+    std::vector<int> mk;                 // max_alpha alpha_k per axis
+    std::vector<double> xi;              // reference nodes [nx][d]
+    std::vector<double> Vinv;            // [nx][nx], row-major, (V^-1)[g][b]
+    // p_beta = p_{par[beta]} * p_{pdeg[beta]}(t_{pax[beta]}) for beta > 0
+    std::vector<int32_t> par, pax, pdeg;
+    // active axes (mk > 0), and offsets of their 1-D Legendre value blocks
+    std::vector<int32_t> act_axis, act_off, act_m;
+    int nleg = 0;                        // sum over active axes of (mk + 1)
+};
+
+bool build_tree(const double *pts_host, int64_t n, int d, const double *b, int leaf, double eta, HostTree &T,
+                std::string &err);
+
+bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string &err);
+
+bool compute_weights(int rule, int d, const double *b, double eta, const double *explicit_omega, double *omega,
+                     std::string &err);
+
+// Lagrange transfer matrices E_c[a][b] = l^parent_b(a_parent^-1(a_c(xi_a))), c >= 1.
+void transfer_matrices(const HostTree &T, const HostBasis &B, std::vector<double> &E);
+
+// Interpolation nodes of every box: nodes[c][a][k] = a_c(xi_a)_k.
+void box_nodes(const HostTree &T, const HostBasis &B, std::vector<double> &nodes);
+
+// Orthonormal Legendre values p_0..p_m at t on [0,1].
+void legendre01(int m, double t, double *out);
+
+}  // namespace dwfmm

@@ -1,0 +1,276 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 CPU oracle.
+
+FP64 mode must match the oracle to 1e-12 relative (norm-wise over the output,
+and every sampled row against the row scale |K| |x|).  Inputs come from the
+seeded generators in paper_2402_09531_amd.workloads and are handed identically
+to both sides.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2402_09531_amd as dw  # noqa: E402
+from paper_2402_09531_amd import workloads as W  # noqa: E402
+
+TOL = 1e-12
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def gpu_op(X, b, leaf, eta, kind, ell, q, nrhs=1, **kw):
+    Xd = torch.from_numpy(np.ascontiguousarray(X)).cuda()
+    tree = dw.build_tree(Xd, b, leaf, eta)
+    op = dw.fmm_create(tree, kind, ell, q, max_nrhs=nrhs, **kw)
+    return tree, op
+
+
+def gpu_matvec(op, x, parts=None):
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    yd = torch.empty_like(xd)
+    dw.fmm_matvec(op, xd, yd, parts=parts)
+    torch.cuda.synchronize()
+    return yd.cpu().numpy()
+
+
+def rel(a, b):
+    return np.linalg.norm(a - b) / np.linalg.norm(b)
+
+
+CASES = [
+    # name, n, d, r, kernel, ell, q, leaf, eta, nrhs
+    ("small_d4_matern", 4096, 4, 2.0, "matern32", 1.0, 4, 64, 0.8, 1),
+    ("ragged_d4_gauss", 5001, 4, 2.0, "gaussian", 0.5, 4, 64, 0.8, 2),
+    ("d10_matern", 30000, 10, 2.0, "matern32", 1.0, 6, 128, 0.8, 1),
+    ("d20_gauss", 30011, 20, 3.0, "gaussian", 0.5, 6, 128, 0.8, 1),
+    ("d20_gauss_r3", 20000, 20, 3.0, "gaussian", 0.5, 6, 128, 0.8, 3),
+    ("d7_exp", 9000, 7, 2.0, "exponential", 0.3, 5, 100, 0.5, 1),
+    ("d1_matern", 3000, 1, 0.0, "matern32", 1.0, 5, 32, 0.8, 1),
+    ("d24_matern", 8000, 24, 3.0, "matern32", 1.0, 6, 128, 0.8, 1),
+    # general (non-symmetric) nearfield kernel: leaves above 128 points, d above 32
+    ("d3_leaf200", 20000, 3, 2.0, "matern32", 1.0, 5, 200, 0.8, 1),
+    ("d40_gauss", 5000, 40, 3.0, "gaussian", 0.5, 6, 128, 0.8, 1),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=[c[0] for c in CASES])
+def test_matvec_parity_fp64(orc, case):
+    name, n, d, r, kind, ell, q, leaf, eta, nrhs = case
+    say(f"[parity] {name} n={n} d={d} nrhs={nrhs}")
+    rng = np.random.default_rng(100 + n)
+    X = W.points(n, d, r, n, rng)
+    b = W.dim_weights(d, r) if r > 0 else np.ones(d)
+    x = rng.standard_normal((n, nrhs))
+    P = orc.Plan(X, b, leaf, eta, kind, ell, q)
+    tree, op = gpu_op(X, b, leaf, eta, kind, ell, q, nrhs=nrhs)
+    assert op.nx == P.nx and tree.J == P.J and tree.nF == P.nF and tree.nN == P.nN
+    y_ref = P.matvec(x)
+    y = gpu_matvec(op, x)
+    # parts separately (diagnostic and stronger: each part is itself within tolerance)
+    for parts in (1, 2):
+        yr = P.matvec(x, parts=parts)
+        yg = gpu_matvec(op, x, parts=parts)
+        if np.linalg.norm(yr) > 0:
+            assert rel(yg, yr) <= TOL, (parts, rel(yg, yr))
+    e = rel(y, y_ref)
+    say(f"   rel err {e:.3e}")
+    assert e <= TOL
+    scale = np.abs(y_ref).max()
+    assert np.abs(y - y_ref).max() <= 10 * TOL * scale
+
+
+def test_tree_and_partition_identical(orc):
+    """Same leaves (as point sets), bitwise identical boxes, identical farfield/nearfield blocks."""
+    n, d = 20000, 20
+    X = W.points(n, d, 3.0, 7)
+    b = W.dim_weights(d, 3.0)
+    P = orc.Plan(X, b, 128, 0.8, "gaussian", 0.5, 6)
+    tree, _ = gpu_op(X, b, 128, 0.8, "gaussian", 0.5, 6)
+    To, Tg = P.tree(), tree.host()
+    assert np.array_equal(To["begin"], Tg["begin"]) and np.array_equal(To["end"], Tg["end"])
+    assert np.array_equal(To["lo"], Tg["lo"]) and np.array_equal(To["hi"], Tg["hi"])
+    for c in range(P.ncl):
+        a = np.sort(To["perm"][To["begin"][c]:To["end"][c]])
+        g = np.sort(Tg["perm"][Tg["begin"][c]:Tg["end"][c]])
+        assert np.array_equal(a, g)
+    Lo = P.lists()
+    for key in ("Fptr", "Nptr"):
+        assert np.array_equal(Lo[key], Tg[key])
+    for c in range(P.ncl):
+        for ptr, src in (("Fptr", "Fsrc"), ("Nptr", "Nsrc")):
+            s0, s1 = Lo[ptr][c], Lo[ptr][c + 1]
+            assert sorted(Lo[src][s0:s1]) == sorted(Tg[src][s0:s1])
+
+
+def test_basis_identical_to_oracle(orc):
+    X = W.points(5000, 10, 2.0, 3)
+    b = W.dim_weights(10, 2.0)
+    P = orc.Plan(X, b, 128, 0.8, "matern32", 1.0, 6)
+    _, op = gpu_op(X, b, 128, 0.8, "matern32", 1.0, 6)
+    Bo, Bg = P.basis(), op.basis()
+    assert np.array_equal(Bo["alpha"], Bg["alpha"])
+    assert np.allclose(Bo["xi"], Bg["xi"], rtol=0, atol=1e-15)
+    assert np.allclose(Bo["Vinv"], Bg["Vinv"], rtol=1e-12, atol=1e-12)
+    assert np.allclose(Bo["omega"], Bg["omega"], rtol=0, atol=1e-15)
+
+
+def test_lagrange_moments_match_oracle(orc):
+    """Stage check: the library's Lagrange moments equal V^-T (oracle Legendre moments)."""
+    n, d = 8000, 4
+    X = W.points(n, d, 2.0, 17)
+    b = W.dim_weights(d, 2.0)
+    x = np.random.default_rng(5).standard_normal((n, 1))
+    P = orc.Plan(X, b, 64, 0.8, "matern32", 1.0, 4)
+    _, mom, _ = P.matvec(x, parts=2, want_moments=True)
+    _, op = gpu_op(X, b, 64, 0.8, "matern32", 1.0, 4)
+    gpu_matvec(op, x)
+    mg, _ = op.moments(1)
+    Vinv = P.basis()["Vinv"]
+    J = P.J
+    Ls = P.lists()
+    has_far = np.nonzero(np.diff(Ls["Fptr"]))[0]
+    min_level = int(np.floor(np.log2(has_far.min() + 1)))
+    assert min_level <= J
+    # the library forms moments only on levels that take part in the farfield
+    for c in range(2 ** min_level - 1, 2 ** (J + 1) - 1):
+        want = Vinv.T @ mom[c, :, 0]
+        assert np.allclose(mg[c, :, 0], want, rtol=1e-11, atol=1e-11 * np.abs(want).max())
+
+
+def test_full_size_sampled_rows(orc):
+    """N = 1e6, d = 20 (Gaussian, q = 6, leaf 128, eta 0.8): rows of a sample of target leaves,
+    computed by the oracle one leaf at a time, against the GPU matvec at full size."""
+    w = W.WORKLOADS["n1m_d20"]
+    say("[full-size] building inputs n=1e6 d=20")
+    X, b, x = W.make(w)
+    tree, op = gpu_op(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q)
+    y = gpu_matvec(op, x)
+    P = orc.Plan(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q)
+    T = P.tree()
+    rng = np.random.default_rng(1)
+    leaves = sorted(rng.choice(2 ** P.J, size=6, replace=False).tolist()) + [0, 2 ** P.J - 1]
+    for l in leaves:
+        yr = P.matvec(x, leaf_range=(l, l + 1))
+        c = 2 ** P.J - 1 + l
+        idx = T["perm"][T["begin"][c]:T["end"][c]]
+        e = np.linalg.norm(y[idx] - yr[idx]) / np.linalg.norm(yr[idx])
+        say(f"   leaf {l}: rel err {e:.3e}")
+        assert e <= TOL
+
+
+def test_deterministic_bitwise():
+    w = W.WORKLOADS["small_d4"]
+    X, b, x = W.make(w)
+    _, op = gpu_op(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q)
+    y1 = gpu_matvec(op, x)
+    y2 = gpu_matvec(op, x)
+    assert np.array_equal(y1, y2)
+
+
+@pytest.mark.parametrize("n,leaf", [(1, 64), (50, 64), (5, 1), (129, 64)])
+def test_edge_sizes(orc, n, leaf):
+    """One point, a single leaf (no farfield), empty clusters (leaf 1), a ragged last level."""
+    X = W.points(n, 3, 2.0, 9)
+    b = W.dim_weights(3, 2.0)
+    x = np.random.default_rng(2).standard_normal((n, 1))
+    P = orc.Plan(X, b, leaf, 0.8, "matern32", 1.0, 4)
+    _, op = gpu_op(X, b, leaf, 0.8, "matern32", 1.0, 4)
+    y = gpu_matvec(op, x)
+    assert rel(y, P.matvec(x)) <= TOL
+
+
+def test_poly_kernel_exact_against_dense():
+    """A kernel inside P_Lambda x P_Lambda is reproduced exactly by the farfield."""
+    import pinlib as PL
+    n = 3000
+    X = W.points(n, 4, 2.0, 4)
+    b = W.dim_weights(4, 2.0)
+    x = np.random.default_rng(3).standard_normal((n, 1))
+    _, op = gpu_op(X, b, 32, 0.8, "poly", 4.0, 4)
+    y = gpu_matvec(op, x)
+    yd = PL.kernel_matrix("poly", 4.0, X, X) @ x
+    assert rel(y, yd) <= 1e-12
+
+
+@pytest.mark.parametrize("q,lam", [(4, 0.1), (8, 0.01)])
+def test_cg_solve_residual_under_oracle(orc, q, lam):
+    """CG on (K~ + lambda I) alpha = f where the shifted operator is positive definite: the GPU's
+    alpha has an oracle-measured residual <= rtol and equals the oracle CG's solution."""
+    w = W.WORKLOADS["small_d4"]
+    X, b, _ = W.make(w)
+    f = W.rhs(w, X)[:, None]
+    P = orc.Plan(X, b, w.leaf, w.eta, w.kernel, w.ell, q)
+    _, op = gpu_op(X, b, w.leaf, w.eta, w.kernel, w.ell, q)
+    fd = torch.from_numpy(f).cuda()
+    ad = torch.zeros_like(fd)
+    rtol = 1e-10
+    info = dw.fmm_solve(op, lam, fd, ad, rtol, 20000)[0]
+    say(f"   cg info {info}")
+    assert info["status"] == 0
+    a = ad.cpu().numpy()
+    res = np.linalg.norm(f - (P.matvec(a) + lam * a)) / np.linalg.norm(f)
+    assert res <= 1.05 * rtol
+    assert abs(res - info["rel_res_true"]) <= 1e-3 * rtol
+    ao, io = P.cg(lam, f, rtol, 20000)
+    assert io[0]["status"] == 0
+    assert np.linalg.norm(a - ao) / np.linalg.norm(ao) <= 1e-6
+
+
+def test_cg_indefinite_small_lambda_reported(orc):
+    """The small workload's own ridge lambda = 1e-6 is below the FMM error, so K~ + lambda I is
+    indefinite (lowest eigenvalue about -0.48 at q = 4): both CGs take negative-curvature steps
+    and report non-convergence; the reported true residual matches the oracle's measurement."""
+    w = W.WORKLOADS["small_d4"]
+    X, b, _ = W.make(w)
+    f = W.rhs(w, X)[:, None]
+    P = orc.Plan(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q)
+    _, op = gpu_op(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q)
+    fd = torch.from_numpy(f).cuda()
+    ad = torch.zeros_like(fd)
+    info = dw.fmm_solve(op, w.lam, fd, ad, w.rtol, 2000)[0]
+    _, io = P.cg(w.lam, f, w.rtol, 2000)
+    say(f"   gpu {info}  oracle {io[0]}")
+    assert info["status"] == dw.E_NOT_CONVERGED and io[0]["status"] == 1
+    assert info["neg_curvature_steps"] > 0 and io[0]["neg_curvature_steps"] > 0
+    a = ad.cpu().numpy()
+    res = np.linalg.norm(f - (P.matvec(a) + w.lam * a)) / np.linalg.norm(f)
+    assert abs(res - info["rel_res_true"]) <= 1e-6 * res
+
+
+def test_cg_not_converged_reported():
+    w = W.WORKLOADS["small_d4"]
+    X, b, _ = W.make(w)
+    _, op = gpu_op(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q)
+    fd = torch.from_numpy(W.rhs(w, X)[:, None]).cuda()
+    ad = torch.zeros_like(fd)
+    info = dw.fmm_solve(op, 1e-6, fd, ad, 1e-14, 3)[0]
+    assert info["status"] == dw.E_NOT_CONVERGED and info["iters"] == 3
+
+
+def test_invalid_arguments():
+    X = torch.from_numpy(W.points(100, 3, 2.0, 1)).cuda()
+    b = W.dim_weights(3, 2.0)
+    with pytest.raises(dw.DwfmmError) as e:
+        dw.build_tree(X, b, 0, 0.8)
+    assert e.value.status == dw.E_INVALID
+    with pytest.raises(dw.DwfmmError):
+        dw.build_tree(X, b, 16, -1.0)
+    Xn = X.clone()
+    Xn[3, 1] = float("nan")
+    with pytest.raises(dw.DwfmmError) as e:
+        dw.build_tree(Xn, b, 16, 0.8)
+    assert e.value.status == dw.E_NONFINITE
+    tree = dw.build_tree(X, b, 16, 0.8)
+    with pytest.raises(dw.DwfmmError):
+        dw.fmm_create(tree, "matern32", -1.0, 4)
+    op = dw.fmm_create(tree, "matern32", 1.0, 4)
+    x = torch.zeros(100, 2, dtype=torch.float64, device="cuda")
+    with pytest.raises(dw.DwfmmError):
+        dw.fmm_matvec(op, x, torch.empty_like(x))   # nrhs 2 > max_nrhs 1
