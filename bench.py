@@ -56,7 +56,35 @@ def cpu_baseline(w, X, b, x, budget_leaves: int):
     }
 
 
+def summarize_profile(path: str) -> None:
+    """Print a per-kernel summary of rocprofv3 CSV output under `path`: counter means per
+    dispatch (``*_counter_collection.csv``) and kernel duration statistics (``*_kernel_stats.csv``)."""
+    import csv
+    import glob
+    from collections import defaultdict
+
+    def short(name):
+        return name.replace("dwfmm::(anonymous namespace)::", "").replace("void ", "").split("(")[0]
+
+    agg = defaultdict(lambda: defaultdict(list))
+    for f in sorted(glob.glob(os.path.join(path, "**", "*_counter_collection.csv"), recursive=True)):
+        for r in csv.DictReader(open(f)):
+            agg[short(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    for k, d in sorted(agg.items()):
+        print(f"{k}")
+        for c, v in sorted(d.items()):
+            print(f"    {c:28s} dispatches={len(v):4d} mean={sum(v) / len(v):.6g}")
+    for f in sorted(glob.glob(os.path.join(path, "**", "*_kernel_stats.csv"), recursive=True)):
+        print(f"kernel stats ({os.path.basename(f)}):")
+        for r in csv.DictReader(open(f)):
+            print(f"    {short(r['Name'])[:60]:60s} calls={r['Calls']:>5s} avg_ns={float(r['AverageNs']):12.1f} "
+                  f"pct={float(r['Percentage']):6.2f}")
+
+
 def main():
+    if len(sys.argv) == 3 and sys.argv[1] == "--summarize":
+        summarize_profile(sys.argv[2])
+        return
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
@@ -67,6 +95,8 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--cpu-leaves", type=int, default=1 << 30, help="oracle sample size in target leaves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="before timing, run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -106,6 +136,14 @@ def main():
     log(f"[bench] setup tree {t_tree:.2f}s create {t_create:.2f}s J={tree.J} nx={op.nx} nF={tree.nF} "
         f"nN={tree.nN} E_N={EN:.4g}")
 
+    if args.calib_copy_mib:
+        src = torch.ones(args.calib_copy_mib << 17, dtype=torch.float64, device=dev)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)   # one elementwise kernel: reads src, writes dst
+        torch.cuda.synchronize()
+        log(f"[bench] calibration copy: {args.calib_copy_mib} MiB read, {args.calib_copy_mib} MiB written")
+        del src, dst
     for _ in range(args.warmup):
         dw.fmm_matvec(op, xd, yd)
     torch.cuda.synchronize()

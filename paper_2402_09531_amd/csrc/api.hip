@@ -70,7 +70,8 @@ struct Arena {
         }                                                                                         \
     } while (0)
 
-int pad_dim(int d) { return d <= 24 ? (d + 1) / 2 * 2 : (d + 7) / 8 * 8; }
+// coordinate rows stored per point: a multiple of 4 (the MFMA k-chunk) up to 32, of 8 beyond
+int pad_dim(int d) { return d <= 32 ? (d + 3) / 4 * 4 : (d + 7) / 8 * 8; }
 
 }  // namespace
 
@@ -302,6 +303,19 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
         for (int a = 0; a < nx; ++a)
             for (int k = 0; k < H.d; ++k)
                 nodes_p[((size_t)c * nx + a) * dp + k] = nodes[((size_t)c * nx + a) * H.d + k];
+    // axis-major zero-padded copy for the MFMA coupling kernel, and squared node norms
+    const int dk = (H.d + 3) / 4 * 4, nxp = (nx + 15) / 16 * 16;
+    std::vector<double> nodesT((size_t)H.ncl * dk * nxp, 0.0), nnorm((size_t)H.ncl * nxp, 0.0);
+    for (int64_t c = 0; c < H.ncl; ++c)
+        for (int a = 0; a < nx; ++a) {
+            double s = 0.0;
+            for (int k = 0; k < H.d; ++k) {
+                const double v = nodes[((size_t)c * nx + a) * H.d + k];
+                nodesT[((size_t)c * dk + k) * nxp + a] = v;
+                s += v * v;
+            }
+            nnorm[(size_t)c * nxp + a] = s;
+        }
     transfer_matrices(H, B, E);
     // Legendre slots (axis, degree >= 1) and, per basis function, the slots whose product it is
     std::vector<int32_t> leg_axis, leg_deg;
@@ -342,7 +356,9 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     double *dnodes, *dE, *dVinv, *dLb, *dxt, *dM, *dL;
     int32_t *dlidx, *dla, *dld;
     hipError_t e = hipSuccess;
+    double *dnodesT, *dnnorm;
     if ((e = up(&dnodes, nodes_p)) != hipSuccess || (e = up(&dE, E)) != hipSuccess ||
+        (e = up(&dnodesT, nodesT)) != hipSuccess || (e = up(&dnnorm, nnorm)) != hipSuccess ||
         (e = up(&dVinv, B.Vinv)) != hipSuccess || (e = up(&dlidx, lidx)) != hipSuccess ||
         (e = up(&dla, leg_axis)) != hipSuccess || (e = up(&dld, leg_deg)) != hipSuccess ||
         (e = op->arena.alloc((void **)&dLb, sizeof(double) * nx * n)) != hipSuccess ||
@@ -373,6 +389,9 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     D.nx = nx;
     D.max_nrhs = o.max_nrhs;
     D.nodes = dnodes;
+    D.nxp = nxp;
+    D.nodesT = dnodesT;
+    D.nnorm = dnnorm;
     D.E = dE;
     D.Lb = dLb;
     D.xt = dxt;

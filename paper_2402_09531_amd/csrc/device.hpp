@@ -36,6 +36,9 @@ struct DevOp {
     const double *Lb;             // [nx][n] Lagrange basis l_a(a_leaf^-1 x_i), tree order
     double *xt;                   // [n][max_nrhs] x in tree order
     double *M, *L;                // [ncl][nx][max_nrhs] moments and locals
+    int nxp;                      // nx rounded up to a multiple of 16
+    const double *nodesT;         // [ncl][dk][nxp] nodes, axis-major, zero padded (dk = d rounded up to 4)
+    const double *nnorm;          // [ncl][nxp] squared norms of the nodes, zero padded
     double *rowbuf;               // [nleaf][128] owner-side nearfield row sums (one rhs)
     double *colbuf;               // [nblk][128] column sums of owned blocks (one rhs)
 };

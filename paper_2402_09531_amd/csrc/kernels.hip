@@ -17,6 +17,7 @@ namespace {
 
 constexpr int kMaxNx = 64;
 constexpr int kMaxNodeWords = 1536;  // nx * dpad bound of the M2L node tiles
+typedef double dbl4 __attribute__((ext_vector_type(4)));  // accumulator of v_mfma_f64_16x16x4f64
 
 template <int KIND>
 __device__ __forceinline__ double kernel_val(double r2, double inv_ell)
@@ -195,6 +196,100 @@ __global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first,
     }
 }
 
+// ---------------------------------------------------------------- M2L on MFMA (one rhs)
+// l_c[a] = sum over farfield sources s of sum_b K(t_a, s_b) m_s[b]: the node-pair
+// distances take their cross term from FP64 MFMA 16x16x4 tiles (NXT x NXT tiles
+// per block pair), the kernel values and the product with the moments run on the
+// vector ALU.  The four waves split the source list; their partial sums are added
+// in a fixed order.
+template <int KIND, int DK, int NXT>
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(DevTree T, DevOp O, int first)
+{
+    constexpr int NKC = DK / 4, NXP = 16 * NXT;
+    __shared__ double part[4 * NXP];
+    const int c = first + blockIdx.x;
+    const int nx = O.nx;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int f0 = T.Fptr[c], f1 = T.Fptr[c + 1];
+    const double inv_ell = 1.0 / O.ell;
+    const double *tnode = O.nodesT + (size_t)c * DK * NXP;
+    double A[NXT][NKC], tn[NXT][4], racc[NXT][4];
+#pragma unroll
+    for (int rt = 0; rt < NXT; ++rt) {
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) A[rt][kc] = tnode[(4 * kc + lg) * NXP + 16 * rt + li];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            tn[rt][v] = O.nnorm[(size_t)c * NXP + 16 * rt + 4 * v + lg];
+            racc[rt][v] = 0.0;
+        }
+    }
+    for (int f = f0 + w; f < f1; f += 4) {
+        const int s = T.Fsrc[f];
+        const double *snode = O.nodesT + (size_t)s * DK * NXP;
+#pragma unroll
+        for (int ct = 0; ct < NXT; ++ct) {
+            const int b = 16 * ct + li;
+            double B[NKC];
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) B[kc] = snode[(4 * kc + lg) * NXP + b];
+            const double nb = O.nnorm[(size_t)s * NXP + b];
+            const double mb = b < nx ? O.M[(size_t)s * nx + b] : 0.0;
+#pragma unroll
+            for (int rt = 0; rt < NXT; ++rt) {
+                dbl4 G = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[rt][kc], B[kc], G, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const double r2 = fmax(fma(-2.0, G[v], tn[rt][v] + nb), 0.0);
+                    racc[rt][v] = fma(kernel_val<KIND>(r2, inv_ell), mb, racc[rt][v]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < NXT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double s = racc[rt][v];
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            s += __shfl_xor(s, 4, 64);
+            s += __shfl_xor(s, 8, 64);
+            if (li == 0) part[w * NXP + 16 * rt + 4 * v + lg] = s;
+        }
+    __syncthreads();
+    if (tid < nx) O.L[(size_t)c * nx + tid] = ((part[tid] + part[NXP + tid]) + part[2 * NXP + tid]) + part[3 * NXP + tid];
+}
+
+template <int KIND, int DK>
+void launch_m2l_mfma_d(const DevTree &T, const DevOp &O, int first, int cnt, hipStream_t st)
+{
+    switch (O.nxp / 16) {
+    case 1: hipLaunchKernelGGL((m2l_mfma_kernel<KIND, DK, 1>), dim3(cnt), dim3(256), 0, st, T, O, first); break;
+    case 2: hipLaunchKernelGGL((m2l_mfma_kernel<KIND, DK, 2>), dim3(cnt), dim3(256), 0, st, T, O, first); break;
+    case 3: hipLaunchKernelGGL((m2l_mfma_kernel<KIND, DK, 3>), dim3(cnt), dim3(256), 0, st, T, O, first); break;
+    default: hipLaunchKernelGGL((m2l_mfma_kernel<KIND, DK, 4>), dim3(cnt), dim3(256), 0, st, T, O, first); break;
+    }
+}
+
+template <int KIND>
+void launch_m2l_mfma_k(const DevTree &T, const DevOp &O, int first, int cnt, hipStream_t st)
+{
+    switch ((T.d + 3) / 4 * 4) {
+    case 4: launch_m2l_mfma_d<KIND, 4>(T, O, first, cnt, st); break;
+    case 8: launch_m2l_mfma_d<KIND, 8>(T, O, first, cnt, st); break;
+    case 12: launch_m2l_mfma_d<KIND, 12>(T, O, first, cnt, st); break;
+    case 16: launch_m2l_mfma_d<KIND, 16>(T, O, first, cnt, st); break;
+    case 20: launch_m2l_mfma_d<KIND, 20>(T, O, first, cnt, st); break;
+    case 24: launch_m2l_mfma_d<KIND, 24>(T, O, first, cnt, st); break;
+    case 28: launch_m2l_mfma_d<KIND, 28>(T, O, first, cnt, st); break;
+    default: launch_m2l_mfma_d<KIND, 32>(T, O, first, cnt, st); break;
+    }
+}
+
 // ---------------------------------------------------------------- L2L, one level
 __global__ __launch_bounds__(64) void l2l_kernel(DevTree T, DevOp O, int first, int nrhs)
 {
@@ -287,9 +382,8 @@ hipError_t launch_p2p_k(const DevTree &T, const DevOp &O, double *y, int nrhs, i
     switch (T.dpad) {
 #define DWFMM_CASE(D) \
     case D: launch_p2p_t<KIND, D>(T, O, y, nrhs, near, far, st); break;
-        DWFMM_CASE(2) DWFMM_CASE(4) DWFMM_CASE(6) DWFMM_CASE(8) DWFMM_CASE(10) DWFMM_CASE(12)
-        DWFMM_CASE(14) DWFMM_CASE(16) DWFMM_CASE(18) DWFMM_CASE(20) DWFMM_CASE(22) DWFMM_CASE(24)
-        DWFMM_CASE(32) DWFMM_CASE(40) DWFMM_CASE(48) DWFMM_CASE(56) DWFMM_CASE(64)
+        DWFMM_CASE(4) DWFMM_CASE(8) DWFMM_CASE(12) DWFMM_CASE(16) DWFMM_CASE(20) DWFMM_CASE(24)
+        DWFMM_CASE(28) DWFMM_CASE(32) DWFMM_CASE(40) DWFMM_CASE(48) DWFMM_CASE(56) DWFMM_CASE(64)
 #undef DWFMM_CASE
     default:
         return hipErrorInvalidValue;
@@ -306,7 +400,6 @@ hipError_t launch_p2p_k(const DevTree &T, const DevOp &O, double *y, int nrhs, i
 // pass, in a fixed order (no atomics, bitwise reproducible).
 // Lane layout of v_mfma_f64_16x16x4f64: A[i][k] in lane i + 16k, B[k][j] in lane
 // j + 16k, D[i][j] in lane j + 16(i%4), element i/4 (checked with a probe).
-typedef double dbl4 __attribute__((ext_vector_type(4)));
 constexpr int kSymLeaf = 128;
 
 template <int KIND, int DK>
@@ -330,29 +423,39 @@ __global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
     const double inv_ell = 1.0 / O.ell;
     const int ntiles = (nt + 15) / 16;
 
-    if (tid < DK) cen[tid] = tid < d ? T.center[(size_t)l * T.dpad + tid] : 0.0;
+    if (nt == 0) return;  // an empty leaf owns no block (uniform over the workgroup)
+    // Coordinate rows k in [d, DK) are stored as zeros and cen[k] = 0 there, so every load
+    // below is unconditional; point indices past the end of a leaf are clamped and masked.
+    if (tid < DK) cen[tid] = T.center[(size_t)l * DK + tid];
     __syncthreads();
     if (tid < kSymLeaf) {
-        double s = 0.0, q = 0.0;
-        if (tid < nt) {
-            for (int k = 0; k < d; ++k) {
-                const double v = T.Xs[(size_t)k * n + cb + tid] - cen[k];
-                s = fma(v, v, s);
-            }
-            q = O.xt[cb + tid];
+        const bool ok = tid < nt;
+        const int ii = cb + (ok ? tid : nt - 1);
+        double xv[DK];
+#pragma unroll
+        for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + ii];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+            const double v = xv[k] - cen[k];
+            s = fma(v, v, s);
         }
-        tN[tid] = s;
-        tQ[tid] = q;
+        const double q = O.xt[ii];
+        tN[tid] = ok ? s : 0.0;
+        tQ[tid] = ok ? q : 0.0;
     }
     const int rt[2] = {w, w + 4};
     double A[2][NKC];
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int i = 16 * rt[u] + li;
+        const bool ok = i < nt;
+        const int ii = cb + (ok ? i : nt - 1);
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
             const int k = 4 * kc + lg;
-            A[u][kc] = (i < nt && k < d) ? T.Xs[(size_t)k * n + cb + i] - cen[k] : 0.0;
+            const double v = T.Xs[(size_t)k * n + ii] - cen[k];
+            A[u][kc] = ok ? v : 0.0;
         }
     }
     __syncthreads();
@@ -376,17 +479,23 @@ __global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
         __syncthreads();
         if (tid < kSymLeaf) {
             const int j = tid;
+            const bool ok = j < ns;  // every listed leaf holds at least one point
+            const int jj = sb + (ok ? j : ns - 1);
+            double xv[DK];
+#pragma unroll
+            for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + jj];
             double s = 0.0;
 #pragma unroll
             for (int k = 0; k < DK; ++k) {
-                const double v = (j < ns && k < d) ? T.Xs[(size_t)k * n + sb + j] - cen[k] : 0.0;
+                const double v = ok ? xv[k] - cen[k] : 0.0;
                 sX[k * kSymLeaf + j] = v;
                 s = fma(v, v, s);
             }
             sN[j] = s;
         } else {
             const int j = tid - kSymLeaf;
-            sQ[j] = j < ns ? O.xt[sb + j] : 0.0;
+            const double q = O.xt[sb + (j < ns ? j : ns - 1)];
+            sQ[j] = j < ns ? q : 0.0;
         }
         __syncthreads();
         const int nct = (ns + 15) / 16;
@@ -530,11 +639,20 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
         const int first = (1 << T.min_far_level) - 1;
         const int cnt = T.ncl - first;
         if (timer) (void)hipEventRecord(timer->m2l_start, st);
-        switch (O.kind) {
-        case 0: hipLaunchKernelGGL(m2l_kernel<0>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
-        case 1: hipLaunchKernelGGL(m2l_kernel<1>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
-        case 2: hipLaunchKernelGGL(m2l_kernel<2>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
-        default: hipLaunchKernelGGL(m2l_kernel<3>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+        const bool mfma = nrhs == 1 && O.kind <= 2 && T.d <= 32 && O.nxp <= 64 && O.nodesT && O.nnorm;
+        if (mfma) {
+            switch (O.kind) {
+            case 0: launch_m2l_mfma_k<0>(T, O, first, cnt, st); break;
+            case 1: launch_m2l_mfma_k<1>(T, O, first, cnt, st); break;
+            default: launch_m2l_mfma_k<2>(T, O, first, cnt, st); break;
+            }
+        } else {
+            switch (O.kind) {
+            case 0: hipLaunchKernelGGL(m2l_kernel<0>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+            case 1: hipLaunchKernelGGL(m2l_kernel<1>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+            case 2: hipLaunchKernelGGL(m2l_kernel<2>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+            default: hipLaunchKernelGGL(m2l_kernel<3>, dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+            }
         }
         if (timer) (void)hipEventRecord(timer->m2l_stop, st);
         for (int j = T.min_far_level + 1; j <= T.J; ++j)
