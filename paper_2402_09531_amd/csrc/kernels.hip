@@ -19,6 +19,46 @@ constexpr int kMaxNx = 64;
 constexpr int kMaxNodeWords = 1536;  // nx * dpad bound of the M2L node tiles
 typedef double dbl4 __attribute__((ext_vector_type(4)));  // accumulator of v_mfma_f64_16x16x4f64
 
+// e^x for x <= 0 in FP64 without special-case branches: Cody-Waite reduction
+// x = n ln2 + r, |r| <= ln2/2, with a two-part ln2, then a degree-11 polynomial
+// for e^r (coefficients: the interpolant of e^r at 12 first-kind Chebyshev points
+// of [-ln2/2, ln2/2], from csrc/gen_exp_coeffs.py), scaled by 2^n.  Arguments
+// below -745 (where e^x underflows to zero) are clamped.
+__device__ __forceinline__ double exp_nonpos(double x)
+{
+    x = fmax(x, -745.0);
+    const double n = rint(x * 1.4426950408889634);
+    double r = fma(-n, 0.6931471805599453, x);
+    r = fma(-n, 2.3201926491189795e-17, r);
+    double p = 2.510908360165664e-08;
+    p = fma(p, r, 2.763264649558832e-07);
+    p = fma(p, r, 2.7557243462120405e-06);
+    p = fma(p, r, 2.4801485463689334e-05);
+    p = fma(p, r, 0.0001984126988784416);
+    p = fma(p, r, 0.001388888895233475);
+    p = fma(p, r, 0.008333333333320283);
+    p = fma(p, r, 0.04166666666648798);
+    p = fma(p, r, 0.1666666666666668);
+    p = fma(p, r, 0.5000000000000019);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)n);
+}
+
+// Kernel value from the squared distance, with the branch-free exponential.
+template <int KIND>
+__device__ __forceinline__ double kernel_fast(double r2, double inv_ell)
+{
+    if constexpr (KIND == 0) {
+        const double s = 1.7320508075688772 * sqrt(r2) * inv_ell;
+        return (1.0 + s) * exp_nonpos(-s);
+    } else if constexpr (KIND == 1) {
+        return exp_nonpos(-r2 * inv_ell);
+    } else {
+        return exp_nonpos(-sqrt(r2) * inv_ell);
+    }
+}
+
 template <int KIND>
 __device__ __forceinline__ double kernel_val(double r2, double inv_ell)
 {
@@ -244,7 +284,7 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(DevTree T, DevOp O, int f
 #pragma unroll
                 for (int v = 0; v < 4; ++v) {
                     const double r2 = fmax(fma(-2.0, G[v], tn[rt][v] + nb), 0.0);
-                    racc[rt][v] = fma(kernel_val<KIND>(r2, inv_ell), mb, racc[rt][v]);
+                    racc[rt][v] = fma(kernel_fast<KIND>(r2, inv_ell), mb, racc[rt][v]);
                 }
             }
         }
@@ -402,6 +442,48 @@ hipError_t launch_p2p_k(const DevTree &T, const DevOp &O, double *y, int nrhs, i
 // j + 16k, D[i][j] in lane j + 16(i%4), element i/4 (checked with a probe).
 constexpr int kSymLeaf = 128;
 
+// One leaf block, all 16x16 tiles of this wave's two row tiles.  DIAG: the block of a
+// leaf with itself (i == j forced to distance 0, no column sums).
+template <int KIND, int NKC, bool DIAG>
+__device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const double (&rN)[2][4],
+                                          const double (&rQ)[2][4], double (&racc)[2][4], const double *sX,
+                                          const double *sN, const double *sQ, double *colpart, int ns, int ntiles,
+                                          int w, int li, int lg, double inv_ell)
+{
+    const int rt[2] = {w, w + 4};
+    const int nct = (ns + 15) / 16;
+    for (int ct = 0; ct < nct; ++ct) {
+        const int j = 16 * ct + li;
+        const double nb = sN[j], qb = sQ[j];
+        double Bf[NKC];
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
+        double cacc = 0.0;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (rt[u] >= ntiles) continue;  // uniform over the wave
+            dbl4 G = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u][kc], Bf[kc], G, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double r2 = fmax(fma(-2.0, G[v], rN[u][v] + nb), 0.0);
+                if constexpr (DIAG) {
+                    if (16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
+                }
+                const double kv = kernel_fast<KIND>(r2, inv_ell);
+                racc[u][v] = fma(kv, qb, racc[u][v]);
+                if constexpr (!DIAG) cacc = fma(kv, rQ[u][v], cacc);
+            }
+        }
+        if constexpr (!DIAG) {
+            cacc += __shfl_xor(cacc, 16, 64);
+            cacc += __shfl_xor(cacc, 32, 64);
+            if (lg == 0) colpart[w * kSymLeaf + j] = cacc;
+        }
+    }
+}
+
 template <int KIND, int DK>
 __global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
 {
@@ -498,35 +580,10 @@ __global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
             sQ[j] = j < ns ? q : 0.0;
         }
         __syncthreads();
-        const int nct = (ns + 15) / 16;
-        for (int ct = 0; ct < nct; ++ct) {
-            const int j = 16 * ct + li;
-            const double nb = sN[j], qb = sQ[j];
-            double Bf[NKC];
-#pragma unroll
-            for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
-            double cacc = 0.0;
-#pragma unroll
-            for (int u = 0; u < 2; ++u) {
-                if (rt[u] >= ntiles) continue;  // uniform over the wave
-                dbl4 G = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-                for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u][kc], Bf[kc], G, 0, 0, 0);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    double r2 = fmax(fma(-2.0, G[v], rN[u][v] + nb), 0.0);
-                    if (diag && 16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
-                    const double kv = kernel_val<KIND>(r2, inv_ell);
-                    racc[u][v] = fma(kv, qb, racc[u][v]);
-                    cacc = fma(kv, rQ[u][v], cacc);
-                }
-            }
-            if (!diag) {
-                cacc += __shfl_xor(cacc, 16, 64);
-                cacc += __shfl_xor(cacc, 32, 64);
-                if (lg == 0) colpart[w * kSymLeaf + j] = cacc;
-            }
-        }
+        if (diag)
+            sym_block<KIND, NKC, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
+        else
+            sym_block<KIND, NKC, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
         if (!diag) {
             __syncthreads();
             if (tid < ns)
