@@ -605,6 +605,184 @@ __global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
         }
 }
 
+// ---------------------------------------------------------------- MFMA nearfield, several rhs
+// One workgroup per target leaf over all its nearfield source leaves.  The Gram tile is
+// formed with the sources as the A operand: element v of lane (i + 16 g) then holds
+// K[target i][source 4v + g], which is exactly the A operand of chunk v of
+//   Y(16 targets x 16 rhs) += K(16 x 16) Q(16 sources x 16 rhs),
+// so the kernel values feed the apply MFMAs without any lane exchange.  RB = number of
+// 16-wide rhs tiles.  L2P and the scatter to caller order are fused at the end.
+template <int RB>
+constexpr int q_stride() { return 16 * RB + 1; }  // padded row of the staged charges
+
+template <int KIND, int DK, int RB, bool DIAG>
+__device__ __forceinline__ void mrhs_block(const double (&Bt)[2][DK / 4], const double (&tn)[2], dbl4 (&Y)[2][RB],
+                                           const double *sX, const double *sN, const double *sQ, int ns, int ntiles,
+                                           int w, int li, int lg, double inv_ell)
+{
+    constexpr int NKC = DK / 4;
+    const int rt[2] = {w, w + 4};
+    const int nct = (ns + 15) / 16;
+    for (int ct = 0; ct < nct; ++ct) {
+        double Af[NKC];
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSymLeaf + 16 * ct + li];
+        double snv[4];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) snv[v] = sN[16 * ct + 4 * v + lg];
+        double Qf[RB][4];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) Qf[rb][v] = sQ[(16 * ct + 4 * v + lg) * q_stride<RB>() + 16 * rb + li];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (rt[u] >= ntiles) continue;  // uniform over the wave
+            dbl4 G = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[kc], Bt[u][kc], G, 0, 0, 0);
+            double Kv[4];
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double r2 = fmax(fma(-2.0, G[v], tn[u] + snv[v]), 0.0);
+                if constexpr (DIAG) {
+                    if (16 * rt[u] + li == 16 * ct + 4 * v + lg) r2 = 0.0;
+                }
+                Kv[v] = kernel_fast<KIND>(r2, inv_ell);
+            }
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int v = 0; v < 4; ++v) Y[u][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kv[v], Qf[rb][v], Y[u][rb], 0, 0, 0);
+        }
+    }
+}
+
+template <int KIND, int DK, int RB>
+__global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
+                                                       int do_near, int do_far)
+{
+    constexpr int NKC = DK / 4;
+    __shared__ double sX[DK * kSymLeaf];
+    __shared__ double sN[kSymLeaf];
+    __shared__ double sQ[kSymLeaf * q_stride<RB>()];
+    __shared__ double cen[DK];
+    const int nleaf = T.nleaf;
+    const int bid = blockIdx.x;
+    const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
+    const int c = T.leaf_first + l;
+    const int cb = T.cbeg[c], nt = T.cend[c] - cb;
+    if (nt == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int n = T.n;
+    const double inv_ell = 1.0 / O.ell;
+    const int ntiles = (nt + 15) / 16;
+    if (tid < DK) cen[tid] = T.center[(size_t)l * DK + tid];
+    __syncthreads();
+    // targets as the B operand: lane (i + 16 g) holds coordinate 4 kc + g of target i
+    const int rt[2] = {w, w + 4};
+    double Bt[2][NKC], tn[2];
+    dbl4 Y[2][RB];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = 16 * rt[u] + li;
+        const bool ok = i < nt;
+        const int ii = cb + (ok ? i : nt - 1);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+            const double v = T.Xs[(size_t)k * n + ii] - cen[k];
+            s = fma(v, v, s);
+        }
+        tn[u] = s;
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) Bt[u][kc] = T.Xs[(size_t)(4 * kc + lg) * n + ii] - cen[4 * kc + lg];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) Y[u][rb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+    if (do_near) {
+        for (int f = T.Nptr[l]; f < T.Nptr[l + 1]; ++f) {
+            const int sl = T.Nsrc[f];
+            const int sc = T.leaf_first + sl;
+            const int sb = T.cbeg[sc], ns = T.cend[sc] - sb;
+            __syncthreads();
+            if (tid < kSymLeaf) {
+                const int j = tid;
+                const bool ok = j < ns;
+                const int jj = sb + (ok ? j : ns - 1);
+                double xv[DK];
+#pragma unroll
+                for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + jj];
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < DK; ++k) {
+                    const double v = ok ? xv[k] - cen[k] : 0.0;
+                    sX[k * kSymLeaf + j] = v;
+                    s = fma(v, v, s);
+                }
+                sN[j] = s;
+            }
+            // charges [j][r], zero beyond the leaf and beyond nrhs
+            for (int e = tid; e < kSymLeaf * 16 * RB; e += 256) {
+                const int j = e / (16 * RB), r = e % (16 * RB);
+                const bool ok = j < ns && r < nrhs;
+                const double q = O.xt[(size_t)(sb + (j < ns ? j : ns - 1)) * nrhs + (r < nrhs ? r : 0)];
+                sQ[j * q_stride<RB>() + r] = ok ? q : 0.0;
+            }
+            __syncthreads();
+            if (sl == l)
+                mrhs_block<KIND, DK, RB, true>(Bt, tn, Y, sX, sN, sQ, ns, ntiles, w, li, lg, inv_ell);
+            else
+                mrhs_block<KIND, DK, RB, false>(Bt, tn, Y, sX, sN, sQ, ns, ntiles, w, li, lg, inv_ell);
+        }
+    }
+    // Y[u][rb] element v of lane (r + 16 g) is output (target 16 rt + 4 v + g, rhs 16 rb + r)
+    const double *lc = O.L + (size_t)c * O.nx * nrhs;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        if (rt[u] >= ntiles) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const int r = 16 * rb + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * rt[u] + 4 * v + lg;
+                double acc = Y[u][rb][v];
+                if (do_far && i < nt && r < nrhs)
+                    for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * n + cb + i], lc[a * nrhs + r], acc);
+                if (i < nt && r < nrhs) y[(size_t)T.perm[cb + i] * nrhs + r] = acc;
+            }
+        }
+    }
+}
+
+template <int KIND, int DK>
+void launch_mrhs_d(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
+{
+    if (nrhs <= 16)
+        hipLaunchKernelGGL((p2p_mrhs_kernel<KIND, DK, 1>), dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs, near, far);
+    else
+        hipLaunchKernelGGL((p2p_mrhs_kernel<KIND, DK, 2>), dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs, near, far);
+}
+
+template <int KIND>
+hipError_t launch_mrhs_k(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
+{
+    switch ((T.d + 3) / 4 * 4) {
+    case 4: launch_mrhs_d<KIND, 4>(T, O, y, nrhs, near, far, st); break;
+    case 8: launch_mrhs_d<KIND, 8>(T, O, y, nrhs, near, far, st); break;
+    case 12: launch_mrhs_d<KIND, 12>(T, O, y, nrhs, near, far, st); break;
+    case 16: launch_mrhs_d<KIND, 16>(T, O, y, nrhs, near, far, st); break;
+    case 20: launch_mrhs_d<KIND, 20>(T, O, y, nrhs, near, far, st); break;
+    case 24: launch_mrhs_d<KIND, 24>(T, O, y, nrhs, near, far, st); break;
+    case 28: launch_mrhs_d<KIND, 28>(T, O, y, nrhs, near, far, st); break;
+    case 32: launch_mrhs_d<KIND, 32>(T, O, y, nrhs, near, far, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // y[perm] = owner row sums + received column sums (fixed order) + L2P
 __global__ __launch_bounds__(kSymLeaf) void p2p_combine_kernel(DevTree T, DevOp O, double *__restrict__ y,
                                                                int do_near, int do_far)
@@ -732,6 +910,18 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
         if (timer) (void)hipEventRecord(timer->p2p_stop, st);
         hipLaunchKernelGGL(p2p_combine_kernel, dim3(T.nleaf), dim3(kSymLeaf), 0, st, T, O, y, near, far);
         return hipGetLastError();
+    }
+    // MFMA nearfield for several rhs (LDS: coordinates + charges stay below 64 KB)
+    const int dk = (T.d + 3) / 4 * 4;
+    const bool mrhs = nrhs > 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && dk <= 32 && !(dk > 28 && nrhs > 16);
+    if (mrhs) {
+        switch (O.kind) {
+        case 0: e = launch_mrhs_k<0>(T, O, y, nrhs, near, far, st); break;
+        case 1: e = launch_mrhs_k<1>(T, O, y, nrhs, near, far, st); break;
+        default: e = launch_mrhs_k<2>(T, O, y, nrhs, near, far, st); break;
+        }
+        if (timer) (void)hipEventRecord(timer->p2p_stop, st);
+        return e;
     }
     switch (O.kind) {
     case 0: e = launch_p2p_k<0>(T, O, y, nrhs, near, far, st); break;

@@ -54,9 +54,14 @@ CASES = [
     ("d7_exp", 9000, 7, 2.0, "exponential", 0.3, 5, 100, 0.5, 1),
     ("d1_matern", 3000, 1, 0.0, "matern32", 1.0, 5, 32, 0.8, 1),
     ("d24_matern", 8000, 24, 3.0, "matern32", 1.0, 6, 128, 0.8, 1),
-    # general (non-symmetric) nearfield kernel: leaves above 128 points, d above 32
+    # several right-hand sides on the MFMA nearfield: one and two 16-wide rhs tiles, ragged rhs
+    ("d20_gauss_r32", 8000, 20, 3.0, "gaussian", 0.5, 6, 128, 0.8, 32),
+    ("d10_matern_r17", 6000, 10, 2.0, "matern32", 1.0, 6, 128, 0.8, 17),
+    ("d4_exp_r16", 3000, 4, 2.0, "exponential", 0.4, 4, 64, 0.8, 16),
+    # general (non-symmetric) nearfield kernel: leaves above 128 points, d above 32, wide rhs at d > 28
     ("d3_leaf200", 20000, 3, 2.0, "matern32", 1.0, 5, 200, 0.8, 1),
     ("d40_gauss", 5000, 40, 3.0, "gaussian", 0.5, 6, 128, 0.8, 1),
+    ("d30_exp_r20", 4000, 30, 3.0, "exponential", 0.3, 6, 128, 0.8, 20),
 ]
 
 
@@ -157,6 +162,24 @@ def test_full_size_sampled_rows(orc):
     rng = np.random.default_rng(1)
     leaves = sorted(rng.choice(2 ** P.J, size=6, replace=False).tolist()) + [0, 2 ** P.J - 1]
     for l in leaves:
+        yr = P.matvec(x, leaf_range=(l, l + 1))
+        c = 2 ** P.J - 1 + l
+        idx = T["perm"][T["begin"][c]:T["end"][c]]
+        e = np.linalg.norm(y[idx] - yr[idx]) / np.linalg.norm(yr[idx])
+        say(f"   leaf {l}: rel err {e:.3e}")
+        assert e <= TOL
+
+
+def test_full_size_sampled_rows_32rhs(orc):
+    """N = 1e6, d = 20 with 32 right-hand sides: sampled leaves against the oracle."""
+    w = W.WORKLOADS["n1m_d20_r32"]
+    say("[full-size] building inputs n=1e6 d=20 nrhs=32")
+    X, b, x = W.make(w)
+    tree, op = gpu_op(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q, nrhs=32)
+    y = gpu_matvec(op, x)
+    P = orc.Plan(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q)
+    T = P.tree()
+    for l in (0, 4097, 2 ** P.J - 1):
         yr = P.matvec(x, leaf_range=(l, l + 1))
         c = 2 ** P.J - 1 + l
         idx = T["perm"][T["begin"][c]:T["end"][c]]
