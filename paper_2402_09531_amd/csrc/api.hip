@@ -94,6 +94,7 @@ struct dwfmm_op_s {
     double ir_inner_rtol = 0.0;
     // CG workspace
     double *r = nullptr, *p = nullptr, *q = nullptr, *partial = nullptr, *scal = nullptr;
+    double *ir_r = nullptr, *ir_d = nullptr;  // refinement: outer residual and correction
     int32_t *state = nullptr;
     // kernel timing: one event pair per timed matvec, summed when read
     bool timing = false;
@@ -370,6 +371,9 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
         (e = op->arena.alloc((void **)&op->r, sizeof(double) * n * R)) != hipSuccess ||
         (e = op->arena.alloc((void **)&op->p, sizeof(double) * n * R)) != hipSuccess ||
         (e = op->arena.alloc((void **)&op->q, sizeof(double) * n * R)) != hipSuccess ||
+        (o.precision != DWFMM_FP64 &&
+         ((e = op->arena.alloc((void **)&op->ir_r, sizeof(double) * n * R)) != hipSuccess ||
+          (e = op->arena.alloc((void **)&op->ir_d, sizeof(double) * n * R)) != hipSuccess)) ||
         (e = op->arena.alloc((void **)&op->partial, sizeof(double) * kDotBlocks * R)) != hipSuccess ||
         (e = op->arena.alloc((void **)&op->scal, sizeof(double) * 16 * R)) != hipSuccess ||
         (e = op->arena.alloc((void **)&op->state, sizeof(int32_t) * 4 * R)) != hipSuccess ||
@@ -552,6 +556,89 @@ constexpr int kEwBlocks = 1024;
 
 }  // namespace
 
+namespace {
+
+// CG on (K~ + lambda I) x = b in the given matvec precision, x holding the start vector.
+// Vectors, inner products and scalars are FP64 on the device; the host reads the column
+// states every check_every iterations.  On return hstate[0..3n) = state (0 active,
+// 1 converged, 2 breakdown), iterations, negative-curvature steps; hrr[0..2n) = |r|^2, |b|^2.
+hipError_t cg_run(dwfmm_op op, double lambda, const double *b, double *x, int nrhs, double rtol, int max_iter,
+                  int precision, hipStream_t st, std::vector<int32_t> &hstate, std::vector<double> &hrr)
+{
+    const DevTree &T = op->tree->D;
+    const size_t total = (size_t)T.n * nrhs;
+    const int nb = (nrhs + 63) / 64;
+    double *r = op->r, *p = op->p, *q = op->q, *scal = op->scal;
+    int32_t *state = op->state;
+    hipError_t e;
+    auto matvecA = [&](const double *v, double *out) -> hipError_t {
+        hipError_t e2 = launch_matvec(T, op->D, v, out, nrhs, 3, precision, st);
+        if (e2 != hipSuccess) return e2;
+        if (lambda != 0.0) hipLaunchKernelGGL(ridge_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, v, lambda, total);
+        return hipGetLastError();
+    };
+    if ((e = hipMemsetAsync(state, 0, sizeof(int32_t) * 3 * nrhs, st)) != hipSuccess) return e;
+    if ((e = matvecA(x, q)) != hipSuccess) return e;
+    hipLaunchKernelGGL(sub_kernel, dim3(kEwBlocks), dim3(256), 0, st, r, b, q, total);
+    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, st, p, r, total);
+    if ((e = launch_dot(r, r, T.n, nrhs, op->partial, scal, st)) != hipSuccess) return e;
+    if ((e = launch_dot(b, b, T.n, nrhs, op->partial, scal + nrhs, st)) != hipSuccess) return e;
+    hstate.assign(3 * nrhs, 0);
+    for (int it = 0; it < max_iter; ++it) {
+        hipLaunchKernelGGL(cg_check_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs, rtol);
+        if (it % op->check_every == 0) {
+            if ((e = hipMemcpyAsync(hstate.data(), state, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st)) !=
+                hipSuccess)
+                return e;
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+            bool active = false;
+            for (int c = 0; c < nrhs; ++c) active |= hstate[c] == 0;
+            if (!active) break;
+        }
+        if ((e = matvecA(p, q)) != hipSuccess) return e;
+        if ((e = launch_dot(p, q, T.n, nrhs, op->partial, scal + 2 * nrhs, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(cg_alpha_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs);
+        // x += a p ; r -= a q  (a = 0 for inactive columns)
+        hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, x, x, p, scal, 4, 1.0, state, 0, total, nrhs);
+        hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, r, r, q, scal, 4, -1.0, state, 0, total,
+                           nrhs);
+        if ((e = launch_dot(r, r, T.n, nrhs, op->partial, scal + 3 * nrhs, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(cg_beta_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs);
+        // p = r + beta p on active columns
+        hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, p, r, p, scal, 5, 1.0, state, 1, total,
+                           nrhs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(cg_check_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs, rtol);
+    hrr.assign(2 * nrhs, 0.0);
+    if ((e = hipMemcpyAsync(hrr.data(), scal, sizeof(double) * 2 * nrhs, hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+    if ((e = hipMemcpyAsync(hstate.data(), state, sizeof(int32_t) * 3 * nrhs, hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+        return e;
+    return hipStreamSynchronize(st);
+}
+
+// out = f - (K~_64 + lambda I) v in FP64; |out|^2 per column into host res.
+hipError_t residual64(dwfmm_op op, double lambda, const double *f, const double *v, double *out, int nrhs,
+                      hipStream_t st, std::vector<double> &res)
+{
+    const DevTree &T = op->tree->D;
+    const size_t total = (size_t)T.n * nrhs;
+    hipError_t e = launch_matvec(T, op->D, v, out, nrhs, 3, DWFMM_FP64, st);
+    if (e != hipSuccess) return e;
+    if (lambda != 0.0) hipLaunchKernelGGL(ridge_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, v, lambda, total);
+    hipLaunchKernelGGL(sub_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, f, out, total);
+    if ((e = launch_dot(out, out, T.n, nrhs, op->partial, op->scal + 8 * nrhs, st)) != hipSuccess) return e;
+    res.assign(nrhs, 0.0);
+    if ((e = hipMemcpyAsync(res.data(), op->scal + 8 * nrhs, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st)) !=
+        hipSuccess)
+        return e;
+    return hipStreamSynchronize(st);
+}
+
+}  // namespace
+
 extern "C" dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double *f, double *alpha, int32_t nrhs,
                                         double rtol, int32_t max_iter, void *stream, dwfmm_solve_info *info)
 {
@@ -563,69 +650,89 @@ extern "C" dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double
     hipStream_t st = (hipStream_t)stream;
     const DevTree &T = op->tree->D;
     const size_t total = (size_t)T.n * nrhs;
-    const int nb = (nrhs + 63) / 64;
-    double *r = op->r, *p = op->p, *q = op->q, *scal = op->scal;
-    int32_t *state = op->state;
-    auto matvecA = [&](const double *v, double *out) -> hipError_t {
-        hipError_t e = launch_matvec(T, op->D, v, out, nrhs, 3, DWFMM_FP64, st);
-        if (e != hipSuccess) return e;
-        if (lambda != 0.0) hipLaunchKernelGGL(ridge_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, v, lambda, total);
-        return hipGetLastError();
-    };
-    HIP_TRY(hipMemsetAsync(state, 0, sizeof(int32_t) * 3 * nrhs, st));
-    HIP_TRY(matvecA(alpha, q));
-    hipLaunchKernelGGL(sub_kernel, dim3(kEwBlocks), dim3(256), 0, st, r, f, q, total);
-    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, st, p, r, total);
-    HIP_TRY(launch_dot(r, r, T.n, nrhs, op->partial, scal, st));
-    HIP_TRY(launch_dot(f, f, T.n, nrhs, op->partial, scal + nrhs, st));
-    std::vector<int32_t> hstate(3 * nrhs);
-    int it = 0;
-    for (; it < max_iter; ++it) {
-        hipLaunchKernelGGL(cg_check_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs, rtol);
-        if (it % op->check_every == 0) {
-            HIP_TRY(hipMemcpyAsync(hstate.data(), state, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            bool active = false;
-            for (int c = 0; c < nrhs; ++c) active |= hstate[c] == 0;
-            if (!active) break;
-        }
-        HIP_TRY(matvecA(p, q));
-        HIP_TRY(launch_dot(p, q, T.n, nrhs, op->partial, scal + 2 * nrhs, st));
-        hipLaunchKernelGGL(cg_alpha_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs);
-        // alpha += a p ; r -= a q  (a = 0 for inactive columns)
-        hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, alpha, alpha, p, scal, 4, 1.0, state, 0,
-                           total, nrhs);
-        hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, r, r, q, scal, 4, -1.0, state, 0, total,
-                           nrhs);
-        HIP_TRY(launch_dot(r, r, T.n, nrhs, op->partial, scal + 3 * nrhs, st));
-        hipLaunchKernelGGL(cg_beta_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs);
-        // p = r + beta p on active columns
-        hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, p, r, p, scal, 5, 1.0, state, 1, total,
-                           nrhs);
-        HIP_TRY(hipGetLastError());
-    }
-    hipLaunchKernelGGL(cg_check_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs, rtol);
-    // true residual |f - A alpha|
-    HIP_TRY(matvecA(alpha, q));
-    hipLaunchKernelGGL(sub_kernel, dim3(kEwBlocks), dim3(256), 0, st, q, f, q, total);
-    HIP_TRY(launch_dot(q, q, T.n, nrhs, op->partial, scal + 6 * nrhs, st));
-    std::vector<double> hs(7 * nrhs);
-    HIP_TRY(hipMemcpyAsync(hs.data(), scal, sizeof(double) * 7 * nrhs, hipMemcpyDeviceToHost, st));
-    HIP_TRY(hipMemcpyAsync(hstate.data(), state, sizeof(int32_t) * 3 * nrhs, hipMemcpyDeviceToHost, st));
+    std::vector<int32_t> hstate;
+    std::vector<double> hrr, res, fn2;
+    HIP_TRY(launch_dot(f, f, T.n, nrhs, op->partial, op->scal + 9 * nrhs, st));
+    fn2.assign(nrhs, 0.0);
+    HIP_TRY(hipMemcpyAsync(fn2.data(), op->scal + 9 * nrhs, sizeof(double) * nrhs, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    auto den = [&](int c) { return fn2[c] > 0 ? std::sqrt(fn2[c]) : 1.0; };
     dwfmm_status worst = DWFMM_OK;
-    for (int c = 0; c < nrhs; ++c) {
-        const double fn = std::sqrt(hs[nrhs + c]);
-        const double den = fn > 0 ? fn : 1.0;
-        dwfmm_solve_info &I = info[c];
-        I.iters = hstate[nrhs + c];
-        I.neg_curvature_steps = hstate[2 * nrhs + c];
-        I.refine_steps = 0;
-        I.rel_res_recursive = std::sqrt(hs[c]) / den;
-        I.rel_res_true = std::sqrt(hs[6 * nrhs + c]) / den;
-        I.status = hstate[c] == 1 ? DWFMM_OK : (hstate[c] == 2 ? DWFMM_E_BREAKDOWN : DWFMM_E_NOT_CONVERGED);
-        if (I.status == DWFMM_E_BREAKDOWN) worst = DWFMM_E_BREAKDOWN;
-        else if (I.status == DWFMM_E_NOT_CONVERGED && worst == DWFMM_OK) worst = DWFMM_E_NOT_CONVERGED;
+    auto record = [&](dwfmm_status s) {
+        if (s == DWFMM_E_BREAKDOWN) worst = DWFMM_E_BREAKDOWN;
+        else if (s == DWFMM_E_NOT_CONVERGED && worst == DWFMM_OK) worst = DWFMM_E_NOT_CONVERGED;
+    };
+
+    if (op->precision == DWFMM_FP64) {
+        HIP_TRY(cg_run(op, lambda, f, alpha, nrhs, rtol, max_iter, DWFMM_FP64, st, hstate, hrr));
+        HIP_TRY(residual64(op, lambda, f, alpha, op->q, nrhs, st, res));
+        for (int c = 0; c < nrhs; ++c) {
+            dwfmm_solve_info &I = info[c];
+            I.iters = hstate[nrhs + c];
+            I.neg_curvature_steps = hstate[2 * nrhs + c];
+            I.refine_steps = 0;
+            I.rel_res_recursive = std::sqrt(hrr[c]) / den(c);
+            I.rel_res_true = std::sqrt(res[c]) / den(c);
+            I.status = hstate[c] == 1 ? DWFMM_OK : (hstate[c] == 2 ? DWFMM_E_BREAKDOWN : DWFMM_E_NOT_CONVERGED);
+            record((dwfmm_status)I.status);
+        }
+    } else {
+        // Iterative refinement: FP64 residual, reduced-precision inner CG, alpha += delta.
+        const double rtol_in =
+            op->ir_inner_rtol > 0 ? op->ir_inner_rtol : (op->precision == DWFMM_FP32 ? 1e-4 : 1e-2);
+        std::vector<int32_t> iters(nrhs, 0), neg(nrhs, 0), stall(nrhs, 0), done(nrhs, 0), broke(nrhs, 0), steps(nrhs, 0);
+        std::vector<double> best;
+        HIP_TRY(residual64(op, lambda, f, alpha, op->ir_r, nrhs, st, res));
+        best = res;
+        int used = 0;
+        for (int c = 0; c < nrhs; ++c) done[c] = std::sqrt(res[c]) <= rtol * den(c);
+        for (int outer = 0; outer < op->ir_max_outer && used < max_iter; ++outer) {
+            bool any = false;
+            for (int c = 0; c < nrhs; ++c) any |= !done[c] && stall[c] < 3;
+            if (!any) break;
+            // mask: 0 = update this column
+            std::vector<int32_t> mask(nrhs);
+            for (int c = 0; c < nrhs; ++c) mask[c] = (!done[c] && stall[c] < 3) ? 0 : 1;
+            HIP_TRY(hipMemcpyAsync(op->state + 3 * op->max_nrhs, mask.data(), sizeof(int32_t) * nrhs,
+                                   hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemsetAsync(op->ir_d, 0, sizeof(double) * total, st));
+            HIP_TRY(cg_run(op, lambda, op->ir_r, op->ir_d, nrhs, rtol_in, max_iter - used, op->precision, st, hstate,
+                           hrr));
+            int most = 0;
+            for (int c = 0; c < nrhs; ++c) {
+                if (mask[c]) continue;
+                iters[c] += hstate[nrhs + c];
+                neg[c] += hstate[2 * nrhs + c];
+                most = std::max(most, hstate[nrhs + c]);
+                if (hstate[c] == 2 && hstate[nrhs + c] == 0) broke[c] = 1;
+                steps[c]++;
+            }
+            used += std::max(most, 1);
+            // alpha += delta on the columns being refined (scale slot 10 holds 1.0)
+            std::vector<double> one(nrhs, 1.0);
+            HIP_TRY(hipMemcpyAsync(op->scal + 10 * nrhs, one.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
+            hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, alpha, alpha, op->ir_d, op->scal, 10, 1.0,
+                               op->state + 3 * op->max_nrhs, 1, total, nrhs);
+            HIP_TRY(hipGetLastError());
+            HIP_TRY(residual64(op, lambda, f, alpha, op->ir_r, nrhs, st, res));
+            for (int c = 0; c < nrhs; ++c) {
+                if (mask[c]) continue;
+                if (std::sqrt(res[c]) <= rtol * den(c)) done[c] = 1;
+                else if (res[c] >= best[c]) stall[c]++;
+                else { best[c] = res[c]; stall[c] = 0; }
+                if (broke[c]) stall[c] = 3;
+            }
+        }
+        for (int c = 0; c < nrhs; ++c) {
+            dwfmm_solve_info &I = info[c];
+            I.iters = iters[c];
+            I.neg_curvature_steps = neg[c];
+            I.refine_steps = steps[c];
+            I.rel_res_recursive = std::sqrt(res[c]) / den(c);
+            I.rel_res_true = std::sqrt(res[c]) / den(c);
+            I.status = done[c] ? DWFMM_OK : (broke[c] ? DWFMM_E_BREAKDOWN : DWFMM_E_NOT_CONVERGED);
+            record((dwfmm_status)I.status);
+        }
     }
     if (worst != DWFMM_OK) g_err = worst == DWFMM_E_BREAKDOWN ? "CG breakdown" : "CG did not converge";
     return worst;

@@ -819,6 +819,470 @@ hipError_t launch_sym_k(const DevTree &T, const DevOp &O, hipStream_t st)
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- FP32 variants (reduced precision)
+// Same algorithms in FP32 arithmetic: coordinates (shifted in FP64, then rounded),
+// Gram tiles on v_mfma_f32_16x16x4f32, kernel values with the hardware exp2/sqrt,
+// FP32 accumulation within a launch; results are stored as FP64.
+// Lane layout of v_mfma_f32_16x16x4f32 (checked with a probe): A[i][k] in lane i + 16k,
+// B[k][j] in lane j + 16k, D[i][j] in lane j + 16(i/4), element i%4.
+typedef float flt4 __attribute__((ext_vector_type(4)));
+
+template <int KIND>
+__device__ __forceinline__ float kernel_f32(float r2, float inv_ell)
+{
+    constexpr float kLog2e = 1.4426950408889634f;
+    if constexpr (KIND == 0) {
+        const float s = 1.7320508f * __builtin_amdgcn_sqrtf(r2) * inv_ell;
+        return (1.0f + s) * __builtin_amdgcn_exp2f(-s * kLog2e);
+    } else if constexpr (KIND == 1) {
+        return __builtin_amdgcn_exp2f(-r2 * inv_ell * kLog2e);
+    } else {
+        return __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(r2) * inv_ell * kLog2e);
+    }
+}
+
+template <int KIND, int NKC, bool DIAG>
+__device__ __forceinline__ void sym_block32(const float (&A)[2][NKC], const float (&rN)[2][4], const float (&rQ)[2][4],
+                                            float (&racc)[2][4], const float *sX, const float *sN, const float *sQ,
+                                            float *colpart, int ns, int ntiles, int w, int li, int lg, float inv_ell)
+{
+    const int rt[2] = {w, w + 4};
+    const int nct = (ns + 15) / 16;
+    for (int ct = 0; ct < nct; ++ct) {
+        const int j = 16 * ct + li;
+        const float nb = sN[j], qb = sQ[j];
+        float Bf[NKC];
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
+        float cacc = 0.0f;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (rt[u] >= ntiles) continue;
+            flt4 G = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(A[u][kc], Bf[kc], G, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float r2 = fmaxf(fmaf(-2.0f, G[v], rN[u][v] + nb), 0.0f);
+                if constexpr (DIAG) {
+                    if (16 * rt[u] + 4 * lg + v == j) r2 = 0.0f;
+                }
+                const float kv = kernel_f32<KIND>(r2, inv_ell);
+                racc[u][v] = fmaf(kv, qb, racc[u][v]);
+                if constexpr (!DIAG) cacc = fmaf(kv, rQ[u][v], cacc);
+            }
+        }
+        if constexpr (!DIAG) {
+            cacc += __shfl_xor(cacc, 16, 64);
+            cacc += __shfl_xor(cacc, 32, 64);
+            if (lg == 0) colpart[w * kSymLeaf + j] = cacc;
+        }
+    }
+}
+
+template <int KIND, int DK>
+__global__ __launch_bounds__(256) void p2p_sym32_kernel(DevTree T, DevOp O)
+{
+    constexpr int NKC = DK / 4;
+    __shared__ float sX[DK * kSymLeaf];
+    __shared__ float sN[kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf], tQ[kSymLeaf];
+    __shared__ float colpart[4 * kSymLeaf];
+    __shared__ double cen[DK];
+    const int nleaf = T.nleaf;
+    const int bid = blockIdx.x;
+    const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
+    const int c = T.leaf_first + l;
+    const int cb = T.cbeg[c], nt = T.cend[c] - cb;
+    if (nt == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int n = T.n;
+    const float inv_ell = (float)(1.0 / O.ell);
+    const int ntiles = (nt + 15) / 16;
+    if (tid < DK) cen[tid] = T.center[(size_t)l * DK + tid];
+    __syncthreads();
+    if (tid < kSymLeaf) {
+        const bool ok = tid < nt;
+        const int ii = cb + (ok ? tid : nt - 1);
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+            const float v = (float)(T.Xs[(size_t)k * n + ii] - cen[k]);
+            s = fmaf(v, v, s);
+        }
+        tN[tid] = ok ? s : 0.0f;
+        tQ[tid] = ok ? (float)O.xt[ii] : 0.0f;
+    }
+    const int rt[2] = {w, w + 4};
+    float A[2][NKC];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = 16 * rt[u] + li;
+        const bool ok = i < nt;
+        const int ii = cb + (ok ? i : nt - 1);
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) {
+            const int k = 4 * kc + lg;
+            const float v = (float)(T.Xs[(size_t)k * n + ii] - cen[k]);
+            A[u][kc] = ok ? v : 0.0f;
+        }
+    }
+    __syncthreads();
+    float rN[2][4], rQ[2][4], racc[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            const int i = 16 * rt[u] + 4 * lg + v;
+            rN[u][v] = tN[i];
+            rQ[u][v] = tQ[i];
+            racc[u][v] = 0.0f;
+        }
+    const int o0 = T.own_ptr[l], o1 = T.own_ptr[l + 1];
+    for (int f = o0; f < o1; ++f) {
+        const int sl = T.own_src[f];
+        const bool diag = sl == l;
+        const int sc = T.leaf_first + sl;
+        const int sb = T.cbeg[sc], ns = T.cend[sc] - sb;
+        __syncthreads();
+        if (tid < kSymLeaf) {
+            const int j = tid;
+            const bool ok = j < ns;
+            const int jj = sb + (ok ? j : ns - 1);
+            double xv[DK];
+#pragma unroll
+            for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + jj];
+            float s = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DK; ++k) {
+                const float v = ok ? (float)(xv[k] - cen[k]) : 0.0f;
+                sX[k * kSymLeaf + j] = v;
+                s = fmaf(v, v, s);
+            }
+            sN[j] = s;
+        } else {
+            const int j = tid - kSymLeaf;
+            const double q = O.xt[sb + (j < ns ? j : ns - 1)];
+            sQ[j] = j < ns ? (float)q : 0.0f;
+        }
+        __syncthreads();
+        if (diag)
+            sym_block32<KIND, NKC, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
+        else
+            sym_block32<KIND, NKC, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
+        if (!diag) {
+            __syncthreads();
+            if (tid < ns)
+                O.colbuf[(size_t)f * kSymLeaf + tid] =
+                    (double)(((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) +
+                             colpart[3 * kSymLeaf + tid]);
+        }
+    }
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float s = racc[u][v];
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            s += __shfl_xor(s, 4, 64);
+            s += __shfl_xor(s, 8, 64);
+            const int i = 16 * rt[u] + 4 * lg + v;
+            if (li == 0 && i < nt) O.rowbuf[(size_t)l * kSymLeaf + i] = (double)s;
+        }
+}
+
+template <int KIND>
+hipError_t launch_sym32_k(const DevTree &T, const DevOp &O, hipStream_t st)
+{
+    switch ((T.d + 3) / 4 * 4) {
+#define DWFMM_SYM(D) \
+    case D: hipLaunchKernelGGL((p2p_sym32_kernel<KIND, D>), dim3(T.nleaf), dim3(256), 0, st, T, O); break;
+        DWFMM_SYM(4) DWFMM_SYM(8) DWFMM_SYM(12) DWFMM_SYM(16) DWFMM_SYM(20) DWFMM_SYM(24) DWFMM_SYM(28)
+        DWFMM_SYM(32)
+#undef DWFMM_SYM
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Nearfield for several rhs in reduced precision.  FP32 Gram tile with the sources as the
+// A operand: element e of lane (i + 16 g) holds K[target i][source 4g + e].  BF16: that is the
+// A operand of v_mfma_f32_16x16x16bf16_1k as is (A[i][k] in lane i + 16(k/4), element k%4),
+// so Y(16 x 16 rhs) += K Q is one MFMA with FP32 accumulation.  FP32: element e is the A
+// operand of chunk e (sources 4g + e) of four v_mfma_f32_16x16x4f32.
+typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+constexpr int kQtStride = kSymLeaf + 8;  // bf16 charges stored [rhs][source], padded
+
+template <int KIND, int DK, int RB, bool BF16, bool DIAG>
+__device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], const float (&tn)[2], flt4 (&Y)[2][RB],
+                                              const float *sX, const float *sN, const float *sQ, const __bf16 *sQt,
+                                              int ns, int ntiles, int w, int li, int lg, float inv_ell)
+{
+    constexpr int NKC = DK / 4;
+    const int rt[2] = {w, w + 4};
+    const int nct = (ns + 15) / 16;
+    for (int ct = 0; ct < nct; ++ct) {
+        float Af[NKC];
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSymLeaf + 16 * ct + li];
+        float snv[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) snv[e] = sN[16 * ct + 4 * lg + e];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (rt[u] >= ntiles) continue;
+            flt4 G = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[kc], Bt[u][kc], G, 0, 0, 0);
+            float Kv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                float r2 = fmaxf(fmaf(-2.0f, G[e], tn[u] + snv[e]), 0.0f);
+                if constexpr (DIAG) {
+                    if (16 * rt[u] + li == 16 * ct + 4 * lg + e) r2 = 0.0f;
+                }
+                Kv[e] = kernel_f32<KIND>(r2, inv_ell);
+            }
+            if constexpr (BF16) {
+                const bf16x4 Ka = {(__bf16)Kv[0], (__bf16)Kv[1], (__bf16)Kv[2], (__bf16)Kv[3]};
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb) {
+                    const bf16x4 Qb = *reinterpret_cast<const bf16x4 *>(&sQt[(16 * rb + li) * kQtStride + 16 * ct + 4 * lg]);
+                    Y[u][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ka, Qb, Y[u][rb], 0, 0, 0);
+                }
+            } else {
+#pragma unroll
+                for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        Y[u][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
+                            Kv[e], sQ[(16 * ct + 4 * lg + e) * q_stride<RB>() + 16 * rb + li], Y[u][rb], 0, 0, 0);
+            }
+        }
+    }
+}
+
+template <int KIND, int DK, int RB, bool BF16>
+__global__ __launch_bounds__(256) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
+                                                          int do_near, int do_far)
+{
+    constexpr int NKC = DK / 4;
+    __shared__ float sX[DK * kSymLeaf];
+    __shared__ float sN[kSymLeaf];
+    __shared__ float sQ[BF16 ? 1 : kSymLeaf * q_stride<RB>()];
+    __shared__ __attribute__((aligned(16))) __bf16 sQt[BF16 ? 16 * RB * kQtStride : 8];
+    __shared__ double cen[DK];
+    const int nleaf = T.nleaf;
+    const int bid = blockIdx.x;
+    const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
+    const int c = T.leaf_first + l;
+    const int cb = T.cbeg[c], nt = T.cend[c] - cb;
+    if (nt == 0) return;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int n = T.n;
+    const float inv_ell = (float)(1.0 / O.ell);
+    const int ntiles = (nt + 15) / 16;
+    if (tid < DK) cen[tid] = T.center[(size_t)l * DK + tid];
+    __syncthreads();
+    const int rt[2] = {w, w + 4};
+    float Bt[2][NKC], tn[2];
+    flt4 Y[2][RB];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = 16 * rt[u] + li;
+        const bool ok = i < nt;
+        const int ii = cb + (ok ? i : nt - 1);
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+            const float v = (float)(T.Xs[(size_t)k * n + ii] - cen[k]);
+            s = fmaf(v, v, s);
+        }
+        tn[u] = s;
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) Bt[u][kc] = (float)(T.Xs[(size_t)(4 * kc + lg) * n + ii] - cen[4 * kc + lg]);
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) Y[u][rb] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    if (do_near) {
+        for (int f = T.Nptr[l]; f < T.Nptr[l + 1]; ++f) {
+            const int sl = T.Nsrc[f];
+            const int sc = T.leaf_first + sl;
+            const int sb = T.cbeg[sc], ns = T.cend[sc] - sb;
+            __syncthreads();
+            if (tid < kSymLeaf) {
+                const int j = tid;
+                const bool ok = j < ns;
+                const int jj = sb + (ok ? j : ns - 1);
+                double xv[DK];
+#pragma unroll
+                for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + jj];
+                float s = 0.0f;
+#pragma unroll
+                for (int k = 0; k < DK; ++k) {
+                    const float v = ok ? (float)(xv[k] - cen[k]) : 0.0f;
+                    sX[k * kSymLeaf + j] = v;
+                    s = fmaf(v, v, s);
+                }
+                sN[j] = s;
+            }
+            for (int e = tid; e < kSymLeaf * 16 * RB; e += 256) {
+                const int j = e / (16 * RB), r = e % (16 * RB);
+                const bool ok = j < ns && r < nrhs;
+                const double q = O.xt[(size_t)(sb + (j < ns ? j : ns - 1)) * nrhs + (r < nrhs ? r : 0)];
+                if constexpr (BF16)
+                    sQt[r * kQtStride + j] = (__bf16)(ok ? (float)q : 0.0f);
+                else
+                    sQ[j * q_stride<RB>() + r] = ok ? (float)q : 0.0f;
+            }
+            __syncthreads();
+            if (sl == l)
+                mrhs_block_lp<KIND, DK, RB, BF16, true>(Bt, tn, Y, sX, sN, sQ, sQt, ns, ntiles, w, li, lg, inv_ell);
+            else
+                mrhs_block_lp<KIND, DK, RB, BF16, false>(Bt, tn, Y, sX, sN, sQ, sQt, ns, ntiles, w, li, lg, inv_ell);
+        }
+    }
+    // Y[u][rb] element v of lane (r + 16 g) is output (target 16 rt + 4 g + v, rhs 16 rb + r)
+    const double *lc = O.L + (size_t)c * O.nx * nrhs;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        if (rt[u] >= ntiles) continue;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb) {
+            const int r = 16 * rb + li;
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                const int i = 16 * rt[u] + 4 * lg + v;
+                double acc = (double)Y[u][rb][v];
+                if (do_far && i < nt && r < nrhs)
+                    for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * n + cb + i], lc[a * nrhs + r], acc);
+                if (i < nt && r < nrhs) y[(size_t)T.perm[cb + i] * nrhs + r] = acc;
+            }
+        }
+    }
+}
+
+template <int KIND, int DK, bool BF16>
+void launch_mrhs_lp_d(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
+{
+    if (nrhs <= 16)
+        hipLaunchKernelGGL((p2p_mrhs_lp_kernel<KIND, DK, 1, BF16>), dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs,
+                           near, far);
+    else
+        hipLaunchKernelGGL((p2p_mrhs_lp_kernel<KIND, DK, 2, BF16>), dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs,
+                           near, far);
+}
+
+template <int KIND, bool BF16>
+hipError_t launch_mrhs_lp_k(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
+{
+    switch ((T.d + 3) / 4 * 4) {
+    case 4: launch_mrhs_lp_d<KIND, 4, BF16>(T, O, y, nrhs, near, far, st); break;
+    case 8: launch_mrhs_lp_d<KIND, 8, BF16>(T, O, y, nrhs, near, far, st); break;
+    case 12: launch_mrhs_lp_d<KIND, 12, BF16>(T, O, y, nrhs, near, far, st); break;
+    case 16: launch_mrhs_lp_d<KIND, 16, BF16>(T, O, y, nrhs, near, far, st); break;
+    case 20: launch_mrhs_lp_d<KIND, 20, BF16>(T, O, y, nrhs, near, far, st); break;
+    case 24: launch_mrhs_lp_d<KIND, 24, BF16>(T, O, y, nrhs, near, far, st); break;
+    case 28: launch_mrhs_lp_d<KIND, 28, BF16>(T, O, y, nrhs, near, far, st); break;
+    case 32: launch_mrhs_lp_d<KIND, 32, BF16>(T, O, y, nrhs, near, far, st); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// M2L for one rhs in FP32: FP32 Gram tiles of the node pairs, FP32 kernel values and sums.
+template <int KIND, int DK, int NXT>
+__global__ __launch_bounds__(256) void m2l_mfma32_kernel(DevTree T, DevOp O, int first)
+{
+    constexpr int NKC = DK / 4, NXP = 16 * NXT;
+    __shared__ float part[4 * NXP];
+    const int c = first + blockIdx.x;
+    const int nx = O.nx;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int f0 = T.Fptr[c], f1 = T.Fptr[c + 1];
+    const float inv_ell = (float)(1.0 / O.ell);
+    const double *tnode = O.nodesT + (size_t)c * DK * NXP;
+    float A[NXT][NKC], tn[NXT][4], racc[NXT][4];
+#pragma unroll
+    for (int rt = 0; rt < NXT; ++rt) {
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) A[rt][kc] = (float)tnode[(4 * kc + lg) * NXP + 16 * rt + li];
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            tn[rt][v] = (float)O.nnorm[(size_t)c * NXP + 16 * rt + 4 * lg + v];
+            racc[rt][v] = 0.0f;
+        }
+    }
+    for (int f = f0 + w; f < f1; f += 4) {
+        const int s = T.Fsrc[f];
+        const double *snode = O.nodesT + (size_t)s * DK * NXP;
+#pragma unroll
+        for (int ct = 0; ct < NXT; ++ct) {
+            const int b = 16 * ct + li;
+            float B[NKC];
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) B[kc] = (float)snode[(4 * kc + lg) * NXP + b];
+            const float nb = (float)O.nnorm[(size_t)s * NXP + b];
+            const float mb = b < nx ? (float)O.M[(size_t)s * nx + b] : 0.0f;
+#pragma unroll
+            for (int rt = 0; rt < NXT; ++rt) {
+                flt4 G = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(A[rt][kc], B[kc], G, 0, 0, 0);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) {
+                    const float r2 = fmaxf(fmaf(-2.0f, G[v], tn[rt][v] + nb), 0.0f);
+                    racc[rt][v] = fmaf(kernel_f32<KIND>(r2, inv_ell), mb, racc[rt][v]);
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int rt = 0; rt < NXT; ++rt)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            float s = racc[rt][v];
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            s += __shfl_xor(s, 4, 64);
+            s += __shfl_xor(s, 8, 64);
+            if (li == 0) part[w * NXP + 16 * rt + 4 * lg + v] = s;
+        }
+    __syncthreads();
+    if (tid < nx)
+        O.L[(size_t)c * nx + tid] = (double)(((part[tid] + part[NXP + tid]) + part[2 * NXP + tid]) + part[3 * NXP + tid]);
+}
+
+template <int KIND, int DK>
+void launch_m2l32_d(const DevTree &T, const DevOp &O, int first, int cnt, hipStream_t st)
+{
+    switch (O.nxp / 16) {
+    case 1: hipLaunchKernelGGL((m2l_mfma32_kernel<KIND, DK, 1>), dim3(cnt), dim3(256), 0, st, T, O, first); break;
+    case 2: hipLaunchKernelGGL((m2l_mfma32_kernel<KIND, DK, 2>), dim3(cnt), dim3(256), 0, st, T, O, first); break;
+    case 3: hipLaunchKernelGGL((m2l_mfma32_kernel<KIND, DK, 3>), dim3(cnt), dim3(256), 0, st, T, O, first); break;
+    default: hipLaunchKernelGGL((m2l_mfma32_kernel<KIND, DK, 4>), dim3(cnt), dim3(256), 0, st, T, O, first); break;
+    }
+}
+
+template <int KIND>
+void launch_m2l32_k(const DevTree &T, const DevOp &O, int first, int cnt, hipStream_t st)
+{
+    switch ((T.d + 3) / 4 * 4) {
+    case 4: launch_m2l32_d<KIND, 4>(T, O, first, cnt, st); break;
+    case 8: launch_m2l32_d<KIND, 8>(T, O, first, cnt, st); break;
+    case 12: launch_m2l32_d<KIND, 12>(T, O, first, cnt, st); break;
+    case 16: launch_m2l32_d<KIND, 16>(T, O, first, cnt, st); break;
+    case 20: launch_m2l32_d<KIND, 20>(T, O, first, cnt, st); break;
+    case 24: launch_m2l32_d<KIND, 24>(T, O, first, cnt, st); break;
+    case 28: launch_m2l32_d<KIND, 28>(T, O, first, cnt, st); break;
+    default: launch_m2l32_d<KIND, 32>(T, O, first, cnt, st); break;
+    }
+}
+
 // ---------------------------------------------------------------- deterministic dot products
 __global__ __launch_bounds__(256) void dot_partial_kernel(const double *__restrict__ a, const double *__restrict__ b,
                                                           int n, int nrhs, double *__restrict__ partial)
@@ -875,7 +1339,13 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
         const int cnt = T.ncl - first;
         if (timer) (void)hipEventRecord(timer->m2l_start, st);
         const bool mfma = nrhs == 1 && O.kind <= 2 && T.d <= 32 && O.nxp <= 64 && O.nodesT && O.nnorm;
-        if (mfma) {
+        if (mfma && precision != 0) {
+            switch (O.kind) {
+            case 0: launch_m2l32_k<0>(T, O, first, cnt, st); break;
+            case 1: launch_m2l32_k<1>(T, O, first, cnt, st); break;
+            default: launch_m2l32_k<2>(T, O, first, cnt, st); break;
+            }
+        } else if (mfma) {
             switch (O.kind) {
             case 0: launch_m2l_mfma_k<0>(T, O, first, cnt, st); break;
             case 1: launch_m2l_mfma_k<1>(T, O, first, cnt, st); break;
@@ -899,11 +1369,18 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
     const bool sym = nrhs == 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && T.d <= 32 && O.rowbuf && O.colbuf;
     if (timer) (void)hipEventRecord(timer->p2p_start, st);
     if (sym) {
-        if (near) {
+        if (near && precision == 0) {
             switch (O.kind) {
             case 0: e = launch_sym_k<0>(T, O, st); break;
             case 1: e = launch_sym_k<1>(T, O, st); break;
             default: e = launch_sym_k<2>(T, O, st); break;
+            }
+            if (e != hipSuccess) return e;
+        } else if (near) {  // FP32 (and BF16, whose single-rhs product has nothing to put on the BF16 MFMA)
+            switch (O.kind) {
+            case 0: e = launch_sym32_k<0>(T, O, st); break;
+            case 1: e = launch_sym32_k<1>(T, O, st); break;
+            default: e = launch_sym32_k<2>(T, O, st); break;
             }
             if (e != hipSuccess) return e;
         }
@@ -915,10 +1392,24 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
     const int dk = (T.d + 3) / 4 * 4;
     const bool mrhs = nrhs > 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && dk <= 32 && !(dk > 28 && nrhs > 16);
     if (mrhs) {
-        switch (O.kind) {
-        case 0: e = launch_mrhs_k<0>(T, O, y, nrhs, near, far, st); break;
-        case 1: e = launch_mrhs_k<1>(T, O, y, nrhs, near, far, st); break;
-        default: e = launch_mrhs_k<2>(T, O, y, nrhs, near, far, st); break;
+        if (precision == 0) {
+            switch (O.kind) {
+            case 0: e = launch_mrhs_k<0>(T, O, y, nrhs, near, far, st); break;
+            case 1: e = launch_mrhs_k<1>(T, O, y, nrhs, near, far, st); break;
+            default: e = launch_mrhs_k<2>(T, O, y, nrhs, near, far, st); break;
+            }
+        } else if (precision == 1) {
+            switch (O.kind) {
+            case 0: e = launch_mrhs_lp_k<0, false>(T, O, y, nrhs, near, far, st); break;
+            case 1: e = launch_mrhs_lp_k<1, false>(T, O, y, nrhs, near, far, st); break;
+            default: e = launch_mrhs_lp_k<2, false>(T, O, y, nrhs, near, far, st); break;
+            }
+        } else {
+            switch (O.kind) {
+            case 0: e = launch_mrhs_lp_k<0, true>(T, O, y, nrhs, near, far, st); break;
+            case 1: e = launch_mrhs_lp_k<1, true>(T, O, y, nrhs, near, far, st); break;
+            default: e = launch_mrhs_lp_k<2, true>(T, O, y, nrhs, near, far, st); break;
+            }
         }
         if (timer) (void)hipEventRecord(timer->p2p_stop, st);
         return e;
