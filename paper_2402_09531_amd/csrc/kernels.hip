@@ -1193,6 +1193,142 @@ hipError_t launch_mrhs_lp_k(const DevTree &T, const DevOp &O, double *y, int nrh
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- M2L for several rhs on MFMA
+// l_c[a][r] += sum_b S[a][b] m_s[b][r] over the farfield sources s of c.  As in the several-rhs
+// nearfield, the Gram tile of node pairs is formed with the source nodes as the A operand so
+// its elements are the A operand of the apply MFMAs.  FP32 = false: FP64 throughout (element
+// v of lane (a + 16 g) is S[a][4v + g]); FP32 = true: FP32 Gram/kernel/apply (element e of lane
+// (a + 16 g) is S[a][4g + e]).  nx <= 32 (two node tiles), up to 32 rhs (two rhs tiles); the
+// four waves split the source list and their partial sums are added in wave order.
+template <bool FP32>
+struct m2l_types;
+template <>
+struct m2l_types<false> {
+    typedef double T;
+    typedef dbl4 V;
+};
+template <>
+struct m2l_types<true> {
+    typedef float T;
+    typedef flt4 V;
+};
+
+template <int KIND, int DK, bool FP32>
+__global__ __launch_bounds__(256) void m2l_mrhs_kernel(DevTree T, DevOp O, int first, int nrhs)
+{
+    typedef typename m2l_types<FP32>::T R;
+    typedef typename m2l_types<FP32>::V V4;
+    constexpr int NKC = DK / 4;
+    __shared__ double part[32 * 33];
+    const int c = first + blockIdx.x;
+    const int nx = O.nx, nxp = O.nxp;
+    const int nxt = nxp / 16, nrb = (nrhs + 15) / 16;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int f0 = T.Fptr[c], f1 = T.Fptr[c + 1];
+    const double inv_ell = 1.0 / O.ell;
+    // target nodes as the B operand: lane (a + 16 g) holds coordinate 4 kc + g of node 16 rt + a
+    const double *tnode = O.nodesT + (size_t)c * DK * nxp;
+    R Bt[2][NKC], tn[2];
+    V4 Y[2][2];
+#pragma unroll
+    for (int rt = 0; rt < 2; ++rt) {
+        const int a = rt < nxt ? 16 * rt + li : li;
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) Bt[rt][kc] = (R)tnode[(4 * kc + lg) * nxp + a];
+        tn[rt] = (R)O.nnorm[(size_t)c * nxp + a];
+#pragma unroll
+        for (int rb = 0; rb < 2; ++rb) Y[rt][rb] = V4{0, 0, 0, 0};
+    }
+    for (int f = f0 + w; f < f1; f += 4) {
+        const int s = T.Fsrc[f];
+        const double *snode = O.nodesT + (size_t)s * DK * nxp;
+        const double *ms = O.M + (size_t)s * nx * nrhs;
+#pragma unroll
+        for (int ct = 0; ct < 2; ++ct) {
+            if (ct >= nxt) continue;
+            R Af[NKC];
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) Af[kc] = (R)snode[(4 * kc + lg) * nxp + 16 * ct + li];
+            R sn[4], Mq[2][4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int b = FP32 ? 16 * ct + 4 * lg + e : 16 * ct + 4 * e + lg;  // source node of element e
+                sn[e] = (R)O.nnorm[(size_t)s * nxp + b];
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) {
+                    // B operand of chunk e: lane (r + 16 g) holds m_s[source node][rhs 16 rb + r]
+                    const int bb = FP32 ? 16 * ct + 4 * lg + e : 16 * ct + 4 * e + lg;
+                    const int r = 16 * rb + li;
+                    Mq[rb][e] = (bb < nx && r < nrhs && rb < nrb) ? (R)ms[(size_t)bb * nrhs + r] : (R)0;
+                }
+            }
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt) {
+                if (rt >= nxt) continue;
+                V4 G = {0, 0, 0, 0};
+                R Kv[4];
+                if constexpr (FP32) {
+#pragma unroll
+                    for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[kc], Bt[rt][kc], G, 0, 0, 0);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        Kv[e] = kernel_f32<KIND>(fmaxf(fmaf(-2.0f, G[e], tn[rt] + sn[e]), 0.0f), (float)inv_ell);
+                } else {
+#pragma unroll
+                    for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[kc], Bt[rt][kc], G, 0, 0, 0);
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) Kv[e] = kernel_fast<KIND>(fmax(fma(-2.0, G[e], tn[rt] + sn[e]), 0.0), inv_ell);
+                }
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) {
+                    if (rb >= nrb) continue;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) {
+                        if constexpr (FP32)
+                            Y[rt][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Kv[e], Mq[rb][e], Y[rt][rb], 0, 0, 0);
+                        else
+                            Y[rt][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kv[e], Mq[rb][e], Y[rt][rb], 0, 0, 0);
+                    }
+                }
+            }
+        }
+    }
+    // output element v of lane (r + 16 g): target node 4g + v (FP32) or 4v + g (FP64), rhs r
+    for (int ww = 0; ww < 4; ++ww) {
+        if (w == ww) {
+#pragma unroll
+            for (int rt = 0; rt < 2; ++rt)
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb)
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const int a = 16 * rt + (FP32 ? 4 * lg + v : 4 * v + lg), r = 16 * rb + li;
+                        const double val = (double)Y[rt][rb][v];
+                        part[a * 33 + r] = ww == 0 ? val : part[a * 33 + r] + val;
+                    }
+        }
+        __syncthreads();
+    }
+    for (int p = tid; p < nx * nrhs; p += 256) {
+        const int a = p / nrhs, r = p % nrhs;
+        O.L[(size_t)c * nx * nrhs + p] = part[a * 33 + r];
+    }
+}
+
+template <int KIND, bool FP32>
+void launch_m2l_mrhs_k(const DevTree &T, const DevOp &O, int first, int cnt, int nrhs, hipStream_t st)
+{
+    switch ((T.d + 3) / 4 * 4) {
+#define DWFMM_M2LR(D) \
+    case D: hipLaunchKernelGGL((m2l_mrhs_kernel<KIND, D, FP32>), dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+        DWFMM_M2LR(4) DWFMM_M2LR(8) DWFMM_M2LR(12) DWFMM_M2LR(16) DWFMM_M2LR(20) DWFMM_M2LR(24) DWFMM_M2LR(28)
+    default:
+        DWFMM_M2LR(32)
+#undef DWFMM_M2LR
+    }
+}
+
 // M2L for one rhs in FP32: FP32 Gram tiles of the node pairs, FP32 kernel values and sums.
 template <int KIND, int DK, int NXT>
 __global__ __launch_bounds__(256) void m2l_mfma32_kernel(DevTree T, DevOp O, int first)
@@ -1339,7 +1475,15 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
         const int cnt = T.ncl - first;
         if (timer) (void)hipEventRecord(timer->m2l_start, st);
         const bool mfma = nrhs == 1 && O.kind <= 2 && T.d <= 32 && O.nxp <= 64 && O.nodesT && O.nnorm;
-        if (mfma && precision != 0) {
+        const bool mfma_r = nrhs > 1 && O.kind <= 2 && T.d <= 32 && O.nxp <= 32 && O.nodesT && O.nnorm;
+        if (mfma_r) {
+            const bool lp = precision != 0;
+            switch (O.kind) {
+            case 0: lp ? launch_m2l_mrhs_k<0, true>(T, O, first, cnt, nrhs, st) : launch_m2l_mrhs_k<0, false>(T, O, first, cnt, nrhs, st); break;
+            case 1: lp ? launch_m2l_mrhs_k<1, true>(T, O, first, cnt, nrhs, st) : launch_m2l_mrhs_k<1, false>(T, O, first, cnt, nrhs, st); break;
+            default: lp ? launch_m2l_mrhs_k<2, true>(T, O, first, cnt, nrhs, st) : launch_m2l_mrhs_k<2, false>(T, O, first, cnt, nrhs, st); break;
+            }
+        } else if (mfma && precision != 0) {
             switch (O.kind) {
             case 0: launch_m2l32_k<0>(T, O, first, cnt, st); break;
             case 1: launch_m2l32_k<1>(T, O, first, cnt, st); break;
