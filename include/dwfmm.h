@@ -135,6 +135,26 @@ dwfmm_status dwfmm_fmm_matvec_parts(dwfmm_op op, const double *x, double *y, int
 dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double *f, double *alpha, int32_t nrhs,
                              double rtol, int32_t max_iter, void *stream, dwfmm_solve_info *info);
 
+/* ---- batches of independent problems --------------------------------------
+ * A batch runs one matvec (one rhs each) of many operators with one launch per
+ * kernel variant and tree level across all of them (work lists of (problem, block)
+ * pairs), so that many small problems fill the GPU together.  Operators with a
+ * polynomial kernel, leaves above 128 points, d > 32 or n_x > 64 are run one by
+ * one inside the same call.  Each problem uses its operator's precision and
+ * workspace: do not run an operator alone while its batch runs.  The operators
+ * must outlive the batch.
+ *   ops    host array of count operators (count >= 1)
+ *   flags  DWFMM_BATCH_GRAPH: capture the batched launches as one HIP graph at
+ *          creation and replay it on every call
+ * Synchronises `stream`.  Errors: E_INVALID, E_NOMEM, E_HIP.                    */
+typedef struct dwfmm_batch_s *dwfmm_batch;
+#define DWFMM_BATCH_GRAPH 1
+dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, int32_t flags, void *stream, dwfmm_batch *out);
+/* y_i = K~_i x_i for every problem i.  xs, ys: host arrays of count device pointers
+ * (N_i x 1 each, caller order, x_i != y_i).  Asynchronous on `stream`; allocates nothing. */
+dwfmm_status dwfmm_batch_matvec(dwfmm_batch batch, const double *const *xs, double *const *ys, void *stream);
+void dwfmm_batch_destroy(dwfmm_batch batch);
+
 /* Device bytes an operator would hold for the given sizes (admission control). */
 size_t dwfmm_estimate_bytes(int64_t n, int32_t d, int32_t leaf_size, int32_t n_x, int32_t nrhs);
 /* Device bytes held by a tree plus operator. */

@@ -58,7 +58,8 @@ _lib = None
 EXPORTS = ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
            "dwfmm_fmm_solve", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
            "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info",
-           "dwfmm_op_basis", "dwfmm_op_moments", "dwfmm_op_timing"]
+           "dwfmm_op_basis", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
+           "dwfmm_batch_destroy"]
 
 
 def lib():
@@ -90,6 +91,12 @@ def lib():
         L.dwfmm_op_basis.argtypes = [vp, C.POINTER(C.c_uint8), dp, dp, dp]
         L.dwfmm_op_moments.argtypes = [vp, dp, dp, C.c_int32]
         L.dwfmm_op_timing.argtypes = [vp, C.c_int32, dp]
+        L.dwfmm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, vp, C.POINTER(vp)]
+        L.dwfmm_batch_create.restype = C.c_int
+        L.dwfmm_batch_matvec.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
+        L.dwfmm_batch_matvec.restype = C.c_int
+        L.dwfmm_batch_destroy.argtypes = [vp]
+        L.dwfmm_batch_destroy.restype = None
         for name in ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
                      "dwfmm_fmm_solve", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info", "dwfmm_op_basis",
                      "dwfmm_op_moments", "dwfmm_op_timing"]:
@@ -256,6 +263,46 @@ def fmm_solve(op: Op, lam: float, f, alpha, rtol: float, max_iter: int = 10000, 
     if st not in (OK, E_NOT_CONVERGED, E_BREAKDOWN) or (raise_on_error and st != OK):
         _check(st)
     return [i.as_dict() for i in infos]
+
+
+BATCH_GRAPH = 1
+
+
+class Batch:
+    """Handle of a dwfmm_batch: one matvec over many operators per call."""
+
+    def __init__(self, handle, ops):
+        self._h = handle
+        self.ops = list(ops)   # keeps the operators alive
+
+    def close(self):
+        if self._h:
+            lib().dwfmm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def batch_create(ops, graph: bool = False, stream=None) -> Batch:
+    """dwfmm_batch_create over a list of Op."""
+    arr = (C.c_void_p * len(ops))(*[o._h for o in ops])
+    h = C.c_void_p()
+    _check(lib().dwfmm_batch_create(arr, len(ops), BATCH_GRAPH if graph else 0, _stream(stream), C.byref(h)))
+    return Batch(h, ops)
+
+
+def batch_matvec(batch: Batch, xs, ys, stream=None):
+    """dwfmm_batch_matvec: ys[i] = K~_i xs[i] for every operator of the batch."""
+    n = len(batch.ops)
+    if len(xs) != n or len(ys) != n:
+        raise ValueError("xs and ys must have one tensor per operator")
+    xa = (C.c_void_p * n)(*[_dev_f64(x, "x").value for x in xs])
+    ya = (C.c_void_p * n)(*[_dev_f64(y, "y").value for y in ys])
+    _check(lib().dwfmm_batch_matvec(batch._h, xa, ya, _stream(stream)))
 
 
 def estimate_bytes(n: int, d: int, leaf_size: int, n_x: int, nrhs: int) -> int:

@@ -738,6 +738,208 @@ extern "C" dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double
     return worst;
 }
 
+// ============================================================== batches of problems
+struct dwfmm_batch_s {
+    std::vector<dwfmm_op> ops;        // all problems, in caller order
+    std::vector<int> item_of;         // op index -> batch item, or -1 (run on its own)
+    std::vector<BatchItem> items;
+    Arena arena;
+    BatchPlan plan;
+    const double **d_xs = nullptr;
+    double **d_ys = nullptr;
+    std::vector<const double *> h_xs;  // staged pointer arrays (pinned by the vectors)
+    std::vector<double *> h_ys;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    ~dwfmm_batch_s()
+    {
+        if (exec) (void)hipGraphExecDestroy(exec);
+        if (graph) (void)hipGraphDestroy(graph);
+    }
+};
+
+namespace {
+
+bool batch_eligible(dwfmm_op op)
+{
+    const DevTree &T = op->tree->D;
+    return op->D.kind <= 2 && T.max_leaf <= 128 && T.d <= 32 && op->D.nxp <= 64 && T.dpad == (T.d + 3) / 4 * 4;
+}
+
+}  // namespace
+
+extern "C" dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, int32_t flags, void *stream,
+                                           dwfmm_batch *out)
+{
+    if (!out) return fail(DWFMM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!ops || count < 1) return fail(DWFMM_E_INVALID, "ops is NULL or count < 1");
+    for (int i = 0; i < count; ++i)
+        if (!ops[i]) return fail(DWFMM_E_INVALID, "ops contains NULL");
+    hipStream_t st = (hipStream_t)stream;
+    dwfmm_batch b = new (std::nothrow) dwfmm_batch_s();
+    if (!b) return fail(DWFMM_E_NOMEM, "host allocation failed");
+    b->ops.assign(ops, ops + count);
+    b->item_of.assign(count, -1);
+    for (int i = 0; i < count; ++i) {
+        if (!batch_eligible(ops[i])) continue;
+        const DevTree &T = ops[i]->tree->D;
+        BatchItem it{};
+        it.T = T;
+        it.O = ops[i]->D;
+        it.far = T.min_far_level <= T.J;
+        it.precision = ops[i]->precision;
+        b->item_of[i] = (int)b->items.size();
+        b->items.push_back(it);
+    }
+    // work lists: leaves, per level M2M / L2L, and one slice per kernel variant for M2L and P2P
+    std::vector<int2> work;
+    BatchPlan &P = b->plan;
+    P.leaf_off = 0;
+    for (int it = 0; it < (int)b->items.size(); ++it)
+        for (int l = 0; l < b->items[it].T.nleaf; ++l) work.push_back(make_int2(it, l));
+    P.leaf_cnt = (int)work.size();
+    int maxJ = 0;
+    for (auto &it : b->items) maxJ = std::max(maxJ, it.T.J);
+    for (int j = maxJ - 1; j >= 0; --j) {
+        const int off = (int)work.size();
+        for (int it = 0; it < (int)b->items.size(); ++it) {
+            const BatchItem &I = b->items[it];
+            if (!I.far || j < I.T.min_far_level || j >= I.T.J) continue;
+            for (int c = (1 << j) - 1; c < (1 << (j + 1)) - 1; ++c) work.push_back(make_int2(it, c));
+        }
+        if ((int)work.size() > off) P.m2m.push_back({off, (int)work.size() - off});
+    }
+    for (int j = 1; j <= maxJ; ++j) {
+        const int off = (int)work.size();
+        for (int it = 0; it < (int)b->items.size(); ++it) {
+            const BatchItem &I = b->items[it];
+            if (!I.far || j < I.T.min_far_level + 1 || j > I.T.J) continue;
+            for (int c = (1 << j) - 1; c < (1 << (j + 1)) - 1; ++c) work.push_back(make_int2(it, c));
+        }
+        if ((int)work.size() > off) P.l2l.push_back({off, (int)work.size() - off});
+    }
+    auto key = [&](const BatchItem &I, bool far_list) {
+        return std::vector<int>{I.O.kind, (I.T.d + 3) / 4 * 4, far_list ? I.O.nxp / 16 : 0, I.precision != 0};
+    };
+    std::vector<std::vector<int>> keys;
+    for (auto &it : b->items) {
+        for (int fl = 0; fl < 2; ++fl) {
+            if (fl && !it.far) continue;
+            auto k = key(it, fl);
+            k.push_back(fl);
+            if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+        }
+    }
+    for (auto &k : keys) {
+        const bool far_list = k[4];
+        std::vector<int2> lst;
+        for (int it = 0; it < (int)b->items.size(); ++it) {
+            const BatchItem &I = b->items[it];
+            auto ki = key(I, far_list);
+            ki.push_back(far_list);
+            if (ki != k) continue;
+            if (far_list) {
+                if (!I.far) continue;
+                for (int c = (1 << I.T.min_far_level) - 1; c < I.T.ncl; ++c) lst.push_back(make_int2(it, c));
+            } else {
+                for (int l = 0; l < I.T.nleaf; ++l) lst.push_back(make_int2(it, l));
+            }
+        }
+        if (lst.empty()) continue;
+        if (!far_list) {
+            // consecutive leaves on one XCD: block q is dealt to XCD q % 8
+            while (lst.size() % 8) lst.push_back(make_int2(-1, 0));
+            std::vector<int2> perm(lst.size());
+            const size_t chunk = lst.size() / 8;
+            for (size_t q = 0; q < lst.size(); ++q) perm[q] = lst[(q % 8) * chunk + q / 8];
+            lst.swap(perm);
+        }
+        BatchLaunch L{k[0], k[1], k[2], k[3], (int)work.size(), (int)lst.size()};
+        work.insert(work.end(), lst.begin(), lst.end());
+        (far_list ? P.m2l : P.p2p).push_back(L);
+    }
+    if (work.empty()) work.push_back(make_int2(-1, 0));
+    const int nitems = std::max<int>(1, (int)b->items.size());
+    BatchItem *d_items;
+    int2 *d_work;
+    hipError_t e;
+    std::vector<BatchItem> items_up(b->items);
+    if (items_up.empty()) items_up.resize(1);
+    if ((e = b->arena.upload(&d_items, items_up, st)) != hipSuccess || (e = b->arena.upload(&d_work, work, st)) != hipSuccess ||
+        (e = b->arena.alloc((void **)&b->d_xs, sizeof(double *) * nitems)) != hipSuccess ||
+        (e = b->arena.alloc((void **)&b->d_ys, sizeof(double *) * nitems)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        b->arena.release();
+        delete b;
+        return fail(e == hipErrorOutOfMemory ? DWFMM_E_NOMEM : DWFMM_E_HIP, std::string("batch setup: ") + hipGetErrorString(e));
+    }
+    P.items = d_items;
+    P.work = d_work;
+    P.xs = b->d_xs;
+    P.ys = b->d_ys;
+    b->h_xs.resize(nitems);
+    b->h_ys.resize(nitems);
+    if ((flags & DWFMM_BATCH_GRAPH) && !b->items.empty()) {
+        // capture the batched matvec once; each call refreshes the x/y pointer arrays, then replays it
+        hipStream_t cs;
+        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) == hipSuccess) {
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t el = launch_batch_matvec(P, cs);
+                e = hipStreamEndCapture(cs, &b->graph);
+                if (el != hipSuccess) e = el;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+            (void)hipStreamDestroy(cs);
+        }
+        if (e != hipSuccess) {
+            dwfmm_status s = fail(DWFMM_E_HIP, std::string("batch graph capture: ") + hipGetErrorString(e));
+            b->arena.release();
+            delete b;
+            return s;
+        }
+    }
+    *out = b;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_batch_matvec(dwfmm_batch b, const double *const *xs, double *const *ys, void *stream)
+{
+    if (!b) return fail(DWFMM_E_INVALID, "batch is NULL");
+    if (!xs || !ys) return fail(DWFMM_E_INVALID, "xs or ys is NULL");
+    hipStream_t st = (hipStream_t)stream;
+    for (size_t i = 0; i < b->ops.size(); ++i) {
+        if (!xs[i] || !ys[i] || xs[i] == ys[i]) return fail(DWFMM_E_INVALID, "bad x/y pointer in batch");
+        const int it = b->item_of[i];
+        if (it >= 0) {
+            b->h_xs[it] = xs[i];
+            b->h_ys[it] = ys[i];
+        }
+    }
+    if (!b->items.empty()) {
+        HIP_TRY(hipMemcpyAsync(b->d_xs, b->h_xs.data(), sizeof(double *) * b->items.size(), hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(b->d_ys, b->h_ys.data(), sizeof(double *) * b->items.size(), hipMemcpyHostToDevice, st));
+        if (b->exec)
+            HIP_TRY(hipGraphLaunch(b->exec, st));
+        else
+            HIP_TRY(launch_batch_matvec(b->plan, st));
+    }
+    for (size_t i = 0; i < b->ops.size(); ++i) {
+        if (b->item_of[i] >= 0) continue;
+        dwfmm_op op = b->ops[i];
+        HIP_TRY(launch_matvec(op->tree->D, op->D, xs[i], ys[i], 1, 3, op->precision, st));
+    }
+    return DWFMM_OK;
+}
+
+extern "C" void dwfmm_batch_destroy(dwfmm_batch b)
+{
+    if (!b) return;
+    b->arena.release();
+    delete b;
+}
+
 // ============================================================== sizes and introspection
 extern "C" size_t dwfmm_estimate_bytes(int64_t n, int32_t d, int32_t leaf_size, int32_t n_x, int32_t nrhs)
 {

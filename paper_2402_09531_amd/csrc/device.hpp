@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <utility>
+#include <vector>
 
 namespace dwfmm {
 
@@ -57,6 +59,32 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
 hipError_t launch_basis(const DevTree &T, int nx, const double *clo, const double *csc, const double *coff,
                         const int32_t *lidx, int nnz_max, const double *Vinv, int nleg, const int32_t *leg_axis,
                         const int32_t *leg_deg, double *Lb, hipStream_t stream);
+
+// ---- batches of independent problems (one rhs each) ----
+struct BatchItem {
+    DevTree T;
+    DevOp O;
+    int far;        // the problem has a farfield
+    int precision;  // 0 FP64, 1/2 FP32 nearfield and coupling
+};
+
+// One launch of a templated kernel over a slice of the work list.
+struct BatchLaunch {
+    int kind, dk, nxt, prec, off, cnt;
+};
+
+// Work list entries are (item, local block); entries with item < 0 are padding.
+struct BatchPlan {
+    const BatchItem *items = nullptr;
+    const double *const *xs = nullptr;
+    double *const *ys = nullptr;
+    const int2 *work = nullptr;
+    int leaf_off = 0, leaf_cnt = 0;
+    std::vector<std::pair<int, int>> m2m, l2l;  // (offset, count) per level in launch order
+    std::vector<BatchLaunch> m2l, p2p;
+};
+
+hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t stream);
 
 // ---- CG building blocks (FP64, deterministic fixed-order reductions) ----
 // partial[b][c] for b < kDotBlocks; out[c] = sum_b partial[b][c] in order.

@@ -135,11 +135,12 @@ __global__ void basis_kernel(DevTree T, int nx, const double *__restrict__ clo, 
 }
 
 // ---------------------------------------------------------------- P2M (+ gather of x into tree order)
-__global__ __launch_bounds__(256) void p2m_kernel(DevTree T, DevOp O, const double *__restrict__ x, int nrhs,
-                                                  int do_far)
+// Kernel bodies are __device__ functions of (tree, operator, block index) so that a single
+// problem and a batch of problems run the same code.
+__device__ __forceinline__ void p2m_body(const DevTree &T, const DevOp &O, int l, const double *__restrict__ x,
+                                         int nrhs, int do_far, double *xl)
 {
-    extern __shared__ double xl[];  // [max_leaf]
-    const int l = blockIdx.x, c = T.leaf_first + l;
+    const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], ce = T.cend[c], np = ce - cb;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     for (int r = 0; r < nrhs; ++r) {
@@ -161,10 +162,16 @@ __global__ __launch_bounds__(256) void p2m_kernel(DevTree T, DevOp O, const doub
     }
 }
 
-// ---------------------------------------------------------------- M2M, one level
-__global__ __launch_bounds__(64) void m2m_kernel(DevTree T, DevOp O, int first, int nrhs)
+__global__ __launch_bounds__(256) void p2m_kernel(DevTree T, DevOp O, const double *__restrict__ x, int nrhs,
+                                                  int do_far)
 {
-    const int c = first + blockIdx.x;
+    extern __shared__ double xl[];  // [max_leaf]
+    p2m_body(T, O, blockIdx.x, x, nrhs, do_far, xl);
+}
+
+// ---------------------------------------------------------------- M2M, one level
+__device__ __forceinline__ void m2m_body(const DevTree &T, const DevOp &O, int c, int nrhs)
+{
     const int nx = O.nx;
     for (int p = threadIdx.x; p < nx * nrhs; p += blockDim.x) {
         const int a = p / nrhs, r = p % nrhs;
@@ -176,6 +183,11 @@ __global__ __launch_bounds__(64) void m2m_kernel(DevTree T, DevOp O, int first, 
         }
         O.M[((size_t)c * nx + a) * nrhs + r] = s;
     }
+}
+
+__global__ __launch_bounds__(64) void m2m_kernel(DevTree T, DevOp O, int first, int nrhs)
+{
+    m2m_body(T, O, first + blockIdx.x, nrhs);
 }
 
 // ---------------------------------------------------------------- M2L, all farfield levels at once
@@ -243,11 +255,9 @@ __global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first,
 // vector ALU.  The four waves split the source list; their partial sums are added
 // in a fixed order.
 template <int KIND, int DK, int NXT>
-__global__ __launch_bounds__(256) void m2l_mfma_kernel(DevTree T, DevOp O, int first)
+__device__ __forceinline__ void m2l_mfma_body(const DevTree &T, const DevOp &O, int c, double *part)
 {
     constexpr int NKC = DK / 4, NXP = 16 * NXT;
-    __shared__ double part[4 * NXP];
-    const int c = first + blockIdx.x;
     const int nx = O.nx;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -304,6 +314,13 @@ __global__ __launch_bounds__(256) void m2l_mfma_kernel(DevTree T, DevOp O, int f
     if (tid < nx) O.L[(size_t)c * nx + tid] = ((part[tid] + part[NXP + tid]) + part[2 * NXP + tid]) + part[3 * NXP + tid];
 }
 
+template <int KIND, int DK, int NXT>
+__global__ __launch_bounds__(256) void m2l_mfma_kernel(DevTree T, DevOp O, int first)
+{
+    __shared__ double part[4 * 16 * NXT];
+    m2l_mfma_body<KIND, DK, NXT>(T, O, first + blockIdx.x, part);
+}
+
 template <int KIND, int DK>
 void launch_m2l_mfma_d(const DevTree &T, const DevOp &O, int first, int cnt, hipStream_t st)
 {
@@ -331,9 +348,8 @@ void launch_m2l_mfma_k(const DevTree &T, const DevOp &O, int first, int cnt, hip
 }
 
 // ---------------------------------------------------------------- L2L, one level
-__global__ __launch_bounds__(64) void l2l_kernel(DevTree T, DevOp O, int first, int nrhs)
+__device__ __forceinline__ void l2l_body(const DevTree &T, const DevOp &O, int c, int nrhs)
 {
-    const int c = first + blockIdx.x;
     const int par = (c - 1) / 2;
     const int nx = O.nx;
     const double *E = O.E + (size_t)c * nx * nx;
@@ -344,6 +360,11 @@ __global__ __launch_bounds__(64) void l2l_kernel(DevTree T, DevOp O, int first, 
         for (int b = 0; b < nx; ++b) s += E[a * nx + b] * lp[b * nrhs + r];
         O.L[((size_t)c * nx + a) * nrhs + r] += s;
     }
+}
+
+__global__ __launch_bounds__(64) void l2l_kernel(DevTree T, DevOp O, int first, int nrhs)
+{
+    l2l_body(T, O, first + blockIdx.x, nrhs);
 }
 
 // ---------------------------------------------------------------- P2P + L2P + scatter to original order
@@ -484,8 +505,14 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
     }
 }
 
+// consecutive leaves (spatial neighbours) on the same XCD: blocks are dealt round-robin over 8 XCDs
+__device__ __forceinline__ int xcd_leaf(int bid, int nleaf)
+{
+    return (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
+}
+
 template <int KIND, int DK>
-__global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
+__device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, int l)
 {
     constexpr int NKC = DK / 4;
     __shared__ double sX[DK * kSymLeaf];  // [k][j] shifted source coordinates
@@ -493,10 +520,6 @@ __global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
     __shared__ double colpart[4 * kSymLeaf];
     __shared__ double cen[DK];
 
-    const int nleaf = T.nleaf;
-    const int bid = blockIdx.x;
-    // consecutive leaves (spatial neighbours) on the same XCD: blocks are dealt round-robin over 8 XCDs
-    const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
     const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -603,6 +626,12 @@ __global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
             const int i = 16 * rt[u] + 4 * v + lg;
             if (li == 0 && i < nt) O.rowbuf[(size_t)l * kSymLeaf + i] = s;
         }
+}
+
+template <int KIND, int DK>
+__global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
+{
+    p2p_sym_body<KIND, DK>(T, O, xcd_leaf(blockIdx.x, T.nleaf));
 }
 
 // ---------------------------------------------------------------- MFMA nearfield, several rhs
@@ -784,10 +813,10 @@ hipError_t launch_mrhs_k(const DevTree &T, const DevOp &O, double *y, int nrhs, 
 }
 
 // y[perm] = owner row sums + received column sums (fixed order) + L2P
-__global__ __launch_bounds__(kSymLeaf) void p2p_combine_kernel(DevTree T, DevOp O, double *__restrict__ y,
-                                                               int do_near, int do_far)
+__device__ __forceinline__ void combine_body(const DevTree &T, const DevOp &O, int l, double *__restrict__ y,
+                                             int do_near, int do_far)
 {
-    const int l = blockIdx.x, c = T.leaf_first + l;
+    const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
     const int i = threadIdx.x;
     if (i >= nt) return;
@@ -801,6 +830,12 @@ __global__ __launch_bounds__(kSymLeaf) void p2p_combine_kernel(DevTree T, DevOp 
         for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * T.n + cb + i], lc[a], acc);
     }
     y[T.perm[cb + i]] = acc;
+}
+
+__global__ __launch_bounds__(kSymLeaf) void p2p_combine_kernel(DevTree T, DevOp O, double *__restrict__ y,
+                                                               int do_near, int do_far)
+{
+    combine_body(T, O, blockIdx.x, y, do_near, do_far);
 }
 
 template <int KIND>
@@ -881,16 +916,13 @@ __device__ __forceinline__ void sym_block32(const float (&A)[2][NKC], const floa
 }
 
 template <int KIND, int DK>
-__global__ __launch_bounds__(256) void p2p_sym32_kernel(DevTree T, DevOp O)
+__device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O, int l)
 {
     constexpr int NKC = DK / 4;
     __shared__ float sX[DK * kSymLeaf];
     __shared__ float sN[kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf], tQ[kSymLeaf];
     __shared__ float colpart[4 * kSymLeaf];
     __shared__ double cen[DK];
-    const int nleaf = T.nleaf;
-    const int bid = blockIdx.x;
-    const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
     const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
     if (nt == 0) return;
@@ -990,6 +1022,12 @@ __global__ __launch_bounds__(256) void p2p_sym32_kernel(DevTree T, DevOp O)
             const int i = 16 * rt[u] + 4 * lg + v;
             if (li == 0 && i < nt) O.rowbuf[(size_t)l * kSymLeaf + i] = (double)s;
         }
+}
+
+template <int KIND, int DK>
+__global__ __launch_bounds__(256) void p2p_sym32_kernel(DevTree T, DevOp O)
+{
+    p2p_sym32_body<KIND, DK>(T, O, xcd_leaf(blockIdx.x, T.nleaf));
 }
 
 template <int KIND>
@@ -1331,11 +1369,9 @@ void launch_m2l_mrhs_k(const DevTree &T, const DevOp &O, int first, int cnt, int
 
 // M2L for one rhs in FP32: FP32 Gram tiles of the node pairs, FP32 kernel values and sums.
 template <int KIND, int DK, int NXT>
-__global__ __launch_bounds__(256) void m2l_mfma32_kernel(DevTree T, DevOp O, int first)
+__device__ __forceinline__ void m2l_mfma32_body(const DevTree &T, const DevOp &O, int c, float *part)
 {
     constexpr int NKC = DK / 4, NXP = 16 * NXT;
-    __shared__ float part[4 * NXP];
-    const int c = first + blockIdx.x;
     const int nx = O.nx;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
@@ -1393,6 +1429,13 @@ __global__ __launch_bounds__(256) void m2l_mfma32_kernel(DevTree T, DevOp O, int
         O.L[(size_t)c * nx + tid] = (double)(((part[tid] + part[NXP + tid]) + part[2 * NXP + tid]) + part[3 * NXP + tid]);
 }
 
+template <int KIND, int DK, int NXT>
+__global__ __launch_bounds__(256) void m2l_mfma32_kernel(DevTree T, DevOp O, int first)
+{
+    __shared__ float part[4 * 16 * NXT];
+    m2l_mfma32_body<KIND, DK, NXT>(T, O, first + blockIdx.x, part);
+}
+
 template <int KIND, int DK>
 void launch_m2l32_d(const DevTree &T, const DevOp &O, int first, int cnt, hipStream_t st)
 {
@@ -1416,6 +1459,118 @@ void launch_m2l32_k(const DevTree &T, const DevOp &O, int first, int cnt, hipStr
     case 24: launch_m2l32_d<KIND, 24>(T, O, first, cnt, st); break;
     case 28: launch_m2l32_d<KIND, 28>(T, O, first, cnt, st); break;
     default: launch_m2l32_d<KIND, 32>(T, O, first, cnt, st); break;
+    }
+}
+
+// ---------------------------------------------------------------- batches of problems
+// Every batched kernel reads (item, local block) from a work list and runs the same body
+// as the single-problem kernel on that item's tree and operator.
+__global__ __launch_bounds__(256) void p2m_batch_kernel(const BatchItem *items, const double *const *xs,
+                                                        const int2 *work)
+{
+    __shared__ double xl[kSymLeaf];
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    const BatchItem &B = items[wk.x];
+    p2m_body(B.T, B.O, wk.y, xs[wk.x], 1, B.far, xl);
+}
+
+__global__ __launch_bounds__(64) void m2m_batch_kernel(const BatchItem *items, const int2 *work)
+{
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    m2m_body(items[wk.x].T, items[wk.x].O, wk.y, 1);
+}
+
+__global__ __launch_bounds__(64) void l2l_batch_kernel(const BatchItem *items, const int2 *work)
+{
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    l2l_body(items[wk.x].T, items[wk.x].O, wk.y, 1);
+}
+
+template <int KIND, int DK, int NXT>
+__global__ __launch_bounds__(256) void m2l_batch_kernel(const BatchItem *items, const int2 *work)
+{
+    __shared__ double part[4 * 16 * NXT];
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    m2l_mfma_body<KIND, DK, NXT>(items[wk.x].T, items[wk.x].O, wk.y, part);
+}
+
+template <int KIND, int DK, int NXT>
+__global__ __launch_bounds__(256) void m2l32_batch_kernel(const BatchItem *items, const int2 *work)
+{
+    __shared__ float part[4 * 16 * NXT];
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    m2l_mfma32_body<KIND, DK, NXT>(items[wk.x].T, items[wk.x].O, wk.y, part);
+}
+
+template <int KIND, int DK, bool FP32>
+__global__ __launch_bounds__(256) void p2p_sym_batch_kernel(const BatchItem *items, const int2 *work)
+{
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    if constexpr (FP32)
+        p2p_sym32_body<KIND, DK>(items[wk.x].T, items[wk.x].O, wk.y);
+    else
+        p2p_sym_body<KIND, DK>(items[wk.x].T, items[wk.x].O, wk.y);
+}
+
+__global__ __launch_bounds__(kSymLeaf) void combine_batch_kernel(const BatchItem *items, double *const *ys,
+                                                                 const int2 *work)
+{
+    const int2 wk = work[blockIdx.x];
+    if (wk.x < 0) return;
+    combine_body(items[wk.x].T, items[wk.x].O, wk.y, ys[wk.x], 1, items[wk.x].far);
+}
+
+template <int KIND, int DK>
+void launch_m2l_batch_d(const BatchPlan &P, const BatchLaunch &L, hipStream_t st)
+{
+    const int2 *w = P.work + L.off;
+#define DWFMM_MB(X)                                                                                        \
+    case X:                                                                                                \
+        if (L.prec != 0)                                                                                   \
+            hipLaunchKernelGGL((m2l32_batch_kernel<KIND, DK, X>), dim3(L.cnt), dim3(256), 0, st, P.items, w); \
+        else                                                                                               \
+            hipLaunchKernelGGL((m2l_batch_kernel<KIND, DK, X>), dim3(L.cnt), dim3(256), 0, st, P.items, w);   \
+        break;
+    switch (L.nxt) {
+        DWFMM_MB(1) DWFMM_MB(2) DWFMM_MB(3)
+    default:
+        DWFMM_MB(4)
+    }
+#undef DWFMM_MB
+}
+
+template <int KIND>
+void launch_m2l_batch_k(const BatchPlan &P, const BatchLaunch &L, hipStream_t st)
+{
+    switch (L.dk) {
+    case 4: launch_m2l_batch_d<KIND, 4>(P, L, st); break;
+    case 8: launch_m2l_batch_d<KIND, 8>(P, L, st); break;
+    case 12: launch_m2l_batch_d<KIND, 12>(P, L, st); break;
+    case 16: launch_m2l_batch_d<KIND, 16>(P, L, st); break;
+    case 20: launch_m2l_batch_d<KIND, 20>(P, L, st); break;
+    case 24: launch_m2l_batch_d<KIND, 24>(P, L, st); break;
+    case 28: launch_m2l_batch_d<KIND, 28>(P, L, st); break;
+    default: launch_m2l_batch_d<KIND, 32>(P, L, st); break;
+    }
+}
+
+template <int KIND, bool FP32>
+void launch_p2p_batch_k(const BatchPlan &P, const BatchLaunch &L, hipStream_t st)
+{
+    const int2 *w = P.work + L.off;
+    switch (L.dk) {
+#define DWFMM_PB(D) \
+    case D: hipLaunchKernelGGL((p2p_sym_batch_kernel<KIND, D, FP32>), dim3(L.cnt), dim3(256), 0, st, P.items, w); break;
+        DWFMM_PB(4) DWFMM_PB(8) DWFMM_PB(12) DWFMM_PB(16) DWFMM_PB(20) DWFMM_PB(24) DWFMM_PB(28)
+    default:
+        DWFMM_PB(32)
+#undef DWFMM_PB
     }
 }
 
@@ -1566,6 +1721,34 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
     }
     if (timer) (void)hipEventRecord(timer->p2p_stop, st);
     return e;
+}
+
+hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t st)
+{
+    if (P.leaf_cnt == 0) return hipSuccess;
+    hipLaunchKernelGGL(p2m_batch_kernel, dim3(P.leaf_cnt), dim3(256), 0, st, P.items, P.xs, P.work + P.leaf_off);
+    for (auto &lv : P.m2m)
+        hipLaunchKernelGGL(m2m_batch_kernel, dim3(lv.second), dim3(64), 0, st, P.items, P.work + lv.first);
+    for (auto &L : P.m2l) {
+        switch (L.kind) {
+        case 0: launch_m2l_batch_k<0>(P, L, st); break;
+        case 1: launch_m2l_batch_k<1>(P, L, st); break;
+        default: launch_m2l_batch_k<2>(P, L, st); break;
+        }
+    }
+    for (auto &lv : P.l2l)
+        hipLaunchKernelGGL(l2l_batch_kernel, dim3(lv.second), dim3(64), 0, st, P.items, P.work + lv.first);
+    for (auto &L : P.p2p) {
+        const bool lp = L.prec != 0;
+        switch (L.kind) {
+        case 0: lp ? launch_p2p_batch_k<0, true>(P, L, st) : launch_p2p_batch_k<0, false>(P, L, st); break;
+        case 1: lp ? launch_p2p_batch_k<1, true>(P, L, st) : launch_p2p_batch_k<1, false>(P, L, st); break;
+        default: lp ? launch_p2p_batch_k<2, true>(P, L, st) : launch_p2p_batch_k<2, false>(P, L, st); break;
+        }
+    }
+    hipLaunchKernelGGL(combine_batch_kernel, dim3(P.leaf_cnt), dim3(kSymLeaf), 0, st, P.items, P.ys,
+                       P.work + P.leaf_off);
+    return hipGetLastError();
 }
 
 hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double *partial, double *out,
