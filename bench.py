@@ -82,6 +82,78 @@ def summarize_profile(path: str) -> None:
                   f"pct={float(r['Percentage']):6.2f}")
 
 
+def make_batch_problems(count: int, seed: int = 4):
+    """The batching workload: N log-uniform in [2e3, 2e5], d uniform in {8..16}, x_k ~ U[0, k^-2];
+    problem i draws its points from seed 4000 + i."""
+    from paper_2402_09531_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    specs = []
+    for i in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(2e3), np.log(2e5)))))
+        d = int(rng.integers(8, 17))
+        specs.append((n, d, 4000 + i))
+    return [(n, d, W.points(n, d, 2.0, s), W.dim_weights(d, 2.0)) for n, d, s in specs]
+
+
+def bench_batch(args):
+    """Batch throughput: one batched matvec over all problems (HIP graph) against the same
+    problems one at a time."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2402_09531_amd as dw
+    dev = torch.device("cuda:0")
+    probs = make_batch_problems(args.batch)
+    total = sum(p[0] for p in probs)
+    log(f"[batch] {len(probs)} problems, {total} points, precision {args.precision}")
+    t0 = time.perf_counter()
+
+    def setup(p):
+        n, d, X, b = p
+        tree = dw.build_tree(torch.from_numpy(X).to(dev), b, 128, 0.8)
+        return dw.fmm_create(tree, "matern32", 1.0, 5, precision=args.precision)
+
+    with ThreadPoolExecutor(8) as ex:
+        ops = list(ex.map(setup, probs))
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    rng = np.random.default_rng(1)
+    xs = [torch.from_numpy(rng.standard_normal((p[0], 1))).to(dev) for p in probs]
+    ys = [torch.empty_like(x) for x in xs]
+    t0 = time.perf_counter()
+    batch = dw.batch_create(ops, graph=True)
+    t_batch = time.perf_counter() - t0
+    log(f"[batch] setup {t_setup:.1f} s, batch plan + graph {t_batch:.2f} s")
+    for _ in range(args.warmup):
+        dw.batch_matvec(batch, xs, ys)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dw.batch_matvec(batch, xs, ys)
+    torch.cuda.synchronize()
+    t_b = (time.perf_counter() - t0) / args.steps
+    ys1 = [torch.empty_like(x) for x in xs]
+    for op, x, y in zip(ops, xs, ys1):
+        dw.fmm_matvec(op, x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        for op, x, y in zip(ops, xs, ys1):
+            dw.fmm_matvec(op, x, y)
+    torch.cuda.synchronize()
+    t_s = (time.perf_counter() - t0) / args.steps
+    same = all(torch.equal(a, b) for a, b in zip(ys, ys1))
+    out = {"metric": "batched FMM matvec, problems/s", "value": round(len(probs) / t_b, 2), "unit": "problems/s",
+           "higher_is_better": True, "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": round(1e3 * t_b, 3), "dtype": args.precision, "data": "synthetic",
+           "config": {"workload": f"batch of {len(probs)} problems, N log-uniform [2e3, 2e5], d in 8..16, "
+                                  "b_k=k^-2, Matern-3/2 l=1, q=5, leaf 128, eta 0.8, 1 rhs",
+                      "total_points": total},
+           "aggregate_mpoints_per_s": round(total / t_b / 1e6, 2),
+           "one_at_a_time_ms": round(1e3 * t_s, 3), "speedup_vs_one_at_a_time": round(t_s / t_b, 3),
+           "bitwise_equal_to_one_at_a_time": bool(same), "setup_s": round(t_setup, 2)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize":
         summarize_profile(sys.argv[2])
@@ -96,6 +168,7 @@ def main():
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16"])
     ap.add_argument("--cpu-leaves", type=int, default=1 << 30, help="oracle sample size in target leaves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--batch", type=int, default=0, help="batch mode: number of independent problems")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -104,6 +177,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of "
               "the matvec is a design note, not built.", file=sys.stderr)
         sys.exit(2)
+    if args.batch:
+        bench_batch(args)
+        return
 
     import torch
     import paper_2402_09531_amd as dw
