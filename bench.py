@@ -154,6 +154,92 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
+def make_trace(count: int, rate: float, seed: int = 5):
+    """Solve requests: Poisson arrivals at `rate` per second; N log-uniform in [1e3, 5e5], d uniform
+    in {6..24}, b_k = k^-2 or k^-3 (coin flip), q in {4, 5, 6}; request i draws its points from
+    seed 5_000_000 + i; data f = sin(sum_k x_k)."""
+    from paper_2402_09531_amd import workloads as W
+    rng = np.random.default_rng(seed)
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
+    reqs = []
+    for i in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(5e5)))))
+        d = int(rng.integers(6, 25))
+        r = 2.0 if rng.random() < 0.5 else 3.0
+        q = int(rng.integers(4, 7))
+        X = W.points(n, d, r, 5_000_000 + i)
+        reqs.append(dict(t=float(arrivals[i]), X=X, b=W.dim_weights(d, r), f=np.sin(X.sum(1)), q=q))
+    return reqs
+
+
+def bench_serve(args):
+    """Continuous-batching server against plain one-at-a-time FP64 solves on the same trace."""
+    import torch
+    import paper_2402_09531_amd as dw
+    dev = torch.device("cuda:0")
+    reqs = make_trace(args.serve, args.rate)
+    lam, rtol, maxit = 1e-6, 1e-8, args.max_iter
+    log(f"[serve] {len(reqs)} requests over {reqs[-1]['t']:.2f} s, total points "
+        f"{sum(r['X'].shape[0] for r in reqs)}, max_iter {maxit}")
+    torch.cuda.synchronize()
+
+    # served: requests are submitted when their arrival time has passed; the server ticks
+    srv = dw.Server(args.budget_gb << 30, max_active=args.max_active, check_every=args.check_every)
+    t0 = time.perf_counter()
+    ids, done, nxt = {}, {}, 0
+    while len(done) < len(reqs):
+        now = time.perf_counter() - t0
+        while nxt < len(reqs) and reqs[nxt]["t"] <= now:
+            r = reqs[nxt]
+            ids[nxt] = srv.submit(r["X"], r["b"], r["f"], 128, 0.8, "matern32", 1.0, r["q"], lam, rtol, maxit)
+            nxt += 1
+        active, queued = srv.tick()
+        if active == 0 and queued == 0 and nxt < len(reqs):
+            time.sleep(max(0.0, min(0.01, reqs[nxt]["t"] - (time.perf_counter() - t0))))
+        for k, rid in ids.items():
+            if k not in done:
+                out = srv.result(rid)
+                if out is not None:
+                    done[k] = (time.perf_counter() - t0, out[1])
+    t_served = time.perf_counter() - t0
+    lat_s = np.array([done[k][0] - reqs[k]["t"] for k in range(len(reqs))])
+    iters_s = sum(done[k][1]["iters"] for k in done)
+    log(f"[serve] served: {t_served:.2f} s")
+
+    # plain: one request at a time in arrival order, FP64 solve
+    t0 = time.perf_counter()
+    fin = []
+    for r in reqs:
+        now = time.perf_counter() - t0
+        if now < r["t"]:
+            time.sleep(r["t"] - now)
+        tree = dw.build_tree(torch.from_numpy(r["X"]).to(dev), r["b"], 128, 0.8)
+        op = dw.fmm_create(tree, "matern32", 1.0, r["q"])
+        fd = torch.from_numpy(r["f"][:, None]).to(dev)
+        ad = torch.zeros_like(fd)
+        dw.fmm_solve(op, lam, fd, ad, rtol, maxit)
+        torch.cuda.synchronize()
+        op.close()
+        tree.close()
+        fin.append(time.perf_counter() - t0)
+    t_plain = time.perf_counter() - t0
+    lat_p = np.array([fin[k] - reqs[k]["t"] for k in range(len(reqs))])
+    log(f"[serve] plain: {t_plain:.2f} s")
+    pct = lambda a, p: round(float(np.percentile(a, p)) * 1e3, 2)
+    out = {"metric": "served solves/s + p99 latency vs plain", "value": round(len(reqs) / t_served, 3),
+           "unit": "solves/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "served": {"solves_per_s": round(len(reqs) / t_served, 3), "p50_ms": pct(lat_s, 50),
+                      "p99_ms": pct(lat_s, 99), "makespan_s": round(t_served, 3), "cg_iterations": int(iters_s)},
+           "plain": {"solves_per_s": round(len(reqs) / t_plain, 3), "p50_ms": pct(lat_p, 50),
+                     "p99_ms": pct(lat_p, 99), "makespan_s": round(t_plain, 3)},
+           "speedup_solves_per_s": round(t_plain / t_served, 3),
+           "config": {"workload": f"{len(reqs)} solve requests, Poisson arrivals at {args.rate}/s, N log-uniform "
+                                  "[1e3, 5e5], d in 6..24, b_k=k^-2 or k^-3, Matern-3/2 l=1, q in 4..6, "
+                                  f"lambda 1e-6, rtol 1e-8, max_iter {maxit}, leaf 128, eta 0.8, FP64 CG",
+                      "budget_gb": args.budget_gb, "max_active": args.max_active, "check_every": args.check_every}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize":
         summarize_profile(sys.argv[2])
@@ -169,6 +255,12 @@ def main():
     ap.add_argument("--cpu-leaves", type=int, default=1 << 30, help="oracle sample size in target leaves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=0, help="batch mode: number of independent problems")
+    ap.add_argument("--serve", type=int, default=0, help="serving mode: number of solve requests")
+    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
+    ap.add_argument("--max-iter", type=int, default=20, help="serving: CG iterations per request")
+    ap.add_argument("--budget-gb", type=int, default=128, help="serving: device memory budget")
+    ap.add_argument("--max-active", type=int, default=64, help="serving: active request slots")
+    ap.add_argument("--check-every", type=int, default=4, help="serving: ticks between retirement checks")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -179,6 +271,9 @@ def main():
         sys.exit(2)
     if args.batch:
         bench_batch(args)
+        return
+    if args.serve:
+        bench_serve(args)
         return
 
     import torch

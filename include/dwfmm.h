@@ -155,6 +155,46 @@ dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, int32_t flag
 dwfmm_status dwfmm_batch_matvec(dwfmm_batch batch, const double *const *xs, double *const *ys, void *stream);
 void dwfmm_batch_destroy(dwfmm_batch batch);
 
+/* ---- solve server (continuous batching) ------------------------------------
+ * Requests solve (K~ + lambda I) alpha = f (eq. (LGS)) by FP64 CG from alpha = 0, one
+ * rhs each.  A tick admits waiting requests first come first served while the device
+ * bytes they will hold fit the budget (a request is always admitted when nothing is
+ * active), runs one batched matvec over every active request, one CG update per
+ * request (scalars on the device), and every check_every ticks retires the requests
+ * that converged, broke down or used max_iter: their alpha is copied to the host and
+ * their device memory freed.  A request's tree, operator and CG state stay on the
+ * device while it is active.  A request whose setup fails is finished with that status.
+ * The server synchronises `stream` inside ticks; it is not thread-safe.            */
+typedef struct dwfmm_server_s *dwfmm_server;
+typedef struct {
+    int64_t n;                  /* points, >= 1 */
+    int32_t d;                  /* 1..64 */
+    const double *points;       /* host, n x d row-major (copied at submit) */
+    const double *dim_weights;  /* host, d values b_k > 0 */
+    const double *f;            /* host, n data values (copied at submit) */
+    int32_t leaf_size;          /* 1..1024 */
+    double eta;                 /* > 0 */
+    dwfmm_kernel kernel;
+    double q;                   /* >= 0 */
+    double lambda;              /* >= 0 */
+    double rtol;                /* > 0 */
+    int32_t max_iter;           /* >= 0 */
+    int32_t precision;          /* dwfmm_precision of the matvec inside CG */
+} dwfmm_request;
+dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_active, int32_t check_every, void *stream,
+                                 dwfmm_server *out);
+/* Queue a request; *id identifies it.  Errors: E_INVALID, E_NOMEM. */
+dwfmm_status dwfmm_server_submit(dwfmm_server server, const dwfmm_request *request, int64_t *id);
+/* One scheduling step (admission, batched matvec, CG updates, retirement). */
+dwfmm_status dwfmm_server_tick(dwfmm_server server, int32_t *n_active, int32_t *n_queued);
+/* If request id has finished: *done = 1, alpha (host, n values, may be NULL) and info are
+ * filled and the request is forgotten; otherwise *done = 0. */
+dwfmm_status dwfmm_server_result(dwfmm_server server, int64_t id, double *alpha, dwfmm_solve_info *info,
+                                 int32_t *done);
+/* Device bytes held by active requests. */
+size_t dwfmm_server_bytes(dwfmm_server server);
+void dwfmm_server_destroy(dwfmm_server server);
+
 /* Device bytes an operator would hold for the given sizes (admission control). */
 size_t dwfmm_estimate_bytes(int64_t n, int32_t d, int32_t leaf_size, int32_t n_x, int32_t nrhs);
 /* Device bytes held by a tree plus operator. */

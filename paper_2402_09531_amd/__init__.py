@@ -59,7 +59,8 @@ EXPORTS = ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fm
            "dwfmm_fmm_solve", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
            "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info",
            "dwfmm_op_basis", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
-           "dwfmm_batch_destroy"]
+           "dwfmm_batch_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
+           "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy"]
 
 
 def lib():
@@ -97,6 +98,16 @@ def lib():
         L.dwfmm_batch_matvec.restype = C.c_int
         L.dwfmm_batch_destroy.argtypes = [vp]
         L.dwfmm_batch_destroy.restype = None
+        L.dwfmm_server_create.argtypes = [C.c_size_t, C.c_int32, C.c_int32, vp, C.POINTER(vp)]
+        L.dwfmm_server_submit.argtypes = [vp, vp, C.POINTER(C.c_int64)]
+        L.dwfmm_server_tick.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
+        L.dwfmm_server_result.argtypes = [vp, C.c_int64, dp, C.POINTER(SolveInfo), C.POINTER(C.c_int32)]
+        for name in ("dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick", "dwfmm_server_result"):
+            getattr(L, name).restype = C.c_int
+        L.dwfmm_server_bytes.argtypes = [vp]
+        L.dwfmm_server_bytes.restype = C.c_size_t
+        L.dwfmm_server_destroy.argtypes = [vp]
+        L.dwfmm_server_destroy.restype = None
         for name in ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
                      "dwfmm_fmm_solve", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info", "dwfmm_op_basis",
                      "dwfmm_op_moments", "dwfmm_op_timing"]:
@@ -303,6 +314,70 @@ def batch_matvec(batch: Batch, xs, ys, stream=None):
     xa = (C.c_void_p * n)(*[_dev_f64(x, "x").value for x in xs])
     ya = (C.c_void_p * n)(*[_dev_f64(y, "y").value for y in ys])
     _check(lib().dwfmm_batch_matvec(batch._h, xa, ya, _stream(stream)))
+
+
+class _Request(C.Structure):
+    _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("points", C.POINTER(C.c_double)),
+                ("dim_weights", C.POINTER(C.c_double)), ("f", C.POINTER(C.c_double)), ("leaf_size", C.c_int32),
+                ("eta", C.c_double), ("kernel", _Kernel), ("q", C.c_double), ("lam", C.c_double),
+                ("rtol", C.c_double), ("max_iter", C.c_int32), ("precision", C.c_int32)]
+
+
+class Server:
+    """dwfmm_server: continuous-batching CG solve server (requests carry host arrays)."""
+
+    def __init__(self, budget_bytes: int, max_active: int = 64, check_every: int = 1, stream=None):
+        h = C.c_void_p()
+        self._stream = _stream(stream)
+        _check(lib().dwfmm_server_create(C.c_size_t(int(budget_bytes)), int(max_active), int(check_every),
+                                         self._stream, C.byref(h)))
+        self._h = h
+        self._n = {}
+
+    def submit(self, points, dim_weights, f, leaf_size, eta, kernel, ell, q, lam, rtol, max_iter,
+               precision="fp64") -> int:
+        pts = np.ascontiguousarray(points, dtype=np.float64)
+        b = np.ascontiguousarray(dim_weights, dtype=np.float64)
+        fv = np.ascontiguousarray(f, dtype=np.float64).reshape(-1)
+        n, d = pts.shape
+        req = _Request(n, d, _f64p(pts), _f64p(b), _f64p(fv), int(leaf_size), float(eta),
+                       _Kernel(KERNELS[kernel], float(ell)), float(q), float(lam), float(rtol), int(max_iter),
+                       PRECISIONS[precision])
+        rid = C.c_int64()
+        _check(lib().dwfmm_server_submit(self._h, C.byref(req), C.byref(rid)))
+        self._n[rid.value] = n
+        return rid.value
+
+    def tick(self):
+        """One scheduling step; returns (active, queued)."""
+        a, q = C.c_int32(), C.c_int32()
+        _check(lib().dwfmm_server_tick(self._h, C.byref(a), C.byref(q)))
+        return a.value, q.value
+
+    def result(self, rid: int):
+        """(alpha, info) if request rid finished, else None."""
+        alpha = np.zeros(self._n[rid])
+        info = SolveInfo()
+        done = C.c_int32()
+        _check(lib().dwfmm_server_result(self._h, int(rid), _f64p(alpha), C.byref(info), C.byref(done)))
+        if not done.value:
+            return None
+        del self._n[rid]
+        return alpha, info.as_dict()
+
+    def bytes_held(self) -> int:
+        return int(lib().dwfmm_server_bytes(self._h))
+
+    def close(self):
+        if self._h:
+            lib().dwfmm_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def estimate_bytes(n: int, d: int, leaf_size: int, n_x: int, nrhs: int) -> int:

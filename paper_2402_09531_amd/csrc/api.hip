@@ -120,6 +120,9 @@ static void tree_release(dwfmm_tree t)
 }
 
 // ============================================================== build_tree
+static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, int32_t d, const double *dim_weights,
+                                   int32_t leaf_size, double eta, hipStream_t st, dwfmm_tree *out);
+
 extern "C" dwfmm_status dwfmm_build_tree(const double *points, int64_t n, int32_t d, const double *dim_weights,
                                          int32_t leaf_size, double eta, void *stream, dwfmm_tree *out)
 {
@@ -138,6 +141,13 @@ extern "C" dwfmm_status dwfmm_build_tree(const double *points, int64_t n, int32_
     std::vector<double> pts((size_t)n * d);
     HIP_TRY(hipMemcpyAsync(pts.data(), points, pts.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return tree_from_host(pts, n, d, dim_weights, leaf_size, eta, st, out);
+}
+
+// Tree from host points (arguments already checked).
+static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, int32_t d, const double *dim_weights,
+                                   int32_t leaf_size, double eta, hipStream_t st, dwfmm_tree *out)
+{
     for (double v : pts)
         if (!std::isfinite(v)) return fail(DWFMM_E_NONFINITE, "points contain NaN or Inf");
 
@@ -939,6 +949,307 @@ extern "C" void dwfmm_batch_destroy(dwfmm_batch b)
     b->arena.release();
     delete b;
 }
+
+// ============================================================== solve server (continuous batching)
+namespace {
+
+struct ServerRequest {
+    int64_t id = 0;
+    int64_t n = 0;
+    int d = 0, leaf = 0, max_iter = 0, precision = 0;
+    double eta = 0, q = 0, lambda = 0, rtol = 0;
+    dwfmm_kernel kernel{};
+    std::vector<double> pts, b, f;  // host copies of the inputs
+    dwfmm_tree tree = nullptr;      // device state while active
+    dwfmm_op op = nullptr;
+    double *d_alpha = nullptr, *d_f = nullptr;
+    size_t bytes = 0;
+    int iters = 0;
+    std::vector<double> alpha;      // result
+    dwfmm_solve_info info{};
+};
+
+}  // namespace
+
+struct dwfmm_server_s {
+    size_t budget = 0, held = 0;
+    int max_active = 0, check_every = 1;
+    hipStream_t st = nullptr;
+    std::vector<ServerRequest *> queue;  // FIFO of waiting requests
+    std::vector<ServerRequest *> active;
+    std::vector<ServerRequest *> finished;
+    int64_t next_id = 0, ticks = 0;
+    dwfmm_batch batch = nullptr;
+    bool dirty = true;
+    std::vector<const double *> xs;
+    std::vector<double *> ys;
+    ~dwfmm_server_s()
+    {
+        if (batch) dwfmm_batch_destroy(batch);
+        for (auto *v : {&queue, &active, &finished})
+            for (ServerRequest *r : *v) {
+                if (r->op) dwfmm_op_destroy(r->op);
+                if (r->tree) dwfmm_tree_destroy(r->tree);
+                if (r->d_alpha) (void)hipFree(r->d_alpha);
+                if (r->d_f) (void)hipFree(r->d_f);
+                delete r;
+            }
+    }
+};
+
+namespace {
+
+void release_request(ServerRequest *r, size_t &held)
+{
+    if (r->op) dwfmm_op_destroy(r->op);
+    if (r->tree) dwfmm_tree_destroy(r->tree);
+    if (r->d_alpha) (void)hipFree(r->d_alpha);
+    if (r->d_f) (void)hipFree(r->d_f);
+    r->op = nullptr;
+    r->tree = nullptr;
+    r->d_alpha = r->d_f = nullptr;
+    held -= std::min(held, r->bytes);
+    r->bytes = 0;
+    std::vector<double>().swap(r->pts);
+    std::vector<double>().swap(r->f);
+}
+
+// Device bytes a request will hold: the operator estimate with its index-set size, plus alpha and f.
+size_t request_bytes(const ServerRequest &r)
+{
+    std::vector<double> om(r.d);
+    std::string err;
+    HostBasis B;
+    int nx = 64;
+    if (compute_weights(DWFMM_W_R1, r.d, r.b.data(), r.eta, nullptr, om.data(), err) &&
+        build_basis(r.d, om.data(), r.q, B, err))
+        nx = B.nx;
+    return dwfmm_estimate_bytes(r.n, r.d, r.leaf, nx, 1) + 2 * (size_t)r.n * sizeof(double);
+}
+
+// Admit one request: tree, operator, alpha = 0, CG start r = p = f.
+dwfmm_status admit(dwfmm_server s, ServerRequest *r)
+{
+    hipStream_t st = s->st;
+    dwfmm_status rc = tree_from_host(r->pts, r->n, r->d, r->b.data(), r->leaf, r->eta, st, &r->tree);
+    if (rc != DWFMM_OK) return rc;
+    dwfmm_opts o{};
+    o.precision = r->precision;
+    o.max_nrhs = 1;
+    o.check_every = 1;
+    rc = dwfmm_fmm_create(r->tree, r->kernel, r->q, &o, st, &r->op);
+    if (rc != DWFMM_OK) return rc;
+    const size_t nb = sizeof(double) * r->n;
+    HIP_TRY(hipMalloc(&r->d_alpha, nb));
+    HIP_TRY(hipMalloc(&r->d_f, nb));
+    HIP_TRY(hipMemcpyAsync(r->d_f, r->f.data(), nb, hipMemcpyHostToDevice, st));
+    HIP_TRY(hipMemsetAsync(r->d_alpha, 0, nb, st));
+    dwfmm_op op = r->op;
+    const size_t total = (size_t)r->n;
+    // alpha = 0: r = f, p = f
+    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->r, r->d_f, total);
+    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->p, r->d_f, total);
+    HIP_TRY(launch_dot(op->r, op->r, (int)r->n, 1, op->partial, op->scal, st));
+    HIP_TRY(launch_dot(r->d_f, r->d_f, (int)r->n, 1, op->partial, op->scal + 1, st));
+    HIP_TRY(hipMemsetAsync(op->state, 0, sizeof(int32_t) * 3, st));
+    hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(64), 0, st, op->scal, op->state, 1, r->rtol);
+    HIP_TRY(hipGetLastError());
+    r->bytes = dwfmm_op_bytes(op) + 2 * nb;
+    s->held += r->bytes;
+    r->iters = 0;
+    return DWFMM_OK;
+}
+
+// Finish a request: true FP64 residual, alpha to the host, release device memory.
+dwfmm_status retire(dwfmm_server s, ServerRequest *r, int32_t state)
+{
+    hipStream_t st = s->st;
+    dwfmm_op op = r->op;
+    std::vector<double> res, sc(2);
+    std::vector<int32_t> hs(3);
+    HIP_TRY(hipMemcpyAsync(sc.data(), op->scal, sizeof(double) * 2, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipMemcpyAsync(hs.data(), op->state, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, st));
+    HIP_TRY(residual64(op, r->lambda, r->d_f, r->d_alpha, op->q, 1, st, res));
+    r->alpha.resize(r->n);
+    HIP_TRY(hipMemcpyAsync(r->alpha.data(), r->d_alpha, sizeof(double) * r->n, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const double den = sc[1] > 0 ? std::sqrt(sc[1]) : 1.0;
+    r->info.iters = hs[1];
+    r->info.neg_curvature_steps = hs[2];
+    r->info.refine_steps = 0;
+    r->info.rel_res_recursive = std::sqrt(sc[0]) / den;
+    r->info.rel_res_true = std::sqrt(res[0]) / den;
+    r->info.status = state == 1 ? DWFMM_OK : (state == 2 ? DWFMM_E_BREAKDOWN : DWFMM_E_NOT_CONVERGED);
+    release_request(r, s->held);
+    return DWFMM_OK;
+}
+
+}  // namespace
+
+extern "C" dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_active, int32_t check_every,
+                                            void *stream, dwfmm_server *out)
+{
+    if (!out) return fail(DWFMM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (budget_bytes == 0 || max_active < 1 || check_every < 1)
+        return fail(DWFMM_E_INVALID, "budget must be > 0, max_active and check_every >= 1");
+    dwfmm_server s = new (std::nothrow) dwfmm_server_s();
+    if (!s) return fail(DWFMM_E_NOMEM, "host allocation failed");
+    s->budget = budget_bytes;
+    s->max_active = max_active;
+    s->check_every = check_every;
+    s->st = (hipStream_t)stream;
+    *out = s;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_server_submit(dwfmm_server s, const dwfmm_request *req, int64_t *id)
+{
+    if (!s || !req || !id) return fail(DWFMM_E_INVALID, "NULL argument");
+    const dwfmm_request &q = *req;
+    if (!q.points || !q.dim_weights || !q.f) return fail(DWFMM_E_INVALID, "points, dim_weights or f is NULL");
+    if (q.n < 1 || q.n > (int64_t)1 << 30 || q.d < 1 || q.d > kMaxDim || q.leaf_size < 1 || q.leaf_size > 1024 ||
+        !(q.eta > 0.0) || !(q.q >= 0.0) || !(q.lambda >= 0.0) || !(q.rtol > 0.0) || q.max_iter < 0 ||
+        q.kernel.kind < 0 || q.kernel.kind > 3 || !(q.kernel.ell > 0.0) || q.precision < 0 || q.precision > 2)
+        return fail(DWFMM_E_INVALID, "request argument out of range");
+    for (int k = 0; k < q.d; ++k)
+        if (!(q.dim_weights[k] > 0.0) || !std::isfinite(q.dim_weights[k]))
+            return fail(DWFMM_E_INVALID, "dim_weights must be finite and > 0");
+    ServerRequest *r = new (std::nothrow) ServerRequest();
+    if (!r) return fail(DWFMM_E_NOMEM, "host allocation failed");
+    r->id = s->next_id++;
+    r->n = q.n;
+    r->d = q.d;
+    r->leaf = q.leaf_size;
+    r->eta = q.eta;
+    r->q = q.q;
+    r->lambda = q.lambda;
+    r->rtol = q.rtol;
+    r->max_iter = q.max_iter;
+    r->precision = q.precision;
+    r->kernel = q.kernel;
+    r->pts.assign(q.points, q.points + (size_t)q.n * q.d);
+    r->b.assign(q.dim_weights, q.dim_weights + q.d);
+    r->f.assign(q.f, q.f + q.n);
+    s->queue.push_back(r);
+    *id = r->id;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int32_t *n_queued)
+{
+    if (!s) return fail(DWFMM_E_INVALID, "server is NULL");
+    hipStream_t st = s->st;
+    // Admission by HBM budget, first come first served (always admit when idle).  It runs
+    // after this tick's GPU work is queued, so the host-side tree builds overlap it.
+    auto admit_waiting = [&]() {
+        while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
+            ServerRequest *r = s->queue.front();
+            const size_t need = request_bytes(*r);
+            if (!s->active.empty() && s->held + need > s->budget) break;
+            s->queue.erase(s->queue.begin());
+            dwfmm_status rc = admit(s, r);
+            if (rc != DWFMM_OK) {  // the request fails, the server goes on
+                release_request(r, s->held);
+                r->info.status = rc;
+                s->finished.push_back(r);
+                continue;
+            }
+            s->active.push_back(r);
+            s->dirty = true;
+        }
+    };
+    if (s->active.empty()) admit_waiting();
+    if (!s->active.empty()) {
+        // 2. one batched matvec q = K~ p over all active requests
+        if (s->dirty) {
+            if (s->batch) dwfmm_batch_destroy(s->batch);
+            s->batch = nullptr;
+            std::vector<dwfmm_op> ops;
+            for (ServerRequest *r : s->active) ops.push_back(r->op);
+            dwfmm_status rc = dwfmm_batch_create(ops.data(), (int)ops.size(), 0, st, &s->batch);
+            if (rc != DWFMM_OK) return rc;
+            s->dirty = false;
+        }
+        s->xs.clear();
+        s->ys.clear();
+        for (ServerRequest *r : s->active) {
+            s->xs.push_back(r->op->p);
+            s->ys.push_back(r->op->q);
+        }
+        dwfmm_status rc = dwfmm_batch_matvec(s->batch, s->xs.data(), s->ys.data(), st);
+        if (rc != DWFMM_OK) return rc;
+        // 3. the CG update of every active request (FP64, its own scalars on the device)
+        for (ServerRequest *r : s->active) {
+            dwfmm_op op = r->op;
+            const size_t total = (size_t)r->n;
+            if (r->lambda != 0.0)
+                hipLaunchKernelGGL(ridge_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->q, op->p, r->lambda, total);
+            HIP_TRY(launch_dot(op->p, op->q, (int)r->n, 1, op->partial, op->scal + 2, st));
+            hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(64), 0, st, op->scal, op->state, 1);
+            hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, r->d_alpha, r->d_alpha, op->p, op->scal,
+                               4, 1.0, op->state, 0, total, 1);
+            hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->r, op->r, op->q, op->scal, 4, -1.0,
+                               op->state, 0, total, 1);
+            HIP_TRY(launch_dot(op->r, op->r, (int)r->n, 1, op->partial, op->scal + 3, st));
+            hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(64), 0, st, op->scal, op->state, 1);
+            hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->p, op->r, op->p, op->scal, 5, 1.0,
+                               op->state, 1, total, 1);
+            hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(64), 0, st, op->scal, op->state, 1, r->rtol);
+            HIP_TRY(hipGetLastError());
+            r->iters++;
+        }
+        s->ticks++;
+        admit_waiting();
+        // 4. every check_every ticks (and when a request reaches max_iter): retire finished requests
+        bool due = s->ticks % s->check_every == 0;
+        for (ServerRequest *r : s->active) due |= r->iters >= r->max_iter;
+        if (due) {
+            std::vector<int32_t> flags(s->active.size());
+            for (size_t i = 0; i < s->active.size(); ++i)
+                HIP_TRY(hipMemcpyAsync(&flags[i], s->active[i]->op->state, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            std::vector<ServerRequest *> keep;
+            for (size_t i = 0; i < s->active.size(); ++i) {
+                ServerRequest *r = s->active[i];
+                if (flags[i] != 0 || r->iters >= r->max_iter) {
+                    dwfmm_status rc = retire(s, r, flags[i]);
+                    if (rc != DWFMM_OK) return rc;
+                    s->finished.push_back(r);
+                    s->dirty = true;
+                } else {
+                    keep.push_back(r);
+                }
+            }
+            s->active.swap(keep);
+        }
+    }
+    if (n_active) *n_active = (int32_t)s->active.size();
+    if (n_queued) *n_queued = (int32_t)s->queue.size();
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_server_result(dwfmm_server s, int64_t id, double *alpha, dwfmm_solve_info *info,
+                                            int32_t *done)
+{
+    if (!s || !done) return fail(DWFMM_E_INVALID, "NULL argument");
+    *done = 0;
+    for (size_t i = 0; i < s->finished.size(); ++i) {
+        ServerRequest *r = s->finished[i];
+        if (r->id != id) continue;
+        if (alpha) std::copy(r->alpha.begin(), r->alpha.end(), alpha);
+        if (info) *info = r->info;
+        *done = 1;
+        s->finished.erase(s->finished.begin() + i);
+        delete r;
+        return DWFMM_OK;
+    }
+    return DWFMM_OK;
+}
+
+extern "C" size_t dwfmm_server_bytes(dwfmm_server s) { return s ? s->held : 0; }
+
+extern "C" void dwfmm_server_destroy(dwfmm_server s) { delete s; }
 
 // ============================================================== sizes and introspection
 extern "C" size_t dwfmm_estimate_bytes(int64_t n, int32_t d, int32_t leaf_size, int32_t n_x, int32_t nrhs)

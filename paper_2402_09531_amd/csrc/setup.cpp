@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <numeric>
+#include <thread>
 
 namespace dwfmm {
 
@@ -275,48 +276,86 @@ bool build_tree(const double *pts, int64_t n, int d, const double *b, int leaf, 
     T.hi.assign((size_t)T.ncl * d, 0.0);
     T.begin[0] = 0;
     T.end[0] = (int32_t)n;
-    for (int j = 0; j <= J; ++j) {
-        const int64_t first = ((int64_t)1 << j) - 1, last = ((int64_t)1 << (j + 1)) - 1;
-        for (int64_t c = first; c < last; ++c) {
-            const int32_t bgn = T.begin[c], e = T.end[c];
-            double *lo = &T.lo[(size_t)c * d], *hi = &T.hi[(size_t)c * d];
-            if (e > bgn) {
-                const double *x0 = pts + (size_t)T.perm[bgn] * d;
-                for (int k = 0; k < d; ++k) lo[k] = hi[k] = x0[k];
-                for (int32_t i = bgn + 1; i < e; ++i) {
-                    const double *x = pts + (size_t)T.perm[i] * d;
-                    for (int k = 0; k < d; ++k) {
-                        lo[k] = std::min(lo[k], x[k]);
-                        hi[k] = std::max(hi[k], x[k]);
-                    }
-                }
+    // Working copy of the coordinates kept in the current tree order (SoA), so that boxes and
+    // median selections read contiguous memory; the clusters of a level are independent and
+    // are processed by parallel threads.
+    std::vector<double> W((size_t)d * n);
+    for (int64_t i = 0; i < n; ++i)
+        for (int k = 0; k < d; ++k) W[(size_t)k * n + i] = pts[(size_t)i * d + k];
+    auto cluster = [&](int64_t c, int j, std::vector<std::pair<double, int32_t>> &key, std::vector<double> &tmp,
+                       std::vector<int32_t> &itmp) {
+        const int32_t bgn = T.begin[c], e = T.end[c], m = e - bgn;
+        double *lo = &T.lo[(size_t)c * d], *hi = &T.hi[(size_t)c * d];
+        for (int k = 0; k < d && m > 0; ++k) {
+            const double *w = &W[(size_t)k * n + bgn];
+            double a = w[0], z = w[0];
+            for (int32_t i = 1; i < m; ++i) {
+                a = std::min(a, w[i]);
+                z = std::max(z, w[i]);
             }
-            if (j == J) {
-                // canonical order inside a leaf: by original index
-                std::sort(T.perm.begin() + bgn, T.perm.begin() + e);
-                continue;
-            }
+            lo[k] = a;
+            hi[k] = z;
+        }
+        std::vector<int32_t> order;
+        if (j == J) {
+            // canonical order inside a leaf: by original index
+            key.resize(m);
+            for (int32_t i = 0; i < m; ++i) key[i] = {(double)T.perm[bgn + i], i};
+            std::sort(key.begin(), key.end());
+        } else {
             int axis = 0;
             double ext = -1.0;
             for (int k = 0; k < d; ++k) {
-                double w = e > bgn ? hi[k] - lo[k] : 0.0;
+                const double w = m > 0 ? hi[k] - lo[k] : 0.0;
                 if (w > ext) {
                     ext = w;
                     axis = k;
                 }
             }
-            const int32_t half = (e - bgn + 1) / 2;
-            if (e - bgn > 1) {
-                auto less = [&](int32_t u, int32_t v) {
-                    double xu = pts[(size_t)u * d + axis], xv = pts[(size_t)v * d + axis];
-                    return xu < xv || (xu == xv && u < v);
-                };
-                std::nth_element(T.perm.begin() + bgn, T.perm.begin() + bgn + half, T.perm.begin() + e, less);
-            }
+            const int32_t half = (m + 1) / 2;
             T.begin[2 * c + 1] = bgn;
             T.end[2 * c + 1] = bgn + half;
             T.begin[2 * c + 2] = bgn + half;
             T.end[2 * c + 2] = e;
+            if (m <= 1) return;
+            // order by (coordinate, original index); the left child takes the first ceil(m/2)
+            key.resize(m);
+            const double *w = &W[(size_t)axis * n + bgn];
+            for (int32_t i = 0; i < m; ++i) key[i] = {w[i], i};
+            const int32_t *pid = &T.perm[bgn];
+            std::nth_element(key.begin(), key.begin() + half, key.end(),
+                             [&](const std::pair<double, int32_t> &u, const std::pair<double, int32_t> &v) {
+                                 return u.first < v.first || (u.first == v.first && pid[u.second] < pid[v.second]);
+                             });
+        }
+        // apply the new order to the working coordinates (not needed below the leaves) and the permutation
+        tmp.resize(m);
+        itmp.resize(m);
+        for (int k = 0; k < d && j < J; ++k) {
+            double *w = &W[(size_t)k * n + bgn];
+            for (int32_t i = 0; i < m; ++i) tmp[i] = w[key[i].second];
+            std::copy(tmp.begin(), tmp.end(), w);
+        }
+        for (int32_t i = 0; i < m; ++i) itmp[i] = T.perm[bgn + key[i].second];
+        std::copy(itmp.begin(), itmp.end(), T.perm.begin() + bgn);
+    };
+    const int nthreads = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    for (int j = 0; j <= J; ++j) {
+        const int64_t first = ((int64_t)1 << j) - 1, last = ((int64_t)1 << (j + 1)) - 1;
+        const int64_t cnt = last - first;
+        const int nt = (int)std::min<int64_t>(nthreads, cnt);
+        auto work = [&](int t) {
+            std::vector<std::pair<double, int32_t>> key;
+            std::vector<double> tmp;
+            std::vector<int32_t> itmp;
+            for (int64_t c = first + t; c < last; c += nt) cluster(c, j, key, tmp, itmp);
+        };
+        if (nt <= 1 || (int64_t)n < 50000) {
+            for (int t = 0; t < nt; ++t) work(t);
+        } else {
+            std::vector<std::thread> pool;
+            for (int t = 0; t < nt; ++t) pool.emplace_back(work, t);
+            for (auto &th : pool) th.join();
         }
     }
     // block partition from (root, root)
