@@ -157,14 +157,18 @@ void dwfmm_batch_destroy(dwfmm_batch batch);
 
 /* ---- solve server (continuous batching) ------------------------------------
  * Requests solve (K~ + lambda I) alpha = f (eq. (LGS)) by FP64 CG from alpha = 0, one
- * rhs each.  A tick admits waiting requests first come first served while the device
- * bytes they will hold fit the budget (a request is always admitted when nothing is
- * active), runs one batched matvec over every active request, one CG update per
- * request (scalars on the device), and every check_every ticks retires the requests
- * that converged, broke down or used max_iter: their alpha is copied to the host and
- * their device memory freed.  A request's tree, operator and CG state stay on the
- * device while it is active.  A request whose setup fails is finished with that status.
- * The server synchronises `stream` inside ticks; it is not thread-safe.            */
+ * rhs each.  Waiting requests are handed, first come first served, to a pool of host
+ * threads (each with its own non-blocking stream) while a slot is free and the device
+ * bytes they will hold fit the budget (a request is always taken when nothing else holds
+ * memory); a thread builds the request's tree, operator and CG start and waits for its
+ * own stream.  A tick makes the prepared requests active, runs one batched matvec over
+ * every active request on `stream`, one CG update per request (scalars on the device),
+ * and every check_every ticks (or when a request used max_iter) synchronises `stream`
+ * and retires the requests that converged, broke down or used max_iter: their alpha is
+ * copied to the host and their device memory freed.  That check is the only point where
+ * a tick waits for the device, except that a tick with nothing active waits for the
+ * first prepared request.  A request whose setup fails is finished with that status.
+ * Server calls must come from one host thread at a time.                          */
 typedef struct dwfmm_server_s *dwfmm_server;
 typedef struct {
     int64_t n;                  /* points, >= 1 */
@@ -185,13 +189,14 @@ dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_active, int32_
                                  dwfmm_server *out);
 /* Queue a request; *id identifies it.  Errors: E_INVALID, E_NOMEM. */
 dwfmm_status dwfmm_server_submit(dwfmm_server server, const dwfmm_request *request, int64_t *id);
-/* One scheduling step (admission, batched matvec, CG updates, retirement). */
+/* One scheduling step (admission, batched matvec, CG updates, retirement).
+ * *n_queued counts requests waiting or being prepared. */
 dwfmm_status dwfmm_server_tick(dwfmm_server server, int32_t *n_active, int32_t *n_queued);
 /* If request id has finished: *done = 1, alpha (host, n values, may be NULL) and info are
  * filled and the request is forgotten; otherwise *done = 0. */
 dwfmm_status dwfmm_server_result(dwfmm_server server, int64_t id, double *alpha, dwfmm_solve_info *info,
                                  int32_t *done);
-/* Device bytes held by active requests. */
+/* Device bytes counted against the budget (requests being prepared or active). */
 size_t dwfmm_server_bytes(dwfmm_server server);
 void dwfmm_server_destroy(dwfmm_server server);
 

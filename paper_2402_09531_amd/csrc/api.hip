@@ -5,9 +5,13 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <condition_variable>
 #include <cstring>
+#include <deque>
+#include <mutex>
 #include <new>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/dwfmm.h"
@@ -759,6 +763,8 @@ struct dwfmm_batch_s {
     double **d_ys = nullptr;
     std::vector<const double *> h_xs;  // staged pointer arrays (pinned by the vectors)
     std::vector<double *> h_ys;
+    std::vector<BatchItem> h_items;    // host sources of the set-up uploads, kept until destruction
+    std::vector<int2> h_work;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~dwfmm_batch_s()
@@ -778,15 +784,25 @@ bool batch_eligible(dwfmm_op op)
 
 }  // namespace
 
+// Batch plan for a set of operators.  With sync == false the uploads stay queued on `st`
+// (their host sources live in the batch object), for callers that only use the batch on `st`.
+static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flags, hipStream_t st, bool sync,
+                                dwfmm_batch *out);
+
 extern "C" dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, int32_t flags, void *stream,
                                            dwfmm_batch *out)
+{
+    return batch_build(ops, count, flags, (hipStream_t)stream, true, out);
+}
+
+static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flags, hipStream_t st, bool sync,
+                                dwfmm_batch *out)
 {
     if (!out) return fail(DWFMM_E_INVALID, "out is NULL");
     *out = nullptr;
     if (!ops || count < 1) return fail(DWFMM_E_INVALID, "ops is NULL or count < 1");
     for (int i = 0; i < count; ++i)
         if (!ops[i]) return fail(DWFMM_E_INVALID, "ops contains NULL");
-    hipStream_t st = (hipStream_t)stream;
     dwfmm_batch b = new (std::nothrow) dwfmm_batch_s();
     if (!b) return fail(DWFMM_E_NOMEM, "host allocation failed");
     b->ops.assign(ops, ops + count);
@@ -874,12 +890,14 @@ extern "C" dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, i
     BatchItem *d_items;
     int2 *d_work;
     hipError_t e;
-    std::vector<BatchItem> items_up(b->items);
-    if (items_up.empty()) items_up.resize(1);
-    if ((e = b->arena.upload(&d_items, items_up, st)) != hipSuccess || (e = b->arena.upload(&d_work, work, st)) != hipSuccess ||
+    b->h_items = b->items;
+    if (b->h_items.empty()) b->h_items.resize(1);
+    b->h_work.swap(work);
+    if ((e = b->arena.upload(&d_items, b->h_items, st)) != hipSuccess ||
+        (e = b->arena.upload(&d_work, b->h_work, st)) != hipSuccess ||
         (e = b->arena.alloc((void **)&b->d_xs, sizeof(double *) * nitems)) != hipSuccess ||
         (e = b->arena.alloc((void **)&b->d_ys, sizeof(double *) * nitems)) != hipSuccess ||
-        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        (sync && (e = hipStreamSynchronize(st)) != hipSuccess)) {
         b->arena.release();
         delete b;
         return fail(e == hipErrorOutOfMemory ? DWFMM_E_NOMEM : DWFMM_E_HIP, std::string("batch setup: ") + hipGetErrorString(e));
@@ -960,46 +978,48 @@ struct ServerRequest {
     double eta = 0, q = 0, lambda = 0, rtol = 0;
     dwfmm_kernel kernel{};
     std::vector<double> pts, b, f;  // host copies of the inputs
-    dwfmm_tree tree = nullptr;      // device state while active
+    size_t need = 0;                // device bytes counted against the budget from hand-off to retirement
+    dwfmm_tree tree = nullptr;      // device state from preparation to retirement
     dwfmm_op op = nullptr;
     double *d_alpha = nullptr, *d_f = nullptr;
-    size_t bytes = 0;
+    dwfmm_status prep = DWFMM_OK;   // outcome of the preparation and its message
+    std::string prep_err;
     int iters = 0;
     std::vector<double> alpha;      // result
     dwfmm_solve_info info{};
 };
 
+constexpr int kServerWorkers = 4;
+
 }  // namespace
 
 struct dwfmm_server_s {
     size_t budget = 0, held = 0;
-    int max_active = 0, check_every = 1;
+    int max_active = 0, check_every = 1, device = 0;
     hipStream_t st = nullptr;
-    std::vector<ServerRequest *> queue;  // FIFO of waiting requests
+    std::deque<ServerRequest *> queue;  // submitted, waiting for budget and a slot (FIFO)
+    int preparing = 0;                  // handed to the workers, not yet active
     std::vector<ServerRequest *> active;
     std::vector<ServerRequest *> finished;
     int64_t next_id = 0, ticks = 0;
     dwfmm_batch batch = nullptr;
+    std::vector<dwfmm_batch> old_batches;  // replaced plans, freed at the next synchronisation
     bool dirty = true;
     std::vector<const double *> xs;
     std::vector<double *> ys;
-    ~dwfmm_server_s()
-    {
-        if (batch) dwfmm_batch_destroy(batch);
-        for (auto *v : {&queue, &active, &finished})
-            for (ServerRequest *r : *v) {
-                if (r->op) dwfmm_op_destroy(r->op);
-                if (r->tree) dwfmm_tree_destroy(r->tree);
-                if (r->d_alpha) (void)hipFree(r->d_alpha);
-                if (r->d_f) (void)hipFree(r->d_f);
-                delete r;
-            }
-    }
+    // preparation workers: each builds tree, operator and CG start on a stream of its own
+    std::mutex mu;
+    std::condition_variable cv_todo, cv_ready;
+    std::deque<ServerRequest *> todo, ready;
+    bool stop = false;
+    std::vector<std::thread> workers;
+    std::vector<hipStream_t> worker_streams;
+    ~dwfmm_server_s();
 };
 
 namespace {
 
-void release_request(ServerRequest *r, size_t &held)
+void free_request_device(ServerRequest *r)
 {
     if (r->op) dwfmm_op_destroy(r->op);
     if (r->tree) dwfmm_tree_destroy(r->tree);
@@ -1008,8 +1028,13 @@ void release_request(ServerRequest *r, size_t &held)
     r->op = nullptr;
     r->tree = nullptr;
     r->d_alpha = r->d_f = nullptr;
-    held -= std::min(held, r->bytes);
-    r->bytes = 0;
+}
+
+void release_request(ServerRequest *r, size_t &held)
+{
+    free_request_device(r);
+    held -= std::min(held, r->need);
+    r->need = 0;
     std::vector<double>().swap(r->pts);
     std::vector<double>().swap(r->f);
 }
@@ -1027,37 +1052,109 @@ size_t request_bytes(const ServerRequest &r)
     return dwfmm_estimate_bytes(r.n, r.d, r.leaf, nx, 1) + 2 * (size_t)r.n * sizeof(double);
 }
 
-// Admit one request: tree, operator, alpha = 0, CG start r = p = f.
-dwfmm_status admit(dwfmm_server s, ServerRequest *r)
+// Everything a request needs before its first iteration: tree, operator, alpha = 0 and the CG
+// start r = p = f, with its scalars.  Runs on a worker thread and its stream; returns once the
+// stream has drained, so the main stream may use the request without waiting on it.
+dwfmm_status prepare_request(ServerRequest *r, hipStream_t ws)
 {
-    hipStream_t st = s->st;
-    dwfmm_status rc = tree_from_host(r->pts, r->n, r->d, r->b.data(), r->leaf, r->eta, st, &r->tree);
+    dwfmm_status rc = tree_from_host(r->pts, r->n, r->d, r->b.data(), r->leaf, r->eta, ws, &r->tree);
     if (rc != DWFMM_OK) return rc;
     dwfmm_opts o{};
     o.precision = r->precision;
     o.max_nrhs = 1;
     o.check_every = 1;
-    rc = dwfmm_fmm_create(r->tree, r->kernel, r->q, &o, st, &r->op);
+    rc = dwfmm_fmm_create(r->tree, r->kernel, r->q, &o, ws, &r->op);
     if (rc != DWFMM_OK) return rc;
     const size_t nb = sizeof(double) * r->n;
     HIP_TRY(hipMalloc(&r->d_alpha, nb));
     HIP_TRY(hipMalloc(&r->d_f, nb));
-    HIP_TRY(hipMemcpyAsync(r->d_f, r->f.data(), nb, hipMemcpyHostToDevice, st));
-    HIP_TRY(hipMemsetAsync(r->d_alpha, 0, nb, st));
+    HIP_TRY(hipMemcpyAsync(r->d_f, r->f.data(), nb, hipMemcpyHostToDevice, ws));
+    HIP_TRY(hipMemsetAsync(r->d_alpha, 0, nb, ws));
     dwfmm_op op = r->op;
     const size_t total = (size_t)r->n;
-    // alpha = 0: r = f, p = f
-    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->r, r->d_f, total);
-    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->p, r->d_f, total);
-    HIP_TRY(launch_dot(op->r, op->r, (int)r->n, 1, op->partial, op->scal, st));
-    HIP_TRY(launch_dot(r->d_f, r->d_f, (int)r->n, 1, op->partial, op->scal + 1, st));
-    HIP_TRY(hipMemsetAsync(op->state, 0, sizeof(int32_t) * 3, st));
-    hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(64), 0, st, op->scal, op->state, 1, r->rtol);
+    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, ws, op->r, r->d_f, total);
+    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, ws, op->p, r->d_f, total);
+    HIP_TRY(launch_dot(op->r, op->r, (int)r->n, 1, op->partial, op->scal, ws));
+    HIP_TRY(launch_dot(r->d_f, r->d_f, (int)r->n, 1, op->partial, op->scal + 1, ws));
+    HIP_TRY(hipMemsetAsync(op->state, 0, sizeof(int32_t) * 3, ws));
+    hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(64), 0, ws, op->scal, op->state, 1, r->rtol);
     HIP_TRY(hipGetLastError());
-    r->bytes = dwfmm_op_bytes(op) + 2 * nb;
-    s->held += r->bytes;
-    r->iters = 0;
+    HIP_TRY(hipStreamSynchronize(ws));
     return DWFMM_OK;
+}
+
+void worker_main(dwfmm_server s, int w)
+{
+    (void)hipSetDevice(s->device);
+    hipStream_t ws = s->worker_streams[w];
+    for (;;) {
+        ServerRequest *r;
+        {
+            std::unique_lock<std::mutex> lk(s->mu);
+            s->cv_todo.wait(lk, [&] { return s->stop || !s->todo.empty(); });
+            if (s->stop) return;
+            r = s->todo.front();
+            s->todo.pop_front();
+        }
+        r->prep = prepare_request(r, ws);
+        if (r->prep != DWFMM_OK) {
+            r->prep_err = g_err;
+            (void)hipStreamSynchronize(ws);  // nothing of the failed request stays in flight
+        }
+        {
+            std::lock_guard<std::mutex> lk(s->mu);
+            s->ready.push_back(r);
+        }
+        s->cv_ready.notify_one();
+    }
+}
+
+// Hand waiting requests to the workers while slots and budget allow, first come first served
+// (a request is always taken when nothing else holds memory).  Its bytes count from here.
+void hand_off(dwfmm_server s)
+{
+    bool any = false;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        while (!s->queue.empty() && (int)s->active.size() + s->preparing < s->max_active) {
+            ServerRequest *r = s->queue.front();
+            const bool idle = s->active.empty() && s->preparing == 0;
+            if (!idle && s->held + r->need > s->budget) break;
+            s->queue.pop_front();
+            s->held += r->need;
+            s->preparing++;
+            s->todo.push_back(r);
+            any = true;
+        }
+    }
+    if (any) s->cv_todo.notify_all();
+}
+
+// Prepared requests join the active set (a failed preparation finishes the request with its
+// status); with `wait`, block until at least one is ready.
+void admit_ready(dwfmm_server s, bool wait)
+{
+    std::deque<ServerRequest *> got;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        if (wait) s->cv_ready.wait(lk, [&] { return !s->ready.empty(); });
+        got.swap(s->ready);
+    }
+    for (ServerRequest *r : got) {
+        s->preparing--;
+        if (r->prep != DWFMM_OK) {
+            release_request(r, s->held);
+            r->info.status = r->prep;
+            s->finished.push_back(r);
+            continue;
+        }
+        const size_t actual = dwfmm_op_bytes(r->op) + 2 * sizeof(double) * (size_t)r->n;
+        s->held = s->held - std::min(s->held, r->need) + actual;
+        r->need = actual;
+        r->iters = 0;
+        s->active.push_back(r);
+        s->dirty = true;
+    }
 }
 
 // Finish a request: true FP64 residual, alpha to the host, release device memory.
@@ -1086,6 +1183,30 @@ dwfmm_status retire(dwfmm_server s, ServerRequest *r, int32_t state)
 
 }  // namespace
 
+dwfmm_server_s::~dwfmm_server_s()
+{
+    {
+        std::lock_guard<std::mutex> lk(mu);
+        stop = true;
+    }
+    cv_todo.notify_all();
+    for (auto &t : workers) t.join();
+    (void)hipStreamSynchronize(st);
+    if (batch) dwfmm_batch_destroy(batch);
+    for (dwfmm_batch b : old_batches) dwfmm_batch_destroy(b);
+    for (auto *v : {&queue, &todo, &ready})
+        for (ServerRequest *r : *v) {
+            free_request_device(r);
+            delete r;
+        }
+    for (auto *v : {&active, &finished})
+        for (ServerRequest *r : *v) {
+            free_request_device(r);
+            delete r;
+        }
+    for (hipStream_t w : worker_streams) (void)hipStreamDestroy(w);
+}
+
 extern "C" dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_active, int32_t check_every,
                                             void *stream, dwfmm_server *out)
 {
@@ -1099,6 +1220,22 @@ extern "C" dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_act
     s->max_active = max_active;
     s->check_every = check_every;
     s->st = (hipStream_t)stream;
+    hipError_t e = hipGetDevice(&s->device);
+    for (int w = 0; w < kServerWorkers && e == hipSuccess; ++w) {
+        hipStream_t ws = nullptr;
+        e = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking);
+        if (e == hipSuccess) s->worker_streams.push_back(ws);
+    }
+    if (e != hipSuccess) {
+        delete s;
+        return fail(DWFMM_E_HIP, std::string("server set-up: ") + hipGetErrorString(e));
+    }
+    try {
+        for (int w = 0; w < kServerWorkers; ++w) s->workers.emplace_back(worker_main, s, w);
+    } catch (...) {
+        delete s;
+        return fail(DWFMM_E_NOMEM, "could not start the preparation threads");
+    }
     *out = s;
     return DWFMM_OK;
 }
@@ -1131,8 +1268,10 @@ extern "C" dwfmm_status dwfmm_server_submit(dwfmm_server s, const dwfmm_request 
     r->pts.assign(q.points, q.points + (size_t)q.n * q.d);
     r->b.assign(q.dim_weights, q.dim_weights + q.d);
     r->f.assign(q.f, q.f + q.n);
+    r->need = request_bytes(*r);
     s->queue.push_back(r);
     *id = r->id;
+    hand_off(s);
     return DWFMM_OK;
 }
 
@@ -1140,34 +1279,16 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
 {
     if (!s) return fail(DWFMM_E_INVALID, "server is NULL");
     hipStream_t st = s->st;
-    // Admission by HBM budget, first come first served (always admit when idle).  It runs
-    // after this tick's GPU work is queued, so the host-side tree builds overlap it.
-    auto admit_waiting = [&]() {
-        while (!s->queue.empty() && (int)s->active.size() < s->max_active) {
-            ServerRequest *r = s->queue.front();
-            const size_t need = request_bytes(*r);
-            if (!s->active.empty() && s->held + need > s->budget) break;
-            s->queue.erase(s->queue.begin());
-            dwfmm_status rc = admit(s, r);
-            if (rc != DWFMM_OK) {  // the request fails, the server goes on
-                release_request(r, s->held);
-                r->info.status = rc;
-                s->finished.push_back(r);
-                continue;
-            }
-            s->active.push_back(r);
-            s->dirty = true;
-        }
-    };
-    if (s->active.empty()) admit_waiting();
+    hand_off(s);
+    admit_ready(s, s->active.empty() && s->preparing > 0);
     if (!s->active.empty()) {
-        // 2. one batched matvec q = K~ p over all active requests
+        // one batched matvec q = K~ p over all active requests
         if (s->dirty) {
-            if (s->batch) dwfmm_batch_destroy(s->batch);
+            if (s->batch) s->old_batches.push_back(s->batch);
             s->batch = nullptr;
             std::vector<dwfmm_op> ops;
             for (ServerRequest *r : s->active) ops.push_back(r->op);
-            dwfmm_status rc = dwfmm_batch_create(ops.data(), (int)ops.size(), 0, st, &s->batch);
+            dwfmm_status rc = batch_build(ops.data(), (int)ops.size(), 0, st, false, &s->batch);
             if (rc != DWFMM_OK) return rc;
             s->dirty = false;
         }
@@ -1179,7 +1300,7 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
         }
         dwfmm_status rc = dwfmm_batch_matvec(s->batch, s->xs.data(), s->ys.data(), st);
         if (rc != DWFMM_OK) return rc;
-        // 3. the CG update of every active request (FP64, its own scalars on the device)
+        // the CG update of every active request (FP64, its own scalars on the device)
         for (ServerRequest *r : s->active) {
             dwfmm_op op = r->op;
             const size_t total = (size_t)r->n;
@@ -1200,8 +1321,8 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
             r->iters++;
         }
         s->ticks++;
-        admit_waiting();
-        // 4. every check_every ticks (and when a request reaches max_iter): retire finished requests
+        // every check_every ticks (and when a request reaches max_iter): retire finished requests.
+        // This is the only place the tick waits for the device.
         bool due = s->ticks % s->check_every == 0;
         for (ServerRequest *r : s->active) due |= r->iters >= r->max_iter;
         if (due) {
@@ -1209,6 +1330,8 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
             for (size_t i = 0; i < s->active.size(); ++i)
                 HIP_TRY(hipMemcpyAsync(&flags[i], s->active[i]->op->state, sizeof(int32_t), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
+            for (dwfmm_batch b : s->old_batches) dwfmm_batch_destroy(b);
+            s->old_batches.clear();
             std::vector<ServerRequest *> keep;
             for (size_t i = 0; i < s->active.size(); ++i) {
                 ServerRequest *r = s->active[i];
@@ -1222,10 +1345,11 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
                 }
             }
             s->active.swap(keep);
+            hand_off(s);
         }
     }
     if (n_active) *n_active = (int32_t)s->active.size();
-    if (n_queued) *n_queued = (int32_t)s->queue.size();
+    if (n_queued) *n_queued = (int32_t)(s->queue.size() + s->preparing);
     return DWFMM_OK;
 }
 
