@@ -1,4 +1,5 @@
-"""Build libdwfmm.so (HIP for gfx950) in-tree with hipcc."""
+"""Build libdwfmm.so (HIP for gfx950) in-tree with hipcc: one object per source, compiled in
+parallel, then linked."""
 from __future__ import annotations
 
 import os
@@ -8,22 +9,37 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdwfmm.so")
+OBJDIR = os.path.join(HERE, "..", "_build")
 SOURCES = ["kernels.hip", "api.hip", "setup.cpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
-    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
     # no packed FP32 instructions anywhere in the device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA accumulators in ordinary VGPRs: no accvgpr moves around the nearfield tiles
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-ffp-contract=fast", "-Wall", "-Wno-unused-function",
 ]
 
 
 def build(verbose: bool = True) -> str:
     """Compile every source into libdwfmm.so (always recompiles)."""
+    os.makedirs(OBJDIR, exist_ok=True)
+    inc = ["-I", os.path.join(HERE, "..", "include")]
+    procs, objs = [], []
+    for s in SOURCES:
+        obj = os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o")
+        cmd = [HIPCC, *FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        procs.append(subprocess.Popen(cmd))
+        objs.append(obj)
+    failed = [p.args for p in procs if p.wait() != 0]
+    if failed:
+        raise subprocess.CalledProcessError(1, failed[0])
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = [HIPCC, *FLAGS, "-I", os.path.join(HERE, "..", "include"),
-           *[os.path.join(CSRC, s) for s in SOURCES], "-o", tmp]
+    cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *objs, "-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)

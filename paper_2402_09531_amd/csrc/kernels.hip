@@ -20,27 +20,26 @@ constexpr int kMaxNodeWords = 1536;  // nx * dpad bound of the M2L node tiles
 typedef double dbl4 __attribute__((ext_vector_type(4)));  // accumulator of v_mfma_f64_16x16x4f64
 
 // e^x for x <= 0 in FP64 without special-case branches: Cody-Waite reduction
-// x = n ln2 + r, |r| <= ln2/2, with a two-part ln2, then a degree-11 polynomial
-// for e^r (coefficients: the interpolant of e^r at 12 first-kind Chebyshev points
-// of [-ln2/2, ln2/2], from csrc/gen_exp_coeffs.py), scaled by 2^n.  Arguments
-// below -745 (where e^x underflows to zero) are clamped.
+// x = n ln2 + r, |r| <= ln2/2, with a two-part ln2, then a degree-10 polynomial
+// for e^r (coefficients: the interpolant of e^r at 11 first-kind Chebyshev points
+// of [-ln2/2, ln2/2], from csrc/gen_exp_coeffs.py; 2.9e-16 relative interpolation
+// error), scaled by 2^n.  Arguments below -745 (where e^x underflows to zero) are clamped.
 __device__ __forceinline__ double exp_nonpos(double x)
 {
     x = fmax(x, -745.0);
     const double n = rint(x * 1.4426950408889634);
     double r = fma(-n, 0.6931471805599453, x);
     r = fma(-n, 2.3201926491189795e-17, r);
-    double p = 2.510908360165664e-08;
-    p = fma(p, r, 2.763264649558832e-07);
-    p = fma(p, r, 2.7557243462120405e-06);
-    p = fma(p, r, 2.4801485463689334e-05);
-    p = fma(p, r, 0.0001984126988784416);
-    p = fma(p, r, 0.001388888895233475);
-    p = fma(p, r, 0.008333333333320283);
-    p = fma(p, r, 0.04166666666648798);
-    p = fma(p, r, 0.1666666666666668);
-    p = fma(p, r, 0.5000000000000019);
-    p = fma(p, r, 1.0);
+    double p = 2.7626373407076024e-07;
+    p = fma(p, r, 2.764018103268004e-06);
+    p = fma(p, r, 2.480150429736007e-05);
+    p = fma(p, r, 0.00019841170269600702);
+    p = fma(p, r, 0.0013888888932537785);
+    p = fma(p, r, 0.008333333385668792);
+    p = fma(p, r, 0.04166666666657299);
+    p = fma(p, r, 0.166666666665544);
+    p = fma(p, r, 0.5000000000000006);
+    p = fma(p, r, 1.0000000000000067);
     p = fma(p, r, 1.0);
     return ldexp(p, (int)n);
 }
@@ -483,12 +482,14 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;  // uniform over the wave
-            dbl4 G = {0.0, 0.0, 0.0, 0.0};
+            // A holds -2 (x - c): the MFMA chain accumulates |x|^2 + |y|^2 - 2 x.y = r^2 directly
+            dbl4 G = {rN[u][0] + nb, rN[u][1] + nb, rN[u][2] + nb, rN[u][3] + nb};
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u][kc], Bf[kc], G, 0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                double r2 = fmax(fma(-2.0, G[v], rN[u][v] + nb), 0.0);
+                // rounding can leave r^2 slightly negative; only the kernels that take sqrt(r^2) need the clamp
+                double r2 = KIND == 1 ? G[v] : fmax(G[v], 0.0);
                 if constexpr (DIAG) {
                     if (16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
                 }
@@ -524,7 +525,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
-    const int n = T.n, d = T.d;
+    const int n = T.n;
     const double inv_ell = 1.0 / O.ell;
     const int ntiles = (nt + 15) / 16;
 
@@ -560,7 +561,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         for (int kc = 0; kc < NKC; ++kc) {
             const int k = 4 * kc + lg;
             const double v = T.Xs[(size_t)k * n + ii] - cen[k];
-            A[u][kc] = ok ? v : 0.0;
+            A[u][kc] = ok ? -2.0 * v : 0.0;
         }
     }
     __syncthreads();
@@ -865,14 +866,16 @@ typedef float flt4 __attribute__((ext_vector_type(4)));
 template <int KIND>
 __device__ __forceinline__ float kernel_f32(float r2, float inv_ell)
 {
+    // the products of constants are loop invariant in the callers and get hoisted
     constexpr float kLog2e = 1.4426950408889634f;
     if constexpr (KIND == 0) {
-        const float s = 1.7320508f * __builtin_amdgcn_sqrtf(r2) * inv_ell;
-        return (1.0f + s) * __builtin_amdgcn_exp2f(-s * kLog2e);
+        const float s = __builtin_amdgcn_sqrtf(r2) * (1.7320508f * inv_ell);
+        const float e = __builtin_amdgcn_exp2f(s * -kLog2e);
+        return fmaf(s, e, e);
     } else if constexpr (KIND == 1) {
-        return __builtin_amdgcn_exp2f(-r2 * inv_ell * kLog2e);
+        return __builtin_amdgcn_exp2f(r2 * (inv_ell * -kLog2e));
     } else {
-        return __builtin_amdgcn_exp2f(-__builtin_amdgcn_sqrtf(r2) * inv_ell * kLog2e);
+        return __builtin_amdgcn_exp2f(__builtin_amdgcn_sqrtf(r2) * (inv_ell * -kLog2e));
     }
 }
 
@@ -893,12 +896,13 @@ __device__ __forceinline__ void sym_block32(const float (&A)[2][NKC], const floa
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;
-            flt4 G = {0.0f, 0.0f, 0.0f, 0.0f};
+            // A holds -2 (x - c): the chain accumulates r^2 = |x|^2 + |y|^2 - 2 x.y
+            flt4 G = {rN[u][0] + nb, rN[u][1] + nb, rN[u][2] + nb, rN[u][3] + nb};
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(A[u][kc], Bf[kc], G, 0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                float r2 = fmaxf(fmaf(-2.0f, G[v], rN[u][v] + nb), 0.0f);
+                float r2 = KIND == 1 ? G[v] : fmaxf(G[v], 0.0f);
                 if constexpr (DIAG) {
                     if (16 * rt[u] + 4 * lg + v == j) r2 = 0.0f;
                 }
@@ -956,7 +960,7 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
         for (int kc = 0; kc < NKC; ++kc) {
             const int k = 4 * kc + lg;
             const float v = (float)(T.Xs[(size_t)k * n + ii] - cen[k]);
-            A[u][kc] = ok ? v : 0.0f;
+            A[u][kc] = ok ? -2.0f * v : 0.0f;
         }
     }
     __syncthreads();

@@ -222,10 +222,11 @@ def test_poly_kernel_exact_against_dense():
     assert rel(y, yd) <= 1e-12
 
 
-@pytest.mark.parametrize("q,lam", [(4, 0.1), (8, 0.01)])
+@pytest.mark.parametrize("q,lam", [(4, 0.5), (8, 0.02)])
 def test_cg_solve_residual_under_oracle(orc, q, lam):
-    """CG on (K~ + lambda I) alpha = f where the shifted operator is positive definite: the GPU's
-    alpha has an oracle-measured residual <= rtol and equals the oracle CG's solution."""
+    """CG on (K~ + lambda I) alpha = f where the shifted operator is positive definite (the lowest
+    eigenvalue of the oracle's dense K~ on this workload is -0.482 at q = 4 and -0.0117 at q = 8):
+    the GPU's alpha has an oracle-measured residual <= rtol and equals the oracle CG's solution."""
     w = W.WORKLOADS["small_d4"]
     X, b, _ = W.make(w)
     f = W.rhs(w, X)[:, None]
