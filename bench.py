@@ -57,6 +57,31 @@ def cpu_baseline(w, X, b, x, budget_leaves: int):
     }
 
 
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "p2p_sym_n1m_d20_counters.txt")
+
+
+def recorded_traffic(workload: str, n: int, nrhs: int, precision: str):
+    """HBM bytes per nearfield launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the committed
+    counter summary, or None unless it was taken on this workload and on the kernel source as it
+    is now (its sha256 is recorded in the summary)."""
+    if (workload, n, nrhs, precision) != ("n1m_d20", 1_000_000, 1, "fp64") or not os.path.exists(COUNTERS_FILE):
+        return None
+    import hashlib
+    text = open(COUNTERS_FILE).read()
+    src = os.path.join(ROOT, "paper_2402_09531_amd", "csrc", "kernels.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    if f"sha256 (paper_2402_09531_amd/csrc/kernels.hip): {sha}" not in text:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        for key in ("traffic_fetch_bytes_per_launch", "traffic_write_bytes_per_launch"):
+            if line.startswith(key + ":"):
+                vals[key] = float(line.split(":")[1].split()[0])
+    if len(vals) != 2:
+        return None
+    return vals["traffic_fetch_bytes_per_launch"] + vals["traffic_write_bytes_per_launch"]
+
+
 def summarize_profile(path: str) -> None:
     """Print a per-kernel summary of rocprofv3 CSV output under `path`: counter means per
     dispatch (``*_counter_collection.csv``) and kernel duration statistics (``*_kernel_stats.csv``)."""
@@ -375,6 +400,10 @@ def main():
         "stage_ms": {"p2p": round(p2p_avg, 4), "m2l": round(m2l_avg, 4),
                      "rest": round(ms_per_step - p2p_avg - m2l_avg, 4)},
     }
+    traffic = recorded_traffic(w.name, n, nrhs, args.precision)
+    if traffic is not None:
+        result["roofline"]["traffic"] = traffic
+        result["roofline"]["traffic_source"] = os.path.relpath(COUNTERS_FILE, ROOT)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(w, X, b, x, args.cpu_leaves)

@@ -44,17 +44,38 @@ __device__ __forceinline__ double exp_nonpos(double x)
     return ldexp(p, (int)n);
 }
 
-// Kernel value from the squared distance, with the branch-free exponential.
+// sqrt(x) for x >= 1e-300 (callers clamp; below that the kernels are 1 to double precision):
+// the hardware reciprocal square root seeds Goldschmidt's coupled iteration for g = sqrt(x)
+// and h = 1/(2 sqrt(x)), followed by two Newton corrections g += h (x - g^2).  The seed's
+// relative error e becomes about e^2 after the coupled step and is squared again by each
+// correction, so the result is within a few units in the last place.  No scaling of tiny
+// arguments and no special values, unlike the library square root.
+__device__ __forceinline__ double sqrt_pos(double x)
+{
+    const double y = __builtin_amdgcn_rsq(x);
+    double g = x * y, h = 0.5 * y;
+    const double e = fma(-h, g, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    double dd = fma(-g, g, x);
+    g = fma(dd, h, g);
+    dd = fma(-g, g, x);
+    return fma(dd, h, g);
+}
+
+// Kernel value from the squared distance, with the branch-free exponential.  r2 may be slightly
+// negative from rounding in the Gram form; the kernels that take its square root clamp it.
 template <int KIND>
 __device__ __forceinline__ double kernel_fast(double r2, double inv_ell)
 {
     if constexpr (KIND == 0) {
-        const double s = 1.7320508075688772 * sqrt(r2) * inv_ell;
-        return (1.0 + s) * exp_nonpos(-s);
+        const double s = sqrt_pos(fmax(r2, 1e-300)) * (1.7320508075688772 * inv_ell);
+        const double e = exp_nonpos(-s);
+        return fma(s, e, e);
     } else if constexpr (KIND == 1) {
         return exp_nonpos(-r2 * inv_ell);
     } else {
-        return exp_nonpos(-sqrt(r2) * inv_ell);
+        return exp_nonpos(-sqrt_pos(fmax(r2, 1e-300)) * inv_ell);
     }
 }
 
@@ -488,8 +509,7 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u][kc], Bf[kc], G, 0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                // rounding can leave r^2 slightly negative; only the kernels that take sqrt(r^2) need the clamp
-                double r2 = KIND == 1 ? G[v] : fmax(G[v], 0.0);
+                double r2 = G[v];  // kernel_fast clamps where it takes a square root
                 if constexpr (DIAG) {
                     if (16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
                 }

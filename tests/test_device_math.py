@@ -1,0 +1,110 @@
+"""The FP64 exponential and square root of the nearfield kernels, checked on the CPU.
+
+The device code evaluates e^x (x <= 0) by Cody-Waite reduction and a degree-10 polynomial.
+Here its constants are read from the kernel source, compared with what the coefficient
+generator derives, and the same operation sequence is replayed in numpy (each fused
+multiply-add formed in extended precision and rounded once to double) against numpy's exp.
+The square root (hardware reciprocal-square-root seed, one Goldschmidt step, two Newton
+corrections) is replayed the same way from seeds carrying a relative error up to 2^-20.
+"""
+import importlib.util
+import io
+import pathlib
+import re
+from contextlib import redirect_stdout
+
+import numpy as np
+
+CSRC = pathlib.Path(__file__).resolve().parents[1] / "paper_2402_09531_amd" / "csrc"
+
+
+def device_constants():
+    src = (CSRC / "kernels.hip").read_text()
+    body = src[src.index("double exp_nonpos(double x)"):]
+    body = body[:body.index("return ldexp")]
+    log2e = float(re.search(r"rint\(x \* ([0-9.e+-]+)\)", body).group(1))
+    ln2 = [float(v) for v in re.findall(r"fma\(-n, ([0-9.e+-]+), ", body)]
+    top = float(re.search(r"double p = ([0-9.e+-]+);", body).group(1))
+    rest = [float(v) for v in re.findall(r"fma\(p, r, ([0-9.e+-]+)\)", body)]
+    return log2e, ln2, [top] + rest   # polynomial coefficients, highest degree first
+
+
+def fma(a, b, c):
+    L = np.longdouble
+    return (L(a) * L(b) + L(c)).astype(np.float64)
+
+
+def exp_device(x, log2e, ln2, coef):
+    x = np.maximum(x, -745.0)
+    n = np.rint(x * log2e)
+    r = fma(-n, ln2[0], x)
+    r = fma(-n, ln2[1], r)
+    p = np.full_like(x, coef[0])
+    for c in coef[1:]:
+        p = fma(p, r, c)
+    return np.ldexp(p, n.astype(np.int64))
+
+
+def test_constants_match_generator():
+    spec = importlib.util.spec_from_file_location("gen_exp_coeffs", CSRC / "gen_exp_coeffs.py")
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    buf = io.StringIO()
+    with redirect_stdout(buf):
+        mod.main()
+    out = buf.getvalue()
+    gen = [float(v) for v in re.findall(r"c\d+ = np\.float64\(([0-9.e+-]+)\)", out)]
+    log2e, ln2, coef = device_constants()
+    assert len(coef) == len(gen) == 11                     # degree 10
+    assert coef[::-1] == gen                               # printed to full double precision
+    assert ln2[0] + ln2[1] == np.log(2.0) and ln2[0] == np.float64(np.log(np.longdouble(2)))
+    assert log2e == 1.0 / np.log(2.0) or abs(log2e * np.log(2.0) - 1) < 2e-16
+
+
+def test_relative_error_few_ulp():
+    log2e, ln2, coef = device_constants()
+    rng = np.random.default_rng(0)
+    x = np.concatenate([-rng.random(200_000) * 2.0, -rng.random(200_000) * 50.0,
+                        -rng.random(100_000) * 700.0, -np.linspace(0.0, 1e-3, 10_001)])
+    got = exp_device(x, log2e, ln2, coef)
+    ref = np.exp(x.astype(np.longdouble))
+    rel = np.abs((got - ref) / ref).astype(np.float64)
+    assert rel.max() <= 5e-16, rel.max()          # a few units in the last place
+    assert exp_device(np.array([0.0]), log2e, ln2, coef)[0] == 1.0
+
+
+def test_underflow_and_clamp():
+    log2e, ln2, coef = device_constants()
+    x = np.array([-745.0, -800.0, -1e6])
+    got = exp_device(x, log2e, ln2, coef)
+    assert np.all(got >= 0.0) and np.all(got <= 5e-324)
+
+
+def sqrt_device(x, seed):
+    g = x * seed
+    h = 0.5 * seed
+    e = fma(-h, g, 0.5)
+    g = fma(g, e, g)
+    h = fma(h, e, h)
+    d = fma(-g, g, x)
+    g = fma(d, h, g)
+    d = fma(-g, g, x)
+    return fma(d, h, g)
+
+
+def test_sqrt_iteration_few_ulp():
+    src = (CSRC / "kernels.hip").read_text()
+    body = src[src.index("double sqrt_pos(double x)"):]
+    body = body[:body.index("}")]
+    # the sequence replayed here is the one in the source
+    for frag in ("__builtin_amdgcn_rsq(x)", "g = x * y, h = 0.5 * y", "fma(-h, g, 0.5)", "g = fma(g, e, g)",
+                 "h = fma(h, e, h)", "fma(-g, g, x)", "fma(dd, h, g)"):
+        assert frag in body, frag
+    rng = np.random.default_rng(1)
+    x = np.concatenate([10.0 ** rng.uniform(-300, 300, 200_000), rng.random(200_000) * 50.0, [1e-300, 1.0, 4.0]])
+    seed = (1.0 / np.sqrt(x.astype(np.longdouble))).astype(np.float64)
+    seed *= 1.0 + rng.uniform(-2.0 ** -20, 2.0 ** -20, x.size)
+    got = sqrt_device(x, seed)
+    ref = np.sqrt(x.astype(np.longdouble))
+    rel = np.abs((got - ref) / ref).astype(np.float64)
+    assert rel.max() <= 3e-16, rel.max()
