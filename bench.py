@@ -400,6 +400,15 @@ def main():
         "stage_ms": {"p2p": round(p2p_avg, 4), "m2l": round(m2l_avg, 4),
                      "rest": round(ms_per_step - p2p_avg - m2l_avg, 4)},
     }
+    if args.precision != "fp64":
+        # accuracy of the timed reduced-precision result against the FP64 path of the same operator
+        # (the FP64 path matches the oracle to 1e-12 relative)
+        y64 = torch.empty_like(xd)
+        dw.fmm_matvec(op, xd, y64, precision="fp64")
+        torch.cuda.synchronize()
+        err = float(torch.linalg.norm(yd - y64) / torch.linalg.norm(y64))
+        result["rel_err_vs_fp64"] = err
+        log(f"[bench] {args.precision} result: relative error {err:.3e} against the FP64 matvec")
     traffic = recorded_traffic(w.name, n, nrhs, args.precision)
     if traffic is not None:
         result["roofline"]["traffic"] = traffic
