@@ -144,18 +144,27 @@ def bench_batch(args):
     rng = np.random.default_rng(1)
     xs = [torch.from_numpy(rng.standard_normal((p[0], 1))).to(dev) for p in probs]
     ys = [torch.empty_like(x) for x in xs]
+    def timed(batch):
+        for _ in range(args.warmup):
+            dw.batch_matvec(batch, xs, ys)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            dw.batch_matvec(batch, xs, ys)
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / args.steps
+
+    # the default M2L tile shape (4 waves per cluster), then the tuned shapes
+    untuned = dw.batch_create(ops, graph=True)
+    t_untuned = timed(untuned)
+    untuned.close()
     t0 = time.perf_counter()
-    batch = dw.batch_create(ops, graph=True)
+    batch = dw.batch_create(ops, graph=True, tune=not args.no_tune)
     t_batch = time.perf_counter() - t0
-    log(f"[batch] setup {t_setup:.1f} s, batch plan + graph {t_batch:.2f} s")
-    for _ in range(args.warmup):
-        dw.batch_matvec(batch, xs, ys)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        dw.batch_matvec(batch, xs, ys)
-    torch.cuda.synchronize()
-    t_b = (time.perf_counter() - t0) / args.steps
+    wpc, m2l_ms = batch.m2l_shapes()
+    log(f"[batch] setup {t_setup:.1f} s, batch plan + tuning + graph {t_batch:.2f} s; M2L waves per cluster {wpc}")
+    t_b = timed(batch)
+    log(f"[batch] {1e3 * t_b:.2f} ms per batched matvec (default M2L shape {1e3 * t_untuned:.2f} ms)")
     ys1 = [torch.empty_like(x) for x in xs]
     for op, x, y in zip(ops, xs, ys1):
         dw.fmm_matvec(op, x, y)
@@ -175,7 +184,10 @@ def bench_batch(args):
                       "total_points": total},
            "aggregate_mpoints_per_s": round(total / t_b / 1e6, 2),
            "one_at_a_time_ms": round(1e3 * t_s, 3), "speedup_vs_one_at_a_time": round(t_s / t_b, 3),
-           "bitwise_equal_to_one_at_a_time": bool(same), "setup_s": round(t_setup, 2)}
+           "bitwise_equal_to_one_at_a_time": bool(same), "setup_s": round(t_setup, 2),
+           "m2l_tuning": {"tuned": not args.no_tune, "waves_per_cluster": wpc,
+                          "tuned_ms_4_2_1_waves": np.round(m2l_ms, 4).tolist(),
+                          "default_shape_ms_per_step": round(1e3 * t_untuned, 3)}}
     print(json.dumps(out), flush=True)
 
 
@@ -280,6 +292,7 @@ def main():
     ap.add_argument("--cpu-leaves", type=int, default=1 << 30, help="oracle sample size in target leaves")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=0, help="batch mode: number of independent problems")
+    ap.add_argument("--no-tune", action="store_true", help="batch: keep the default M2L tile shape")
     ap.add_argument("--serve", type=int, default=0, help="serving mode: number of solve requests")
     ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
     ap.add_argument("--max-iter", type=int, default=20, help="serving: CG iterations per request")

@@ -146,10 +146,27 @@ dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double *f, double
  *   ops    host array of count operators (count >= 1)
  *   flags  DWFMM_BATCH_GRAPH: capture the batched launches as one HIP graph at
  *          creation and replay it on every call
- * Synchronises `stream`.  Errors: E_INVALID, E_NOMEM, E_HIP.                    */
+ *          DWFMM_BATCH_TUNE: before any capture, time every compiled tile shape of
+ *          each M2L launch (waves per target cluster: 4, 2, or 1 when n_x <= 32;
+ *          4 / waves clusters per 256-thread workgroup) on this batch and keep the
+ *          fastest.  All shapes split a cluster's farfield list into the same four
+ *          classes and add the class sums in the same order, so the choice never
+ *          changes a result bit.  Tuning runs M2L on the operators' current moments
+ *          (its output is overwritten by the next matvec).
+ *          DWFMM_BATCH_M2L_WAVES(w), w in {1, 2, 4}: use w waves per cluster in every
+ *          M2L launch where that shape is compiled (else 4); ignored with TUNE.
+ *          Default: 4 waves per cluster.
+ * Synchronises `stream`.  Errors: E_INVALID (also unknown flag bits), E_NOMEM, E_HIP. */
 typedef struct dwfmm_batch_s *dwfmm_batch;
 #define DWFMM_BATCH_GRAPH 1
+#define DWFMM_BATCH_TUNE 2
+#define DWFMM_BATCH_M2L_WAVES(w) ((w) << 4)
 dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, int32_t flags, void *stream, dwfmm_batch *out);
+/* The batch's M2L launches: *count = their number; for i < min(count, cap), wpc[i] = the
+ * waves per cluster launch i uses and, if ms is not NULL, ms[3 i + j] = its tuned time in
+ * milliseconds with 4, 2 and 1 waves (j = 0, 1, 2; -1 where not timed).  Host arrays.
+ * Errors: E_INVALID. */
+dwfmm_status dwfmm_batch_m2l_shapes(dwfmm_batch batch, int32_t *wpc, double *ms, int32_t cap, int32_t *count);
 /* y_i = K~_i x_i for every problem i.  xs, ys: host arrays of count device pointers
  * (N_i x 1 each, caller order, x_i != y_i).  Asynchronous on `stream`; allocates nothing. */
 dwfmm_status dwfmm_batch_matvec(dwfmm_batch batch, const double *const *xs, double *const *ys, void *stream);

@@ -59,7 +59,7 @@ EXPORTS = ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fm
            "dwfmm_fmm_solve", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
            "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info",
            "dwfmm_op_basis", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
-           "dwfmm_batch_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
+           "dwfmm_batch_m2l_shapes", "dwfmm_batch_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
            "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy"]
 
 
@@ -96,6 +96,9 @@ def lib():
         L.dwfmm_batch_create.restype = C.c_int
         L.dwfmm_batch_matvec.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), vp]
         L.dwfmm_batch_matvec.restype = C.c_int
+        L.dwfmm_batch_m2l_shapes.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
+                                             C.POINTER(C.c_int32)]
+        L.dwfmm_batch_m2l_shapes.restype = C.c_int
         L.dwfmm_batch_destroy.argtypes = [vp]
         L.dwfmm_batch_destroy.restype = None
         L.dwfmm_server_create.argtypes = [C.c_size_t, C.c_int32, C.c_int32, vp, C.POINTER(vp)]
@@ -277,6 +280,11 @@ def fmm_solve(op: Op, lam: float, f, alpha, rtol: float, max_iter: int = 10000, 
 
 
 BATCH_GRAPH = 1
+BATCH_TUNE = 2
+
+
+def BATCH_M2L_WAVES(w: int) -> int:
+    return w << 4
 
 
 class Batch:
@@ -285,6 +293,16 @@ class Batch:
     def __init__(self, handle, ops):
         self._h = handle
         self.ops = list(ops)   # keeps the operators alive
+
+    def m2l_shapes(self):
+        """(waves per cluster of each M2L launch, tuned ms [launch][4, 2, 1 waves] or -1)."""
+        cnt = C.c_int32()
+        _check(lib().dwfmm_batch_m2l_shapes(self._h, None, None, 0, C.byref(cnt)))
+        n = cnt.value
+        wpc = (C.c_int32 * max(n, 1))()
+        ms = (C.c_double * max(3 * n, 1))()
+        _check(lib().dwfmm_batch_m2l_shapes(self._h, wpc, ms, n, C.byref(cnt)))
+        return [wpc[i] for i in range(n)], np.array([ms[i] for i in range(3 * n)]).reshape(n, 3)
 
     def close(self):
         if self._h:
@@ -298,11 +316,14 @@ class Batch:
             pass
 
 
-def batch_create(ops, graph: bool = False, stream=None) -> Batch:
-    """dwfmm_batch_create over a list of Op."""
+def batch_create(ops, graph: bool = False, tune: bool = False, m2l_waves: int | None = None,
+                 stream=None) -> Batch:
+    """dwfmm_batch_create over a list of Op (graph capture, M2L shape tuning or a forced shape)."""
     arr = (C.c_void_p * len(ops))(*[o._h for o in ops])
     h = C.c_void_p()
-    _check(lib().dwfmm_batch_create(arr, len(ops), BATCH_GRAPH if graph else 0, _stream(stream), C.byref(h)))
+    flags = (BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0) | \
+        (BATCH_M2L_WAVES(m2l_waves) if m2l_waves else 0)
+    _check(lib().dwfmm_batch_create(arr, len(ops), flags, _stream(stream), C.byref(h)))
     return Batch(h, ops)
 
 

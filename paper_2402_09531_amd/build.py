@@ -10,7 +10,12 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdwfmm.so")
 OBJDIR = os.path.join(HERE, "..", "_build")
-SOURCES = ["kernels.hip", "api.hip", "setup.cpp"]
+# (source, object, extra flags): kernels.hip is compiled in two parts (single-problem and
+# batched entry points) so the two halves of its template instantiations build in parallel
+UNITS = [("kernels.hip", "kernels_single.o", ["-DDWFMM_KERNELS_PART=1"]),
+         ("kernels.hip", "kernels_batch.o", ["-DDWFMM_KERNELS_PART=2"]),
+         ("api.hip", "api.o", []),
+         ("setup.cpp", "setup.o", [])]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [
@@ -28,9 +33,9 @@ def build(verbose: bool = True) -> str:
     os.makedirs(OBJDIR, exist_ok=True)
     inc = ["-I", os.path.join(HERE, "..", "include")]
     procs, objs = [], []
-    for s in SOURCES:
-        obj = os.path.join(OBJDIR, os.path.splitext(s)[0] + ".o")
-        cmd = [HIPCC, *FLAGS, *inc, "-c", os.path.join(CSRC, s), "-o", obj]
+    for src, o, extra in UNITS:
+        obj = os.path.join(OBJDIR, o)
+        cmd = [HIPCC, *FLAGS, *extra, *inc, "-c", os.path.join(CSRC, src), "-o", obj]
         if verbose:
             print(" ".join(cmd), flush=True)
         procs.append(subprocess.Popen(cmd))

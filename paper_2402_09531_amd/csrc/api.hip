@@ -765,6 +765,7 @@ struct dwfmm_batch_s {
     std::vector<double *> h_ys;
     std::vector<BatchItem> h_items;    // host sources of the set-up uploads, kept until destruction
     std::vector<int2> h_work;
+    std::vector<double> m2l_ms;        // tuned M2L times, [launch][4, 2, 1 waves], -1 = not timed
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~dwfmm_batch_s()
@@ -803,6 +804,10 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
     if (!ops || count < 1) return fail(DWFMM_E_INVALID, "ops is NULL or count < 1");
     for (int i = 0; i < count; ++i)
         if (!ops[i]) return fail(DWFMM_E_INVALID, "ops contains NULL");
+    const int forced = (flags >> 4) & 7;
+    if ((flags & ~(DWFMM_BATCH_GRAPH | DWFMM_BATCH_TUNE | DWFMM_BATCH_M2L_WAVES(7))) != 0 ||
+        (forced != 0 && forced != 1 && forced != 2 && forced != 4))
+        return fail(DWFMM_E_INVALID, "unknown batch flags");
     dwfmm_batch b = new (std::nothrow) dwfmm_batch_s();
     if (!b) return fail(DWFMM_E_NOMEM, "host allocation failed");
     b->ops.assign(ops, ops + count);
@@ -908,6 +913,45 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
     P.ys = b->d_ys;
     b->h_xs.resize(nitems);
     b->h_ys.resize(nitems);
+    b->m2l_ms.assign(3 * P.m2l.size(), -1.0);
+    for (auto &L : P.m2l)
+        if (forced && m2l_wpc_available(L.nxt, forced)) L.wpc = forced;
+    if ((flags & DWFMM_BATCH_TUNE) && !P.m2l.empty()) {
+        // time each compiled shape of every M2L launch on this batch (one warm-up, three timed)
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        const int shapes[3] = {4, 2, 1};
+        for (size_t i = 0; i < P.m2l.size() && e == hipSuccess; ++i) {
+            BatchLaunch &L = P.m2l[i];
+            float best = 0.0f;
+            for (int j = 0; j < 3 && e == hipSuccess; ++j) {
+                if (!m2l_wpc_available(L.nxt, shapes[j])) continue;
+                BatchLaunch c = L;
+                c.wpc = shapes[j];
+                float ms = 0.0f;
+                if ((e = launch_batch_m2l(P, c, st)) != hipSuccess || (e = hipEventRecord(e0, st)) != hipSuccess) break;
+                for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch_batch_m2l(P, c, st);
+                if (e == hipSuccess) e = hipEventRecord(e1, st);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) break;
+                b->m2l_ms[3 * i + j] = ms / 3.0;
+                if (j == 0 || ms < best) {
+                    best = ms;
+                    L.wpc = shapes[j];
+                }
+            }
+        }
+        if (e0) (void)hipEventDestroy(e0);
+        if (e1) (void)hipEventDestroy(e1);
+        if (e != hipSuccess) {
+            dwfmm_status s = fail(DWFMM_E_HIP, std::string("batch tuning: ") + hipGetErrorString(e));
+            b->arena.release();
+            delete b;
+            return s;
+        }
+    }
     if ((flags & DWFMM_BATCH_GRAPH) && !b->items.empty()) {
         // capture the batched matvec once; each call refreshes the x/y pointer arrays, then replays it
         hipStream_t cs;
@@ -929,6 +973,19 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
         }
     }
     *out = b;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_batch_m2l_shapes(dwfmm_batch b, int32_t *wpc, double *ms, int32_t cap, int32_t *count)
+{
+    if (!b || !count || cap < 0 || (cap > 0 && !wpc)) return fail(DWFMM_E_INVALID, "bad argument");
+    const auto &m2l = b->plan.m2l;
+    *count = (int32_t)m2l.size();
+    for (int i = 0; i < std::min<int>(cap, (int)m2l.size()); ++i) {
+        wpc[i] = m2l[i].wpc;
+        if (ms)
+            for (int j = 0; j < 3; ++j) ms[3 * i + j] = b->m2l_ms[3 * i + j];
+    }
     return DWFMM_OK;
 }
 

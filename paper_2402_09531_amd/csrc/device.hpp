@@ -68,9 +68,11 @@ struct BatchItem {
     int precision;  // 0 FP64, 1/2 FP32 nearfield and coupling
 };
 
-// One launch of a templated kernel over a slice of the work list.
+// One launch of a templated kernel over a slice of the work list.  wpc (M2L only): waves per
+// target cluster, 4, 2 or 1; every choice gives bitwise the same locals.
 struct BatchLaunch {
     int kind, dk, nxt, prec, off, cnt;
+    int wpc = 4;
 };
 
 // Work list entries are (item, local block); entries with item < 0 are padding.
@@ -85,6 +87,11 @@ struct BatchPlan {
 };
 
 hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t stream);
+// Waves per cluster compiled for an M2L launch with nxt node tiles: 1 only up to two tiles
+// (its per-lane accumulators grow with 4 / wpc x nxt).
+inline bool m2l_wpc_available(int nxt, int wpc) { return wpc == 4 || wpc == 2 || (wpc == 1 && nxt <= 2); }
+// One M2L launch of the plan on its own (the tile-shape tuner times these).
+hipError_t launch_batch_m2l(const BatchPlan &P, const BatchLaunch &L, hipStream_t stream);
 
 // ---- CG building blocks (FP64, deterministic fixed-order reductions) ----
 // partial[b][c] for b < kDotBlocks; out[c] = sum_b partial[b][c] in order.

@@ -272,73 +272,88 @@ __global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first,
 // l_c[a] = sum over farfield sources s of sum_b K(t_a, s_b) m_s[b]: the node-pair
 // distances take their cross term from FP64 MFMA 16x16x4 tiles (NXT x NXT tiles
 // per block pair), the kernel values and the product with the moments run on the
-// vector ALU.  The four waves split the source list; their partial sums are added
-// in a fixed order.
-template <int KIND, int DK, int NXT>
-__device__ __forceinline__ void m2l_mfma_body(const DevTree &T, const DevOp &O, int c, double *part)
+// vector ALU.  The farfield list of a cluster is split into four classes
+// f = Fptr[c] + k (mod 4); each class is summed in list order in its own
+// accumulators and the four class sums are added in a fixed order.  WPC waves carry
+// one cluster (4 / WPC classes each, 4 / WPC clusters per 256-thread workgroup); the
+// result is bitwise the same for every WPC.  part: this cluster's [4][NXP] slice of LDS;
+// every wave reaches the barrier (an idle slot passes valid = false).
+template <int KIND, int DK, int NXT, int WPC>
+__device__ __forceinline__ void m2l_mfma_body(const DevTree &T, const DevOp &O, int c, bool valid, double *part)
 {
-    constexpr int NKC = DK / 4, NXP = 16 * NXT;
+    constexpr int NKC = DK / 4, NXP = 16 * NXT, RPW = 4 / WPC;
     const int nx = O.nx;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wi = (tid >> 6) % WPC, lt = tid % (64 * WPC);
     const int li = lane & 15, lg = lane >> 4;
-    const int f0 = T.Fptr[c], f1 = T.Fptr[c + 1];
+    const int f0 = valid ? T.Fptr[c] : 0, f1 = valid ? T.Fptr[c + 1] : 0;
     const double inv_ell = 1.0 / O.ell;
-    const double *tnode = O.nodesT + (size_t)c * DK * NXP;
-    double A[NXT][NKC], tn[NXT][4], racc[NXT][4];
+    const double *tnode = O.nodesT + (size_t)(valid ? c : 0) * DK * NXP;
+    double A[NXT][NKC], tn[NXT][4], racc[RPW][NXT][4];
 #pragma unroll
     for (int rt = 0; rt < NXT; ++rt) {
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) A[rt][kc] = tnode[(4 * kc + lg) * NXP + 16 * rt + li];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            tn[rt][v] = O.nnorm[(size_t)c * NXP + 16 * rt + 4 * v + lg];
-            racc[rt][v] = 0.0;
-        }
+        for (int v = 0; v < 4; ++v) tn[rt][v] = O.nnorm[(size_t)(valid ? c : 0) * NXP + 16 * rt + 4 * v + lg];
     }
-    for (int f = f0 + w; f < f1; f += 4) {
-        const int s = T.Fsrc[f];
-        const double *snode = O.nodesT + (size_t)s * DK * NXP;
 #pragma unroll
-        for (int ct = 0; ct < NXT; ++ct) {
-            const int b = 16 * ct + li;
-            double B[NKC];
+    for (int k = 0; k < RPW; ++k)
 #pragma unroll
-            for (int kc = 0; kc < NKC; ++kc) B[kc] = snode[(4 * kc + lg) * NXP + b];
-            const double nb = O.nnorm[(size_t)s * NXP + b];
-            const double mb = b < nx ? O.M[(size_t)s * nx + b] : 0.0;
+        for (int rt = 0; rt < NXT; ++rt)
 #pragma unroll
-            for (int rt = 0; rt < NXT; ++rt) {
-                dbl4 G = {0.0, 0.0, 0.0, 0.0};
+            for (int v = 0; v < 4; ++v) racc[k][rt][v] = 0.0;
+    for (int base = f0 + wi; base < f1; base += 4) {
 #pragma unroll
-                for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[rt][kc], B[kc], G, 0, 0, 0);
+        for (int k = 0; k < RPW; ++k) {
+            const int f = base + k * WPC;  // class wi + k WPC
+            if (f >= f1) break;            // uniform over the wave
+            const int s = T.Fsrc[f];
+            const double *snode = O.nodesT + (size_t)s * DK * NXP;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const double r2 = fmax(fma(-2.0, G[v], tn[rt][v] + nb), 0.0);
-                    racc[rt][v] = fma(kernel_fast<KIND>(r2, inv_ell), mb, racc[rt][v]);
+            for (int ct = 0; ct < NXT; ++ct) {
+                const int b = 16 * ct + li;
+                double B[NKC];
+#pragma unroll
+                for (int kc = 0; kc < NKC; ++kc) B[kc] = snode[(4 * kc + lg) * NXP + b];
+                const double nb = O.nnorm[(size_t)s * NXP + b];
+                const double mb = b < nx ? O.M[(size_t)s * nx + b] : 0.0;
+#pragma unroll
+                for (int rt = 0; rt < NXT; ++rt) {
+                    dbl4 G = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+                    for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[rt][kc], B[kc], G, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const double r2 = fmax(fma(-2.0, G[v], tn[rt][v] + nb), 0.0);
+                        racc[k][rt][v] = fma(kernel_fast<KIND>(r2, inv_ell), mb, racc[k][rt][v]);
+                    }
                 }
             }
         }
     }
 #pragma unroll
-    for (int rt = 0; rt < NXT; ++rt)
+    for (int k = 0; k < RPW; ++k)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            double s = racc[rt][v];
-            s += __shfl_xor(s, 1, 64);
-            s += __shfl_xor(s, 2, 64);
-            s += __shfl_xor(s, 4, 64);
-            s += __shfl_xor(s, 8, 64);
-            if (li == 0) part[w * NXP + 16 * rt + 4 * v + lg] = s;
-        }
+        for (int rt = 0; rt < NXT; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                double s = racc[k][rt][v];
+                s += __shfl_xor(s, 1, 64);
+                s += __shfl_xor(s, 2, 64);
+                s += __shfl_xor(s, 4, 64);
+                s += __shfl_xor(s, 8, 64);
+                if (li == 0) part[(wi + k * WPC) * NXP + 16 * rt + 4 * v + lg] = s;
+            }
     __syncthreads();
-    if (tid < nx) O.L[(size_t)c * nx + tid] = ((part[tid] + part[NXP + tid]) + part[2 * NXP + tid]) + part[3 * NXP + tid];
+    if (valid && lt < nx)
+        O.L[(size_t)c * nx + lt] = ((part[lt] + part[NXP + lt]) + part[2 * NXP + lt]) + part[3 * NXP + lt];
 }
 
 template <int KIND, int DK, int NXT>
 __global__ __launch_bounds__(256) void m2l_mfma_kernel(DevTree T, DevOp O, int first)
 {
     __shared__ double part[4 * 16 * NXT];
-    m2l_mfma_body<KIND, DK, NXT>(T, O, first + blockIdx.x, part);
+    m2l_mfma_body<KIND, DK, NXT, 4>(T, O, first + blockIdx.x, true, part);
 }
 
 template <int KIND, int DK>
@@ -1392,72 +1407,83 @@ void launch_m2l_mrhs_k(const DevTree &T, const DevOp &O, int first, int cnt, int
 }
 
 // M2L for one rhs in FP32: FP32 Gram tiles of the node pairs, FP32 kernel values and sums.
-template <int KIND, int DK, int NXT>
-__device__ __forceinline__ void m2l_mfma32_body(const DevTree &T, const DevOp &O, int c, float *part)
+// Same list classes, WPC layout and fixed-order class sum as the FP64 version.
+template <int KIND, int DK, int NXT, int WPC>
+__device__ __forceinline__ void m2l_mfma32_body(const DevTree &T, const DevOp &O, int c, bool valid, float *part)
 {
-    constexpr int NKC = DK / 4, NXP = 16 * NXT;
+    constexpr int NKC = DK / 4, NXP = 16 * NXT, RPW = 4 / WPC;
     const int nx = O.nx;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, wi = (tid >> 6) % WPC, lt = tid % (64 * WPC);
     const int li = lane & 15, lg = lane >> 4;
-    const int f0 = T.Fptr[c], f1 = T.Fptr[c + 1];
+    const int f0 = valid ? T.Fptr[c] : 0, f1 = valid ? T.Fptr[c + 1] : 0;
     const float inv_ell = (float)(1.0 / O.ell);
-    const double *tnode = O.nodesT + (size_t)c * DK * NXP;
-    float A[NXT][NKC], tn[NXT][4], racc[NXT][4];
+    const double *tnode = O.nodesT + (size_t)(valid ? c : 0) * DK * NXP;
+    float A[NXT][NKC], tn[NXT][4], racc[RPW][NXT][4];
 #pragma unroll
     for (int rt = 0; rt < NXT; ++rt) {
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) A[rt][kc] = (float)tnode[(4 * kc + lg) * NXP + 16 * rt + li];
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            tn[rt][v] = (float)O.nnorm[(size_t)c * NXP + 16 * rt + 4 * lg + v];
-            racc[rt][v] = 0.0f;
-        }
+        for (int v = 0; v < 4; ++v) tn[rt][v] = (float)O.nnorm[(size_t)(valid ? c : 0) * NXP + 16 * rt + 4 * lg + v];
     }
-    for (int f = f0 + w; f < f1; f += 4) {
-        const int s = T.Fsrc[f];
-        const double *snode = O.nodesT + (size_t)s * DK * NXP;
 #pragma unroll
-        for (int ct = 0; ct < NXT; ++ct) {
-            const int b = 16 * ct + li;
-            float B[NKC];
+    for (int k = 0; k < RPW; ++k)
 #pragma unroll
-            for (int kc = 0; kc < NKC; ++kc) B[kc] = (float)snode[(4 * kc + lg) * NXP + b];
-            const float nb = (float)O.nnorm[(size_t)s * NXP + b];
-            const float mb = b < nx ? (float)O.M[(size_t)s * nx + b] : 0.0f;
+        for (int rt = 0; rt < NXT; ++rt)
 #pragma unroll
-            for (int rt = 0; rt < NXT; ++rt) {
-                flt4 G = {0.0f, 0.0f, 0.0f, 0.0f};
+            for (int v = 0; v < 4; ++v) racc[k][rt][v] = 0.0f;
+    for (int base = f0 + wi; base < f1; base += 4) {
 #pragma unroll
-                for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(A[rt][kc], B[kc], G, 0, 0, 0);
+        for (int k = 0; k < RPW; ++k) {
+            const int f = base + k * WPC;
+            if (f >= f1) break;
+            const int s = T.Fsrc[f];
+            const double *snode = O.nodesT + (size_t)s * DK * NXP;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) {
-                    const float r2 = fmaxf(fmaf(-2.0f, G[v], tn[rt][v] + nb), 0.0f);
-                    racc[rt][v] = fmaf(kernel_f32<KIND>(r2, inv_ell), mb, racc[rt][v]);
+            for (int ct = 0; ct < NXT; ++ct) {
+                const int b = 16 * ct + li;
+                float B[NKC];
+#pragma unroll
+                for (int kc = 0; kc < NKC; ++kc) B[kc] = (float)snode[(4 * kc + lg) * NXP + b];
+                const float nb = (float)O.nnorm[(size_t)s * NXP + b];
+                const float mb = b < nx ? (float)O.M[(size_t)s * nx + b] : 0.0f;
+#pragma unroll
+                for (int rt = 0; rt < NXT; ++rt) {
+                    flt4 G = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+                    for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(A[rt][kc], B[kc], G, 0, 0, 0);
+#pragma unroll
+                    for (int v = 0; v < 4; ++v) {
+                        const float r2 = fmaxf(fmaf(-2.0f, G[v], tn[rt][v] + nb), 0.0f);
+                        racc[k][rt][v] = fmaf(kernel_f32<KIND>(r2, inv_ell), mb, racc[k][rt][v]);
+                    }
                 }
             }
         }
     }
 #pragma unroll
-    for (int rt = 0; rt < NXT; ++rt)
+    for (int k = 0; k < RPW; ++k)
 #pragma unroll
-        for (int v = 0; v < 4; ++v) {
-            float s = racc[rt][v];
-            s += __shfl_xor(s, 1, 64);
-            s += __shfl_xor(s, 2, 64);
-            s += __shfl_xor(s, 4, 64);
-            s += __shfl_xor(s, 8, 64);
-            if (li == 0) part[w * NXP + 16 * rt + 4 * lg + v] = s;
-        }
+        for (int rt = 0; rt < NXT; ++rt)
+#pragma unroll
+            for (int v = 0; v < 4; ++v) {
+                float s = racc[k][rt][v];
+                s += __shfl_xor(s, 1, 64);
+                s += __shfl_xor(s, 2, 64);
+                s += __shfl_xor(s, 4, 64);
+                s += __shfl_xor(s, 8, 64);
+                if (li == 0) part[(wi + k * WPC) * NXP + 16 * rt + 4 * lg + v] = s;
+            }
     __syncthreads();
-    if (tid < nx)
-        O.L[(size_t)c * nx + tid] = (double)(((part[tid] + part[NXP + tid]) + part[2 * NXP + tid]) + part[3 * NXP + tid]);
+    if (valid && lt < nx)
+        O.L[(size_t)c * nx + lt] = (double)(((part[lt] + part[NXP + lt]) + part[2 * NXP + lt]) + part[3 * NXP + lt]);
 }
 
 template <int KIND, int DK, int NXT>
 __global__ __launch_bounds__(256) void m2l_mfma32_kernel(DevTree T, DevOp O, int first)
 {
     __shared__ float part[4 * 16 * NXT];
-    m2l_mfma32_body<KIND, DK, NXT>(T, O, first + blockIdx.x, part);
+    m2l_mfma32_body<KIND, DK, NXT, 4>(T, O, first + blockIdx.x, true, part);
 }
 
 template <int KIND, int DK>
@@ -1513,22 +1539,30 @@ __global__ __launch_bounds__(64) void l2l_batch_kernel(const BatchItem *items, c
     l2l_body(items[wk.x].T, items[wk.x].O, wk.y, 1);
 }
 
-template <int KIND, int DK, int NXT>
-__global__ __launch_bounds__(256) void m2l_batch_kernel(const BatchItem *items, const int2 *work)
+// 4 / WPC clusters of the work list per workgroup; slots past the end or on padding idle
+// through the barrier.
+template <int KIND, int DK, int NXT, int WPC>
+__global__ __launch_bounds__(256) void m2l_batch_kernel(const BatchItem *items, const int2 *work, int cnt)
 {
-    __shared__ double part[4 * 16 * NXT];
-    const int2 wk = work[blockIdx.x];
-    if (wk.x < 0) return;
-    m2l_mfma_body<KIND, DK, NXT>(items[wk.x].T, items[wk.x].O, wk.y, part);
+    constexpr int CPB = 4 / WPC;
+    __shared__ double part[CPB][4 * 16 * NXT];
+    const int slot = (threadIdx.x >> 6) / WPC, q = blockIdx.x * CPB + slot;
+    const int2 wk = q < cnt ? work[q] : make_int2(-1, 0);
+    const bool valid = wk.x >= 0;
+    const BatchItem &I = items[valid ? wk.x : 0];
+    m2l_mfma_body<KIND, DK, NXT, WPC>(I.T, I.O, wk.y, valid, part[slot]);
 }
 
-template <int KIND, int DK, int NXT>
-__global__ __launch_bounds__(256) void m2l32_batch_kernel(const BatchItem *items, const int2 *work)
+template <int KIND, int DK, int NXT, int WPC>
+__global__ __launch_bounds__(256) void m2l32_batch_kernel(const BatchItem *items, const int2 *work, int cnt)
 {
-    __shared__ float part[4 * 16 * NXT];
-    const int2 wk = work[blockIdx.x];
-    if (wk.x < 0) return;
-    m2l_mfma32_body<KIND, DK, NXT>(items[wk.x].T, items[wk.x].O, wk.y, part);
+    constexpr int CPB = 4 / WPC;
+    __shared__ float part[CPB][4 * 16 * NXT];
+    const int slot = (threadIdx.x >> 6) / WPC, q = blockIdx.x * CPB + slot;
+    const int2 wk = q < cnt ? work[q] : make_int2(-1, 0);
+    const bool valid = wk.x >= 0;
+    const BatchItem &I = items[valid ? wk.x : 0];
+    m2l_mfma32_body<KIND, DK, NXT, WPC>(I.T, I.O, wk.y, valid, part[slot]);
 }
 
 template <int KIND, int DK, bool FP32>
@@ -1550,23 +1584,44 @@ __global__ __launch_bounds__(kSymLeaf) void combine_batch_kernel(const BatchItem
     combine_body(items[wk.x].T, items[wk.x].O, wk.y, ys[wk.x], 1, items[wk.x].far);
 }
 
+template <int KIND, int DK, int NXT>
+void launch_m2l_batch_x(const BatchPlan &P, const BatchLaunch &L, hipStream_t st)
+{
+    const int2 *w = P.work + L.off;
+#define DWFMM_MW(W)                                                                                         \
+    case W:                                                                                                 \
+        if (L.prec != 0)                                                                                    \
+            hipLaunchKernelGGL((m2l32_batch_kernel<KIND, DK, NXT, W>), dim3((L.cnt + 4 / W - 1) / (4 / W)),  \
+                               dim3(256), 0, st, P.items, w, L.cnt);                                        \
+        else                                                                                                \
+            hipLaunchKernelGGL((m2l_batch_kernel<KIND, DK, NXT, W>), dim3((L.cnt + 4 / W - 1) / (4 / W)),    \
+                               dim3(256), 0, st, P.items, w, L.cnt);                                        \
+        break;
+    if constexpr (NXT <= 2) {
+        switch (L.wpc) {
+            DWFMM_MW(1) DWFMM_MW(2)
+        default:
+            DWFMM_MW(4)
+        }
+    } else {
+        switch (L.wpc) {
+            DWFMM_MW(2)
+        default:
+            DWFMM_MW(4)
+        }
+    }
+#undef DWFMM_MW
+}
+
 template <int KIND, int DK>
 void launch_m2l_batch_d(const BatchPlan &P, const BatchLaunch &L, hipStream_t st)
 {
-    const int2 *w = P.work + L.off;
-#define DWFMM_MB(X)                                                                                        \
-    case X:                                                                                                \
-        if (L.prec != 0)                                                                                   \
-            hipLaunchKernelGGL((m2l32_batch_kernel<KIND, DK, X>), dim3(L.cnt), dim3(256), 0, st, P.items, w); \
-        else                                                                                               \
-            hipLaunchKernelGGL((m2l_batch_kernel<KIND, DK, X>), dim3(L.cnt), dim3(256), 0, st, P.items, w);   \
-        break;
     switch (L.nxt) {
-        DWFMM_MB(1) DWFMM_MB(2) DWFMM_MB(3)
-    default:
-        DWFMM_MB(4)
+    case 1: launch_m2l_batch_x<KIND, DK, 1>(P, L, st); break;
+    case 2: launch_m2l_batch_x<KIND, DK, 2>(P, L, st); break;
+    case 3: launch_m2l_batch_x<KIND, DK, 3>(P, L, st); break;
+    default: launch_m2l_batch_x<KIND, DK, 4>(P, L, st); break;
     }
-#undef DWFMM_MB
 }
 
 template <int KIND>
@@ -1627,6 +1682,10 @@ __global__ void dot_final_kernel(const double *__restrict__ partial, int nblocks
 
 }  // namespace
 
+// The library compiles this file twice, in parallel: DWFMM_KERNELS_PART 1 holds the
+// single-problem entry points, 2 the batched ones; each instantiates only the kernel
+// templates it launches.  Without the macro both parts are compiled.
+#if !defined(DWFMM_KERNELS_PART) || DWFMM_KERNELS_PART == 1
 hipError_t launch_basis(const DevTree &T, int nx, const double *clo, const double *csc, const double *coff,
                         const int32_t *lidx, int nnz_max, const double *Vinv, int nleg, const int32_t *leg_axis,
                         const int32_t *leg_deg, double *Lb, hipStream_t stream)
@@ -1747,19 +1806,26 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
     return e;
 }
 
+#endif
+
+#if !defined(DWFMM_KERNELS_PART) || DWFMM_KERNELS_PART == 2
+hipError_t launch_batch_m2l(const BatchPlan &P, const BatchLaunch &L, hipStream_t st)
+{
+    switch (L.kind) {
+    case 0: launch_m2l_batch_k<0>(P, L, st); break;
+    case 1: launch_m2l_batch_k<1>(P, L, st); break;
+    default: launch_m2l_batch_k<2>(P, L, st); break;
+    }
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t st)
 {
     if (P.leaf_cnt == 0) return hipSuccess;
     hipLaunchKernelGGL(p2m_batch_kernel, dim3(P.leaf_cnt), dim3(256), 0, st, P.items, P.xs, P.work + P.leaf_off);
     for (auto &lv : P.m2m)
         hipLaunchKernelGGL(m2m_batch_kernel, dim3(lv.second), dim3(64), 0, st, P.items, P.work + lv.first);
-    for (auto &L : P.m2l) {
-        switch (L.kind) {
-        case 0: launch_m2l_batch_k<0>(P, L, st); break;
-        case 1: launch_m2l_batch_k<1>(P, L, st); break;
-        default: launch_m2l_batch_k<2>(P, L, st); break;
-        }
-    }
+    for (auto &L : P.m2l) (void)launch_batch_m2l(P, L, st);
     for (auto &lv : P.l2l)
         hipLaunchKernelGGL(l2l_batch_kernel, dim3(lv.second), dim3(64), 0, st, P.items, P.work + lv.first);
     for (auto &L : P.p2p) {
@@ -1775,6 +1841,9 @@ hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t st)
     return hipGetLastError();
 }
 
+#endif
+
+#if !defined(DWFMM_KERNELS_PART) || DWFMM_KERNELS_PART == 1
 hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double *partial, double *out,
                       hipStream_t stream)
 {
@@ -1782,5 +1851,7 @@ hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double 
     hipLaunchKernelGGL(dot_final_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, stream, partial, kDotBlocks, nrhs, out);
     return hipGetLastError();
 }
+
+#endif
 
 }  // namespace dwfmm

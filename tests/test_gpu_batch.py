@@ -3,8 +3,9 @@
 The batched launches run the same kernel bodies in the same reduction order as the
 single-problem launches, so results must be bitwise equal (FP64 and FP32 modes), also
 when the batch is replayed from a captured HIP graph several times with other work in
-between, and for problems that fall back to single launches.  One problem per batch is
-also checked against the CPU oracle.
+between, for problems that fall back to single launches, for every M2L tile shape
+(1, 2 or 4 waves per cluster) and for the shapes the tuner picks.  One problem per
+batch is also checked against the CPU oracle.
 """
 import sys
 
@@ -46,11 +47,26 @@ def make_problems(seed=11):
     return probs
 
 
-@pytest.mark.parametrize("graph", [False, True])
-def test_batch_equals_single(orc, graph):
+@pytest.mark.parametrize("graph,shape", [(False, None), (True, None), (False, 1), (False, 2), (True, "tune")])
+def test_batch_equals_single(orc, graph, shape):
     probs = make_problems()
     ops = [p["op"] for p in probs]
-    batch = dw.batch_create(ops, graph=graph)
+    tune = shape == "tune"
+    batch = dw.batch_create(ops, graph=graph, tune=tune, m2l_waves=None if tune else shape)
+    wpc, ms = batch.m2l_shapes()
+    say(f"[batch graph={graph} shape={shape}] M2L launches {len(wpc)}: waves {wpc}")
+    assert len(wpc) >= 2
+    if tune:
+        say(f"   tuned ms [4, 2, 1 waves]: {ms.round(4).tolist()}")
+        for k, w in enumerate(wpc):
+            timed = {4: ms[k, 0], 2: ms[k, 1], 1: ms[k, 2]}
+            assert timed[4] > 0 and timed[2] > 0 and timed[w] == min(t for t in timed.values() if t > 0)
+    elif shape == 2:
+        assert all(w == 2 for w in wpc)
+    elif shape == 1:
+        assert 1 in wpc and all(w in (1, 4) for w in wpc)
+    else:
+        assert all(w == 4 for w in wpc) and np.all(ms == -1)
     rng = np.random.default_rng(5)
     for rep in range(3):
         xs = [torch.from_numpy(rng.standard_normal((p["X"].shape[0], 1))).cuda() for p in probs]
@@ -63,7 +79,7 @@ def test_batch_equals_single(orc, graph):
             dw.fmm_matvec(p["op"], x, y1)
             torch.cuda.synchronize()
             assert torch.equal(y, y1), p["spec"]
-        say(f"[batch graph={graph}] replay {rep}: {len(probs)} problems bitwise equal to single matvecs")
+        say(f"[batch graph={graph} shape={shape}] replay {rep}: {len(probs)} problems bitwise equal to single matvecs")
     # one FP64 problem of the batch against the oracle
     p = probs[0]
     n, d, r, kind, ell, q, leaf, eta, prec = p["spec"]
