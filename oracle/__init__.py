@@ -60,6 +60,17 @@ def lib():
         L.orc_create.restype = C.c_void_p
         L.orc_create.argtypes = [dp, C.c_long, C.c_int, dp, C.c_int, C.c_double, C.c_int, C.c_double,
                                  C.c_double, C.c_int, dp]
+        L.orc_create_ex.restype = C.c_void_p
+        L.orc_create_ex.argtypes = [dp, C.c_long, C.c_int, dp, C.c_int, C.c_double, C.c_int, C.c_double,
+                                    C.c_double, C.c_int, dp, C.c_int, C.c_long]
+        L.orc_radical_inverse.restype = C.c_double
+        L.orc_radical_inverse.argtypes = [C.c_long, C.c_int]
+        L.orc_halton_candidates.restype = None
+        L.orc_halton_candidates.argtypes = [C.c_int, C.POINTER(C.c_int), C.c_long, dp]
+        L.orc_afp_select.restype = C.c_int
+        L.orc_afp_select.argtypes = [C.c_int, C.c_long, up, C.c_long, dp, lp]
+        L.orc_afp_candidates.restype = C.c_long
+        L.orc_afp_candidates.argtypes = [C.c_long]
         L.orc_destroy.restype = None
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_matvec_ex.restype = None
@@ -137,17 +148,52 @@ def legendre(j: int, t: float) -> float:
     return lib().orc_legendre(int(j), float(t))
 
 
+def radical_inverse(i: int, p: int) -> float:
+    """Halton coordinate: the radical inverse of i in base p."""
+    return lib().orc_radical_inverse(int(i), int(p))
+
+
+def halton_candidates(mk, count: int) -> np.ndarray:
+    """AFP candidates (Sec 5.4): Halton points 1..count over the axes with m_k > 0, else 1/2."""
+    mk = np.ascontiguousarray(mk, dtype=np.int32)
+    Y = np.zeros((count, mk.size))
+    lib().orc_halton_candidates(mk.size, mk.ctypes.data_as(C.POINTER(C.c_int)), int(count), _dp(Y))
+    return Y
+
+
+def afp_select(alpha, Y) -> np.ndarray:
+    """Indices of the candidates Y chosen by the pivoted QR of the Vandermonde matrix (Sec 5.4)."""
+    alpha = np.ascontiguousarray(alpha, dtype=np.uint8)
+    Y = _f64(Y)
+    nx, d = alpha.shape
+    out = np.zeros(nx, dtype=np.int64)
+    rc = lib().orc_afp_select(d, nx, alpha.ctypes.data_as(C.POINTER(C.c_ubyte)), Y.shape[0], _dp(Y), _lp(out))
+    if rc != 0:
+        raise ValueError("oracle: candidates do not span the polynomial space")
+    return out
+
+
+def afp_candidates(nx: int) -> int:
+    return int(lib().orc_afp_candidates(int(nx)))
+
+
+NODES_CHEB_LEJA = 0
+NODES_AFP = 1
+
+
 class Plan:
-    """Tree, partition, index set, nodes and transfer matrices (Secs 4, 5.1, 5.2)."""
+    """Tree, partition, index set, nodes and transfer matrices (Secs 4, 5.1, 5.2, 5.4)."""
 
     def __init__(self, points, dim_weights, leaf_size: int, eta: float, kernel: str, ell: float,
-                 q: float, weight_rule: int = W_R1, weight_aux=None):
+                 q: float, weight_rule: int = W_R1, weight_aux=None, node_rule: int = NODES_CHEB_LEJA,
+                 n_candidates: int = 0):
         pts = _f64(points)
         self.n, self.d = pts.shape
         b = _f64(dim_weights)
         aux = None if weight_aux is None else _f64(weight_aux)
-        h = lib().orc_create(_dp(pts), self.n, self.d, _dp(b), int(leaf_size), float(eta),
-                             KERNELS[kernel], float(ell), float(q), int(weight_rule), _dp(aux))
+        h = lib().orc_create_ex(_dp(pts), self.n, self.d, _dp(b), int(leaf_size), float(eta),
+                                KERNELS[kernel], float(ell), float(q), int(weight_rule), _dp(aux),
+                                int(node_rule), int(n_candidates))
         if not h:
             raise ValueError("oracle: invalid arguments")
         self._h = h

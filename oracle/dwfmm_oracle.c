@@ -314,6 +314,116 @@ static int invert(int n, const double *A, double *Ainv)
 }
 
 /* ------------------------------------------------------------------ */
+/* Approximate Fekete points (Sec 5.4): a greedy column-pivoted QR of  */
+/* the Vandermonde matrix over candidate points of the Halton sequence. */
+/* ------------------------------------------------------------------ */
+
+/* Radical inverse of i in base p (the Halton coordinate), exactly: the
+ * digits of i reversed behind the radix point, formed as an integer over
+ * p^(number of digits) and divided once. */
+double orc_radical_inverse(long i, int p)
+{
+    long num = 0, den = 1;
+    while (i > 0) {
+        num = num * p + i % p;
+        den *= p;
+        i /= p;
+    }
+    return (double)num / (double)den;
+}
+
+static int nth_prime(int r)
+{
+    int count = -1;
+    for (int c = 2;; ++c) {
+        int prime = 1;
+        for (int f = 2; f * f <= c; ++f)
+            if (c % f == 0) { prime = 0; break; }
+        if (prime && ++count == r) return c;
+    }
+}
+
+/* Candidate j (j = 0..M-1) is Halton point j+1 over the axes with m_k > 0
+ * (the r-th such axis in base prime r); the other coordinates are 1/2. */
+void orc_halton_candidates(int d, const int *mk, long M, double *Y)
+{
+    for (long j = 0; j < M; ++j) {
+        int r = 0;
+        for (int k = 0; k < d; ++k)
+            Y[j * d + k] = mk[k] > 0 ? orc_radical_inverse(j + 1, nth_prime(r++)) : 0.5;
+    }
+}
+
+/* Select nx of the M candidates Y: A = [p_b(y_j)] (basis b by row, candidate
+ * j by column) is reduced by Householder reflections; step k takes the column
+ * whose remaining part (rows k..nx-1) has the largest norm, a norm within
+ * relative 1e-12 of the largest going to the lowest candidate index.  The
+ * norms are recomputed from the reduced matrix at every step.  chosen[k] is
+ * the candidate taken at step k.  Returns 0, or -1 if a step finds no column
+ * with a non-zero remaining part. */
+int orc_afp_select(int d, long nx, const unsigned char *alpha, long M, const double *Y, long *chosen)
+{
+    double *A = (double *)malloc(sizeof(double) * (size_t)nx * M);
+    long *id = (long *)malloc(sizeof(long) * (size_t)M);
+    double *v = (double *)malloc(sizeof(double) * (size_t)nx);
+    for (long j = 0; j < M; ++j) {
+        id[j] = j;
+        for (long b = 0; b < nx; ++b) A[b * M + j] = leg_tensor(d, alpha + b * d, Y + j * d);
+    }
+    int rc = 0;
+    for (long k = 0; k < nx; ++k) {
+        double best = -1.0;
+        for (long j = k; j < M; ++j) {
+            double s = 0.0;
+            for (long r = k; r < nx; ++r) s += A[r * M + j] * A[r * M + j];
+            if (s > best) best = s;
+        }
+        if (!(best > 0.0)) { rc = -1; break; }
+        long jp = -1;
+        for (long j = k; j < M; ++j) {
+            double s = 0.0;
+            for (long r = k; r < nx; ++r) s += A[r * M + j] * A[r * M + j];
+            if (s >= best * (1.0 - 1e-12) && (jp < 0 || id[j] < id[jp])) jp = j;
+        }
+        if (jp != k) {
+            for (long r = 0; r < nx; ++r) {
+                double t = A[r * M + k];
+                A[r * M + k] = A[r * M + jp];
+                A[r * M + jp] = t;
+            }
+            long t = id[k];
+            id[k] = id[jp];
+            id[jp] = t;
+        }
+        chosen[k] = id[k];
+        /* reflector H = I - 2 v v^T / (v^T v) mapping column k (rows k..) onto a multiple of e_k */
+        double nrm = 0.0;
+        for (long r = k; r < nx; ++r) nrm += A[r * M + k] * A[r * M + k];
+        nrm = sqrt(nrm);
+        double a0 = A[k * M + k];
+        double alpha_k = a0 >= 0.0 ? -nrm : nrm;
+        for (long r = k; r < nx; ++r) v[r] = A[r * M + k];
+        v[k] = a0 - alpha_k;
+        double vv = 0.0;
+        for (long r = k; r < nx; ++r) vv += v[r] * v[r];
+        if (vv == 0.0) continue;
+        for (long j = k; j < M; ++j) {
+            double dot = 0.0;
+            for (long r = k; r < nx; ++r) dot += v[r] * A[r * M + j];
+            double f = 2.0 * dot / vv;
+            for (long r = k; r < nx; ++r) A[r * M + j] -= f * v[r];
+        }
+    }
+    free(A);
+    free(id);
+    free(v);
+    return rc;
+}
+
+/* Default number of candidates for nx nodes. */
+long orc_afp_candidates(long nx) { return nx * 50 > 2000 ? nx * 50 : 2000; }
+
+/* ------------------------------------------------------------------ */
 /* The plan: tree, partition, index set, nodes, V, V^-1, T matrices.   */
 /* ------------------------------------------------------------------ */
 typedef struct {
@@ -495,8 +605,21 @@ void orc_destroy(orc_plan *P)
 }
 
 /* Build everything the matvec needs.  points: n*d row-major, original order. */
+orc_plan *orc_create_ex(const double *points, long n, int d, const double *b, int leaf, double eta,
+                        int kind, double ell, double q, int weight_rule, const double *weight_aux,
+                        int node_rule, long n_candidates);
+
 orc_plan *orc_create(const double *points, long n, int d, const double *b, int leaf, double eta,
                      int kind, double ell, double q, int weight_rule, const double *weight_aux)
+{
+    return orc_create_ex(points, n, d, b, leaf, eta, kind, ell, q, weight_rule, weight_aux, 0, 0);
+}
+
+/* node_rule 0: per-axis Chebyshev-Leja nodes; 1: approximate Fekete points from
+ * n_candidates Halton candidates (0 = the default count). */
+orc_plan *orc_create_ex(const double *points, long n, int d, const double *b, int leaf, double eta,
+                        int kind, double ell, double q, int weight_rule, const double *weight_aux,
+                        int node_rule, long n_candidates)
 {
     if (n < 1 || d < 1 || d > ORC_MAXD || leaf < 1 || !(eta > 0)) return NULL;
     orc_plan *P = (orc_plan *)calloc(1, sizeof(orc_plan));
@@ -513,12 +636,26 @@ orc_plan *orc_create(const double *points, long n, int d, const double *b, int l
         for (long a = 0; a < nx; ++a)
             if (P->alpha[a * d + k] > P->mk[k]) P->mk[k] = P->alpha[a * d + k];
     }
-    /* nodes xi_alpha = (z^(1)_{alpha_1}, ..., z^(d)_{alpha_d}) */
     P->xi = (double *)malloc(sizeof(double) * (size_t)nx * d);
-    for (int k = 0; k < d; ++k) {
-        double z[256];
-        orc_axis_nodes(P->mk[k], z);
-        for (long a = 0; a < nx; ++a) P->xi[a * d + k] = z[P->alpha[a * d + k]];
+    if (node_rule == 0) {
+        /* nodes xi_alpha = (z^(1)_{alpha_1}, ..., z^(d)_{alpha_d}) */
+        for (int k = 0; k < d; ++k) {
+            double z[256];
+            orc_axis_nodes(P->mk[k], z);
+            for (long a = 0; a < nx; ++a) P->xi[a * d + k] = z[P->alpha[a * d + k]];
+        }
+    } else {
+        long M = n_candidates > 0 ? n_candidates : orc_afp_candidates(nx);
+        if (M < nx) { orc_destroy(P); return NULL; }
+        double *Y = (double *)malloc(sizeof(double) * (size_t)M * d);
+        long *chosen = (long *)malloc(sizeof(long) * (size_t)nx);
+        orc_halton_candidates(d, P->mk, M, Y);
+        int rc = orc_afp_select(d, nx, P->alpha, M, Y, chosen);
+        if (rc == 0)
+            for (long a = 0; a < nx; ++a) memcpy(P->xi + a * d, Y + chosen[a] * d, sizeof(double) * d);
+        free(Y);
+        free(chosen);
+        if (rc != 0) { orc_destroy(P); return NULL; }
     }
     /* eq. (Vandermonde): V[alpha][alpha'] = p_alpha'(xi_alpha) */
     P->V = (double *)malloc(sizeof(double) * (size_t)nx * nx);
