@@ -65,6 +65,16 @@ typedef enum { DWFMM_W_R1 = 0, DWFMM_W_R2 = 1, DWFMM_W_R3 = 2, DWFMM_W_EXPLICIT 
  * moments, transfers, CG inner products and residuals are always FP64.   */
 typedef enum { DWFMM_FP64 = 0, DWFMM_FP32 = 1, DWFMM_BF16 = 2 } dwfmm_precision;
 
+/* Interpolation nodes on the reference box (Sec 5.4 and the per-axis reading):
+ *   CHEB_LEJA  node alpha = (z^(1)_{alpha_1}, ..., z^(d)_{alpha_d}), z^(k) the m_k+1
+ *              first-kind Chebyshev points of [0,1] in Leja order (default)
+ *   AFP        approximate Fekete points: the n_x pivots of a greedy column-pivoted
+ *              QR of the Legendre Vandermonde matrix over Halton candidates (points
+ *              1..M over the axes with m_k > 0, in consecutive prime bases; other
+ *              coordinates 1/2); a residual norm within relative 1e-12 of the
+ *              largest goes to the lowest candidate index                          */
+typedef enum { DWFMM_NODES_CHEB_LEJA = 0, DWFMM_NODES_AFP = 1 } dwfmm_node_rule;
+
 typedef struct {
     int32_t weight_rule;     /* dwfmm_weight_rule, default R1 */
     const double *omega;     /* host, length d, only for DWFMM_W_EXPLICIT */
@@ -73,6 +83,8 @@ typedef struct {
     int32_t check_every;     /* CG iterations between host convergence checks, default 1 */
     double ir_inner_rtol;    /* reduced precision: inner CG tolerance (0 = 1e-4 FP32, 1e-2 BF16) */
     int32_t ir_max_outer;    /* reduced precision: max refinement steps, default 30 */
+    int32_t node_rule;       /* dwfmm_node_rule, default CHEB_LEJA */
+    int32_t afp_candidates;  /* AFP: Halton candidates M >= n_x, 0 = max(2000, 50 n_x) */
 } dwfmm_opts;
 
 /* Per right-hand-side result of dwfmm_fmm_solve. */
@@ -103,11 +115,12 @@ dwfmm_status dwfmm_build_tree(const double *points, int64_t n, int32_t d, const 
 
 /* FMM operator for a tree (Sec 4 index set; Sec 5.2 interpolation, cluster bases,
  * transfer matrices).  q >= 0 is the weighted total degree.  opts may be NULL.
- * Builds Lambda, per-axis Leja-ordered Chebyshev nodes, V^-1, the transfer
- * matrices of every cluster and the interpolation nodes of every box, and
- * allocates the workspace for opts->max_nrhs right-hand sides.  The operator
- * keeps a reference on the tree.  Synchronises `stream`.
- * Errors: E_INVALID (bad kernel, q, opts), E_NOMEM, E_HIP.                       */
+ * Builds Lambda, the nodes (opts->node_rule), V^-1, the transfer matrices of
+ * every cluster and the interpolation nodes of every box, and allocates the
+ * workspace for opts->max_nrhs right-hand sides.  The operator keeps a reference
+ * on the tree.  Synchronises `stream`.  n_x <= 128 and n_x * d (rounded up to a
+ * multiple of 4) <= 3072; above n_x = 64 the coupling runs on the general kernel.
+ * Errors: E_INVALID (bad kernel, q, opts, index set too large), E_NOMEM, E_HIP.  */
 dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, double q, const dwfmm_opts *opts,
                               void *stream, dwfmm_op *out);
 

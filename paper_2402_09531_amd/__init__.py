@@ -42,7 +42,10 @@ class _Kernel(C.Structure):
 class _Opts(C.Structure):
     _fields_ = [("weight_rule", C.c_int32), ("omega", C.POINTER(C.c_double)), ("precision", C.c_int32),
                 ("max_nrhs", C.c_int32), ("check_every", C.c_int32), ("ir_inner_rtol", C.c_double),
-                ("ir_max_outer", C.c_int32)]
+                ("ir_max_outer", C.c_int32), ("node_rule", C.c_int32), ("afp_candidates", C.c_int32)]
+
+
+NODE_RULES = {"cheb_leja": 0, "afp": 1}
 
 
 class SolveInfo(C.Structure):
@@ -245,11 +248,11 @@ def build_tree(points, dim_weights, leaf_size: int, eta: float, stream=None) -> 
 
 def fmm_create(tree: Tree, kernel: str, ell: float, q: float, precision: str = "fp64", max_nrhs: int = 1,
                weight_rule: str = "R1", omega=None, check_every: int = 1, ir_inner_rtol: float = 0.0,
-               ir_max_outer: int = 30, stream=None) -> Op:
-    """dwfmm_fmm_create."""
+               ir_max_outer: int = 30, nodes: str = "cheb_leja", afp_candidates: int = 0, stream=None) -> Op:
+    """dwfmm_fmm_create (nodes: "cheb_leja" or "afp", the approximate Fekete points)."""
     om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
     opts = _Opts(WEIGHT_RULES[weight_rule], _f64p(om), PRECISIONS[precision], int(max_nrhs), int(check_every),
-                 float(ir_inner_rtol), int(ir_max_outer))
+                 float(ir_inner_rtol), int(ir_max_outer), NODE_RULES[nodes], int(afp_candidates))
     h = C.c_void_p()
     _check(lib().dwfmm_fmm_create(tree._h, _Kernel(KERNELS[kernel], float(ell)), float(q), C.byref(opts),
                                   _stream(stream), C.byref(h)))

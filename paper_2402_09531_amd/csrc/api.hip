@@ -294,6 +294,8 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     if (o.max_nrhs < 1 || o.max_nrhs > 32) return fail(DWFMM_E_INVALID, "max_nrhs must be in [1, 32]");
     if (o.check_every < 1) return fail(DWFMM_E_INVALID, "check_every must be >= 1");
     if (o.precision < 0 || o.precision > 2) return fail(DWFMM_E_INVALID, "unknown precision");
+    if (o.node_rule < 0 || o.node_rule > 1 || o.afp_candidates < 0)
+        return fail(DWFMM_E_INVALID, "unknown node rule or negative candidate count");
     const HostTree &H = tree->H;
     hipStream_t st = (hipStream_t)stream;
 
@@ -302,15 +304,15 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     std::string err;
     std::vector<double> omega(H.d);
     if (!compute_weights(o.weight_rule, H.d, H.b.data(), H.eta, o.omega, omega.data(), err) ||
-        !build_basis(H.d, omega.data(), q, op->B, err)) {
+        !build_basis(H.d, omega.data(), q, op->B, err, o.node_rule, o.afp_candidates)) {
         delete op;
         return fail(DWFMM_E_INVALID, err);
     }
     const HostBasis &B = op->B;
     const int nx = B.nx, dp = tree->D.dpad;
-    if (nx > 64 || nx * dp > 1536) {
+    if (nx > 128 || nx * dp > 3072) {
         delete op;
-        return fail(DWFMM_E_INVALID, "index set too large for the GPU kernels (n_x <= 64, n_x * d <= 1536)");
+        return fail(DWFMM_E_INVALID, "index set too large for the GPU kernels (n_x <= 128, n_x * d <= 3072)");
     }
     std::vector<double> nodes, nodes_p((size_t)H.ncl * nx * dp, 0.0), E;
     box_nodes(H, B, nodes);

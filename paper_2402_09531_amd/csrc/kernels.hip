@@ -15,8 +15,9 @@ namespace dwfmm {
 
 namespace {
 
-constexpr int kMaxNx = 64;
-constexpr int kMaxNodeWords = 1536;  // nx * dpad bound of the M2L node tiles
+constexpr int kMaxNx = 128;
+constexpr int kMaxNodeWords = 3072;  // nx * dpad bound of the generic M2L node tiles
+constexpr int kM2lRows = 16;         // coupling rows the generic M2L forms at a time
 typedef double dbl4 __attribute__((ext_vector_type(4)));  // accumulator of v_mfma_f64_16x16x4f64
 
 // e^x for x <= 0 in FP64 without special-case branches: Cody-Waite reduction
@@ -211,12 +212,15 @@ __global__ __launch_bounds__(64) void m2m_kernel(DevTree T, DevOp O, int first, 
 }
 
 // ---------------------------------------------------------------- M2L, all farfield levels at once
+// General kernel (any kernel kind, n_x <= 128, up to 32 rhs): one workgroup per target
+// cluster, node coordinates of the target and of each farfield source in LDS, the coupling
+// matrix S formed kM2lRows rows at a time and applied to the source moments.
 template <int KIND>
 __global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first, int nrhs)
 {
     __shared__ double tn[kMaxNodeWords];
     __shared__ double sn[kMaxNodeWords];
-    __shared__ double S[kMaxNx * kMaxNx];
+    __shared__ double S[kM2lRows * kMaxNx];
     const int c = first + blockIdx.x;
     const int nx = O.nx, dp = T.dpad;
     const int f0 = T.Fptr[c], f1 = T.Fptr[c + 1];
@@ -229,36 +233,39 @@ __global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first,
         for (int q = threadIdx.x; q < nx * dp; q += blockDim.x) tn[q] = O.nodes[(size_t)c * nx * dp + q];
         for (int f = f0; f < f1; ++f) {
             const int s = T.Fsrc[f];
-            for (int q = threadIdx.x; q < nx * dp; q += blockDim.x) sn[q] = O.nodes[(size_t)s * nx * dp + q];
-            __syncthreads();
-            for (int q = threadIdx.x; q < nx * nx; q += blockDim.x) {
-                const int a = q / nx, b = q % nx;
-                double v;
-                if constexpr (KIND == 3) {
-                    v = poly_kernel(&tn[a * dp], &sn[b * dp], (int)O.ell);
-                } else {
-                    double r2 = 0.0;
-                    for (int k = 0; k < dp; ++k) {
-                        const double t = tn[a * dp + k] - sn[b * dp + k];
-                        r2 += t * t;
-                    }
-                    v = kernel_val<KIND>(r2, inv_ell);
-                }
-                S[q] = v;
-            }
-            __syncthreads();
             const double *m = O.M + (size_t)s * nx * nrhs;
+            for (int q = threadIdx.x; q < nx * dp; q += blockDim.x) sn[q] = O.nodes[(size_t)s * nx * dp + q];
+            for (int a0 = 0; a0 < nx; a0 += kM2lRows) {
+                const int rows = min(kM2lRows, nx - a0);
+                __syncthreads();  // sn staged / the previous chunk consumed
+                for (int q = threadIdx.x; q < rows * nx; q += blockDim.x) {
+                    const int a = a0 + q / nx, b = q % nx;
+                    double v;
+                    if constexpr (KIND == 3) {
+                        v = poly_kernel(&tn[a * dp], &sn[b * dp], (int)O.ell);
+                    } else {
+                        double r2 = 0.0;
+                        for (int k = 0; k < dp; ++k) {
+                            const double t = tn[a * dp + k] - sn[b * dp + k];
+                            r2 += t * t;
+                        }
+                        v = kernel_val<KIND>(r2, inv_ell);
+                    }
+                    S[q] = v;
+                }
+                __syncthreads();
 #pragma unroll
-            for (int k = 0; k < kAcc; ++k) {
-                const int p = threadIdx.x + 256 * k;
-                if (p < nx * nrhs) {
+                for (int k = 0; k < kAcc; ++k) {
+                    const int p = threadIdx.x + 256 * k;
                     const int a = p / nrhs, r = p % nrhs;
-                    double v = 0.0;
-                    for (int b = 0; b < nx; ++b) v += S[a * nx + b] * m[b * nrhs + r];
-                    acc[k] += v;
+                    if (p < nx * nrhs && a >= a0 && a < a0 + rows) {
+                        double v = 0.0;
+                        for (int b = 0; b < nx; ++b) v += S[(a - a0) * nx + b] * m[b * nrhs + r];
+                        acc[k] += v;
+                    }
                 }
             }
-            __syncthreads();
+            __syncthreads();  // before the next source overwrites sn
         }
     }
 #pragma unroll

@@ -142,7 +142,97 @@ static bool lu_inverse(int n, const std::vector<double> &A, std::vector<double> 
 }
 
 // ------------------------------------------------------------------ basis
-bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string &err)
+// Basis values p_b(t), b in canonical order, through the parent recursion of the index set.
+static void basis_values(const HostBasis &B, const double *t, std::vector<std::vector<double>> &axv, double *pv)
+{
+    for (int k = 0; k < B.d; ++k) legendre01(B.mk[k], t[k], axv[k].data());
+    pv[0] = 1.0;
+    for (int j = 1; j < B.nx; ++j) pv[j] = pv[B.par[j]] * axv[B.pax[j]][B.pdeg[j]];
+}
+
+// Approximate Fekete points (Sec 5.4).  Candidates: Halton points 1..M over the axes with
+// m_k > 0 (the r-th active axis in the r-th prime base; the radical inverse is formed as an
+// integer over a power of the base, so it is exact up to one rounding), 1/2 elsewhere.
+// Selection: greedy volume maximisation over the candidates' basis-value vectors c_j --
+// step k takes the candidate whose component orthogonal to the vectors already taken is
+// longest (relative 1e-12 ties to the lowest index), which is the pivot order of a
+// column-pivoted QR of the Vandermonde matrix.  The orthogonal components are kept by
+// modified Gram-Schmidt, projecting each new direction out twice.
+static bool afp_nodes(HostBasis &B, int64_t M, std::string &err)
+{
+    const int d = B.d, nx = B.nx;
+    if (M < nx) {
+        err = "fewer AFP candidates than nodes";
+        return false;
+    }
+    std::vector<int> primes;
+    for (int c = 2; (int)primes.size() < d; ++c) {
+        bool pr = true;
+        for (int f : primes) {
+            if (f * f > c) break;
+            if (c % f == 0) { pr = false; break; }
+        }
+        if (pr) primes.push_back(c);
+    }
+    std::vector<double> Y((size_t)M * d);
+    for (int64_t j = 0; j < M; ++j) {
+        int r = 0;
+        for (int k = 0; k < d; ++k) {
+            if (B.mk[k] == 0) {
+                Y[(size_t)j * d + k] = 0.5;
+                continue;
+            }
+            const uint64_t base = (uint64_t)primes[r++];
+            uint64_t i = (uint64_t)j + 1, num = 0, den = 1;
+            for (; i > 0; i /= base) {
+                num = num * base + i % base;
+                den *= base;
+            }
+            Y[(size_t)j * d + k] = (double)num / (double)den;
+        }
+    }
+    // residual vectors, candidate-major
+    std::vector<double> R((size_t)M * nx), qv(nx);
+    std::vector<std::vector<double>> axv(d);
+    for (int k = 0; k < d; ++k) axv[k].resize(B.mk[k] + 1);
+    for (int64_t j = 0; j < M; ++j) basis_values(B, &Y[(size_t)j * d], axv, &R[(size_t)j * nx]);
+    std::vector<char> taken(M, 0);
+    std::vector<double> nrm2(M);
+    B.xi.assign((size_t)nx * d, 0.0);
+    for (int k = 0; k < nx; ++k) {
+        double top = 0.0;
+        for (int64_t j = 0; j < M; ++j) {
+            if (taken[j]) continue;
+            double s = 0.0;
+            for (int b = 0; b < nx; ++b) s += R[(size_t)j * nx + b] * R[(size_t)j * nx + b];
+            nrm2[j] = s;
+            top = std::max(top, s);
+        }
+        if (!(top > 0.0)) {
+            err = "AFP candidates do not span the polynomial space";
+            return false;
+        }
+        int64_t pick = -1;
+        for (int64_t j = 0; j < M && pick < 0; ++j)
+            if (!taken[j] && nrm2[j] >= top * (1.0 - 1e-12)) pick = j;
+        taken[pick] = 1;
+        std::copy(&Y[(size_t)pick * d], &Y[(size_t)pick * d] + d, &B.xi[(size_t)k * d]);
+        const double inv = 1.0 / std::sqrt(nrm2[pick]);
+        for (int b = 0; b < nx; ++b) qv[b] = R[(size_t)pick * nx + b] * inv;
+        for (int pass = 0; pass < 2; ++pass)
+            for (int64_t j = 0; j < M; ++j) {
+                if (taken[j]) continue;
+                double *rj = &R[(size_t)j * nx];
+                double dot = 0.0;
+                for (int b = 0; b < nx; ++b) dot += qv[b] * rj[b];
+                for (int b = 0; b < nx; ++b) rj[b] -= dot * qv[b];
+            }
+    }
+    return true;
+}
+
+bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string &err, int node_rule,
+                 int64_t n_cand)
 {
     B = HostBasis();
     B.d = d;
@@ -193,12 +283,6 @@ bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string
     B.mk.assign(d, 0);
     for (int i = 0; i < nx; ++i)
         for (int k = 0; k < d; ++k) B.mk[k] = std::max<int>(B.mk[k], B.alpha[(size_t)i * d + k]);
-    // per-axis nodes; xi_alpha = (z^(1)_{alpha_1}, ..., z^(d)_{alpha_d})
-    B.xi.resize((size_t)nx * d);
-    for (int k = 0; k < d; ++k) {
-        std::vector<double> z = leja_chebyshev(B.mk[k]);
-        for (int i = 0; i < nx; ++i) B.xi[(size_t)i * d + k] = z[B.alpha[(size_t)i * d + k]];
-    }
     // parent structure: beta = parent + beta_k e_k with k the last non-zero axis
     B.par.assign(nx, -1);
     B.pax.assign(nx, 0);
@@ -228,6 +312,16 @@ bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string
             off += B.mk[k] + 1;
         }
     B.nleg = off;
+    if (node_rule == 0) {
+        // per-axis nodes; xi_alpha = (z^(1)_{alpha_1}, ..., z^(d)_{alpha_d})
+        B.xi.resize((size_t)nx * d);
+        for (int k = 0; k < d; ++k) {
+            std::vector<double> z = leja_chebyshev(B.mk[k]);
+            for (int i = 0; i < nx; ++i) B.xi[(size_t)i * d + k] = z[B.alpha[(size_t)i * d + k]];
+        }
+    } else if (!afp_nodes(B, n_cand > 0 ? n_cand : std::max<int64_t>(2000, 50 * (int64_t)nx), err)) {
+        return false;
+    }
     // Vandermonde V[a][b] = p_b(xi_a) and its inverse
     std::vector<double> V((size_t)nx * nx);
     std::vector<double> leg(256);

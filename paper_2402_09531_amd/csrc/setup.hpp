@@ -44,7 +44,10 @@ struct HostBasis {
 bool build_tree(const double *pts_host, int64_t n, int d, const double *b, int leaf, double eta, HostTree &T,
                 std::string &err);
 
-bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string &err);
+// node_rule 0: per-axis Chebyshev-Leja nodes; 1: approximate Fekete points from n_cand
+// Halton candidates (0 = max(2000, 50 n_x)).
+bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string &err, int node_rule = 0,
+                 int64_t n_cand = 0);
 
 bool compute_weights(int rule, int d, const double *b, double eta, const double *explicit_omega, double *omega,
                      std::string &err);
