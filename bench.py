@@ -341,6 +341,80 @@ def bench_paper_ce(args):
     print(json.dumps(out), flush=True)
 
 
+# The best (length scale, ridge) pairs the paper reports for its Sec 6.2 prediction study, on its
+# grids (sigma: the printed CE grid; lambda: 15 log-equispaced values in [1e-6, 1e-1]), with the
+# printed average prediction error and its deviation.
+PAPER_PE_BEST = {2: (4.6911823e-02, 10.0 ** (-6 + 5 * 0 / 14), 5.98e-3, 3.94e-4),
+                 3: (3.2921150e-01, 10.0 ** (-6 + 5 * 5 / 14), 6.31e-3, 3.24e-4),
+                 4: (5.0101830e-01, 10.0 ** (-6 + 5 * 4 / 14), 2.46e-3, 1.38e-4)}
+
+
+def bench_paper_pe(args):
+    """Prediction error at the paper's best Sec 6.2 parameters: solve (K~ + lambda I) alpha = f on
+    N = 1e5 points (CG to 1e-6), f(x) = sin(4 pi |x|) / (8 pi |x|), then compare the interpolant
+    s(t) = sum_j alpha_j K(t, x_j), summed exactly, with f at 1000 uniform points of the root box
+    (five draws)."""
+    import torch
+    import paper_2402_09531_amd as dw
+    from paper_2402_09531_amd import workloads as W
+    dev = torch.device("cuda:0")
+    n = args.ce_n
+    out = {"metric": "prediction error at the paper's best Sec 6.2 parameters", "unit": "relative 2-norm error",
+           "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"N={n}, d=20, b_k=k^-r, exponential kernel, q=8, Sec 6.2 weights, AFP nodes, "
+                                  f"admissibility {args.ce_eta} x full diagonal, leaf {args.ce_leaf}, CG rtol 1e-6, "
+                                  "1000 test points x 5 draws"},
+           "results": {}}
+
+    def f_true(P):
+        r = torch.linalg.norm(P, dim=1)
+        return torch.sin(4 * np.pi * r) / (8 * np.pi * r)
+
+    for r in (2, 3, 4):
+        sigma, lam, pe_p, sd_p = PAPER_PE_BEST[r]
+        X = W.points(n, 20, float(r), 6200 + r)
+        b = W.dim_weights(20, float(r))
+        Xd = torch.from_numpy(X).to(dev)
+        tree = dw.build_tree(Xd, b, args.ce_leaf, args.ce_eta)
+        t_start = time.perf_counter()
+
+        def progress(it, rr, r=r):
+            if it % 256 == 0:
+                log(f"[pe] r={r} CG iteration {it}: relative residual {rr[0]:.3e} "
+                    f"({time.perf_counter() - t_start:.1f} s)")
+
+        op = dw.fmm_create(tree, "exponential", sigma, 8, weight_rule="R3", nodes="afp", check_every=16,
+                           progress=progress)
+        fd = f_true(Xd)[:, None].contiguous()
+        ad = torch.zeros_like(fd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        info = dw.fmm_solve(op, lam, fd, ad, 1e-6, args.pe_max_iter)[0]
+        torch.cuda.synchronize()
+        t_solve = time.perf_counter() - t0
+        lo, hi = Xd.min(0).values, Xd.max(0).values
+        pes = []
+        for rep in range(5):
+            g = torch.Generator(device="cpu").manual_seed(7000 * r + rep)
+            T = (lo.cpu() + (hi - lo).cpu() * torch.rand((1000, 20), generator=g, dtype=torch.float64)).to(dev)
+            s_t = torch.zeros(1000, dtype=torch.float64, device=dev)
+            for c0 in range(0, 1000, 100):
+                D = torch.cdist(T[c0:c0 + 100], Xd, compute_mode="donot_use_mm_for_euclid_dist")
+                s_t[c0:c0 + 100] = torch.exp(-D / sigma) @ ad[:, 0]
+            ft = f_true(T)
+            pes.append(float(torch.linalg.norm(s_t - ft) / torch.linalg.norm(ft)))
+        m, sd = float(np.mean(pes)), float(np.std(pes))
+        out["results"][f"r{r}"] = {"sigma": sigma, "lambda": lam, "cg": info, "solve_s": round(t_solve, 2),
+                                   "pe_mean": m, "pe_std": sd, "paper_pe": pe_p, "paper_std": sd_p, "ratio": m / pe_p}
+        log(f"[pe] r={r} sigma={sigma:.3e} lambda={lam:.3e}: CG {info['iters']} iterations, status {info['status']}, "
+            f"true residual {info['rel_res_true']:.2e}, {t_solve:.1f} s; PE {m:.3e} +- {sd:.1e}, "
+            f"paper {pe_p:.2e} +- {sd_p:.1e}")
+        op.close()
+        tree.close()
+    out["value"] = float(np.exp(np.mean([np.log(v["ratio"]) for v in out["results"].values()])))
+    print(json.dumps(out), flush=True)
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize":
         summarize_profile(sys.argv[2])
@@ -358,7 +432,10 @@ def main():
     ap.add_argument("--batch", type=int, default=0, help="batch mode: number of independent problems")
     ap.add_argument("--no-tune", action="store_true", help="batch: keep the default M2L tile shape")
     ap.add_argument("--paper-ce", action="store_true", help="compression error at the paper's Sec 6.2 settings")
-    ap.add_argument("--ce-n", type=int, default=100_000, help="paper-ce: number of points")
+    ap.add_argument("--paper-pe", action="store_true",
+                    help="prediction error at the paper's best Sec 6.2 parameters (CG solves)")
+    ap.add_argument("--pe-max-iter", type=int, default=4000, help="paper-pe: CG iteration limit")
+    ap.add_argument("--ce-n", type=int, default=100_000, help="paper-ce/pe: number of points")
     ap.add_argument("--ce-leaf", type=int, default=128, help="paper-ce: leaf size")
     ap.add_argument("--ce-eta", type=float, default=1.0,
                     help="paper-ce: admissibility parameter of build_tree (dist >= eta * max full diagonal); "
@@ -385,6 +462,9 @@ def main():
         return
     if args.paper_ce:
         bench_paper_ce(args)
+        return
+    if args.paper_pe:
+        bench_paper_pe(args)
         return
 
     import torch

@@ -85,6 +85,12 @@ typedef struct {
     int32_t ir_max_outer;    /* reduced precision: max refinement steps, default 30 */
     int32_t node_rule;       /* dwfmm_node_rule, default CHEB_LEJA */
     int32_t afp_candidates;  /* AFP: Halton candidates M >= n_x, 0 = max(2000, 50 n_x) */
+    /* Optional (NULL = none): called by dwfmm_fmm_solve on the calling thread at each host
+     * convergence check (every check_every iterations) with the iteration count, nrhs and
+     * the recursive relative residuals |r|/|f| per column (host array, valid during the
+     * call).  It must not call into the library for this operator. */
+    void (*progress)(void *ctx, int32_t iteration, int32_t nrhs, const double *rel_res);
+    void *progress_ctx;
 } dwfmm_opts;
 
 /* Per right-hand-side result of dwfmm_fmm_solve. */

@@ -96,6 +96,8 @@ struct dwfmm_op_s {
     Arena arena;
     int precision = 0, max_nrhs = 1, check_every = 1, ir_max_outer = 30;
     double ir_inner_rtol = 0.0;
+    void (*progress)(void *, int32_t, int32_t, const double *) = nullptr;
+    void *progress_ctx = nullptr;
     // CG workspace
     double *r = nullptr, *p = nullptr, *q = nullptr, *partial = nullptr, *scal = nullptr;
     double *ir_r = nullptr, *ir_d = nullptr;  // refinement: outer residual and correction
@@ -422,6 +424,8 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     op->check_every = o.check_every;
     op->ir_inner_rtol = o.ir_inner_rtol;
     op->ir_max_outer = o.ir_max_outer;
+    op->progress = o.progress;
+    op->progress_ctx = o.progress_ctx;
     op->tree = tree;
     tree->refs++;
     *out = op;
@@ -600,13 +604,23 @@ hipError_t cg_run(dwfmm_op op, double lambda, const double *b, double *x, int nr
     if ((e = launch_dot(r, r, T.n, nrhs, op->partial, scal, st)) != hipSuccess) return e;
     if ((e = launch_dot(b, b, T.n, nrhs, op->partial, scal + nrhs, st)) != hipSuccess) return e;
     hstate.assign(3 * nrhs, 0);
+    hrr.assign(2 * nrhs, 0.0);
     for (int it = 0; it < max_iter; ++it) {
         hipLaunchKernelGGL(cg_check_kernel, dim3(nb), dim3(64), 0, st, scal, state, nrhs, rtol);
         if (it % op->check_every == 0) {
             if ((e = hipMemcpyAsync(hstate.data(), state, sizeof(int32_t) * nrhs, hipMemcpyDeviceToHost, st)) !=
                 hipSuccess)
                 return e;
+            if (op->progress && (e = hipMemcpyAsync(hrr.data(), scal, sizeof(double) * 2 * nrhs,
+                                                    hipMemcpyDeviceToHost, st)) != hipSuccess)
+                return e;
             if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+            if (op->progress) {
+                std::vector<double> rel(nrhs);
+                for (int c = 0; c < nrhs; ++c)
+                    rel[c] = hrr[nrhs + c] > 0 ? std::sqrt(hrr[c] / hrr[nrhs + c]) : std::sqrt(hrr[c]);
+                op->progress(op->progress_ctx, it, nrhs, rel.data());
+            }
             bool active = false;
             for (int c = 0; c < nrhs; ++c) active |= hstate[c] == 0;
             if (!active) break;

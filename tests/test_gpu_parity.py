@@ -298,3 +298,21 @@ def test_invalid_arguments():
     x = torch.zeros(100, 2, dtype=torch.float64, device="cuda")
     with pytest.raises(dw.DwfmmError):
         dw.fmm_matvec(op, x, torch.empty_like(x))   # nrhs 2 > max_nrhs 1
+
+
+def test_solve_progress_callback(orc):
+    """The optional progress callback sees every host check: iterations are multiples of
+    check_every and the last reported residual is the one the solve ends with."""
+    w = W.WORKLOADS["small_d4"]
+    X, b, _ = W.make(w)
+    f = W.rhs(w, X)[:, None]
+    seen = []
+    _, op = gpu_op(X, b, w.leaf, w.eta, w.kernel, w.ell, 4, check_every=4,
+                   progress=lambda it, rr: seen.append((it, rr[0])))
+    fd = torch.from_numpy(f).cuda()
+    ad = torch.zeros_like(fd)
+    info = dw.fmm_solve(op, 0.5, fd, ad, 1e-10, 20000)[0]
+    assert info["status"] == 0 and len(seen) >= 2
+    assert all(it % 4 == 0 for it, _ in seen)
+    assert seen[0][1] == pytest.approx(1.0)
+    assert seen[-1][1] <= 1e-10 and seen[-1][1] == pytest.approx(info["rel_res_recursive"], rel=1e-12)
