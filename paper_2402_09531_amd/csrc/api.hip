@@ -84,6 +84,9 @@ struct dwfmm_tree_s {
     DevTree D{};
     Arena arena;
     double *clo = nullptr, *csc = nullptr, *coff = nullptr;  // [ncl][d] reference-coordinate maps
+    // max over nearfield leaf pairs (t, s) of (R_t + |c_s - c_t| + R_s)^2, R the half diagonal and
+    // c the midpoint of a leaf box: bounds every squared shifted distance the nearfield forms
+    double near_reach2 = 0.0;
     int refs = 1;       // the caller's reference plus one per operator
     bool destroyed = false;
     int device = 0;
@@ -212,10 +215,29 @@ static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, in
         for (size_t b = 0; b < owned.size(); ++b)
             if (owned[b].first != owned[b].second) inc_blk[fill[owned[b].second]++] = (int32_t)b;
     }
-    std::vector<double> center((size_t)H.nleaf * dp, 0.0);
+    std::vector<double> center((size_t)H.nleaf * dp, 0.0), rad(H.nleaf, 0.0);
+    for (int64_t l = 0; l < H.nleaf; ++l) {
+        double r2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+            const double lo = H.lo[(size_t)(lf + l) * d + k], hi = H.hi[(size_t)(lf + l) * d + k];
+            center[(size_t)l * dp + k] = 0.5 * (lo + hi);
+            r2 += 0.25 * (hi - lo) * (hi - lo);
+        }
+        rad[l] = std::sqrt(r2);
+    }
+    double reach2 = 0.0;
     for (int64_t l = 0; l < H.nleaf; ++l)
-        for (int k = 0; k < d; ++k)
-            center[(size_t)l * dp + k] = 0.5 * (H.lo[(size_t)(lf + l) * d + k] + H.hi[(size_t)(lf + l) * d + k]);
+        for (int32_t q = nptr_leaf[l]; q < nptr_leaf[l + 1]; ++q) {
+            const int32_t s = nsrc_local[q];
+            double dc = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double t = center[(size_t)s * dp + k] - center[(size_t)l * dp + k];
+                dc += t * t;
+            }
+            const double reach = rad[l] + std::sqrt(dc) + rad[s];
+            reach2 = std::max(reach2, reach * reach);
+        }
+    t->near_reach2 = reach2;
 
     DevTree &D = t->D;
     auto up = [&](auto **dst, const auto &v) { return t->arena.upload(dst, v, st); };
@@ -408,6 +430,8 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     DevOp &D = op->D;
     D.kind = kernel.kind;
     D.ell = kernel.ell;
+    D.gauss_split = kernel.kind == DWFMM_GAUSSIAN && tree->near_reach2 / kernel.ell <= 600.0;
+    D.gauss_split32 = kernel.kind == DWFMM_GAUSSIAN && tree->near_reach2 / kernel.ell <= 80.0;
     D.nx = nx;
     D.max_nrhs = o.max_nrhs;
     D.nodes = dnodes;
@@ -867,7 +891,12 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
         if ((int)work.size() > off) P.l2l.push_back({off, (int)work.size() - off});
     }
     auto key = [&](const BatchItem &I, bool far_list) {
-        return std::vector<int>{I.O.kind, (I.T.d + 3) / 4 * 4, far_list ? I.O.nxp / 16 : 0, I.precision != 0};
+        // the FP64 nearfield of a split Gaussian runs its own kernel variant (kind 4)
+        const int kind = !far_list && I.O.kind == DWFMM_GAUSSIAN &&
+                                 (I.precision == 0 ? I.O.gauss_split : I.O.gauss_split32)
+                             ? 4
+                             : I.O.kind;
+        return std::vector<int>{kind, (I.T.d + 3) / 4 * 4, far_list ? I.O.nxp / 16 : 0, I.precision != 0};
     };
     std::vector<std::vector<int>> keys;
     for (auto &it : b->items) {
@@ -1514,6 +1543,7 @@ extern "C" dwfmm_status dwfmm_op_info(dwfmm_op op, int64_t *out)
     out[1] = op->max_nrhs;
     out[2] = op->precision;
     out[3] = (int64_t)dwfmm_op_bytes(op);
+    out[4] = op->D.gauss_split;
     return DWFMM_OK;
 }
 

@@ -43,6 +43,11 @@ struct DevOp {
     const double *nnorm;          // [ncl][nxp] squared norms of the nodes, zero padded
     double *rowbuf;               // [nleaf][128] owner-side nearfield row sums (one rhs)
     double *colbuf;               // [nblk][128] column sums of owned blocks (one rhs)
+    // Gaussian only: every nearfield exponent |x - c|^2 / ell, |y - c|^2 / ell, 2 (x - c).(y - c) / ell
+    // (c the owner leaf's midpoint) is at most 600 in magnitude, so the symmetric FP64 nearfield may
+    // evaluate exp(-|x-y|^2/ell) = exp(-|x-c|^2/ell) exp(-|y-c|^2/ell) exp(2 (x-c).(y-c)/ell).
+    int gauss_split;
+    int gauss_split32;            // the same with every exponent within 80 (the FP32 nearfield)
 };
 
 // Optional HIP events recorded around the nearfield (P2P) and coupling (M2L)

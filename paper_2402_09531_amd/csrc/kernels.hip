@@ -20,14 +20,13 @@ constexpr int kMaxNodeWords = 3072;  // nx * dpad bound of the generic M2L node 
 constexpr int kM2lRows = 16;         // coupling rows the generic M2L forms at a time
 typedef double dbl4 __attribute__((ext_vector_type(4)));  // accumulator of v_mfma_f64_16x16x4f64
 
-// e^x for x <= 0 in FP64 without special-case branches: Cody-Waite reduction
+// e^x in FP64 for |x| <= 708 without special-case branches: Cody-Waite reduction
 // x = n ln2 + r, |r| <= ln2/2, with a two-part ln2, then a degree-10 polynomial
 // for e^r (coefficients: the interpolant of e^r at 11 first-kind Chebyshev points
 // of [-ln2/2, ln2/2], from csrc/gen_exp_coeffs.py; 2.9e-16 relative interpolation
-// error), scaled by 2^n.  Arguments below -745 (where e^x underflows to zero) are clamped.
-__device__ __forceinline__ double exp_nonpos(double x)
+// error), scaled by 2^n.
+__device__ __forceinline__ double exp_bounded(double x)
 {
-    x = fmax(x, -745.0);
     const double n = rint(x * 1.4426950408889634);
     double r = fma(-n, 0.6931471805599453, x);
     r = fma(-n, 2.3201926491189795e-17, r);
@@ -44,6 +43,9 @@ __device__ __forceinline__ double exp_nonpos(double x)
     p = fma(p, r, 1.0);
     return ldexp(p, (int)n);
 }
+
+// e^x for x <= 0: arguments below -745 (where e^x underflows to zero) are clamped.
+__device__ __forceinline__ double exp_nonpos(double x) { return exp_bounded(fmax(x, -745.0)); }
 
 // sqrt(x) for x >= 1e-300 (callers clamp; below that the kernels are 1 to double precision):
 // the hardware reciprocal square root seeds Goldschmidt's coupled iteration for g = sqrt(x)
@@ -504,6 +506,9 @@ hipError_t launch_p2p_k(const DevTree &T, const DevOp &O, double *y, int nrhs, i
 // Lane layout of v_mfma_f64_16x16x4f64: A[i][k] in lane i + 16k, B[k][j] in lane
 // j + 16k, D[i][j] in lane j + 16(i%4), element i/4 (checked with a probe).
 constexpr int kSymLeaf = 128;
+// Internal kernel variant of the symmetric FP64 nearfield: the Gaussian evaluated as
+// exp(-|x-c|^2/ell) exp(-|y-c|^2/ell) exp(2 (x-c).(y-c)/ell) (operators with gauss_split set).
+constexpr int kGaussSplit = 4;
 
 // One leaf block, all 16x16 tiles of this wave's two row tiles.  DIAG: the block of a
 // leaf with itself (i == j forced to distance 0, no column sums).
@@ -517,7 +522,7 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
     const int nct = (ns + 15) / 16;
     for (int ct = 0; ct < nct; ++ct) {
         const int j = 16 * ct + li;
-        const double nb = sN[j], qb = sQ[j];
+        const double nb = KIND == kGaussSplit ? 0.0 : sN[j], qb = sQ[j];
         double Bf[NKC];
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
@@ -525,17 +530,28 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;  // uniform over the wave
-            // A holds -2 (x - c): the MFMA chain accumulates |x|^2 + |y|^2 - 2 x.y = r^2 directly
-            dbl4 G = {rN[u][0] + nb, rN[u][1] + nb, rN[u][2] + nb, rN[u][3] + nb};
+            // A holds -2 (x - c): the MFMA chain accumulates |x|^2 + |y|^2 - 2 x.y = r^2 directly.
+            // Split Gaussian: A holds (2 / ell)(x - c) and the chain gives the exponent of the
+            // cross factor; the row and column factors sit in the charges.
+            dbl4 G;
+            if constexpr (KIND == kGaussSplit)
+                G = dbl4{0.0, 0.0, 0.0, 0.0};
+            else
+                G = dbl4{rN[u][0] + nb, rN[u][1] + nb, rN[u][2] + nb, rN[u][3] + nb};
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u][kc], Bf[kc], G, 0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                double r2 = G[v];  // kernel_fast clamps where it takes a square root
-                if constexpr (DIAG) {
-                    if (16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
+                double kv;
+                if constexpr (KIND == kGaussSplit) {
+                    kv = exp_bounded(G[v]);
+                } else {
+                    double r2 = G[v];  // kernel_fast clamps where it takes a square root
+                    if constexpr (DIAG) {
+                        if (16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
+                    }
+                    kv = kernel_fast<KIND>(r2, inv_ell);
                 }
-                const double kv = kernel_fast<KIND>(r2, inv_ell);
                 racc[u][v] = fma(kv, qb, racc[u][v]);
                 if constexpr (!DIAG) cacc = fma(kv, rQ[u][v], cacc);
             }
@@ -589,8 +605,14 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
             s = fma(v, v, s);
         }
         const double q = O.xt[ii];
-        tN[tid] = ok ? s : 0.0;
-        tQ[tid] = ok ? q : 0.0;
+        if constexpr (KIND == kGaussSplit) {
+            const double a = exp_bounded(-s * inv_ell);  // row factor
+            tN[tid] = ok ? a : 0.0;
+            tQ[tid] = ok ? q * a : 0.0;
+        } else {
+            tN[tid] = ok ? s : 0.0;
+            tQ[tid] = ok ? q : 0.0;
+        }
     }
     const int rt[2] = {w, w + 4};
     double A[2][NKC];
@@ -599,11 +621,12 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         const int i = 16 * rt[u] + li;
         const bool ok = i < nt;
         const int ii = cb + (ok ? i : nt - 1);
+        const double scale = KIND == kGaussSplit ? 2.0 * inv_ell : -2.0;
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
             const int k = 4 * kc + lg;
             const double v = T.Xs[(size_t)k * n + ii] - cen[k];
-            A[u][kc] = ok ? -2.0 * v : 0.0;
+            A[u][kc] = ok ? scale * v : 0.0;
         }
     }
     __syncthreads();
@@ -639,8 +662,14 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
                 sX[k * kSymLeaf + j] = v;
                 s = fma(v, v, s);
             }
-            sN[j] = s;
-        } else {
+            if constexpr (KIND == kGaussSplit) {
+                const double bfac = exp_bounded(-s * inv_ell);  // column factor
+                sN[j] = bfac;
+                sQ[j] = ok ? O.xt[jj] * bfac : 0.0;
+            } else {
+                sN[j] = s;
+            }
+        } else if constexpr (KIND != kGaussSplit) {
             const int j = tid - kSymLeaf;
             const double q = O.xt[sb + (j < ns ? j : ns - 1)];
             sQ[j] = j < ns ? q : 0.0;
@@ -652,9 +681,12 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
             sym_block<KIND, NKC, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
         if (!diag) {
             __syncthreads();
-            if (tid < ns)
-                O.colbuf[(size_t)f * kSymLeaf + tid] =
-                    ((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) + colpart[3 * kSymLeaf + tid];
+            if (tid < ns) {
+                double cs = ((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) +
+                            colpart[3 * kSymLeaf + tid];
+                if constexpr (KIND == kGaussSplit) cs *= sN[tid];
+                O.colbuf[(size_t)f * kSymLeaf + tid] = cs;
+            }
         }
     }
 #pragma unroll
@@ -667,12 +699,17 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
             s += __shfl_xor(s, 4, 64);
             s += __shfl_xor(s, 8, 64);
             const int i = 16 * rt[u] + 4 * v + lg;
+            if constexpr (KIND == kGaussSplit) s *= rN[u][v];
             if (li == 0 && i < nt) O.rowbuf[(size_t)l * kSymLeaf + i] = s;
         }
 }
 
+// Three waves per SIMD where the registers allow it without spilling (the split Gaussian
+// otherwise settles at two for d <= 20).
 template <int KIND, int DK>
-__global__ __launch_bounds__(256) void p2p_sym_kernel(DevTree T, DevOp O)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(DK <= 20 || (KIND != kGaussSplit && DK <= 24) ? 3 : 1, 8)))
+void p2p_sym_kernel(DevTree T, DevOp O)
 {
     p2p_sym_body<KIND, DK>(T, O, xcd_leaf(blockIdx.x, T.nleaf));
 }
@@ -930,7 +967,7 @@ __device__ __forceinline__ void sym_block32(const float (&A)[2][NKC], const floa
     const int nct = (ns + 15) / 16;
     for (int ct = 0; ct < nct; ++ct) {
         const int j = 16 * ct + li;
-        const float nb = sN[j], qb = sQ[j];
+        const float nb = KIND == kGaussSplit ? 0.0f : sN[j], qb = sQ[j];
         float Bf[NKC];
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
@@ -938,17 +975,28 @@ __device__ __forceinline__ void sym_block32(const float (&A)[2][NKC], const floa
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;
-            // A holds -2 (x - c): the chain accumulates r^2 = |x|^2 + |y|^2 - 2 x.y
-            flt4 G = {rN[u][0] + nb, rN[u][1] + nb, rN[u][2] + nb, rN[u][3] + nb};
+            // A holds -2 (x - c): the chain accumulates r^2 = |x|^2 + |y|^2 - 2 x.y.  Split
+            // Gaussian: A holds (2 log2(e) / ell)(x - c), the chain gives the base-2 exponent of
+            // the cross factor; the row and column factors sit in the charges.
+            flt4 G;
+            if constexpr (KIND == kGaussSplit)
+                G = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+            else
+                G = flt4{rN[u][0] + nb, rN[u][1] + nb, rN[u][2] + nb, rN[u][3] + nb};
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(A[u][kc], Bf[kc], G, 0, 0, 0);
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                float r2 = KIND == 1 ? G[v] : fmaxf(G[v], 0.0f);
-                if constexpr (DIAG) {
-                    if (16 * rt[u] + 4 * lg + v == j) r2 = 0.0f;
+                float kv;
+                if constexpr (KIND == kGaussSplit) {
+                    kv = __builtin_amdgcn_exp2f(G[v]);
+                } else {
+                    float r2 = KIND == 1 ? G[v] : fmaxf(G[v], 0.0f);
+                    if constexpr (DIAG) {
+                        if (16 * rt[u] + 4 * lg + v == j) r2 = 0.0f;
+                    }
+                    kv = kernel_f32<KIND>(r2, inv_ell);
                 }
-                const float kv = kernel_f32<KIND>(r2, inv_ell);
                 racc[u][v] = fmaf(kv, qb, racc[u][v]);
                 if constexpr (!DIAG) cacc = fmaf(kv, rQ[u][v], cacc);
             }
@@ -988,8 +1036,14 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
             const float v = (float)(T.Xs[(size_t)k * n + ii] - cen[k]);
             s = fmaf(v, v, s);
         }
-        tN[tid] = ok ? s : 0.0f;
-        tQ[tid] = ok ? (float)O.xt[ii] : 0.0f;
+        if constexpr (KIND == kGaussSplit) {
+            const float a = __builtin_amdgcn_exp2f(s * (inv_ell * -1.4426950408889634f));  // row factor
+            tN[tid] = ok ? a : 0.0f;
+            tQ[tid] = ok ? (float)O.xt[ii] * a : 0.0f;
+        } else {
+            tN[tid] = ok ? s : 0.0f;
+            tQ[tid] = ok ? (float)O.xt[ii] : 0.0f;
+        }
     }
     const int rt[2] = {w, w + 4};
     float A[2][NKC];
@@ -998,11 +1052,12 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
         const int i = 16 * rt[u] + li;
         const bool ok = i < nt;
         const int ii = cb + (ok ? i : nt - 1);
+        const float scale = KIND == kGaussSplit ? 2.0f * 1.4426950408889634f * inv_ell : -2.0f;
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
             const int k = 4 * kc + lg;
             const float v = (float)(T.Xs[(size_t)k * n + ii] - cen[k]);
-            A[u][kc] = ok ? -2.0f * v : 0.0f;
+            A[u][kc] = ok ? scale * v : 0.0f;
         }
     }
     __syncthreads();
@@ -1037,8 +1092,14 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
                 sX[k * kSymLeaf + j] = v;
                 s = fmaf(v, v, s);
             }
-            sN[j] = s;
-        } else {
+            if constexpr (KIND == kGaussSplit) {
+                const float bfac = __builtin_amdgcn_exp2f(s * (inv_ell * -1.4426950408889634f));  // column factor
+                sN[j] = bfac;
+                sQ[j] = ok ? (float)O.xt[jj] * bfac : 0.0f;
+            } else {
+                sN[j] = s;
+            }
+        } else if constexpr (KIND != kGaussSplit) {
             const int j = tid - kSymLeaf;
             const double q = O.xt[sb + (j < ns ? j : ns - 1)];
             sQ[j] = j < ns ? (float)q : 0.0f;
@@ -1050,10 +1111,12 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
             sym_block32<KIND, NKC, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
         if (!diag) {
             __syncthreads();
-            if (tid < ns)
-                O.colbuf[(size_t)f * kSymLeaf + tid] =
-                    (double)(((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) +
-                             colpart[3 * kSymLeaf + tid]);
+            if (tid < ns) {
+                float cs = ((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) +
+                           colpart[3 * kSymLeaf + tid];
+                if constexpr (KIND == kGaussSplit) cs *= sN[tid];
+                O.colbuf[(size_t)f * kSymLeaf + tid] = (double)cs;
+            }
         }
     }
 #pragma unroll
@@ -1066,6 +1129,7 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
             s += __shfl_xor(s, 4, 64);
             s += __shfl_xor(s, 8, 64);
             const int i = 16 * rt[u] + 4 * lg + v;
+            if constexpr (KIND == kGaussSplit) s *= rN[u][v];
             if (li == 0 && i < nt) O.rowbuf[(size_t)l * kSymLeaf + i] = (double)s;
         }
 }
@@ -1761,14 +1825,14 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
         if (near && precision == 0) {
             switch (O.kind) {
             case 0: e = launch_sym_k<0>(T, O, st); break;
-            case 1: e = launch_sym_k<1>(T, O, st); break;
+            case 1: e = O.gauss_split ? launch_sym_k<kGaussSplit>(T, O, st) : launch_sym_k<1>(T, O, st); break;
             default: e = launch_sym_k<2>(T, O, st); break;
             }
             if (e != hipSuccess) return e;
         } else if (near) {  // FP32 (and BF16, whose single-rhs product has nothing to put on the BF16 MFMA)
             switch (O.kind) {
             case 0: e = launch_sym32_k<0>(T, O, st); break;
-            case 1: e = launch_sym32_k<1>(T, O, st); break;
+            case 1: e = O.gauss_split32 ? launch_sym32_k<kGaussSplit>(T, O, st) : launch_sym32_k<1>(T, O, st); break;
             default: e = launch_sym32_k<2>(T, O, st); break;
             }
             if (e != hipSuccess) return e;
@@ -1840,6 +1904,9 @@ hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t st)
         switch (L.kind) {
         case 0: lp ? launch_p2p_batch_k<0, true>(P, L, st) : launch_p2p_batch_k<0, false>(P, L, st); break;
         case 1: lp ? launch_p2p_batch_k<1, true>(P, L, st) : launch_p2p_batch_k<1, false>(P, L, st); break;
+        case kGaussSplit:
+            lp ? launch_p2p_batch_k<kGaussSplit, true>(P, L, st) : launch_p2p_batch_k<kGaussSplit, false>(P, L, st);
+            break;
         default: lp ? launch_p2p_batch_k<2, true>(P, L, st) : launch_p2p_batch_k<2, false>(P, L, st); break;
         }
     }

@@ -20,7 +20,9 @@ CSRC = pathlib.Path(__file__).resolve().parents[1] / "paper_2402_09531_amd" / "c
 
 def device_constants():
     src = (CSRC / "kernels.hip").read_text()
-    body = src[src.index("double exp_nonpos(double x)"):]
+    # exp_nonpos is exp_bounded behind the underflow clamp
+    assert "double exp_nonpos(double x) { return exp_bounded(fmax(x, -745.0)); }" in src
+    body = src[src.index("double exp_bounded(double x)"):]
     body = body[:body.index("return ldexp")]
     log2e = float(re.search(r"rint\(x \* ([0-9.e+-]+)\)", body).group(1))
     ln2 = [float(v) for v in re.findall(r"fma\(-n, ([0-9.e+-]+), ", body)]

@@ -62,6 +62,9 @@ CASES = [
     ("d3_leaf200", 20000, 3, 2.0, "matern32", 1.0, 5, 200, 0.8, 1),
     ("d40_gauss", 5000, 40, 3.0, "gaussian", 0.5, 6, 128, 0.8, 1),
     ("d30_exp_r20", 4000, 30, 3.0, "exponential", 0.3, 6, 128, 0.8, 20),
+    # Gaussian with a length scale so short that the split form's exponents would exceed 600:
+    # the single-rhs nearfield keeps the direct form
+    ("d6_gauss_short", 6000, 6, 1.0, "gaussian", 2e-4, 4, 64, 0.8, 1),
 ]
 
 
@@ -76,6 +79,8 @@ def test_matvec_parity_fp64(orc, case):
     P = orc.Plan(X, b, leaf, eta, kind, ell, q)
     tree, op = gpu_op(X, b, leaf, eta, kind, ell, q, nrhs=nrhs)
     assert op.nx == P.nx and tree.J == P.J and tree.nF == P.nF and tree.nN == P.nN
+    # the split Gaussian nearfield runs wherever its exponents stay bounded
+    assert op.gauss_split == (kind == "gaussian" and name != "d6_gauss_short")
     y_ref = P.matvec(x)
     y = gpu_matvec(op, x)
     # parts separately (diagnostic and stronger: each part is itself within tolerance)
