@@ -33,6 +33,18 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def pairwise_dist(A, B, chunk_bytes: float = 2e9):
+    """|a_i - b_j| for device tensors A (m x d), B (n x d), from explicit differences in row
+    chunks (torch.cdist on this platform returns wrong values for some shapes)."""
+    import torch
+    m, n, d = A.shape[0], B.shape[0], A.shape[1]
+    rows = max(1, int(chunk_bytes // (8 * n * d)))
+    out = torch.empty((m, n), dtype=A.dtype, device=A.device)
+    for i in range(0, m, rows):
+        out[i:i + rows] = torch.sqrt(((A[i:i + rows, None, :] - B[None, :, :]) ** 2).sum(-1))
+    return out
+
+
 def cpu_baseline(w, X, b, x, budget_leaves: int):
     """The FP64 oracle on the host cores, on the first `budget_leaves` target leaves."""
     import oracle
@@ -322,7 +334,7 @@ def bench_paper_ce(args):
                     torch.cuda.synchronize()
                     t_mv.append(time.perf_counter() - t0)
                     Kt[:, c0:c0 + chunk] = Y
-                D = torch.cdist(Xd, Xd[Jd], compute_mode="donot_use_mm_for_euclid_dist")
+                D = pairwise_dist(Xd, Xd[Jd])
                 K = torch.exp(-D / sigma)
                 ces.append(float(torch.linalg.norm(Kt - K) / torch.linalg.norm(K)))
             op.close()
@@ -399,7 +411,7 @@ def bench_paper_pe(args):
             T = (lo.cpu() + (hi - lo).cpu() * torch.rand((1000, 20), generator=g, dtype=torch.float64)).to(dev)
             s_t = torch.zeros(1000, dtype=torch.float64, device=dev)
             for c0 in range(0, 1000, 100):
-                D = torch.cdist(T[c0:c0 + 100], Xd, compute_mode="donot_use_mm_for_euclid_dist")
+                D = pairwise_dist(T[c0:c0 + 100], Xd)
                 s_t[c0:c0 + 100] = torch.exp(-D / sigma) @ ad[:, 0]
             ft = f_true(T)
             pes.append(float(torch.linalg.norm(s_t - ft) / torch.linalg.norm(ft)))
@@ -412,6 +424,59 @@ def bench_paper_pe(args):
         op.close()
         tree.close()
     out["value"] = float(np.exp(np.mean([np.log(v["ratio"]) for v in out["results"].values()])))
+    print(json.dumps(out), flush=True)
+
+
+def bench_index_compare(args):
+    """Cost of the three index sets of Sec 6.1 on one problem: weighted total degree (R1
+    weights), total degree (omega = 1) and tensor product, over a range of q.  For each: n_x,
+    the FP64 matvec time and the relative error of K~ x against direct kernel sums on 2000
+    sampled rows (N = 1e5, b_k = k^-r, leaf 128, eta 0.8; d, r and the kernel from the
+    command line: Matern-3/2 l = 1 or Gaussian exp(-r^2 / 0.5))."""
+    import torch
+    import paper_2402_09531_amd as dw
+    from paper_2402_09531_amd import workloads as W
+    dev = torch.device("cuda:0")
+    n, d, r, kind = 100_000, args.ic_d, args.ic_r, args.ic_kernel
+    ell = 1.0 if kind == "matern32" else 0.5
+    X = W.points(n, d, r, 6100)
+    b = W.dim_weights(d, r)
+    Xd = torch.from_numpy(X).to(dev)
+    x = torch.from_numpy(np.random.default_rng(6101).standard_normal((n, 1))).to(dev)
+    rows = torch.from_numpy(np.random.default_rng(6102).choice(n, 2000, replace=False)).to(dev)
+    D = pairwise_dist(Xd[rows], Xd)
+    if kind == "matern32":
+        s3 = np.sqrt(3.0) * D / ell
+        y_exact = ((1 + s3) * torch.exp(-s3)) @ x[:, 0]
+    else:
+        y_exact = torch.exp(-D * D / ell) @ x[:, 0]
+    tree = dw.build_tree(Xd, b, 128, 0.8)
+    sets = [("WTDI", dict(weight_rule="R1"), list(range(2, 13))),
+            ("TDI", dict(weight_rule="explicit", omega=np.ones(d)), [1, 2, 3, 4]),
+            ("TPI", dict(weight_rule="explicit", omega=np.ones(d), index_set="tensor"), [1, 2])]
+    out = {"metric": "index-set cost comparison (Sec 6.1)", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"N={n}, d={d}, b_k=k^-{r:g}, {kind} l={ell}, leaf 128, eta 0.8, 1 rhs"},
+           "results": []}
+    y = torch.empty_like(x)
+    for name, kw, qs in sets:
+        for q in qs:
+            try:
+                op = dw.fmm_create(tree, kind, ell, q, **kw)
+            except dw.DwfmmError as e:
+                log(f"[index] {name} q={q}: {e}")
+                continue
+            for _ in range(2):
+                dw.fmm_matvec(op, x, y)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(5):
+                dw.fmm_matvec(op, x, y)
+            torch.cuda.synchronize()
+            ms = 1e3 * (time.perf_counter() - t0) / 5
+            err = float(torch.linalg.norm(y[rows, 0] - y_exact) / torch.linalg.norm(y_exact))
+            out["results"].append({"set": name, "q": q, "n_x": op.nx, "ms": round(ms, 3), "rel_err": err})
+            log(f"[index] {name} q={q}: n_x {op.nx}, matvec {ms:.2f} ms, relative error {err:.2e}")
+            op.close()
     print(json.dumps(out), flush=True)
 
 
@@ -435,6 +500,11 @@ def main():
     ap.add_argument("--paper-pe", action="store_true",
                     help="prediction error at the paper's best Sec 6.2 parameters (CG solves)")
     ap.add_argument("--pe-max-iter", type=int, default=4000, help="paper-pe: CG iteration limit")
+    ap.add_argument("--index-compare", action="store_true",
+                    help="error and matvec time of the WTDI, TDI and TPI index sets (Sec 6.1)")
+    ap.add_argument("--ic-d", type=int, default=6, help="index-compare: dimension")
+    ap.add_argument("--ic-r", type=float, default=2.0, help="index-compare: b_k = k^-r")
+    ap.add_argument("--ic-kernel", default="matern32", choices=["matern32", "gaussian"])
     ap.add_argument("--ce-n", type=int, default=100_000, help="paper-ce/pe: number of points")
     ap.add_argument("--ce-leaf", type=int, default=128, help="paper-ce: leaf size")
     ap.add_argument("--ce-eta", type=float, default=1.0,
@@ -465,6 +535,9 @@ def main():
         return
     if args.paper_pe:
         bench_paper_pe(args)
+        return
+    if args.index_compare:
+        bench_index_compare(args)
         return
 
     import torch

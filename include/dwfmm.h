@@ -75,6 +75,13 @@ typedef enum { DWFMM_FP64 = 0, DWFMM_FP32 = 1, DWFMM_BF16 = 2 } dwfmm_precision;
  *              largest goes to the lowest candidate index                          */
 typedef enum { DWFMM_NODES_CHEB_LEJA = 0, DWFMM_NODES_AFP = 1 } dwfmm_node_rule;
 
+/* Index set (Sec 4; Sec 6.1):
+ *   WEIGHTED_TOTAL_DEGREE  Lambda = { alpha : sum_k omega_k alpha_k <= q } (default; with
+ *                          omega = 1 through DWFMM_W_EXPLICIT it is the total degree set)
+ *   TENSOR                 { alpha : max_k alpha_k <= q }, the tensor product set; the
+ *                          weights are not used                                      */
+typedef enum { DWFMM_INDEX_WEIGHTED_TOTAL_DEGREE = 0, DWFMM_INDEX_TENSOR = 1 } dwfmm_index_rule;
+
 typedef struct {
     int32_t weight_rule;     /* dwfmm_weight_rule, default R1 */
     const double *omega;     /* host, length d, only for DWFMM_W_EXPLICIT */
@@ -91,6 +98,7 @@ typedef struct {
      * call).  It must not call into the library for this operator. */
     void (*progress)(void *ctx, int32_t iteration, int32_t nrhs, const double *rel_res);
     void *progress_ctx;
+    int32_t index_rule;      /* dwfmm_index_rule, default WEIGHTED_TOTAL_DEGREE */
 } dwfmm_opts;
 
 /* Per right-hand-side result of dwfmm_fmm_solve. */

@@ -62,7 +62,7 @@ def lib():
                                  C.c_double, C.c_int, dp]
         L.orc_create_ex.restype = C.c_void_p
         L.orc_create_ex.argtypes = [dp, C.c_long, C.c_int, dp, C.c_int, C.c_double, C.c_int, C.c_double,
-                                    C.c_double, C.c_int, dp, C.c_int, C.c_long]
+                                    C.c_double, C.c_int, dp, C.c_int, C.c_long, C.c_int]
         L.orc_radical_inverse.restype = C.c_double
         L.orc_radical_inverse.argtypes = [C.c_long, C.c_int]
         L.orc_halton_candidates.restype = None
@@ -186,14 +186,14 @@ class Plan:
 
     def __init__(self, points, dim_weights, leaf_size: int, eta: float, kernel: str, ell: float,
                  q: float, weight_rule: int = W_R1, weight_aux=None, node_rule: int = NODES_CHEB_LEJA,
-                 n_candidates: int = 0):
+                 n_candidates: int = 0, tensor_set: bool = False):
         pts = _f64(points)
         self.n, self.d = pts.shape
         b = _f64(dim_weights)
         aux = None if weight_aux is None else _f64(weight_aux)
         h = lib().orc_create_ex(_dp(pts), self.n, self.d, _dp(b), int(leaf_size), float(eta),
                                 KERNELS[kernel], float(ell), float(q), int(weight_rule), _dp(aux),
-                                int(node_rule), int(n_candidates))
+                                int(node_rule), int(n_candidates), int(bool(tensor_set)))
         if not h:
             raise ValueError("oracle: invalid arguments")
         self._h = h

@@ -607,19 +607,20 @@ void orc_destroy(orc_plan *P)
 /* Build everything the matvec needs.  points: n*d row-major, original order. */
 orc_plan *orc_create_ex(const double *points, long n, int d, const double *b, int leaf, double eta,
                         int kind, double ell, double q, int weight_rule, const double *weight_aux,
-                        int node_rule, long n_candidates);
+                        int node_rule, long n_candidates, int index_rule);
 
 orc_plan *orc_create(const double *points, long n, int d, const double *b, int leaf, double eta,
                      int kind, double ell, double q, int weight_rule, const double *weight_aux)
 {
-    return orc_create_ex(points, n, d, b, leaf, eta, kind, ell, q, weight_rule, weight_aux, 0, 0);
+    return orc_create_ex(points, n, d, b, leaf, eta, kind, ell, q, weight_rule, weight_aux, 0, 0, 0);
 }
 
 /* node_rule 0: per-axis Chebyshev-Leja nodes; 1: approximate Fekete points from
- * n_candidates Halton candidates (0 = the default count). */
+ * n_candidates Halton candidates (0 = the default count).  index_rule 0: weighted
+ * total degree set; 1: the tensor set max_k alpha_k <= q (Sec 6.1, TPI). */
 orc_plan *orc_create_ex(const double *points, long n, int d, const double *b, int leaf, double eta,
                         int kind, double ell, double q, int weight_rule, const double *weight_aux,
-                        int node_rule, long n_candidates)
+                        int node_rule, long n_candidates, int index_rule)
 {
     if (n < 1 || d < 1 || d > ORC_MAXD || leaf < 1 || !(eta > 0)) return NULL;
     orc_plan *P = (orc_plan *)calloc(1, sizeof(orc_plan));
@@ -627,10 +628,10 @@ orc_plan *orc_create_ex(const double *points, long n, int d, const double *b, in
     P->X = (double *)malloc(sizeof(double) * (size_t)n * d);
     memcpy(P->X, points, sizeof(double) * (size_t)n * d);
     if (orc_weights(weight_rule, d, b, eta, weight_aux, P->omega) != 0) { orc_destroy(P); return NULL; }
-    long nx = orc_index_set(d, P->omega, q, 0, NULL, 0);
+    long nx = orc_index_set(d, P->omega, q, index_rule, NULL, 0);
     P->nx = (int)nx;
     P->alpha = (unsigned char *)malloc((size_t)nx * d);
-    orc_index_set(d, P->omega, q, 0, P->alpha, nx);
+    orc_index_set(d, P->omega, q, index_rule, P->alpha, nx);
     for (int k = 0; k < d; ++k) {
         P->mk[k] = 0;
         for (long a = 0; a < nx; ++a)

@@ -320,6 +320,7 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     if (o.precision < 0 || o.precision > 2) return fail(DWFMM_E_INVALID, "unknown precision");
     if (o.node_rule < 0 || o.node_rule > 1 || o.afp_candidates < 0)
         return fail(DWFMM_E_INVALID, "unknown node rule or negative candidate count");
+    if (o.index_rule < 0 || o.index_rule > 1) return fail(DWFMM_E_INVALID, "unknown index rule");
     const HostTree &H = tree->H;
     hipStream_t st = (hipStream_t)stream;
 
@@ -328,7 +329,7 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     std::string err;
     std::vector<double> omega(H.d);
     if (!compute_weights(o.weight_rule, H.d, H.b.data(), H.eta, o.omega, omega.data(), err) ||
-        !build_basis(H.d, omega.data(), q, op->B, err, o.node_rule, o.afp_candidates)) {
+        !build_basis(H.d, omega.data(), q, op->B, err, o.node_rule, o.afp_candidates, o.index_rule)) {
         delete op;
         return fail(DWFMM_E_INVALID, err);
     }

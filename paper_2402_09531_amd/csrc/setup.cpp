@@ -232,7 +232,7 @@ static bool afp_nodes(HostBasis &B, int64_t M, std::string &err)
 }
 
 bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string &err, int node_rule,
-                 int64_t n_cand)
+                 int64_t n_cand, int index_rule)
 {
     B = HostBasis();
     B.d = d;
@@ -242,9 +242,17 @@ bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string
     std::vector<int> a(d, 0);
     const double slack = 1e-9;
     for (;;) {
-        double used = 0.0;
-        for (int k = 0; k < d; ++k) used += omega[k] * a[k];
-        if (used <= q + slack) {
+        bool inside;
+        if (index_rule == 1) {
+            int top = 0;
+            for (int k = 0; k < d; ++k) top = std::max(top, a[k]);
+            inside = top <= q + slack;
+        } else {
+            double used = 0.0;
+            for (int k = 0; k < d; ++k) used += omega[k] * a[k];
+            inside = used <= q + slack;
+        }
+        if (inside) {
             set.emplace_back(a.begin(), a.end());
             if (set.size() > 4096) {
                 err = "index set larger than 4096 entries";

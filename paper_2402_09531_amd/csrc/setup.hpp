@@ -45,9 +45,10 @@ bool build_tree(const double *pts_host, int64_t n, int d, const double *b, int l
                 std::string &err);
 
 // node_rule 0: per-axis Chebyshev-Leja nodes; 1: approximate Fekete points from n_cand
-// Halton candidates (0 = max(2000, 50 n_x)).
+// Halton candidates (0 = max(2000, 50 n_x)).  index_rule 0: weighted total degree set;
+// 1: tensor set max_k alpha_k <= q.
 bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string &err, int node_rule = 0,
-                 int64_t n_cand = 0);
+                 int64_t n_cand = 0, int index_rule = 0);
 
 bool compute_weights(int rule, int d, const double *b, double eta, const double *explicit_omega, double *omega,
                      std::string &err);

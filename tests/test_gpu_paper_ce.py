@@ -43,7 +43,9 @@ def ce(op, Xd, sigma, J):
         cols.append(Y)
     Kt = torch.cat(cols, 1)
     Jd = torch.from_numpy(J).to(dev)
-    K = torch.exp(-torch.cdist(Xd, Xd[Jd], compute_mode="donot_use_mm_for_euclid_dist") / sigma)
+    Y = Xd[Jd]
+    D = torch.cat([torch.sqrt(((Xd[i:i + 10000, None, :] - Y[None]) ** 2).sum(-1)) for i in range(0, n, 10000)])
+    K = torch.exp(-D / sigma)
     return float(torch.linalg.norm(Kt - K) / torch.linalg.norm(K))
 
 

@@ -321,3 +321,21 @@ def test_solve_progress_callback(orc):
     assert all(it % 4 == 0 for it, _ in seen)
     assert seen[0][1] == pytest.approx(1.0)
     assert seen[-1][1] <= 1e-10 and seen[-1][1] == pytest.approx(info["rel_res_recursive"], rel=1e-12)
+
+
+@pytest.mark.parametrize("d,q,kind,ell", [(3, 3, "matern32", 1.0), (4, 2, "gaussian", 0.5)])
+def test_tensor_index_set_parity(orc, d, q, kind, ell):
+    """Tensor index set (the TPI baseline of Sec 6.1): same multi-indices and nodes as the oracle,
+    matvec within 1e-12."""
+    n = 8000
+    X = W.points(n, d, 2.0, 90 + d)
+    b = W.dim_weights(d, 2.0)
+    x = np.random.default_rng(91).standard_normal((n, 1))
+    P = orc.Plan(X, b, 64, 0.8, kind, ell, q, tensor_set=True)
+    _, op = gpu_op(X, b, 64, 0.8, kind, ell, q, index_set="tensor")
+    assert op.nx == P.nx == (q + 1) ** d
+    Bo, Bg = P.basis(), op.basis()
+    assert np.array_equal(Bo["alpha"], Bg["alpha"]) and np.array_equal(Bo["xi"], Bg["xi"])
+    e = rel(gpu_matvec(op, x), P.matvec(x))
+    say(f"   tensor set d={d} q={q}: n_x {P.nx}, rel err {e:.2e}")
+    assert e <= TOL

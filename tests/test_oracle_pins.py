@@ -359,3 +359,19 @@ def test_cg_reports_not_converged(orc):
     P = orc.Plan(X, W.dim_weights(3, 2.0), 32, 0.8, "matern32", 1.0, 4)
     _, info = P.cg(1e-6, np.sin(X.sum(1)), 1e-12, 2)
     assert info[0]["status"] == 1 and info[0]["iters"] == 2
+
+
+def test_tensor_set_plan_is_the_full_grid(orc):
+    """Tensor index set (Sec 6.1, TPI): (q+1)^d multi-indices, the nodes form the full tensor grid of
+    the per-axis points, and a kernel of degree <= q in each variable is reproduced exactly."""
+    X = W.points(3000, 3, 2.0, 5)
+    P = orc.Plan(X, W.dim_weights(3, 2.0), 64, 0.8, "poly", 4.0, 2, tensor_set=True)
+    assert P.nx == 27 and P.nF > 0
+    B = P.basis()
+    z = PL.cheb_leja(2)
+    grid = {tuple(np.round([z[i], z[j], z[k]], 15)) for i in range(3) for j in range(3) for k in range(3)}
+    assert {tuple(np.round(r, 15)) for r in B["xi"]} == grid
+    x = np.random.default_rng(3).standard_normal(3000)
+    y = P.matvec(x)
+    yd = PL.kernel_matrix("poly", 4.0, X, X) @ x
+    assert np.linalg.norm(y - yd) <= 1e-12 * np.linalg.norm(yd)
