@@ -71,6 +71,16 @@ def lib():
         L.orc_afp_select.argtypes = [C.c_int, C.c_long, up, C.c_long, dp, lp]
         L.orc_afp_candidates.restype = C.c_long
         L.orc_afp_candidates.argtypes = [C.c_long]
+        L.orc_eval_create.restype = C.c_void_p
+        L.orc_eval_create.argtypes = [C.c_void_p, dp, C.c_long]
+        L.orc_eval_destroy.restype = None
+        L.orc_eval_destroy.argtypes = [C.c_void_p]
+        L.orc_eval_apply.restype = None
+        L.orc_eval_apply.argtypes = [C.c_void_p, dp, dp, C.c_int]
+        L.orc_eval_sizes.restype = None
+        L.orc_eval_sizes.argtypes = [C.c_void_p, lp]
+        L.orc_eval_get.restype = None
+        L.orc_eval_get.argtypes = [C.c_void_p, lp, lp, lp, dp, dp, lp, lp, lp, lp]
         L.orc_destroy.restype = None
         L.orc_destroy.argtypes = [C.c_void_p]
         L.orc_matvec_ex.restype = None
@@ -276,3 +286,52 @@ class Plan:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+class Eval:
+    """Evaluation of K~(targets, sources) x at new points: a target tree of the source plan's depth
+    and the level-wise (target, source) block partition with the same admissibility (Secs 5.1,
+    5.2)."""
+
+    def __init__(self, plan: Plan, targets):
+        T = _f64(targets)
+        assert T.ndim == 2 and T.shape[1] == plan.d
+        self.plan = plan          # keeps the source plan alive
+        h = lib().orc_eval_create(plan._h, _dp(T), T.shape[0])
+        if not h:
+            raise ValueError("oracle: invalid evaluation targets")
+        self._h = h
+        s = np.zeros(5, dtype=np.int64)
+        lib().orc_eval_sizes(h, _lp(s))
+        self.m, self.J, self.ncl, self.nF, self.nN = (int(v) for v in s)
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h and lib is not None:
+            lib().orc_eval_destroy(h)
+            self._h = None
+
+    def apply(self, x):
+        x = _f64(x)
+        squeeze = x.ndim == 1
+        if squeeze:
+            x = x[:, None]
+        y = np.zeros((self.m, x.shape[1]))
+        lib().orc_eval_apply(self._h, _dp(x), _dp(y), x.shape[1])
+        return y[:, 0] if squeeze else y
+
+    def lists(self):
+        d = self.plan.d
+        perm = np.zeros(self.m, np.int64)
+        cb = np.zeros(self.ncl, np.int64)
+        ce = np.zeros(self.ncl, np.int64)
+        lo = np.zeros((self.ncl, d))
+        hi = np.zeros((self.ncl, d))
+        Fp = np.zeros(self.ncl + 1, np.int64)
+        Fs = np.zeros(max(self.nF, 1), np.int64)
+        Np = np.zeros(self.ncl + 1, np.int64)
+        Ns = np.zeros(max(self.nN, 1), np.int64)
+        lib().orc_eval_get(self._h, _lp(perm), _lp(cb), _lp(ce), _dp(lo), _dp(hi), _lp(Fp), _lp(Fs), _lp(Np),
+                           _lp(Ns))
+        return dict(perm=perm, begin=cb, end=ce, lo=lo, hi=hi, Fptr=Fp, Fsrc=Fs[:self.nF], Nptr=Np,
+                    Nsrc=Ns[:self.nN])

@@ -484,12 +484,20 @@ static void box_of(orc_plan *P, long c)
 /* Sec 5.1: cardinality balanced clustering, split along the longest edge
  * of the tight bounding box so that both halves hold (nearly) equally
  * many points. */
+static void build_tree_depth(orc_plan *P, int J);
+
 static void build_tree(orc_plan *P)
+{
+    int J = 0;
+    while ((P->n + (1L << J) - 1) / (1L << J) > P->leaf) ++J;
+    build_tree_depth(P, J);
+}
+
+/* The tree of Sec 5.1 with a given depth J (clusters may be empty when n < 2^J). */
+static void build_tree_depth(orc_plan *P, int J)
 {
     long n = P->n;
     int d = P->d;
-    int J = 0;
-    while ((n + (1L << J) - 1) / (1L << J) > P->leaf) ++J;
     P->J = J;
     P->ncl = (1L << (J + 1)) - 1;
     P->perm = (long *)malloc(sizeof(long) * (size_t)n);
@@ -987,4 +995,232 @@ int orc_num_threads(void)
 #else
     return 1;
 #endif
+}
+
+/* ------------------------------------------------------------------ */
+/* Evaluation at new points: y_i = sum_j K~(t_i, x_j) x_j for targets t_i  */
+/* that are not the data sites.  The targets get a tree of the source      */
+/* tree's depth built by the same rules (Sec 5.1); target and source        */
+/* clusters of equal level are paired as in Sec 5.2 with the same           */
+/* admissibility (a block is farfield when admissible and its parent pair   */
+/* is not, nearfield when an inadmissible pair of leaves); farfield blocks  */
+/* are interpolated in both variables exactly as in eq. (LowRankBlock),     */
+/* with the target clusters' own boxes, nodes and transfer matrices.        */
+/* ------------------------------------------------------------------ */
+typedef struct {
+    orc_plan T;              /* target tree: X, n, d, J, ncl, perm, cb, ce, lo, hi, T (transfer) */
+    const orc_plan *S;       /* the source plan */
+    long nF, nN;
+    long *Fptr, *Fsrc, *Nptr, *Nsrc;   /* CSR over target clusters of source clusters */
+} orc_eval;
+
+static int admissible_cross(const orc_plan *A, long a, const orc_plan *B, long b, double eta)
+{
+    int d = A->d;
+    const double *la = A->lo + a * d, *ha = A->hi + a * d, *lb = B->lo + b * d, *hb = B->hi + b * d;
+    double dist2 = 0.0, da2 = 0.0, db2 = 0.0;
+    for (int k = 0; k < d; ++k) {
+        double g1 = lb[k] - ha[k], g2 = la[k] - hb[k];
+        double g = g1 > g2 ? g1 : g2;
+        if (g < 0.0) g = 0.0;
+        dist2 += g * g;
+        da2 += (ha[k] - la[k]) * (ha[k] - la[k]);
+        db2 += (hb[k] - lb[k]) * (hb[k] - lb[k]);
+    }
+    double dm = da2 > db2 ? da2 : db2;
+    return dist2 >= eta * eta * dm;
+}
+
+static void partition_cross(const orc_plan *A, const orc_plan *B, long a, long b, int level, pairlist *F,
+                            pairlist *N)
+{
+    if (A->ce[a] == A->cb[a] || B->ce[b] == B->cb[b]) return;
+    if (admissible_cross(A, a, B, b, B->eta)) { pl_push(F, a, b); return; }
+    if (level < B->J) {
+        for (int i = 1; i <= 2; ++i)
+            for (int j = 1; j <= 2; ++j) partition_cross(A, B, 2 * a + i, 2 * b + j, level + 1, F, N);
+        return;
+    }
+    pl_push(N, a, b);
+}
+
+orc_eval *orc_eval_create(const orc_plan *S, const double *targets, long m)
+{
+    if (!S || m < 1) return NULL;
+    orc_eval *E = (orc_eval *)calloc(1, sizeof(orc_eval));
+    orc_plan *T = &E->T;
+    int d = S->d, nx = S->nx;
+    E->S = S;
+    T->n = m; T->d = d; T->leaf = S->leaf; T->eta = S->eta; T->nx = nx;
+    T->X = (double *)malloc(sizeof(double) * (size_t)m * d);
+    memcpy(T->X, targets, sizeof(double) * (size_t)m * d);
+    build_tree_depth(T, S->J);
+    pairlist F = {0, 0, NULL, NULL}, N = {0, 0, NULL, NULL};
+    partition_cross(T, S, 0, 0, 0, &F, &N);
+    E->nF = F.n;
+    E->nN = N.n;
+    to_csr(T->ncl, &F, &E->Fptr, &E->Fsrc);
+    to_csr(T->ncl, &N, &E->Nptr, &E->Nsrc);
+    free(F.t); free(F.s); free(N.t); free(N.s);
+    /* target transfer matrices T_c = V^-1 M_c, M_c[alpha][alpha'] = p_alpha'(a_par^-1(a_c(xi_alpha))) */
+    T->T = (double *)calloc((size_t)T->ncl * nx * nx, sizeof(double));
+    double *M = (double *)malloc(sizeof(double) * (size_t)nx * nx);
+    double xc[ORC_MAXD], t[ORC_MAXD];
+    for (long c = 1; c < T->ncl; ++c) {
+        long pa = (c - 1) / 2;
+        if (T->ce[c] == T->cb[c]) continue;
+        for (long a = 0; a < nx; ++a) {
+            map_to_box(d, T->lo + c * d, T->hi + c * d, S->xi + a * d, xc);
+            map_from_box(d, T->lo + pa * d, T->hi + pa * d, xc, t);
+            for (long b2 = 0; b2 < nx; ++b2) M[a * nx + b2] = leg_tensor(d, S->alpha + b2 * d, t);
+        }
+        double *Tc = T->T + c * nx * nx;
+        for (long a = 0; a < nx; ++a)
+            for (long b2 = 0; b2 < nx; ++b2) {
+                double sum = 0.0;
+                for (long g = 0; g < nx; ++g) sum += S->Vinv[a * nx + g] * M[g * nx + b2];
+                Tc[a * nx + b2] = sum;
+            }
+    }
+    free(M);
+    return E;
+}
+
+void orc_eval_destroy(orc_eval *E)
+{
+    if (!E) return;
+    orc_plan *T = &E->T;
+    free(T->X); free(T->perm); free(T->cb); free(T->ce); free(T->lo); free(T->hi); free(T->T);
+    free(E->Fptr); free(E->Fsrc); free(E->Nptr); free(E->Nsrc);
+    free(E);
+}
+
+/* y (m x nrhs, target order) = K~(targets, sources) x (n x nrhs, source order) */
+void orc_eval_apply(const orc_eval *E, const double *x, double *y, int nrhs)
+{
+    const orc_plan *S = E->S, *T = &E->T;
+    int d = S->d, nx = S->nx, J = S->J;
+    long m = T->n, L0 = cl_level_first(J);
+    memset(y, 0, sizeof(double) * (size_t)m * nrhs);
+    size_t msz = (size_t)S->ncl * nx * nrhs, lsz = (size_t)T->ncl * nx * nrhs;
+    double *mom = (double *)calloc(msz, sizeof(double));
+    double *loc = (double *)calloc(lsz, sizeof(double));
+    /* source leaf moments mhat = P^T x, upward with T_c^T (Sec 5.2) */
+#pragma omp parallel for schedule(dynamic, 4)
+    for (long c = L0; c < S->ncl; ++c) {
+        double t[ORC_MAXD];
+        for (long i = S->cb[c]; i < S->ce[c]; ++i) {
+            long oi = S->perm[i];
+            map_from_box(d, S->lo + c * d, S->hi + c * d, S->X + oi * d, t);
+            for (int a = 0; a < nx; ++a) {
+                double p = leg_tensor(d, S->alpha + a * d, t);
+                for (int r = 0; r < nrhs; ++r) mom[(c * nx + a) * nrhs + r] += p * x[oi * nrhs + r];
+            }
+        }
+    }
+    for (int j = J - 1; j >= 0; --j) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (long c = cl_level_first(j); c < cl_level_first(j + 1); ++c)
+            for (long ch = 2 * c + 1; ch <= 2 * c + 2; ++ch) {
+                const double *Tc = S->T + ch * nx * nx;
+                for (int b2 = 0; b2 < nx; ++b2)
+                    for (int a = 0; a < nx; ++a)
+                        for (int r = 0; r < nrhs; ++r)
+                            mom[(c * nx + b2) * nrhs + r] += Tc[a * nx + b2] * mom[(ch * nx + a) * nrhs + r];
+            }
+    }
+    /* coupling of target cluster c with its farfield source clusters: C = V^-1 S V^-T */
+#pragma omp parallel
+    {
+        double *Sm = (double *)malloc(sizeof(double) * (size_t)nx * nx);
+        double *W = (double *)malloc(sizeof(double) * (size_t)nx * nx);
+        double *C = (double *)malloc(sizeof(double) * (size_t)nx * nx);
+        double *xa = (double *)malloc(sizeof(double) * (size_t)nx * d);
+        double *xb = (double *)malloc(sizeof(double) * (size_t)nx * d);
+#pragma omp for schedule(dynamic, 1)
+        for (long c = 0; c < T->ncl; ++c) {
+            if (E->Fptr[c] == E->Fptr[c + 1]) continue;
+            for (int a = 0; a < nx; ++a) map_to_box(d, T->lo + c * d, T->hi + c * d, S->xi + a * d, xa + a * d);
+            for (long f = E->Fptr[c]; f < E->Fptr[c + 1]; ++f) {
+                long s = E->Fsrc[f];
+                for (int a = 0; a < nx; ++a) map_to_box(d, S->lo + s * d, S->hi + s * d, S->xi + a * d, xb + a * d);
+                for (int a = 0; a < nx; ++a)
+                    for (int b2 = 0; b2 < nx; ++b2) Sm[a * nx + b2] = orc_kernel(S->kind, S->ell, d, xa + a * d, xb + b2 * d);
+                for (int a = 0; a < nx; ++a)
+                    for (int b2 = 0; b2 < nx; ++b2) {
+                        double sum = 0.0;
+                        for (int g = 0; g < nx; ++g) sum += S->Vinv[a * nx + g] * Sm[g * nx + b2];
+                        W[a * nx + b2] = sum;
+                    }
+                for (int a = 0; a < nx; ++a)
+                    for (int b2 = 0; b2 < nx; ++b2) {
+                        double sum = 0.0;
+                        for (int g = 0; g < nx; ++g) sum += W[a * nx + g] * S->Vinv[b2 * nx + g];
+                        C[a * nx + b2] = sum;
+                    }
+                for (int a = 0; a < nx; ++a)
+                    for (int b2 = 0; b2 < nx; ++b2)
+                        for (int r = 0; r < nrhs; ++r)
+                            loc[(c * nx + a) * nrhs + r] += C[a * nx + b2] * mom[(s * nx + b2) * nrhs + r];
+            }
+        }
+        free(Sm); free(W); free(C); free(xa); free(xb);
+    }
+    /* downward on the target tree: lhat_c += T_c lhat_parent */
+    for (int j = 0; j < J; ++j) {
+#pragma omp parallel for schedule(dynamic, 4)
+        for (long c = cl_level_first(j); c < cl_level_first(j + 1); ++c)
+            for (long ch = 2 * c + 1; ch <= 2 * c + 2; ++ch) {
+                if (T->ce[ch] == T->cb[ch]) continue;
+                const double *Tc = T->T + ch * nx * nx;
+                for (int a = 0; a < nx; ++a)
+                    for (int b2 = 0; b2 < nx; ++b2)
+                        for (int r = 0; r < nrhs; ++r)
+                            loc[(ch * nx + a) * nrhs + r] += Tc[a * nx + b2] * loc[(c * nx + b2) * nrhs + r];
+            }
+    }
+    /* target leaves: y_i += p(a_leaf^-1 t_i)^T lhat_leaf, plus the direct nearfield */
+#pragma omp parallel for schedule(dynamic, 1)
+    for (long c = L0; c < T->ncl; ++c) {
+        double t[ORC_MAXD];
+        for (long i = T->cb[c]; i < T->ce[c]; ++i) {
+            long oi = T->perm[i];
+            map_from_box(d, T->lo + c * d, T->hi + c * d, T->X + oi * d, t);
+            for (int a = 0; a < nx; ++a) {
+                double p = leg_tensor(d, S->alpha + a * d, t);
+                for (int r = 0; r < nrhs; ++r) y[oi * nrhs + r] += p * loc[(c * nx + a) * nrhs + r];
+            }
+            for (long f = E->Nptr[c]; f < E->Nptr[c + 1]; ++f) {
+                long s = E->Nsrc[f];
+                for (long jj = S->cb[s]; jj < S->ce[s]; ++jj) {
+                    long oj = S->perm[jj];
+                    double k = orc_kernel(S->kind, S->ell, d, T->X + oi * d, S->X + oj * d);
+                    for (int r = 0; r < nrhs; ++r) y[oi * nrhs + r] += k * x[oj * nrhs + r];
+                }
+            }
+        }
+    }
+    free(mom);
+    free(loc);
+}
+
+void orc_eval_sizes(const orc_eval *E, long *out)
+{
+    out[0] = E->T.n; out[1] = E->T.J; out[2] = E->T.ncl; out[3] = E->nF; out[4] = E->nN;
+}
+
+void orc_eval_get(const orc_eval *E, long *perm, long *cb, long *ce, double *lo, double *hi, long *Fptr, long *Fsrc,
+                  long *Nptr, long *Nsrc)
+{
+    const orc_plan *T = &E->T;
+    long ncl = T->ncl;
+    if (perm) memcpy(perm, T->perm, sizeof(long) * (size_t)T->n);
+    if (cb) memcpy(cb, T->cb, sizeof(long) * (size_t)ncl);
+    if (ce) memcpy(ce, T->ce, sizeof(long) * (size_t)ncl);
+    if (lo) memcpy(lo, T->lo, sizeof(double) * (size_t)ncl * T->d);
+    if (hi) memcpy(hi, T->hi, sizeof(double) * (size_t)ncl * T->d);
+    if (Fptr) memcpy(Fptr, E->Fptr, sizeof(long) * (size_t)(ncl + 1));
+    if (Fsrc) memcpy(Fsrc, E->Fsrc, sizeof(long) * (size_t)E->nF);
+    if (Nptr) memcpy(Nptr, E->Nptr, sizeof(long) * (size_t)(ncl + 1));
+    if (Nsrc) memcpy(Nsrc, E->Nsrc, sizeof(long) * (size_t)E->nN);
 }
