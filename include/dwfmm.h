@@ -199,6 +199,32 @@ dwfmm_status dwfmm_batch_m2l_shapes(dwfmm_batch batch, int32_t *wpc, double *ms,
 dwfmm_status dwfmm_batch_matvec(dwfmm_batch batch, const double *const *xs, double *const *ys, void *stream);
 void dwfmm_batch_destroy(dwfmm_batch batch);
 
+/* ---- evaluation at new points ------------------------------------------------
+ * y_i = sum_j K~(t_i, x_j) x_j at targets t_i other than the data sites (the
+ * interpolant of a solved alpha at new points).  The targets get a tree of the
+ * source tree's depth built by the same rules (Sec 5.1; clusters may be empty);
+ * target and source clusters of equal level are paired with the same admissibility
+ * (Sec 5.2): farfield blocks are interpolated in both variables with the operator's
+ * index set and nodes on the target clusters' own boxes, nearfield leaf pairs are
+ * summed directly.  With the data sites as targets it is the operator's matvec.
+ *   op       source operator; must outlive the plan; the plan uses the operator's
+ *            charge and moment workspace, so the two must not run concurrently
+ *   targets  device, m x d row-major, copied at creation (1 <= m <= 2^30)
+ * Synchronises `stream`.  Errors: E_INVALID, E_NONFINITE, E_NOMEM, E_HIP.        */
+typedef struct dwfmm_eval_s *dwfmm_eval;
+dwfmm_status dwfmm_eval_create(dwfmm_op op, const double *targets, int64_t m, void *stream, dwfmm_eval *out);
+/* y (device, m x nrhs, target order) = K~(targets, sources) x (device, N x nrhs, caller
+ * order), 1 <= nrhs <= the operator's max_nrhs.  Asynchronous on `stream`. */
+dwfmm_status dwfmm_eval_apply(dwfmm_eval ev, const double *x, double *y, int32_t nrhs, void *stream);
+/* out[0..4] = m, J, clusters, farfield blocks, nearfield blocks. */
+dwfmm_status dwfmm_eval_info(dwfmm_eval ev, int64_t *out);
+/* Host copies of the target tree and the cross lists: perm[m], begin/end[ncl],
+ * lo/hi[ncl*d], Fptr[ncl+1], Fsrc[nF] (source clusters), Nptr[ncl+1], Nsrc[nN]
+ * (source clusters); any pointer may be NULL. */
+dwfmm_status dwfmm_eval_tree_get(dwfmm_eval ev, int64_t *perm, int64_t *begin, int64_t *end, double *lo, double *hi,
+                                 int64_t *Fptr, int64_t *Fsrc, int64_t *Nptr, int64_t *Nsrc);
+void dwfmm_eval_destroy(dwfmm_eval ev);
+
 /* ---- solve server (continuous batching) ------------------------------------
  * Requests solve (K~ + lambda I) alpha = f (eq. (LGS)) by FP64 CG from alpha = 0, one
  * rhs each.  Waiting requests are handed, first come first served, to a pool of host

@@ -68,7 +68,8 @@ EXPORTS = ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fm
            "dwfmm_fmm_solve", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
            "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info",
            "dwfmm_op_basis", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
-           "dwfmm_batch_m2l_shapes", "dwfmm_batch_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
+           "dwfmm_batch_m2l_shapes", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
+           "dwfmm_eval_info", "dwfmm_eval_tree_get", "dwfmm_eval_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
            "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy"]
 
 
@@ -108,6 +109,18 @@ def lib():
         L.dwfmm_batch_m2l_shapes.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
                                              C.POINTER(C.c_int32)]
         L.dwfmm_batch_m2l_shapes.restype = C.c_int
+        L.dwfmm_eval_create.argtypes = [vp, vp, C.c_int64, vp, C.POINTER(vp)]
+        L.dwfmm_eval_create.restype = C.c_int
+        L.dwfmm_eval_apply.argtypes = [vp, vp, vp, C.c_int32, vp]
+        L.dwfmm_eval_apply.restype = C.c_int
+        L.dwfmm_eval_info.argtypes = [vp, C.POINTER(C.c_int64)]
+        L.dwfmm_eval_info.restype = C.c_int
+        i64p = C.POINTER(C.c_int64)
+        f64p = C.POINTER(C.c_double)
+        L.dwfmm_eval_tree_get.argtypes = [vp, i64p, i64p, i64p, f64p, f64p, i64p, i64p, i64p, i64p]
+        L.dwfmm_eval_tree_get.restype = C.c_int
+        L.dwfmm_eval_destroy.argtypes = [vp]
+        L.dwfmm_eval_destroy.restype = None
         L.dwfmm_batch_destroy.argtypes = [vp]
         L.dwfmm_batch_destroy.restype = None
         L.dwfmm_server_create.argtypes = [C.c_size_t, C.c_int32, C.c_int32, vp, C.POINTER(vp)]
@@ -295,6 +308,55 @@ def fmm_solve(op: Op, lam: float, f, alpha, rtol: float, max_iter: int = 10000, 
     if st not in (OK, E_NOT_CONVERGED, E_BREAKDOWN) or (raise_on_error and st != OK):
         _check(st)
     return [i.as_dict() for i in infos]
+
+
+class Eval:
+    """Handle of a dwfmm_eval: K~(targets, sources) x at new points."""
+
+    def __init__(self, handle, op):
+        self._h = handle
+        self.op = op            # the source operator must outlive the plan
+        info = np.zeros(5, dtype=np.int64)
+        _check(lib().dwfmm_eval_info(self._h, _i64(info)))
+        self.m, self.J, self.ncl, self.nF, self.nN = (int(v) for v in info)
+
+    def tree(self):
+        d = self.op.tree.d
+        out = dict(perm=np.zeros(self.m, np.int64), begin=np.zeros(self.ncl, np.int64),
+                   end=np.zeros(self.ncl, np.int64), lo=np.zeros((self.ncl, d)), hi=np.zeros((self.ncl, d)),
+                   Fptr=np.zeros(self.ncl + 1, np.int64), Fsrc=np.zeros(max(self.nF, 1), np.int64),
+                   Nptr=np.zeros(self.ncl + 1, np.int64), Nsrc=np.zeros(max(self.nN, 1), np.int64))
+        _check(lib().dwfmm_eval_tree_get(self._h, *[_i64(out[k]) if out[k].dtype == np.int64 else _f64p(out[k])
+                                                    for k in ("perm", "begin", "end", "lo", "hi", "Fptr", "Fsrc",
+                                                              "Nptr", "Nsrc")]))
+        out["Fsrc"] = out["Fsrc"][:self.nF]
+        out["Nsrc"] = out["Nsrc"][:self.nN]
+        return out
+
+    def close(self):
+        if self._h:
+            lib().dwfmm_eval_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def eval_create(op: Op, targets, stream=None) -> Eval:
+    """dwfmm_eval_create: a plan to evaluate K~(targets, sources) x at the m x d device targets."""
+    h = C.c_void_p()
+    _check(lib().dwfmm_eval_create(op._h, _dev_f64(targets, "targets"), targets.shape[0], _stream(stream),
+                                   C.byref(h)))
+    return Eval(h, op)
+
+
+def eval_apply(ev: Eval, x, y, stream=None):
+    """dwfmm_eval_apply: y (m x nrhs) = K~(targets, sources) x (N x nrhs), device tensors."""
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    _check(lib().dwfmm_eval_apply(ev._h, _dev_f64(x, "x"), _dev_f64(y, "y"), nrhs, _stream(stream)))
 
 
 BATCH_GRAPH = 1

@@ -101,6 +101,10 @@ struct dwfmm_op_s {
     double ir_inner_rtol = 0.0;
     void (*progress)(void *, int32_t, int32_t, const double *) = nullptr;
     void *progress_ctx = nullptr;
+    // basis tables on the device (Legendre slots, their products, V^-1), kept for evaluation plans
+    int32_t *b_lidx = nullptr, *b_la = nullptr, *b_ld = nullptr;
+    double *b_Vinv = nullptr;
+    int b_nnz = 0, b_nleg = 0;
     // CG workspace
     double *r = nullptr, *p = nullptr, *q = nullptr, *partial = nullptr, *scal = nullptr;
     double *ir_r = nullptr, *ir_d = nullptr;  // refinement: outer residual and correction
@@ -451,6 +455,12 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     op->ir_max_outer = o.ir_max_outer;
     op->progress = o.progress;
     op->progress_ctx = o.progress_ctx;
+    op->b_lidx = dlidx;
+    op->b_la = dla;
+    op->b_ld = dld;
+    op->b_Vinv = dVinv;
+    op->b_nnz = nnz_max;
+    op->b_nleg = (int)leg_axis.size();
     op->tree = tree;
     tree->refs++;
     *out = op;
@@ -1477,6 +1487,172 @@ extern "C" dwfmm_status dwfmm_server_result(dwfmm_server s, int64_t id, double *
 extern "C" size_t dwfmm_server_bytes(dwfmm_server s) { return s ? s->held : 0; }
 
 extern "C" void dwfmm_server_destroy(dwfmm_server s) { delete s; }
+
+// ============================================================== evaluation at new points
+struct dwfmm_eval_s {
+    dwfmm_op op = nullptr;  // the source operator (must outlive the plan)
+    HostTree H;             // target tree
+    DevTree D{};
+    DevOp O{};
+    Arena arena;
+    int64_t nF = 0, nN = 0;
+};
+
+extern "C" dwfmm_status dwfmm_eval_create(dwfmm_op op, const double *targets, int64_t m, void *stream,
+                                          dwfmm_eval *out)
+{
+    if (!out) return fail(DWFMM_E_INVALID, "out is NULL");
+    *out = nullptr;
+    if (!op || !targets) return fail(DWFMM_E_INVALID, "op or targets is NULL");
+    if (m < 1 || m > (int64_t)1 << 30) return fail(DWFMM_E_INVALID, "m must be in [1, 2^30]");
+    const dwfmm_tree src = op->tree;
+    const HostTree &Hs = src->H;
+    const int d = Hs.d, dp = src->D.dpad, nx = op->B.nx;
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<double> pts((size_t)m * d);
+    HIP_TRY(hipMemcpyAsync(pts.data(), targets, pts.size() * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    for (double v : pts)
+        if (!std::isfinite(v)) return fail(DWFMM_E_NONFINITE, "targets contain NaN or Inf");
+    dwfmm_eval ev = new (std::nothrow) dwfmm_eval_s();
+    if (!ev) return fail(DWFMM_E_NOMEM, "host allocation failed");
+    ev->op = op;
+    std::string err;
+    // target tree of the source tree's depth, same rules; cross partition with the same admissibility
+    if (!build_tree(pts.data(), m, d, Hs.b.data(), Hs.leaf, Hs.eta, ev->H, err, Hs.J, false)) {
+        delete ev;
+        return fail(DWFMM_E_INVALID, err);
+    }
+    HostTree &H = ev->H;
+    partition_pairs(H, Hs, Hs.eta, H.Fptr, H.Fsrc, H.Nptr, H.Nsrc, H.min_far_level);
+    ev->nF = (int64_t)H.Fsrc.size();
+    ev->nN = (int64_t)H.Nsrc.size();
+    const int32_t lf = (int32_t)(H.nleaf - 1);
+    std::vector<double> Xs((size_t)dp * m, 0.0);
+    for (int64_t i = 0; i < m; ++i)
+        for (int k = 0; k < d; ++k) Xs[(size_t)k * m + i] = pts[(size_t)H.perm[i] * d + k];
+    std::vector<double> clo(H.lo), csc((size_t)H.ncl * d), coff((size_t)H.ncl * d);
+    for (size_t i = 0; i < csc.size(); ++i) {
+        const double w = H.hi[i] - H.lo[i];
+        csc[i] = w > 0 ? 1.0 / w : 0.0;
+        coff[i] = w > 0 ? 0.0 : 0.5;
+    }
+    // nearfield lists per target leaf, naming source leaves leaf-locally
+    std::vector<int32_t> nptr_leaf(H.nleaf + 1), nsrc_local(H.Nsrc.size());
+    for (int64_t l = 0; l <= H.nleaf; ++l) nptr_leaf[l] = H.Nptr[lf + l];
+    for (size_t i = 0; i < H.Nsrc.size(); ++i) nsrc_local[i] = H.Nsrc[i] - lf;
+    int max_leaf = 0;
+    for (int64_t l = 0; l < H.nleaf; ++l) max_leaf = std::max(max_leaf, H.end[lf + l] - H.begin[lf + l]);
+    std::vector<double> nodes, nodes_p((size_t)H.ncl * nx * dp, 0.0), E;
+    box_nodes(H, op->B, nodes);
+    for (int64_t c = 0; c < H.ncl; ++c)
+        for (int a = 0; a < nx; ++a)
+            for (int k = 0; k < d; ++k)
+                nodes_p[((size_t)c * nx + a) * dp + k] = nodes[((size_t)c * nx + a) * d + k];
+    transfer_matrices(H, op->B, E);
+
+    auto up = [&](auto **dst, const auto &v) { return ev->arena.upload(dst, v, st); };
+    hipError_t e = hipSuccess;
+    double *dXs, *dclo, *dcsc, *dcoff, *dnodes, *dE, *dLb, *dL;
+    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs;
+    const size_t R = (size_t)op->max_nrhs;
+    if ((e = up(&dXs, Xs)) != hipSuccess || (e = up(&dperm, H.perm)) != hipSuccess ||
+        (e = up(&dcb, H.begin)) != hipSuccess || (e = up(&dce, H.end)) != hipSuccess ||
+        (e = up(&dFp, H.Fptr)) != hipSuccess || (e = up(&dFs, H.Fsrc)) != hipSuccess ||
+        (e = up(&dNp, nptr_leaf)) != hipSuccess || (e = up(&dNs, nsrc_local)) != hipSuccess ||
+        (e = up(&dclo, clo)) != hipSuccess || (e = up(&dcsc, csc)) != hipSuccess ||
+        (e = up(&dcoff, coff)) != hipSuccess || (e = up(&dnodes, nodes_p)) != hipSuccess ||
+        (e = up(&dE, E)) != hipSuccess ||
+        (e = ev->arena.alloc((void **)&dLb, sizeof(double) * nx * (size_t)m)) != hipSuccess ||
+        (e = ev->arena.alloc((void **)&dL, sizeof(double) * H.ncl * nx * R)) != hipSuccess) {
+        ev->arena.release();
+        delete ev;
+        return fail(e == hipErrorOutOfMemory ? DWFMM_E_NOMEM : DWFMM_E_HIP,
+                    std::string("evaluation setup: ") + hipGetErrorString(e));
+    }
+    DevTree &D = ev->D;
+    D.n = (int)m;
+    D.d = d;
+    D.J = H.J;
+    D.dpad = dp;
+    D.nleaf = (int)H.nleaf;
+    D.ncl = (int)H.ncl;
+    D.leaf_first = lf;
+    D.max_leaf = max_leaf;
+    D.min_far_level = H.min_far_level;
+    D.Xs = dXs;
+    D.perm = dperm;
+    D.cbeg = dcb;
+    D.cend = dce;
+    D.Fptr = dFp;
+    D.Fsrc = dFs;
+    D.Nptr = dNp;
+    D.Nsrc = dNs;
+    DevOp &O = ev->O;
+    O.kind = op->D.kind;
+    O.ell = op->D.ell;
+    O.nx = nx;
+    O.max_nrhs = op->max_nrhs;
+    O.nodes = dnodes;
+    O.E = dE;
+    O.Lb = dLb;
+    O.L = dL;
+    O.nxp = op->D.nxp;
+    if ((e = hipMemsetAsync(dL, 0, sizeof(double) * H.ncl * nx * R, st)) != hipSuccess ||
+        (e = launch_basis(D, nx, dclo, dcsc, dcoff, op->b_lidx, op->b_nnz, op->b_Vinv, op->b_nleg, op->b_la, op->b_ld,
+                          dLb, st)) != hipSuccess ||
+        (e = hipStreamSynchronize(st)) != hipSuccess) {
+        ev->arena.release();
+        delete ev;
+        return fail(DWFMM_E_HIP, std::string("evaluation setup: ") + hipGetErrorString(e));
+    }
+    *out = ev;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_eval_apply(dwfmm_eval ev, const double *x, double *y, int32_t nrhs, void *stream)
+{
+    if (!ev) return fail(DWFMM_E_INVALID, "evaluation plan is NULL");
+    if (!x || !y) return fail(DWFMM_E_INVALID, "x or y is NULL");
+    if (nrhs < 1 || nrhs > ev->op->max_nrhs) return fail(DWFMM_E_INVALID, "nrhs must be in [1, max_nrhs]");
+    HIP_TRY(launch_eval(ev->D, ev->O, ev->op->tree->D, ev->op->D, x, y, nrhs, (hipStream_t)stream));
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_eval_info(dwfmm_eval ev, int64_t *out)
+{
+    if (!ev || !out) return fail(DWFMM_E_INVALID, "NULL argument");
+    out[0] = ev->D.n;
+    out[1] = ev->D.J;
+    out[2] = ev->D.ncl;
+    out[3] = ev->nF;
+    out[4] = ev->nN;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_eval_tree_get(dwfmm_eval ev, int64_t *perm, int64_t *begin, int64_t *end, double *lo,
+                                            double *hi, int64_t *Fptr, int64_t *Fsrc, int64_t *Nptr, int64_t *Nsrc)
+{
+    if (!ev) return fail(DWFMM_E_INVALID, "evaluation plan is NULL");
+    const HostTree &H = ev->H;
+    if (perm) std::copy(H.perm.begin(), H.perm.end(), perm);
+    if (begin) std::copy(H.begin.begin(), H.begin.end(), begin);
+    if (end) std::copy(H.end.begin(), H.end.end(), end);
+    if (lo) std::copy(H.lo.begin(), H.lo.end(), lo);
+    if (hi) std::copy(H.hi.begin(), H.hi.end(), hi);
+    if (Fptr) std::copy(H.Fptr.begin(), H.Fptr.end(), Fptr);
+    if (Fsrc) std::copy(H.Fsrc.begin(), H.Fsrc.end(), Fsrc);
+    if (Nptr) std::copy(H.Nptr.begin(), H.Nptr.end(), Nptr);
+    if (Nsrc) std::copy(H.Nsrc.begin(), H.Nsrc.end(), Nsrc);
+    return DWFMM_OK;
+}
+
+extern "C" void dwfmm_eval_destroy(dwfmm_eval ev)
+{
+    if (!ev) return;
+    ev->arena.release();
+    delete ev;
+}
 
 // ============================================================== sizes and introspection
 extern "C" size_t dwfmm_estimate_bytes(int64_t n, int32_t d, int32_t leaf_size, int32_t n_x, int32_t nrhs)

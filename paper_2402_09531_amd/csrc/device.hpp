@@ -60,6 +60,13 @@ struct KernelTimer {
 hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, double *y, int nrhs, int parts,
                          int precision, hipStream_t stream, const KernelTimer *timer = nullptr);
 
+// Evaluation at new points: y (targets, caller order) = K~(targets, sources) x (sources, caller
+// order).  Tt/Ot: the target tree (cross farfield/nearfield lists naming source clusters and
+// leaves) and the target side (box nodes, transfer matrices, basis at the targets, locals);
+// Ts/Os: the source tree and operator, whose charge and moment workspace it uses.
+hipError_t launch_eval(const DevTree &Tt, const DevOp &Ot, const DevTree &Ts, const DevOp &Os, const double *x,
+                       double *y, int nrhs, hipStream_t stream);
+
 // Lagrange basis cache Lb from the boxes and the index set (setup).
 hipError_t launch_basis(const DevTree &T, int nx, const double *clo, const double *csc, const double *coff,
                         const int32_t *lidx, int nnz_max, const double *Vinv, int nleg, const int32_t *leg_axis,

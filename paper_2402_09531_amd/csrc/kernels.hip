@@ -217,13 +217,15 @@ __global__ __launch_bounds__(64) void m2m_kernel(DevTree T, DevOp O, int first, 
 // General kernel (any kernel kind, n_x <= 128, up to 32 rhs): one workgroup per target
 // cluster, node coordinates of the target and of each farfield source in LDS, the coupling
 // matrix S formed kM2lRows rows at a time and applied to the source moments.
+// Ot/Os: target and source side (the same operator for the matvec; for evaluation at new
+// points the target side holds the target tree's nodes and locals).  T: the target tree,
+// whose Fptr/Fsrc name source clusters.
 template <int KIND>
-__global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first, int nrhs)
+__device__ __forceinline__ void m2l_general_body(const DevTree &T, const DevOp &O, const DevOp &Os, int c, int nrhs)
 {
     __shared__ double tn[kMaxNodeWords];
     __shared__ double sn[kMaxNodeWords];
     __shared__ double S[kM2lRows * kMaxNx];
-    const int c = first + blockIdx.x;
     const int nx = O.nx, dp = T.dpad;
     const int f0 = T.Fptr[c], f1 = T.Fptr[c + 1];
     const double inv_ell = 1.0 / O.ell;
@@ -235,8 +237,8 @@ __global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first,
         for (int q = threadIdx.x; q < nx * dp; q += blockDim.x) tn[q] = O.nodes[(size_t)c * nx * dp + q];
         for (int f = f0; f < f1; ++f) {
             const int s = T.Fsrc[f];
-            const double *m = O.M + (size_t)s * nx * nrhs;
-            for (int q = threadIdx.x; q < nx * dp; q += blockDim.x) sn[q] = O.nodes[(size_t)s * nx * dp + q];
+            const double *m = Os.M + (size_t)s * nx * nrhs;
+            for (int q = threadIdx.x; q < nx * dp; q += blockDim.x) sn[q] = Os.nodes[(size_t)s * nx * dp + q];
             for (int a0 = 0; a0 < nx; a0 += kM2lRows) {
                 const int rows = min(kM2lRows, nx - a0);
                 __syncthreads();  // sn staged / the previous chunk consumed
@@ -275,6 +277,18 @@ __global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first,
         const int p = threadIdx.x + 256 * k;
         if (p < nx * nrhs) O.L[(size_t)c * nx * nrhs + p] = acc[k];
     }
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void m2l_kernel(DevTree T, DevOp O, int first, int nrhs)
+{
+    m2l_general_body<KIND>(T, O, O, first + blockIdx.x, nrhs);
+}
+
+template <int KIND>
+__global__ __launch_bounds__(256) void m2l_cross_kernel(DevTree T, DevOp Ot, DevOp Os, int first, int nrhs)
+{
+    m2l_general_body<KIND>(T, Ot, Os, first + blockIdx.x, nrhs);
 }
 
 // ---------------------------------------------------------------- M2L on MFMA (one rhs)
@@ -414,9 +428,12 @@ __global__ __launch_bounds__(64) void l2l_kernel(DevTree T, DevOp O, int first, 
 // ---------------------------------------------------------------- P2P + L2P + scatter to original order
 constexpr int kP2PThreads = 128;
 
+// T/O: target tree and target side; Ts/xs: source tree and the charges in source tree order
+// (the same tree and O.xt for the matvec).  T's nearfield lists name source leaves.
 template <int KIND, int DP>
-__global__ __launch_bounds__(kP2PThreads) void p2p_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
-                                                          int do_near, int do_far)
+__device__ __forceinline__ void p2p_general_body(const DevTree &T, const DevOp &O, const DevTree &Ts,
+                                                 const double *__restrict__ xs, double *__restrict__ y, int nrhs,
+                                                 int do_near, int do_far)
 {
     // source points staged per pass; fewer for wide points so that LDS stays below 32 KB
     constexpr int SCH = DP <= 32 ? kP2PThreads : kP2PThreads / 2;
@@ -425,7 +442,7 @@ __global__ __launch_bounds__(kP2PThreads) void p2p_kernel(DevTree T, DevOp O, do
     const int l = blockIdx.x, c = T.leaf_first + l;
     const int cb = T.cbeg[c], ce = T.cend[c];
     const double inv_ell = 1.0 / O.ell;
-    const int n = T.n;
+    const int n = T.n, ns_all = Ts.n;
     for (int t0 = cb; t0 < ce; t0 += kP2PThreads) {
         const int i = t0 + (int)threadIdx.x;
         const bool active = i < ce;
@@ -436,15 +453,15 @@ __global__ __launch_bounds__(kP2PThreads) void p2p_kernel(DevTree T, DevOp O, do
             double acc = 0.0;
             if (do_near) {
                 for (int f = T.Nptr[l]; f < T.Nptr[l + 1]; ++f) {
-                    const int s = T.leaf_first + T.Nsrc[f];
-                    const int sb = T.cbeg[s], se = T.cend[s];
+                    const int s = Ts.leaf_first + T.Nsrc[f];
+                    const int sb = Ts.cbeg[s], se = Ts.cend[s];
                     for (int s0 = sb; s0 < se; s0 += SCH) {
                         __syncthreads();
                         const int j = s0 + (int)threadIdx.x;
                         if ((int)threadIdx.x < SCH && j < se) {
 #pragma unroll
-                            for (int k = 0; k < DP; ++k) sx[threadIdx.x * DP + k] = T.Xs[(size_t)k * n + j];
-                            sq[threadIdx.x] = O.xt[(size_t)j * nrhs + r];
+                            for (int k = 0; k < DP; ++k) sx[threadIdx.x * DP + k] = Ts.Xs[(size_t)k * ns_all + j];
+                            sq[threadIdx.x] = xs[(size_t)j * nrhs + r];
                         }
                         __syncthreads();
                         const int m = min(SCH, se - s0);
@@ -476,9 +493,32 @@ __global__ __launch_bounds__(kP2PThreads) void p2p_kernel(DevTree T, DevOp O, do
 }
 
 template <int KIND, int DP>
+__global__ __launch_bounds__(kP2PThreads) void p2p_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
+                                                          int do_near, int do_far)
+{
+    p2p_general_body<KIND, DP>(T, O, T, O.xt, y, nrhs, do_near, do_far);
+}
+
+template <int KIND, int DP>
+__global__ __launch_bounds__(kP2PThreads) void p2p_cross_kernel(DevTree T, DevOp Ot, DevTree Ts,
+                                                                const double *__restrict__ xs, double *__restrict__ y,
+                                                                int nrhs, int do_far)
+{
+    p2p_general_body<KIND, DP>(T, Ot, Ts, xs, y, nrhs, 1, do_far);
+}
+
+template <int KIND, int DP>
 void launch_p2p_t(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
 {
     hipLaunchKernelGGL((p2p_kernel<KIND, DP>), dim3(T.nleaf), dim3(kP2PThreads), 0, st, T, O, y, nrhs, near, far);
+}
+
+template <int KIND, int DP>
+void launch_p2p_cross_t(const DevTree &Tt, const DevOp &Ot, const DevTree &Ts, const double *xs, double *y, int nrhs,
+                        int far, hipStream_t st)
+{
+    hipLaunchKernelGGL((p2p_cross_kernel<KIND, DP>), dim3(Tt.nleaf), dim3(kP2PThreads), 0, st, Tt, Ot, Ts, xs, y,
+                       nrhs, far);
 }
 
 template <int KIND>
@@ -487,6 +527,22 @@ hipError_t launch_p2p_k(const DevTree &T, const DevOp &O, double *y, int nrhs, i
     switch (T.dpad) {
 #define DWFMM_CASE(D) \
     case D: launch_p2p_t<KIND, D>(T, O, y, nrhs, near, far, st); break;
+        DWFMM_CASE(4) DWFMM_CASE(8) DWFMM_CASE(12) DWFMM_CASE(16) DWFMM_CASE(20) DWFMM_CASE(24)
+        DWFMM_CASE(28) DWFMM_CASE(32) DWFMM_CASE(40) DWFMM_CASE(48) DWFMM_CASE(56) DWFMM_CASE(64)
+#undef DWFMM_CASE
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int KIND>
+hipError_t launch_p2p_cross_k(const DevTree &Tt, const DevOp &Ot, const DevTree &Ts, const double *xs, double *y,
+                              int nrhs, int far, hipStream_t st)
+{
+    switch (Tt.dpad) {
+#define DWFMM_CASE(D) \
+    case D: launch_p2p_cross_t<KIND, D>(Tt, Ot, Ts, xs, y, nrhs, far, st); break;
         DWFMM_CASE(4) DWFMM_CASE(8) DWFMM_CASE(12) DWFMM_CASE(16) DWFMM_CASE(20) DWFMM_CASE(24)
         DWFMM_CASE(28) DWFMM_CASE(32) DWFMM_CASE(40) DWFMM_CASE(48) DWFMM_CASE(56) DWFMM_CASE(64)
 #undef DWFMM_CASE
@@ -1918,6 +1974,39 @@ hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t st)
 #endif
 
 #if !defined(DWFMM_KERNELS_PART) || DWFMM_KERNELS_PART == 1
+hipError_t launch_eval(const DevTree &Tt, const DevOp &Ot, const DevTree &Ts, const DevOp &Os, const double *x,
+                       double *y, int nrhs, hipStream_t st)
+{
+    if (Os.nx > kMaxNx || Os.nx * Ts.dpad > kMaxNodeWords || nrhs > 32 || Tt.dpad != Ts.dpad)
+        return hipErrorInvalidValue;
+    const int far = Tt.min_far_level <= Tt.J;
+    // source side: charges into tree order and, if needed, moments up to the first cross-farfield level
+    hipLaunchKernelGGL(p2m_kernel, dim3(Ts.nleaf), dim3(256), sizeof(double) * Ts.max_leaf, st, Ts, Os, x, nrhs, far);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if (far) {
+        for (int j = Ts.J - 1; j >= Tt.min_far_level; --j)
+            hipLaunchKernelGGL(m2m_kernel, dim3(1 << j), dim3(64), 0, st, Ts, Os, (1 << j) - 1, nrhs);
+        const int first = (1 << Tt.min_far_level) - 1;
+        const int cnt = Tt.ncl - first;
+        switch (Os.kind) {
+        case 0: hipLaunchKernelGGL(m2l_cross_kernel<0>, dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first, nrhs); break;
+        case 1: hipLaunchKernelGGL(m2l_cross_kernel<1>, dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first, nrhs); break;
+        case 2: hipLaunchKernelGGL(m2l_cross_kernel<2>, dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first, nrhs); break;
+        default: hipLaunchKernelGGL(m2l_cross_kernel<3>, dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first, nrhs); break;
+        }
+        for (int j = Tt.min_far_level + 1; j <= Tt.J; ++j)
+            hipLaunchKernelGGL(l2l_kernel, dim3(1 << j), dim3(64), 0, st, Tt, Ot, (1 << j) - 1, nrhs);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    switch (Os.kind) {
+    case 0: return launch_p2p_cross_k<0>(Tt, Ot, Ts, Os.xt, y, nrhs, far, st);
+    case 1: return launch_p2p_cross_k<1>(Tt, Ot, Ts, Os.xt, y, nrhs, far, st);
+    case 2: return launch_p2p_cross_k<2>(Tt, Ot, Ts, Os.xt, y, nrhs, far, st);
+    default: return launch_p2p_cross_k<3>(Tt, Ot, Ts, Os.xt, y, nrhs, far, st);
+    }
+}
+
 hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double *partial, double *out,
                       hipStream_t stream)
 {

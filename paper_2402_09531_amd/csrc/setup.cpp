@@ -353,7 +353,7 @@ bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string
 
 // ------------------------------------------------------------------ tree
 bool build_tree(const double *pts, int64_t n, int d, const double *b, int leaf, double eta, HostTree &T,
-                std::string &err)
+                std::string &err, int forced_J, bool with_partition)
 {
     T = HostTree();
     T.n = n;
@@ -362,7 +362,10 @@ bool build_tree(const double *pts, int64_t n, int d, const double *b, int leaf, 
     T.eta = eta;
     T.b.assign(b, b + d);
     int J = 0;
-    while ((n + ((int64_t)1 << J) - 1) >> J > leaf) ++J;
+    if (forced_J >= 0)
+        J = forced_J;
+    else
+        while ((n + ((int64_t)1 << J) - 1) >> J > leaf) ++J;
     if (J > 30) {
         err = "tree too deep";
         return false;
@@ -460,12 +463,22 @@ bool build_tree(const double *pts, int64_t n, int d, const double *b, int leaf, 
             for (auto &th : pool) th.join();
         }
     }
-    // block partition from (root, root)
+    if (with_partition) partition_pairs(T, T, eta, T.Fptr, T.Fsrc, T.Nptr, T.Nsrc, T.min_far_level);
+    else T.min_far_level = J + 1;
+    return true;
+}
+
+// ------------------------------------------------------------------ transfer
+void partition_pairs(const HostTree &A, const HostTree &B, double eta, std::vector<int32_t> &Fptr,
+                     std::vector<int32_t> &Fsrc, std::vector<int32_t> &Nptr, std::vector<int32_t> &Nsrc,
+                     int &min_far_level)
+{
+    const int d = A.d, J = B.J;
     std::vector<std::pair<int32_t, int32_t>> far, near;
     const double eta2 = eta * eta;
     auto admissible = [&](int64_t u, int64_t v) {
-        const double *lu = &T.lo[(size_t)u * d], *hu = &T.hi[(size_t)u * d];
-        const double *lv = &T.lo[(size_t)v * d], *hv = &T.hi[(size_t)v * d];
+        const double *lu = &A.lo[(size_t)u * d], *hu = &A.hi[(size_t)u * d];
+        const double *lv = &B.lo[(size_t)v * d], *hv = &B.hi[(size_t)v * d];
         double dist2 = 0.0, du = 0.0, dv = 0.0;
         for (int k = 0; k < d; ++k) {
             double gap = std::max(std::max(lv[k] - hu[k], lu[k] - hv[k]), 0.0);
@@ -480,7 +493,7 @@ bool build_tree(const double *pts, int64_t n, int d, const double *b, int leaf, 
     while (!stack.empty()) {
         Item it = stack.back();
         stack.pop_back();
-        if (T.end[it.u] == T.begin[it.u] || T.end[it.v] == T.begin[it.v]) continue;
+        if (A.end[it.u] == A.begin[it.u] || B.end[it.v] == B.begin[it.v]) continue;
         if (admissible(it.u, it.v)) {
             far.push_back({it.u, it.v});
         } else if (it.lev < J) {
@@ -497,24 +510,22 @@ bool build_tree(const double *pts, int64_t n, int d, const double *b, int leaf, 
                          [](const std::pair<int32_t, int32_t> &x, const std::pair<int32_t, int32_t> &y) {
                              return x.first < y.first || (x.first == y.first && x.second < y.second);
                          });
-        ptr.assign(T.ncl + 1, 0);
+        ptr.assign(A.ncl + 1, 0);
         src.resize(pairs.size());
         for (auto &p : pairs) ptr[p.first + 1]++;
-        for (int64_t c = 0; c < T.ncl; ++c) ptr[c + 1] += ptr[c];
+        for (int64_t c = 0; c < A.ncl; ++c) ptr[c + 1] += ptr[c];
         for (size_t i = 0; i < pairs.size(); ++i) src[i] = pairs[i].second;
     };
-    csr(far, T.Fptr, T.Fsrc);
-    csr(near, T.Nptr, T.Nsrc);
-    T.min_far_level = J + 1;
+    csr(far, Fptr, Fsrc);
+    csr(near, Nptr, Nsrc);
+    min_far_level = J + 1;
     for (auto &p : far) {
         int lev = 0;
         while ((((int64_t)1 << (lev + 1)) - 1) <= p.first) ++lev;
-        T.min_far_level = std::min(T.min_far_level, lev);
+        min_far_level = std::min(min_far_level, lev);
     }
-    return true;
 }
 
-// ------------------------------------------------------------------ transfer
 static void ref_coords(const double *lo, const double *hi, const double *x, int d, double *t)
 {
     for (int k = 0; k < d; ++k) t[k] = hi[k] > lo[k] ? (x[k] - lo[k]) / (hi[k] - lo[k]) : 0.5;

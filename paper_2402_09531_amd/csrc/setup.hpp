@@ -41,8 +41,18 @@ struct HostBasis {
     int nleg = 0;                        // sum over active axes of (mk + 1)
 };
 
+// forced_J >= 0 builds a tree of that depth (clusters may be empty); with_partition = false
+// skips the block partition (Fptr/Fsrc/Nptr/Nsrc stay empty).
 bool build_tree(const double *pts_host, int64_t n, int d, const double *b, int leaf, double eta, HostTree &T,
-                std::string &err);
+                std::string &err, int forced_J = -1, bool with_partition = true);
+
+// Level-wise block partition of (target cluster, source cluster) pairs of two trees of equal
+// depth with the admissibility of Sec 5.2: CSR over target clusters of source clusters;
+// nearfield entries are leaf pairs.  min_far_level: first level with a farfield block (J+1 if
+// none).  With A = B it is the square partition of build_tree.
+void partition_pairs(const HostTree &A, const HostTree &B, double eta, std::vector<int32_t> &Fptr,
+                     std::vector<int32_t> &Fsrc, std::vector<int32_t> &Nptr, std::vector<int32_t> &Nsrc,
+                     int &min_far_level);
 
 // node_rule 0: per-axis Chebyshev-Leja nodes; 1: approximate Fekete points from n_cand
 // Halton candidates (0 = max(2000, 50 n_x)).  index_rule 0: weighted total degree set;
