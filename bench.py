@@ -480,6 +480,50 @@ def bench_index_compare(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_eval(args):
+    """Evaluation at new points with the headline operator (N = 1e6, d = 20, b_k = k^-3, Gaussian
+    l = 0.5, q = 6, leaf 128, eta 0.8): args.eval targets drawn from the same distribution, FP64.
+    Reports the time per evaluation, targets/s and the relative error against direct kernel sums at
+    1000 sampled targets."""
+    import torch
+    import paper_2402_09531_amd as dw
+    from paper_2402_09531_amd import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.WORKLOADS["n1m_d20"]
+    X, b, x = W.make(w)
+    m = args.eval
+    T = W.points(m, w.d, w.r, 9100)
+    Xd = torch.from_numpy(X).to(dev)
+    Td = torch.from_numpy(T).to(dev)
+    xd = torch.from_numpy(x).to(dev)
+    tree = dw.build_tree(Xd, b, w.leaf, w.eta)
+    op = dw.fmm_create(tree, w.kernel, w.ell, w.q)
+    t0 = time.perf_counter()
+    ev = dw.eval_create(op, Td)
+    t_setup = time.perf_counter() - t0
+    y = torch.empty((m, 1), dtype=torch.float64, device=dev)
+    for _ in range(args.warmup):
+        dw.eval_apply(ev, xd, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        dw.eval_apply(ev, xd, y)
+    torch.cuda.synchronize()
+    t = (time.perf_counter() - t0) / args.steps
+    rows = torch.from_numpy(np.random.default_rng(9101).choice(m, 1000, replace=False)).to(dev)
+    D = pairwise_dist(Td[rows], Xd)
+    y_exact = torch.exp(-D * D / w.ell) @ xd[:, 0]
+    err = float(torch.linalg.norm(y[rows, 0] - y_exact) / torch.linalg.norm(y_exact))
+    out = {"metric": "FMM evaluation at new points", "value": round(m / t / 1e6, 3), "unit": "Mtargets/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * t, 3),
+           "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"n1m_d20 operator, {m} targets from the same distribution", "targets": m,
+                      "far_blocks": ev.nF, "near_blocks": ev.nN},
+           "setup_s": round(t_setup, 3), "rel_err_vs_direct_1000_targets": err}
+    log(f"[eval] {m} targets: {1e3 * t:.2f} ms per evaluation, setup {t_setup:.2f} s, error {err:.2e}")
+    print(json.dumps(out), flush=True)
+
+
 def main():
     if len(sys.argv) == 3 and sys.argv[1] == "--summarize":
         summarize_profile(sys.argv[2])
@@ -502,6 +546,7 @@ def main():
     ap.add_argument("--pe-max-iter", type=int, default=4000, help="paper-pe: CG iteration limit")
     ap.add_argument("--index-compare", action="store_true",
                     help="error and matvec time of the WTDI, TDI and TPI index sets (Sec 6.1)")
+    ap.add_argument("--eval", type=int, default=0, help="evaluation at this many new points (headline operator)")
     ap.add_argument("--ic-d", type=int, default=6, help="index-compare: dimension")
     ap.add_argument("--ic-r", type=float, default=2.0, help="index-compare: b_k = k^-r")
     ap.add_argument("--ic-kernel", default="matern32", choices=["matern32", "gaussian"])
@@ -538,6 +583,9 @@ def main():
         return
     if args.index_compare:
         bench_index_compare(args)
+        return
+    if args.eval:
+        bench_eval(args)
         return
 
     import torch
