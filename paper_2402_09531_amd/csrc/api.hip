@@ -113,8 +113,12 @@ struct dwfmm_op_s {
     bool timing = false;
     std::vector<KernelTimer> timers;
     size_t timers_used = 0;
+    StreamFork fork;  // farfield beside the one-rhs nearfield
     ~dwfmm_op_s()
     {
+        if (fork.forked) (void)hipEventDestroy(fork.forked);
+        if (fork.joined) (void)hipEventDestroy(fork.joined);
+        if (fork.side) (void)hipStreamDestroy(fork.side);
         for (auto &t : timers) {
             (void)hipEventDestroy(t.p2p_start);
             (void)hipEventDestroy(t.p2p_stop);
@@ -461,6 +465,13 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     op->b_Vinv = dVinv;
     op->b_nnz = nnz_max;
     op->b_nleg = (int)leg_axis.size();
+    if ((e = hipStreamCreateWithFlags(&op->fork.side, hipStreamNonBlocking)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&op->fork.forked, hipEventDisableTiming)) != hipSuccess ||
+        (e = hipEventCreateWithFlags(&op->fork.joined, hipEventDisableTiming)) != hipSuccess) {
+        op->arena.release();
+        delete op;
+        return fail(DWFMM_E_HIP, std::string("operator streams: ") + hipGetErrorString(e));
+    }
     op->tree = tree;
     tree->refs++;
     *out = op;
@@ -498,7 +509,7 @@ extern "C" dwfmm_status dwfmm_fmm_matvec_parts(dwfmm_op op, const double *x, dou
         }
         tm = &op->timers[op->timers_used++];
     }
-    HIP_TRY(launch_matvec(op->tree->D, op->D, x, y, nrhs, parts, precision, (hipStream_t)stream, tm));
+    HIP_TRY(launch_matvec(op->tree->D, op->D, x, y, nrhs, parts, precision, (hipStream_t)stream, tm, &op->fork));
     return DWFMM_OK;
 }
 
@@ -627,7 +638,7 @@ hipError_t cg_run(dwfmm_op op, double lambda, const double *b, double *x, int nr
     int32_t *state = op->state;
     hipError_t e;
     auto matvecA = [&](const double *v, double *out) -> hipError_t {
-        hipError_t e2 = launch_matvec(T, op->D, v, out, nrhs, 3, precision, st);
+        hipError_t e2 = launch_matvec(T, op->D, v, out, nrhs, 3, precision, st, nullptr, &op->fork);
         if (e2 != hipSuccess) return e2;
         if (lambda != 0.0) hipLaunchKernelGGL(ridge_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, v, lambda, total);
         return hipGetLastError();
@@ -690,7 +701,7 @@ hipError_t residual64(dwfmm_op op, double lambda, const double *f, const double 
 {
     const DevTree &T = op->tree->D;
     const size_t total = (size_t)T.n * nrhs;
-    hipError_t e = launch_matvec(T, op->D, v, out, nrhs, 3, DWFMM_FP64, st);
+    hipError_t e = launch_matvec(T, op->D, v, out, nrhs, 3, DWFMM_FP64, st, nullptr, &op->fork);
     if (e != hipSuccess) return e;
     if (lambda != 0.0) hipLaunchKernelGGL(ridge_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, v, lambda, total);
     hipLaunchKernelGGL(sub_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, f, out, total);

@@ -56,9 +56,18 @@ struct KernelTimer {
     hipEvent_t p2p_start = nullptr, p2p_stop = nullptr, m2l_start = nullptr, m2l_stop = nullptr;
 };
 
-// One matvec (or parts of it) on `stream`.  parts: bit0 nearfield, bit1 farfield.
+// A second stream and two events with which the farfield (M2M, M2L, L2L) of a one-rhs matvec
+// runs beside the symmetric nearfield: forked after P2M, joined before the combine.
+struct StreamFork {
+    hipStream_t side = nullptr;
+    hipEvent_t forked = nullptr, joined = nullptr;
+};
+
+// One matvec (or parts of it) on `stream` (with `fork`, partly on its side stream; the result
+// is ordered on `stream` as without it).  parts: bit0 nearfield, bit1 farfield.
 hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, double *y, int nrhs, int parts,
-                         int precision, hipStream_t stream, const KernelTimer *timer = nullptr);
+                         int precision, hipStream_t stream, const KernelTimer *timer = nullptr,
+                         const StreamFork *fork = nullptr);
 
 // Evaluation at new points: y (targets, caller order) = K~(targets, sources) x (sources, caller
 // order).  Tt/Ot: the target tree (cross farfield/nearfield lists naming source clusters and

@@ -558,13 +558,17 @@ hipError_t launch_p2p_cross_k(const DevTree &Tt, const DevOp &Ot, const DevTree 
 // MFMA 16x16x4 tiles (coordinates shifted to the owner leaf's box midpoint), the
 // kernel value on the vector ALU.  Row sums K q_s stay in registers; column sums
 // K^T q_t go to colbuf[block] and are added by the partner leaf in the combine
-// pass, in a fixed order (no atomics, bitwise reproducible).
+// pass, in a fixed order (no atomics, bitwise reproducible).  After the diagonal block
+// the owner's other blocks are swept as one concatenated stream of source points, so a
+// 16-wide column tile may hold the end of one block and the start of the next and only
+// the stream's last tile carries padding.
 // Lane layout of v_mfma_f64_16x16x4f64: A[i][k] in lane i + 16k, B[k][j] in lane
 // j + 16k, D[i][j] in lane j + 16(i%4), element i/4 (checked with a probe).
 constexpr int kSymLeaf = 128;
 // Internal kernel variant of the symmetric FP64 nearfield: the Gaussian evaluated as
 // exp(-|x-c|^2/ell) exp(-|y-c|^2/ell) exp(2 (x-c).(y-c)/ell) (operators with gauss_split set).
 constexpr int kGaussSplit = 4;
+constexpr int kSymSeg = 256;  // owned blocks per column-stream segment (= threads per workgroup)
 
 // One leaf block, all 16x16 tiles of this wave's two row tiles.  DIAG: the block of a
 // leaf with itself (i == j forced to distance 0, no column sums).
@@ -634,6 +638,9 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
     __shared__ double sN[kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf], tQ[kSymLeaf];
     __shared__ double colpart[4 * kSymLeaf];
     __shared__ double cen[DK];
+    __shared__ int32_t sPre[kSymSeg + 1], sBlk[kSymSeg];  // owned-block segment: size prefix, block ids
+    __shared__ int32_t colF[kSymLeaf], colJ[kSymLeaf];    // block and point of each stream column
+    __shared__ int32_t sDiag;                             // the leaf owns its self block
 
     const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
@@ -647,7 +654,13 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
     // Coordinate rows k in [d, DK) are stored as zeros and cen[k] = 0 there, so every load
     // below is unconditional; point indices past the end of a leaf are clamped and masked.
     if (tid < DK) cen[tid] = T.center[(size_t)l * DK + tid];
+    if (tid == 0) sDiag = 0;
     __syncthreads();
+    // The self block is listed only when the leaf is not admissible with itself (a leaf whose
+    // points all coincide has a zero-size box and takes its self block in the farfield).
+    const int o0 = T.own_ptr[l], o1 = T.own_ptr[l + 1];
+    for (int f = o0 + tid; f < o1; f += blockDim.x)
+        if (T.own_src[f] == l) sDiag = 1;
     if (tid < kSymLeaf) {
         const bool ok = tid < nt;
         const int ii = cb + (ok ? tid : nt - 1);
@@ -697,51 +710,94 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
             racc[u][v] = 0.0;
         }
 
-    const int o0 = T.own_ptr[l], o1 = T.own_ptr[l + 1];
-    for (int f = o0; f < o1; ++f) {
-        const int sl = T.own_src[f];
-        const bool diag = sl == l;
-        const int sc = T.leaf_first + sl;
-        const int sb = T.cbeg[sc], ns = T.cend[sc] - sb;
+    // Column j of the tile arrays: point pidx shifted to the owner's midpoint, its squared norm
+    // (split Gaussian: its column factor) and its charge; columns past the data are zero.
+    auto stage = [&](int j, int pidx, bool ok) {
+        double xv[DK];
+#pragma unroll
+        for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + pidx];
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+            const double v = ok ? xv[k] - cen[k] : 0.0;
+            sX[k * kSymLeaf + j] = v;
+            s = fma(v, v, s);
+        }
+        const double q = O.xt[pidx];
+        if constexpr (KIND == kGaussSplit) {
+            const double bfac = exp_bounded(-s * inv_ell);  // column factor
+            sN[j] = bfac;
+            sQ[j] = ok ? q * bfac : 0.0;
+        } else {
+            sN[j] = s;
+            sQ[j] = ok ? q : 0.0;
+        }
+    };
+    // 1) the leaf with itself (sDiag was set before the barrier that precedes rN)
+    if (sDiag) {
         __syncthreads();
-        if (tid < kSymLeaf) {
-            const int j = tid;
-            const bool ok = j < ns;  // every listed leaf holds at least one point
-            const int jj = sb + (ok ? j : ns - 1);
-            double xv[DK];
-#pragma unroll
-            for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + jj];
-            double s = 0.0;
-#pragma unroll
-            for (int k = 0; k < DK; ++k) {
-                const double v = ok ? xv[k] - cen[k] : 0.0;
-                sX[k * kSymLeaf + j] = v;
-                s = fma(v, v, s);
+        if (tid < kSymLeaf) stage(tid, cb + (tid < nt ? tid : nt - 1), tid < nt);
+        __syncthreads();
+        sym_block<KIND, NKC, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, nt, ntiles, w, li, lg, inv_ell);
+    }
+    // 2) the other owned blocks as one stream of source points, kSymLeaf columns at a time: a
+    //    16-wide column tile may span two source leaves, so only the stream's last tile is padded.
+    //    Owned blocks are taken kSymSeg at a time; sPre holds the prefix sums of their sizes.
+    for (int fb = o0; fb < o1; fb += kSymSeg) {
+        const int fe = min(fb + kSymSeg, o1);
+        __syncthreads();  // the previous segment's table is no longer read
+        {
+            int sz = 0;
+            const int f = fb + tid;
+            if (f < fe) {
+                const int sl = T.own_src[f];
+                if (sl != l) sz = T.cend[T.leaf_first + sl] - T.cbeg[T.leaf_first + sl];
             }
-            if constexpr (KIND == kGaussSplit) {
-                const double bfac = exp_bounded(-s * inv_ell);  // column factor
-                sN[j] = bfac;
-                sQ[j] = ok ? O.xt[jj] * bfac : 0.0;
-            } else {
-                sN[j] = s;
-            }
-        } else if constexpr (KIND != kGaussSplit) {
-            const int j = tid - kSymLeaf;
-            const double q = O.xt[sb + (j < ns ? j : ns - 1)];
-            sQ[j] = j < ns ? q : 0.0;
+            sPre[tid + 1] = sz;
+            sBlk[tid] = f;
+            if (tid == 0) sPre[0] = 0;
         }
         __syncthreads();
-        if (diag)
-            sym_block<KIND, NKC, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
-        else
+        for (int off = 1; off < kSymSeg; off <<= 1) {  // inclusive scan of sPre[1..kSymSeg]
+            const int add = tid >= off ? sPre[tid + 1 - off] : 0;
+            __syncthreads();
+            sPre[tid + 1] += add;
+            __syncthreads();
+        }
+        const int total = sPre[kSymSeg];
+        for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+            const int ns = min(kSymLeaf, total - c0);
+            __syncthreads();  // the previous chunk's tiles and column sums are consumed
+            if (tid < kSymLeaf) {
+                const int j = tid;
+                const bool ok = j < ns;
+                int pidx = cb, fblk = 0, jl = 0;
+                if (ok) {
+                    // the block holding stream column c0 + j: the largest k with sPre[k] <= c0 + j
+                    // (it has a positive size, since sPre[k + 1] > c0 + j)
+                    const int col = c0 + j;
+                    int lo = 0, hi = kSymSeg;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (sPre[mid] <= col) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    fblk = sBlk[lo];
+                    jl = col - sPre[lo];
+                    pidx = T.cbeg[T.leaf_first + T.own_src[fblk]] + jl;
+                }
+                stage(j, pidx, ok);
+                colF[j] = fblk;
+                colJ[j] = jl;
+            }
+            __syncthreads();
             sym_block<KIND, NKC, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
-        if (!diag) {
             __syncthreads();
             if (tid < ns) {
                 double cs = ((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) +
                             colpart[3 * kSymLeaf + tid];
                 if constexpr (KIND == kGaussSplit) cs *= sN[tid];
-                O.colbuf[(size_t)f * kSymLeaf + tid] = cs;
+                O.colbuf[(size_t)colF[tid] * kSymLeaf + colJ[tid]] = cs;
             }
         }
     }
@@ -1073,6 +1129,9 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
     __shared__ float sN[kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf], tQ[kSymLeaf];
     __shared__ float colpart[4 * kSymLeaf];
     __shared__ double cen[DK];
+    __shared__ int32_t sPre[kSymSeg + 1], sBlk[kSymSeg];
+    __shared__ int32_t colF[kSymLeaf], colJ[kSymLeaf];
+    __shared__ int32_t sDiag;
     const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
     if (nt == 0) return;
@@ -1082,7 +1141,11 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
     const float inv_ell = (float)(1.0 / O.ell);
     const int ntiles = (nt + 15) / 16;
     if (tid < DK) cen[tid] = T.center[(size_t)l * DK + tid];
+    if (tid == 0) sDiag = 0;
     __syncthreads();
+    const int o0 = T.own_ptr[l], o1 = T.own_ptr[l + 1];
+    for (int f = o0 + tid; f < o1; f += blockDim.x)  // is the self block listed (as in FP64)
+        if (T.own_src[f] == l) sDiag = 1;
     if (tid < kSymLeaf) {
         const bool ok = tid < nt;
         const int ii = cb + (ok ? tid : nt - 1);
@@ -1127,51 +1190,89 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
             rQ[u][v] = tQ[i];
             racc[u][v] = 0.0f;
         }
-    const int o0 = T.own_ptr[l], o1 = T.own_ptr[l + 1];
-    for (int f = o0; f < o1; ++f) {
-        const int sl = T.own_src[f];
-        const bool diag = sl == l;
-        const int sc = T.leaf_first + sl;
-        const int sb = T.cbeg[sc], ns = T.cend[sc] - sb;
+    // Tile column j: point pidx shifted to the owner's midpoint, its squared norm (split
+    // Gaussian: its column factor) and its charge; columns past the data are zero.
+    auto stage = [&](int j, int pidx, bool ok) {
+        double xv[DK];
+#pragma unroll
+        for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + pidx];
+        float s = 0.0f;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+            const float v = ok ? (float)(xv[k] - cen[k]) : 0.0f;
+            sX[k * kSymLeaf + j] = v;
+            s = fmaf(v, v, s);
+        }
+        const float q = (float)O.xt[pidx];
+        if constexpr (KIND == kGaussSplit) {
+            const float bfac = __builtin_amdgcn_exp2f(s * (inv_ell * -1.4426950408889634f));  // column factor
+            sN[j] = bfac;
+            sQ[j] = ok ? q * bfac : 0.0f;
+        } else {
+            sN[j] = s;
+            sQ[j] = ok ? q : 0.0f;
+        }
+    };
+    // the leaf with itself when listed, then the other owned blocks as one column stream (as in FP64)
+    if (sDiag) {
         __syncthreads();
-        if (tid < kSymLeaf) {
-            const int j = tid;
-            const bool ok = j < ns;
-            const int jj = sb + (ok ? j : ns - 1);
-            double xv[DK];
-#pragma unroll
-            for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + jj];
-            float s = 0.0f;
-#pragma unroll
-            for (int k = 0; k < DK; ++k) {
-                const float v = ok ? (float)(xv[k] - cen[k]) : 0.0f;
-                sX[k * kSymLeaf + j] = v;
-                s = fmaf(v, v, s);
+        if (tid < kSymLeaf) stage(tid, cb + (tid < nt ? tid : nt - 1), tid < nt);
+        __syncthreads();
+        sym_block32<KIND, NKC, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, nt, ntiles, w, li, lg, inv_ell);
+    }
+    for (int fb = o0; fb < o1; fb += kSymSeg) {
+        const int fe = min(fb + kSymSeg, o1);
+        __syncthreads();
+        {
+            int sz = 0;
+            const int f = fb + tid;
+            if (f < fe) {
+                const int sl = T.own_src[f];
+                if (sl != l) sz = T.cend[T.leaf_first + sl] - T.cbeg[T.leaf_first + sl];
             }
-            if constexpr (KIND == kGaussSplit) {
-                const float bfac = __builtin_amdgcn_exp2f(s * (inv_ell * -1.4426950408889634f));  // column factor
-                sN[j] = bfac;
-                sQ[j] = ok ? (float)O.xt[jj] * bfac : 0.0f;
-            } else {
-                sN[j] = s;
-            }
-        } else if constexpr (KIND != kGaussSplit) {
-            const int j = tid - kSymLeaf;
-            const double q = O.xt[sb + (j < ns ? j : ns - 1)];
-            sQ[j] = j < ns ? (float)q : 0.0f;
+            sPre[tid + 1] = sz;
+            sBlk[tid] = f;
+            if (tid == 0) sPre[0] = 0;
         }
         __syncthreads();
-        if (diag)
-            sym_block32<KIND, NKC, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
-        else
+        for (int off = 1; off < kSymSeg; off <<= 1) {
+            const int add = tid >= off ? sPre[tid + 1 - off] : 0;
+            __syncthreads();
+            sPre[tid + 1] += add;
+            __syncthreads();
+        }
+        const int total = sPre[kSymSeg];
+        for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+            const int ns = min(kSymLeaf, total - c0);
+            __syncthreads();
+            if (tid < kSymLeaf) {
+                const int j = tid;
+                const bool ok = j < ns;
+                int pidx = cb, fblk = 0, jl = 0;
+                if (ok) {
+                    const int col = c0 + j;
+                    int lo = 0, hi = kSymSeg;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (sPre[mid] <= col) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    fblk = sBlk[lo];
+                    jl = col - sPre[lo];
+                    pidx = T.cbeg[T.leaf_first + T.own_src[fblk]] + jl;
+                }
+                stage(j, pidx, ok);
+                colF[j] = fblk;
+                colJ[j] = jl;
+            }
+            __syncthreads();
             sym_block32<KIND, NKC, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
-        if (!diag) {
             __syncthreads();
             if (tid < ns) {
                 float cs = ((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) +
                            colpart[3 * kSymLeaf + tid];
                 if constexpr (KIND == kGaussSplit) cs *= sN[tid];
-                O.colbuf[(size_t)f * kSymLeaf + tid] = (double)cs;
+                O.colbuf[(size_t)colF[tid] * kSymLeaf + colJ[tid]] = (double)cs;
             }
         }
     }
@@ -1824,15 +1925,26 @@ hipError_t launch_basis(const DevTree &T, int nx, const double *clo, const doubl
 }
 
 hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, double *y, int nrhs, int parts,
-                         int precision, hipStream_t st, const KernelTimer *timer)
+                         int precision, hipStream_t main_st, const KernelTimer *timer, const StreamFork *fork)
 {
     (void)precision;
     if (O.nx > kMaxNx || O.nx * T.dpad > kMaxNodeWords || nrhs > 32) return hipErrorInvalidValue;
     const int near = parts & 1;
     const int far = (parts & 2) && T.min_far_level <= T.J;
-    hipLaunchKernelGGL(p2m_kernel, dim3(T.nleaf), dim3(256), sizeof(double) * T.max_leaf, st, T, O, x, nrhs, far);
+    // symmetric MFMA nearfield for one rhs, leaves <= 128 points, d <= 32, radial kernels
+    const bool sym = nrhs == 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && T.d <= 32 && O.rowbuf && O.colbuf;
+    hipLaunchKernelGGL(p2m_kernel, dim3(T.nleaf), dim3(256), sizeof(double) * T.max_leaf, main_st, T, O, x, nrhs,
+                       far);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    // the symmetric nearfield does not read the locals: the farfield may run beside it
+    const bool split = far && near && sym && fork && fork->side;
+    hipStream_t st = main_st;
+    if (split) {
+        if ((e = hipEventRecord(fork->forked, main_st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(fork->side, fork->forked, 0)) != hipSuccess) return e;
+        st = fork->side;
+    }
     if (far) {
         for (int j = T.J - 1; j >= T.min_far_level; --j)
             hipLaunchKernelGGL(m2m_kernel, dim3(1 << j), dim3(64), 0, st, T, O, (1 << j) - 1, nrhs);
@@ -1873,9 +1985,9 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
             hipLaunchKernelGGL(l2l_kernel, dim3(1 << j), dim3(64), 0, st, T, O, (1 << j) - 1, nrhs);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
+        if (split && (e = hipEventRecord(fork->joined, fork->side)) != hipSuccess) return e;
     }
-    // symmetric MFMA nearfield for one rhs, leaves <= 128 points, d <= 32, radial kernels
-    const bool sym = nrhs == 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && T.d <= 32 && O.rowbuf && O.colbuf;
+    st = main_st;
     if (timer) (void)hipEventRecord(timer->p2p_start, st);
     if (sym) {
         if (near && precision == 0) {
@@ -1894,6 +2006,7 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
             if (e != hipSuccess) return e;
         }
         if (timer) (void)hipEventRecord(timer->p2p_stop, st);
+        if (split && (e = hipStreamWaitEvent(st, fork->joined, 0)) != hipSuccess) return e;
         hipLaunchKernelGGL(p2p_combine_kernel, dim3(T.nleaf), dim3(kSymLeaf), 0, st, T, O, y, near, far);
         return hipGetLastError();
     }

@@ -214,6 +214,22 @@ def test_edge_sizes(orc, n, leaf):
     assert rel(y, P.matvec(x)) <= TOL
 
 
+@pytest.mark.parametrize("kind", ["matern32", "gaussian"])
+def test_coincident_points(orc, kind):
+    """Leaves whose points all coincide have zero-size boxes and take their self block in the
+    farfield; the symmetric nearfield must then skip it while still sweeping the leaf's other
+    owned blocks."""
+    X = W.points(700, 5, 2.0, 21)
+    X[:160] = X[0]
+    X[400:430] = X[401]
+    b = W.dim_weights(5, 2.0)
+    x = np.random.default_rng(22).standard_normal((700, 1))
+    P = orc.Plan(X, b, 32, 0.8, kind, 1.0, 5)
+    _, op = gpu_op(X, b, 32, 0.8, kind, 1.0, 5)
+    y = gpu_matvec(op, x)
+    assert rel(y, P.matvec(x)) <= TOL
+
+
 def test_poly_kernel_exact_against_dense():
     """A kernel inside P_Lambda x P_Lambda is reproduced exactly by the farfield."""
     import pinlib as PL
