@@ -44,6 +44,28 @@ __device__ __forceinline__ double exp_bounded(double x)
     return ldexp(p, (int)n);
 }
 
+// 2^t in FP64 for |t| <= 1020: t = n + f with n = rint(t) and f = t - n in [-1/2, 1/2]
+// (exact), then the degree-10 interpolant of 2^f at 11 first-kind Chebyshev points of
+// [-1/2, 1/2] (same generator; 2.9e-16 relative), scaled by 2^n.  Two operations fewer
+// than exp_bounded where the caller can fold log2(e) into its own operands.
+__device__ __forceinline__ double exp2_bounded(double t)
+{
+    const double n = rint(t);
+    const double f = t - n;
+    double p = 7.072587226569927e-09;
+    p = fma(p, f, 1.0208690586037056e-07);
+    p = fma(p, f, 1.3215442576793237e-06);
+    p = fma(p, f, 1.5252657258547322e-05);
+    p = fma(p, f, 0.00015403530441763784);
+    p = fma(p, f, 0.001333355823016814);
+    p = fma(p, f, 0.00961812910760687);
+    p = fma(p, f, 0.055504108664447695);
+    p = fma(p, f, 0.24022650695910097);
+    p = fma(p, f, 0.69314718055995);
+    p = fma(p, f, 1.0);
+    return ldexp(p, (int)n);
+}
+
 // e^x for x <= 0: arguments below -745 (where e^x underflows to zero) are clamped.
 __device__ __forceinline__ double exp_nonpos(double x) { return exp_bounded(fmax(x, -745.0)); }
 
@@ -591,8 +613,8 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;  // uniform over the wave
             // A holds -2 (x - c): the MFMA chain accumulates |x|^2 + |y|^2 - 2 x.y = r^2 directly.
-            // Split Gaussian: A holds (2 / ell)(x - c) and the chain gives the exponent of the
-            // cross factor; the row and column factors sit in the charges.
+            // Split Gaussian: A holds (2 log2(e) / ell)(x - c) and the chain gives the base-2
+            // exponent of the cross factor; the row and column factors sit in the charges.
             dbl4 G;
             if constexpr (KIND == kGaussSplit)
                 G = dbl4{0.0, 0.0, 0.0, 0.0};
@@ -604,7 +626,7 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
             for (int v = 0; v < 4; ++v) {
                 double kv;
                 if constexpr (KIND == kGaussSplit) {
-                    kv = exp_bounded(G[v]);
+                    kv = exp2_bounded(G[v]);  // the row operand carries log2(e)
                 } else {
                     double r2 = G[v];  // kernel_fast clamps where it takes a square root
                     if constexpr (DIAG) {
@@ -690,7 +712,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         const int i = 16 * rt[u] + li;
         const bool ok = i < nt;
         const int ii = cb + (ok ? i : nt - 1);
-        const double scale = KIND == kGaussSplit ? 2.0 * inv_ell : -2.0;
+        const double scale = KIND == kGaussSplit ? 2.0 * 1.4426950408889634 * inv_ell : -2.0;
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
             const int k = 4 * kc + lg;

@@ -1,6 +1,7 @@
 """The FP64 exponential and square root of the nearfield kernels, checked on the CPU.
 
-The device code evaluates e^x (x <= 0) by Cody-Waite reduction and a degree-10 polynomial.
+The device code evaluates e^x (x <= 0) by Cody-Waite reduction and a degree-10 polynomial,
+and 2^t by splitting off the nearest integer and a degree-10 polynomial.
 Here its constants are read from the kernel source, compared with what the coefficient
 generator derives, and the same operation sequence is replayed in numpy (each fused
 multiply-add formed in extended precision and rounded once to double) against numpy's exp.
@@ -80,6 +81,62 @@ def test_underflow_and_clamp():
     x = np.array([-745.0, -800.0, -1e6])
     got = exp_device(x, log2e, ln2, coef)
     assert np.all(got >= 0.0) and np.all(got <= 5e-324)
+
+
+def device_constants2():
+    src = (CSRC / "kernels.hip").read_text()
+    body = src[src.index("double exp2_bounded(double t)"):]
+    body = body[:body.index("return ldexp")]
+    assert "const double n = rint(t);" in body and "const double f = t - n;" in body
+    top = float(re.search(r"double p = ([0-9.e+-]+);", body).group(1))
+    rest = [float(v) for v in re.findall(r"fma\(p, f, ([0-9.e+-]+)\)", body)]
+    return [top] + rest
+
+
+def exp2_device(t, coef):
+    n = np.rint(t)
+    f = t - n
+    p = np.full_like(t, coef[0])
+    for c in coef[1:]:
+        p = fma(p, f, c)
+    return np.ldexp(p, n.astype(np.int64))
+
+
+def test_exp2_constants_match_generator():
+    spec = importlib.util.spec_from_file_location("gen_exp_coeffs", CSRC / "gen_exp_coeffs.py")
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    buf = io.StringIO()
+    with redirect_stdout(buf):
+        mod.main()
+    gen = [float(v) for v in re.findall(r"b\d+ = np\.float64\(([0-9.e+-]+)\)", buf.getvalue())]
+    coef = device_constants2()
+    assert len(coef) == len(gen) == 11
+    assert coef[::-1] == gen
+    # 2^f = e^(f ln 2) and both interpolate at the mapped Chebyshev points: the two
+    # polynomials agree on [-1/2, 1/2] (up to the rounding of their coefficients)
+    _, _, ce = device_constants()
+    f = np.linspace(-0.5, 0.5, 4001, dtype=np.longdouble)
+    r = f * np.log(np.longdouble(2))
+    p2 = np.zeros_like(f)
+    pe = np.zeros_like(f)
+    for b, c in zip(coef, ce):
+        p2 = p2 * f + np.longdouble(b)
+        pe = pe * r + np.longdouble(c)
+    assert np.max(np.abs(p2 / pe - 1)) <= 1e-16
+
+
+def test_exp2_relative_error_few_ulp():
+    coef = device_constants2()
+    rng = np.random.default_rng(3)
+    t = np.concatenate([rng.uniform(-2.0, 2.0, 200_000), rng.uniform(-80.0, 80.0, 200_000),
+                        rng.uniform(-1000.0, 1000.0, 100_000), np.linspace(-1e-3, 1e-3, 10_001),
+                        np.arange(-20.0, 21.0), np.arange(-20.0, 21.0) + 0.5])
+    got = exp2_device(t, coef)
+    ref = np.exp2(t.astype(np.longdouble))
+    rel = np.abs((got - ref) / ref).astype(np.float64)
+    assert rel.max() <= 5e-16, rel.max()
+    assert np.array_equal(exp2_device(np.arange(-30.0, 31.0), coef), np.exp2(np.arange(-30.0, 31.0)))
 
 
 def sqrt_device(x, seed):
