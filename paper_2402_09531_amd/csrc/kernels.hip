@@ -66,41 +66,43 @@ __device__ __forceinline__ double exp2_bounded(double t)
     return ldexp(p, (int)n);
 }
 
-// e^x for x <= 0: arguments below -745 (where e^x underflows to zero) are clamped.
-__device__ __forceinline__ double exp_nonpos(double x) { return exp_bounded(fmax(x, -745.0)); }
+// 2^t for t <= 0: arguments below -1075 (where 2^t underflows to zero) are clamped.
+__device__ __forceinline__ double exp2_nonpos(double t) { return exp2_bounded(fmax(t, -1075.0)); }
 
 // sqrt(x) for x >= 1e-300 (callers clamp; below that the kernels are 1 to double precision):
-// the hardware reciprocal square root seeds Goldschmidt's coupled iteration for g = sqrt(x)
-// and h = 1/(2 sqrt(x)), followed by two Newton corrections g += h (x - g^2).  The seed's
-// relative error e becomes about e^2 after the coupled step and is squared again by each
-// correction, so the result is within a few units in the last place.  No scaling of tiny
-// arguments and no special values, unlike the library square root.
+// the hardware reciprocal square root y (relative error e) seeds one Goldschmidt step for
+// g = sqrt(x), which leaves an error of order e^2, and one Newton correction
+// g += (y/2)(x - g^2), whose residual is of order e^2 times the error e of y/2.  For
+// e <= 2^-20 (the device builtin is far better) the result is within about one unit in
+// the last place.  No scaling of tiny arguments and no special values, unlike the
+// library square root.
 __device__ __forceinline__ double sqrt_pos(double x)
 {
     const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y, h = 0.5 * y;
+    double g = x * y;
+    const double h = 0.5 * y;
     const double e = fma(-h, g, 0.5);
     g = fma(g, e, g);
-    h = fma(h, e, h);
-    double dd = fma(-g, g, x);
-    g = fma(dd, h, g);
-    dd = fma(-g, g, x);
+    const double dd = fma(-g, g, x);
     return fma(dd, h, g);
 }
 
 // Kernel value from the squared distance, with the branch-free exponential.  r2 may be slightly
 // negative from rounding in the Gram form; the kernels that take its square root clamp it.
+// The exponentials are taken as 2^t with log2(e) folded into the scale of the argument.
 template <int KIND>
 __device__ __forceinline__ double kernel_fast(double r2, double inv_ell)
 {
+    constexpr double kLog2e = 1.4426950408889634, kSqrt3 = 1.7320508075688772;
     if constexpr (KIND == 0) {
-        const double s = sqrt_pos(fmax(r2, 1e-300)) * (1.7320508075688772 * inv_ell);
-        const double e = exp_nonpos(-s);
+        const double r = sqrt_pos(fmax(r2, 1e-300));
+        const double s = r * (kSqrt3 * inv_ell);
+        const double e = exp2_nonpos(r * (-kSqrt3 * kLog2e * inv_ell));
         return fma(s, e, e);
     } else if constexpr (KIND == 1) {
-        return exp_nonpos(-r2 * inv_ell);
+        return exp2_nonpos(r2 * (-kLog2e * inv_ell));
     } else {
-        return exp_nonpos(-sqrt_pos(fmax(r2, 1e-300)) * inv_ell);
+        return exp2_nonpos(sqrt_pos(fmax(r2, 1e-300)) * (-kLog2e * inv_ell));
     }
 }
 
