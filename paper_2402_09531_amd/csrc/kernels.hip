@@ -70,21 +70,18 @@ __device__ __forceinline__ double exp2_bounded(double t)
 __device__ __forceinline__ double exp2_nonpos(double t) { return exp2_bounded(fmax(t, -1075.0)); }
 
 // sqrt(x) for x >= 1e-300 (callers clamp; below that the kernels are 1 to double precision):
-// the hardware reciprocal square root y (relative error e) seeds one Goldschmidt step for
-// g = sqrt(x), which leaves an error of order e^2, and one Newton correction
-// g += (y/2)(x - g^2), whose residual is of order e^2 times the error e of y/2.  For
-// e <= 2^-20 (the device builtin is far better) the result is within about one unit in
-// the last place.  No scaling of tiny arguments and no special values, unlike the
-// library square root.
+// with y the hardware reciprocal square root and g = x y, e = 1 - g y is small (about twice
+// the seed's relative error) and sqrt(x) = g (1 - e)^(-1/2) = g (1 + e/2 + 3e^2/8 + ...).
+// Two terms of the series leave 5e^3/16, below 2^-58 for a seed within 2^-20 (the device
+// builtin is far better), so the result is within one unit in the last place.  No scaling of
+// tiny arguments and no special values, unlike the library square root.
 __device__ __forceinline__ double sqrt_pos(double x)
 {
     const double y = __builtin_amdgcn_rsq(x);
-    double g = x * y;
-    const double h = 0.5 * y;
-    const double e = fma(-h, g, 0.5);
-    g = fma(g, e, g);
-    const double dd = fma(-g, g, x);
-    return fma(dd, h, g);
+    const double g = x * y;
+    const double e = fma(-g, y, 1.0);
+    const double w = g * e;
+    return fma(w, fma(e, 0.375, 0.5), g);
 }
 
 // Kernel value from the squared distance, with the branch-free exponential.  r2 may be slightly
@@ -614,14 +611,16 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;  // uniform over the wave
-            // A holds -2 (x - c): the MFMA chain accumulates |x|^2 + |y|^2 - 2 x.y = r^2 directly.
+            // A holds -2 (x - c): the MFMA chain starts from |x|^2 and adds -2 x.y, then |y|^2 is
+            // added on the vector ALU (an ordinary add, so the clamp in kernel_fast needs no
+            // canonicalisation of the MFMA result).
             // Split Gaussian: A holds (2 log2(e) / ell)(x - c) and the chain gives the base-2
             // exponent of the cross factor; the row and column factors sit in the charges.
             dbl4 G;
             if constexpr (KIND == kGaussSplit)
                 G = dbl4{0.0, 0.0, 0.0, 0.0};
             else
-                G = dbl4{rN[u][0] + nb, rN[u][1] + nb, rN[u][2] + nb, rN[u][3] + nb};
+                G = dbl4{rN[u][0], rN[u][1], rN[u][2], rN[u][3]};
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u][kc], Bf[kc], G, 0, 0, 0);
 #pragma unroll
@@ -630,7 +629,7 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
                 if constexpr (KIND == kGaussSplit) {
                     kv = exp2_bounded(G[v]);  // the row operand carries log2(e)
                 } else {
-                    double r2 = G[v];  // kernel_fast clamps where it takes a square root
+                    double r2 = G[v] + nb;
                     if constexpr (DIAG) {
                         if (16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
                     }
@@ -1111,14 +1110,15 @@ __device__ __forceinline__ void sym_block32(const float (&A)[2][NKC], const floa
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;
-            // A holds -2 (x - c): the chain accumulates r^2 = |x|^2 + |y|^2 - 2 x.y.  Split
-            // Gaussian: A holds (2 log2(e) / ell)(x - c), the chain gives the base-2 exponent of
-            // the cross factor; the row and column factors sit in the charges.
+            // A holds -2 (x - c): the chain starts from |x|^2 and adds -2 x.y, then |y|^2 is added
+            // on the vector ALU (an ordinary add, so the clamp needs no canonicalisation of the
+            // MFMA result).  Split Gaussian: A holds (2 log2(e) / ell)(x - c), the chain gives the
+            // base-2 exponent of the cross factor; the row and column factors sit in the charges.
             flt4 G;
             if constexpr (KIND == kGaussSplit)
                 G = flt4{0.0f, 0.0f, 0.0f, 0.0f};
             else
-                G = flt4{rN[u][0] + nb, rN[u][1] + nb, rN[u][2] + nb, rN[u][3] + nb};
+                G = flt4{rN[u][0], rN[u][1], rN[u][2], rN[u][3]};
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(A[u][kc], Bf[kc], G, 0, 0, 0);
 #pragma unroll
@@ -1127,7 +1127,8 @@ __device__ __forceinline__ void sym_block32(const float (&A)[2][NKC], const floa
                 if constexpr (KIND == kGaussSplit) {
                     kv = __builtin_amdgcn_exp2f(G[v]);
                 } else {
-                    float r2 = KIND == 1 ? G[v] : fmaxf(G[v], 0.0f);
+                    const float g2 = G[v] + nb;
+                    float r2 = KIND == 1 ? g2 : fmaxf(g2, 0.0f);
                     if constexpr (DIAG) {
                         if (16 * rt[u] + 4 * lg + v == j) r2 = 0.0f;
                     }

@@ -5,8 +5,8 @@ and 2^t by splitting off the nearest integer and a degree-10 polynomial.
 Here its constants are read from the kernel source, compared with what the coefficient
 generator derives, and the same operation sequence is replayed in numpy (each fused
 multiply-add formed in extended precision and rounded once to double) against numpy's exp.
-The square root (hardware reciprocal-square-root seed, one Goldschmidt step, one Newton
-correction) is replayed the same way from seeds carrying a relative error up to 2^-20.
+The square root (hardware reciprocal-square-root seed, then a two-term series correction
+g (1 + e/2 + 3e^2/8)) is replayed the same way from seeds carrying a relative error up to 2^-20.
 """
 import importlib.util
 import io
@@ -147,11 +147,9 @@ def test_exp2_relative_error_few_ulp():
 
 def sqrt_device(x, seed):
     g = x * seed
-    h = 0.5 * seed
-    e = fma(-h, g, 0.5)
-    g = fma(g, e, g)
-    d = fma(-g, g, x)
-    return fma(d, h, g)
+    e = fma(-g, seed, 1.0)
+    w = g * e
+    return fma(w, fma(e, 0.375, 0.5), g)
 
 
 def test_sqrt_iteration_few_ulp():
@@ -159,10 +157,10 @@ def test_sqrt_iteration_few_ulp():
     body = src[src.index("double sqrt_pos(double x)"):]
     body = body[:body.index("}")]
     # the sequence replayed here is the one in the source
-    for frag in ("__builtin_amdgcn_rsq(x)", "g = x * y;", "h = 0.5 * y;", "fma(-h, g, 0.5)", "g = fma(g, e, g)",
-                 "dd = fma(-g, g, x)", "return fma(dd, h, g)"):
+    for frag in ("__builtin_amdgcn_rsq(x)", "g = x * y;", "e = fma(-g, y, 1.0);", "w = g * e;",
+                 "return fma(w, fma(e, 0.375, 0.5), g);"):
         assert frag in body, frag
-    assert body.count("fma(") == 4
+    assert body.count("fma(") == 3
     rng = np.random.default_rng(1)
     x = np.concatenate([10.0 ** rng.uniform(-300, 300, 200_000), rng.random(200_000) * 50.0, [1e-300, 1.0, 4.0]])
     seed = (1.0 / np.sqrt(x.astype(np.longdouble))).astype(np.float64)
