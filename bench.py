@@ -480,6 +480,111 @@ def bench_index_compare(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_oracle_timing(args):
+    """The FP64 oracle on the host cores: one matvec of the N=4096 d=4, N=1e6 d=10 and N=1e6 d=20
+    workloads with all threads (median of 3 at N=4096; at N=1e6 one matvec taken as four calls over
+    a quarter of the target leaves each, so each quarter repeats the upward pass) and with one
+    thread (the whole matvec at N=4096; at N=1e6 the rows of the first 128 target leaves, including
+    the full upward pass), plus CG on the N=4096 workload (lambda 1e-6, f = sin(sum x), 500
+    iterations: that system is indefinite at q = 4 and does not reach 1e-8)."""
+    import oracle
+    from paper_2402_09531_amd import workloads as W
+    cpu = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                cpu = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    threads = oracle.num_threads()
+    out = {"metric": "oracle matvec Mpoints/s on the host", "n_gpus": 0, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "N=4096 d=4 Matern, N=1e6 d=10 Matern, N=1e6 d=20 Gaussian"},
+           "cpu": cpu, "threads": threads, "results": []}
+    for name in ("small_d4", "n1m_d10", "n1m_d20"):
+        w = W.WORKLOADS[name]
+        X, b, x = W.make(w)
+        t0 = time.perf_counter()
+        P = oracle.Plan(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q)
+        row = {"workload": name, "n": w.n, "d": w.d, "setup_s": round(time.perf_counter() - t0, 3)}
+        oracle.set_threads(threads)
+        if w.n <= 10_000:
+            ts = []
+            for _ in range(3):
+                t0 = time.perf_counter()
+                P.matvec(x)
+                ts.append(time.perf_counter() - t0)
+            t_all = sorted(ts)[1]
+        else:
+            nl, t_all = 2 ** P.J, 0.0
+            for qtr in range(4):
+                t0 = time.perf_counter()
+                P.matvec(x, leaf_range=(qtr * nl // 4, (qtr + 1) * nl // 4))
+                t_all += time.perf_counter() - t0
+                log(f"[oracle] {name}: quarter {qtr + 1}/4 of the target leaves done, {t_all:.1f} s so far")
+        row["all_threads_s"] = round(t_all, 3)
+        row["all_threads_mpts"] = w.n / t_all / 1e6
+        oracle.set_threads(1)
+        if w.n <= 10_000:
+            t0 = time.perf_counter()
+            P.matvec(x)
+            t1 = time.perf_counter() - t0
+            rows = w.n
+        else:
+            T = P.tree()
+            c0 = 2 ** P.J - 1
+            rows = int(T["end"][c0 + 127] - T["begin"][c0])
+            t0 = time.perf_counter()
+            P.matvec(x, leaf_range=(0, 128))
+            t1 = time.perf_counter() - t0
+        row["one_thread_rows"] = rows
+        row["one_thread_s"] = round(t1, 3)
+        row["one_thread_mpts"] = rows / t1 / 1e6
+        oracle.set_threads(threads)
+        if name == "small_d4":
+            f = W.rhs(w, X)
+            t0 = time.perf_counter()
+            _, info = P.cg(w.lam, f, 1e-8, 500)
+            tcg = time.perf_counter() - t0
+            row["cg"] = {"iters": info[0]["iters"], "rel_res": info[0]["rel_res_true"],
+                         "neg_curvature_steps": info[0]["neg_curvature_steps"], "s": round(tcg, 3),
+                         "ms_per_iter": round(1e3 * tcg / max(info[0]["iters"], 1), 3)}
+        out["results"].append(row)
+        log(f"[oracle] {name}: setup {row['setup_s']} s, {threads} threads {row['all_threads_s']} s "
+            f"({row['all_threads_mpts']:.4f} Mpts/s), 1 thread {row['one_thread_mpts']:.5f} Mpts/s over {rows} rows")
+        del P
+    print(json.dumps(out), flush=True)
+
+
+def bench_lebesgue(args):
+    """Sampled Lebesgue constants (Sec 5.4) of the Chebyshev-Leja and approximate Fekete nodes on
+    the index sets of the benchmark workloads: the library's dwfmm_op_lebesgue over the two
+    cube corners and 20000 Halton points (host work; the index set does not depend on the points,
+    so a small tree suffices)."""
+    import torch
+    import paper_2402_09531_amd as dw
+    from paper_2402_09531_amd import workloads as W
+    cases = [("N=1e6 d=20 workload: b_k=k^-3, q=6, weights R1", 20, 3.0, 6, 0.8, "R1"),
+             ("N=1e6 d=10 workload: b_k=k^-2, q=6, weights R1", 10, 2.0, 6, 0.8, "R1"),
+             ("Sec 6.2: d=20, b_k=k^-2, q=8, eta=0.5, weights R3", 20, 2.0, 8, 0.5, "R3"),
+             ("Sec 6.2: d=20, b_k=k^-4, q=8, eta=0.5, weights R3", 20, 4.0, 8, 0.5, "R3")]
+    out = {"metric": "sampled Lebesgue constant (Sec 5.4)", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "index sets of the benchmark workloads; corners + 20000 Halton points"},
+           "results": []}
+    for label, d, r, q, eta, rule in cases:
+        X = torch.from_numpy(W.points(2000, d, r, 6300)).to("cuda:0")
+        tree = dw.build_tree(X, W.dim_weights(d, r), 128, eta)
+        row = {"case": label}
+        for nodes in ("cheb_leja", "afp"):
+            op = dw.fmm_create(tree, "matern32", 1.0, q, weight_rule=rule, nodes=nodes)
+            row["n_x"] = op.nx
+            row[nodes] = op.lebesgue(20000)
+            op.close()
+        out["results"].append(row)
+        log(f"[lebesgue] {label}: n_x {row['n_x']}, Chebyshev-Leja {row['cheb_leja']:.3f}, AFP {row['afp']:.3f}")
+    print(json.dumps(out), flush=True)
+
+
 def bench_eval(args):
     """Evaluation at new points with the headline operator (N = 1e6, d = 20, b_k = k^-3, Gaussian
     l = 0.5, q = 6, leaf 128, eta 0.8): args.eval targets drawn from the same distribution, FP64.
@@ -544,6 +649,8 @@ def main():
     ap.add_argument("--paper-pe", action="store_true",
                     help="prediction error at the paper's best Sec 6.2 parameters (CG solves)")
     ap.add_argument("--pe-max-iter", type=int, default=4000, help="paper-pe: CG iteration limit")
+    ap.add_argument("--lebesgue", action="store_true", help="sampled Lebesgue constants of both node rules")
+    ap.add_argument("--oracle-timing", action="store_true", help="the CPU oracle alone, all threads and one")
     ap.add_argument("--index-compare", action="store_true",
                     help="error and matvec time of the WTDI, TDI and TPI index sets (Sec 6.1)")
     ap.add_argument("--eval", type=int, default=0, help="evaluation at this many new points (headline operator)")
@@ -580,6 +687,12 @@ def main():
         return
     if args.paper_pe:
         bench_paper_pe(args)
+        return
+    if args.lebesgue:
+        bench_lebesgue(args)
+        return
+    if args.oracle_timing:
+        bench_oracle_timing(args)
         return
     if args.index_compare:
         bench_index_compare(args)

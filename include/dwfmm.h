@@ -127,6 +127,24 @@ typedef struct dwfmm_op_s *dwfmm_op;
 dwfmm_status dwfmm_build_tree(const double *points, int64_t n, int32_t d, const double *dim_weights,
                               int32_t leaf_size, double eta, void *stream, dwfmm_tree *out);
 
+/* Which box size the admissibility compares against (Sec 5.2 eq. (admissibility) names the
+ * diameter; the paper's Sec 6.2 settings are consistent with half of the box diagonal).
+ *   FULL_DIAGONAL  dist(B,B') >= eta max(diag B, diag B')          (dwfmm_build_tree)
+ *   HALF_DIAGONAL  eta dist(B,B') >= max(diag B, diag B') / 2
+ * Both are evaluated squared and inclusive; HALF with eta gives the same partition as FULL
+ * with 1/(2 eta) wherever the two products round alike (exactly so for eta = 0.5 and 1).   */
+typedef enum {
+    DWFMM_ADM_FULL_DIAGONAL = 0,
+    DWFMM_ADM_HALF_DIAGONAL = 1
+} dwfmm_admissibility;
+
+/* dwfmm_build_tree with the admissibility rule chosen; the rule is kept with the tree and
+ * also applies to evaluation at new points (dwfmm_eval_create).  Errors as dwfmm_build_tree,
+ * plus E_INVALID for an unknown rule.                                                       */
+dwfmm_status dwfmm_build_tree_ex(const double *points, int64_t n, int32_t d, const double *dim_weights,
+                                 int32_t leaf_size, double eta, dwfmm_admissibility admissibility,
+                                 void *stream, dwfmm_tree *out);
+
 /* FMM operator for a tree (Sec 4 index set; Sec 5.2 interpolation, cluster bases,
  * transfer matrices).  q >= 0 is the weighted total degree.  opts may be NULL.
  * Builds Lambda, the nodes (opts->node_rule), V^-1, the transfer matrices of
@@ -295,6 +313,14 @@ dwfmm_status dwfmm_tree_get(dwfmm_tree tree, int64_t *perm, int64_t *begin, int6
 dwfmm_status dwfmm_op_info(dwfmm_op op, int64_t *out);
 /* Index set alpha[n_x*d] (uint8), reference nodes xi[n_x*d], Vinv[n_x*n_x], omega[d]. */
 dwfmm_status dwfmm_op_basis(dwfmm_op op, uint8_t *alpha, double *xi, double *Vinv, double *omega);
+/* Sampled Lebesgue constant of the operator's nodes (Sec 5.4, the constant
+ * max_x sum_a |l_a(x)| over [0,1]^d of the Lagrange basis l = V^-T p): the largest
+ * value over the corners x = (0,...,0) and (1,...,1) and the Halton points 1..n_samples
+ * (r-th prime base on the r-th axis with m_k > 0, 1/2 on the others; the candidate
+ * sequence of the approximate Fekete points).  A lower bound of the constant; host
+ * work of n_samples * n_x^2 operations.  out: host, one double.
+ * Errors: E_INVALID (NULL op/out, n_samples outside [0, 1e8]).                        */
+dwfmm_status dwfmm_op_lebesgue(dwfmm_op op, int64_t n_samples, double *out);
 /* Kernel timing for measurement: while enabled, each matvec records HIP events
  * on its stream around the nearfield (P2P) and coupling (M2L) launches.  out
  * (host, 3 doubles, may be NULL) receives the summed P2P ms, summed M2L ms and

@@ -62,7 +62,9 @@ def lib():
                                  C.c_double, C.c_int, dp]
         L.orc_create_ex.restype = C.c_void_p
         L.orc_create_ex.argtypes = [dp, C.c_long, C.c_int, dp, C.c_int, C.c_double, C.c_int, C.c_double,
-                                    C.c_double, C.c_int, dp, C.c_int, C.c_long, C.c_int]
+                                    C.c_double, C.c_int, dp, C.c_int, C.c_long, C.c_int, C.c_int]
+        L.orc_lebesgue.restype = C.c_double
+        L.orc_lebesgue.argtypes = [C.c_void_p, C.c_long]
         L.orc_radical_inverse.restype = C.c_double
         L.orc_radical_inverse.argtypes = [C.c_long, C.c_int]
         L.orc_halton_candidates.restype = None
@@ -99,6 +101,8 @@ def lib():
         L.orc_near_entries.argtypes = [C.c_void_p]
         L.orc_num_threads.restype = C.c_int
         L.orc_num_threads.argtypes = []
+        L.orc_set_threads.restype = None
+        L.orc_set_threads.argtypes = [C.c_int]
         _lib = L
     return _lib
 
@@ -196,14 +200,15 @@ class Plan:
 
     def __init__(self, points, dim_weights, leaf_size: int, eta: float, kernel: str, ell: float,
                  q: float, weight_rule: int = W_R1, weight_aux=None, node_rule: int = NODES_CHEB_LEJA,
-                 n_candidates: int = 0, tensor_set: bool = False):
+                 n_candidates: int = 0, tensor_set: bool = False, half_diagonal: bool = False):
         pts = _f64(points)
         self.n, self.d = pts.shape
         b = _f64(dim_weights)
         aux = None if weight_aux is None else _f64(weight_aux)
         h = lib().orc_create_ex(_dp(pts), self.n, self.d, _dp(b), int(leaf_size), float(eta),
                                 KERNELS[kernel], float(ell), float(q), int(weight_rule), _dp(aux),
-                                int(node_rule), int(n_candidates), int(bool(tensor_set)))
+                                int(node_rule), int(n_candidates), int(bool(tensor_set)),
+                                int(bool(half_diagonal)))
         if not h:
             raise ValueError("oracle: invalid arguments")
         self._h = h
@@ -261,6 +266,10 @@ class Plan:
         lib().orc_get_tree(self._h, _lp(perm), _lp(cb), _lp(ce), _dp(lo), _dp(hi))
         return dict(perm=perm, begin=cb, end=ce, lo=lo, hi=hi)
 
+    def lebesgue(self, n_samples: int = 20000) -> float:
+        """Sampled Lebesgue constant (corners and Halton points 1..n_samples)."""
+        return float(lib().orc_lebesgue(self._h, int(n_samples)))
+
     def lists(self):
         Fp = np.zeros(self.ncl + 1, dtype=np.int64)
         Fs = np.zeros(max(self.nF, 1), dtype=np.int64)
@@ -286,6 +295,11 @@ class Plan:
 
 def num_threads() -> int:
     return lib().orc_num_threads()
+
+
+def set_threads(n: int) -> None:
+    """OpenMP thread count of the following oracle calls (timing runs)."""
+    lib().orc_set_threads(int(n))
 
 
 class Eval:

@@ -15,6 +15,7 @@
  *   Vandermonde        V = [p_a'(xi_a)]      Sec 5.2, eq. (Vandermonde)
  *   cluster tree       balanced binary tree  Sec 5.1, Def 5.1/5.2 (longest-edge median split)
  *   admissibility      dist >= eta max diam  Sec 5.2, eq. (admissibility)
+ *                      (or eta dist >= max diam / 2, the half-diagonal reading)
  *   farfield block     P_nu V^-1 S V^-T P_nu'^T           Sec 5.2, eq. (LowRankBlock)
  *   nested bases       T_child = V^-1 [p^nu_a'(a_child(xi_a))]  Sec 5.2 (two-scale relation)
  *   solver             CG on (K + lambda I) alpha = y      Sec 2, eq. (LGS); Sec 6.2
@@ -430,6 +431,7 @@ typedef struct {
     long n;
     int d, leaf, J, kind, nx;
     double eta, ell, q;
+    int adm_half;   /* admissibility against half the box diagonal */
     long ncl;
     double *X;      /* n*d, original order */
     long *perm;     /* tree position -> original index */
@@ -532,7 +534,15 @@ static void build_tree_depth(orc_plan *P, int J)
     }
 }
 
-/* eq. (admissibility): dist(B, B') >= eta max{diam B, diam B'}, compared squared. */
+/* eq. (admissibility): dist(B, B') >= eta max{diam B, diam B'}, compared squared; with
+ * adm_half the diameter is half the box diagonal: eta dist >= max diag / 2, i.e.
+ * (2 eta)^2 dist^2 >= max diag^2. */
+static int adm_test(double dist2, double dm, double eta, int half)
+{
+    if (half) return (2.0 * eta) * (2.0 * eta) * dist2 >= dm;
+    return dist2 >= eta * eta * dm;
+}
+
 static int admissible(const orc_plan *P, long a, long b)
 {
     int d = P->d;
@@ -547,7 +557,7 @@ static int admissible(const orc_plan *P, long a, long b)
         db2 += (hb[k] - lb[k]) * (hb[k] - lb[k]);
     }
     double dm = da2 > db2 ? da2 : db2;
-    return dist2 >= P->eta * P->eta * dm;
+    return adm_test(dist2, dm, P->eta, P->adm_half);
 }
 
 typedef struct {
@@ -615,24 +625,26 @@ void orc_destroy(orc_plan *P)
 /* Build everything the matvec needs.  points: n*d row-major, original order. */
 orc_plan *orc_create_ex(const double *points, long n, int d, const double *b, int leaf, double eta,
                         int kind, double ell, double q, int weight_rule, const double *weight_aux,
-                        int node_rule, long n_candidates, int index_rule);
+                        int node_rule, long n_candidates, int index_rule, int adm_half);
 
 orc_plan *orc_create(const double *points, long n, int d, const double *b, int leaf, double eta,
                      int kind, double ell, double q, int weight_rule, const double *weight_aux)
 {
-    return orc_create_ex(points, n, d, b, leaf, eta, kind, ell, q, weight_rule, weight_aux, 0, 0, 0);
+    return orc_create_ex(points, n, d, b, leaf, eta, kind, ell, q, weight_rule, weight_aux, 0, 0, 0, 0);
 }
 
 /* node_rule 0: per-axis Chebyshev-Leja nodes; 1: approximate Fekete points from
  * n_candidates Halton candidates (0 = the default count).  index_rule 0: weighted
- * total degree set; 1: the tensor set max_k alpha_k <= q (Sec 6.1, TPI). */
+ * total degree set; 1: the tensor set max_k alpha_k <= q (Sec 6.1, TPI).  adm_half:
+ * admissibility against half the box diagonal. */
 orc_plan *orc_create_ex(const double *points, long n, int d, const double *b, int leaf, double eta,
                         int kind, double ell, double q, int weight_rule, const double *weight_aux,
-                        int node_rule, long n_candidates, int index_rule)
+                        int node_rule, long n_candidates, int index_rule, int adm_half)
 {
     if (n < 1 || d < 1 || d > ORC_MAXD || leaf < 1 || !(eta > 0)) return NULL;
     orc_plan *P = (orc_plan *)calloc(1, sizeof(orc_plan));
     P->n = n; P->d = d; P->leaf = leaf; P->eta = eta; P->kind = kind; P->ell = ell; P->q = q;
+    P->adm_half = adm_half != 0;
     P->X = (double *)malloc(sizeof(double) * (size_t)n * d);
     memcpy(P->X, points, sizeof(double) * (size_t)n * d);
     if (orc_weights(weight_rule, d, b, eta, weight_aux, P->omega) != 0) { orc_destroy(P); return NULL; }
@@ -977,6 +989,36 @@ void orc_get_basis(const orc_plan *P, unsigned char *alpha, double *xi, double *
     if (Vinv) memcpy(Vinv, P->Vinv, sizeof(double) * (size_t)nx * nx);
     if (omega) memcpy(omega, P->omega, sizeof(double) * (size_t)d);
 }
+/* Sampled Lebesgue constant (Sec 5.4): the largest sum_a |l_a(t)| over the corners
+ * t = (0,...,0), (1,...,1) and the Halton candidates 1..M, with the Lagrange basis
+ * l_a(t) = sum_g (V^-1)[g][a] p_g(t) (so that l_a(xi_b) = delta_ab). */
+double orc_lebesgue(const orc_plan *P, long M)
+{
+    int nx = P->nx, d = P->d;
+    double *Y = (double *)malloc(sizeof(double) * (size_t)(M + 2) * d);
+    for (int k = 0; k < d; ++k) {
+        Y[k] = 0.0;
+        Y[d + k] = 1.0;
+    }
+    orc_halton_candidates(d, P->mk, M, Y + 2 * d);
+    double *p = (double *)malloc(sizeof(double) * (size_t)nx);
+    double best = 0.0;
+    for (long j = 0; j < M + 2; ++j) {
+        const double *t = Y + j * d;
+        for (int g = 0; g < nx; ++g) p[g] = leg_tensor(d, P->alpha + (size_t)g * d, t);
+        double sum = 0.0;
+        for (int a = 0; a < nx; ++a) {
+            double l = 0.0;
+            for (int g = 0; g < nx; ++g) l += P->Vinv[(size_t)g * nx + a] * p[g];
+            sum += fabs(l);
+        }
+        if (sum > best) best = sum;
+    }
+    free(p);
+    free(Y);
+    return best;
+}
+
 /* Near-field entry count E_N = sum over near blocks of |nu||nu'|. */
 double orc_near_entries(const orc_plan *P)
 {
@@ -987,6 +1029,15 @@ double orc_near_entries(const orc_plan *P)
             s += (double)(P->ce[c] - P->cb[c]) * (double)(P->ce[src] - P->cb[src]);
         }
     return s;
+}
+/* Thread count for the following calls (n >= 1; timing runs only). */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n >= 1) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
 }
 int orc_num_threads(void)
 {
@@ -1028,7 +1079,7 @@ static int admissible_cross(const orc_plan *A, long a, const orc_plan *B, long b
         db2 += (hb[k] - lb[k]) * (hb[k] - lb[k]);
     }
     double dm = da2 > db2 ? da2 : db2;
-    return dist2 >= eta * eta * dm;
+    return adm_test(dist2, dm, eta, B->adm_half);
 }
 
 static void partition_cross(const orc_plan *A, const orc_plan *B, long a, long b, int level, pairlist *F,
@@ -1051,7 +1102,7 @@ orc_eval *orc_eval_create(const orc_plan *S, const double *targets, long m)
     orc_plan *T = &E->T;
     int d = S->d, nx = S->nx;
     E->S = S;
-    T->n = m; T->d = d; T->leaf = S->leaf; T->eta = S->eta; T->nx = nx;
+    T->n = m; T->d = d; T->leaf = S->leaf; T->eta = S->eta; T->nx = nx; T->adm_half = S->adm_half;
     T->X = (double *)malloc(sizeof(double) * (size_t)m * d);
     memcpy(T->X, targets, sizeof(double) * (size_t)m * d);
     build_tree_depth(T, S->J);

@@ -64,10 +64,10 @@ class SolveInfo(C.Structure):
 
 _lib = None
 
-EXPORTS = ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
+EXPORTS = ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
            "dwfmm_fmm_solve", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
            "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info",
-           "dwfmm_op_basis", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
+           "dwfmm_op_basis", "dwfmm_op_lebesgue", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
            "dwfmm_batch_m2l_shapes", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
            "dwfmm_eval_info", "dwfmm_eval_tree_get", "dwfmm_eval_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
            "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy"]
@@ -82,6 +82,8 @@ def lib():
         L = C.CDLL(LIB_PATH)
         vp, dp, i64p = C.c_void_p, C.POINTER(C.c_double), C.POINTER(C.c_int64)
         L.dwfmm_build_tree.argtypes = [vp, C.c_int64, C.c_int32, dp, C.c_int32, C.c_double, vp, C.POINTER(vp)]
+        L.dwfmm_build_tree_ex.argtypes = [vp, C.c_int64, C.c_int32, dp, C.c_int32, C.c_double, C.c_int,
+                                          vp, C.POINTER(vp)]
         L.dwfmm_fmm_create.argtypes = [vp, _Kernel, C.c_double, C.POINTER(_Opts), vp, C.POINTER(vp)]
         L.dwfmm_fmm_matvec.argtypes = [vp, vp, vp, C.c_int32, vp]
         L.dwfmm_fmm_matvec_parts.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp]
@@ -100,6 +102,7 @@ def lib():
         L.dwfmm_tree_get.argtypes = [vp, i64p, i64p, i64p, dp, dp, i64p, i64p, i64p, i64p]
         L.dwfmm_op_info.argtypes = [vp, i64p]
         L.dwfmm_op_basis.argtypes = [vp, C.POINTER(C.c_uint8), dp, dp, dp]
+        L.dwfmm_op_lebesgue.argtypes = [vp, C.c_int64, dp]
         L.dwfmm_op_moments.argtypes = [vp, dp, dp, C.c_int32]
         L.dwfmm_op_timing.argtypes = [vp, C.c_int32, dp]
         L.dwfmm_batch_create.argtypes = [C.POINTER(vp), C.c_int32, C.c_int32, vp, C.POINTER(vp)]
@@ -133,9 +136,10 @@ def lib():
         L.dwfmm_server_bytes.restype = C.c_size_t
         L.dwfmm_server_destroy.argtypes = [vp]
         L.dwfmm_server_destroy.restype = None
-        for name in ["dwfmm_build_tree", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
+        for name in ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm_fmm_matvec",
+                     "dwfmm_fmm_matvec_parts",
                      "dwfmm_fmm_solve", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info", "dwfmm_op_basis",
-                     "dwfmm_op_moments", "dwfmm_op_timing"]:
+                     "dwfmm_op_lebesgue", "dwfmm_op_moments", "dwfmm_op_timing"]:
             getattr(L, name).restype = C.c_int
         _lib = L
     return _lib
@@ -231,6 +235,12 @@ class Op:
                                     _f64p(om)))
         return dict(alpha=alpha, xi=xi, Vinv=Vinv, omega=om)
 
+    def lebesgue(self, n_samples: int = 20000) -> float:
+        """dwfmm_op_lebesgue: sampled Lebesgue constant of the nodes (corners + Halton points)."""
+        out = C.c_double()
+        _check(lib().dwfmm_op_lebesgue(self._h, int(n_samples), C.byref(out)))
+        return out.value
+
     def moments(self, nrhs: int = 1):
         m = np.zeros((self.tree.ncl, self.nx, nrhs))
         l = np.zeros_like(m)
@@ -255,13 +265,22 @@ class Op:
             pass
 
 
-def build_tree(points, dim_weights, leaf_size: int, eta: float, stream=None) -> Tree:
-    """dwfmm_build_tree: points is an N x d float64 GPU tensor, dim_weights host values b_k."""
+ADMISSIBILITY = {"full": 0, "half": 1}
+
+
+def build_tree(points, dim_weights, leaf_size: int, eta: float, stream=None, admissibility: str = "full") -> Tree:
+    """dwfmm_build_tree (dwfmm_build_tree_ex for admissibility="half"): points is an N x d float64
+    GPU tensor, dim_weights host values b_k; admissibility compares eta times the box gap with the
+    full ("full") or half ("half") box diagonal."""
     n, d = points.shape
     b = np.ascontiguousarray(dim_weights, dtype=np.float64)
     h = C.c_void_p()
-    _check(lib().dwfmm_build_tree(_dev_f64(points, "points"), n, d, _f64p(b), int(leaf_size), float(eta),
-                                  _stream(stream), C.byref(h)))
+    if admissibility == "full":
+        _check(lib().dwfmm_build_tree(_dev_f64(points, "points"), n, d, _f64p(b), int(leaf_size), float(eta),
+                                      _stream(stream), C.byref(h)))
+    else:
+        _check(lib().dwfmm_build_tree_ex(_dev_f64(points, "points"), n, d, _f64p(b), int(leaf_size), float(eta),
+                                         ADMISSIBILITY[admissibility], _stream(stream), C.byref(h)))
     return Tree(h)
 
 

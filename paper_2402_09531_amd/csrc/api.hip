@@ -138,10 +138,17 @@ static void tree_release(dwfmm_tree t)
 
 // ============================================================== build_tree
 static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, int32_t d, const double *dim_weights,
-                                   int32_t leaf_size, double eta, hipStream_t st, dwfmm_tree *out);
+                                   int32_t leaf_size, double eta, hipStream_t st, dwfmm_tree *out, int adm_half);
 
 extern "C" dwfmm_status dwfmm_build_tree(const double *points, int64_t n, int32_t d, const double *dim_weights,
                                          int32_t leaf_size, double eta, void *stream, dwfmm_tree *out)
+{
+    return dwfmm_build_tree_ex(points, n, d, dim_weights, leaf_size, eta, DWFMM_ADM_FULL_DIAGONAL, stream, out);
+}
+
+extern "C" dwfmm_status dwfmm_build_tree_ex(const double *points, int64_t n, int32_t d, const double *dim_weights,
+                                            int32_t leaf_size, double eta, dwfmm_admissibility admissibility,
+                                            void *stream, dwfmm_tree *out)
 {
     if (!out) return fail(DWFMM_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -150,6 +157,8 @@ extern "C" dwfmm_status dwfmm_build_tree(const double *points, int64_t n, int32_
     if (d < 1 || d > kMaxDim) return fail(DWFMM_E_INVALID, "d must be in [1, 64]");
     if (leaf_size < 1 || leaf_size > 1024) return fail(DWFMM_E_INVALID, "leaf_size must be in [1, 1024]");
     if (!(eta > 0.0) || !std::isfinite(eta)) return fail(DWFMM_E_INVALID, "eta must be finite and > 0");
+    if (admissibility != DWFMM_ADM_FULL_DIAGONAL && admissibility != DWFMM_ADM_HALF_DIAGONAL)
+        return fail(DWFMM_E_INVALID, "unknown admissibility rule");
     for (int k = 0; k < d; ++k) {
         if (!std::isfinite(dim_weights[k])) return fail(DWFMM_E_NONFINITE, "dim_weights not finite");
         if (!(dim_weights[k] > 0.0)) return fail(DWFMM_E_INVALID, "dim_weights must be > 0");
@@ -158,12 +167,12 @@ extern "C" dwfmm_status dwfmm_build_tree(const double *points, int64_t n, int32_
     std::vector<double> pts((size_t)n * d);
     HIP_TRY(hipMemcpyAsync(pts.data(), points, pts.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
-    return tree_from_host(pts, n, d, dim_weights, leaf_size, eta, st, out);
+    return tree_from_host(pts, n, d, dim_weights, leaf_size, eta, st, out, (int)admissibility);
 }
 
 // Tree from host points (arguments already checked).
 static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, int32_t d, const double *dim_weights,
-                                   int32_t leaf_size, double eta, hipStream_t st, dwfmm_tree *out)
+                                   int32_t leaf_size, double eta, hipStream_t st, dwfmm_tree *out, int adm_half)
 {
     for (double v : pts)
         if (!std::isfinite(v)) return fail(DWFMM_E_NONFINITE, "points contain NaN or Inf");
@@ -171,7 +180,7 @@ static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, in
     dwfmm_tree t = new (std::nothrow) dwfmm_tree_s();
     if (!t) return fail(DWFMM_E_NOMEM, "host allocation failed");
     std::string err;
-    if (!build_tree(pts.data(), n, d, dim_weights, leaf_size, eta, t->H, err)) {
+    if (!build_tree(pts.data(), n, d, dim_weights, leaf_size, eta, t->H, err, -1, true, adm_half)) {
         delete t;
         return fail(DWFMM_E_INVALID, err);
     }
@@ -1181,7 +1190,7 @@ size_t request_bytes(const ServerRequest &r)
 // stream has drained, so the main stream may use the request without waiting on it.
 dwfmm_status prepare_request(ServerRequest *r, hipStream_t ws)
 {
-    dwfmm_status rc = tree_from_host(r->pts, r->n, r->d, r->b.data(), r->leaf, r->eta, ws, &r->tree);
+    dwfmm_status rc = tree_from_host(r->pts, r->n, r->d, r->b.data(), r->leaf, r->eta, ws, &r->tree, 0);
     if (rc != DWFMM_OK) return rc;
     dwfmm_opts o{};
     o.precision = r->precision;
@@ -1743,6 +1752,14 @@ extern "C" dwfmm_status dwfmm_op_basis(dwfmm_op op, uint8_t *alpha, double *xi, 
     if (xi) std::copy(B.xi.begin(), B.xi.end(), xi);
     if (Vinv) std::copy(B.Vinv.begin(), B.Vinv.end(), Vinv);
     if (omega) std::copy(B.omega.begin(), B.omega.end(), omega);
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_op_lebesgue(dwfmm_op op, int64_t n_samples, double *out)
+{
+    if (!op || !out) return fail(DWFMM_E_INVALID, "NULL op or out");
+    if (n_samples < 0 || n_samples > 100000000) return fail(DWFMM_E_INVALID, "n_samples must be in [0, 1e8]");
+    *out = lebesgue_sampled(op->B, n_samples);
     return DWFMM_OK;
 }
 

@@ -158,13 +158,11 @@ static void basis_values(const HostBasis &B, const double *t, std::vector<std::v
 // longest (relative 1e-12 ties to the lowest index), which is the pivot order of a
 // column-pivoted QR of the Vandermonde matrix.  The orthogonal components are kept by
 // modified Gram-Schmidt, projecting each new direction out twice.
-static bool afp_nodes(HostBasis &B, int64_t M, std::string &err)
+// Halton points 1..M over the axes with m_k > 0 (the r-th active axis in the r-th prime base),
+// 1/2 on the others: Y[j][k], j < M.
+static void halton_points(const HostBasis &B, int64_t M, std::vector<double> &Y)
 {
-    const int d = B.d, nx = B.nx;
-    if (M < nx) {
-        err = "fewer AFP candidates than nodes";
-        return false;
-    }
+    const int d = B.d;
     std::vector<int> primes;
     for (int c = 2; (int)primes.size() < d; ++c) {
         bool pr = true;
@@ -174,14 +172,11 @@ static bool afp_nodes(HostBasis &B, int64_t M, std::string &err)
         }
         if (pr) primes.push_back(c);
     }
-    std::vector<double> Y((size_t)M * d);
+    Y.assign((size_t)M * d, 0.5);
     for (int64_t j = 0; j < M; ++j) {
         int r = 0;
         for (int k = 0; k < d; ++k) {
-            if (B.mk[k] == 0) {
-                Y[(size_t)j * d + k] = 0.5;
-                continue;
-            }
+            if (B.mk[k] == 0) continue;
             const uint64_t base = (uint64_t)primes[r++];
             uint64_t i = (uint64_t)j + 1, num = 0, den = 1;
             for (; i > 0; i /= base) {
@@ -191,6 +186,17 @@ static bool afp_nodes(HostBasis &B, int64_t M, std::string &err)
             Y[(size_t)j * d + k] = (double)num / (double)den;
         }
     }
+}
+
+static bool afp_nodes(HostBasis &B, int64_t M, std::string &err)
+{
+    const int d = B.d, nx = B.nx;
+    if (M < nx) {
+        err = "fewer AFP candidates than nodes";
+        return false;
+    }
+    std::vector<double> Y;
+    halton_points(B, M, Y);
     // residual vectors, candidate-major
     std::vector<double> R((size_t)M * nx), qv(nx);
     std::vector<std::vector<double>> axv(d);
@@ -229,6 +235,30 @@ static bool afp_nodes(HostBasis &B, int64_t M, std::string &err)
             }
     }
     return true;
+}
+
+double lebesgue_sampled(const HostBasis &B, int64_t n_samples)
+{
+    const int d = B.d, nx = B.nx;
+    std::vector<double> Y;
+    halton_points(B, n_samples, Y);
+    std::vector<double> corner0(d, 0.0), corner1(d, 1.0);
+    std::vector<std::vector<double>> axv(d);
+    for (int k = 0; k < d; ++k) axv[k].resize(B.mk[k] + 1);
+    std::vector<double> pv(nx);
+    auto lebesgue_at = [&](const double *t) {
+        basis_values(B, t, axv, pv.data());
+        double sum = 0.0;
+        for (int a = 0; a < nx; ++a) {
+            double l = 0.0;  // l_a(t) = sum_g (V^-1)[g][a] p_g(t)
+            for (int g = 0; g < nx; ++g) l += B.Vinv[(size_t)g * nx + a] * pv[g];
+            sum += std::fabs(l);
+        }
+        return sum;
+    };
+    double best = std::max(lebesgue_at(corner0.data()), lebesgue_at(corner1.data()));
+    for (int64_t j = 0; j < n_samples; ++j) best = std::max(best, lebesgue_at(&Y[(size_t)j * d]));
+    return best;
 }
 
 bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string &err, int node_rule,
@@ -353,13 +383,14 @@ bool build_basis(int d, const double *omega, double q, HostBasis &B, std::string
 
 // ------------------------------------------------------------------ tree
 bool build_tree(const double *pts, int64_t n, int d, const double *b, int leaf, double eta, HostTree &T,
-                std::string &err, int forced_J, bool with_partition)
+                std::string &err, int forced_J, bool with_partition, int adm_half)
 {
     T = HostTree();
     T.n = n;
     T.d = d;
     T.leaf = leaf;
     T.eta = eta;
+    T.adm_half = adm_half;
     T.b.assign(b, b + d);
     int J = 0;
     if (forced_J >= 0)
@@ -475,7 +506,9 @@ void partition_pairs(const HostTree &A, const HostTree &B, double eta, std::vect
 {
     const int d = A.d, J = B.J;
     std::vector<std::pair<int32_t, int32_t>> far, near;
-    const double eta2 = eta * eta;
+    // full diagonal: dist^2 >= eta^2 D^2; half diagonal: eta dist >= D / 2, i.e. (2 eta)^2 dist^2 >= D^2
+    const bool half = B.adm_half != 0;
+    const double lhs_scale = half ? (2.0 * eta) * (2.0 * eta) : 1.0, rhs_scale = half ? 1.0 : eta * eta;
     auto admissible = [&](int64_t u, int64_t v) {
         const double *lu = &A.lo[(size_t)u * d], *hu = &A.hi[(size_t)u * d];
         const double *lv = &B.lo[(size_t)v * d], *hv = &B.hi[(size_t)v * d];
@@ -486,7 +519,7 @@ void partition_pairs(const HostTree &A, const HostTree &B, double eta, std::vect
             du += (hu[k] - lu[k]) * (hu[k] - lu[k]);
             dv += (hv[k] - lv[k]) * (hv[k] - lv[k]);
         }
-        return dist2 >= eta2 * std::max(du, dv);
+        return lhs_scale * dist2 >= rhs_scale * std::max(du, dv);
     };
     struct Item { int32_t u, v; int lev; };
     std::vector<Item> stack{{0, 0, 0}};

@@ -16,6 +16,7 @@ struct HostTree {
     int64_t n = 0;
     int d = 0, leaf = 0, J = 0;
     double eta = 0.0;
+    int adm_half = 0;                    // admissibility against the half box diagonal
     int64_t ncl = 0, nleaf = 0;
     std::vector<double> b;               // box side lengths b_k (dimension weights)
     std::vector<int32_t> perm;           // tree position -> original index
@@ -42,17 +43,24 @@ struct HostBasis {
 };
 
 // forced_J >= 0 builds a tree of that depth (clusters may be empty); with_partition = false
-// skips the block partition (Fptr/Fsrc/Nptr/Nsrc stay empty).
+// skips the block partition (Fptr/Fsrc/Nptr/Nsrc stay empty).  adm_half selects the
+// admissibility eta dist >= max half diagonal instead of dist >= eta max diagonal.
 bool build_tree(const double *pts_host, int64_t n, int d, const double *b, int leaf, double eta, HostTree &T,
-                std::string &err, int forced_J = -1, bool with_partition = true);
+                std::string &err, int forced_J = -1, bool with_partition = true, int adm_half = 0);
 
 // Level-wise block partition of (target cluster, source cluster) pairs of two trees of equal
-// depth with the admissibility of Sec 5.2: CSR over target clusters of source clusters;
-// nearfield entries are leaf pairs.  min_far_level: first level with a farfield block (J+1 if
-// none).  With A = B it is the square partition of build_tree.
+// depth with the admissibility of Sec 5.2 (against the full or, when B.adm_half is set, the
+// half box diagonal): CSR over target clusters of source clusters; nearfield entries are leaf
+// pairs.  min_far_level: first level with a farfield block (J+1 if none).  With A = B it is
+// the square partition of build_tree.
 void partition_pairs(const HostTree &A, const HostTree &B, double eta, std::vector<int32_t> &Fptr,
                      std::vector<int32_t> &Fsrc, std::vector<int32_t> &Nptr, std::vector<int32_t> &Nsrc,
                      int &min_far_level);
+
+// Sampled Lebesgue constant (Sec 5.4): the largest sum_a |l_a(t)| of the Lagrange basis
+// l(t) = V^-T p(t) over the corners t = 0 and t = 1 and the Halton points 1..n_samples of the
+// AFP candidate sequence (a lower bound of the constant over [0,1]^d).
+double lebesgue_sampled(const HostBasis &B, int64_t n_samples);
 
 // node_rule 0: per-axis Chebyshev-Leja nodes; 1: approximate Fekete points from n_cand
 // Halton candidates (0 = max(2000, 50 n_x)).  index_rule 0: weighted total degree set;

@@ -75,3 +75,28 @@ def test_large_index_set_on_the_general_coupling(orc):
     e = np.linalg.norm(yd.cpu().numpy() - yr) / np.linalg.norm(yr)
     say(f"[large n_x] n_x {P.nx}, far blocks {P.nF}, relative error vs oracle {e:.2e}")
     assert e <= 1e-12
+
+
+@pytest.mark.parametrize("nodes", ["cheb_leja", "afp"])
+@pytest.mark.parametrize("d,r,q,eta", [(4, 2.0, 4, 0.8), (10, 2.0, 6, 0.8), (20, 2.0, 8, 0.5)])
+def test_sampled_lebesgue_constant_matches_oracle(orc, nodes, d, r, q, eta):
+    """dwfmm_op_lebesgue against the oracle's sampled Lebesgue constant on the same samples."""
+    X = W.points(3000, d, r, 50 + d)
+    b = W.dim_weights(d, r)
+    P = orc.Plan(X, b, 128, eta, "exponential", 0.3, q,
+                 node_rule=orc.NODES_AFP if nodes == "afp" else orc.NODES_CHEB_LEJA)
+    tree = dw.build_tree(torch.from_numpy(X).cuda(), b, 128, eta)
+    op = dw.fmm_create(tree, "exponential", 0.3, q, nodes=nodes)
+    lg, lo = op.lebesgue(3000), P.lebesgue(3000)
+    say(f"[lebesgue] d={d} q={q} {nodes}: n_x {op.nx}, library {lg:.6f}, oracle {lo:.6f}")
+    assert abs(lg - lo) <= 1e-12 * lo and lg >= 1.0
+
+
+def test_sampled_lebesgue_constant_one_dimension():
+    import math
+    X = W.points(500, 1, 0.0, 5)
+    tree = dw.build_tree(torch.from_numpy(X).cuda(), [1.0], 64, 0.8)
+    for m in (1, 2, 5, 9):
+        op = dw.fmm_create(tree, "matern32", 1.0, m)
+        want = sum(1.0 / math.tan((2 * k + 1) * math.pi / (4 * (m + 1))) for k in range(m + 1)) / (m + 1)
+        assert abs(op.lebesgue(200) - want) <= 1e-13 * want

@@ -214,6 +214,46 @@ def test_edge_sizes(orc, n, leaf):
     assert rel(y, P.matvec(x)) <= TOL
 
 
+@pytest.mark.parametrize("eta", [0.8, 0.5])
+def test_half_diagonal_admissibility(orc, eta):
+    """The half-diagonal rule: identical partition to the oracle's, matvec within 1e-12, also for
+    evaluation at new points (the rule is kept with the tree)."""
+    n, d = 12000, 6
+    X = W.points(n, d, 2.0, 41)
+    b = W.dim_weights(d, 2.0)
+    x = np.random.default_rng(42).standard_normal((n, 1))
+    P = orc.Plan(X, b, 64, eta, "matern32", 1.0, 5, half_diagonal=True)
+    Xd = torch.from_numpy(X).cuda()
+    tree = dw.build_tree(Xd, b, 64, eta, admissibility="half")
+    op = dw.fmm_create(tree, "matern32", 1.0, 5)
+    assert (tree.nF, tree.nN) == (P.nF, P.nN)
+    Lo, Tg = P.lists(), tree.host()
+    for key in ("Fptr", "Nptr"):
+        assert np.array_equal(Lo[key], Tg[key])
+    y = gpu_matvec(op, x)
+    e = rel(y, P.matvec(x))
+    say(f"[half diagonal eta={eta}] far {P.nF} near {P.nN}, rel err {e:.2e}")
+    assert e <= TOL
+    T = W.points(3000, d, 2.0, 43) * 1.1
+    E = orc.Eval(P, T)
+    ev = dw.eval_create(op, torch.from_numpy(T).cuda())
+    assert (ev.nF, ev.nN) == (E.nF, E.nN)
+    ye = torch.empty((3000, 1), dtype=torch.float64, device="cuda")
+    dw.eval_apply(ev, torch.from_numpy(x).cuda(), ye)
+    torch.cuda.synchronize()
+    assert rel(ye.cpu().numpy(), E.apply(x)) <= TOL
+
+
+def test_build_tree_rejects_unknown_admissibility():
+    X = torch.from_numpy(W.points(100, 3, 2.0, 1)).cuda()
+    with pytest.raises(KeyError):
+        dw.build_tree(X, W.dim_weights(3, 2.0), 16, 0.8, admissibility="radius")
+    h = dw.C.c_void_p()
+    st = dw.lib().dwfmm_build_tree_ex(X.data_ptr(), 100, 3, dw._f64p(np.ascontiguousarray(W.dim_weights(3, 2.0))),
+                                      16, 0.8, 7, None, dw.C.byref(h))
+    assert st == dw.E_INVALID and not h.value
+
+
 @pytest.mark.parametrize("kind", ["matern32", "gaussian"])
 def test_coincident_points(orc, kind):
     """Leaves whose points all coincide have zero-size boxes and take their self block in the
