@@ -662,6 +662,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
     __shared__ double colpart[4 * kSymLeaf];
     __shared__ double cen[DK];
     __shared__ int32_t sPre[kSymSeg + 1], sBlk[kSymSeg];  // owned-block segment: size prefix, block ids
+    __shared__ int32_t sBeg[kSymSeg];                     // first source point of each block
     __shared__ int32_t colF[kSymLeaf], colJ[kSymLeaf];    // block and point of each stream column
     __shared__ int32_t sDiag;                             // the leaf owns its self block
 
@@ -770,14 +771,16 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         const int fe = min(fb + kSymSeg, o1);
         __syncthreads();  // the previous segment's table is no longer read
         {
-            int sz = 0;
+            int sz = 0, beg = 0;
             const int f = fb + tid;
             if (f < fe) {
                 const int sl = T.own_src[f];
-                if (sl != l) sz = T.cend[T.leaf_first + sl] - T.cbeg[T.leaf_first + sl];
+                beg = T.cbeg[T.leaf_first + sl];
+                if (sl != l) sz = T.cend[T.leaf_first + sl] - beg;
             }
             sPre[tid + 1] = sz;
             sBlk[tid] = f;
+            sBeg[tid] = beg;
             if (tid == 0) sPre[0] = 0;
         }
         __syncthreads();
@@ -807,7 +810,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
                     }
                     fblk = sBlk[lo];
                     jl = col - sPre[lo];
-                    pidx = T.cbeg[T.leaf_first + T.own_src[fblk]] + jl;
+                    pidx = sBeg[lo] + jl;  // from LDS: only the coordinates are loaded from memory
                 }
                 stage(j, pidx, ok);
                 colF[j] = fblk;
@@ -1154,7 +1157,7 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
     __shared__ float sN[kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf], tQ[kSymLeaf];
     __shared__ float colpart[4 * kSymLeaf];
     __shared__ double cen[DK];
-    __shared__ int32_t sPre[kSymSeg + 1], sBlk[kSymSeg];
+    __shared__ int32_t sPre[kSymSeg + 1], sBlk[kSymSeg], sBeg[kSymSeg];
     __shared__ int32_t colF[kSymLeaf], colJ[kSymLeaf];
     __shared__ int32_t sDiag;
     const int c = T.leaf_first + l;
@@ -1249,14 +1252,16 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
         const int fe = min(fb + kSymSeg, o1);
         __syncthreads();
         {
-            int sz = 0;
+            int sz = 0, beg = 0;
             const int f = fb + tid;
             if (f < fe) {
                 const int sl = T.own_src[f];
-                if (sl != l) sz = T.cend[T.leaf_first + sl] - T.cbeg[T.leaf_first + sl];
+                beg = T.cbeg[T.leaf_first + sl];
+                if (sl != l) sz = T.cend[T.leaf_first + sl] - beg;
             }
             sPre[tid + 1] = sz;
             sBlk[tid] = f;
+            sBeg[tid] = beg;
             if (tid == 0) sPre[0] = 0;
         }
         __syncthreads();
@@ -1284,7 +1289,7 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
                     }
                     fblk = sBlk[lo];
                     jl = col - sPre[lo];
-                    pidx = T.cbeg[T.leaf_first + T.own_src[fblk]] + jl;
+                    pidx = sBeg[lo] + jl;  // from LDS: only the coordinates are loaded from memory
                 }
                 stage(j, pidx, ok);
                 colF[j] = fblk;
