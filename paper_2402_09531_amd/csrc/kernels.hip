@@ -729,7 +729,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
 #pragma unroll
         for (int v = 0; v < 4; ++v) {
             const int i = 16 * rt[u] + 4 * v + lg;
-            rN[u][v] = tN[i];
+            rN[u][v] = KIND == kGaussSplit ? 0.0 : tN[i];  // split: the row factor is applied at the end
             rQ[u][v] = tQ[i];
             racc[u][v] = 0.0;
         }
@@ -837,16 +837,17 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
             s += __shfl_xor(s, 4, 64);
             s += __shfl_xor(s, 8, 64);
             const int i = 16 * rt[u] + 4 * v + lg;
-            if constexpr (KIND == kGaussSplit) s *= rN[u][v];
+            if constexpr (KIND == kGaussSplit) s *= tN[i];  // row factor, from LDS
             if (li == 0 && i < nt) O.rowbuf[(size_t)l * kSymLeaf + i] = s;
         }
 }
 
-// Three waves per SIMD where the registers allow it without spilling (the split Gaussian
-// otherwise settles at two for d <= 20).
+// Waves per SIMD: four for the split Gaussian up to d = 20 (128 registers; the few spills sit
+// outside the tile loop, and the extra wave beats the third by ~2%), three for the other kinds
+// up to d = 20 (four were slower there), else what the registers allow.
 template <int KIND, int DK>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(DK <= 20 || (KIND != kGaussSplit && DK <= 24) ? 3 : 1, 8)))
+__attribute__((amdgpu_waves_per_eu(KIND == kGaussSplit && DK <= 20 ? 4 : (DK <= 20 || (KIND != kGaussSplit && DK <= 24) ? 3 : 1), 8)))
 void p2p_sym_kernel(DevTree T, DevOp O)
 {
     p2p_sym_body<KIND, DK>(T, O, xcd_leaf(blockIdx.x, T.nleaf));
