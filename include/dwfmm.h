@@ -158,8 +158,13 @@ dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, double q, co
 
 /* y = K~ x (Sec 5.2 eq. (LowRankBlock) on the farfield, kernel entries on the
  * nearfield), in the operator's precision.  x, y: device N x nrhs, distinct.
- * 1 <= nrhs <= max_nrhs.  Asynchronous on `stream`; allocates nothing.
- * Errors: E_INVALID, E_HIP.                                                     */
+ * 1 <= nrhs <= max_nrhs.  Asynchronous on `stream`; allocates nothing.  With one
+ * rhs the farfield (M2M, M2L, L2L) runs on the operator's own side stream beside
+ * the nearfield, ordered after the P2M on `stream` and joined back into `stream`
+ * before the final combine, so the result is ordered on `stream` as usual.  The
+ * call may be captured into a HIP graph from `stream`; while `stream` is capturing
+ * all work stays on `stream`.  Calls on one operator must not overlap (they share
+ * its workspace and side stream).  Errors: E_INVALID, E_HIP.                      */
 dwfmm_status dwfmm_fmm_matvec(dwfmm_op op, const double *x, double *y, int32_t nrhs, void *stream);
 
 /* Same as dwfmm_fmm_matvec restricted to parts of the operator (bit 0 nearfield,

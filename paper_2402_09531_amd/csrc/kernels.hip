@@ -1968,8 +1968,11 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
                        far);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the symmetric nearfield does not read the locals: the farfield may run beside it
-    const bool split = far && near && sym && fork && fork->side;
+    // the symmetric nearfield does not read the locals: the farfield may run beside it (not
+    // while the caller's stream is being captured into a graph, which then holds the serial order)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (fork && fork->side && hipStreamIsCapturing(main_st, &cap) != hipSuccess) return hipGetLastError();
+    const bool split = far && near && sym && fork && fork->side && cap == hipStreamCaptureStatusNone;
     hipStream_t st = main_st;
     if (split) {
         if ((e = hipEventRecord(fork->forked, main_st)) != hipSuccess) return e;
