@@ -162,8 +162,9 @@ dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, double q, co
  * rhs the farfield (M2M, M2L, L2L) runs on the operator's own side stream beside
  * the nearfield, ordered after the P2M on `stream` and joined back into `stream`
  * before the final combine, so the result is ordered on `stream` as usual.  The
- * call may be captured into a HIP graph from `stream` (thread-local or relaxed capture
- * mode); while `stream` is capturing all work stays on `stream`.  Calls on one operator must not overlap (they share
+ * call may be captured into a HIP graph from `stream`; while `stream` is capturing
+ * all work stays on `stream` (no library object may be destroyed during a capture:
+ * the destroy calls free device memory).  Calls on one operator must not overlap (they share
  * its workspace and side stream).  Errors: E_INVALID, E_HIP.                      */
 dwfmm_status dwfmm_fmm_matvec(dwfmm_op op, const double *x, double *y, int32_t nrhs, void *stream);
 

@@ -5,6 +5,7 @@ and every sampled row against the row scale |K| |x|).  Inputs come from the
 seeded generators in paper_2402_09531_amd.workloads and are handed identically
 to both sides.
 """
+import gc
 import math
 import sys
 
@@ -401,8 +402,7 @@ def test_matvec_on_a_user_stream_and_from_a_graph():
     """The one-rhs matvec forks its farfield onto a side stream and joins it before the combine:
     on a caller's non-default stream and replayed from a captured HIP graph (with eager work and
     synchronisations between replays) it must give the eager result bitwise.  The capture uses
-    the thread-local mode: in the global mode any unsafe HIP call from another thread of the
-    process (the runtime's own included) invalidates it."""
+    the thread-local mode, so the matvec itself must make no call that is unsafe during capture."""
     n, d = 30000, 8
     X = W.points(n, d, 2.0, 61)
     b = W.dim_weights(d, 2.0)
@@ -423,6 +423,9 @@ def test_matvec_on_a_user_stream_and_from_a_graph():
     assert torch.equal(y1, y_ref)
     yg = torch.zeros_like(x)
     g = torch.cuda.CUDAGraph()
+    # objects of earlier tests left in reference cycles must not be destroyed (hipFree) while
+    # the stream captures: collect them first
+    gc.collect()
     with torch.cuda.graph(g, capture_error_mode="thread_local"):
         dw.fmm_matvec(op, x, yg)
     for rep in range(4):
