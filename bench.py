@@ -174,7 +174,9 @@ def bench_batch(args):
     batch = dw.batch_create(ops, graph=True, tune=not args.no_tune)
     t_batch = time.perf_counter() - t0
     wpc, m2l_ms = batch.m2l_shapes()
-    log(f"[batch] setup {t_setup:.1f} s, batch plan + tuning + graph {t_batch:.2f} s; M2L waves per cluster {wpc}")
+    grid, m2l_ms_pers = batch.m2l_layout()
+    log(f"[batch] setup {t_setup:.1f} s, batch plan + tuning + graph {t_batch:.2f} s; M2L waves per cluster {wpc}, "
+        f"persistent grid {grid}")
     t_b = timed(batch)
     log(f"[batch] {1e3 * t_b:.2f} ms per batched matvec (default M2L shape {1e3 * t_untuned:.2f} ms)")
     ys1 = [torch.empty_like(x) for x in xs]
@@ -197,8 +199,9 @@ def bench_batch(args):
            "aggregate_mpoints_per_s": round(total / t_b / 1e6, 2),
            "one_at_a_time_ms": round(1e3 * t_s, 3), "speedup_vs_one_at_a_time": round(t_s / t_b, 3),
            "bitwise_equal_to_one_at_a_time": bool(same), "setup_s": round(t_setup, 2),
-           "m2l_tuning": {"tuned": not args.no_tune, "waves_per_cluster": wpc,
+           "m2l_tuning": {"tuned": not args.no_tune, "waves_per_cluster": wpc, "persistent_grid": grid,
                           "tuned_ms_4_2_1_waves": np.round(m2l_ms, 4).tolist(),
+                          "tuned_ms_persistent_4_2_1_waves": np.round(m2l_ms_pers, 4).tolist(),
                           "default_shape_ms_per_step": round(1e3 * t_untuned, 3)}}
     print(json.dumps(out), flush=True)
 

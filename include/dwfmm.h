@@ -207,10 +207,15 @@ dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double *f, double
  *          DWFMM_BATCH_M2L_WAVES(w), w in {1, 2, 4}: use w waves per cluster in every
  *          M2L launch where that shape is compiled (else 4); ignored with TUNE.
  *          Default: 4 waves per cluster.
+ *          DWFMM_BATCH_M2L_PERSISTENT: every M2L launch is one persistent grid (1024
+ *          workgroups, 4 per CU) striding over its whole work list instead of one
+ *          workgroup per 4 / waves clusters; with TUNE both layouts of every shape are
+ *          timed.  The layout never changes a bit of the result.
  * Synchronises `stream`.  Errors: E_INVALID (also unknown flag bits), E_NOMEM, E_HIP. */
 typedef struct dwfmm_batch_s *dwfmm_batch;
 #define DWFMM_BATCH_GRAPH 1
 #define DWFMM_BATCH_TUNE 2
+#define DWFMM_BATCH_M2L_PERSISTENT 4
 #define DWFMM_BATCH_M2L_WAVES(w) ((w) << 4)
 dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, int32_t flags, void *stream, dwfmm_batch *out);
 /* The batch's M2L launches: *count = their number; for i < min(count, cap), wpc[i] = the
@@ -218,6 +223,11 @@ dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, int32_t flag
  * milliseconds with 4, 2 and 1 waves (j = 0, 1, 2; -1 where not timed).  Host arrays.
  * Errors: E_INVALID. */
 dwfmm_status dwfmm_batch_m2l_shapes(dwfmm_batch batch, int32_t *wpc, double *ms, int32_t cap, int32_t *count);
+/* The layout of the batch's M2L launches: *count = their number; for i < min(count, cap),
+ * grid[i] = 0 when launch i uses one workgroup per 4 / waves clusters, else the size of its
+ * persistent grid; if ms is not NULL, ms[3 i + j] = the tuned time of the persistent layout
+ * with 4, 2 and 1 waves (-1 where not timed).  Host arrays.  Errors: E_INVALID.           */
+dwfmm_status dwfmm_batch_m2l_layout(dwfmm_batch batch, int32_t *grid, double *ms, int32_t cap, int32_t *count);
 /* y_i = K~_i x_i for every problem i.  xs, ys: host arrays of count device pointers
  * (N_i x 1 each, caller order, x_i != y_i).  Asynchronous on `stream`; allocates nothing. */
 dwfmm_status dwfmm_batch_matvec(dwfmm_batch batch, const double *const *xs, double *const *ys, void *stream);

@@ -68,7 +68,7 @@ EXPORTS = ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm
            "dwfmm_fmm_solve", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
            "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info",
            "dwfmm_op_basis", "dwfmm_op_lebesgue", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
-           "dwfmm_batch_m2l_shapes", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
+           "dwfmm_batch_m2l_shapes", "dwfmm_batch_m2l_layout", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
            "dwfmm_eval_info", "dwfmm_eval_tree_get", "dwfmm_eval_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
            "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy"]
 
@@ -112,6 +112,9 @@ def lib():
         L.dwfmm_batch_m2l_shapes.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
                                              C.POINTER(C.c_int32)]
         L.dwfmm_batch_m2l_shapes.restype = C.c_int
+        L.dwfmm_batch_m2l_layout.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
+                                             C.POINTER(C.c_int32)]
+        L.dwfmm_batch_m2l_layout.restype = C.c_int
         L.dwfmm_eval_create.argtypes = [vp, vp, C.c_int64, vp, C.POINTER(vp)]
         L.dwfmm_eval_create.restype = C.c_int
         L.dwfmm_eval_apply.argtypes = [vp, vp, vp, C.c_int32, vp]
@@ -380,6 +383,7 @@ def eval_apply(ev: Eval, x, y, stream=None):
 
 BATCH_GRAPH = 1
 BATCH_TUNE = 2
+BATCH_M2L_PERSISTENT = 4
 
 
 def BATCH_M2L_WAVES(w: int) -> int:
@@ -403,6 +407,17 @@ class Batch:
         _check(lib().dwfmm_batch_m2l_shapes(self._h, wpc, ms, n, C.byref(cnt)))
         return [wpc[i] for i in range(n)], np.array([ms[i] for i in range(3 * n)]).reshape(n, 3)
 
+    def m2l_layout(self):
+        """(persistent grid of each M2L launch, 0 = one workgroup per 4 / waves clusters; tuned ms
+        of the persistent layout [launch][4, 2, 1 waves] or -1)."""
+        cnt = C.c_int32()
+        _check(lib().dwfmm_batch_m2l_layout(self._h, None, None, 0, C.byref(cnt)))
+        n = cnt.value
+        grid = (C.c_int32 * max(n, 1))()
+        ms = (C.c_double * max(3 * n, 1))()
+        _check(lib().dwfmm_batch_m2l_layout(self._h, grid, ms, n, C.byref(cnt)))
+        return [grid[i] for i in range(n)], np.array([ms[i] for i in range(3 * n)]).reshape(n, 3)
+
     def close(self):
         if self._h:
             lib().dwfmm_batch_destroy(self._h)
@@ -416,12 +431,13 @@ class Batch:
 
 
 def batch_create(ops, graph: bool = False, tune: bool = False, m2l_waves: int | None = None,
-                 stream=None) -> Batch:
-    """dwfmm_batch_create over a list of Op (graph capture, M2L shape tuning or a forced shape)."""
+                 persistent: bool = False, stream=None) -> Batch:
+    """dwfmm_batch_create over a list of Op (graph capture, M2L shape tuning, a forced shape, the
+    persistent M2L layout)."""
     arr = (C.c_void_p * len(ops))(*[o._h for o in ops])
     h = C.c_void_p()
     flags = (BATCH_GRAPH if graph else 0) | (BATCH_TUNE if tune else 0) | \
-        (BATCH_M2L_WAVES(m2l_waves) if m2l_waves else 0)
+        (BATCH_M2L_WAVES(m2l_waves) if m2l_waves else 0) | (BATCH_M2L_PERSISTENT if persistent else 0)
     _check(lib().dwfmm_batch_create(arr, len(ops), flags, _stream(stream), C.byref(h)))
     return Batch(h, ops)
 

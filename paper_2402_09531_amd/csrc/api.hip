@@ -837,6 +837,7 @@ struct dwfmm_batch_s {
     std::vector<BatchItem> h_items;    // host sources of the set-up uploads, kept until destruction
     std::vector<int2> h_work;
     std::vector<double> m2l_ms;        // tuned M2L times, [launch][4, 2, 1 waves], -1 = not timed
+    std::vector<double> m2l_ms_pers;   // the same in the persistent layout
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     ~dwfmm_batch_s()
@@ -876,13 +877,15 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
     for (int i = 0; i < count; ++i)
         if (!ops[i]) return fail(DWFMM_E_INVALID, "ops contains NULL");
     const int forced = (flags >> 4) & 7;
-    if ((flags & ~(DWFMM_BATCH_GRAPH | DWFMM_BATCH_TUNE | DWFMM_BATCH_M2L_WAVES(7))) != 0 ||
+    if ((flags & ~(DWFMM_BATCH_GRAPH | DWFMM_BATCH_TUNE | DWFMM_BATCH_M2L_PERSISTENT | DWFMM_BATCH_M2L_WAVES(7))) !=
+            0 ||
         (forced != 0 && forced != 1 && forced != 2 && forced != 4))
         return fail(DWFMM_E_INVALID, "unknown batch flags");
     dwfmm_batch b = new (std::nothrow) dwfmm_batch_s();
     if (!b) return fail(DWFMM_E_NOMEM, "host allocation failed");
     b->ops.assign(ops, ops + count);
     b->item_of.assign(count, -1);
+    std::vector<const HostTree *> item_tree;  // host tree of each batch item
     for (int i = 0; i < count; ++i) {
         if (!batch_eligible(ops[i])) continue;
         const DevTree &T = ops[i]->tree->D;
@@ -893,6 +896,7 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
         it.precision = ops[i]->precision;
         b->item_of[i] = (int)b->items.size();
         b->items.push_back(it);
+        item_tree.push_back(&ops[i]->tree->H);
     }
     // work lists: leaves, per level M2M / L2L, and one slice per kernel variant for M2L and P2P
     std::vector<int2> work;
@@ -954,6 +958,15 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
             }
         }
         if (lst.empty()) continue;
+        if (far_list) {
+            // longest farfield lists first (ties in list order): the costly clusters start early,
+            // and a persistent grid striding over the list takes a balanced mix of them
+            auto nfar = [&](const int2 &w) {
+                const HostTree &H = *item_tree[w.x];
+                return H.Fptr[w.y + 1] - H.Fptr[w.y];
+            };
+            std::stable_sort(lst.begin(), lst.end(), [&](const int2 &a, const int2 &b2) { return nfar(a) > nfar(b2); });
+        }
         if (!far_list) {
             // consecutive leaves on one XCD: block q is dealt to XCD q % 8
             while (lst.size() % 8) lst.push_back(make_int2(-1, 0));
@@ -990,34 +1003,42 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
     b->h_xs.resize(nitems);
     b->h_ys.resize(nitems);
     b->m2l_ms.assign(3 * P.m2l.size(), -1.0);
-    for (auto &L : P.m2l)
+    b->m2l_ms_pers.assign(3 * P.m2l.size(), -1.0);
+    for (auto &L : P.m2l) {
         if (forced && m2l_wpc_available(L.nxt, forced)) L.wpc = forced;
+        if (flags & DWFMM_BATCH_M2L_PERSISTENT) L.grid = kM2lPersistentGrid;
+    }
     if ((flags & DWFMM_BATCH_TUNE) && !P.m2l.empty()) {
-        // time each compiled shape of every M2L launch on this batch (one warm-up, three timed)
+        // time each compiled shape of every M2L launch on this batch in both layouts (one
+        // warm-up, three timed launches) and keep the fastest
         hipEvent_t e0 = nullptr, e1 = nullptr;
         e = hipEventCreate(&e0);
         if (e == hipSuccess) e = hipEventCreate(&e1);
         const int shapes[3] = {4, 2, 1};
         for (size_t i = 0; i < P.m2l.size() && e == hipSuccess; ++i) {
             BatchLaunch &L = P.m2l[i];
-            float best = 0.0f;
-            for (int j = 0; j < 3 && e == hipSuccess; ++j) {
-                if (!m2l_wpc_available(L.nxt, shapes[j])) continue;
-                BatchLaunch c = L;
-                c.wpc = shapes[j];
-                float ms = 0.0f;
-                if ((e = launch_batch_m2l(P, c, st)) != hipSuccess || (e = hipEventRecord(e0, st)) != hipSuccess) break;
-                for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch_batch_m2l(P, c, st);
-                if (e == hipSuccess) e = hipEventRecord(e1, st);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess) break;
-                b->m2l_ms[3 * i + j] = ms / 3.0;
-                if (j == 0 || ms < best) {
-                    best = ms;
-                    L.wpc = shapes[j];
+            float best = -1.0f;
+            for (int lay = 0; lay < 2 && e == hipSuccess; ++lay)
+                for (int j = 0; j < 3 && e == hipSuccess; ++j) {
+                    if (!m2l_wpc_available(L.nxt, shapes[j])) continue;
+                    BatchLaunch c = L;
+                    c.wpc = shapes[j];
+                    c.grid = lay ? kM2lPersistentGrid : 0;
+                    float ms = 0.0f;
+                    if ((e = launch_batch_m2l(P, c, st)) != hipSuccess || (e = hipEventRecord(e0, st)) != hipSuccess)
+                        break;
+                    for (int rep = 0; rep < 3 && e == hipSuccess; ++rep) e = launch_batch_m2l(P, c, st);
+                    if (e == hipSuccess) e = hipEventRecord(e1, st);
+                    if (e == hipSuccess) e = hipEventSynchronize(e1);
+                    if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                    if (e != hipSuccess) break;
+                    (lay ? b->m2l_ms_pers : b->m2l_ms)[3 * i + j] = ms / 3.0;
+                    if (best < 0.0f || ms < best) {
+                        best = ms;
+                        L.wpc = c.wpc;
+                        L.grid = c.grid;
+                    }
                 }
-            }
         }
         if (e0) (void)hipEventDestroy(e0);
         if (e1) (void)hipEventDestroy(e1);
@@ -1061,6 +1082,19 @@ extern "C" dwfmm_status dwfmm_batch_m2l_shapes(dwfmm_batch b, int32_t *wpc, doub
         wpc[i] = m2l[i].wpc;
         if (ms)
             for (int j = 0; j < 3; ++j) ms[3 * i + j] = b->m2l_ms[3 * i + j];
+    }
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_batch_m2l_layout(dwfmm_batch b, int32_t *grid, double *ms, int32_t cap, int32_t *count)
+{
+    if (!b || !count || cap < 0 || (cap > 0 && !grid)) return fail(DWFMM_E_INVALID, "bad argument");
+    const auto &m2l = b->plan.m2l;
+    *count = (int32_t)m2l.size();
+    for (int i = 0; i < std::min<int>(cap, (int)m2l.size()); ++i) {
+        grid[i] = m2l[i].grid;
+        if (ms)
+            for (int j = 0; j < 3; ++j) ms[3 * i + j] = b->m2l_ms_pers[3 * i + j];
     }
     return DWFMM_OK;
 }

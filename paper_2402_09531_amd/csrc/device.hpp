@@ -94,7 +94,10 @@ struct BatchItem {
 struct BatchLaunch {
     int kind, dk, nxt, prec, off, cnt;
     int wpc = 4;
+    int grid = 0;  // M2L: 0 = one workgroup per 4 / wpc list entries; > 0 = a persistent grid of
+                   // this many workgroups striding over the list
 };
+constexpr int kM2lPersistentGrid = 1024;  // 4 workgroups per CU on 256 CUs
 
 // Work list entries are (item, local block); entries with item < 0 are padding.
 struct BatchPlan {

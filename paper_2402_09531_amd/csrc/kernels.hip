@@ -1798,18 +1798,25 @@ __global__ __launch_bounds__(64) void l2l_batch_kernel(const BatchItem *items, c
     l2l_body(items[wk.x].T, items[wk.x].O, wk.y, 1);
 }
 
-// 4 / WPC clusters of the work list per workgroup; slots past the end or on padding idle
-// through the barrier.
+// 4 / WPC clusters of the work list per workgroup and pass; slots past the end or on padding
+// idle through the barrier.  A grid smaller than the list (the persistent layout) strides over
+// it, the same for every thread of a workgroup; a barrier separates the passes, since a pass
+// reuses the partial sums of the previous one.  Which workgroup takes an entry does not change
+// its arithmetic, so both layouts give the same bits.
 template <int KIND, int DK, int NXT, int WPC>
 __global__ __launch_bounds__(256) void m2l_batch_kernel(const BatchItem *items, const int2 *work, int cnt)
 {
     constexpr int CPB = 4 / WPC;
     __shared__ double part[CPB][4 * 16 * NXT];
-    const int slot = (threadIdx.x >> 6) / WPC, q = blockIdx.x * CPB + slot;
-    const int2 wk = q < cnt ? work[q] : make_int2(-1, 0);
-    const bool valid = wk.x >= 0;
-    const BatchItem &I = items[valid ? wk.x : 0];
-    m2l_mfma_body<KIND, DK, NXT, WPC>(I.T, I.O, wk.y, valid, part[slot]);
+    const int slot = (threadIdx.x >> 6) / WPC;
+    for (int base = blockIdx.x * CPB; base < cnt; base += gridDim.x * CPB) {
+        if (base != (int)blockIdx.x * CPB) __syncthreads();
+        const int q = base + slot;
+        const int2 wk = q < cnt ? work[q] : make_int2(-1, 0);
+        const bool valid = wk.x >= 0;
+        const BatchItem &I = items[valid ? wk.x : 0];
+        m2l_mfma_body<KIND, DK, NXT, WPC>(I.T, I.O, wk.y, valid, part[slot]);
+    }
 }
 
 template <int KIND, int DK, int NXT, int WPC>
@@ -1817,11 +1824,15 @@ __global__ __launch_bounds__(256) void m2l32_batch_kernel(const BatchItem *items
 {
     constexpr int CPB = 4 / WPC;
     __shared__ float part[CPB][4 * 16 * NXT];
-    const int slot = (threadIdx.x >> 6) / WPC, q = blockIdx.x * CPB + slot;
-    const int2 wk = q < cnt ? work[q] : make_int2(-1, 0);
-    const bool valid = wk.x >= 0;
-    const BatchItem &I = items[valid ? wk.x : 0];
-    m2l_mfma32_body<KIND, DK, NXT, WPC>(I.T, I.O, wk.y, valid, part[slot]);
+    const int slot = (threadIdx.x >> 6) / WPC;
+    for (int base = blockIdx.x * CPB; base < cnt; base += gridDim.x * CPB) {
+        if (base != (int)blockIdx.x * CPB) __syncthreads();
+        const int q = base + slot;
+        const int2 wk = q < cnt ? work[q] : make_int2(-1, 0);
+        const bool valid = wk.x >= 0;
+        const BatchItem &I = items[valid ? wk.x : 0];
+        m2l_mfma32_body<KIND, DK, NXT, WPC>(I.T, I.O, wk.y, valid, part[slot]);
+    }
 }
 
 template <int KIND, int DK, bool FP32>
@@ -1847,15 +1858,19 @@ template <int KIND, int DK, int NXT>
 void launch_m2l_batch_x(const BatchPlan &P, const BatchLaunch &L, hipStream_t st)
 {
     const int2 *w = P.work + L.off;
+    // workgroups: one per 4 / W entries, or at most L.grid in the persistent layout
 #define DWFMM_MW(W)                                                                                         \
-    case W:                                                                                                 \
+    case W: {                                                                                               \
+        const int groups = (L.cnt + 4 / W - 1) / (4 / W);                                                   \
+        const int nwg = L.grid > 0 && L.grid < groups ? L.grid : groups;                                    \
         if (L.prec != 0)                                                                                    \
-            hipLaunchKernelGGL((m2l32_batch_kernel<KIND, DK, NXT, W>), dim3((L.cnt + 4 / W - 1) / (4 / W)),  \
-                               dim3(256), 0, st, P.items, w, L.cnt);                                        \
+            hipLaunchKernelGGL((m2l32_batch_kernel<KIND, DK, NXT, W>), dim3(nwg), dim3(256), 0, st, P.items, \
+                               w, L.cnt);                                                                   \
         else                                                                                                \
-            hipLaunchKernelGGL((m2l_batch_kernel<KIND, DK, NXT, W>), dim3((L.cnt + 4 / W - 1) / (4 / W)),    \
-                               dim3(256), 0, st, P.items, w, L.cnt);                                        \
-        break;
+            hipLaunchKernelGGL((m2l_batch_kernel<KIND, DK, NXT, W>), dim3(nwg), dim3(256), 0, st, P.items,   \
+                               w, L.cnt);                                                                   \
+        break;                                                                                              \
+    }
     if constexpr (NXT <= 2) {
         switch (L.wpc) {
             DWFMM_MW(1) DWFMM_MW(2)

@@ -4,7 +4,8 @@ The batched launches run the same kernel bodies in the same reduction order as t
 single-problem launches, so results must be bitwise equal (FP64 and FP32 modes), also
 when the batch is replayed from a captured HIP graph several times with other work in
 between, for problems that fall back to single launches, for every M2L tile shape
-(1, 2 or 4 waves per cluster) and for the shapes the tuner picks.  One problem per
+(1, 2 or 4 waves per cluster), in the persistent M2L layout (a fixed grid striding over the
+work list) and for the shapes and layouts the tuner picks.  One problem per
 batch is also checked against the CPU oracle.
 """
 import sys
@@ -47,26 +48,35 @@ def make_problems(seed=11):
     return probs
 
 
-@pytest.mark.parametrize("graph,shape", [(False, None), (True, None), (False, 1), (False, 2), (True, "tune")])
+@pytest.mark.parametrize("graph,shape", [(False, None), (True, None), (False, 1), (False, 2), (True, "tune"),
+                                         (True, "persistent"), (False, "persistent-2")])
 def test_batch_equals_single(orc, graph, shape):
     probs = make_problems()
     ops = [p["op"] for p in probs]
     tune = shape == "tune"
-    batch = dw.batch_create(ops, graph=graph, tune=tune, m2l_waves=None if tune else shape)
+    persistent = isinstance(shape, str) and shape.startswith("persistent")
+    waves = 2 if shape == "persistent-2" else (None if tune or persistent else shape)
+    batch = dw.batch_create(ops, graph=graph, tune=tune, m2l_waves=waves, persistent=persistent)
     wpc, ms = batch.m2l_shapes()
-    say(f"[batch graph={graph} shape={shape}] M2L launches {len(wpc)}: waves {wpc}")
-    assert len(wpc) >= 2
+    grid, ms_p = batch.m2l_layout()
+    say(f"[batch graph={graph} shape={shape}] M2L launches {len(wpc)}: waves {wpc}, persistent grid {grid}")
+    assert len(wpc) >= 2 and len(grid) == len(wpc)
     if tune:
-        say(f"   tuned ms [4, 2, 1 waves]: {ms.round(4).tolist()}")
-        for k, w in enumerate(wpc):
-            timed = {4: ms[k, 0], 2: ms[k, 1], 1: ms[k, 2]}
-            assert timed[4] > 0 and timed[2] > 0 and timed[w] == min(t for t in timed.values() if t > 0)
+        say(f"   tuned ms [4, 2, 1 waves]: {ms.round(4).tolist()}, persistent: {ms_p.round(4).tolist()}")
+        for k, (w, g) in enumerate(zip(wpc, grid)):
+            col = {4: 0, 2: 1, 1: 2}[w]
+            chosen = (ms_p if g else ms)[k, col]
+            times = [t for t in np.concatenate([ms[k], ms_p[k]]) if t > 0]
+            assert ms[k, 0] > 0 and ms_p[k, 0] > 0 and chosen == min(times)
+    elif persistent:
+        assert all(g == 1024 for g in grid) and np.all(ms_p == -1)
+        assert all(w == (2 if waves == 2 else 4) for w in wpc)
     elif shape == 2:
-        assert all(w == 2 for w in wpc)
+        assert all(w == 2 for w in wpc) and all(g == 0 for g in grid)
     elif shape == 1:
         assert 1 in wpc and all(w in (1, 4) for w in wpc)
     else:
-        assert all(w == 4 for w in wpc) and np.all(ms == -1)
+        assert all(w == 4 for w in wpc) and np.all(ms == -1) and all(g == 0 for g in grid)
     rng = np.random.default_rng(5)
     for rep in range(3):
         xs = [torch.from_numpy(rng.standard_normal((p["X"].shape[0], 1))).cuda() for p in probs]
