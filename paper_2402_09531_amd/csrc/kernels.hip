@@ -853,6 +853,203 @@ void p2p_sym_kernel(DevTree T, DevOp O)
     p2p_sym_body<KIND, DK>(T, O, xcd_leaf(blockIdx.x, T.nleaf));
 }
 
+// ---------------------------------------------------------------- MFMA cross nearfield (new points, one rhs)
+// Evaluation at new points: every (target leaf, source leaf) pair of the cross nearfield is its
+// own block (no symmetry to use).  One workgroup per target leaf (at most kSymLeaf points): its
+// rows, shifted to the leaf's first point, stay in registers as in the symmetric kernel; the
+// source leaves of its nearfield list are swept as one stream of points, kSymLeaf columns at a
+// time (sizes prefix-summed in LDS, a binary search per column); the Gram tile r^2 comes from
+// FP64 MFMA, the kernel from kernel_fast.  The row sums get the farfield (L2P) added and are
+// scattered to the caller's order.
+template <int KIND, int NKC>
+__device__ __forceinline__ void cross_block(const double (&A)[2][NKC], const double (&rN)[2][4], double (&racc)[2][4],
+                                            const double *sX, const double *sN, const double *sQ, int ns, int ntiles,
+                                            int w, int li, int lg, double inv_ell)
+{
+    const int rt[2] = {w, w + 4};
+    const int nct = (ns + 15) / 16;
+    for (int ct = 0; ct < nct; ++ct) {
+        const int j = 16 * ct + li;
+        const double nb = sN[j], qb = sQ[j];
+        double Bf[NKC];
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (rt[u] >= ntiles) continue;  // uniform over the wave
+            dbl4 G = {rN[u][0], rN[u][1], rN[u][2], rN[u][3]};
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u][kc], Bf[kc], G, 0, 0, 0);
+#pragma unroll
+            for (int v = 0; v < 4; ++v) racc[u][v] = fma(kernel_fast<KIND>(G[v] + nb, inv_ell), qb, racc[u][v]);
+        }
+    }
+}
+
+template <int KIND, int DK>
+__device__ __forceinline__ void p2p_cross_mfma_body(const DevTree &T, const DevOp &O, const DevTree &Ts,
+                                                    const double *__restrict__ xs, double *__restrict__ y, int do_far,
+                                                    int l)
+{
+    constexpr int NKC = DK / 4;
+    __shared__ double sX[DK * kSymLeaf];
+    __shared__ double sN[kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf];
+    __shared__ double cen[DK];
+    __shared__ int32_t sPre[kSymSeg + 1], sBeg[kSymSeg];
+
+    const int c = T.leaf_first + l;
+    const int cb = T.cbeg[c], nt = T.cend[c] - cb;
+    if (nt == 0) return;  // uniform over the workgroup
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lg = lane >> 4;
+    const int n = T.n, ns_all = Ts.n;
+    const double inv_ell = 1.0 / O.ell;
+    const int ntiles = (nt + 15) / 16;
+    // rows k in [d, DK) of both trees' coordinates are zeros, so the shift is zero there
+    if (tid < DK) cen[tid] = T.Xs[(size_t)tid * n + cb];
+    __syncthreads();
+    if (tid < kSymLeaf) {
+        const bool ok = tid < nt;
+        const int ii = cb + (ok ? tid : nt - 1);
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k < DK; ++k) {
+            const double v = T.Xs[(size_t)k * n + ii] - cen[k];
+            s = fma(v, v, s);
+        }
+        tN[tid] = ok ? s : 0.0;
+    }
+    const int rt[2] = {w, w + 4};
+    double A[2][NKC];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int i = 16 * rt[u] + li;
+        const bool ok = i < nt;
+        const int ii = cb + (ok ? i : nt - 1);
+#pragma unroll
+        for (int kc = 0; kc < NKC; ++kc) {
+            const int k = 4 * kc + lg;
+            A[u][kc] = ok ? -2.0 * (T.Xs[(size_t)k * n + ii] - cen[k]) : 0.0;
+        }
+    }
+    __syncthreads();
+    double rN[2][4], racc[2][4];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            rN[u][v] = tN[16 * rt[u] + 4 * v + lg];
+            racc[u][v] = 0.0;
+        }
+    const int f0 = T.Nptr[l], f1 = T.Nptr[l + 1];
+    for (int fb = f0; fb < f1; fb += kSymSeg) {
+        const int fe = min(fb + kSymSeg, f1);
+        __syncthreads();  // the previous segment's table is no longer read
+        {
+            int sz = 0, beg = 0;
+            const int f = fb + tid;
+            if (f < fe) {
+                const int sc = Ts.leaf_first + T.Nsrc[f];
+                beg = Ts.cbeg[sc];
+                sz = Ts.cend[sc] - beg;
+            }
+            sPre[tid + 1] = sz;
+            sBeg[tid] = beg;
+            if (tid == 0) sPre[0] = 0;
+        }
+        __syncthreads();
+        for (int off = 1; off < kSymSeg; off <<= 1) {  // inclusive scan of sPre[1..kSymSeg]
+            const int add = tid >= off ? sPre[tid + 1 - off] : 0;
+            __syncthreads();
+            sPre[tid + 1] += add;
+            __syncthreads();
+        }
+        const int total = sPre[kSymSeg];
+        for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+            const int ns = min(kSymLeaf, total - c0);
+            __syncthreads();  // the previous chunk's tiles are consumed
+            if (tid < kSymLeaf) {
+                const int j = tid;
+                const bool ok = j < ns;
+                int pidx = 0;  // any valid source point for the padding columns
+                if (ok) {
+                    // the list entry holding stream column c0 + j: the largest k with sPre[k] <= c0 + j
+                    const int col = c0 + j;
+                    int lo = 0, hi = kSymSeg;
+                    while (lo < hi) {
+                        const int mid = (lo + hi + 1) >> 1;
+                        if (sPre[mid] <= col) lo = mid;
+                        else hi = mid - 1;
+                    }
+                    pidx = sBeg[lo] + (col - sPre[lo]);
+                }
+                double xv[DK];
+#pragma unroll
+                for (int k = 0; k < DK; ++k) xv[k] = Ts.Xs[(size_t)k * ns_all + pidx];
+                double s = 0.0;
+#pragma unroll
+                for (int k = 0; k < DK; ++k) {
+                    const double v = ok ? xv[k] - cen[k] : 0.0;
+                    sX[k * kSymLeaf + j] = v;
+                    s = fma(v, v, s);
+                }
+                sN[j] = s;
+                sQ[j] = ok ? xs[pidx] : 0.0;
+            }
+            __syncthreads();
+            cross_block<KIND, NKC>(A, rN, racc, sX, sN, sQ, ns, ntiles, w, li, lg, inv_ell);
+        }
+    }
+    // row sums: reduce over the 16 column lanes, then farfield (L2P) and the scatter
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+            double s = racc[u][v];
+            s += __shfl_xor(s, 1, 64);
+            s += __shfl_xor(s, 2, 64);
+            s += __shfl_xor(s, 4, 64);
+            s += __shfl_xor(s, 8, 64);
+            const int i = 16 * rt[u] + 4 * v + lg;
+            if (li == 0) tN[i] = s;
+        }
+    __syncthreads();
+    if (tid < nt) {
+        double acc = tN[tid];
+        if (do_far) {
+            const double *lc = O.L + (size_t)c * O.nx;
+            for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * n + cb + tid], lc[a], acc);
+        }
+        y[T.perm[cb + tid]] = acc;
+    }
+}
+
+template <int KIND, int DK>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 24 ? 3 : 1, 8)))
+void p2p_cross_mfma_kernel(DevTree T, DevOp O, DevTree Ts, const double *__restrict__ xs, double *__restrict__ y,
+                           int do_far)
+{
+    p2p_cross_mfma_body<KIND, DK>(T, O, Ts, xs, y, do_far, xcd_leaf(blockIdx.x, T.nleaf));
+}
+
+template <int KIND>
+hipError_t launch_cross_mfma_k(const DevTree &Tt, const DevOp &Ot, const DevTree &Ts, const double *xs, double *y,
+                               int do_far, hipStream_t st)
+{
+    switch (Tt.dpad) {
+#define DWFMM_XM(D)                                                                                        \
+    case D:                                                                                                \
+        hipLaunchKernelGGL((p2p_cross_mfma_kernel<KIND, D>), dim3(Tt.nleaf), dim3(256), 0, st, Tt, Ot, Ts, xs, y, \
+                           do_far);                                                                        \
+        break;
+        DWFMM_XM(4) DWFMM_XM(8) DWFMM_XM(12) DWFMM_XM(16) DWFMM_XM(20) DWFMM_XM(24) DWFMM_XM(28) DWFMM_XM(32)
+#undef DWFMM_XM
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- MFMA nearfield, several rhs
 // One workgroup per target leaf over all its nearfield source leaves.  The Gram tile is
 // formed with the sources as the A operand: element v of lane (i + 16 g) then holds
@@ -2160,6 +2357,14 @@ hipError_t launch_eval(const DevTree &Tt, const DevOp &Ot, const DevTree &Ts, co
         for (int j = Tt.min_far_level + 1; j <= Tt.J; ++j)
             hipLaunchKernelGGL(l2l_kernel, dim3(1 << j), dim3(64), 0, st, Tt, Ot, (1 << j) - 1, nrhs);
         if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    // one rhs, radial kernels, target leaves of at most kSymLeaf points, d <= 32: MFMA nearfield
+    if (nrhs == 1 && Os.kind <= 2 && Tt.max_leaf <= kSymLeaf && Tt.dpad <= 32) {
+        switch (Os.kind) {
+        case 0: return launch_cross_mfma_k<0>(Tt, Ot, Ts, Os.xt, y, far, st);
+        case 1: return launch_cross_mfma_k<1>(Tt, Ot, Ts, Os.xt, y, far, st);
+        default: return launch_cross_mfma_k<2>(Tt, Ot, Ts, Os.xt, y, far, st);
+        }
     }
     switch (Os.kind) {
     case 0: return launch_p2p_cross_k<0>(Tt, Ot, Ts, Os.xt, y, nrhs, far, st);
