@@ -842,9 +842,10 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         }
 }
 
-// Waves per SIMD: four for the split Gaussian up to d = 20 (128 registers; the few spills sit
-// outside the tile loop, and the extra wave beats the third by ~2%), three for the other kinds
-// up to d = 20 (four were slower there), else what the registers allow.
+// Waves per SIMD (also for the batched variant): four for the split Gaussian up to d = 20 (128
+// registers; the few spills sit outside the tile loop, and the extra wave beats the third by
+// ~2%), three for the other kinds up to d = 20 (four were slower there), else what the
+// registers allow.
 template <int KIND, int DK>
 __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(KIND == kGaussSplit && DK <= 20 ? 4 : (DK <= 20 || (KIND != kGaussSplit && DK <= 24) ? 3 : 1), 8)))
@@ -2033,7 +2034,9 @@ __global__ __launch_bounds__(256) void m2l32_batch_kernel(const BatchItem *items
 }
 
 template <int KIND, int DK, bool FP32>
-__global__ __launch_bounds__(256) void p2p_sym_batch_kernel(const BatchItem *items, const int2 *work)
+__global__ __launch_bounds__(256)
+__attribute__((amdgpu_waves_per_eu(KIND == kGaussSplit && DK <= 20 ? 4 : (DK <= 20 || (KIND != kGaussSplit && DK <= 24) ? 3 : 1), 8)))
+void p2p_sym_batch_kernel(const BatchItem *items, const int2 *work)
 {
     const int2 wk = work[blockIdx.x];
     if (wk.x < 0) return;
