@@ -559,6 +559,67 @@ def bench_oracle_timing(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_solve(args):
+    """CG on (K~ + lambda I) alpha = f at full size (the workload's lambda = 1e-6, or --solve-lambda,
+    and data f, rtol 1e-8, at most --solve-max-iter iterations): FP64 CG, or with --precision fp32 / bf16 the reduced
+    matvec inside FP64 iterative refinement.  Reports iterations, time per iteration and the true
+    relative residual the library measures with its FP64 matvec; --solve-check re-measures the
+    residual of column 0 with the FP64 oracle's own matvec on the host."""
+    import torch
+    import paper_2402_09531_amd as dw
+    from paper_2402_09531_amd import workloads as W
+    dev = torch.device("cuda:0")
+    w = W.WORKLOADS[args.workload]
+    nrhs = args.nrhs or w.nrhs
+    X, b, _ = W.make(w)
+    f = np.empty((w.n, nrhs))
+    f[:, 0] = W.rhs(w, X)
+    if nrhs > 1:   # further columns: seeded normal data of the same scale
+        f[:, 1:] = np.random.default_rng(7000).standard_normal((w.n, nrhs - 1)) * np.abs(f[:, 0]).mean()
+    Xd = torch.from_numpy(X).to(dev)
+    tree = dw.build_tree(Xd, b, w.leaf, w.eta)
+    t_start = [time.perf_counter()]
+
+    def progress(it, rr):
+        if it % 64 == 0:
+            log(f"[solve] CG iteration {it}: largest relative residual {max(rr):.3e} "
+                f"({time.perf_counter() - t_start[0]:.1f} s)")
+
+    op = dw.fmm_create(tree, w.kernel, w.ell, w.q, precision=args.precision, max_nrhs=nrhs, check_every=16,
+                       progress=progress)
+    fd = torch.from_numpy(f).to(dev).contiguous()
+    ad = torch.zeros_like(fd)
+    torch.cuda.synchronize()
+    t_start[0] = time.perf_counter()
+    lam = w.lam if args.solve_lambda is None else args.solve_lambda
+    infos = dw.fmm_solve(op, lam, fd, ad, 1e-8, args.solve_max_iter)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t_start[0]
+    iters = max(i["iters"] for i in infos)
+    names = dw.STATUS_NAMES
+    out = {"metric": "CG solve of (K~ + lambda I) alpha = f", "n_gpus": 1,
+           "dtype": "f64" if args.precision == "fp64" else args.precision + " inner, f64 outer",
+           "data": "synthetic",
+           "config": {"workload": w.name, "N": w.n, "d": w.d, "kernel": w.kernel, "q": w.q, "nrhs": nrhs,
+                      "lambda": lam, "rtol": 1e-8, "max_iter": args.solve_max_iter, "precision": args.precision},
+           "time_s": round(t, 3), "iterations": iters, "ms_per_iteration": round(1e3 * t / max(iters, 1), 3),
+           "columns": [{"iters": i["iters"], "refine_steps": i["refine_steps"], "status": names.get(i["status"], i["status"]),
+                        "neg_curvature_steps": i["neg_curvature_steps"], "rel_res_true": i["rel_res_true"]}
+                       for i in infos[:4]]}
+    log(f"[solve] {w.name} nrhs={nrhs} {args.precision}: {iters} iterations in {t:.2f} s "
+        f"({out['ms_per_iteration']} ms each), column 0: {out['columns'][0]}")
+    if args.solve_check:
+        import oracle
+        P = oracle.Plan(X, b, w.leaf, w.eta, w.kernel, w.ell, w.q)
+        a0 = ad[:, 0].cpu().numpy()
+        t0 = time.perf_counter()
+        r = f[:, 0] - (P.matvec(a0[:, None])[:, 0] + lam * a0)
+        out["oracle_rel_res_col0"] = float(np.linalg.norm(r) / np.linalg.norm(f[:, 0]))
+        log(f"[solve] oracle residual of column 0: {out['oracle_rel_res_col0']:.3e} "
+            f"({time.perf_counter() - t0:.1f} s on the host)")
+    print(json.dumps(out), flush=True)
+
+
 def bench_lebesgue(args):
     """Sampled Lebesgue constants (Sec 5.4) of the Chebyshev-Leja and approximate Fekete nodes on
     the index sets of the benchmark workloads: the library's dwfmm_op_lebesgue over the two
@@ -653,6 +714,10 @@ def main():
                     help="prediction error at the paper's best Sec 6.2 parameters (CG solves)")
     ap.add_argument("--pe-max-iter", type=int, default=4000, help="paper-pe: CG iteration limit")
     ap.add_argument("--lebesgue", action="store_true", help="sampled Lebesgue constants of both node rules")
+    ap.add_argument("--solve", action="store_true", help="full-size CG solve (FP64, or reduced precision with IR)")
+    ap.add_argument("--solve-max-iter", type=int, default=300)
+    ap.add_argument("--solve-check", action="store_true", help="solve: oracle residual of column 0")
+    ap.add_argument("--solve-lambda", type=float, default=None, help="solve: ridge instead of the workload's 1e-6")
     ap.add_argument("--oracle-timing", action="store_true", help="the CPU oracle alone, all threads and one")
     ap.add_argument("--index-compare", action="store_true",
                     help="error and matvec time of the WTDI, TDI and TPI index sets (Sec 6.1)")
@@ -693,6 +758,9 @@ def main():
         return
     if args.lebesgue:
         bench_lebesgue(args)
+        return
+    if args.solve:
+        bench_solve(args)
         return
     if args.oracle_timing:
         bench_oracle_timing(args)
