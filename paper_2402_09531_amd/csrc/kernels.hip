@@ -590,6 +590,10 @@ constexpr int kSymLeaf = 128;
 // exp(-|x-c|^2/ell) exp(-|y-c|^2/ell) exp(2 (x-c).(y-c)/ell) (operators with gauss_split set).
 constexpr int kGaussSplit = 4;
 constexpr int kSymSeg = 256;  // owned blocks per column-stream segment (= threads per workgroup)
+// Row stride of the FP32 tile coordinates in LDS: a wave reads rows 4kc + g (g = 0..3) at 16
+// consecutive columns; with 16 floats of padding the rows g and g + 1 fall on the two halves
+// of the 32 banks instead of the same 16.
+constexpr int kSX32 = 128 + 16;
 
 // One leaf block, all 16x16 tiles of this wave's two row tiles.  DIAG: the block of a
 // leaf with itself (i == j forced to distance 0, no column sums).
@@ -1307,7 +1311,7 @@ __device__ __forceinline__ void sym_block32(const float (&A)[2][NKC], const floa
         const float nb = KIND == kGaussSplit ? 0.0f : sN[j], qb = sQ[j];
         float Bf[NKC];
 #pragma unroll
-        for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
+        for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSX32 + j];
         float cacc = 0.0f;
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -1352,7 +1356,7 @@ template <int KIND, int DK>
 __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O, int l)
 {
     constexpr int NKC = DK / 4;
-    __shared__ float sX[DK * kSymLeaf];
+    __shared__ float sX[DK * kSX32];
     __shared__ float sN[kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf], tQ[kSymLeaf];
     __shared__ float colpart[4 * kSymLeaf];
     __shared__ double cen[DK];
@@ -1427,7 +1431,7 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
 #pragma unroll
         for (int k = 0; k < DK; ++k) {
             const float v = ok ? (float)(xv[k] - cen[k]) : 0.0f;
-            sX[k * kSymLeaf + j] = v;
+            sX[k * kSX32 + j] = v;
             s = fmaf(v, v, s);
         }
         const float q = (float)O.xt[pidx];
@@ -1547,7 +1551,13 @@ hipError_t launch_sym32_k(const DevTree &T, const DevOp &O, hipStream_t st)
 // so Y(16 x 16 rhs) += K Q is one MFMA with FP32 accumulation.  FP32: element e is the A
 // operand of chunk e (sources 4g + e) of four v_mfma_f32_16x16x4f32.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-constexpr int kQtStride = kSymLeaf + 8;  // bf16 charges stored [rhs][source], padded
+// bf16 charges stored [rhs][source]; a row of 132 elements puts the 16 lanes of a group on 16
+// different bank pairs for their 8-byte reads
+constexpr int kQtStride = kSymLeaf + 4;
+// FP32 charges stored [source][rhs]; rows of 16 RB + 4 floats put consecutive lane groups on
+// the two halves of the banks
+template <int RB>
+constexpr int q_stride32() { return 16 * RB + 4; }
 
 template <int KIND, int DK, int RB, bool BF16, bool DIAG>
 __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], const float (&tn)[2], flt4 (&Y)[2][RB],
@@ -1560,7 +1570,7 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
     for (int ct = 0; ct < nct; ++ct) {
         float Af[NKC];
 #pragma unroll
-        for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSymLeaf + 16 * ct + li];
+        for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSX32 + 16 * ct + li];
         float snv[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) snv[e] = sN[16 * ct + 4 * lg + e];
@@ -1592,7 +1602,7 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
 #pragma unroll
                     for (int e = 0; e < 4; ++e)
                         Y[u][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(
-                            Kv[e], sQ[(16 * ct + 4 * lg + e) * q_stride<RB>() + 16 * rb + li], Y[u][rb], 0, 0, 0);
+                            Kv[e], sQ[(16 * ct + 4 * lg + e) * q_stride32<RB>() + 16 * rb + li], Y[u][rb], 0, 0, 0);
             }
         }
     }
@@ -1603,9 +1613,9 @@ __global__ __launch_bounds__(256) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, do
                                                           int do_near, int do_far)
 {
     constexpr int NKC = DK / 4;
-    __shared__ float sX[DK * kSymLeaf];
+    __shared__ float sX[DK * kSX32];
     __shared__ float sN[kSymLeaf];
-    __shared__ float sQ[BF16 ? 1 : kSymLeaf * q_stride<RB>()];
+    __shared__ float sQ[BF16 ? 1 : kSymLeaf * q_stride32<RB>()];
     __shared__ __attribute__((aligned(16))) __bf16 sQt[BF16 ? 16 * RB * kQtStride : 8];
     __shared__ double cen[DK];
     const int nleaf = T.nleaf;
@@ -1658,7 +1668,7 @@ __global__ __launch_bounds__(256) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, do
 #pragma unroll
                 for (int k = 0; k < DK; ++k) {
                     const float v = ok ? (float)(xv[k] - cen[k]) : 0.0f;
-                    sX[k * kSymLeaf + j] = v;
+                    sX[k * kSX32 + j] = v;
                     s = fmaf(v, v, s);
                 }
                 sN[j] = s;
@@ -1670,7 +1680,7 @@ __global__ __launch_bounds__(256) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, do
                 if constexpr (BF16)
                     sQt[r * kQtStride + j] = (__bf16)(ok ? (float)q : 0.0f);
                 else
-                    sQ[j * q_stride<RB>() + r] = ok ? (float)q : 0.0f;
+                    sQ[j * q_stride32<RB>() + r] = ok ? (float)q : 0.0f;
             }
             __syncthreads();
             if (sl == l)
