@@ -438,3 +438,43 @@ def test_matvec_on_a_user_stream_and_from_a_graph():
         torch.cuda.synchronize()
         assert torch.equal(y3, y2_ref), rep
     say("[stream/graph] user stream and 4 graph replays bitwise equal to the eager matvec")
+
+
+@pytest.mark.parametrize("case", [
+    # name, n, d, r, q, leaf, nrhs: d = 64 and leaf 1024 (the largest accepted) with n_x * d near
+    # its cap of 3072 (n_x = 46); n_x = 127 just below its cap of 128
+    ("d64_leaf1024", 5000, 64, 2.0, 7.0, 1024, 2),
+    ("nx127_d12", 6000, 12, 2.0, 9.5, 128, 1),
+], ids=lambda c: c[0])
+def test_largest_sizes(orc, case):
+    name, n, d, r, q, leaf, nrhs = case
+    X = W.points(n, d, r, 80)
+    b = W.dim_weights(d, r)
+    x = np.random.default_rng(81).standard_normal((n, nrhs))
+    P = orc.Plan(X, b, leaf, 0.8, "matern32", 1.0, q)
+    _, op = gpu_op(X, b, leaf, 0.8, "matern32", 1.0, q, nrhs=nrhs)
+    assert op.nx == P.nx
+    e = rel(gpu_matvec(op, x), P.matvec(x))
+    say(f"[largest] {name}: n_x {P.nx}, rel err {e:.2e}")
+    assert e <= TOL
+
+
+def test_size_limits_rejected():
+    """d above 64, leaf above 1024, n_x above 128 and n_x * d above 3072 are refused cleanly."""
+    X = torch.from_numpy(W.points(200, 65, 2.0, 82)).cuda()
+    with pytest.raises(dw.DwfmmError) as e:
+        dw.build_tree(X, W.dim_weights(65, 2.0), 16, 0.8)
+    assert e.value.status == dw.E_INVALID
+    X12 = torch.from_numpy(W.points(300, 12, 2.0, 83)).cuda()
+    with pytest.raises(dw.DwfmmError) as e:
+        dw.build_tree(X12, W.dim_weights(12, 2.0), 1025, 0.8)
+    assert e.value.status == dw.E_INVALID
+    tree = dw.build_tree(X12, W.dim_weights(12, 2.0), 64, 0.8)
+    with pytest.raises(dw.DwfmmError) as e:
+        dw.fmm_create(tree, "matern32", 1.0, 10.5)       # n_x above 128
+    assert e.value.status == dw.E_INVALID
+    X64 = torch.from_numpy(W.points(300, 64, 2.0, 84)).cuda()
+    tree64 = dw.build_tree(X64, W.dim_weights(64, 2.0), 64, 0.8)
+    with pytest.raises(dw.DwfmmError) as e:
+        dw.fmm_create(tree64, "matern32", 1.0, 8.0)      # n_x = 77, n_x * 64 above 3072
+    assert e.value.status == dw.E_INVALID
