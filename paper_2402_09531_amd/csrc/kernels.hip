@@ -213,6 +213,33 @@ __global__ __launch_bounds__(256) void p2m_kernel(DevTree T, DevOp O, const doub
     p2m_body(T, O, blockIdx.x, x, nrhs, do_far, xl);
 }
 
+// P2M for several rhs: the leaf's whole block of charges is staged once (rows of nrhs
+// doubles, read and written in order), then every (node, rhs) moment sums over the leaf's
+// points from LDS, in point order.  For leaves of at most 4096 / nrhs points.
+__global__ __launch_bounds__(256) void p2m_multi_kernel(DevTree T, DevOp O, const double *__restrict__ x, int nrhs,
+                                                        int do_far)
+{
+    extern __shared__ double xl[];  // [np][nrhs]
+    const int l = blockIdx.x, c = T.leaf_first + l;
+    const int cb = T.cbeg[c], np = T.cend[c] - cb;
+    for (int e = threadIdx.x; e < np * nrhs; e += blockDim.x) {
+        const int i = e / nrhs, r = e - i * nrhs;
+        const double v = x[(size_t)T.perm[cb + i] * nrhs + r];
+        xl[e] = v;
+        O.xt[(size_t)cb * nrhs + e] = v;
+    }
+    if (!do_far) return;  // uniform over the workgroup
+    __syncthreads();
+    const int nx = O.nx;
+    for (int p = threadIdx.x; p < nx * nrhs; p += blockDim.x) {
+        const int a = p / nrhs, r = p - a * nrhs;
+        const double *lb = O.Lb + (size_t)a * T.n + cb;
+        double s = 0.0;
+        for (int i = 0; i < np; ++i) s = fma(lb[i], xl[i * nrhs + r], s);
+        O.M[((size_t)c * nx + a) * nrhs + r] = s;
+    }
+}
+
 // ---------------------------------------------------------------- M2M, one level
 __device__ __forceinline__ void m2m_body(const DevTree &T, const DevOp &O, int c, int nrhs)
 {
@@ -2189,8 +2216,12 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
     const int far = (parts & 2) && T.min_far_level <= T.J;
     // symmetric MFMA nearfield for one rhs, leaves <= 128 points, d <= 32, radial kernels
     const bool sym = nrhs == 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && T.d <= 32 && O.rowbuf && O.colbuf;
-    hipLaunchKernelGGL(p2m_kernel, dim3(T.nleaf), dim3(256), sizeof(double) * T.max_leaf, main_st, T, O, x, nrhs,
-                       far);
+    if (nrhs > 1 && T.max_leaf * nrhs <= 4096)
+        hipLaunchKernelGGL(p2m_multi_kernel, dim3(T.nleaf), dim3(256), sizeof(double) * T.max_leaf * nrhs, main_st, T,
+                           O, x, nrhs, far);
+    else
+        hipLaunchKernelGGL(p2m_kernel, dim3(T.nleaf), dim3(256), sizeof(double) * T.max_leaf, main_st, T, O, x, nrhs,
+                           far);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     // the symmetric nearfield does not read the locals: the farfield may run beside it (not
