@@ -1144,6 +1144,7 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
     __shared__ double sN[kSymLeaf];
     __shared__ double sQ[kSymLeaf * q_stride<RB>()];
     __shared__ double cen[DK];
+    __shared__ int32_t sPre[kSymSeg + 1], sBeg[kSymSeg], colP[kSymLeaf], sDiag;
     const int nleaf = T.nleaf;
     const int bid = blockIdx.x;
     const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
@@ -1179,15 +1180,21 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
         for (int rb = 0; rb < RB; ++rb) Y[u][rb] = dbl4{0.0, 0.0, 0.0, 0.0};
     }
     if (do_near) {
-        for (int f = T.Nptr[l]; f < T.Nptr[l + 1]; ++f) {
-            const int sl = T.Nsrc[f];
-            const int sc = T.leaf_first + sl;
-            const int sb = T.cbeg[sc], ns = T.cend[sc] - sb;
-            __syncthreads();
+        // the leaf's own block first (when listed), then the other source leaves as one stream of
+        // points, kSymLeaf columns at a time (only the stream's last column tile is padded)
+        const int f0 = T.Nptr[l], f1 = T.Nptr[l + 1];
+        if (tid == 0) sDiag = 0;
+        __syncthreads();
+        for (int f = f0 + tid; f < f1; f += blockDim.x)
+            if (T.Nsrc[f] == l) sDiag = 1;
+        __syncthreads();
+        // columns [c0, c0 + ns) of the current stream (or of the own block): colP holds each
+        // column's point, set by the caller of stage_chunk before the barrier
+        auto stage_chunk = [&](int ns) {
             if (tid < kSymLeaf) {
                 const int j = tid;
                 const bool ok = j < ns;
-                const int jj = sb + (ok ? j : ns - 1);
+                const int jj = colP[j];
                 double xv[DK];
 #pragma unroll
                 for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + jj];
@@ -1200,18 +1207,72 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
                 }
                 sN[j] = s;
             }
-            // charges [j][r], zero beyond the leaf and beyond nrhs
-            for (int e = tid; e < kSymLeaf * 16 * RB; e += 256) {
-                const int j = e / (16 * RB), r = e % (16 * RB);
-                const bool ok = j < ns && r < nrhs;
-                const double q = O.xt[(size_t)(sb + (j < ns ? j : ns - 1)) * nrhs + (r < nrhs ? r : 0)];
-                sQ[j * q_stride<RB>() + r] = ok ? q : 0.0;
+            // charges [j][r], zero beyond the stream and beyond nrhs: thread tid stages rhs
+            // r = tid % 16RB of columns j0 + t * 256 / 16RB, every load issued before the first store
+            constexpr int QPT = kSymLeaf * 16 * RB / 256;
+            const int r = tid % (16 * RB), j0 = tid / (16 * RB);
+            const int rr = r < nrhs ? r : 0;
+            double qv[QPT];
+#pragma unroll
+            for (int t = 0; t < QPT; ++t) qv[t] = O.xt[(size_t)colP[j0 + t * (256 / (16 * RB))] * nrhs + rr];
+#pragma unroll
+            for (int t = 0; t < QPT; ++t) {
+                const int j = j0 + t * (256 / (16 * RB));
+                sQ[j * q_stride<RB>() + r] = (j < ns && r < nrhs) ? qv[t] : 0.0;
+            }
+        };
+        if (sDiag) {
+            if (tid < kSymLeaf) colP[tid] = cb + (tid < nt ? tid : nt - 1);
+            __syncthreads();
+            stage_chunk(nt);
+            __syncthreads();
+            mrhs_block<KIND, DK, RB, true>(Bt, tn, Y, sX, sN, sQ, nt, ntiles, w, li, lg, inv_ell);
+        }
+        for (int fb = f0; fb < f1; fb += kSymSeg) {
+            const int fe = min(fb + kSymSeg, f1);
+            __syncthreads();  // the previous tiles and table are consumed
+            {
+                int sz = 0, beg = 0;
+                const int f = fb + tid;
+                if (f < fe) {
+                    const int sl = T.Nsrc[f];
+                    beg = T.cbeg[T.leaf_first + sl];
+                    if (sl != l) sz = T.cend[T.leaf_first + sl] - beg;
+                }
+                sPre[tid + 1] = sz;
+                sBeg[tid] = beg;
+                if (tid == 0) sPre[0] = 0;
             }
             __syncthreads();
-            if (sl == l)
-                mrhs_block<KIND, DK, RB, true>(Bt, tn, Y, sX, sN, sQ, ns, ntiles, w, li, lg, inv_ell);
-            else
+            for (int off = 1; off < kSymSeg; off <<= 1) {  // inclusive scan of sPre[1..kSymSeg]
+                const int add = tid >= off ? sPre[tid + 1 - off] : 0;
+                __syncthreads();
+                sPre[tid + 1] += add;
+                __syncthreads();
+            }
+            const int total = sPre[kSymSeg];
+            for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+                const int ns = min(kSymLeaf, total - c0);
+                __syncthreads();  // the previous chunk's tiles are consumed
+                if (tid < kSymLeaf) {
+                    int pidx = cb;  // any valid point for the padding columns
+                    if (tid < ns) {
+                        const int col = c0 + tid;  // the entry holding it: the largest k with sPre[k] <= col
+                        int lo = 0, hi = kSymSeg;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (sPre[mid] <= col) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        pidx = sBeg[lo] + (col - sPre[lo]);
+                    }
+                    colP[tid] = pidx;
+                }
+                __syncthreads();
+                stage_chunk(ns);
+                __syncthreads();
                 mrhs_block<KIND, DK, RB, false>(Bt, tn, Y, sX, sN, sQ, ns, ntiles, w, li, lg, inv_ell);
+            }
         }
     }
     // Y[u][rb] element v of lane (r + 16 g) is output (target 16 rt + 4 v + g, rhs 16 rb + r)
@@ -1636,7 +1697,7 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
 }
 
 template <int KIND, int DK, int RB, bool BF16>
-__global__ __launch_bounds__(256) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 3 : 1, 8))) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
                                                           int do_near, int do_far)
 {
     constexpr int NKC = DK / 4;
@@ -1645,6 +1706,7 @@ __global__ __launch_bounds__(256) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, do
     __shared__ float sQ[BF16 ? 1 : kSymLeaf * q_stride32<RB>()];
     __shared__ __attribute__((aligned(16))) __bf16 sQt[BF16 ? 16 * RB * kQtStride : 8];
     __shared__ double cen[DK];
+    __shared__ int32_t sPre[kSymSeg + 1], sBeg[kSymSeg], colP[kSymLeaf], sDiag;
     const int nleaf = T.nleaf;
     const int bid = blockIdx.x;
     const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
@@ -1679,15 +1741,19 @@ __global__ __launch_bounds__(256) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, do
         for (int rb = 0; rb < RB; ++rb) Y[u][rb] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
     }
     if (do_near) {
-        for (int f = T.Nptr[l]; f < T.Nptr[l + 1]; ++f) {
-            const int sl = T.Nsrc[f];
-            const int sc = T.leaf_first + sl;
-            const int sb = T.cbeg[sc], ns = T.cend[sc] - sb;
-            __syncthreads();
+        // the leaf's own block first (when listed), then the other source leaves as one stream of
+        // points, kSymLeaf columns at a time (as in the FP64 kernel)
+        const int f0 = T.Nptr[l], f1 = T.Nptr[l + 1];
+        if (tid == 0) sDiag = 0;
+        __syncthreads();
+        for (int f = f0 + tid; f < f1; f += blockDim.x)
+            if (T.Nsrc[f] == l) sDiag = 1;
+        __syncthreads();
+        auto stage_chunk = [&](int ns) {  // columns of colP[0..kSymLeaf), the first ns real
             if (tid < kSymLeaf) {
                 const int j = tid;
                 const bool ok = j < ns;
-                const int jj = sb + (ok ? j : ns - 1);
+                const int jj = colP[j];
                 double xv[DK];
 #pragma unroll
                 for (int k = 0; k < DK; ++k) xv[k] = T.Xs[(size_t)k * n + jj];
@@ -1700,20 +1766,75 @@ __global__ __launch_bounds__(256) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, do
                 }
                 sN[j] = s;
             }
-            for (int e = tid; e < kSymLeaf * 16 * RB; e += 256) {
-                const int j = e / (16 * RB), r = e % (16 * RB);
-                const bool ok = j < ns && r < nrhs;
-                const double q = O.xt[(size_t)(sb + (j < ns ? j : ns - 1)) * nrhs + (r < nrhs ? r : 0)];
+            // as in the FP64 kernel: every charge load of the thread issued before the first store
+            constexpr int QPT = kSymLeaf * 16 * RB / 256;
+            const int r = tid % (16 * RB), j0 = tid / (16 * RB);
+            const int rr = r < nrhs ? r : 0;
+            double qv[QPT];
+#pragma unroll
+            for (int t = 0; t < QPT; ++t) qv[t] = O.xt[(size_t)colP[j0 + t * (256 / (16 * RB))] * nrhs + rr];
+#pragma unroll
+            for (int t = 0; t < QPT; ++t) {
+                const int j = j0 + t * (256 / (16 * RB));
+                const float q = (j < ns && r < nrhs) ? (float)qv[t] : 0.0f;
                 if constexpr (BF16)
-                    sQt[r * kQtStride + j] = (__bf16)(ok ? (float)q : 0.0f);
+                    sQt[r * kQtStride + j] = (__bf16)q;
                 else
-                    sQ[j * q_stride32<RB>() + r] = ok ? (float)q : 0.0f;
+                    sQ[j * q_stride32<RB>() + r] = q;
+            }
+        };
+        if (sDiag) {
+            if (tid < kSymLeaf) colP[tid] = cb + (tid < nt ? tid : nt - 1);
+            __syncthreads();
+            stage_chunk(nt);
+            __syncthreads();
+            mrhs_block_lp<KIND, DK, RB, BF16, true>(Bt, tn, Y, sX, sN, sQ, sQt, nt, ntiles, w, li, lg, inv_ell);
+        }
+        for (int fb = f0; fb < f1; fb += kSymSeg) {
+            const int fe = min(fb + kSymSeg, f1);
+            __syncthreads();  // the previous tiles and table are consumed
+            {
+                int sz = 0, beg = 0;
+                const int f = fb + tid;
+                if (f < fe) {
+                    const int sl = T.Nsrc[f];
+                    beg = T.cbeg[T.leaf_first + sl];
+                    if (sl != l) sz = T.cend[T.leaf_first + sl] - beg;
+                }
+                sPre[tid + 1] = sz;
+                sBeg[tid] = beg;
+                if (tid == 0) sPre[0] = 0;
             }
             __syncthreads();
-            if (sl == l)
-                mrhs_block_lp<KIND, DK, RB, BF16, true>(Bt, tn, Y, sX, sN, sQ, sQt, ns, ntiles, w, li, lg, inv_ell);
-            else
+            for (int off = 1; off < kSymSeg; off <<= 1) {
+                const int add = tid >= off ? sPre[tid + 1 - off] : 0;
+                __syncthreads();
+                sPre[tid + 1] += add;
+                __syncthreads();
+            }
+            const int total = sPre[kSymSeg];
+            for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+                const int ns = min(kSymLeaf, total - c0);
+                __syncthreads();
+                if (tid < kSymLeaf) {
+                    int pidx = cb;
+                    if (tid < ns) {
+                        const int col = c0 + tid;
+                        int lo = 0, hi = kSymSeg;
+                        while (lo < hi) {
+                            const int mid = (lo + hi + 1) >> 1;
+                            if (sPre[mid] <= col) lo = mid;
+                            else hi = mid - 1;
+                        }
+                        pidx = sBeg[lo] + (col - sPre[lo]);
+                    }
+                    colP[tid] = pidx;
+                }
+                __syncthreads();
+                stage_chunk(ns);
+                __syncthreads();
                 mrhs_block_lp<KIND, DK, RB, BF16, false>(Bt, tn, Y, sX, sN, sQ, sQt, ns, ntiles, w, li, lg, inv_ell);
+            }
         }
     }
     // Y[u][rb] element v of lane (r + 16 g) is output (target 16 rt + 4 g + v, rhs 16 rb + r)
