@@ -1767,20 +1767,33 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
                 sN[j] = s;
             }
             // as in the FP64 kernel: every charge load of the thread issued before the first store
-            constexpr int QPT = kSymLeaf * 16 * RB / 256;
+            constexpr int QPT = kSymLeaf * 16 * RB / 256, G = 256 / (16 * RB);
             const int r = tid % (16 * RB), j0 = tid / (16 * RB);
             const int rr = r < nrhs ? r : 0;
             double qv[QPT];
+            if constexpr (BF16) {
+                // columns 4 (j0 + G t) + e, e < 4: one 8-byte store of four columns per t into the
+                // transposed tile (single 2-byte stores put rhs r and r + 16 on one bank)
 #pragma unroll
-            for (int t = 0; t < QPT; ++t) qv[t] = O.xt[(size_t)colP[j0 + t * (256 / (16 * RB))] * nrhs + rr];
+                for (int t = 0; t < QPT / 4; ++t)
 #pragma unroll
-            for (int t = 0; t < QPT; ++t) {
-                const int j = j0 + t * (256 / (16 * RB));
-                const float q = (j < ns && r < nrhs) ? (float)qv[t] : 0.0f;
-                if constexpr (BF16)
-                    sQt[r * kQtStride + j] = (__bf16)q;
-                else
-                    sQ[j * q_stride32<RB>() + r] = q;
+                    for (int e = 0; e < 4; ++e) qv[4 * t + e] = O.xt[(size_t)colP[4 * (j0 + G * t) + e] * nrhs + rr];
+#pragma unroll
+                for (int t = 0; t < QPT / 4; ++t) {
+                    const int j = 4 * (j0 + G * t);
+                    bf16x4 v;
+#pragma unroll
+                    for (int e = 0; e < 4; ++e) v[e] = (__bf16)((j + e < ns && r < nrhs) ? (float)qv[4 * t + e] : 0.0f);
+                    *reinterpret_cast<bf16x4 *>(&sQt[r * kQtStride + j]) = v;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < QPT; ++t) qv[t] = O.xt[(size_t)colP[j0 + t * G] * nrhs + rr];
+#pragma unroll
+                for (int t = 0; t < QPT; ++t) {
+                    const int j = j0 + t * G;
+                    sQ[j * q_stride32<RB>() + r] = (j < ns && r < nrhs) ? (float)qv[t] : 0.0f;
+                }
             }
         };
         if (sDiag) {

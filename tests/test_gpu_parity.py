@@ -255,18 +255,19 @@ def test_build_tree_rejects_unknown_admissibility():
     assert st == dw.E_INVALID and not h.value
 
 
-@pytest.mark.parametrize("kind", ["matern32", "gaussian"])
-def test_coincident_points(orc, kind):
+@pytest.mark.parametrize("kind,nrhs", [("matern32", 1), ("gaussian", 1), ("gaussian", 3), ("matern32", 20)])
+def test_coincident_points(orc, kind, nrhs):
     """Leaves whose points all coincide have zero-size boxes and take their self block in the
-    farfield; the symmetric nearfield must then skip it while still sweeping the leaf's other
-    owned blocks."""
+    farfield; the nearfield (the symmetric one-rhs kernel, and the several-rhs kernels with one
+    and two 16-wide rhs tiles) must then skip it while still streaming the leaf's other near
+    blocks."""
     X = W.points(700, 5, 2.0, 21)
     X[:160] = X[0]
     X[400:430] = X[401]
     b = W.dim_weights(5, 2.0)
-    x = np.random.default_rng(22).standard_normal((700, 1))
+    x = np.random.default_rng(22).standard_normal((700, nrhs))
     P = orc.Plan(X, b, 32, 0.8, kind, 1.0, 5)
-    _, op = gpu_op(X, b, 32, 0.8, kind, 1.0, 5)
+    _, op = gpu_op(X, b, 32, 0.8, kind, 1.0, 5, nrhs=nrhs)
     y = gpu_matvec(op, x)
     assert rel(y, P.matvec(x)) <= TOL
 

@@ -60,6 +60,28 @@ def test_reduced_precision_matvec_error(orc, case, prec):
     assert e > 1e-13  # the reduced path really ran
 
 
+@pytest.mark.parametrize("prec", ["fp32", "bf16"])
+@pytest.mark.parametrize("nrhs", [1, 3, 20])
+def test_reduced_precision_coincident_points(orc, prec, nrhs):
+    """Zero-size leaf boxes (all points equal) put the self block in the farfield; the reduced
+    nearfield kernels must skip it as the FP64 ones do."""
+    X = W.points(700, 5, 2.0, 21)
+    X[:160] = X[0]
+    X[400:430] = X[401]
+    b = W.dim_weights(5, 2.0)
+    x = np.random.default_rng(23).standard_normal((700, nrhs))
+    P = orc.Plan(X, b, 32, 0.8, "gaussian", 1.0, 5)
+    tree = dw.build_tree(torch.from_numpy(X).cuda(), b, 32, 0.8)
+    op = dw.fmm_create(tree, "gaussian", 1.0, 5, max_nrhs=nrhs)
+    xd = torch.from_numpy(x).cuda()
+    yd = torch.empty_like(xd)
+    dw.fmm_matvec(op, xd, yd, precision=prec)
+    torch.cuda.synchronize()
+    e = rel(yd.cpu().numpy(), P.matvec(x))
+    say(f"[{prec} coincident x{nrhs}] relative error vs FP64 oracle {e:.3e}")
+    assert e <= BOUND[prec]
+
+
 @pytest.mark.parametrize("prec,nrhs", [("fp32", 1), ("fp32", 4), ("bf16", 4)])
 def test_iterative_refinement_reaches_fp64_tolerance(orc, prec, nrhs):
     """Inner CG in reduced precision, FP64 residuals: the oracle-measured residual of the
