@@ -1613,7 +1613,7 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
 }
 
 template <int KIND, int DK>
-__global__ __launch_bounds__(256) void p2p_sym32_kernel(DevTree T, DevOp O)
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 12 ? 5 : 1, 8))) void p2p_sym32_kernel(DevTree T, DevOp O)
 {
     p2p_sym32_body<KIND, DK>(T, O, xcd_leaf(blockIdx.x, T.nleaf));
 }
