@@ -1652,6 +1652,36 @@ extern "C" dwfmm_status dwfmm_eval_create(dwfmm_op op, const double *targets, in
     O.Lb = dLb;
     O.L = dL;
     O.nxp = op->D.nxp;
+    // Split Gaussian in the cross nearfield, exp(-|x-c|^2/ell) exp(-|y-c|^2/ell) exp(2 (x-c).(y-c)/ell)
+    // with c the target leaf's first point: |x - c| <= 2 r_t and |y - c| <= r_t + |m_t - m_s| + r_s
+    // (r: half box diagonals, m: box midpoints), so with B = 2 r_t + |m_t - m_s| + r_s over all cross
+    // near pairs, B^2 / ell <= 300 keeps every exponent within 600.
+    {
+        const int32_t lfs = src->D.leaf_first;
+        auto half_diag = [d](const HostTree &T, int64_t c, double *mid) {
+            double r2 = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double lo = T.lo[(size_t)c * d + k], hi = T.hi[(size_t)c * d + k];
+                mid[k] = 0.5 * (lo + hi);
+                r2 += 0.25 * (hi - lo) * (hi - lo);
+            }
+            return std::sqrt(r2);
+        };
+        std::vector<double> mt(d), ms(d);
+        double bmax2 = 0.0;
+        for (int64_t l = 0; l < H.nleaf; ++l) {
+            if (nptr_leaf[l] == nptr_leaf[l + 1]) continue;
+            const double rt = half_diag(H, lf + l, mt.data());
+            for (int32_t q = nptr_leaf[l]; q < nptr_leaf[l + 1]; ++q) {
+                const double rs = half_diag(Hs, lfs + nsrc_local[q], ms.data());
+                double dc = 0.0;
+                for (int k = 0; k < d; ++k) dc += (mt[k] - ms[k]) * (mt[k] - ms[k]);
+                const double B = 2.0 * rt + std::sqrt(dc) + rs;
+                bmax2 = std::max(bmax2, B * B);
+            }
+        }
+        O.gauss_split = O.kind == DWFMM_GAUSSIAN && bmax2 / O.ell <= 300.0;
+    }
     if ((e = hipMemsetAsync(dL, 0, sizeof(double) * H.ncl * nx * R, st)) != hipSuccess ||
         (e = launch_basis(D, nx, dclo, dcsc, dcoff, op->b_lidx, op->b_nnz, op->b_Vinv, op->b_nleg, op->b_la, op->b_ld,
                           dLb, st)) != hipSuccess ||

@@ -902,18 +902,28 @@ __device__ __forceinline__ void cross_block(const double (&A)[2][NKC], const dou
     const int nct = (ns + 15) / 16;
     for (int ct = 0; ct < nct; ++ct) {
         const int j = 16 * ct + li;
-        const double nb = sN[j], qb = sQ[j];
+        const double nb = KIND == kGaussSplit ? 0.0 : sN[j], qb = sQ[j];
         double Bf[NKC];
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;  // uniform over the wave
-            dbl4 G = {rN[u][0], rN[u][1], rN[u][2], rN[u][3]};
+            // split Gaussian: A carries (2 log2(e) / ell)(x - c), the chain gives the base-2 exponent
+            // of the cross factor, the column factor sits in the charge and the row factor (rN)
+            // is applied to the row sums at the end
+            dbl4 G;
+            if constexpr (KIND == kGaussSplit)
+                G = dbl4{0.0, 0.0, 0.0, 0.0};
+            else
+                G = dbl4{rN[u][0], rN[u][1], rN[u][2], rN[u][3]};
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(A[u][kc], Bf[kc], G, 0, 0, 0);
 #pragma unroll
-            for (int v = 0; v < 4; ++v) racc[u][v] = fma(kernel_fast<KIND>(G[v] + nb, inv_ell), qb, racc[u][v]);
+            for (int v = 0; v < 4; ++v) {
+                const double kv = KIND == kGaussSplit ? exp2_bounded(G[v]) : kernel_fast<KIND>(G[v] + nb, inv_ell);
+                racc[u][v] = fma(kv, qb, racc[u][v]);
+            }
         }
     }
 }
@@ -949,10 +959,14 @@ __device__ __forceinline__ void p2p_cross_mfma_body(const DevTree &T, const DevO
             const double v = T.Xs[(size_t)k * n + ii] - cen[k];
             s = fma(v, v, s);
         }
-        tN[tid] = ok ? s : 0.0;
+        if constexpr (KIND == kGaussSplit)
+            tN[tid] = ok ? exp_bounded(-s * inv_ell) : 0.0;  // row factor
+        else
+            tN[tid] = ok ? s : 0.0;
     }
     const int rt[2] = {w, w + 4};
     double A[2][NKC];
+    const double scale = KIND == kGaussSplit ? 2.0 * 1.4426950408889634 * inv_ell : -2.0;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int i = 16 * rt[u] + li;
@@ -961,7 +975,7 @@ __device__ __forceinline__ void p2p_cross_mfma_body(const DevTree &T, const DevO
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
             const int k = 4 * kc + lg;
-            A[u][kc] = ok ? -2.0 * (T.Xs[(size_t)k * n + ii] - cen[k]) : 0.0;
+            A[u][kc] = ok ? scale * (T.Xs[(size_t)k * n + ii] - cen[k]) : 0.0;
         }
     }
     __syncthreads();
@@ -1026,7 +1040,10 @@ __device__ __forceinline__ void p2p_cross_mfma_body(const DevTree &T, const DevO
                     s = fma(v, v, s);
                 }
                 sN[j] = s;
-                sQ[j] = ok ? xs[pidx] : 0.0;
+                if constexpr (KIND == kGaussSplit)
+                    sQ[j] = ok ? xs[pidx] * exp_bounded(-s * inv_ell) : 0.0;  // charge times column factor
+                else
+                    sQ[j] = ok ? xs[pidx] : 0.0;
             }
             __syncthreads();
             cross_block<KIND, NKC>(A, rN, racc, sX, sN, sQ, ns, ntiles, w, li, lg, inv_ell);
@@ -1042,6 +1059,7 @@ __device__ __forceinline__ void p2p_cross_mfma_body(const DevTree &T, const DevO
             s += __shfl_xor(s, 2, 64);
             s += __shfl_xor(s, 4, 64);
             s += __shfl_xor(s, 8, 64);
+            if constexpr (KIND == kGaussSplit) s *= rN[u][v];  // row factor
             const int i = 16 * rt[u] + 4 * v + lg;
             if (li == 0) tN[i] = s;
         }
@@ -1057,7 +1075,7 @@ __device__ __forceinline__ void p2p_cross_mfma_body(const DevTree &T, const DevO
 }
 
 template <int KIND, int DK>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 24 ? 3 : 1, 8)))
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == kGaussSplit && DK <= 20 ? 4 : (DK <= 24 ? 3 : 1), 8)))
 void p2p_cross_mfma_kernel(DevTree T, DevOp O, DevTree Ts, const double *__restrict__ xs, double *__restrict__ y,
                            int do_far)
 {
@@ -2540,7 +2558,9 @@ hipError_t launch_eval(const DevTree &Tt, const DevOp &Ot, const DevTree &Ts, co
     if (nrhs == 1 && Os.kind <= 2 && Tt.max_leaf <= kSymLeaf && Tt.dpad <= 32) {
         switch (Os.kind) {
         case 0: return launch_cross_mfma_k<0>(Tt, Ot, Ts, Os.xt, y, far, st);
-        case 1: return launch_cross_mfma_k<1>(Tt, Ot, Ts, Os.xt, y, far, st);
+        case 1:
+            return Ot.gauss_split ? launch_cross_mfma_k<kGaussSplit>(Tt, Ot, Ts, Os.xt, y, far, st)
+                                  : launch_cross_mfma_k<1>(Tt, Ot, Ts, Os.xt, y, far, st);
         default: return launch_cross_mfma_k<2>(Tt, Ot, Ts, Os.xt, y, far, st);
         }
     }

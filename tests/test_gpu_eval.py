@@ -32,6 +32,10 @@ CASES = [
     # name, n, m, d, r, kernel, ell, q, leaf, eta, nrhs, target scale
     ("d4_matern", 6000, 2500, 4, 2.0, "matern32", 1.0, 5, 64, 0.8, 1, 1.1),
     ("d20_gauss_3rhs", 20000, 7000, 20, 3.0, "gaussian", 0.5, 6, 128, 0.8, 3, 1.05),
+    # one rhs on the MFMA cross nearfield: the Gaussian in split form (every exponent within range),
+    # and with a length scale so short that the split form is refused and the direct form runs
+    ("d20_gauss_1rhs", 20000, 7000, 20, 3.0, "gaussian", 0.5, 6, 128, 0.8, 1, 1.05),
+    ("d6_gauss_short", 6000, 2000, 6, 1.0, "gaussian", 2e-4, 4, 64, 0.8, 1, 1.1),
     ("d7_exp", 9000, 3000, 7, 2.0, "exponential", 0.3, 5, 100, 0.5, 1, 1.2),
     ("few_targets", 6000, 37, 4, 2.0, "matern32", 1.0, 4, 64, 0.8, 1, 1.0),
     ("one_target", 6000, 1, 4, 2.0, "matern32", 1.0, 4, 64, 0.8, 2, 1.0),
