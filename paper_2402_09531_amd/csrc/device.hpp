@@ -118,8 +118,9 @@ inline bool m2l_wpc_available(int nxt, int wpc) { return wpc == 4 || wpc == 2 ||
 hipError_t launch_batch_m2l(const BatchPlan &P, const BatchLaunch &L, hipStream_t stream);
 
 // ---- CG building blocks (FP64, deterministic fixed-order reductions) ----
-// partial[b][c] for b < kDotBlocks; out[c] = sum_b partial[b][c] in order.
-constexpr int kDotBlocks = 240;
+// partial[b][c] for b < kDotBlocks (the grid grows with n nrhs up to that); out[c] = sum_b partial[b][c]
+// by a fixed-order tree, so a result depends only on n, nrhs and the inputs.
+constexpr int kDotBlocks = 1024;
 hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double *partial, double *out,
                       hipStream_t stream);
 

@@ -9,6 +9,8 @@
 // throughout: it is the same operator, K~_{nu,nu'} = P_nu V^-1 S V^-T P_nu'^T.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include "device.hpp"
 
 namespace dwfmm {
@@ -2317,30 +2319,52 @@ void launch_p2p_batch_k(const BatchPlan &P, const BatchLaunch &L, hipStream_t st
 }
 
 // ---------------------------------------------------------------- deterministic dot products
+// Partial inner products of the columns of a and b (n rows of nrhs <= 32 values, row-major).
+// Block blockIdx.x takes rows [i0, i1); thread t handles column r = t mod nrhs in the row group
+// g = t / nrhs, rows i0 + g + G k, with G the largest power of two <= 256 / nrhs, so the G nrhs
+// active threads of a block read consecutive addresses.  The G group sums of each column are
+// added by a fixed pairwise tree in LDS: the result depends only on n, nrhs and the grid.
 __global__ __launch_bounds__(256) void dot_partial_kernel(const double *__restrict__ a, const double *__restrict__ b,
                                                           int n, int nrhs, double *__restrict__ partial)
 {
-    __shared__ double red[4];
+    __shared__ double red[256];
+    int G = 1;
+    while (2 * G * nrhs <= 256) G *= 2;
+    const int t = threadIdx.x, r = t % nrhs, g = t / nrhs;
     const int chunk = (n + gridDim.x - 1) / gridDim.x;
     const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
-    for (int r = 0; r < nrhs; ++r) {
-        double s = 0.0;
-        for (int i = i0 + (int)threadIdx.x; i < i1; i += blockDim.x) s = fma(a[(size_t)i * nrhs + r], b[(size_t)i * nrhs + r], s);
-        s = wave_sum(s);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
-        __syncthreads();
-        if (threadIdx.x == 0) partial[(size_t)blockIdx.x * nrhs + r] = ((red[0] + red[1]) + red[2]) + red[3];
-        __syncthreads();
+    double s0 = 0.0, s1 = 0.0;
+    if (g < G) {
+        int i = i0 + g;
+        for (; i + G < i1; i += 2 * G) {
+            s0 = fma(a[(size_t)i * nrhs + r], b[(size_t)i * nrhs + r], s0);
+            s1 = fma(a[(size_t)(i + G) * nrhs + r], b[(size_t)(i + G) * nrhs + r], s1);
+        }
+        if (i < i1) s0 = fma(a[(size_t)i * nrhs + r], b[(size_t)i * nrhs + r], s0);
     }
+    red[t] = s0 + s1;
+    for (int h = G / 2; h > 0; h >>= 1) {
+        __syncthreads();
+        if (g < h) red[t] += red[t + h * nrhs];
+    }
+    if (t < nrhs) partial[(size_t)blockIdx.x * nrhs + t] = red[t];
 }
 
-__global__ void dot_final_kernel(const double *__restrict__ partial, int nblocks, int nrhs, double *__restrict__ out)
+// out[r] = sum over blocks of partial[b][r]: one workgroup per column, thread t adds the blocks
+// t, t + 256, ... in order, then a fixed pairwise tree over the 256 threads.
+__global__ __launch_bounds__(256) void dot_final_kernel(const double *__restrict__ partial, int nblocks, int nrhs,
+                                                        double *__restrict__ out)
 {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= nrhs) return;
+    __shared__ double red[256];
+    const int r = blockIdx.x, t = threadIdx.x;
     double s = 0.0;
-    for (int b = 0; b < nblocks; ++b) s += partial[(size_t)b * nrhs + r];
-    out[r] = s;
+    for (int b = t; b < nblocks; b += 256) s += partial[(size_t)b * nrhs + r];
+    red[t] = s;
+    for (int h = 128; h > 0; h >>= 1) {
+        __syncthreads();
+        if (t < h) red[t] += red[t + h];
+    }
+    if (t == 0) out[r] = red[0];
 }
 
 }  // namespace
@@ -2575,8 +2599,12 @@ hipError_t launch_eval(const DevTree &Tt, const DevOp &Ot, const DevTree &Ts, co
 hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double *partial, double *out,
                       hipStream_t stream)
 {
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(kDotBlocks), dim3(256), 0, stream, a, b, n, nrhs, partial);
-    hipLaunchKernelGGL(dot_final_kernel, dim3((nrhs + 63) / 64), dim3(64), 0, stream, partial, kDotBlocks, nrhs, out);
+    if (nrhs < 1 || nrhs > 256) return hipErrorInvalidValue;
+    // at least 4096 values per block, at most kDotBlocks blocks (the partial buffer's rows)
+    const int64_t vals = (int64_t)n * nrhs;
+    const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (vals + 4095) / 4096));
+    hipLaunchKernelGGL(dot_partial_kernel, dim3(nblk), dim3(256), 0, stream, a, b, n, nrhs, partial);
+    hipLaunchKernelGGL(dot_final_kernel, dim3(nrhs), dim3(256), 0, stream, partial, nblk, nrhs, out);
     return hipGetLastError();
 }
 
