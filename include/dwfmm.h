@@ -158,10 +158,12 @@ dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, double q, co
 
 /* y = K~ x (Sec 5.2 eq. (LowRankBlock) on the farfield, kernel entries on the
  * nearfield), in the operator's precision.  x, y: device N x nrhs, distinct.
- * 1 <= nrhs <= max_nrhs.  Asynchronous on `stream`; allocates nothing.  With one
- * rhs the farfield (M2M, M2L, L2L) runs on the operator's own side stream beside
- * the nearfield, ordered after the P2M on `stream` and joined back into `stream`
- * before the final combine, so the result is ordered on `stream` as usual.  The
+ * 1 <= nrhs <= max_nrhs.  Asynchronous on `stream`; allocates nothing.  On the
+ * MFMA nearfield paths (one rhs, or up to 32 with leaves of at most 128 points and
+ * d <= 32) the farfield (M2M, M2L, L2L) runs on the operator's own side stream
+ * beside the nearfield, ordered after the P2M on `stream` and joined back into
+ * `stream` before the final combine or L2P, so the result is ordered on `stream`
+ * as usual.  The
  * call may be captured into a HIP graph from `stream`; while `stream` is capturing
  * all work stays on `stream` (no library object may be destroyed during a capture:
  * the destroy calls free device memory).  Calls on one operator must not overlap (they share

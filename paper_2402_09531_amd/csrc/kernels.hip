@@ -1367,6 +1367,22 @@ __global__ __launch_bounds__(kSymLeaf) void p2p_combine_kernel(DevTree T, DevOp 
     combine_body(T, O, blockIdx.x, y, do_near, do_far);
 }
 
+// Farfield evaluation (L2P) added to a several-rhs nearfield result that was computed beside the
+// farfield: y[perm i][r] += sum_a l_a(x_i) L_c[a][r] for the points i of leaf blockIdx.x (the sum
+// over a formed first, in order, then added once).
+__global__ __launch_bounds__(256) void l2p_add_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs)
+{
+    const int c = T.leaf_first + blockIdx.x;
+    const int cb = T.cbeg[c], nt = T.cend[c] - cb;
+    const double *lc = O.L + (size_t)c * O.nx * nrhs;
+    for (int e = threadIdx.x; e < nt * nrhs; e += blockDim.x) {
+        const int i = e / nrhs, r = e % nrhs;
+        double acc = 0.0;
+        for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * T.n + cb + i], lc[a * nrhs + r], acc);
+        y[(size_t)T.perm[cb + i] * nrhs + r] += acc;
+    }
+}
+
 template <int KIND>
 hipError_t launch_sym_k(const DevTree &T, const DevOp &O, hipStream_t st)
 {
@@ -2392,6 +2408,9 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
     const int far = (parts & 2) && T.min_far_level <= T.J;
     // symmetric MFMA nearfield for one rhs, leaves <= 128 points, d <= 32, radial kernels
     const bool sym = nrhs == 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && T.d <= 32 && O.rowbuf && O.colbuf;
+    // MFMA nearfield for several rhs (LDS: coordinates + charges stay below 64 KB)
+    const int dk = (T.d + 3) / 4 * 4;
+    const bool mrhs = nrhs > 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && dk <= 32 && !(dk > 28 && nrhs > 16);
     if (nrhs > 1 && T.max_leaf * nrhs <= 4096)
         hipLaunchKernelGGL(p2m_multi_kernel, dim3(T.nleaf), dim3(256), sizeof(double) * T.max_leaf * nrhs, main_st, T,
                            O, x, nrhs, far);
@@ -2400,11 +2419,12 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
                            far);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    // the symmetric nearfield does not read the locals: the farfield may run beside it (not
-    // while the caller's stream is being captured into a graph, which then holds the serial order)
+    // the symmetric nearfield does not read the locals, nor does the several-rhs one when its L2P
+    // is left to a later kernel: the farfield may run beside it (not while the caller's stream is
+    // being captured into a graph, which then holds the serial order)
     hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
     if (fork && fork->side && hipStreamIsCapturing(main_st, &cap) != hipSuccess) return hipGetLastError();
-    const bool split = far && near && sym && fork && fork->side && cap == hipStreamCaptureStatusNone;
+    const bool split = far && near && (sym || mrhs) && fork && fork->side && cap == hipStreamCaptureStatusNone;
     hipStream_t st = main_st;
     if (split) {
         if ((e = hipEventRecord(fork->forked, main_st)) != hipSuccess) return e;
@@ -2476,31 +2496,33 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
         hipLaunchKernelGGL(p2p_combine_kernel, dim3(T.nleaf), dim3(kSymLeaf), 0, st, T, O, y, near, far);
         return hipGetLastError();
     }
-    // MFMA nearfield for several rhs (LDS: coordinates + charges stay below 64 KB)
-    const int dk = (T.d + 3) / 4 * 4;
-    const bool mrhs = nrhs > 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && dk <= 32 && !(dk > 28 && nrhs > 16);
     if (mrhs) {
+        // split: the nearfield kernel writes the near part only; L2P adds the farfield after the join
+        const int nfar = split ? 0 : far;
         if (precision == 0) {
             switch (O.kind) {
-            case 0: e = launch_mrhs_k<0>(T, O, y, nrhs, near, far, st); break;
-            case 1: e = launch_mrhs_k<1>(T, O, y, nrhs, near, far, st); break;
-            default: e = launch_mrhs_k<2>(T, O, y, nrhs, near, far, st); break;
+            case 0: e = launch_mrhs_k<0>(T, O, y, nrhs, near, nfar, st); break;
+            case 1: e = launch_mrhs_k<1>(T, O, y, nrhs, near, nfar, st); break;
+            default: e = launch_mrhs_k<2>(T, O, y, nrhs, near, nfar, st); break;
             }
         } else if (precision == 1) {
             switch (O.kind) {
-            case 0: e = launch_mrhs_lp_k<0, false>(T, O, y, nrhs, near, far, st); break;
-            case 1: e = launch_mrhs_lp_k<1, false>(T, O, y, nrhs, near, far, st); break;
-            default: e = launch_mrhs_lp_k<2, false>(T, O, y, nrhs, near, far, st); break;
+            case 0: e = launch_mrhs_lp_k<0, false>(T, O, y, nrhs, near, nfar, st); break;
+            case 1: e = launch_mrhs_lp_k<1, false>(T, O, y, nrhs, near, nfar, st); break;
+            default: e = launch_mrhs_lp_k<2, false>(T, O, y, nrhs, near, nfar, st); break;
             }
         } else {
             switch (O.kind) {
-            case 0: e = launch_mrhs_lp_k<0, true>(T, O, y, nrhs, near, far, st); break;
-            case 1: e = launch_mrhs_lp_k<1, true>(T, O, y, nrhs, near, far, st); break;
-            default: e = launch_mrhs_lp_k<2, true>(T, O, y, nrhs, near, far, st); break;
+            case 0: e = launch_mrhs_lp_k<0, true>(T, O, y, nrhs, near, nfar, st); break;
+            case 1: e = launch_mrhs_lp_k<1, true>(T, O, y, nrhs, near, nfar, st); break;
+            default: e = launch_mrhs_lp_k<2, true>(T, O, y, nrhs, near, nfar, st); break;
             }
         }
         if (timer) (void)hipEventRecord(timer->p2p_stop, st);
-        return e;
+        if (e != hipSuccess || !split) return e;
+        if ((e = hipStreamWaitEvent(st, fork->joined, 0)) != hipSuccess) return e;
+        hipLaunchKernelGGL(l2p_add_kernel, dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs);
+        return hipGetLastError();
     }
     switch (O.kind) {
     case 0: e = launch_p2p_k<0>(T, O, y, nrhs, near, far, st); break;
