@@ -1733,7 +1733,7 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
 }
 
 template <int KIND, int DK, int RB, bool BF16>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 3 : 1, 8))) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 4 : 1, 8))) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
                                                           int do_near, int do_far)
 {
     constexpr int NKC = DK / 4;
