@@ -1307,8 +1307,13 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * rt[u] + 4 * v + lg;
                 double acc = Y[u][rb][v];
-                if (do_far && i < nt && r < nrhs)
-                    for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * n + cb + i], lc[a * nrhs + r], acc);
+                if (do_far && i < nt && r < nrhs) {
+                    // the farfield sum formed from zero and added once, as l2p_add_kernel does when
+                    // the farfield ran beside this kernel: both orders give the same bits
+                    double fs = 0.0;
+                    for (int a = 0; a < O.nx; ++a) fs = fma(O.Lb[(size_t)a * n + cb + i], lc[a * nrhs + r], fs);
+                    acc += fs;
+                }
                 if (i < nt && r < nrhs) y[(size_t)T.perm[cb + i] * nrhs + r] = acc;
             }
         }
@@ -1898,8 +1903,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * rt[u] + 4 * lg + v;
                 double acc = (double)Y[u][rb][v];
-                if (do_far && i < nt && r < nrhs)
-                    for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * n + cb + i], lc[a * nrhs + r], acc);
+                if (do_far && i < nt && r < nrhs) {
+                    // the farfield sum formed from zero and added once, as l2p_add_kernel does when
+                    // the farfield ran beside this kernel: both orders give the same bits
+                    double fs = 0.0;
+                    for (int a = 0; a < O.nx; ++a) fs = fma(O.Lb[(size_t)a * n + cb + i], lc[a * nrhs + r], fs);
+                    acc += fs;
+                }
                 if (i < nt && r < nrhs) y[(size_t)T.perm[cb + i] * nrhs + r] = acc;
             }
         }

@@ -441,6 +441,32 @@ def test_matvec_on_a_user_stream_and_from_a_graph():
     say("[stream/graph] user stream and 4 graph replays bitwise equal to the eager matvec")
 
 
+@pytest.mark.parametrize("nrhs,prec", [(3, "fp64"), (20, "fp32")])
+def test_several_rhs_matvec_from_a_graph(nrhs, prec):
+    """With several rhs the eager matvec runs the farfield beside the nearfield and adds the
+    farfield evaluation afterwards; under capture everything stays on one stream and the
+    nearfield kernel adds it itself.  Both must give the same bits."""
+    n, d = 20000, 8
+    X = W.points(n, d, 2.0, 63)
+    b = W.dim_weights(d, 2.0)
+    _, op = gpu_op(X, b, 128, 0.8, "gaussian", 0.5, 5, nrhs=nrhs)
+    x = torch.from_numpy(np.random.default_rng(64).standard_normal((n, nrhs))).cuda()
+    y_ref = torch.empty_like(x)
+    dw.fmm_matvec(op, x, y_ref, precision=prec)
+    torch.cuda.synchronize()
+    yg = torch.zeros_like(x)
+    g = torch.cuda.CUDAGraph()
+    gc.collect()
+    with torch.cuda.graph(g, capture_error_mode="thread_local"):
+        dw.fmm_matvec(op, x, yg, precision=prec)
+    for rep in range(3):
+        yg.zero_()
+        g.replay()
+        torch.cuda.synchronize()
+        assert torch.equal(yg, y_ref), rep
+    say(f"[graph x{nrhs} {prec}] 3 replays bitwise equal to the eager matvec")
+
+
 @pytest.mark.parametrize("case", [
     # name, n, d, r, q, leaf, nrhs: d = 64 and leaf 1024 (the largest accepted) with n_x * d near
     # its cap of 3072 (n_x = 46); n_x = 127 just below its cap of 128
