@@ -1357,7 +1357,17 @@ __device__ __forceinline__ void combine_body(const DevTree &T, const DevOp &O, i
     double acc = 0.0;
     if (do_near) {
         acc = O.rowbuf[(size_t)l * kSymLeaf + i];
-        for (int q = T.inc_ptr[l]; q < T.inc_ptr[l + 1]; ++q) acc += O.colbuf[(size_t)T.inc_blk[q] * kSymLeaf + i];
+        // eight column sums in flight at a time, added in list order
+        const int q1 = T.inc_ptr[l + 1];
+        int q = T.inc_ptr[l];
+        for (; q + 8 <= q1; q += 8) {
+            double v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = O.colbuf[(size_t)T.inc_blk[q + k] * kSymLeaf + i];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) acc += v[k];
+        }
+        for (; q < q1; ++q) acc += O.colbuf[(size_t)T.inc_blk[q] * kSymLeaf + i];
     }
     if (do_far) {
         const double *lc = O.L + (size_t)c * O.nx;
