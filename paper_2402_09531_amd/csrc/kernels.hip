@@ -2428,7 +2428,8 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
     const int far = (parts & 2) && T.min_far_level <= T.J;
     // symmetric MFMA nearfield for one rhs, leaves <= 128 points, d <= 32, radial kernels
     const bool sym = nrhs == 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && T.d <= 32 && O.rowbuf && O.colbuf;
-    // MFMA nearfield for several rhs (LDS: coordinates + charges stay below 64 KB)
+    // MFMA nearfield for several rhs (LDS of the FP64 kernel: at most 66 KB, at d <= 28 with two
+    // 16-wide rhs tiles; gfx950 gives a workgroup up to 160 KB)
     const int dk = (T.d + 3) / 4 * 4;
     const bool mrhs = nrhs > 1 && O.kind <= 2 && T.max_leaf <= kSymLeaf && dk <= 32 && !(dk > 28 && nrhs > 16);
     if (nrhs > 1 && T.max_leaf * nrhs <= 4096)

@@ -59,6 +59,8 @@ CASES = [
     ("d20_gauss_r32", 8000, 20, 3.0, "gaussian", 0.5, 6, 128, 0.8, 32),
     ("d10_matern_r17", 6000, 10, 2.0, "matern32", 1.0, 6, 128, 0.8, 17),
     ("d4_exp_r16", 3000, 4, 2.0, "exponential", 0.4, 4, 64, 0.8, 16),
+    # the largest tile of the FP64 several-rhs kernel: d padded to 28 with two rhs tiles (66 KB LDS)
+    ("d27_gauss_r20", 4000, 27, 3.0, "gaussian", 0.5, 5, 128, 0.8, 20),
     # general (non-symmetric) nearfield kernel: leaves above 128 points, d above 32, wide rhs at d > 28
     ("d3_leaf200", 20000, 3, 2.0, "matern32", 1.0, 5, 200, 0.8, 1),
     ("d40_gauss", 5000, 40, 3.0, "gaussian", 0.5, 6, 128, 0.8, 1),
