@@ -1603,11 +1603,24 @@ extern "C" dwfmm_status dwfmm_eval_create(dwfmm_op op, const double *targets, in
         for (int a = 0; a < nx; ++a)
             for (int k = 0; k < d; ++k)
                 nodes_p[((size_t)c * nx + a) * dp + k] = nodes[((size_t)c * nx + a) * d + k];
+    // axis-major zero-padded nodes and squared node norms for the MFMA coupling (as for the operator)
+    const int dkx = (d + 3) / 4 * 4, nxp = op->D.nxp;
+    std::vector<double> nodesT((size_t)H.ncl * dkx * nxp, 0.0), nnorm((size_t)H.ncl * nxp, 0.0);
+    for (int64_t c = 0; c < H.ncl; ++c)
+        for (int a = 0; a < nx; ++a) {
+            double sq = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double v = nodes[((size_t)c * nx + a) * d + k];
+                nodesT[((size_t)c * dkx + k) * nxp + a] = v;
+                sq += v * v;
+            }
+            nnorm[(size_t)c * nxp + a] = sq;
+        }
     transfer_matrices(H, op->B, E);
 
     auto up = [&](auto **dst, const auto &v) { return ev->arena.upload(dst, v, st); };
     hipError_t e = hipSuccess;
-    double *dXs, *dclo, *dcsc, *dcoff, *dnodes, *dE, *dLb, *dL;
+    double *dXs, *dclo, *dcsc, *dcoff, *dnodes, *dE, *dLb, *dL, *dnodesT = nullptr, *dnnorm = nullptr;
     int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs;
     const size_t R = (size_t)op->max_nrhs;
     if ((e = up(&dXs, Xs)) != hipSuccess || (e = up(&dperm, H.perm)) != hipSuccess ||
@@ -1616,7 +1629,8 @@ extern "C" dwfmm_status dwfmm_eval_create(dwfmm_op op, const double *targets, in
         (e = up(&dNp, nptr_leaf)) != hipSuccess || (e = up(&dNs, nsrc_local)) != hipSuccess ||
         (e = up(&dclo, clo)) != hipSuccess || (e = up(&dcsc, csc)) != hipSuccess ||
         (e = up(&dcoff, coff)) != hipSuccess || (e = up(&dnodes, nodes_p)) != hipSuccess ||
-        (e = up(&dE, E)) != hipSuccess ||
+        (e = up(&dE, E)) != hipSuccess || (e = up(&dnodesT, nodesT)) != hipSuccess ||
+        (e = up(&dnnorm, nnorm)) != hipSuccess ||
         (e = ev->arena.alloc((void **)&dLb, sizeof(double) * nx * (size_t)m)) != hipSuccess ||
         (e = ev->arena.alloc((void **)&dL, sizeof(double) * H.ncl * nx * R)) != hipSuccess) {
         ev->arena.release();
@@ -1652,6 +1666,8 @@ extern "C" dwfmm_status dwfmm_eval_create(dwfmm_op op, const double *targets, in
     O.Lb = dLb;
     O.L = dL;
     O.nxp = op->D.nxp;
+    O.nodesT = op->D.nodesT ? dnodesT : nullptr;  // the MFMA coupling needs both sides' layouts
+    O.nnorm = op->D.nnorm ? dnnorm : nullptr;
     // Split Gaussian in the cross nearfield, exp(-|x-c|^2/ell) exp(-|y-c|^2/ell) exp(2 (x-c).(y-c)/ell)
     // with c the target leaf's first point: |x - c| <= 2 r_t and |y - c| <= r_t + |m_t - m_s| + r_s
     // (r: half box diagonals, m: box midpoints), so with B = 2 r_t + |m_t - m_s| + r_s over all cross

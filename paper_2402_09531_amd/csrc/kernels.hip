@@ -352,7 +352,8 @@ __global__ __launch_bounds__(256) void m2l_cross_kernel(DevTree T, DevOp Ot, Dev
 // result is bitwise the same for every WPC.  part: this cluster's [4][NXP] slice of LDS;
 // every wave reaches the barrier (an idle slot passes valid = false).
 template <int KIND, int DK, int NXT, int WPC>
-__device__ __forceinline__ void m2l_mfma_body(const DevTree &T, const DevOp &O, int c, bool valid, double *part)
+__device__ __forceinline__ void m2l_mfma_body(const DevTree &T, const DevOp &O, const DevOp &Os, int c, bool valid,
+                                              double *part)
 {
     constexpr int NKC = DK / 4, NXP = 16 * NXT, RPW = 4 / WPC;
     const int nx = O.nx;
@@ -381,15 +382,15 @@ __device__ __forceinline__ void m2l_mfma_body(const DevTree &T, const DevOp &O, 
             const int f = base + k * WPC;  // class wi + k WPC
             if (f >= f1) break;            // uniform over the wave
             const int s = T.Fsrc[f];
-            const double *snode = O.nodesT + (size_t)s * DK * NXP;
+            const double *snode = Os.nodesT + (size_t)s * DK * NXP;
 #pragma unroll
             for (int ct = 0; ct < NXT; ++ct) {
                 const int b = 16 * ct + li;
                 double B[NKC];
 #pragma unroll
                 for (int kc = 0; kc < NKC; ++kc) B[kc] = snode[(4 * kc + lg) * NXP + b];
-                const double nb = O.nnorm[(size_t)s * NXP + b];
-                const double mb = b < nx ? O.M[(size_t)s * nx + b] : 0.0;
+                const double nb = Os.nnorm[(size_t)s * NXP + b];
+                const double mb = b < nx ? Os.M[(size_t)s * nx + b] : 0.0;
 #pragma unroll
                 for (int rt = 0; rt < NXT; ++rt) {
                     dbl4 G = {0.0, 0.0, 0.0, 0.0};
@@ -426,7 +427,42 @@ template <int KIND, int DK, int NXT>
 __global__ __launch_bounds__(256) void m2l_mfma_kernel(DevTree T, DevOp O, int first)
 {
     __shared__ double part[4 * 16 * NXT];
-    m2l_mfma_body<KIND, DK, NXT, 4>(T, O, first + blockIdx.x, true, part);
+    m2l_mfma_body<KIND, DK, NXT, 4>(T, O, O, first + blockIdx.x, true, part);
+}
+
+// The coupling of an evaluation: target clusters of the target tree (its cross farfield lists
+// name source clusters), source nodes and moments from the source operator.
+template <int KIND, int DK, int NXT>
+__global__ __launch_bounds__(256) void m2l_cross_mfma_kernel(DevTree Tt, DevOp Ot, DevOp Os, int first)
+{
+    __shared__ double part[4 * 16 * NXT];
+    m2l_mfma_body<KIND, DK, NXT, 4>(Tt, Ot, Os, first + blockIdx.x, true, part);
+}
+
+template <int KIND, int DK>
+void launch_m2l_cross_mfma_d(const DevTree &Tt, const DevOp &Ot, const DevOp &Os, int first, int cnt, hipStream_t st)
+{
+    switch (Os.nxp / 16) {
+    case 1: hipLaunchKernelGGL((m2l_cross_mfma_kernel<KIND, DK, 1>), dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first); break;
+    case 2: hipLaunchKernelGGL((m2l_cross_mfma_kernel<KIND, DK, 2>), dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first); break;
+    case 3: hipLaunchKernelGGL((m2l_cross_mfma_kernel<KIND, DK, 3>), dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first); break;
+    default: hipLaunchKernelGGL((m2l_cross_mfma_kernel<KIND, DK, 4>), dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first); break;
+    }
+}
+
+template <int KIND>
+void launch_m2l_cross_mfma_k(const DevTree &Tt, const DevOp &Ot, const DevOp &Os, int first, int cnt, hipStream_t st)
+{
+    switch ((Tt.d + 3) / 4 * 4) {
+    case 4: launch_m2l_cross_mfma_d<KIND, 4>(Tt, Ot, Os, first, cnt, st); break;
+    case 8: launch_m2l_cross_mfma_d<KIND, 8>(Tt, Ot, Os, first, cnt, st); break;
+    case 12: launch_m2l_cross_mfma_d<KIND, 12>(Tt, Ot, Os, first, cnt, st); break;
+    case 16: launch_m2l_cross_mfma_d<KIND, 16>(Tt, Ot, Os, first, cnt, st); break;
+    case 20: launch_m2l_cross_mfma_d<KIND, 20>(Tt, Ot, Os, first, cnt, st); break;
+    case 24: launch_m2l_cross_mfma_d<KIND, 24>(Tt, Ot, Os, first, cnt, st); break;
+    case 28: launch_m2l_cross_mfma_d<KIND, 28>(Tt, Ot, Os, first, cnt, st); break;
+    default: launch_m2l_cross_mfma_d<KIND, 32>(Tt, Ot, Os, first, cnt, st); break;
+    }
 }
 
 template <int KIND, int DK>
@@ -2240,7 +2276,7 @@ __global__ __launch_bounds__(256) void m2l_batch_kernel(const BatchItem *items, 
         const int2 wk = q < cnt ? work[q] : make_int2(-1, 0);
         const bool valid = wk.x >= 0;
         const BatchItem &I = items[valid ? wk.x : 0];
-        m2l_mfma_body<KIND, DK, NXT, WPC>(I.T, I.O, wk.y, valid, part[slot]);
+        m2l_mfma_body<KIND, DK, NXT, WPC>(I.T, I.O, I.O, wk.y, valid, part[slot]);
     }
 }
 
@@ -2611,7 +2647,15 @@ hipError_t launch_eval(const DevTree &Tt, const DevOp &Ot, const DevTree &Ts, co
             hipLaunchKernelGGL(m2m_kernel, dim3(1 << j), dim3(64), 0, st, Ts, Os, (1 << j) - 1, nrhs);
         const int first = (1 << Tt.min_far_level) - 1;
         const int cnt = Tt.ncl - first;
-        switch (Os.kind) {
+        // one rhs, radial kernels, d <= 32, n_x <= 64: node-pair distances on FP64 MFMA
+        const bool mfma = nrhs == 1 && Os.kind <= 2 && Tt.d <= 32 && Os.nxp <= 64 && Ot.nodesT && Ot.nnorm &&
+                          Os.nodesT && Os.nnorm;
+        if (mfma) switch (Os.kind) {
+        case 0: launch_m2l_cross_mfma_k<0>(Tt, Ot, Os, first, cnt, st); break;
+        case 1: launch_m2l_cross_mfma_k<1>(Tt, Ot, Os, first, cnt, st); break;
+        default: launch_m2l_cross_mfma_k<2>(Tt, Ot, Os, first, cnt, st); break;
+        }
+        else switch (Os.kind) {
         case 0: hipLaunchKernelGGL(m2l_cross_kernel<0>, dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first, nrhs); break;
         case 1: hipLaunchKernelGGL(m2l_cross_kernel<1>, dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first, nrhs); break;
         case 2: hipLaunchKernelGGL(m2l_cross_kernel<2>, dim3(cnt), dim3(256), 0, st, Tt, Ot, Os, first, nrhs); break;
