@@ -58,6 +58,44 @@ def test_weight_rule_R3_normalised(orc):
     assert np.allclose(om, 1.0 + np.log(g / g[0]), rtol=1e-14)
 
 
+def test_weight_rule_R2_values(orc):
+    """Reading R2: omega_k = 1 + log2(b_1/b_k); for b_k = k^-2 that is 1 + 2 log2 k: 1, 3, 1 + 2 log2 3, 5."""
+    om = orc.weights(orc.W_R2, W.dim_weights(4, 2))
+    assert np.allclose(om, [1.0, 3.0, 1.0 + 2.0 * math.log2(3.0), 5.0], rtol=0, atol=1e-15)
+    # b_k = k^-3 on eight axes: 1 + 3 log2 k, so omega_2, omega_4, omega_8 = 4, 7, 10
+    om8 = orc.weights(orc.W_R2, W.dim_weights(8, 3))
+    assert np.allclose(om8[[0, 1, 3, 7]], [1.0, 4.0, 7.0, 10.0], rtol=0, atol=1e-14)
+    # a constant box gives the total degree weights omega = 1 (Sec 6.1 TDI)
+    assert np.array_equal(orc.weights(orc.W_R2, np.full(5, 0.3)), np.ones(5))
+
+
+def test_weight_rule_thm_closed_form(orc):
+    """Thm 4.6: omega_k = log(2 tau_k + sqrt(1 + 4 tau_k^2)), which is arcsinh(2 tau_k).  At tau = 1
+    the argument is 2 + sqrt 5 = phi^3 (phi the golden ratio), so omega = 3 log phi; at tau = 0 it is 0;
+    for large tau, omega ~ log(4 tau)."""
+    phi = (1.0 + math.sqrt(5.0)) / 2.0
+    tau = np.array([1.0, 0.0, 0.75, 1e6])
+    om = orc.weights(orc.W_THM, aux=tau)
+    assert abs(om[0] - 3.0 * math.log(phi)) < 2e-15
+    assert om[1] == 0.0
+    # 2 * 0.75 = 1.5 and sqrt(1 + 1.5^2) = 1.80277..., arcsinh from numpy (a different formula)
+    assert abs(om[2] - float(np.arcsinh(1.5))) < 2e-15
+    assert abs(om[3] - math.log(4e6)) < 1e-12
+    tk = np.arange(1, 21, dtype=float) ** 2  # the Sec 6.1 setting tau_k = k^2
+    assert np.allclose(orc.weights(orc.W_THM, aux=tk), np.arcsinh(2.0 * tk), rtol=1e-15, atol=0)
+
+
+def test_weight_rule_R3_as_arcsinh(orc):
+    """Sec 6.2 rule through the identity log g(tau) = arcsinh(2 tau): omega_k = 1 + arcsinh(2 tau_k) -
+    arcsinh(2 tau_1) with tau_k = 1/(eta b_k).  At b_k = k^-2 and eta = 0.8 this is
+    (1, 2.35, 3.16, 3.73) to two decimals, the values the weight comparison quotes."""
+    b = W.dim_weights(4, 2)
+    om = orc.weights(orc.W_R3, b, eta=0.8)
+    tau = 1.0 / (0.8 * b)
+    assert np.allclose(om, 1.0 + np.arcsinh(2 * tau) - np.arcsinh(2 * tau[0]), rtol=0, atol=1e-14)
+    assert np.allclose(np.round(om, 2), [1.0, 2.35, 3.16, 3.73], rtol=0, atol=1e-12)
+
+
 def test_count_wtdi_paper_worst_case_unpinned(orc):
     """Sec 6.1 prints 244 points at d=20, q=10, tau_k=k^2.  No weight reading reproduces it exactly
     (parity unpinned); the Thm 4.6 weights give a count of the same order and the counts grow
