@@ -321,6 +321,10 @@ const char *dwfmm_last_error(void);
 /* ---- introspection (host copies; for tests and statistics) ---------------- */
 /* out[0..7] = n, d, J, ncl (clusters), nF (farfield blocks), nN (nearfield blocks), nleaf, leaf_size */
 dwfmm_status dwfmm_tree_info(dwfmm_tree tree, int64_t *out);
+/* Nearfield list statistics: out[0..2] = the most blocks one leaf owns in the symmetric
+ * nearfield (its self block plus the unordered pairs dealt to it), the longest nearfield
+ * list of a leaf, and the number of owned blocks.  Host values; E_INVALID on NULL.    */
+dwfmm_status dwfmm_tree_stats(dwfmm_tree tree, int64_t *out);
 /* Tree order and boxes: perm[n] (tree position -> original index), begin/end[ncl],
  * lo/hi[ncl*d]; farfield CSR by target cluster Fptr[ncl+1], Fsrc[nF]; nearfield
  * CSR by target cluster Nptr[ncl+1], Nsrc[nN].  Any pointer may be NULL.      */

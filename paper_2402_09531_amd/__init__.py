@@ -66,7 +66,7 @@ _lib = None
 
 EXPORTS = ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
            "dwfmm_fmm_solve", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
-           "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info",
+           "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_stats", "dwfmm_tree_get", "dwfmm_op_info",
            "dwfmm_op_basis", "dwfmm_op_lebesgue", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
            "dwfmm_batch_m2l_shapes", "dwfmm_batch_m2l_layout", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
            "dwfmm_eval_info", "dwfmm_eval_tree_get", "dwfmm_eval_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
@@ -99,6 +99,7 @@ def lib():
         L.dwfmm_tree_destroy.restype = None
         L.dwfmm_last_error.restype = C.c_char_p
         L.dwfmm_tree_info.argtypes = [vp, i64p]
+        L.dwfmm_tree_stats.argtypes = [vp, i64p]
         L.dwfmm_tree_get.argtypes = [vp, i64p, i64p, i64p, dp, dp, i64p, i64p, i64p, i64p]
         L.dwfmm_op_info.argtypes = [vp, i64p]
         L.dwfmm_op_basis.argtypes = [vp, C.POINTER(C.c_uint8), dp, dp, dp]
@@ -141,7 +142,7 @@ def lib():
         L.dwfmm_server_destroy.restype = None
         for name in ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm_fmm_matvec",
                      "dwfmm_fmm_matvec_parts",
-                     "dwfmm_fmm_solve", "dwfmm_tree_info", "dwfmm_tree_get", "dwfmm_op_info", "dwfmm_op_basis",
+                     "dwfmm_fmm_solve", "dwfmm_tree_info", "dwfmm_tree_stats", "dwfmm_tree_get", "dwfmm_op_info", "dwfmm_op_basis",
                      "dwfmm_op_lebesgue", "dwfmm_op_moments", "dwfmm_op_timing"]:
             getattr(L, name).restype = C.c_int
         _lib = L
@@ -198,6 +199,13 @@ class Tree:
                                     _i64(Fs), _i64(Np), _i64(Ns)))
         return dict(perm=perm, begin=b, end=e, lo=lo, hi=hi, Fptr=Fp, Fsrc=Fs[:self.nF], Nptr=Np,
                     Nsrc=Ns[:self.nN])
+
+    def stats(self):
+        """dwfmm_tree_stats: (most blocks one leaf owns in the symmetric nearfield, longest nearfield
+        list of a leaf, owned blocks in total)."""
+        out = np.zeros(3, dtype=np.int64)
+        _check(lib().dwfmm_tree_stats(self._h, _i64(out)))
+        return int(out[0]), int(out[1]), int(out[2])
 
     def near_entries(self) -> float:
         """E_N = sum over nearfield blocks |nu||nu'|."""

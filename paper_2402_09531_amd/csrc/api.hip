@@ -87,6 +87,7 @@ struct dwfmm_tree_s {
     // max over nearfield leaf pairs (t, s) of (R_t + |c_s - c_t| + R_s)^2, R the half diagonal and
     // c the midpoint of a leaf box: bounds every squared shifted distance the nearfield forms
     double near_reach2 = 0.0;
+    int64_t own_max = 0, own_total = 0, near_max = 0;  // symmetric-nearfield ownership statistics
     int refs = 1;       // the caller's reference plus one per operator
     bool destroyed = false;
     int device = 0;
@@ -218,6 +219,11 @@ static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, in
             owned.push_back({o, p});
         }
     std::sort(owned.begin(), owned.end());
+    t->own_total = (int64_t)owned.size();
+    for (int64_t l = 0; l < H.nleaf; ++l) {
+        t->own_max = std::max<int64_t>(t->own_max, own_cnt[l]);
+        t->near_max = std::max<int64_t>(t->near_max, nptr_leaf[l + 1] - nptr_leaf[l]);
+    }
     std::vector<int32_t> own_ptr(H.nleaf + 1, 0), own_src(owned.size()), inc_ptr(H.nleaf + 1, 0), inc_blk;
     for (auto &op : owned) own_ptr[op.first + 1]++;
     for (int64_t l = 0; l < H.nleaf; ++l) own_ptr[l + 1] += own_ptr[l];
@@ -1793,6 +1799,15 @@ extern "C" dwfmm_status dwfmm_tree_info(dwfmm_tree t, int64_t *out)
     out[5] = (int64_t)H.Nsrc.size();
     out[6] = H.nleaf;
     out[7] = H.leaf;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_tree_stats(dwfmm_tree t, int64_t *out)
+{
+    if (!t || !out) return fail(DWFMM_E_INVALID, "NULL argument");
+    out[0] = t->own_max;
+    out[1] = t->near_max;
+    out[2] = t->own_total;
     return DWFMM_OK;
 }
 

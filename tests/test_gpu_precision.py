@@ -2,9 +2,12 @@
 
 FP32 mode: nearfield and coupling in FP32 (Gram tiles on FP32 MFMA, hardware exp2);
 BF16 mode: as FP32, and with several right-hand sides the nearfield product K Q runs on
-BF16 MFMA with FP32 accumulation.  The error bounds below are the stated accuracy of
-each mode (relative 2-norm over the output against the FP64 oracle).  The solve refines
-in FP64 and must reach the FP64 tolerance.
+BF16 MFMA with FP32 accumulation (with one rhs BF16 runs the FP32 nearfield).  The error
+bounds below are the stated accuracy of each mode against the FP64 oracle, about three times
+the largest error measured over these cases: the relative 2-norm over the output, and the
+largest entry error against its row scale (K~|x|)_i (all kernels here are positive, so K~|x|
+is the FMM value of the sum of absolute terms).  The solve refines in FP64 and must reach the
+FP64 tolerance.
 """
 import sys
 
@@ -17,7 +20,8 @@ pytestmark = pytest.mark.gpu
 import paper_2402_09531_amd as dw  # noqa: E402
 from paper_2402_09531_amd import workloads as W  # noqa: E402
 
-BOUND = {"fp32": 1e-5, "bf16": 2e-2}
+NORM_BOUND = {("fp32", False): 5e-6, ("fp32", True): 6e-6, ("bf16", False): 5e-6, ("bf16", True): 6e-3}
+ROW_BOUND = {("fp32", False): 1.5e-7, ("fp32", True): 5e-7, ("bf16", False): 1.5e-7, ("bf16", True): 4e-4}
 
 
 def say(*a):
@@ -54,9 +58,14 @@ def test_reduced_precision_matvec_error(orc, case, prec):
     dw.fmm_matvec(op, xd, yd, precision=prec)
     torch.cuda.synchronize()
     y_ref = P.matvec(x)
-    e = rel(yd.cpu().numpy(), y_ref)
-    say(f"[{prec}] {name}: relative error vs FP64 oracle {e:.3e}")
-    assert e <= BOUND[prec]
+    y = yd.cpu().numpy()
+    e = rel(y, y_ref)
+    # element-wise: each entry's error against its row scale (K~|x|)_i (all three kernels are positive)
+    ya = P.matvec(np.abs(x))
+    er = float(np.max(np.abs(y - y_ref) / ya))
+    say(f"[{prec}] {name}: relative error vs FP64 oracle {e:.3e}, largest entry error / row scale {er:.3e}")
+    assert e <= NORM_BOUND[(prec, nrhs > 1)]
+    assert er <= ROW_BOUND[(prec, nrhs > 1)]
     assert e > 1e-13  # the reduced path really ran
 
 
@@ -77,9 +86,12 @@ def test_reduced_precision_coincident_points(orc, prec, nrhs):
     yd = torch.empty_like(xd)
     dw.fmm_matvec(op, xd, yd, precision=prec)
     torch.cuda.synchronize()
-    e = rel(yd.cpu().numpy(), P.matvec(x))
-    say(f"[{prec} coincident x{nrhs}] relative error vs FP64 oracle {e:.3e}")
-    assert e <= BOUND[prec]
+    y, y_ref = yd.cpu().numpy(), P.matvec(x)
+    e = rel(y, y_ref)
+    er = float(np.max(np.abs(y - y_ref) / P.matvec(np.abs(x))))
+    say(f"[{prec} coincident x{nrhs}] relative error vs FP64 oracle {e:.3e}, largest entry error / row scale {er:.3e}")
+    assert e <= NORM_BOUND[(prec, nrhs > 1)]
+    assert er <= ROW_BOUND[(prec, nrhs > 1)]
 
 
 @pytest.mark.parametrize("prec,nrhs", [("fp32", 1), ("fp32", 4), ("bf16", 4)])
