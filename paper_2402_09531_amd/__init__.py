@@ -65,7 +65,7 @@ class SolveInfo(C.Structure):
 _lib = None
 
 EXPORTS = ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm_fmm_matvec", "dwfmm_fmm_matvec_parts",
-           "dwfmm_fmm_solve", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
+           "dwfmm_fmm_solve", "dwfmm_fmm_matvec_static", "dwfmm_estimate_bytes", "dwfmm_op_bytes", "dwfmm_op_destroy",
            "dwfmm_tree_destroy", "dwfmm_last_error", "dwfmm_tree_info", "dwfmm_tree_stats", "dwfmm_tree_get", "dwfmm_op_info",
            "dwfmm_op_basis", "dwfmm_op_lebesgue", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
            "dwfmm_batch_m2l_shapes", "dwfmm_batch_m2l_layout", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
@@ -86,6 +86,7 @@ def lib():
                                           vp, C.POINTER(vp)]
         L.dwfmm_fmm_create.argtypes = [vp, _Kernel, C.c_double, C.POINTER(_Opts), vp, C.POINTER(vp)]
         L.dwfmm_fmm_matvec.argtypes = [vp, vp, vp, C.c_int32, vp]
+        L.dwfmm_fmm_matvec_static.argtypes = [vp, vp, vp, C.c_int32, vp]
         L.dwfmm_fmm_matvec_parts.argtypes = [vp, vp, vp, C.c_int32, C.c_int32, C.c_int32, vp]
         L.dwfmm_fmm_solve.argtypes = [vp, C.c_double, vp, vp, C.c_int32, C.c_double, C.c_int32, vp,
                                       C.POINTER(SolveInfo)]
@@ -141,6 +142,7 @@ def lib():
         L.dwfmm_server_destroy.argtypes = [vp]
         L.dwfmm_server_destroy.restype = None
         for name in ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm_fmm_matvec",
+                     "dwfmm_fmm_matvec_static",
                      "dwfmm_fmm_matvec_parts",
                      "dwfmm_fmm_solve", "dwfmm_tree_info", "dwfmm_tree_stats", "dwfmm_tree_get", "dwfmm_op_info", "dwfmm_op_basis",
                      "dwfmm_op_lebesgue", "dwfmm_op_moments", "dwfmm_op_timing"]:
@@ -326,6 +328,26 @@ def fmm_matvec(op: Op, x, y, stream=None, parts: int | None = None, precision: s
         prec = op.precision if precision is None else PRECISIONS[precision]
         _check(lib().dwfmm_fmm_matvec_parts(op._h, _dev_f64(x, "x"), _dev_f64(y, "y"), nrhs,
                                             3 if parts is None else int(parts), prec, _stream(stream)))
+
+
+STATIC_SCRATCH_BYTES = 64 << 20
+
+
+def fmm_matvec_static(op: Op, x, y, stream=None):
+    """dwfmm_fmm_matvec_static: y = K~ x with the library's static per-GPU workspace (allocates
+    nothing; calls on one GPU must not overlap)."""
+    nrhs = 1 if x.dim() == 1 else x.shape[1]
+    _check(lib().dwfmm_fmm_matvec_static(op._h, _dev_f64(x, "x"), _dev_f64(y, "y"), nrhs, _stream(stream)))
+
+
+def static_scratch_bytes(op: Op, nrhs: int) -> int:
+    """Workspace bytes of dwfmm_fmm_matvec_static (the header's formula; each part rounded to 256)."""
+    a = lambda b: (b + 255) // 256 * 256  # noqa: E731
+    t = op.tree
+    need = a(8 * t.n * nrhs) + 2 * a(8 * t.ncl * op.nx * nrhs)
+    if nrhs == 1:
+        need += a(1024 * t.nleaf) + a(1024 * t.stats()[2])
+    return need
 
 
 def fmm_solve(op: Op, lam: float, f, alpha, rtol: float, max_iter: int = 10000, stream=None,

@@ -557,6 +557,86 @@ extern "C" dwfmm_status dwfmm_fmm_matvec(dwfmm_op op, const double *x, double *y
     return dwfmm_fmm_matvec_parts(op, x, y, nrhs, 3, op->precision, stream);
 }
 
+// ============================================================== allocation-free matvec
+// The per-call workspace of a matvec (charges in tree order, moments, locals, nearfield row and
+// column sums) taken from one file-scope device array instead of the operator's buffers.  Each
+// GPU holds its own copy of the array; host code reaches it only through the address that
+// hipGetSymbolAddress returns on that device (the array's name is no device address on the host).
+namespace {
+constexpr size_t kStaticScratchBytes = DWFMM_STATIC_SCRATCH_BYTES;
+constexpr int kMaxDevices = 64;
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices] = {};
+
+size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+}  // namespace
+
+// The device address of this GPU's scratch array, looked up once per device (with that device
+// current, as the caller's device is here).
+static dwfmm_status static_scratch(int dev, void **out)
+{
+    if (dev < 0 || dev >= kMaxDevices) return fail(DWFMM_E_INVALID, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress((void **)&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !ptr)
+            return fail(DWFMM_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return DWFMM_OK;
+}
+
+// Workspace bytes of one allocation-free matvec: every part starts at a multiple of 256 bytes.
+static size_t static_scratch_need(dwfmm_op op, int32_t nrhs)
+{
+    const DevTree &T = op->tree->D;
+    const size_t n = (size_t)T.n, nx = (size_t)op->D.nx, r = (size_t)nrhs;
+    size_t b = align256(sizeof(double) * n * r) + 2 * align256(sizeof(double) * (size_t)T.ncl * nx * r);
+    if (nrhs == 1) b += align256(sizeof(double) * 128 * (size_t)T.nleaf) + align256(sizeof(double) * 128 * (size_t)T.nblk);
+    return b;
+}
+
+extern "C" dwfmm_status dwfmm_fmm_matvec_static(dwfmm_op op, const double *x, double *y, int32_t nrhs, void *stream)
+{
+    if (!op) return fail(DWFMM_E_INVALID, "op is NULL");
+    if (!x || !y) return fail(DWFMM_E_INVALID, "x or y is NULL");
+    if (x == y) return fail(DWFMM_E_INVALID, "x and y must be distinct");
+    if (nrhs < 1 || nrhs > 32) return fail(DWFMM_E_INVALID, "nrhs must be in [1, 32]");
+    const size_t need = static_scratch_need(op, nrhs);
+    if (need > kStaticScratchBytes)
+        return fail(DWFMM_E_INVALID, "workspace of " + std::to_string(need) + " bytes exceeds the static scratch of " +
+                                         std::to_string(kStaticScratchBytes) + " bytes");
+    int dev = -1;
+    HIP_TRY(hipGetDevice(&dev));
+    if (dev != op->tree->device) return fail(DWFMM_E_INVALID, "the operator's device must be current");
+    void *base = nullptr;
+    const dwfmm_status s = static_scratch(dev, &base);
+    if (s != DWFMM_OK) return s;
+    const DevTree &T = op->tree->D;
+    const size_t n = (size_t)T.n, nx = (size_t)op->D.nx, r = (size_t)nrhs;
+    unsigned char *p = (unsigned char *)base;
+    DevOp O = op->D;  // the operator's tables, this call's workspace
+    O.xt = (double *)p;
+    p += align256(sizeof(double) * n * r);
+    O.M = (double *)p;
+    p += align256(sizeof(double) * (size_t)T.ncl * nx * r);
+    O.L = (double *)p;
+    p += align256(sizeof(double) * (size_t)T.ncl * nx * r);
+    if (nrhs == 1) {
+        O.rowbuf = (double *)p;
+        p += align256(sizeof(double) * 128 * (size_t)T.nleaf);
+        O.colbuf = (double *)p;
+    } else {
+        O.rowbuf = O.colbuf = nullptr;  // only the one-rhs symmetric nearfield uses them
+    }
+    O.max_nrhs = nrhs;
+    HIP_TRY(launch_matvec(T, O, x, y, nrhs, 3, op->precision, (hipStream_t)stream, nullptr, &op->fork));
+    return DWFMM_OK;
+}
+
 // ============================================================== CG
 namespace {
 

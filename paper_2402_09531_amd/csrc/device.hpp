@@ -24,7 +24,7 @@ struct DevTree {
     // its two leaves (balanced); the owner evaluates the block once and applies it both
     // ways.  own: CSR over owner leaves of partner leaves, block id = CSR position.
     // inc: CSR over partner leaves of the block ids whose column sums they receive.
-    int nblk;                     // number of off-diagonal owned blocks
+    int nblk;                     // number of owned blocks of the symmetric nearfield (self blocks included)
     const int32_t *own_ptr, *own_src, *inc_ptr, *inc_blk;
     const double *center;         // [nleaf][dpad] leaf box midpoints (coordinate shift)
 };
