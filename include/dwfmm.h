@@ -62,7 +62,12 @@ typedef struct {
 typedef enum { DWFMM_W_R1 = 0, DWFMM_W_R2 = 1, DWFMM_W_R3 = 2, DWFMM_W_EXPLICIT = 3 } dwfmm_weight_rule;
 
 /* Arithmetic of the coupling (M2L) and nearfield (P2P) stages.  Geometry,
- * moments, transfers, CG inner products and residuals are always FP64.   */
+ * moments, transfers, CG inner products and residuals are always FP64.
+ *   FP32  distances on FP32 MFMA, kernel values and sums in FP32
+ *   BF16  FP32 mode, and with several rhs the products on BF16 MFMA with FP32
+ *         accumulation: the nearfield K Q with K and Q rounded to BF16, the
+ *         coupling S m with S and m each carried as a pair of BF16 numbers
+ *         (three products); with one rhs it is FP32 mode                    */
 typedef enum { DWFMM_FP64 = 0, DWFMM_FP32 = 1, DWFMM_BF16 = 2 } dwfmm_precision;
 
 /* Interpolation nodes on the reference box (Sec 5.4 and the per-axis reading):
@@ -99,6 +104,8 @@ typedef struct {
     void (*progress)(void *ctx, int32_t iteration, int32_t nrhs, const double *rel_res);
     void *progress_ctx;
     int32_t index_rule;      /* dwfmm_index_rule, default WEIGHTED_TOTAL_DEGREE */
+    int32_t ir_max_inner;    /* reduced precision: max inner CG iterations per refinement step
+                                (0 = up to the solve's remaining max_iter) */
 } dwfmm_opts;
 
 /* Per right-hand-side result of dwfmm_fmm_solve. */

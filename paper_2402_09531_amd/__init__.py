@@ -43,7 +43,8 @@ class _Opts(C.Structure):
     _fields_ = [("weight_rule", C.c_int32), ("omega", C.POINTER(C.c_double)), ("precision", C.c_int32),
                 ("max_nrhs", C.c_int32), ("check_every", C.c_int32), ("ir_inner_rtol", C.c_double),
                 ("ir_max_outer", C.c_int32), ("node_rule", C.c_int32), ("afp_candidates", C.c_int32),
-                ("progress", C.c_void_p), ("progress_ctx", C.c_void_p), ("index_rule", C.c_int32)]
+                ("progress", C.c_void_p), ("progress_ctx", C.c_void_p), ("index_rule", C.c_int32),
+                ("ir_max_inner", C.c_int32)]
 
 
 # void (*)(void *ctx, int32_t iteration, int32_t nrhs, const double *rel_res)
@@ -300,7 +301,7 @@ def build_tree(points, dim_weights, leaf_size: int, eta: float, stream=None, adm
 def fmm_create(tree: Tree, kernel: str, ell: float, q: float, precision: str = "fp64", max_nrhs: int = 1,
                weight_rule: str = "R1", omega=None, check_every: int = 1, ir_inner_rtol: float = 0.0,
                ir_max_outer: int = 30, nodes: str = "cheb_leja", afp_candidates: int = 0, progress=None,
-               index_set: str = "weighted_total_degree", stream=None) -> Op:
+               index_set: str = "weighted_total_degree", ir_max_inner: int = 0, stream=None) -> Op:
     """dwfmm_fmm_create (nodes: "cheb_leja" or "afp", the approximate Fekete points; index_set:
     "weighted_total_degree" or "tensor"; progress: optional callable(iteration, rel_res list) run at
     the solver's host convergence checks)."""
@@ -310,7 +311,8 @@ def fmm_create(tree: Tree, kernel: str, ell: float, q: float, precision: str = "
         cb = _PROGRESS(lambda _ctx, it, n, rr: progress(int(it), [rr[i] for i in range(n)]))
     opts = _Opts(WEIGHT_RULES[weight_rule], _f64p(om), PRECISIONS[precision], int(max_nrhs), int(check_every),
                  float(ir_inner_rtol), int(ir_max_outer), NODE_RULES[nodes], int(afp_candidates),
-                 C.cast(cb, C.c_void_p) if cb is not None else None, None, INDEX_RULES[index_set])
+                 C.cast(cb, C.c_void_p) if cb is not None else None, None, INDEX_RULES[index_set],
+                 int(ir_max_inner))
     h = C.c_void_p()
     _check(lib().dwfmm_fmm_create(tree._h, _Kernel(KERNELS[kernel], float(ell)), float(q), C.byref(opts),
                                   _stream(stream), C.byref(h)))

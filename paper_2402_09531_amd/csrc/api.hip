@@ -98,7 +98,7 @@ struct dwfmm_op_s {
     HostBasis B;
     DevOp D{};
     Arena arena;
-    int precision = 0, max_nrhs = 1, check_every = 1, ir_max_outer = 30;
+    int precision = 0, max_nrhs = 1, check_every = 1, ir_max_outer = 30, ir_max_inner = 0;
     double ir_inner_rtol = 0.0;
     void (*progress)(void *, int32_t, int32_t, const double *) = nullptr;
     void *progress_ctx = nullptr;
@@ -344,6 +344,7 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     if (o.node_rule < 0 || o.node_rule > 1 || o.afp_candidates < 0)
         return fail(DWFMM_E_INVALID, "unknown node rule or negative candidate count");
     if (o.index_rule < 0 || o.index_rule > 1) return fail(DWFMM_E_INVALID, "unknown index rule");
+    if (o.ir_max_inner < 0) return fail(DWFMM_E_INVALID, "ir_max_inner must be >= 0");
     const HostTree &H = tree->H;
     hipStream_t st = (hipStream_t)stream;
 
@@ -472,6 +473,7 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     op->check_every = o.check_every;
     op->ir_inner_rtol = o.ir_inner_rtol;
     op->ir_max_outer = o.ir_max_outer;
+    op->ir_max_inner = o.ir_max_inner;
     op->progress = o.progress;
     op->progress_ctx = o.progress_ctx;
     op->b_lidx = dlidx;
@@ -867,8 +869,8 @@ extern "C" dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double
             HIP_TRY(hipMemcpyAsync(op->state + 3 * op->max_nrhs, mask.data(), sizeof(int32_t) * nrhs,
                                    hipMemcpyHostToDevice, st));
             HIP_TRY(hipMemsetAsync(op->ir_d, 0, sizeof(double) * total, st));
-            HIP_TRY(cg_run(op, lambda, op->ir_r, op->ir_d, nrhs, rtol_in, max_iter - used, op->precision, st, hstate,
-                           hrr));
+            const int inner = op->ir_max_inner > 0 ? std::min(op->ir_max_inner, max_iter - used) : max_iter - used;
+            HIP_TRY(cg_run(op, lambda, op->ir_r, op->ir_d, nrhs, rtol_in, inner, op->precision, st, hstate, hrr));
             int most = 0;
             for (int c = 0; c < nrhs; ++c) {
                 if (mask[c]) continue;

@@ -1993,28 +1993,46 @@ hipError_t launch_mrhs_lp_k(const DevTree &T, const DevOp &O, double *y, int nrh
 // ---------------------------------------------------------------- M2L for several rhs on MFMA
 // l_c[a][r] += sum_b S[a][b] m_s[b][r] over the farfield sources s of c.  As in the several-rhs
 // nearfield, the Gram tile of node pairs is formed with the source nodes as the A operand so
-// its elements are the A operand of the apply MFMAs.  FP32 = false: FP64 throughout (element
-// v of lane (a + 16 g) is S[a][4v + g]); FP32 = true: FP32 Gram/kernel/apply (element e of lane
-// (a + 16 g) is S[a][4g + e]).  nx <= 32 (two node tiles), up to 32 rhs (two rhs tiles); the
-// four waves split the source list and their partial sums are added in wave order.
-template <bool FP32>
-struct m2l_types;
-template <>
-struct m2l_types<false> {
-    typedef double T;
-    typedef dbl4 V;
-};
-template <>
-struct m2l_types<true> {
+// its elements are the A operand of the apply MFMAs.  PREC 0: FP64 throughout (element v of
+// lane (a + 16 g) is S[a][4v + g]).  PREC 1: FP32 Gram/kernel/apply (element e of lane
+// (a + 16 g) is S[a][4g + e], the A operand of chunk e of four v_mfma_f32_16x16x4f32).
+// PREC 2: as PREC 1 up to the kernel values; the product S m then runs on BF16 MFMA with FP32
+// accumulation: the four elements of a lane are the A operand of v_mfma_f32_16x16x16bf16_1k
+// (A[a][k] in lane a + 16(k/4), element k%4, k = source node 4g + e) and the moments its B
+// operand (lane r + 16g holds nodes 4g..4g+3 of rhs r).  Both operands are carried as BF16
+// pairs hi + lo (lo the rounding remainder of hi), and the three products lo.hi, hi.lo, hi.hi
+// are accumulated (the dropped lo.lo is below 2^-16 of the product): a single BF16 rounding
+// of S and m costs ~7e-3 relative in the farfield through the interpolation's Lebesgue
+// constant, enough to stall or reverse the FP64 refinement on small shifts.  nx <= 32 (two
+// node tiles), up to 32 rhs (two rhs tiles); the four waves split the source list and their
+// partial sums are added in wave order.
+// v = hi + lo + O(2^-16 |v|) with hi, lo in BF16 (lo the BF16 rounding of v - hi)
+__device__ __forceinline__ void bf16_pair(const float (&v)[4], bf16x4 &hi, bf16x4 &lo)
+{
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        hi[e] = (__bf16)v[e];
+        lo[e] = (__bf16)(v[e] - (float)hi[e]);
+    }
+}
+
+template <int PREC>
+struct m2l_types {
     typedef float T;
     typedef flt4 V;
 };
+template <>
+struct m2l_types<0> {
+    typedef double T;
+    typedef dbl4 V;
+};
 
-template <int KIND, int DK, bool FP32>
+template <int KIND, int DK, int PREC>
 __global__ __launch_bounds__(256) void m2l_mrhs_kernel(DevTree T, DevOp O, int first, int nrhs)
 {
-    typedef typename m2l_types<FP32>::T R;
-    typedef typename m2l_types<FP32>::V V4;
+    typedef typename m2l_types<PREC>::T R;
+    typedef typename m2l_types<PREC>::V V4;
+    constexpr bool LP = PREC != 0;
     constexpr int NKC = DK / 4;
     __shared__ double part[32 * 33];
     const int c = first + blockIdx.x;
@@ -2050,22 +2068,26 @@ __global__ __launch_bounds__(256) void m2l_mrhs_kernel(DevTree T, DevOp O, int f
             R sn[4], Mq[2][4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const int b = FP32 ? 16 * ct + 4 * lg + e : 16 * ct + 4 * e + lg;  // source node of element e
+                const int b = LP ? 16 * ct + 4 * lg + e : 16 * ct + 4 * e + lg;  // source node of element e
                 sn[e] = (R)O.nnorm[(size_t)s * nxp + b];
 #pragma unroll
                 for (int rb = 0; rb < 2; ++rb) {
                     // B operand of chunk e: lane (r + 16 g) holds m_s[source node][rhs 16 rb + r]
-                    const int bb = FP32 ? 16 * ct + 4 * lg + e : 16 * ct + 4 * e + lg;
                     const int r = 16 * rb + li;
-                    Mq[rb][e] = (bb < nx && r < nrhs && rb < nrb) ? (R)ms[(size_t)bb * nrhs + r] : (R)0;
+                    Mq[rb][e] = (b < nx && r < nrhs && rb < nrb) ? (R)ms[(size_t)b * nrhs + r] : (R)0;
                 }
+            }
+            bf16x4 Mh[2], Ml[2];  // PREC 2: the moments as BF16 pairs
+            if constexpr (PREC == 2) {
+#pragma unroll
+                for (int rb = 0; rb < 2; ++rb) bf16_pair(Mq[rb], Mh[rb], Ml[rb]);
             }
 #pragma unroll
             for (int rt = 0; rt < 2; ++rt) {
                 if (rt >= nxt) continue;
                 V4 G = {0, 0, 0, 0};
                 R Kv[4];
-                if constexpr (FP32) {
+                if constexpr (LP) {
 #pragma unroll
                     for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[kc], Bt[rt][kc], G, 0, 0, 0);
 #pragma unroll
@@ -2077,21 +2099,34 @@ __global__ __launch_bounds__(256) void m2l_mrhs_kernel(DevTree T, DevOp O, int f
 #pragma unroll
                     for (int e = 0; e < 4; ++e) Kv[e] = kernel_fast<KIND>(fmax(fma(-2.0, G[e], tn[rt] + sn[e]), 0.0), inv_ell);
                 }
+                if constexpr (PREC == 2) {
+                    bf16x4 Kh, Kl;
+                    bf16_pair(Kv, Kh, Kl);
 #pragma unroll
-                for (int rb = 0; rb < 2; ++rb) {
-                    if (rb >= nrb) continue;
+                    for (int rb = 0; rb < 2; ++rb) {
+                        if (rb >= nrb) continue;
+                        // the two small cross terms first, then the leading product
+                        Y[rt][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Kl, Mh[rb], Y[rt][rb], 0, 0, 0);
+                        Y[rt][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Kh, Ml[rb], Y[rt][rb], 0, 0, 0);
+                        Y[rt][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Kh, Mh[rb], Y[rt][rb], 0, 0, 0);
+                    }
+                } else {
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) {
-                        if constexpr (FP32)
-                            Y[rt][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Kv[e], Mq[rb][e], Y[rt][rb], 0, 0, 0);
-                        else
-                            Y[rt][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kv[e], Mq[rb][e], Y[rt][rb], 0, 0, 0);
+                    for (int rb = 0; rb < 2; ++rb) {
+                        if (rb >= nrb) continue;
+#pragma unroll
+                        for (int e = 0; e < 4; ++e) {
+                            if constexpr (LP)
+                                Y[rt][rb] = __builtin_amdgcn_mfma_f32_16x16x4f32(Kv[e], Mq[rb][e], Y[rt][rb], 0, 0, 0);
+                            else
+                                Y[rt][rb] = __builtin_amdgcn_mfma_f64_16x16x4f64(Kv[e], Mq[rb][e], Y[rt][rb], 0, 0, 0);
+                        }
                     }
                 }
             }
         }
     }
-    // output element v of lane (r + 16 g): target node 4g + v (FP32) or 4v + g (FP64), rhs r
+    // output element v of lane (r + 16 g): target node 4g + v (PREC 1, 2) or 4v + g (FP64), rhs r
     for (int ww = 0; ww < 4; ++ww) {
         if (w == ww) {
 #pragma unroll
@@ -2100,7 +2135,7 @@ __global__ __launch_bounds__(256) void m2l_mrhs_kernel(DevTree T, DevOp O, int f
                 for (int rb = 0; rb < 2; ++rb)
 #pragma unroll
                     for (int v = 0; v < 4; ++v) {
-                        const int a = 16 * rt + (FP32 ? 4 * lg + v : 4 * v + lg), r = 16 * rb + li;
+                        const int a = 16 * rt + (LP ? 4 * lg + v : 4 * v + lg), r = 16 * rb + li;
                         const double val = (double)Y[rt][rb][v];
                         part[a * 33 + r] = ww == 0 ? val : part[a * 33 + r] + val;
                     }
@@ -2113,12 +2148,12 @@ __global__ __launch_bounds__(256) void m2l_mrhs_kernel(DevTree T, DevOp O, int f
     }
 }
 
-template <int KIND, bool FP32>
+template <int KIND, int PREC>
 void launch_m2l_mrhs_k(const DevTree &T, const DevOp &O, int first, int cnt, int nrhs, hipStream_t st)
 {
     switch ((T.d + 3) / 4 * 4) {
 #define DWFMM_M2LR(D) \
-    case D: hipLaunchKernelGGL((m2l_mrhs_kernel<KIND, D, FP32>), dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
+    case D: hipLaunchKernelGGL((m2l_mrhs_kernel<KIND, D, PREC>), dim3(cnt), dim3(256), 0, st, T, O, first, nrhs); break;
         DWFMM_M2LR(4) DWFMM_M2LR(8) DWFMM_M2LR(12) DWFMM_M2LR(16) DWFMM_M2LR(20) DWFMM_M2LR(24) DWFMM_M2LR(28)
     default:
         DWFMM_M2LR(32)
@@ -2497,12 +2532,16 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
         const bool mfma = nrhs == 1 && O.kind <= 2 && T.d <= 32 && O.nxp <= 64 && O.nodesT && O.nnorm;
         const bool mfma_r = nrhs > 1 && O.kind <= 2 && T.d <= 32 && O.nxp <= 32 && O.nodesT && O.nnorm;
         if (mfma_r) {
-            const bool lp = precision != 0;
+#define DWFMM_M2LR_PREC(K)                                                      \
+    (precision == 0   ? launch_m2l_mrhs_k<K, 0>(T, O, first, cnt, nrhs, st)     \
+     : precision == 1 ? launch_m2l_mrhs_k<K, 1>(T, O, first, cnt, nrhs, st)     \
+                      : launch_m2l_mrhs_k<K, 2>(T, O, first, cnt, nrhs, st))
             switch (O.kind) {
-            case 0: lp ? launch_m2l_mrhs_k<0, true>(T, O, first, cnt, nrhs, st) : launch_m2l_mrhs_k<0, false>(T, O, first, cnt, nrhs, st); break;
-            case 1: lp ? launch_m2l_mrhs_k<1, true>(T, O, first, cnt, nrhs, st) : launch_m2l_mrhs_k<1, false>(T, O, first, cnt, nrhs, st); break;
-            default: lp ? launch_m2l_mrhs_k<2, true>(T, O, first, cnt, nrhs, st) : launch_m2l_mrhs_k<2, false>(T, O, first, cnt, nrhs, st); break;
+            case 0: DWFMM_M2LR_PREC(0); break;
+            case 1: DWFMM_M2LR_PREC(1); break;
+            default: DWFMM_M2LR_PREC(2); break;
             }
+#undef DWFMM_M2LR_PREC
         } else if (mfma && precision != 0) {
             switch (O.kind) {
             case 0: launch_m2l32_k<0>(T, O, first, cnt, st); break;

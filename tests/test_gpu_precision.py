@@ -1,8 +1,9 @@
 """Reduced-precision modes against the FP64 oracle, and FP64 iterative refinement.
 
 FP32 mode: nearfield and coupling in FP32 (Gram tiles on FP32 MFMA, hardware exp2);
-BF16 mode: as FP32, and with several right-hand sides the nearfield product K Q runs on
-BF16 MFMA with FP32 accumulation (with one rhs BF16 runs the FP32 nearfield).  The error
+BF16 mode: as FP32, and with several right-hand sides the nearfield product K Q and the
+coupling product S m run on BF16 MFMA with FP32 accumulation (with one rhs there is no
+product for a BF16 MFMA to carry, and BF16 runs the FP32 nearfield and coupling).  The error
 bounds below are the stated accuracy of each mode against the FP64 oracle, about three times
 the largest error measured over these cases: the relative 2-norm over the output, and the
 largest entry error against its row scale (K~|x|)_i (all kernels here are positive, so K~|x|
@@ -117,3 +118,44 @@ def test_iterative_refinement_reaches_fp64_tolerance(orc, prec, nrhs):
         assert infos[c]["refine_steps"] >= 1
         assert res[c] <= 1.05 * rtol
         assert abs(res[c] - infos[c]["rel_res_true"]) <= 1e-3 * rtol + 1e-12 * res[c]
+
+
+# Farfield only, several rhs: FP32 and the BF16 coupling against the oracle's FP64 farfield.  The
+# BF16 coupling evaluates S in FP32 and applies it on v_mfma_f32_16x16x16bf16_1k with FP32
+# accumulation, S and the moments each carried as a pair of BF16 numbers (three products, each
+# product good to about 2^-16); the bounds are about three times the measured errors.
+FAR_NORM_BOUND = {"fp32": 6e-6, "bf16": 1.2e-4}
+FAR_ROW_BOUND = {"fp32": 1.5e-6, "bf16": 1.1e-5}
+
+
+@pytest.mark.parametrize("case", [
+    # name, n, d, r, kernel, ell, q, leaf, eta, nrhs: one and two node tiles, one and two rhs tiles
+    ("d20_gauss_32rhs", 12000, 20, 3.0, "gaussian", 0.5, 6, 128, 0.8, 32),
+    ("d10_matern_17rhs", 15000, 10, 2.0, "matern32", 1.0, 6, 128, 0.8, 17),
+    ("d7_exp_5rhs", 8000, 7, 2.0, "exponential", 0.3, 5, 100, 0.5, 5),
+], ids=lambda c: c[0])
+def test_reduced_precision_coupling_several_rhs(orc, case):
+    name, n, d, r, kind, ell, q, leaf, eta, nrhs = case
+    rng = np.random.default_rng(31 + n)
+    X = W.points(n, d, r, n + 1, rng)
+    b = W.dim_weights(d, r)
+    x = rng.standard_normal((n, nrhs))
+    P = orc.Plan(X, b, leaf, eta, kind, ell, q)
+    assert P.nx <= 32  # the MFMA coupling for several rhs
+    tree = dw.build_tree(torch.from_numpy(X).cuda(), b, leaf, eta)
+    op = dw.fmm_create(tree, kind, ell, q, max_nrhs=nrhs)
+    xd = torch.from_numpy(x).cuda()
+    y_ref = P.matvec(x, parts=2)
+    ya = P.matvec(np.abs(x), parts=2)
+    ys = {}
+    for prec in ("fp32", "bf16"):
+        yd = torch.full_like(xd, float("nan"))
+        dw.fmm_matvec(op, xd, yd, parts=2, precision=prec)
+        torch.cuda.synchronize()
+        y = ys[prec] = yd.cpu().numpy()
+        e = rel(y, y_ref)
+        er = float(np.max(np.abs(y - y_ref) / np.abs(ya)))
+        say(f"[{prec} farfield] {name} n_x={P.nx}: relative error vs FP64 oracle {e:.3e}, "
+            f"largest entry error / row scale {er:.3e}")
+        assert e <= FAR_NORM_BOUND[prec] and er <= FAR_ROW_BOUND[prec]
+    assert not np.array_equal(ys["bf16"], ys["fp32"])  # the BF16 products really ran
