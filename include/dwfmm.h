@@ -258,6 +258,25 @@ dwfmm_status dwfmm_batch_m2l_layout(dwfmm_batch batch, int32_t *grid, double *ms
 /* y_i = K~_i x_i for every problem i.  xs, ys: host arrays of count device pointers
  * (N_i x 1 each, caller order, x_i != y_i).  Asynchronous on `stream`; allocates nothing. */
 dwfmm_status dwfmm_batch_matvec(dwfmm_batch batch, const double *const *xs, double *const *ys, void *stream);
+/* Solve (K~_i + lambda I) alpha_i = f_i (eq. (LGS)) for every problem of the batch at once:
+ * one CG iteration per problem in lockstep, each iteration one batched matvec (the batch's
+ * plan, or a plan over the problems still iterating once they are at most half of it) and
+ * one launch per CG vector step for all problems.  Per problem the arithmetic is that of
+ * dwfmm_fmm_solve with one rhs on its operator, so each alpha_i, its iteration count and its
+ * residuals are bitwise those of solving problem i alone.  All operators must share one
+ * precision: FP64 runs CG; FP32/BF16 runs the iterative refinement of dwfmm_fmm_solve with
+ * the operators' refinement options (FP64 residuals on an FP64 plan of the same problems,
+ * built at the first such call and kept with the batch).  The solve uses each operator's
+ * CG workspace (max_nrhs >= 1 suffices).
+ *   fs, alphas  host arrays of count device pointers, N_i x 1 each, caller order; alpha_i
+ *               is the start vector on entry and the solution on return; alpha_i != f_i
+ *   check_every iterations between reads of the problems' states (each read synchronises)
+ *   infos       host array of count entries
+ * Synchronises `stream`.  Returns the worst per-problem status.
+ * Errors: E_INVALID (also mixed precisions), E_NOMEM, E_HIP, E_NOT_CONVERGED, E_BREAKDOWN. */
+dwfmm_status dwfmm_batch_solve(dwfmm_batch batch, double lambda, const double *const *fs, double *const *alphas,
+                               double rtol, int32_t max_iter, int32_t check_every, void *stream,
+                               dwfmm_solve_info *infos);
 void dwfmm_batch_destroy(dwfmm_batch batch);
 
 /* ---- evaluation at new points ------------------------------------------------
@@ -331,10 +350,17 @@ dwfmm_status dwfmm_server_result(dwfmm_server server, int64_t id, double *alpha,
 size_t dwfmm_server_bytes(dwfmm_server server);
 void dwfmm_server_destroy(dwfmm_server server);
 
-/* Device bytes an operator would hold for the given sizes (admission control). */
+/* Device bytes a tree plus operator would hold for the given sizes, from the sizes alone: an
+ * estimate (the nearfield column sums, 1 KiB per owned leaf pair, are counted at 128 owned
+ * pairs per leaf; the true count depends on the geometry).  The solve server reserves this
+ * for a request first and re-checks with dwfmm_op_bytes_for once the request's tree is built. */
 size_t dwfmm_estimate_bytes(int64_t n, int32_t d, int32_t leaf_size, int32_t n_x, int32_t nrhs);
 /* Device bytes held by a tree plus operator. */
 size_t dwfmm_op_bytes(dwfmm_op op);
+/* Exactly the device bytes dwfmm_op_bytes will report for dwfmm_fmm_create(tree, kernel, q,
+ * opts) on this tree (any kernel), computed on the host before anything is allocated; 0 for
+ * invalid arguments or an index set that cannot be built.                               */
+size_t dwfmm_op_bytes_for(dwfmm_tree tree, double q, const dwfmm_opts *opts);
 
 void dwfmm_op_destroy(dwfmm_op op);
 /* Destroying a tree that an operator still references is deferred until that operator is destroyed. */

@@ -71,7 +71,7 @@ EXPORTS = ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm
            "dwfmm_op_basis", "dwfmm_op_lebesgue", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
            "dwfmm_batch_m2l_shapes", "dwfmm_batch_m2l_layout", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
            "dwfmm_eval_info", "dwfmm_eval_tree_get", "dwfmm_eval_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
-           "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy"]
+           "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy", "dwfmm_batch_solve", "dwfmm_op_bytes_for"]
 
 
 def lib():
@@ -95,6 +95,8 @@ def lib():
         L.dwfmm_estimate_bytes.restype = C.c_size_t
         L.dwfmm_op_bytes.argtypes = [vp]
         L.dwfmm_op_bytes.restype = C.c_size_t
+        L.dwfmm_op_bytes_for.argtypes = [vp, C.c_double, C.POINTER(_Opts)]
+        L.dwfmm_op_bytes_for.restype = C.c_size_t
         L.dwfmm_op_destroy.argtypes = [vp]
         L.dwfmm_op_destroy.restype = None
         L.dwfmm_tree_destroy.argtypes = [vp]
@@ -118,6 +120,9 @@ def lib():
         L.dwfmm_batch_m2l_layout.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_double), C.c_int32,
                                              C.POINTER(C.c_int32)]
         L.dwfmm_batch_m2l_layout.restype = C.c_int
+        L.dwfmm_batch_solve.argtypes = [vp, C.c_double, C.POINTER(vp), C.POINTER(vp), C.c_double, C.c_int32,
+                                        C.c_int32, vp, C.POINTER(SolveInfo)]
+        L.dwfmm_batch_solve.restype = C.c_int
         L.dwfmm_eval_create.argtypes = [vp, vp, C.c_int64, vp, C.POINTER(vp)]
         L.dwfmm_eval_create.restype = C.c_int
         L.dwfmm_eval_apply.argtypes = [vp, vp, vp, C.c_int32, vp]
@@ -484,6 +489,24 @@ def batch_matvec(batch: Batch, xs, ys, stream=None):
     _check(lib().dwfmm_batch_matvec(batch._h, xa, ya, _stream(stream)))
 
 
+def batch_solve(batch: Batch, lam: float, fs, alphas, rtol: float, max_iter: int = 10000, check_every: int = 8,
+                stream=None, raise_on_status: bool = False):
+    """dwfmm_batch_solve: (K~_i + lam I) alphas[i] = fs[i] for every operator of the batch (alphas hold
+    the start vectors and receive the solutions).  Returns one info dict per problem; a
+    not-converged or breakdown status is reported in the infos (raised only with raise_on_status)."""
+    n = len(batch.ops)
+    if len(fs) != n or len(alphas) != n:
+        raise ValueError("fs and alphas must have one tensor per operator")
+    fa = (C.c_void_p * n)(*[_dev_f64(f, "f").value for f in fs])
+    aa = (C.c_void_p * n)(*[_dev_f64(a, "alpha").value for a in alphas])
+    infos = (SolveInfo * n)()
+    st = lib().dwfmm_batch_solve(batch._h, float(lam), fa, aa, float(rtol), int(max_iter), int(check_every),
+                                 _stream(stream), infos)
+    if st not in (OK, E_NOT_CONVERGED, E_BREAKDOWN) or (raise_on_status and st != OK):
+        _check(st)
+    return [infos[i].as_dict() for i in range(n)]
+
+
 class _Request(C.Structure):
     _fields_ = [("n", C.c_int64), ("d", C.c_int32), ("points", C.POINTER(C.c_double)),
                 ("dim_weights", C.POINTER(C.c_double)), ("f", C.POINTER(C.c_double)), ("leaf_size", C.c_int32),
@@ -546,6 +569,20 @@ class Server:
             self.close()
         except Exception:
             pass
+
+
+def op_bytes(op: Op) -> int:
+    """dwfmm_op_bytes: device bytes held by the operator and its tree."""
+    return int(lib().dwfmm_op_bytes(op._h))
+
+
+def op_bytes_for(tree: Tree, q: float, precision: str = "fp64", max_nrhs: int = 1, weight_rule: str = "R1",
+                 omega=None, nodes: str = "cheb_leja", index_set: str = "weighted_total_degree") -> int:
+    """dwfmm_op_bytes_for: the device bytes an operator with these options would hold on this tree."""
+    om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
+    opts = _Opts(WEIGHT_RULES[weight_rule], _f64p(om), PRECISIONS[precision], int(max_nrhs), 1, 0.0, 30,
+                 NODE_RULES[nodes], 0, None, None, INDEX_RULES[index_set], 0)
+    return int(lib().dwfmm_op_bytes_for(tree._h, float(q), C.byref(opts)))
 
 
 def estimate_bytes(n: int, d: int, leaf_size: int, n_x: int, nrhs: int) -> int:

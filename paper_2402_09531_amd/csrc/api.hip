@@ -8,6 +8,7 @@
 #include <condition_variable>
 #include <cstring>
 #include <deque>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
@@ -79,8 +80,16 @@ int pad_dim(int d) { return d <= 32 ? (d + 3) / 4 * 4 : (d + 7) / 8 * 8; }
 
 }  // namespace
 
+// Host arrays of a tree built but not yet uploaded (the tree's device arrays, in upload order).
+struct TreeStage {
+    std::vector<double> Xs, clo, csc, coff, center;
+    std::vector<int32_t> nsrc_local, nptr_leaf, own_ptr, own_src, inc_ptr, inc_blk;
+    int max_leaf = 0;
+};
+
 struct dwfmm_tree_s {
     HostTree H;
+    std::unique_ptr<TreeStage> stage;  // between the host build and the upload
     DevTree D{};
     Arena arena;
     double *clo = nullptr, *csc = nullptr, *coff = nullptr;  // [ncl][d] reference-coordinate maps
@@ -171,9 +180,11 @@ extern "C" dwfmm_status dwfmm_build_tree_ex(const double *points, int64_t n, int
     return tree_from_host(pts, n, d, dim_weights, leaf_size, eta, st, out, (int)admissibility);
 }
 
-// Tree from host points (arguments already checked).
-static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, int32_t d, const double *dim_weights,
-                                   int32_t leaf_size, double eta, hipStream_t st, dwfmm_tree *out, int adm_half)
+// Tree from host points (arguments already checked), in two phases: tree_host builds the tree,
+// the nearfield ownership and every array the device will hold, on the host only (so the
+// device bytes are known before anything is allocated); tree_upload allocates and uploads them.
+static dwfmm_status tree_host(const std::vector<double> &pts, int64_t n, int32_t d, const double *dim_weights,
+                              int32_t leaf_size, double eta, dwfmm_tree *out, int adm_half)
 {
     for (double v : pts)
         if (!std::isfinite(v)) return fail(DWFMM_E_NONFINITE, "points contain NaN or Inf");
@@ -185,26 +196,34 @@ static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, in
         delete t;
         return fail(DWFMM_E_INVALID, err);
     }
-    (void)hipGetDevice(&t->device);
+    t->stage.reset(new (std::nothrow) TreeStage());
+    if (!t->stage) {
+        delete t;
+        return fail(DWFMM_E_NOMEM, "host allocation failed");
+    }
+    TreeStage &S = *t->stage;
     const HostTree &H = t->H;
     const int dp = pad_dim(d);
     // SoA coordinates in tree order, zero rows up to dpad
-    std::vector<double> Xs((size_t)dp * n, 0.0);
+    S.Xs.assign((size_t)dp * n, 0.0);
     for (int64_t i = 0; i < n; ++i)
-        for (int k = 0; k < d; ++k) Xs[(size_t)k * n + i] = pts[(size_t)H.perm[i] * d + k];
+        for (int k = 0; k < d; ++k) S.Xs[(size_t)k * n + i] = pts[(size_t)H.perm[i] * d + k];
     // reference-coordinate maps t = (x - lo) * sc + off (degenerate axes -> 1/2)
-    std::vector<double> clo(H.lo), csc((size_t)H.ncl * d), coff((size_t)H.ncl * d);
-    for (size_t i = 0; i < csc.size(); ++i) {
+    S.clo = H.lo;
+    S.csc.resize((size_t)H.ncl * d);
+    S.coff.resize((size_t)H.ncl * d);
+    for (size_t i = 0; i < S.csc.size(); ++i) {
         double w = H.hi[i] - H.lo[i];
-        csc[i] = w > 0 ? 1.0 / w : 0.0;
-        coff[i] = w > 0 ? 0.0 : 0.5;
+        S.csc[i] = w > 0 ? 1.0 / w : 0.0;
+        S.coff[i] = w > 0 ? 0.0 : 0.5;
     }
-    std::vector<int32_t> nsrc_local(H.Nsrc.size()), nptr_leaf(H.nleaf + 1);
+    std::vector<int32_t> &nsrc_local = S.nsrc_local, &nptr_leaf = S.nptr_leaf;
+    nsrc_local.resize(H.Nsrc.size());
+    nptr_leaf.resize(H.nleaf + 1);
     const int32_t lf = (int32_t)(H.nleaf - 1);
     for (size_t i = 0; i < H.Nsrc.size(); ++i) nsrc_local[i] = H.Nsrc[i] - lf;
     for (int64_t l = 0; l <= H.nleaf; ++l) nptr_leaf[l] = H.Nptr[lf + l];
-    int max_leaf = 0;
-    for (int64_t l = 0; l < H.nleaf; ++l) max_leaf = std::max(max_leaf, H.end[lf + l] - H.begin[lf + l]);
+    for (int64_t l = 0; l < H.nleaf; ++l) S.max_leaf = std::max(S.max_leaf, H.end[lf + l] - H.begin[lf + l]);
     // Symmetric nearfield: the self block is owned by its leaf; every other unordered pair
     // {t, s} goes to whichever leaf owns fewer blocks so far (ties to the smaller index).
     std::vector<std::pair<int32_t, int32_t>> owned;
@@ -224,7 +243,10 @@ static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, in
         t->own_max = std::max<int64_t>(t->own_max, own_cnt[l]);
         t->near_max = std::max<int64_t>(t->near_max, nptr_leaf[l + 1] - nptr_leaf[l]);
     }
-    std::vector<int32_t> own_ptr(H.nleaf + 1, 0), own_src(owned.size()), inc_ptr(H.nleaf + 1, 0), inc_blk;
+    std::vector<int32_t> &own_ptr = S.own_ptr, &own_src = S.own_src, &inc_ptr = S.inc_ptr, &inc_blk = S.inc_blk;
+    own_ptr.assign(H.nleaf + 1, 0);
+    own_src.resize(owned.size());
+    inc_ptr.assign(H.nleaf + 1, 0);
     for (auto &op : owned) own_ptr[op.first + 1]++;
     for (int64_t l = 0; l < H.nleaf; ++l) own_ptr[l + 1] += own_ptr[l];
     for (size_t b = 0; b < owned.size(); ++b) {
@@ -238,7 +260,8 @@ static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, in
         for (size_t b = 0; b < owned.size(); ++b)
             if (owned[b].first != owned[b].second) inc_blk[fill[owned[b].second]++] = (int32_t)b;
     }
-    std::vector<double> center((size_t)H.nleaf * dp, 0.0), rad(H.nleaf, 0.0);
+    std::vector<double> &center = S.center, rad(H.nleaf, 0.0);
+    center.assign((size_t)H.nleaf * dp, 0.0);
     for (int64_t l = 0; l < H.nleaf; ++l) {
         double r2 = 0.0;
         for (int k = 0; k < d; ++k) {
@@ -251,45 +274,64 @@ static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, in
     double reach2 = 0.0;
     for (int64_t l = 0; l < H.nleaf; ++l)
         for (int32_t q = nptr_leaf[l]; q < nptr_leaf[l + 1]; ++q) {
-            const int32_t s = nsrc_local[q];
+            const int32_t s2 = nsrc_local[q];
             double dc = 0.0;
             for (int k = 0; k < d; ++k) {
-                const double t = center[(size_t)s * dp + k] - center[(size_t)l * dp + k];
-                dc += t * t;
+                const double dd = center[(size_t)s2 * dp + k] - center[(size_t)l * dp + k];
+                dc += dd * dd;
             }
-            const double reach = rad[l] + std::sqrt(dc) + rad[s];
+            const double reach = rad[l] + std::sqrt(dc) + rad[s2];
             reach2 = std::max(reach2, reach * reach);
         }
     t->near_reach2 = reach2;
+    *out = t;
+    return DWFMM_OK;
+}
 
+// Device bytes the upload of a staged tree allocates (what its arena will report).
+static size_t tree_stage_bytes(const dwfmm_tree t)
+{
+    const TreeStage &S = *t->stage;
+    const HostTree &H = t->H;
+    size_t b = sizeof(double) * (S.Xs.size() + S.clo.size() + S.csc.size() + S.coff.size() + S.center.size());
+    b += sizeof(int32_t) * (H.perm.size() + H.begin.size() + H.end.size() + H.Fptr.size() + H.Fsrc.size() +
+                            S.nptr_leaf.size() + S.nsrc_local.size() + S.own_ptr.size() + S.own_src.size() +
+                            S.inc_ptr.size() + S.inc_blk.size());
+    return b;
+}
+
+static dwfmm_status tree_upload(dwfmm_tree t, hipStream_t st)
+{
+    (void)hipGetDevice(&t->device);
+    const HostTree &H = t->H;
+    TreeStage &S = *t->stage;
     DevTree &D = t->D;
     auto up = [&](auto **dst, const auto &v) { return t->arena.upload(dst, v, st); };
     hipError_t e = hipSuccess;
     double *dXs;
     int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs, *dop, *dos, *dip, *dib;
     double *dcen;
-    if ((e = up(&dXs, Xs)) != hipSuccess || (e = up(&dperm, H.perm)) != hipSuccess ||
+    if ((e = up(&dXs, S.Xs)) != hipSuccess || (e = up(&dperm, H.perm)) != hipSuccess ||
         (e = up(&dcb, H.begin)) != hipSuccess || (e = up(&dce, H.end)) != hipSuccess ||
         (e = up(&dFp, H.Fptr)) != hipSuccess || (e = up(&dFs, H.Fsrc)) != hipSuccess ||
-        (e = up(&dNp, nptr_leaf)) != hipSuccess || (e = up(&dNs, nsrc_local)) != hipSuccess ||
-        (e = up(&t->clo, clo)) != hipSuccess || (e = up(&t->csc, csc)) != hipSuccess ||
-        (e = up(&t->coff, coff)) != hipSuccess || (e = up(&dop, own_ptr)) != hipSuccess ||
-        (e = up(&dos, own_src)) != hipSuccess || (e = up(&dip, inc_ptr)) != hipSuccess ||
-        (e = up(&dib, inc_blk)) != hipSuccess || (e = up(&dcen, center)) != hipSuccess ||
+        (e = up(&dNp, S.nptr_leaf)) != hipSuccess || (e = up(&dNs, S.nsrc_local)) != hipSuccess ||
+        (e = up(&t->clo, S.clo)) != hipSuccess || (e = up(&t->csc, S.csc)) != hipSuccess ||
+        (e = up(&t->coff, S.coff)) != hipSuccess || (e = up(&dop, S.own_ptr)) != hipSuccess ||
+        (e = up(&dos, S.own_src)) != hipSuccess || (e = up(&dip, S.inc_ptr)) != hipSuccess ||
+        (e = up(&dib, S.inc_blk)) != hipSuccess || (e = up(&dcen, S.center)) != hipSuccess ||
         (e = hipStreamSynchronize(st)) != hipSuccess) {
         t->arena.release();
-        delete t;
         return fail(e == hipErrorOutOfMemory ? DWFMM_E_NOMEM : DWFMM_E_HIP,
                     std::string("tree upload: ") + hipGetErrorString(e));
     }
-    D.n = (int)n;
-    D.d = d;
+    D.n = (int)H.n;
+    D.d = H.d;
     D.J = H.J;
-    D.dpad = dp;
+    D.dpad = pad_dim(H.d);
     D.nleaf = (int)H.nleaf;
     D.ncl = (int)H.ncl;
-    D.leaf_first = lf;
-    D.max_leaf = max_leaf;
+    D.leaf_first = (int)(H.nleaf - 1);
+    D.max_leaf = S.max_leaf;
     D.min_far_level = H.min_far_level;
     D.Xs = dXs;
     D.perm = dperm;
@@ -299,12 +341,27 @@ static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, in
     D.Fsrc = dFs;
     D.Nptr = dNp;
     D.Nsrc = dNs;
-    D.nblk = (int)owned.size();
+    D.nblk = (int)S.own_src.size();
     D.own_ptr = dop;
     D.own_src = dos;
     D.inc_ptr = dip;
     D.inc_blk = dib;
     D.center = dcen;
+    t->stage.reset();
+    return DWFMM_OK;
+}
+
+static dwfmm_status tree_from_host(const std::vector<double> &pts, int64_t n, int32_t d, const double *dim_weights,
+                                   int32_t leaf_size, double eta, hipStream_t st, dwfmm_tree *out, int adm_half)
+{
+    dwfmm_tree t = nullptr;
+    dwfmm_status rc = tree_host(pts, n, d, dim_weights, leaf_size, eta, &t, adm_half);
+    if (rc != DWFMM_OK) return rc;
+    rc = tree_upload(t, st);
+    if (rc != DWFMM_OK) {
+        delete t;
+        return rc;
+    }
     *out = t;
     return DWFMM_OK;
 }
@@ -439,7 +496,7 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
         (o.precision != DWFMM_FP64 &&
          ((e = op->arena.alloc((void **)&op->ir_r, sizeof(double) * n * R)) != hipSuccess ||
           (e = op->arena.alloc((void **)&op->ir_d, sizeof(double) * n * R)) != hipSuccess)) ||
-        (e = op->arena.alloc((void **)&op->partial, sizeof(double) * kDotBlocks * R)) != hipSuccess ||
+        (e = op->arena.alloc((void **)&op->partial, sizeof(double) * 2 * kDotBlocks * R)) != hipSuccess ||
         (e = op->arena.alloc((void **)&op->scal, sizeof(double) * 16 * R)) != hipSuccess ||
         (e = op->arena.alloc((void **)&op->state, sizeof(int32_t) * 4 * R)) != hipSuccess ||
         (e = hipMemsetAsync(dM, 0, sizeof(double) * H.ncl * nx * R, st)) != hipSuccess ||
@@ -493,6 +550,52 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     tree->refs++;
     *out = op;
     return DWFMM_OK;
+}
+
+// Device bytes dwfmm_fmm_create allocates for an operator with basis B and workspace for R
+// right-hand sides on a tree with these sizes (what the operator's arena reports).
+static size_t op_device_bytes(const HostTree &H, int64_t nblk, const HostBasis &B, int R, int precision)
+{
+    const size_t nx = (size_t)B.nx, dp = (size_t)pad_dim(H.d), dk = (size_t)(H.d + 3) / 4 * 4;
+    const size_t nxp = (nx + 15) / 16 * 16, ncl = (size_t)H.ncl, n = (size_t)H.n;
+    size_t nleg = 0, nnz_max = 1;
+    for (int k = 0; k < H.d; ++k) nleg += (size_t)B.mk[k];
+    for (size_t a = 0; a < nx; ++a) {
+        size_t c = 0;
+        for (int k = 0; k < H.d; ++k) c += B.alpha[a * H.d + k] != 0;
+        nnz_max = std::max(nnz_max, c);
+    }
+    nleg = std::max<size_t>(nleg, 1);
+    size_t b = 8 * (ncl * nx * dp + ncl * nx * nx + ncl * dk * nxp + ncl * nxp + nx * nx);  // nodes, E, nodesT, norms, V^-1
+    b += 4 * (nx * nnz_max + 2 * nleg);                                                     // Legendre slot tables
+    b += 8 * (nx * n + n * R + 2 * ncl * nx * R);                                          // basis cache, xt, M, L
+    b += 8 * 128 * ((size_t)H.nleaf + (size_t)nblk);                                       // row and column sums
+    b += 8 * n * R * (precision != DWFMM_FP64 ? 5 : 3);                                    // r, p, q (, ir_r, ir_d)
+    b += 8 * (2 * (size_t)kDotBlocks * R + 16 * (size_t)R) + 4 * 4 * (size_t)R;            // partial, scal, state
+    return b;
+}
+
+extern "C" size_t dwfmm_op_bytes_for(dwfmm_tree tree, double q, const dwfmm_opts *opts)
+{
+    if (!tree || tree->destroyed || !(q >= 0.0) || !std::isfinite(q)) return 0;
+    dwfmm_opts o{};
+    o.weight_rule = DWFMM_W_R1;
+    o.max_nrhs = 1;
+    if (opts) {
+        o = *opts;
+        if (o.max_nrhs == 0) o.max_nrhs = 1;
+    }
+    if (o.max_nrhs < 1 || o.max_nrhs > 32 || o.precision < 0 || o.precision > 2) return 0;
+    const HostTree &H = tree->H;
+    std::string err;
+    std::vector<double> omega(H.d);
+    HostBasis B;
+    if (!compute_weights(o.weight_rule, H.d, H.b.data(), H.eta, o.omega, omega.data(), err) ||
+        !build_basis(H.d, omega.data(), q, B, err, o.node_rule, o.afp_candidates, o.index_rule))
+        return 0;
+    const int64_t nblk = tree->stage ? (int64_t)tree->stage->own_src.size() : (int64_t)tree->D.nblk;
+    const size_t tb = tree->stage ? tree_stage_bytes(tree) : tree->arena.total;
+    return tb + op_device_bytes(H, nblk, B, o.max_nrhs, o.precision);
 }
 
 extern "C" void dwfmm_op_destroy(dwfmm_op op)
@@ -721,6 +824,66 @@ constexpr int kEwBlocks = 1024;
 
 namespace {
 
+// The CG descriptor of a one-rhs problem on its operator's workspace.
+CgItem cg_item(dwfmm_op op, double lambda, const double *b, double *x, double rtol, int max_it)
+{
+    CgItem it{};
+    it.x = x;
+    it.r = op->r;
+    it.p = op->p;
+    it.q = op->q;
+    it.b = b;
+    it.partial = op->partial;
+    it.scal = op->scal;
+    it.state = op->state;
+    it.lambda = lambda;
+    it.rtol = rtol;
+    it.n = op->tree->D.n;
+    it.nblk = cg_blocks(it.n);
+    it.chunk = (it.n + it.nblk - 1) / it.nblk;
+    it.max_it = max_it;
+    return it;
+}
+
+// CG on (K~ + lambda I) x = b with one rhs: the matvec, then the vector steps of launch_cg.
+hipError_t cg_run1(dwfmm_op op, double lambda, const double *b, double *x, double rtol, int max_iter, int precision,
+                   hipStream_t st, std::vector<int32_t> &hstate, std::vector<double> &hrr)
+{
+    const DevTree &T = op->tree->D;
+    const CgItem it = cg_item(op, lambda, b, x, rtol, max_iter);
+    hipError_t e;
+    if ((e = launch_matvec(T, op->D, x, op->q, 1, 3, precision, st, nullptr, &op->fork)) != hipSuccess ||
+        (e = launch_cg(CG_START, nullptr, 0, 0, it, st)) != hipSuccess ||
+        (e = launch_cg(CG_START_SUM, nullptr, 0, 0, it, st)) != hipSuccess)
+        return e;
+    hstate.assign(3, 0);
+    hrr.assign(2, 0.0);
+    for (int k = 0; k < max_iter; ++k) {
+        if (k % op->check_every == 0) {
+            if ((e = hipMemcpyAsync(hstate.data(), op->state, sizeof(int32_t), hipMemcpyDeviceToHost, st)) !=
+                    hipSuccess ||
+                (op->progress &&
+                 (e = hipMemcpyAsync(hrr.data(), op->scal, sizeof(double) * 2, hipMemcpyDeviceToHost, st)) !=
+                     hipSuccess) ||
+                (e = hipStreamSynchronize(st)) != hipSuccess)
+                return e;
+            if (op->progress) {
+                const double rel = hrr[1] > 0 ? std::sqrt(hrr[0] / hrr[1]) : std::sqrt(hrr[0]);
+                op->progress(op->progress_ctx, k, 1, &rel);
+            }
+            if (hstate[0] != 0) break;
+        }
+        if ((e = launch_matvec(T, op->D, op->p, op->q, 1, 3, precision, st, nullptr, &op->fork)) != hipSuccess)
+            return e;
+        for (int step : {CG_PQ, CG_ALPHA, CG_XR, CG_BETA, CG_P})
+            if ((e = launch_cg(step, nullptr, 0, 0, it, st)) != hipSuccess) return e;
+    }
+    if ((e = hipMemcpyAsync(hrr.data(), op->scal, sizeof(double) * 2, hipMemcpyDeviceToHost, st)) != hipSuccess ||
+        (e = hipMemcpyAsync(hstate.data(), op->state, sizeof(int32_t) * 3, hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+    return hipStreamSynchronize(st);
+}
+
 // CG on (K~ + lambda I) x = b in the given matvec precision, x holding the start vector.
 // Vectors, inner products and scalars are FP64 on the device; the host reads the column
 // states every check_every iterations.  On return hstate[0..3n) = state (0 active,
@@ -728,6 +891,7 @@ namespace {
 hipError_t cg_run(dwfmm_op op, double lambda, const double *b, double *x, int nrhs, double rtol, int max_iter,
                   int precision, hipStream_t st, std::vector<int32_t> &hstate, std::vector<double> &hrr)
 {
+    if (nrhs == 1) return cg_run1(op, lambda, b, x, rtol, max_iter, precision, st, hstate, hrr);
     const DevTree &T = op->tree->D;
     const size_t total = (size_t)T.n * nrhs;
     const int nb = (nrhs + 63) / 64;
@@ -800,6 +964,18 @@ hipError_t residual64(dwfmm_op op, double lambda, const double *f, const double 
     const size_t total = (size_t)T.n * nrhs;
     hipError_t e = launch_matvec(T, op->D, v, out, nrhs, 3, DWFMM_FP64, st, nullptr, &op->fork);
     if (e != hipSuccess) return e;
+    if (nrhs == 1) {
+        CgItem it = cg_item(op, lambda, nullptr, nullptr, 0.0, 0);
+        it.f = f;
+        it.v = v;
+        it.out = out;
+        res.assign(1, 0.0);
+        if ((e = launch_cg(CG_RES, nullptr, 0, 0, it, st)) != hipSuccess ||
+            (e = launch_cg(CG_RES_SUM, nullptr, 0, 0, it, st)) != hipSuccess ||
+            (e = hipMemcpyAsync(res.data(), op->scal + 8, sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return e;
+        return hipStreamSynchronize(st);
+    }
     if (lambda != 0.0) hipLaunchKernelGGL(ridge_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, v, lambda, total);
     hipLaunchKernelGGL(sub_kernel, dim3(kEwBlocks), dim3(256), 0, st, out, f, out, total);
     if ((e = launch_dot(out, out, T.n, nrhs, op->partial, op->scal + 8 * nrhs, st)) != hipSuccess) return e;
@@ -882,11 +1058,19 @@ extern "C" dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double
             }
             used += std::max(most, 1);
             // alpha += delta on the columns being refined (scale slot 10 holds 1.0)
-            std::vector<double> one(nrhs, 1.0);
-            HIP_TRY(hipMemcpyAsync(op->scal + 10 * nrhs, one.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice, st));
-            hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, alpha, alpha, op->ir_d, op->scal, 10, 1.0,
-                               op->state + 3 * op->max_nrhs, 1, total, nrhs);
-            HIP_TRY(hipGetLastError());
+            if (nrhs == 1) {
+                CgItem it = cg_item(op, lambda, nullptr, op->ir_d, 0.0, 0);
+                it.acc = alpha;
+                it.frozen = mask[0];
+                HIP_TRY(launch_cg(CG_ADD, nullptr, 0, 0, it, st));
+            } else {
+                std::vector<double> one(nrhs, 1.0);
+                HIP_TRY(hipMemcpyAsync(op->scal + 10 * nrhs, one.data(), sizeof(double) * nrhs, hipMemcpyHostToDevice,
+                                       st));
+                hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, alpha, alpha, op->ir_d, op->scal, 10,
+                                   1.0, op->state + 3 * op->max_nrhs, 1, total, nrhs);
+                HIP_TRY(hipGetLastError());
+            }
             HIP_TRY(residual64(op, lambda, f, alpha, op->ir_r, nrhs, st, res));
             for (int c = 0; c < nrhs; ++c) {
                 if (mask[c]) continue;
@@ -928,6 +1112,11 @@ struct dwfmm_batch_s {
     std::vector<double> m2l_ms_pers;   // the same in the persistent layout
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    int flags = 0;
+    int force_prec = -1;              // >= 0: every problem runs in this precision (the FP64 companion)
+    dwfmm_batch b64 = nullptr;        // FP64 companion plan for the refinement residuals of a solve
+    CgItem *d_cg = nullptr;           // solve: CG descriptors and status mirror, one per problem
+    double *d_mirror = nullptr;
     ~dwfmm_batch_s()
     {
         if (exec) (void)hipGraphExecDestroy(exec);
@@ -948,7 +1137,7 @@ bool batch_eligible(dwfmm_op op)
 // Batch plan for a set of operators.  With sync == false the uploads stay queued on `st`
 // (their host sources live in the batch object), for callers that only use the batch on `st`.
 static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flags, hipStream_t st, bool sync,
-                                dwfmm_batch *out);
+                                dwfmm_batch *out, int force_prec = -1);
 
 extern "C" dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, int32_t flags, void *stream,
                                            dwfmm_batch *out)
@@ -957,7 +1146,7 @@ extern "C" dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, i
 }
 
 static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flags, hipStream_t st, bool sync,
-                                dwfmm_batch *out)
+                                dwfmm_batch *out, int force_prec)
 {
     if (!out) return fail(DWFMM_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -973,6 +1162,8 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
     if (!b) return fail(DWFMM_E_NOMEM, "host allocation failed");
     b->ops.assign(ops, ops + count);
     b->item_of.assign(count, -1);
+    b->flags = flags;
+    b->force_prec = force_prec;
     std::vector<const HostTree *> item_tree;  // host tree of each batch item
     for (int i = 0; i < count; ++i) {
         if (!batch_eligible(ops[i])) continue;
@@ -981,7 +1172,7 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
         it.T = T;
         it.O = ops[i]->D;
         it.far = T.min_far_level <= T.J;
-        it.precision = ops[i]->precision;
+        it.precision = force_prec >= 0 ? force_prec : ops[i]->precision;
         b->item_of[i] = (int)b->items.size();
         b->items.push_back(it);
         item_tree.push_back(&ops[i]->tree->H);
@@ -1211,7 +1402,8 @@ extern "C" dwfmm_status dwfmm_batch_matvec(dwfmm_batch b, const double *const *x
     for (size_t i = 0; i < b->ops.size(); ++i) {
         if (b->item_of[i] >= 0) continue;
         dwfmm_op op = b->ops[i];
-        HIP_TRY(launch_matvec(op->tree->D, op->D, xs[i], ys[i], 1, 3, op->precision, st));
+        HIP_TRY(launch_matvec(op->tree->D, op->D, xs[i], ys[i], 1, 3, b->force_prec >= 0 ? b->force_prec : op->precision,
+                              st));
     }
     return DWFMM_OK;
 }
@@ -1219,8 +1411,292 @@ extern "C" dwfmm_status dwfmm_batch_matvec(dwfmm_batch b, const double *const *x
 extern "C" void dwfmm_batch_destroy(dwfmm_batch b)
 {
     if (!b) return;
+    if (b->b64) dwfmm_batch_destroy(b->b64);
     b->arena.release();
     delete b;
+}
+
+namespace {
+
+// The batched matvec of a solve over the problems still iterating: a plan over a subset of the
+// batch's operators (the whole batch at first), rebuilt when the subset halves.  Batched and
+// single-problem kernels give the same bits, so the subset never changes a result.
+struct SolvePlan {
+    dwfmm_batch full = nullptr;  // the batch (or its FP64 companion)
+    dwfmm_batch sub = nullptr;   // owned plan over idx, or NULL while idx is the whole batch
+    std::vector<int> idx;        // problem index of each operator of the current plan
+    std::vector<const double *> xs;
+    std::vector<double *> ys;
+    ~SolvePlan()
+    {
+        if (sub) dwfmm_batch_destroy(sub);
+    }
+    void reset(dwfmm_batch b)
+    {
+        if (sub) dwfmm_batch_destroy(sub);
+        sub = nullptr;
+        full = b;
+        idx.resize(b->ops.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = (int)i;
+    }
+    // call only after the stream has drained (the old plan may still be referenced by queued work)
+    dwfmm_status shrink(const std::vector<int> &keep, hipStream_t st)
+    {
+        if (keep.empty() || keep.size() * 2 > idx.size()) return DWFMM_OK;
+        std::vector<dwfmm_op> ops;
+        for (int i : keep) ops.push_back(full->ops[i]);
+        dwfmm_batch nb = nullptr;
+        dwfmm_status rc = batch_build(ops.data(), (int)ops.size(), full->flags & DWFMM_BATCH_GRAPH, st, true, &nb,
+                                      full->force_prec);
+        if (rc != DWFMM_OK) return rc;
+        if (sub) dwfmm_batch_destroy(sub);
+        sub = nb;
+        idx = keep;
+        return DWFMM_OK;
+    }
+    dwfmm_status matvec(const std::vector<const double *> &src, const std::vector<double *> &dst, hipStream_t st)
+    {
+        xs.resize(idx.size());
+        ys.resize(idx.size());
+        for (size_t k = 0; k < idx.size(); ++k) {
+            xs[k] = src[idx[k]];
+            ys[k] = dst[idx[k]];
+        }
+        return dwfmm_batch_matvec(sub ? sub : full, xs.data(), ys.data(), st);
+    }
+};
+
+}  // namespace
+
+extern "C" dwfmm_status dwfmm_batch_solve(dwfmm_batch b, double lambda, const double *const *fs,
+                                          double *const *alphas, double rtol, int32_t max_iter, int32_t check_every,
+                                          void *stream, dwfmm_solve_info *infos)
+{
+    if (!b) return fail(DWFMM_E_INVALID, "batch is NULL");
+    if (!fs || !alphas || !infos) return fail(DWFMM_E_INVALID, "fs, alphas or infos is NULL");
+    if (!std::isfinite(lambda) || lambda < 0.0) return fail(DWFMM_E_INVALID, "lambda must be finite and >= 0");
+    if (!(rtol > 0.0) || max_iter < 0 || check_every < 1)
+        return fail(DWFMM_E_INVALID, "rtol must be > 0, max_iter >= 0 and check_every >= 1");
+    if (b->force_prec >= 0) return fail(DWFMM_E_INVALID, "not a batch from dwfmm_batch_create");
+    const int P = (int)b->ops.size();
+    const int prec = b->ops[0]->precision;
+    for (int i = 0; i < P; ++i) {
+        if (b->ops[i]->precision != prec) return fail(DWFMM_E_INVALID, "the batch's operators differ in precision");
+        if (!fs[i] || !alphas[i] || (const double *)alphas[i] == fs[i])
+            return fail(DWFMM_E_INVALID, "bad f/alpha pointer in batch");
+    }
+    hipStream_t st = (hipStream_t)stream;
+    if (!b->d_cg) {
+        HIP_TRY(b->arena.alloc((void **)&b->d_cg, sizeof(CgItem) * P));
+        HIP_TRY(b->arena.alloc((void **)&b->d_mirror, sizeof(double) * 8 * P));
+    }
+    std::vector<CgItem> items(P);
+    std::vector<double> mir(8 * (size_t)P);
+    std::vector<const double *> src(P);
+    std::vector<double *> dst(P);
+    int nblocks = 0;
+    auto set_items = [&](auto fill) -> hipError_t {
+        // the previous upload from `items` may still be queued
+        hipError_t e0 = hipStreamSynchronize(st);
+        if (e0 != hipSuccess) return e0;
+        nblocks = 0;
+        for (int i = 0; i < P; ++i) {
+            items[i] = CgItem{};
+            fill(i, items[i]);
+            items[i].blk0 = nblocks;
+            items[i].mirror = b->d_mirror + 8 * (size_t)i;
+            nblocks += items[i].nblk;
+        }
+        return hipMemcpyAsync(b->d_cg, items.data(), sizeof(CgItem) * P, hipMemcpyHostToDevice, st);
+    };
+    auto step = [&](int s) { return launch_cg(s, b->d_cg, P, nblocks, items[0], st); };
+    auto read_mirror = [&]() -> hipError_t {
+        hipError_t e = step(CG_MIRROR);
+        if (e == hipSuccess) e = hipMemcpyAsync(mir.data(), b->d_mirror, sizeof(double) * 8 * P, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        return e;
+    };
+    // CG iterations on the current items until no problem steps; matvecs on `plan`, which
+    // shrinks to the stepping problems
+    SolvePlan plan;
+    auto iterate = [&](dwfmm_batch lo, int cap) -> dwfmm_status {
+        plan.reset(lo);
+        for (int i = 0; i < P; ++i) {
+            src[i] = items[i].p;
+            dst[i] = items[i].q;
+        }
+        for (int k = 0; k < cap; ++k) {
+            if (k % check_every == 0) {
+                HIP_TRY(read_mirror());
+                std::vector<int> keep;
+                for (int i = 0; i < P; ++i)
+                    if (mir[8 * (size_t)i] == 0.0 && mir[8 * (size_t)i + 1] < items[i].max_it) keep.push_back(i);
+                if (keep.empty()) break;
+                dwfmm_status rc = plan.shrink(keep, st);
+                if (rc != DWFMM_OK) return rc;
+            }
+            dwfmm_status rc = plan.matvec(src, dst, st);
+            if (rc != DWFMM_OK) return rc;
+            for (int sstep : {CG_PQ, CG_ALPHA, CG_XR, CG_BETA, CG_P}) HIP_TRY(step(sstep));
+        }
+        HIP_TRY(read_mirror());
+        return DWFMM_OK;
+    };
+    // res[i] = |f_i - (K~_64 + lambda I) alpha_i|^2 for the problems with include[i]
+    dwfmm_batch full64 = b;
+    std::vector<double> res(P, 0.0);
+    auto residual = [&](const std::vector<int> &include) -> dwfmm_status {
+        for (int i = 0; i < P; ++i) {
+            src[i] = alphas[i];
+            dst[i] = prec == DWFMM_FP64 ? b->ops[i]->q : b->ops[i]->ir_r;
+        }
+        SolvePlan rp;
+        rp.reset(full64);
+        std::vector<int> keep;
+        for (int i = 0; i < P; ++i)
+            if (include[i]) keep.push_back(i);
+        dwfmm_status rc = rp.shrink(keep, st);
+        if (rc != DWFMM_OK) return rc;
+        rc = rp.matvec(src, dst, st);
+        if (rc != DWFMM_OK) return rc;
+        HIP_TRY(set_items([&](int i, CgItem &it) {
+            it = cg_item(b->ops[i], lambda, nullptr, nullptr, 0.0, 0);
+            it.f = fs[i];
+            it.v = alphas[i];
+            it.out = dst[i];
+            it.frozen = !include[i];
+        }));
+        HIP_TRY(step(CG_RES));
+        HIP_TRY(step(CG_RES_SUM));
+        HIP_TRY(read_mirror());
+        for (int i = 0; i < P; ++i)
+            if (include[i]) res[i] = mir[8 * (size_t)i + 5];
+        return DWFMM_OK;
+    };
+    std::vector<double> den(P, 1.0);
+    dwfmm_status worst = DWFMM_OK;
+    auto record = [&](dwfmm_status s2) {
+        if (s2 == DWFMM_E_BREAKDOWN) worst = DWFMM_E_BREAKDOWN;
+        else if (s2 == DWFMM_E_NOT_CONVERGED && worst == DWFMM_OK) worst = DWFMM_E_NOT_CONVERGED;
+    };
+    const std::vector<int> all(P, 1);
+
+    if (prec == DWFMM_FP64) {
+        for (int i = 0; i < P; ++i) {
+            src[i] = alphas[i];
+            dst[i] = b->ops[i]->q;
+        }
+        plan.reset(b);
+        dwfmm_status rc = plan.matvec(src, dst, st);
+        if (rc != DWFMM_OK) return rc;
+        HIP_TRY(set_items([&](int i, CgItem &it) { it = cg_item(b->ops[i], lambda, fs[i], alphas[i], rtol, max_iter); }));
+        HIP_TRY(step(CG_START));
+        HIP_TRY(step(CG_START_SUM));
+        rc = iterate(b, max_iter);
+        if (rc != DWFMM_OK) return rc;
+        std::vector<double> m(mir);
+        rc = residual(all);
+        if (rc != DWFMM_OK) return rc;
+        for (int i = 0; i < P; ++i) {
+            const double *mi = m.data() + 8 * (size_t)i;
+            const double dn = mi[4] > 0 ? std::sqrt(mi[4]) : 1.0;
+            dwfmm_solve_info &I = infos[i];
+            I.iters = (int32_t)mi[1];
+            I.neg_curvature_steps = (int32_t)mi[2];
+            I.refine_steps = 0;
+            I.rel_res_recursive = std::sqrt(mi[3]) / dn;
+            I.rel_res_true = std::sqrt(res[i]) / dn;
+            I.status = mi[0] == 1.0 ? DWFMM_OK : (mi[0] == 2.0 ? DWFMM_E_BREAKDOWN : DWFMM_E_NOT_CONVERGED);
+            record((dwfmm_status)I.status);
+        }
+    } else {
+        // iterative refinement per problem, its outer steps taken together: FP64 residual on
+        // the FP64 companion plan, inner CG on the batch's own (reduced) matvec, alpha += delta
+        if (!b->b64) {
+            dwfmm_status rc = batch_build(b->ops.data(), P, b->flags & DWFMM_BATCH_GRAPH, st, true, &b->b64, DWFMM_FP64);
+            if (rc != DWFMM_OK) return rc;
+        }
+        full64 = b->b64;
+        for (int i = 0; i < P; ++i) {
+            dwfmm_op op = b->ops[i];
+            HIP_TRY(launch_dot(fs[i], fs[i], op->tree->D.n, 1, op->partial, op->scal + 9, st));
+        }
+        dwfmm_status rc = residual(all);
+        if (rc != DWFMM_OK) return rc;
+        std::vector<int32_t> iters(P, 0), neg(P, 0), stall(P, 0), done(P, 0), broke(P, 0), steps(P, 0), used(P, 0);
+        std::vector<double> best(res);
+        for (int i = 0; i < P; ++i) {
+            const double ff = mir[8 * (size_t)i + 6];
+            den[i] = ff > 0 ? std::sqrt(ff) : 1.0;
+            done[i] = std::sqrt(res[i]) <= rtol * den[i];
+        }
+        for (int outer = 0;; ++outer) {
+            std::vector<int> run(P, 0);
+            bool any = false;
+            for (int i = 0; i < P; ++i) {
+                run[i] = !done[i] && stall[i] < 3 && outer < b->ops[i]->ir_max_outer && used[i] < max_iter;
+                any |= run[i] != 0;
+            }
+            if (!any) break;
+            int cap = 0;
+            HIP_TRY(set_items([&](int i, CgItem &it) {
+                dwfmm_op op = b->ops[i];
+                const double rtol_in =
+                    op->ir_inner_rtol > 0 ? op->ir_inner_rtol : (op->precision == DWFMM_FP32 ? 1e-4 : 1e-2);
+                const int inner =
+                    op->ir_max_inner > 0 ? std::min(op->ir_max_inner, max_iter - used[i]) : max_iter - used[i];
+                it = cg_item(op, lambda, op->ir_r, op->ir_d, rtol_in, run[i] ? inner : 0);
+                it.zero_x = 1;
+                it.frozen = !run[i];
+                if (run[i]) cap = std::max(cap, inner);
+            }));
+            HIP_TRY(step(CG_START));
+            HIP_TRY(step(CG_START_SUM));
+            rc = iterate(b, cap);
+            if (rc != DWFMM_OK) return rc;
+            for (int i = 0; i < P; ++i) {
+                if (!run[i]) continue;
+                const double *mi = mir.data() + 8 * (size_t)i;
+                const int it_i = (int)mi[1];
+                iters[i] += it_i;
+                neg[i] += (int)mi[2];
+                used[i] += std::max(it_i, 1);
+                if (mi[0] == 2.0 && it_i == 0) broke[i] = 1;
+                steps[i]++;
+            }
+            // alpha += delta on the problems being refined
+            HIP_TRY(set_items([&](int i, CgItem &it) {
+                it = cg_item(b->ops[i], lambda, nullptr, b->ops[i]->ir_d, 0.0, 0);
+                it.acc = alphas[i];
+                it.frozen = !run[i];
+            }));
+            HIP_TRY(step(CG_ADD));
+            rc = residual(run);
+            if (rc != DWFMM_OK) return rc;
+            for (int i = 0; i < P; ++i) {
+                if (!run[i]) continue;
+                if (std::sqrt(res[i]) <= rtol * den[i]) done[i] = 1;
+                else if (res[i] >= best[i]) stall[i]++;
+                else {
+                    best[i] = res[i];
+                    stall[i] = 0;
+                }
+                if (broke[i]) stall[i] = 3;
+            }
+        }
+        for (int i = 0; i < P; ++i) {
+            dwfmm_solve_info &I = infos[i];
+            I.iters = iters[i];
+            I.neg_curvature_steps = neg[i];
+            I.refine_steps = steps[i];
+            I.rel_res_recursive = std::sqrt(res[i]) / den[i];
+            I.rel_res_true = std::sqrt(res[i]) / den[i];
+            I.status = done[i] ? DWFMM_OK : (broke[i] ? DWFMM_E_BREAKDOWN : DWFMM_E_NOT_CONVERGED);
+            record((dwfmm_status)I.status);
+        }
+    }
+    if (worst != DWFMM_OK) g_err = worst == DWFMM_E_BREAKDOWN ? "CG breakdown" : "CG did not converge";
+    return worst;
 }
 
 // ============================================================== solve server (continuous batching)
@@ -1239,6 +1715,8 @@ struct ServerRequest {
     double *d_alpha = nullptr, *d_f = nullptr;
     dwfmm_status prep = DWFMM_OK;   // outcome of the preparation and its message
     std::string prep_err;
+    size_t exact = 0;               // device bytes from the host-built tree (0 until it is built)
+    bool more = false;              // handed back: exact exceeds the bytes reserved at hand-off
     int iters = 0;
     std::vector<double> alpha;      // result
     dwfmm_solve_info info{};
@@ -1262,6 +1740,13 @@ struct dwfmm_server_s {
     bool dirty = true;
     std::vector<const double *> xs;
     std::vector<double *> ys;
+    // CG descriptors of the active requests (rebuilt with the batch plan) and their status mirror
+    CgItem *d_cg = nullptr;
+    double *d_mirror = nullptr;
+    std::vector<CgItem> h_cg;
+    std::vector<std::vector<CgItem>> old_cg;  // host sources of queued uploads, freed at the next synchronisation
+    std::vector<double> h_mirror;
+    int cg_nblocks = 0;
     // preparation workers: each builds tree, operator and CG start on a stream of its own
     std::mutex mu;
     std::condition_variable cv_todo, cv_ready;
@@ -1307,12 +1792,27 @@ size_t request_bytes(const ServerRequest &r)
     return dwfmm_estimate_bytes(r.n, r.d, r.leaf, nx, 1) + 2 * (size_t)r.n * sizeof(double);
 }
 
-// Everything a request needs before its first iteration: tree, operator, alpha = 0 and the CG
-// start r = p = f, with its scalars.  Runs on a worker thread and its stream; returns once the
-// stream has drained, so the main stream may use the request without waiting on it.
+// First phase of a request's preparation, host only: the tree and the exact device bytes the
+// request will hold (tree, operator, alpha and f).
+dwfmm_status prepare_host(ServerRequest *r)
+{
+    dwfmm_status rc = tree_host(r->pts, r->n, r->d, r->b.data(), r->leaf, r->eta, &r->tree, 0);
+    if (rc != DWFMM_OK) return rc;
+    dwfmm_opts o{};
+    o.precision = r->precision;
+    o.max_nrhs = 1;
+    const size_t ob = dwfmm_op_bytes_for(r->tree, r->q, &o);
+    if (ob == 0) return fail(DWFMM_E_INVALID, "index set of the request cannot be built");
+    r->exact = ob + 2 * sizeof(double) * (size_t)r->n;
+    return DWFMM_OK;
+}
+
+// Second phase: upload the tree, build the operator, alpha = 0 and the CG start r = p = f,
+// with its scalars.  Runs on a worker thread and its stream; returns once the stream has
+// drained, so the main stream may use the request without waiting on it.
 dwfmm_status prepare_request(ServerRequest *r, hipStream_t ws)
 {
-    dwfmm_status rc = tree_from_host(r->pts, r->n, r->d, r->b.data(), r->leaf, r->eta, ws, &r->tree, 0);
+    dwfmm_status rc = tree_upload(r->tree, ws);
     if (rc != DWFMM_OK) return rc;
     dwfmm_opts o{};
     o.precision = r->precision;
@@ -1324,16 +1824,11 @@ dwfmm_status prepare_request(ServerRequest *r, hipStream_t ws)
     HIP_TRY(hipMalloc(&r->d_alpha, nb));
     HIP_TRY(hipMalloc(&r->d_f, nb));
     HIP_TRY(hipMemcpyAsync(r->d_f, r->f.data(), nb, hipMemcpyHostToDevice, ws));
-    HIP_TRY(hipMemsetAsync(r->d_alpha, 0, nb, ws));
-    dwfmm_op op = r->op;
-    const size_t total = (size_t)r->n;
-    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, ws, op->r, r->d_f, total);
-    hipLaunchKernelGGL(copy_kernel, dim3(kEwBlocks), dim3(256), 0, ws, op->p, r->d_f, total);
-    HIP_TRY(launch_dot(op->r, op->r, (int)r->n, 1, op->partial, op->scal, ws));
-    HIP_TRY(launch_dot(r->d_f, r->d_f, (int)r->n, 1, op->partial, op->scal + 1, ws));
-    HIP_TRY(hipMemsetAsync(op->state, 0, sizeof(int32_t) * 3, ws));
-    hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(64), 0, ws, op->scal, op->state, 1, r->rtol);
-    HIP_TRY(hipGetLastError());
+    // alpha = 0, so A alpha = 0: the start step clears both instead of running a matvec
+    CgItem it = cg_item(r->op, r->lambda, r->d_f, r->d_alpha, r->rtol, r->max_iter);
+    it.zero_x = 1;
+    HIP_TRY(launch_cg(CG_START, nullptr, 0, 0, it, ws));
+    HIP_TRY(launch_cg(CG_START_SUM, nullptr, 0, 0, it, ws));
     HIP_TRY(hipStreamSynchronize(ws));
     return DWFMM_OK;
 }
@@ -1351,7 +1846,20 @@ void worker_main(dwfmm_server s, int w)
             r = s->todo.front();
             s->todo.pop_front();
         }
-        r->prep = prepare_request(r, ws);
+        if (!r->tree) {
+            r->prep = prepare_host(r);
+            if (r->prep == DWFMM_OK && r->exact > r->need) {
+                // reserved too little: back to the main thread, which re-queues it with its exact bytes
+                r->more = true;
+                {
+                    std::lock_guard<std::mutex> lk(s->mu);
+                    s->ready.push_back(r);
+                }
+                s->cv_ready.notify_one();
+                continue;
+            }
+        }
+        if (r->prep == DWFMM_OK) r->prep = prepare_request(r, ws);
         if (r->prep != DWFMM_OK) {
             r->prep_err = g_err;
             (void)hipStreamSynchronize(ws);  // nothing of the failed request stays in flight
@@ -1397,6 +1905,14 @@ void admit_ready(dwfmm_server s, bool wait)
     }
     for (ServerRequest *r : got) {
         s->preparing--;
+        if (r->more) {
+            // its host tree is built; it waits at the front of the queue for its exact bytes
+            r->more = false;
+            s->held -= std::min(s->held, r->need);
+            r->need = r->exact;
+            s->queue.push_front(r);
+            continue;
+        }
         if (r->prep != DWFMM_OK) {
             release_request(r, s->held);
             r->info.status = r->prep;
@@ -1460,6 +1976,8 @@ dwfmm_server_s::~dwfmm_server_s()
             delete r;
         }
     for (hipStream_t w : worker_streams) (void)hipStreamDestroy(w);
+    if (d_cg) (void)hipFree(d_cg);
+    if (d_mirror) (void)hipFree(d_mirror);
 }
 
 extern "C" dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_active, int32_t check_every,
@@ -1476,6 +1994,8 @@ extern "C" dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_act
     s->check_every = check_every;
     s->st = (hipStream_t)stream;
     hipError_t e = hipGetDevice(&s->device);
+    if (e == hipSuccess) e = hipMalloc(&s->d_cg, sizeof(CgItem) * max_active);
+    if (e == hipSuccess) e = hipMalloc(&s->d_mirror, sizeof(double) * 8 * max_active);
     for (int w = 0; w < kServerWorkers && e == hipSuccess; ++w) {
         hipStream_t ws = nullptr;
         e = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking);
@@ -1545,6 +2065,18 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
             for (ServerRequest *r : s->active) ops.push_back(r->op);
             dwfmm_status rc = batch_build(ops.data(), (int)ops.size(), 0, st, false, &s->batch);
             if (rc != DWFMM_OK) return rc;
+            s->old_cg.push_back(std::move(s->h_cg));
+            s->h_cg.clear();
+            s->cg_nblocks = 0;
+            for (ServerRequest *r : s->active) {
+                CgItem it = cg_item(r->op, r->lambda, r->d_f, r->d_alpha, r->rtol, r->max_iter);
+                it.blk0 = s->cg_nblocks;
+                it.mirror = s->d_mirror + 8 * s->h_cg.size();
+                s->cg_nblocks += it.nblk;
+                s->h_cg.push_back(it);
+            }
+            HIP_TRY(hipMemcpyAsync(s->d_cg, s->h_cg.data(), sizeof(CgItem) * s->h_cg.size(), hipMemcpyHostToDevice,
+                                   st));
             s->dirty = false;
         }
         s->xs.clear();
@@ -1555,38 +2087,28 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
         }
         dwfmm_status rc = dwfmm_batch_matvec(s->batch, s->xs.data(), s->ys.data(), st);
         if (rc != DWFMM_OK) return rc;
-        // the CG update of every active request (FP64, its own scalars on the device)
-        for (ServerRequest *r : s->active) {
-            dwfmm_op op = r->op;
-            const size_t total = (size_t)r->n;
-            if (r->lambda != 0.0)
-                hipLaunchKernelGGL(ridge_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->q, op->p, r->lambda, total);
-            HIP_TRY(launch_dot(op->p, op->q, (int)r->n, 1, op->partial, op->scal + 2, st));
-            hipLaunchKernelGGL(cg_alpha_kernel, dim3(1), dim3(64), 0, st, op->scal, op->state, 1);
-            hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, r->d_alpha, r->d_alpha, op->p, op->scal,
-                               4, 1.0, op->state, 0, total, 1);
-            hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->r, op->r, op->q, op->scal, 4, -1.0,
-                               op->state, 0, total, 1);
-            HIP_TRY(launch_dot(op->r, op->r, (int)r->n, 1, op->partial, op->scal + 3, st));
-            hipLaunchKernelGGL(cg_beta_kernel, dim3(1), dim3(64), 0, st, op->scal, op->state, 1);
-            hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, op->p, op->r, op->p, op->scal, 5, 1.0,
-                               op->state, 1, total, 1);
-            hipLaunchKernelGGL(cg_check_kernel, dim3(1), dim3(64), 0, st, op->scal, op->state, 1, r->rtol);
-            HIP_TRY(hipGetLastError());
-            r->iters++;
-        }
+        // the CG update of every active request (FP64, its own scalars on the device): each step
+        // is one launch over all of them
+        const int nact = (int)s->active.size();
+        for (int step : {CG_PQ, CG_ALPHA, CG_XR, CG_BETA, CG_P})
+            HIP_TRY(launch_cg(step, s->d_cg, nact, s->cg_nblocks, s->h_cg[0], st));
+        for (ServerRequest *r : s->active) r->iters++;
         s->ticks++;
         // every check_every ticks (and when a request reaches max_iter): retire finished requests.
         // This is the only place the tick waits for the device.
         bool due = s->ticks % s->check_every == 0;
         for (ServerRequest *r : s->active) due |= r->iters >= r->max_iter;
         if (due) {
-            std::vector<int32_t> flags(s->active.size());
-            for (size_t i = 0; i < s->active.size(); ++i)
-                HIP_TRY(hipMemcpyAsync(&flags[i], s->active[i]->op->state, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            s->h_mirror.resize(8 * (size_t)nact);
+            HIP_TRY(launch_cg(CG_MIRROR, s->d_cg, nact, s->cg_nblocks, s->h_cg[0], st));
+            HIP_TRY(hipMemcpyAsync(s->h_mirror.data(), s->d_mirror, sizeof(double) * 8 * nact, hipMemcpyDeviceToHost,
+                                   st));
             HIP_TRY(hipStreamSynchronize(st));
+            std::vector<int32_t> flags(nact);
+            for (int i = 0; i < nact; ++i) flags[i] = (int32_t)s->h_mirror[8 * (size_t)i];
             for (dwfmm_batch b : s->old_batches) dwfmm_batch_destroy(b);
             s->old_batches.clear();
+            s->old_cg.clear();
             std::vector<ServerRequest *> keep;
             for (size_t i = 0; i < s->active.size(); ++i) {
                 ServerRequest *r = s->active[i];
@@ -1858,6 +2380,8 @@ extern "C" size_t dwfmm_estimate_bytes(int64_t n, int32_t d, int32_t leaf_size, 
     b += (size_t)n_x * n * 8;                        // basis cache
     b += (size_t)n * nrhs * 8 * 4;                   // xt, r, p, q
     b += 2 * ncl * n_x * nrhs * 8;                   // moments, locals
+    const size_t nleaf = ((size_t)1 << J);
+    b += 128 * 8 * nleaf * (1 + 128);                // nearfield row sums, column sums (estimate: 128 owned blocks per leaf)
     return b;
 }
 

@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdint>
 #include <utility>
 #include <vector>
@@ -123,5 +124,47 @@ hipError_t launch_batch_m2l(const BatchPlan &P, const BatchLaunch &L, hipStream_
 constexpr int kDotBlocks = 1024;
 hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double *partial, double *out,
                       hipStream_t stream);
+
+// ---- FP64 CG for problems with one right-hand side, any number of them per launch ----
+// One problem of a CG launch: CG on (K~ + lambda I) x = b, with A p (or A x) already in q when
+// a step needs it.  The inner products of a problem are taken over nblk blocks of chunk rows
+// (nblk = min(kDotBlocks, ceil(n / 4096)), the grid launch_dot uses for one column) and summed in
+// the same fixed order as launch_dot, so a problem's iterates do not depend on what else the
+// launch carries.  scal: [0] |r|^2, [1] |b|^2, [2] p.Ap, [3] new |r|^2, [4] step, [5] beta,
+// [8] |out|^2 of the residual step; state: [0] 0 active, 1 converged, 2 breakdown, 3 frozen,
+// [1] iterations, [2] steps with p.Ap < 0.
+struct CgItem {
+    double *x, *r, *p, *q;
+    const double *b;
+    // residual step: out = f - (out + lambda v) with K~ v already in out; add step: acc += x
+    const double *f, *v;
+    double *out, *acc;
+    double *partial;          // [2][kDotBlocks]
+    double *scal;
+    int32_t *state;
+    double lambda, rtol;
+    int n, nblk, chunk, blk0;  // blk0: first block of the problem in the launch's block numbering
+    int max_it;                // the problem takes no step once state[1] reaches max_it
+    int frozen;                // start: the problem starts frozen; residual and add steps skip it
+    int zero_x;                // start: x = 0 and q = 0 (= K~ 0) instead of reading them
+    double *mirror;            // mirror step: state[0..2], scal[0], scal[1], scal[8], scal[9] (8 doubles)
+};
+enum CgStep {
+    CG_START,      // blocks: q += lambda x, r = b - q, p = r; partial |r|^2 and |b|^2
+    CG_START_SUM,  // problems: |r|^2, |b|^2, state (frozen or active), convergence check
+    CG_PQ,         // blocks: q += lambda p; partial p.q
+    CG_ALPHA,      // problems: p.q, step a = |r|^2 / p.q (breakdown, negative curvature)
+    CG_XR,         // blocks: x += a p, r -= a q; partial |r|^2
+    CG_BETA,       // problems: new |r|^2, beta, iteration count, convergence check
+    CG_P,          // blocks: p = r + beta p
+    CG_RES,        // blocks: out = f - (out + lambda v); partial |out|^2
+    CG_RES_SUM,    // problems: |out|^2 into scal[8]
+    CG_ADD,        // blocks: acc += x
+    CG_MIRROR      // problems: copy state and scalars to mirror, for one host read of many problems
+};
+inline int cg_blocks(int n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, ((int64_t)n + 4095) / 4096)); }
+// One step for `nitems` problems (device array `items`, blk0 ascending, nblocks blocks in all),
+// or, with items == nullptr, for the single problem `one` passed by value.
+hipError_t launch_cg(int step, const CgItem *items, int nitems, int nblocks, const CgItem &one, hipStream_t stream);
 
 }  // namespace dwfmm

@@ -2474,6 +2474,234 @@ __global__ __launch_bounds__(256) void dot_final_kernel(const double *__restrict
     if (t == 0) out[r] = red[0];
 }
 
+// ---------------------------------------------------------------- CG steps for one-rhs problems
+// Sum of u_i v_i over rows [i0, i1) in the order of dot_partial_kernel with one column: thread t
+// takes rows i0 + t + 256 k into two alternating accumulators, then a fixed pairwise tree over the
+// 256 threads.  term(i, u, v) yields the factors of row i and may update vectors first (a row is
+// visited by one thread only).  The sum is valid in thread 0.
+template <class Term>
+__device__ __forceinline__ double block_dot1(int i0, int i1, double *red, Term term)
+{
+    const int t = threadIdx.x;
+    double s0 = 0.0, s1 = 0.0, u, v;
+    int i = i0 + t;
+    for (; i + 256 < i1; i += 512) {
+        term(i, u, v);
+        s0 = fma(u, v, s0);
+        term(i + 256, u, v);
+        s1 = fma(u, v, s1);
+    }
+    if (i < i1) {
+        term(i, u, v);
+        s0 = fma(u, v, s0);
+    }
+    red[t] = s0 + s1;
+    for (int h = 128; h > 0; h >>= 1) {
+        __syncthreads();
+        if (t < h) red[t] += red[t + h];
+    }
+    return red[0];
+}
+
+// The blocks' partial sums of one problem, added as dot_final_kernel adds them (valid in thread 0).
+__device__ __forceinline__ double final_dot1(const double *partial, int nblk, double *red)
+{
+    const int t = threadIdx.x;
+    double s = 0.0;
+    for (int b = t; b < nblk; b += 256) s += partial[b];
+    red[t] = s;
+    for (int h = 128; h > 0; h >>= 1) {
+        __syncthreads();
+        if (t < h) red[t] += red[t + h];
+    }
+    return red[0];
+}
+
+__global__ __launch_bounds__(256) void dot1_partial_kernel(const double *__restrict__ a, const double *__restrict__ b,
+                                                           int n, double *__restrict__ partial)
+{
+    __shared__ double red[256];
+    const int chunk = (n + gridDim.x - 1) / gridDim.x;
+    const int i0 = blockIdx.x * chunk, i1 = min(n, i0 + chunk);
+    const double s = block_dot1(i0, i1, red, [&](int i, double &u, double &v) {
+        u = a[i];
+        v = b[i];
+    });
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+__device__ __forceinline__ bool cg_stepping(const int32_t *state, int max_it)
+{
+    return state[0] == 0 && state[1] < max_it;
+}
+
+// Block steps: workgroup g takes block g - blk0 of the problem whose blocks contain g.
+template <int STEP>
+__global__ __launch_bounds__(256) void cg_block_kernel(const CgItem *__restrict__ items, int nitems, CgItem one)
+{
+    __shared__ double red[256];
+    int k = 0;
+    if (items) {
+        int lo = 0, hi = nitems - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[mid].blk0 <= (int)blockIdx.x) lo = mid;
+            else hi = mid - 1;
+        }
+        k = lo;
+    }
+    const CgItem &it = items ? items[k] : one;
+    const int blk = (int)blockIdx.x - it.blk0;
+    if (blk < 0 || blk >= it.nblk) return;
+    const int i0 = blk * it.chunk, i1 = min(it.n, i0 + it.chunk);
+    const double lam = it.lambda;
+    double *x = it.x, *r = it.r, *p = it.p, *q = it.q;
+    if (STEP == CG_START) {
+        if (it.frozen) return;
+        const double *b = it.b;
+        if (it.zero_x)
+            for (int i = i0 + threadIdx.x; i < i1; i += 256) {
+                x[i] = 0.0;
+                q[i] = 0.0;
+            }
+        const double s = block_dot1(i0, i1, red, [&](int i, double &u, double &v) {
+            double qi = q[i];
+            if (lam != 0.0) {
+                qi = fma(lam, x[i], qi);
+                q[i] = qi;
+            }
+            const double ri = b[i] - qi;
+            r[i] = ri;
+            p[i] = ri;
+            u = ri;
+            v = ri;
+        });
+        if (threadIdx.x == 0) it.partial[blk] = s;
+        __syncthreads();
+        const double s2 = block_dot1(i0, i1, red, [&](int i, double &u, double &v) {
+            u = b[i];
+            v = b[i];
+        });
+        if (threadIdx.x == 0) it.partial[kDotBlocks + blk] = s2;
+    } else if (STEP == CG_PQ) {
+        if (!cg_stepping(it.state, it.max_it)) return;
+        const double s = block_dot1(i0, i1, red, [&](int i, double &u, double &v) {
+            double qi = q[i];
+            if (lam != 0.0) {
+                qi = fma(lam, p[i], qi);
+                q[i] = qi;
+            }
+            u = p[i];
+            v = qi;
+        });
+        if (threadIdx.x == 0) it.partial[blk] = s;
+    } else if (STEP == CG_XR) {
+        if (!cg_stepping(it.state, it.max_it)) return;
+        const double a = it.scal[4];
+        const double s = block_dot1(i0, i1, red, [&](int i, double &u, double &v) {
+            x[i] = fma(a, p[i], x[i]);
+            const double ri = fma(-a, q[i], r[i]);
+            r[i] = ri;
+            u = ri;
+            v = ri;
+        });
+        if (threadIdx.x == 0) it.partial[blk] = s;
+    } else if (STEP == CG_P) {
+        if (it.state[0] != 0) return;
+        const double beta = it.scal[5];
+        for (int i = i0 + threadIdx.x; i < i1; i += 256) p[i] = fma(beta, p[i], r[i]);
+    } else if (STEP == CG_RES) {
+        if (it.frozen) return;
+        const double *f = it.f, *vv = it.v;
+        double *out = it.out;
+        const double s = block_dot1(i0, i1, red, [&](int i, double &u, double &v) {
+            double o = out[i];
+            if (lam != 0.0) o = fma(lam, vv[i], o);
+            o = f[i] - o;
+            out[i] = o;
+            u = o;
+            v = o;
+        });
+        if (threadIdx.x == 0) it.partial[blk] = s;
+    } else if (STEP == CG_ADD) {
+        if (it.frozen) return;
+        double *acc = it.acc;
+        for (int i = i0 + threadIdx.x; i < i1; i += 256) acc[i] = acc[i] + x[i];
+    }
+}
+
+// Problem steps: workgroup k takes problem k.
+template <int STEP>
+__global__ __launch_bounds__(256) void cg_item_kernel(const CgItem *__restrict__ items, CgItem one)
+{
+    __shared__ double red[256];
+    const CgItem &it = items ? items[blockIdx.x] : one;
+    double *scal = it.scal;
+    int32_t *state = it.state;
+    const int t = threadIdx.x;
+    if (STEP == CG_START_SUM) {
+        if (it.frozen) {
+            if (t == 0) {
+                state[0] = 3;
+                state[1] = 0;
+                state[2] = 0;
+            }
+            return;
+        }
+        const double rr = final_dot1(it.partial, it.nblk, red);
+        __syncthreads();
+        const double bb = final_dot1(it.partial + kDotBlocks, it.nblk, red);
+        if (t == 0) {
+            scal[0] = rr;
+            scal[1] = bb;
+            state[1] = 0;
+            state[2] = 0;
+            state[0] = sqrt(rr) <= it.rtol * sqrt(bb) ? 1 : 0;
+        }
+    } else if (STEP == CG_ALPHA) {
+        if (!cg_stepping(state, it.max_it)) {
+            if (t == 0) scal[4] = 0.0;
+            return;
+        }
+        const double pq = final_dot1(it.partial, it.nblk, red);
+        if (t == 0) {
+            scal[2] = pq;
+            double a = 0.0;
+            if (!isfinite(pq) || fabs(pq) <= 1e-300) {
+                state[0] = 2;
+            } else {
+                if (pq < 0.0) state[2] += 1;
+                a = scal[0] / pq;
+            }
+            scal[4] = a;
+        }
+    } else if (STEP == CG_BETA) {
+        if (!cg_stepping(state, it.max_it)) {
+            if (t == 0) scal[5] = 0.0;
+            return;
+        }
+        const double rrn = final_dot1(it.partial, it.nblk, red);
+        if (t == 0) {
+            scal[3] = rrn;
+            scal[5] = rrn / scal[0];
+            scal[0] = rrn;
+            state[1] += 1;
+            if (sqrt(rrn) <= it.rtol * sqrt(scal[1])) state[0] = 1;
+        }
+    } else if (STEP == CG_RES_SUM) {
+        if (it.frozen) return;
+        const double s = final_dot1(it.partial, it.nblk, red);
+        if (t == 0) scal[8] = s;
+    } else if (STEP == CG_MIRROR) {
+        double *m = it.mirror;
+        if (t < 3) m[t] = (double)state[t];
+        else if (t == 3) m[3] = scal[0];
+        else if (t == 4) m[4] = scal[1];
+        else if (t == 5) m[5] = scal[8];
+        else if (t == 6) m[6] = scal[9];
+    }
+}
+
 }  // namespace
 
 // The library compiles this file twice, in parallel: DWFMM_KERNELS_PART 1 holds the
@@ -2729,8 +2957,36 @@ hipError_t launch_dot(const double *a, const double *b, int n, int nrhs, double 
     // at least 4096 values per block, at most kDotBlocks blocks (the partial buffer's rows)
     const int64_t vals = (int64_t)n * nrhs;
     const int nblk = (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, (vals + 4095) / 4096));
-    hipLaunchKernelGGL(dot_partial_kernel, dim3(nblk), dim3(256), 0, stream, a, b, n, nrhs, partial);
+    if (nrhs == 1)
+        hipLaunchKernelGGL(dot1_partial_kernel, dim3(nblk), dim3(256), 0, stream, a, b, n, partial);
+    else
+        hipLaunchKernelGGL(dot_partial_kernel, dim3(nblk), dim3(256), 0, stream, a, b, n, nrhs, partial);
     hipLaunchKernelGGL(dot_final_kernel, dim3(nrhs), dim3(256), 0, stream, partial, nblk, nrhs, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_cg(int step, const CgItem *items, int nitems, int nblocks, const CgItem &one, hipStream_t stream)
+{
+    if (!items) {
+        nitems = 1;
+        nblocks = one.nblk;
+    }
+    if (nitems < 1 || nblocks < 1) return hipErrorInvalidValue;
+    const dim3 blocks(nblocks), probs(nitems), th(256);
+    switch (step) {
+    case CG_START: hipLaunchKernelGGL(cg_block_kernel<CG_START>, blocks, th, 0, stream, items, nitems, one); break;
+    case CG_PQ: hipLaunchKernelGGL(cg_block_kernel<CG_PQ>, blocks, th, 0, stream, items, nitems, one); break;
+    case CG_XR: hipLaunchKernelGGL(cg_block_kernel<CG_XR>, blocks, th, 0, stream, items, nitems, one); break;
+    case CG_P: hipLaunchKernelGGL(cg_block_kernel<CG_P>, blocks, th, 0, stream, items, nitems, one); break;
+    case CG_RES: hipLaunchKernelGGL(cg_block_kernel<CG_RES>, blocks, th, 0, stream, items, nitems, one); break;
+    case CG_ADD: hipLaunchKernelGGL(cg_block_kernel<CG_ADD>, blocks, th, 0, stream, items, nitems, one); break;
+    case CG_START_SUM: hipLaunchKernelGGL(cg_item_kernel<CG_START_SUM>, probs, th, 0, stream, items, one); break;
+    case CG_ALPHA: hipLaunchKernelGGL(cg_item_kernel<CG_ALPHA>, probs, th, 0, stream, items, one); break;
+    case CG_BETA: hipLaunchKernelGGL(cg_item_kernel<CG_BETA>, probs, th, 0, stream, items, one); break;
+    case CG_RES_SUM: hipLaunchKernelGGL(cg_item_kernel<CG_RES_SUM>, probs, th, 0, stream, items, one); break;
+    case CG_MIRROR: hipLaunchKernelGGL(cg_item_kernel<CG_MIRROR>, probs, th, 0, stream, items, one); break;
+    default: return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

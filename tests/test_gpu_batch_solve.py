@@ -1,0 +1,168 @@
+"""Batched CG solves and exact device-memory accounting.
+
+dwfmm_batch_solve runs CG for every problem of a batch in lockstep: batched matvecs (over the
+problems still iterating) and one launch per CG vector step for all problems.  Per problem the
+arithmetic is dwfmm_fmm_solve's with one rhs, so alpha, the iteration count and the residuals
+must be bitwise those of solving the problem alone -- in FP64 CG and in FP32 / BF16 iterative
+refinement, for problems that fall back to single launches, and when the matvec plan shrinks
+as problems finish.  One solution is re-measured by the CPU oracle.  dwfmm_op_bytes_for must
+predict dwfmm_op_bytes exactly, and the server must stay within its budget although its first
+reservation (the size-only estimate) can be too small.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2402_09531_amd as dw  # noqa: E402
+from paper_2402_09531_amd import workloads as W  # noqa: E402
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def make_problems(prec, seed=21, count=9):
+    rng = np.random.default_rng(seed)
+    probs = []
+    for i in range(count):
+        n = int(round(np.exp(rng.uniform(np.log(800), np.log(30000)))))
+        d = int(rng.integers(4, 15))
+        kind = ["matern32", "gaussian", "exponential"][i % 3]
+        leaf = 200 if i == count - 1 else (64 if i % 4 == 0 else 128)   # the last one runs on its own
+        X = W.points(n, d, 2.0, 300 + i)
+        b = W.dim_weights(d, 2.0)
+        tree = dw.build_tree(torch.from_numpy(X).cuda(), b, leaf, 0.8)
+        op = dw.fmm_create(tree, kind, 1.0, 4 + i % 2, precision=prec, check_every=3)
+        f = np.sin(X.sum(1))[:, None]
+        probs.append(dict(X=X, b=b, tree=tree, op=op, f=f, leaf=leaf, kind=kind, q=4 + i % 2))
+    return probs
+
+
+@pytest.mark.parametrize("prec,lam,rtol", [("fp64", 2.0, 1e-10), ("fp64", 0.05, 1e-9), ("fp32", 2.0, 1e-9),
+                                           ("bf16", 2.0, 1e-8)])
+def test_batch_solve_equals_alone(orc, prec, lam, rtol):
+    probs = make_problems(prec)
+    say(f"[batch-solve] {prec} lambda {lam}: sizes {[p['f'].shape[0] for p in probs]}")
+    ops = [p["op"] for p in probs]
+    batch = dw.batch_create(ops, graph=True)
+    fs = [torch.from_numpy(p["f"]).cuda() for p in probs]
+    als = [torch.zeros_like(f) for f in fs]
+    infos = dw.batch_solve(batch, lam, fs, als, rtol, 600, check_every=2)
+    torch.cuda.synchronize()
+    iters = []
+    for k, p in enumerate(probs):
+        a1 = torch.zeros_like(fs[k])
+        info1 = dw.fmm_solve(p["op"], lam, fs[k], a1, rtol, 600)[0]
+        iters.append(info1["iters"])
+        say(f"[batch-solve] problem {k}: n={p['f'].shape[0]} batch {infos[k]['iters']} it / "
+            f"{infos[k]['refine_steps']} ref / status {infos[k]['status']}, alone {info1['iters']} it")
+        assert infos[k] == info1, (k, infos[k], info1)
+        assert torch.equal(als[k], a1), k
+    # the problems finish at different iterations, so the matvec plan shrank on the way
+    assert max(iters) > 2 * min(iters)
+    if lam < 0.5:
+        # K~ + 0.05 I is indefinite for most of these problems: CG stops at the cap with the same
+        # not-converged report as alone
+        assert any(i["status"] == dw.E_NOT_CONVERGED for i in infos)
+        return
+    # in FP32 / BF16 the largest problem (leaf 200, general kernels) can exhaust its iterations in
+    # the inner solves, alone as in the batch
+    assert sum(i["status"] == 0 for i in infos) >= len(infos) - (0 if prec == "fp64" else 1)
+    k = 1
+    p = probs[k]
+    P = orc.Plan(p["X"], p["b"], p["leaf"], 0.8, p["kind"], 1.0, p["q"])
+    a = als[k].cpu().numpy()
+    res = np.linalg.norm(p["f"] - (P.matvec(a) + lam * a)) / np.linalg.norm(p["f"])
+    say(f"[batch-solve] oracle residual of problem {k}: {res:.2e}")
+    assert res <= 1.05 * rtol
+    batch.close()
+
+
+def test_batch_solve_start_vector_and_errors():
+    probs = make_problems("fp64", seed=5, count=4)
+    ops = [p["op"] for p in probs]
+    batch = dw.batch_create(ops)
+    fs = [torch.from_numpy(p["f"]).cuda() for p in probs]
+    rng = np.random.default_rng(1)
+    starts = [torch.from_numpy(rng.standard_normal(p["f"].shape)).cuda() for p in probs]
+    als = [s.clone() for s in starts]
+    infos = dw.batch_solve(batch, 1.0, fs, als, 1e-9, 400)
+    for k, p in enumerate(probs):
+        a1 = starts[k].clone()
+        info1 = dw.fmm_solve(p["op"], 1.0, fs[k], a1, 1e-9, 400)[0]
+        assert infos[k] == info1
+        assert torch.equal(als[k], a1)
+    # a capped solve reports NOT_CONVERGED per problem, as alone
+    als = [torch.zeros_like(f) for f in fs]
+    infos = dw.batch_solve(batch, 1.0, fs, als, 1e-14, 3)
+    assert all(i["iters"] == 3 and i["status"] == dw.E_NOT_CONVERGED for i in infos)
+    with pytest.raises(dw.DwfmmError):
+        dw.batch_solve(batch, -1.0, fs, als, 1e-9, 10)
+    with pytest.raises(dw.DwfmmError):
+        dw.batch_solve(batch, 1.0, fs, fs, 1e-9, 10)
+    mixed = [probs[0]["op"], dw.fmm_create(probs[1]["tree"], "matern32", 1.0, 4, precision="fp32")]
+    b2 = dw.batch_create(mixed)
+    with pytest.raises(dw.DwfmmError):
+        dw.batch_solve(b2, 1.0, fs[:2], [torch.zeros_like(f) for f in fs[:2]], 1e-9, 10)
+
+
+@pytest.mark.parametrize("case", ["d20_gauss", "d10_matern", "d4_leaf16", "d6_afp"])
+@pytest.mark.parametrize("prec,nrhs", [("fp64", 1), ("fp32", 4), ("bf16", 32)])
+def test_op_bytes_for_is_exact(case, prec, nrhs):
+    n, d, r, kind, q, leaf, kw = {
+        "d20_gauss": (20000, 20, 3.0, "gaussian", 6, 128, {}),
+        "d10_matern": (30000, 10, 2.0, "matern32", 6, 128, {}),
+        "d4_leaf16": (5000, 4, 2.0, "matern32", 4, 16, {}),
+        "d6_afp": (6000, 6, 2.0, "exponential", 5, 64, dict(nodes="afp", weight_rule="R3")),
+    }[case]
+    X = W.points(n, d, r, 77)
+    tree = dw.build_tree(torch.from_numpy(X).cuda(), W.dim_weights(d, r), leaf, 0.8)
+    pred = dw.op_bytes_for(tree, q, precision=prec, max_nrhs=nrhs, **kw)
+    op = dw.fmm_create(tree, kind, 0.5, q, precision=prec, max_nrhs=nrhs, **kw)
+    got = dw.op_bytes(op)
+    say(f"[bytes] {case} {prec} nrhs {nrhs}: predicted {pred}, held {got}, "
+        f"size-only estimate {dw.estimate_bytes(n, d, leaf, op.nx, nrhs)}")
+    assert pred == got
+
+
+def test_server_stays_within_budget():
+    # requests with long nearfield lists (leaf 32 and eta = 3: 240-410 owned leaf pairs per leaf
+    # by the oracle's partition): the size-only estimate is below their true bytes, so the server
+    # must re-check each one before allocating
+    rng = np.random.default_rng(17)
+    reqs = []
+    for i in range(6):
+        n = int(rng.integers(20000, 40000))
+        X = W.points(n, 6, 2.0, 900 + i)
+        reqs.append(dict(X=X, b=W.dim_weights(6, 2.0), f=np.sin(X.sum(1))))
+    exact = []
+    for r in reqs:
+        tree = dw.build_tree(torch.from_numpy(r["X"]).cuda(), r["b"], 32, 3.0)
+        exact.append(dw.op_bytes_for(tree, 4) + 16 * r["X"].shape[0])
+        tree.close()
+    est = [dw.estimate_bytes(r["X"].shape[0], 6, 32, 11, 1) + 16 * r["X"].shape[0] for r in reqs]
+    say(f"[budget] exact {exact}, size-only estimates {est}")
+    assert any(e > s for e, s in zip(exact, est))
+    budget = int(1.5 * max(exact))
+    srv = dw.Server(budget, max_active=8, check_every=1)
+    ids = [srv.submit(r["X"], r["b"], r["f"], 32, 3.0, "matern32", 1.0, 4, 10.0, 1e-8, 300) for r in reqs]
+    done, peak, ticks = {}, 0, 0
+    while len(done) < len(ids):
+        srv.tick()
+        ticks += 1
+        peak = max(peak, srv.bytes_held())
+        assert srv.bytes_held() <= budget
+        for k, rid in enumerate(ids):
+            if k not in done:
+                out = srv.result(rid)
+                if out is not None:
+                    done[k] = out
+        assert ticks < 100000
+    say(f"[budget] budget {budget}, peak held {peak}, {ticks} ticks")
+    assert all(done[k][1]["status"] == 0 for k in done)
+    assert srv.bytes_held() == 0
