@@ -46,6 +46,17 @@ def pairwise_dist(A, B, chunk_bytes: float = 2e9):
     return out
 
 
+def cpu_model() -> str:
+    """The host CPU's model name (/proc/cpuinfo)."""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(w, X, b, x, budget_leaves: int):
     """The FP64 oracle on the host cores, on the first `budget_leaves` target leaves."""
     import oracle
@@ -63,6 +74,7 @@ def cpu_baseline(w, X, b, x, budget_leaves: int):
         "value": npts * x.shape[1] / t / 1e6,
         "unit": "Mpoints/s",
         "cores": oracle.num_threads(),
+        "cpu_model": cpu_model(),
         "kind": "oracle",
         "sample": (f"rows of the first {L} of {2 ** P.J} target leaves ({npts} points) of the same "
                    f"N={X.shape[0]} workload; time {t:.2f} s includes the full upward pass over all "
@@ -207,89 +219,195 @@ def bench_batch(args):
     print(json.dumps(out), flush=True)
 
 
-def make_trace(count: int, rate: float, seed: int = 5):
-    """Solve requests: Poisson arrivals at `rate` per second; N log-uniform in [1e3, 5e5], d uniform
-    in {6..24}, b_k = k^-2 or k^-3 (coin flip), q in {4, 5, 6}; request i draws its points from
-    seed 5_000_000 + i; data f = sin(sum_k x_k)."""
+def bench_batch_solve(args):
+    """The batching workload solved: (K~_i + lambda I) alpha_i = f_i, f = sin(sum_k x_k), for every
+    problem at once with dwfmm_batch_solve (FP32 batched matvecs inside FP64 CG with FP64
+    iterative refinement to rtol 1e-8, or FP64 CG), against the same solves one problem at a time."""
+    import torch
+    from concurrent.futures import ThreadPoolExecutor
+    import paper_2402_09531_amd as dw
+    dev = torch.device("cuda:0")
+    probs = make_batch_problems(args.batch)
+    total = sum(p[0] for p in probs)
+    lam, rtol, maxit = args.serve_lambda, 1e-8, args.batch_max_iter
+    log(f"[batch-solve] {len(probs)} problems, {total} points, {args.precision}, lambda {lam:g}")
+
+    def setup(p):
+        n, d, X, b = p
+        tree = dw.build_tree(torch.from_numpy(X).to(dev), b, 128, 0.8)
+        return dw.fmm_create(tree, "matern32", 1.0, 5, precision=args.precision, check_every=8)
+
+    t0 = time.perf_counter()
+    with ThreadPoolExecutor(8) as ex:
+        ops = list(ex.map(setup, probs))
+    fs = [torch.from_numpy(np.sin(p[2].sum(1))[:, None]).to(dev) for p in probs]
+    torch.cuda.synchronize()
+    t_setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    batch = dw.batch_create(ops, graph=True, tune=not args.no_tune)
+    t_plan = time.perf_counter() - t0
+    als = [torch.zeros_like(f) for f in fs]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = dw.batch_solve(batch, lam, fs, als, rtol, maxit, check_every=8)
+    torch.cuda.synchronize()
+    t_b = time.perf_counter() - t0
+    log(f"[batch-solve] batched: {t_b:.2f} s ({len(probs) / t_b:.1f} solves/s)")
+    t0 = time.perf_counter()
+    same = 0
+    for k, (op, f) in enumerate(zip(ops, fs)):
+        a1 = torch.zeros_like(f)
+        i1 = dw.fmm_solve(op, lam, f, a1, rtol, maxit)[0]
+        same += int(i1 == infos[k] and torch.equal(a1, als[k]))
+        if k % 128 == 127:
+            log(f"[batch-solve] one at a time: {k + 1}/{len(probs)} ({time.perf_counter() - t0:.0f} s)")
+    torch.cuda.synchronize()
+    t_s = time.perf_counter() - t0
+    conv = sum(i["status"] == 0 for i in infos)
+    out = {"metric": "batched CG solves/s", "value": round(len(probs) / t_b, 3), "unit": "solves/s",
+           "higher_is_better": True, "n_gpus": 1,
+           "dtype": "f64" if args.precision == "fp64" else args.precision + " matvec, f64 CG + refinement",
+           "data": "synthetic",
+           "config": {"workload": f"batch of {len(probs)} problems, N log-uniform [2e3, 2e5], d in 8..16, "
+                                  "b_k=k^-2, Matern-3/2 l=1, q=5, leaf 128, eta 0.8, f=sin(sum x)",
+                      "lambda": lam, "rtol": rtol, "max_iter": maxit, "total_points": total},
+           "batched_s": round(t_b, 3), "one_at_a_time_s": round(t_s, 3),
+           "one_at_a_time_solves_per_s": round(len(probs) / t_s, 3), "speedup": round(t_s / t_b, 3),
+           "converged": conv, "bitwise_equal_to_one_at_a_time": same,
+           "cg_iterations": int(sum(i["iters"] for i in infos)),
+           "refinement_steps": int(sum(i["refine_steps"] for i in infos)),
+           "max_rel_res_true": float(max(i["rel_res_true"] for i in infos)),
+           "not_converged": [{"problem": k, "n": probs[k][0], "d": probs[k][1], "iters": i["iters"],
+                              "refine_steps": i["refine_steps"], "neg_curvature_steps": i["neg_curvature_steps"],
+                              "rel_res_true": i["rel_res_true"]} for k, i in enumerate(infos) if i["status"] != 0],
+           "setup_s": round(t_setup, 2), "plan_s": round(t_plan, 2)}
+    print(json.dumps(out), flush=True)
+
+
+def make_trace(seconds: float, rate: float = 200.0, seed: int = 5, horizon: float = 60.0):
+    """Solve requests of the serving workload: Poisson arrivals at `rate` per second over `horizon`
+    seconds; per request (in arrival order) N log-uniform in [1e3, 5e5], d uniform in {6..24},
+    b_k = k^-2 or k^-3 (coin flip), q in {4, 5, 6}; request i draws its points from seed
+    5_000_000 + i; data f = sin(sum_k x_k).  Returns the requests that arrive in the first `seconds`
+    (points are generated for those only)."""
     from paper_2402_09531_amd import workloads as W
     rng = np.random.default_rng(seed)
-    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=count))
-    reqs = []
-    for i in range(count):
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, size=int(rate * horizon * 1.5) + 100))
+    arrivals = arrivals[arrivals < horizon]
+    spec = []
+    for i in range(len(arrivals)):
         n = int(round(np.exp(rng.uniform(np.log(1e3), np.log(5e5)))))
         d = int(rng.integers(6, 25))
         r = 2.0 if rng.random() < 0.5 else 3.0
         q = int(rng.integers(4, 7))
+        spec.append((float(arrivals[i]), n, d, r, q))
+    reqs = []
+    for i, (t, n, d, r, q) in enumerate(spec):
+        if t >= seconds:
+            break
         X = W.points(n, d, r, 5_000_000 + i)
-        reqs.append(dict(t=float(arrivals[i]), X=X, b=W.dim_weights(d, r), f=np.sin(X.sum(1)), q=q))
+        reqs.append(dict(t=t, X=X, b=W.dim_weights(d, r), f=np.sin(X.sum(1)), q=q))
     return reqs
 
 
-def bench_serve(args):
-    """Continuous-batching server against plain one-at-a-time FP64 solves on the same trace."""
+SERVE_LAMBDA = 10.0   # every request of the trace converges to rtol 1e-8 at this ridge; at 1e-6 none does
+
+
+def served_vs_plain(reqs, lam: float, rtol: float, maxit: int, budget_gb: int, max_active: int, check_every: int):
+    """The continuous-batching server against plain one-at-a-time FP64 solves on the same arrivals.
+    Each request ends when CG reaches rtol (or at maxit).  Latency = arrival to alpha on the host;
+    the server also reports its wait for a slot and memory (queueing), its preparation (tree and
+    operator on a host thread) and its service (from activation to retirement); plain solves wait in
+    arrival order (queueing) and are then solved (service, preparation included)."""
     import torch
     import paper_2402_09531_amd as dw
     dev = torch.device("cuda:0")
-    reqs = make_trace(args.serve, args.rate)
-    lam, rtol, maxit = 1e-6, 1e-8, args.max_iter
-    log(f"[serve] {len(reqs)} requests over {reqs[-1]['t']:.2f} s, total points "
-        f"{sum(r['X'].shape[0] for r in reqs)}, max_iter {maxit}")
     torch.cuda.synchronize()
-
-    # served: requests are submitted when their arrival time has passed; the server ticks
-    srv = dw.Server(args.budget_gb << 30, max_active=args.max_active, check_every=args.check_every)
+    srv = dw.Server(budget_gb << 30, max_active=max_active, check_every=check_every)
     t0 = time.perf_counter()
-    ids, done, nxt = {}, {}, 0
+    ids, done, nxt, req_of = {}, {}, 0, {}
+    last_log = t0
     while len(done) < len(reqs):
         now = time.perf_counter() - t0
         while nxt < len(reqs) and reqs[nxt]["t"] <= now:
             r = reqs[nxt]
             ids[nxt] = srv.submit(r["X"], r["b"], r["f"], 128, 0.8, "matern32", 1.0, r["q"], lam, rtol, maxit)
+            req_of[ids[nxt]] = nxt
             nxt += 1
         active, queued = srv.tick()
         if active == 0 and queued == 0 and nxt < len(reqs):
             time.sleep(max(0.0, min(0.01, reqs[nxt]["t"] - (time.perf_counter() - t0))))
-        for k, rid in ids.items():
-            if k not in done:
-                out = srv.result(rid)
-                if out is not None:
-                    done[k] = (time.perf_counter() - t0, out[1])
+        for rid in srv.finished():
+            k = req_of[rid]
+            out = srv.result(rid, with_times=True)
+            done[k] = (time.perf_counter() - t0, out[1], out[2])
+        if time.perf_counter() - last_log > 10:
+            last_log = time.perf_counter()
+            log(f"[serve] served: {len(done)}/{len(reqs)} done, {active} active, {queued} queued "
+                f"({last_log - t0:.0f} s)")
     t_served = time.perf_counter() - t0
+    srv.close()
+    log(f"[serve] served: {len(reqs)} requests in {t_served:.2f} s")
     lat_s = np.array([done[k][0] - reqs[k]["t"] for k in range(len(reqs))])
-    iters_s = sum(done[k][1]["iters"] for k in done)
-    log(f"[serve] served: {t_served:.2f} s")
+    tm = np.array([done[k][2] for k in range(len(reqs))])            # submit, hand-off, active, retired
+    q_s, prep_s, svc_s = tm[:, 1] - tm[:, 0], tm[:, 2] - tm[:, 1], tm[:, 3] - tm[:, 2]
 
-    # plain: one request at a time in arrival order, FP64 solve
     t0 = time.perf_counter()
-    fin = []
-    for r in reqs:
+    start, fin, plain_info = [], [], []
+    for k, r in enumerate(reqs):
         now = time.perf_counter() - t0
         if now < r["t"]:
             time.sleep(r["t"] - now)
+        start.append(time.perf_counter() - t0)
         tree = dw.build_tree(torch.from_numpy(r["X"]).to(dev), r["b"], 128, 0.8)
         op = dw.fmm_create(tree, "matern32", 1.0, r["q"])
         fd = torch.from_numpy(r["f"][:, None]).to(dev)
         ad = torch.zeros_like(fd)
-        dw.fmm_solve(op, lam, fd, ad, rtol, maxit)
-        torch.cuda.synchronize()
+        plain_info.append(dw.fmm_solve(op, lam, fd, ad, rtol, maxit)[0])
+        ad.cpu()
         op.close()
         tree.close()
         fin.append(time.perf_counter() - t0)
+        if k % 100 == 99:
+            log(f"[serve] plain: {k + 1}/{len(reqs)} done ({fin[-1]:.0f} s)")
     t_plain = time.perf_counter() - t0
-    lat_p = np.array([fin[k] - reqs[k]["t"] for k in range(len(reqs))])
     log(f"[serve] plain: {t_plain:.2f} s")
-    pct = lambda a, p: round(float(np.percentile(a, p)) * 1e3, 2)
-    out = {"metric": "served solves/s + p99 latency vs plain", "value": round(len(reqs) / t_served, 3),
-           "unit": "solves/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic",
-           "served": {"solves_per_s": round(len(reqs) / t_served, 3), "p50_ms": pct(lat_s, 50),
-                      "p99_ms": pct(lat_s, 99), "makespan_s": round(t_served, 3), "cg_iterations": int(iters_s)},
-           "plain": {"solves_per_s": round(len(reqs) / t_plain, 3), "p50_ms": pct(lat_p, 50),
-                     "p99_ms": pct(lat_p, 99), "makespan_s": round(t_plain, 3)},
-           "speedup_solves_per_s": round(t_plain / t_served, 3),
-           "config": {"workload": f"{len(reqs)} solve requests, Poisson arrivals at {args.rate}/s, N log-uniform "
-                                  "[1e3, 5e5], d in 6..24, b_k=k^-2 or k^-3, Matern-3/2 l=1, q in 4..6, "
-                                  f"lambda 1e-6, rtol 1e-8, max_iter {maxit}, leaf 128, eta 0.8, FP64 CG",
-                      "budget_gb": args.budget_gb, "max_active": args.max_active, "check_every": args.check_every}}
+    lat_p = np.array([fin[k] - reqs[k]["t"] for k in range(len(reqs))])
+    q_p = np.array([start[k] - reqs[k]["t"] for k in range(len(reqs))])
+    svc_p = np.array([fin[k] - start[k] for k in range(len(reqs))])
+    ms = lambda a, p: round(float(np.percentile(a, p)) * 1e3, 2)  # noqa: E731
+    pct = lambda a: {"p50_ms": ms(a, 50), "p99_ms": ms(a, 99)}  # noqa: E731
+    info_s = [done[k][1] for k in range(len(reqs))]
+    conv = lambda infos: sum(i["status"] == 0 for i in infos)  # noqa: E731
+    same_iters = sum(a["iters"] == b["iters"] for a, b in zip(info_s, plain_info))
+    return {
+        "requests": len(reqs), "arrival_window_s": round(reqs[-1]["t"], 3),
+        "ends_when": f"relative residual <= {rtol:g} (or {maxit} CG iterations); lambda = {lam:g}",
+        "server": {"solves_per_s": round(len(reqs) / t_served, 3), "makespan_s": round(t_served, 3),
+                   "latency": pct(lat_s), "queueing": pct(q_s), "preparation": pct(prep_s), "service": pct(svc_s),
+                   "converged": conv(info_s), "cg_iterations": int(sum(i["iters"] for i in info_s)),
+                   "max_rel_res_true": float(max(i["rel_res_true"] for i in info_s))},
+        "plain": {"solves_per_s": round(len(reqs) / t_plain, 3), "makespan_s": round(t_plain, 3),
+                  "latency": pct(lat_p), "queueing": pct(q_p), "service": pct(svc_p),
+                  "converged": conv(plain_info), "cg_iterations": int(sum(i["iters"] for i in plain_info))},
+        "speedup_solves_per_s": round(t_plain / t_served, 3),
+        "same_iterations_as_plain": same_iters,
+        "config": {"workload": "serving trace: Poisson arrivals at 200/s, N log-uniform [1e3, 5e5], d in 6..24, "
+                               "b_k=k^-2 or k^-3, Matern-3/2 l=1, q in 4..6, leaf 128, eta 0.8, FP64 CG, f=sin(sum x)",
+                   "lambda": lam, "rtol": rtol, "max_iter": maxit, "budget_gb": budget_gb,
+                   "max_active": max_active, "check_every": check_every},
+    }
+
+
+def bench_serve(args):
+    """Continuous-batching server against plain one-at-a-time FP64 solves on the serving trace."""
+    reqs = make_trace(args.serve_seconds)
+    log(f"[serve] {len(reqs)} requests over {reqs[-1]['t']:.2f} s, total points "
+        f"{sum(r['X'].shape[0] for r in reqs)}")
+    res = served_vs_plain(reqs, args.serve_lambda, 1e-8, args.max_iter, args.budget_gb, args.max_active,
+                          args.check_every)
+    out = {"metric": "served solves/s + p99 latency vs plain", "value": res["server"]["solves_per_s"],
+           "unit": "solves/s", "higher_is_better": True, "n_gpus": 1, "dtype": "f64", "data": "synthetic", **res}
     print(json.dumps(out), flush=True)
 
 
@@ -493,14 +611,7 @@ def bench_oracle_timing(args):
     iterations: that system is indefinite at q = 4 and does not reach 1e-8)."""
     import oracle
     from paper_2402_09531_amd import workloads as W
-    cpu = "unknown"
-    try:
-        for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                cpu = line.split(":", 1)[1].strip()
-                break
-    except OSError:
-        pass
+    cpu = cpu_model()
     threads = oracle.num_threads()
     out = {"metric": "oracle matvec Mpoints/s on the host", "n_gpus": 0, "dtype": "f64", "data": "synthetic",
            "config": {"workload": "N=4096 d=4 Matern, N=1e6 d=10 Matern, N=1e6 d=20 Gaussian"},
@@ -710,6 +821,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--batch", type=int, default=0, help="batch mode: number of independent problems")
     ap.add_argument("--no-tune", action="store_true", help="batch: keep the default M2L tile shape")
+    ap.add_argument("--batch-solve", action="store_true",
+                    help="batch: CG solves of every problem at once (dwfmm_batch_solve) vs one at a time")
+    ap.add_argument("--batch-max-iter", type=int, default=600, help="batch-solve: CG iteration cap per problem")
     ap.add_argument("--paper-ce", action="store_true", help="compression error at the paper's Sec 6.2 settings")
     ap.add_argument("--paper-pe", action="store_true",
                     help="prediction error at the paper's best Sec 6.2 parameters (CG solves)")
@@ -731,12 +845,15 @@ def main():
     ap.add_argument("--ce-eta", type=float, default=1.0,
                     help="paper-ce: admissibility parameter of build_tree (dist >= eta * max full diagonal); "
                          "1.0 is the paper's eta = 0.5 read as eta * dist >= max half-diagonal")
-    ap.add_argument("--serve", type=int, default=0, help="serving mode: number of solve requests")
-    ap.add_argument("--rate", type=float, default=200.0, help="serving: arrivals per second")
-    ap.add_argument("--max-iter", type=int, default=20, help="serving: CG iterations per request")
+    ap.add_argument("--serve", action="store_true", help="serving mode: served vs plain on the serving trace")
+    ap.add_argument("--serve-seconds", type=float, default=0.5,
+                    help="serving: the requests arriving in the first this many seconds of the trace "
+                         "(also the served leg of the default run; 0 skips it there)")
+    ap.add_argument("--serve-lambda", type=float, default=SERVE_LAMBDA, help="serving: ridge of every request")
+    ap.add_argument("--max-iter", type=int, default=400, help="serving: CG iteration cap per request")
     ap.add_argument("--budget-gb", type=int, default=128, help="serving: device memory budget")
     ap.add_argument("--max-active", type=int, default=64, help="serving: active request slots")
-    ap.add_argument("--check-every", type=int, default=4, help="serving: ticks between retirement checks")
+    ap.add_argument("--check-every", type=int, default=1, help="serving: ticks between retirement checks")
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="before timing, run one plain device copy of this many MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -745,6 +862,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU sharding of "
               "the matvec is a design note, not built.", file=sys.stderr)
         sys.exit(2)
+    if args.batch and args.batch_solve:
+        bench_batch_solve(args)
+        return
     if args.batch:
         bench_batch(args)
         return
@@ -898,6 +1018,16 @@ def main():
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(w, X, b, x, args.cpu_leaves)
+    if args.serve_seconds > 0 and args.workload == "n1m_d20" and args.n is None:
+        # the metric's second half: served vs plain solves on the serving trace (untimed by the
+        # matvec steps above; its own wall clocks)
+        op.close()
+        tree.close()
+        del Xd, xd, yd
+        reqs = make_trace(args.serve_seconds)
+        log(f"[bench] serving leg: {len(reqs)} requests arriving in the first {args.serve_seconds:g} s of the trace")
+        result["served"] = served_vs_plain(reqs, args.serve_lambda, 1e-8, args.max_iter, args.budget_gb,
+                                           args.max_active, args.check_every)
     print(json.dumps(result), flush=True)
 
 

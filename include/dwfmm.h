@@ -207,7 +207,9 @@ dwfmm_status dwfmm_fmm_matvec_parts(dwfmm_op op, const double *x, double *y, int
  * residual), checked every opts.check_every iterations.  Steps with
  * p^T A p < 0 are taken and counted.  In FP32/BF16 operator precision the
  * solve is iterative refinement: an FP64 residual f - (K~ + lambda I) alpha,
- * an inner CG in reduced precision, alpha += delta.  info: host, nrhs entries.
+ * an inner CG in reduced precision, alpha += delta; a correction that raises the
+ * FP64 residual is taken back and its column stops (NOT_CONVERGED) at the lowest
+ * residual it reached.  info: host, nrhs entries.
  * Synchronises `stream`.  Returns the worst per-column status.
  * Errors: E_INVALID, E_HIP, E_NOT_CONVERGED, E_BREAKDOWN.                       */
 dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double *f, double *alpha, int32_t nrhs,
@@ -343,9 +345,15 @@ dwfmm_status dwfmm_server_submit(dwfmm_server server, const dwfmm_request *reque
  * *n_queued counts requests waiting or being prepared. */
 dwfmm_status dwfmm_server_tick(dwfmm_server server, int32_t *n_active, int32_t *n_queued);
 /* If request id has finished: *done = 1, alpha (host, n values, may be NULL) and info are
- * filled and the request is forgotten; otherwise *done = 0. */
+ * filled and the request is forgotten; otherwise *done = 0.  times (host, 4 values, may be
+ * NULL): seconds since the server's creation at which the request was submitted, handed to a
+ * preparation thread (the end of its wait for a slot and memory), made active (preparation
+ * done) and retired (alpha on the host). */
 dwfmm_status dwfmm_server_result(dwfmm_server server, int64_t id, double *alpha, dwfmm_solve_info *info,
-                                 int32_t *done);
+                                 double *times, int32_t *done);
+/* Requests finished and not yet collected by dwfmm_server_result: *count = their number,
+ * ids[0 .. min(count, cap)) their ids (host array), in retirement order.  Errors: E_INVALID. */
+dwfmm_status dwfmm_server_finished(dwfmm_server server, int64_t *ids, int32_t cap, int32_t *count);
 /* Device bytes counted against the budget (requests being prepared or active). */
 size_t dwfmm_server_bytes(dwfmm_server server);
 void dwfmm_server_destroy(dwfmm_server server);

@@ -71,7 +71,8 @@ EXPORTS = ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm
            "dwfmm_op_basis", "dwfmm_op_lebesgue", "dwfmm_op_moments", "dwfmm_op_timing", "dwfmm_batch_create", "dwfmm_batch_matvec",
            "dwfmm_batch_m2l_shapes", "dwfmm_batch_m2l_layout", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
            "dwfmm_eval_info", "dwfmm_eval_tree_get", "dwfmm_eval_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
-           "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy", "dwfmm_batch_solve", "dwfmm_op_bytes_for"]
+           "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy", "dwfmm_batch_solve", "dwfmm_op_bytes_for",
+           "dwfmm_server_finished"]
 
 
 def lib():
@@ -140,9 +141,11 @@ def lib():
         L.dwfmm_server_create.argtypes = [C.c_size_t, C.c_int32, C.c_int32, vp, C.POINTER(vp)]
         L.dwfmm_server_submit.argtypes = [vp, vp, C.POINTER(C.c_int64)]
         L.dwfmm_server_tick.argtypes = [vp, C.POINTER(C.c_int32), C.POINTER(C.c_int32)]
-        L.dwfmm_server_result.argtypes = [vp, C.c_int64, dp, C.POINTER(SolveInfo), C.POINTER(C.c_int32)]
+        L.dwfmm_server_result.argtypes = [vp, C.c_int64, dp, C.POINTER(SolveInfo), dp, C.POINTER(C.c_int32)]
         for name in ("dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick", "dwfmm_server_result"):
             getattr(L, name).restype = C.c_int
+        L.dwfmm_server_finished.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)]
+        L.dwfmm_server_finished.restype = C.c_int
         L.dwfmm_server_bytes.argtypes = [vp]
         L.dwfmm_server_bytes.restype = C.c_size_t
         L.dwfmm_server_destroy.argtypes = [vp]
@@ -545,16 +548,27 @@ class Server:
         _check(lib().dwfmm_server_tick(self._h, C.byref(a), C.byref(q)))
         return a.value, q.value
 
-    def result(self, rid: int):
-        """(alpha, info) if request rid finished, else None."""
+    def result(self, rid: int, with_times: bool = False):
+        """(alpha, info) -- with with_times, (alpha, info, times) with times = seconds since the server's
+        creation at submit, hand-off, activation and retirement -- if request rid finished, else None."""
         alpha = np.zeros(self._n[rid])
         info = SolveInfo()
         done = C.c_int32()
-        _check(lib().dwfmm_server_result(self._h, int(rid), _f64p(alpha), C.byref(info), C.byref(done)))
+        times = np.zeros(4)
+        _check(lib().dwfmm_server_result(self._h, int(rid), _f64p(alpha), C.byref(info), _f64p(times),
+                                         C.byref(done)))
         if not done.value:
             return None
         del self._n[rid]
-        return alpha, info.as_dict()
+        return (alpha, info.as_dict(), times) if with_times else (alpha, info.as_dict())
+
+    def finished(self):
+        """Ids of the requests finished and not yet collected by result()."""
+        cnt = C.c_int32()
+        _check(lib().dwfmm_server_finished(self._h, None, 0, C.byref(cnt)))
+        ids = (C.c_int64 * max(cnt.value, 1))()
+        _check(lib().dwfmm_server_finished(self._h, ids, cnt.value, C.byref(cnt)))
+        return [ids[i] for i in range(cnt.value)]
 
     def bytes_held(self) -> int:
         return int(lib().dwfmm_server_bytes(self._h))

@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <condition_variable>
@@ -1072,12 +1073,40 @@ extern "C" dwfmm_status dwfmm_fmm_solve(dwfmm_op op, double lambda, const double
                 HIP_TRY(hipGetLastError());
             }
             HIP_TRY(residual64(op, lambda, f, alpha, op->ir_r, nrhs, st, res));
+            std::vector<int32_t> keep(nrhs, 1);  // 0: take the correction back
+            bool undo = false;
             for (int c = 0; c < nrhs; ++c) {
                 if (mask[c]) continue;
                 if (std::sqrt(res[c]) <= rtol * den(c)) done[c] = 1;
-                else if (res[c] >= best[c]) stall[c]++;
+                else if (res[c] > best[c]) {
+                    keep[c] = 0;
+                    undo = true;
+                    stall[c] = 3;
+                } else if (res[c] == best[c]) stall[c]++;
                 else { best[c] = res[c]; stall[c] = 0; }
                 if (broke[c]) stall[c] = 3;
+            }
+            if (undo) {
+                // a correction that raised the FP64 residual is taken back and the column stops
+                // at the lowest residual it reached
+                if (nrhs == 1) {
+                    CgItem it = cg_item(op, lambda, nullptr, op->ir_d, 0.0, 0);
+                    it.acc = alpha;
+                    HIP_TRY(launch_cg(CG_SUB, nullptr, 0, 0, it, st));
+                } else {
+                    std::vector<double> one(nrhs, 1.0);
+                    HIP_TRY(hipMemcpyAsync(op->state + 3 * op->max_nrhs, keep.data(), sizeof(int32_t) * nrhs,
+                                           hipMemcpyHostToDevice, st));
+                    HIP_TRY(hipMemcpyAsync(op->scal + 10 * nrhs, one.data(), sizeof(double) * nrhs,
+                                           hipMemcpyHostToDevice, st));
+                    hipLaunchKernelGGL(axpy_kernel, dim3(kEwBlocks), dim3(256), 0, st, alpha, alpha, op->ir_d, op->scal,
+                                       10, -1.0, op->state + 3 * op->max_nrhs, 1, total, nrhs);
+                    HIP_TRY(hipGetLastError());
+                }
+                std::vector<double> res2;
+                HIP_TRY(residual64(op, lambda, f, alpha, op->ir_r, nrhs, st, res2));
+                for (int c = 0; c < nrhs; ++c)
+                    if (!keep[c]) res[c] = res2[c];
             }
         }
         for (int c = 0; c < nrhs; ++c) {
@@ -1117,8 +1146,12 @@ struct dwfmm_batch_s {
     dwfmm_batch b64 = nullptr;        // FP64 companion plan for the refinement residuals of a solve
     CgItem *d_cg = nullptr;           // solve: CG descriptors and status mirror, one per problem
     double *d_mirror = nullptr;
+    StreamFork fork;                  // eager calls: the farfield beside the nearfield
     ~dwfmm_batch_s()
     {
+        if (fork.forked) (void)hipEventDestroy(fork.forked);
+        if (fork.joined) (void)hipEventDestroy(fork.joined);
+        if (fork.side) (void)hipStreamDestroy(fork.side);
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
     }
@@ -1328,8 +1361,17 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
             return s;
         }
     }
+    if (!(flags & DWFMM_BATCH_GRAPH) && !b->items.empty() &&
+        ((e = hipStreamCreateWithFlags(&b->fork.side, hipStreamNonBlocking)) != hipSuccess ||
+         (e = hipEventCreateWithFlags(&b->fork.forked, hipEventDisableTiming)) != hipSuccess ||
+         (e = hipEventCreateWithFlags(&b->fork.joined, hipEventDisableTiming)) != hipSuccess)) {
+        b->arena.release();
+        delete b;
+        return fail(DWFMM_E_HIP, std::string("batch streams: ") + hipGetErrorString(e));
+    }
     if ((flags & DWFMM_BATCH_GRAPH) && !b->items.empty()) {
-        // capture the batched matvec once; each call refreshes the x/y pointer arrays, then replays it
+        // capture the batched matvec once (its stages in order on one stream); each call refreshes
+        // the x/y pointer arrays, then replays it
         hipStream_t cs;
         if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) == hipSuccess) {
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
@@ -1397,7 +1439,7 @@ extern "C" dwfmm_status dwfmm_batch_matvec(dwfmm_batch b, const double *const *x
         if (b->exec)
             HIP_TRY(hipGraphLaunch(b->exec, st));
         else
-            HIP_TRY(launch_batch_matvec(b->plan, st));
+            HIP_TRY(launch_batch_matvec(b->plan, st, &b->fork));
     }
     for (size_t i = 0; i < b->ops.size(); ++i) {
         if (b->item_of[i] >= 0) continue;
@@ -1673,15 +1715,32 @@ extern "C" dwfmm_status dwfmm_batch_solve(dwfmm_batch b, double lambda, const do
             HIP_TRY(step(CG_ADD));
             rc = residual(run);
             if (rc != DWFMM_OK) return rc;
+            std::vector<int> back(P, 0);
+            bool undo = false;
             for (int i = 0; i < P; ++i) {
                 if (!run[i]) continue;
                 if (std::sqrt(res[i]) <= rtol * den[i]) done[i] = 1;
-                else if (res[i] >= best[i]) stall[i]++;
+                else if (res[i] > best[i]) {
+                    back[i] = 1;
+                    undo = true;
+                    stall[i] = 3;
+                } else if (res[i] == best[i]) stall[i]++;
                 else {
                     best[i] = res[i];
                     stall[i] = 0;
                 }
                 if (broke[i]) stall[i] = 3;
+            }
+            if (undo) {
+                // as alone: a correction that raised the residual is taken back, the problem stops
+                HIP_TRY(set_items([&](int i, CgItem &it) {
+                    it = cg_item(b->ops[i], lambda, nullptr, b->ops[i]->ir_d, 0.0, 0);
+                    it.acc = alphas[i];
+                    it.frozen = !back[i];
+                }));
+                HIP_TRY(step(CG_SUB));
+                rc = residual(back);
+                if (rc != DWFMM_OK) return rc;
             }
         }
         for (int i = 0; i < P; ++i) {
@@ -1720,6 +1779,7 @@ struct ServerRequest {
     int iters = 0;
     std::vector<double> alpha;      // result
     dwfmm_solve_info info{};
+    double t_submit = 0, t_handoff = 0, t_active = 0, t_retired = 0;  // seconds since the server's creation
 };
 
 constexpr int kServerWorkers = 4;
@@ -1727,6 +1787,8 @@ constexpr int kServerWorkers = 4;
 }  // namespace
 
 struct dwfmm_server_s {
+    std::chrono::steady_clock::time_point t0 = std::chrono::steady_clock::now();
+    double now() const { return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count(); }
     size_t budget = 0, held = 0;
     int max_active = 0, check_every = 1, device = 0;
     hipStream_t st = nullptr;
@@ -1886,6 +1948,7 @@ void hand_off(dwfmm_server s)
             s->queue.pop_front();
             s->held += r->need;
             s->preparing++;
+            r->t_handoff = s->now();
             s->todo.push_back(r);
             any = true;
         }
@@ -1916,6 +1979,7 @@ void admit_ready(dwfmm_server s, bool wait)
         if (r->prep != DWFMM_OK) {
             release_request(r, s->held);
             r->info.status = r->prep;
+            r->t_active = r->t_retired = s->now();
             s->finished.push_back(r);
             continue;
         }
@@ -1923,6 +1987,7 @@ void admit_ready(dwfmm_server s, bool wait)
         s->held = s->held - std::min(s->held, r->need) + actual;
         r->need = actual;
         r->iters = 0;
+        r->t_active = s->now();
         s->active.push_back(r);
         s->dirty = true;
     }
@@ -1949,6 +2014,7 @@ dwfmm_status retire(dwfmm_server s, ServerRequest *r, int32_t state)
     r->info.rel_res_true = std::sqrt(res[0]) / den;
     r->info.status = state == 1 ? DWFMM_OK : (state == 2 ? DWFMM_E_BREAKDOWN : DWFMM_E_NOT_CONVERGED);
     release_request(r, s->held);
+    r->t_retired = s->now();
     return DWFMM_OK;
 }
 
@@ -2044,6 +2110,7 @@ extern "C" dwfmm_status dwfmm_server_submit(dwfmm_server s, const dwfmm_request 
     r->b.assign(q.dim_weights, q.dim_weights + q.d);
     r->f.assign(q.f, q.f + q.n);
     r->need = request_bytes(*r);
+    r->t_submit = s->now();
     s->queue.push_back(r);
     *id = r->id;
     hand_off(s);
@@ -2131,7 +2198,7 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
 }
 
 extern "C" dwfmm_status dwfmm_server_result(dwfmm_server s, int64_t id, double *alpha, dwfmm_solve_info *info,
-                                            int32_t *done)
+                                            double *times, int32_t *done)
 {
     if (!s || !done) return fail(DWFMM_E_INVALID, "NULL argument");
     *done = 0;
@@ -2140,11 +2207,25 @@ extern "C" dwfmm_status dwfmm_server_result(dwfmm_server s, int64_t id, double *
         if (r->id != id) continue;
         if (alpha) std::copy(r->alpha.begin(), r->alpha.end(), alpha);
         if (info) *info = r->info;
+        if (times) {
+            times[0] = r->t_submit;
+            times[1] = r->t_handoff;
+            times[2] = r->t_active;
+            times[3] = r->t_retired;
+        }
         *done = 1;
         s->finished.erase(s->finished.begin() + i);
         delete r;
         return DWFMM_OK;
     }
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_server_finished(dwfmm_server s, int64_t *ids, int32_t cap, int32_t *count)
+{
+    if (!s || !count || cap < 0 || (cap > 0 && !ids)) return fail(DWFMM_E_INVALID, "bad argument");
+    *count = (int32_t)s->finished.size();
+    for (int i = 0; i < std::min<int>(cap, (int)s->finished.size()); ++i) ids[i] = s->finished[i]->id;
     return DWFMM_OK;
 }
 

@@ -111,7 +111,8 @@ struct BatchPlan {
     std::vector<BatchLaunch> m2l, p2p;
 };
 
-hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t stream);
+// With `fork`, the farfield stages run on its side stream beside the nearfield (same bits).
+hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t stream, const StreamFork *fork = nullptr);
 // Waves per cluster compiled for an M2L launch with nxt node tiles: 1 only up to two tiles
 // (its per-lane accumulators grow with 4 / wpc x nxt).
 inline bool m2l_wpc_available(int nxt, int wpc) { return wpc == 4 || wpc == 2 || (wpc == 1 && nxt <= 2); }
@@ -160,6 +161,7 @@ enum CgStep {
     CG_RES,        // blocks: out = f - (out + lambda v); partial |out|^2
     CG_RES_SUM,    // problems: |out|^2 into scal[8]
     CG_ADD,        // blocks: acc += x
+    CG_SUB,        // blocks: acc -= x
     CG_MIRROR      // problems: copy state and scalars to mirror, for one host read of many problems
 };
 inline int cg_blocks(int n) { return (int)std::max<int64_t>(1, std::min<int64_t>(kDotBlocks, ((int64_t)n + 4095) / 4096)); }

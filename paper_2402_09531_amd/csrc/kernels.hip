@@ -2627,6 +2627,10 @@ __global__ __launch_bounds__(256) void cg_block_kernel(const CgItem *__restrict_
         if (it.frozen) return;
         double *acc = it.acc;
         for (int i = i0 + threadIdx.x; i < i1; i += 256) acc[i] = acc[i] + x[i];
+    } else if (STEP == CG_SUB) {
+        if (it.frozen) return;
+        double *acc = it.acc;
+        for (int i = i0 + threadIdx.x; i < i1; i += 256) acc[i] = acc[i] - x[i];
     }
 }
 
@@ -2871,15 +2875,30 @@ hipError_t launch_batch_m2l(const BatchPlan &P, const BatchLaunch &L, hipStream_
     return hipGetLastError();
 }
 
-hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t st)
+hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t st, const StreamFork *fork)
 {
     if (P.leaf_cnt == 0) return hipSuccess;
     hipLaunchKernelGGL(p2m_batch_kernel, dim3(P.leaf_cnt), dim3(256), 0, st, P.items, P.xs, P.work + P.leaf_off);
+    // the farfield (moments, coupling, locals) only reads the charges P2M wrote and writes the
+    // moments and locals, the nearfield only the row and column sums: with a fork the farfield
+    // runs on the side stream beside the nearfield and is joined before the combine
+    const bool forked = fork && fork->side && (!P.m2m.empty() || !P.m2l.empty() || !P.l2l.empty());
+    hipStream_t fs = st;
+    if (forked) {
+        hipError_t e = hipEventRecord(fork->forked, st);
+        if (e == hipSuccess) e = hipStreamWaitEvent(fork->side, fork->forked, 0);
+        if (e != hipSuccess) return e;
+        fs = fork->side;
+    }
     for (auto &lv : P.m2m)
-        hipLaunchKernelGGL(m2m_batch_kernel, dim3(lv.second), dim3(64), 0, st, P.items, P.work + lv.first);
-    for (auto &L : P.m2l) (void)launch_batch_m2l(P, L, st);
+        hipLaunchKernelGGL(m2m_batch_kernel, dim3(lv.second), dim3(64), 0, fs, P.items, P.work + lv.first);
+    for (auto &L : P.m2l) (void)launch_batch_m2l(P, L, fs);
     for (auto &lv : P.l2l)
-        hipLaunchKernelGGL(l2l_batch_kernel, dim3(lv.second), dim3(64), 0, st, P.items, P.work + lv.first);
+        hipLaunchKernelGGL(l2l_batch_kernel, dim3(lv.second), dim3(64), 0, fs, P.items, P.work + lv.first);
+    if (forked) {
+        hipError_t e = hipEventRecord(fork->joined, fs);
+        if (e != hipSuccess) return e;
+    }
     for (auto &L : P.p2p) {
         const bool lp = L.prec != 0;
         switch (L.kind) {
@@ -2890,6 +2909,10 @@ hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t st)
             break;
         default: lp ? launch_p2p_batch_k<2, true>(P, L, st) : launch_p2p_batch_k<2, false>(P, L, st); break;
         }
+    }
+    if (forked) {
+        hipError_t e = hipStreamWaitEvent(st, fork->joined, 0);
+        if (e != hipSuccess) return e;
     }
     hipLaunchKernelGGL(combine_batch_kernel, dim3(P.leaf_cnt), dim3(kSymLeaf), 0, st, P.items, P.ys,
                        P.work + P.leaf_off);
@@ -2980,6 +3003,7 @@ hipError_t launch_cg(int step, const CgItem *items, int nitems, int nblocks, con
     case CG_P: hipLaunchKernelGGL(cg_block_kernel<CG_P>, blocks, th, 0, stream, items, nitems, one); break;
     case CG_RES: hipLaunchKernelGGL(cg_block_kernel<CG_RES>, blocks, th, 0, stream, items, nitems, one); break;
     case CG_ADD: hipLaunchKernelGGL(cg_block_kernel<CG_ADD>, blocks, th, 0, stream, items, nitems, one); break;
+    case CG_SUB: hipLaunchKernelGGL(cg_block_kernel<CG_SUB>, blocks, th, 0, stream, items, nitems, one); break;
     case CG_START_SUM: hipLaunchKernelGGL(cg_item_kernel<CG_START_SUM>, probs, th, 0, stream, items, one); break;
     case CG_ALPHA: hipLaunchKernelGGL(cg_item_kernel<CG_ALPHA>, probs, th, 0, stream, items, one); break;
     case CG_BETA: hipLaunchKernelGGL(cg_item_kernel<CG_BETA>, probs, th, 0, stream, items, one); break;

@@ -166,3 +166,31 @@ def test_server_stays_within_budget():
     say(f"[budget] budget {budget}, peak held {peak}, {ticks} ticks")
     assert all(done[k][1]["status"] == 0 for k in done)
     assert srv.bytes_held() == 0
+
+
+def test_refinement_never_ends_above_its_best_residual():
+    # problem 1 of the 512-problem batching workload (N = 179274, d = 12): at lambda = 10 its FP32
+    # inner CG meets negative curvature and returns a correction that raises the FP64 residual;
+    # the correction is taken back and the solve stops NOT_CONVERGED at the start's residual
+    sys.path.insert(0, __import__("os").path.dirname(__import__("os").path.dirname(__file__)))
+    rng = np.random.default_rng(4)
+    for _ in range(2):
+        n = int(round(np.exp(rng.uniform(np.log(2e3), np.log(2e5)))))
+        d = int(rng.integers(8, 17))
+    assert (n, d) == (179274, 12)
+    X = W.points(n, d, 2.0, 4001)
+    tree = dw.build_tree(torch.from_numpy(X).cuda(), W.dim_weights(d, 2.0), 128, 0.8)
+    op = dw.fmm_create(tree, "matern32", 1.0, 5, precision="fp32", check_every=8)
+    f = torch.from_numpy(np.sin(X.sum(1))[:, None]).cuda()
+    a = torch.zeros_like(f)
+    info = dw.fmm_solve(op, 10.0, f, a, 1e-8, 600)[0]
+    say(f"[undo] {info}")
+    assert info["status"] == dw.E_NOT_CONVERGED
+    assert info["refine_steps"] >= 1
+    # the FP64 residual of the returned alpha, measured apart from the solver, is its best one
+    op64 = dw.fmm_create(tree, "matern32", 1.0, 5)
+    y = torch.empty_like(f)
+    dw.fmm_matvec(op64, a, y)
+    res = float(torch.linalg.norm(f - (y + 10.0 * a)) / torch.linalg.norm(f))
+    assert res <= 1.0 + 1e-12
+    assert abs(res - info["rel_res_true"]) <= 1e-12
