@@ -515,6 +515,8 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     D.ell = kernel.ell;
     D.gauss_split = kernel.kind == DWFMM_GAUSSIAN && tree->near_reach2 / kernel.ell <= 600.0;
     D.gauss_split32 = kernel.kind == DWFMM_GAUSSIAN && tree->near_reach2 / kernel.ell <= 80.0;
+    D.matern_in_range = kernel.kind == DWFMM_MATERN32 &&
+                        std::sqrt(tree->near_reach2) * (1.7320508075688772 * 1.4426950408889634) / kernel.ell <= 1000.0;
     D.nx = nx;
     D.max_nrhs = o.max_nrhs;
     D.nodes = dnodes;
@@ -1238,11 +1240,14 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
         if ((int)work.size() > off) P.l2l.push_back({off, (int)work.size() - off});
     }
     auto key = [&](const BatchItem &I, bool far_list) {
-        // the FP64 nearfield of a split Gaussian runs its own kernel variant (kind 4)
+        // the FP64 nearfield of a split Gaussian runs its own kernel variant (kind 4), the FP64
+        // nearfield of a Matern kernel within the exponent range its unclamped variant (kind 5)
         const int kind = !far_list && I.O.kind == DWFMM_GAUSSIAN &&
                                  (I.precision == 0 ? I.O.gauss_split : I.O.gauss_split32)
                              ? 4
-                             : I.O.kind;
+                             : (!far_list && I.O.kind == DWFMM_MATERN32 && I.precision == 0 && I.O.matern_in_range
+                                    ? 5
+                                    : I.O.kind);
         return std::vector<int>{kind, (I.T.d + 3) / 4 * 4, far_list ? I.O.nxp / 16 : 0, I.precision != 0};
     };
     std::vector<std::vector<int>> keys;

@@ -49,6 +49,9 @@ struct DevOp {
     // evaluate exp(-|x-y|^2/ell) = exp(-|x-c|^2/ell) exp(-|y-c|^2/ell) exp(2 (x-c).(y-c)/ell).
     int gauss_split;
     int gauss_split32;            // the same with every exponent within 80 (the FP32 nearfield)
+    // Matern only: sqrt(3) max|x - y| / ell log2(e) <= 1000 over the nearfield (from the host's reach
+    // bound), so the FP64 nearfield's 2^-s log2(e) needs no underflow clamp
+    int matern_in_range;
 };
 
 // Optional HIP events recorded around the nearfield (P2P) and coupling (M2L)

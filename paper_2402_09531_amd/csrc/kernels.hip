@@ -105,6 +105,18 @@ __device__ __forceinline__ double kernel_fast(double r2, double inv_ell)
     }
 }
 
+// Matern-3/2 (1 + s) e^-s from s^2 = 3 r^2 / ell^2, for callers whose coordinates are already
+// scaled by sqrt(3) / ell: one multiplication fewer than kernel_fast<0>.  Without CLAMP the
+// caller guarantees s log2(e) <= 1000, so 2^-s log2(e) needs no underflow clamp.
+template <bool CLAMP>
+__device__ __forceinline__ double matern_s2(double s2)
+{
+    const double s = sqrt_pos(fmax(s2, 1e-300));
+    const double t = s * -1.4426950408889634;
+    const double e = CLAMP ? exp2_nonpos(t) : exp2_bounded(t);
+    return fma(s, e, e);
+}
+
 template <int KIND>
 __device__ __forceinline__ double kernel_val(double r2, double inv_ell)
 {
@@ -654,6 +666,12 @@ constexpr int kSymLeaf = 128;
 // Internal kernel variant of the symmetric FP64 nearfield: the Gaussian evaluated as
 // exp(-|x-c|^2/ell) exp(-|y-c|^2/ell) exp(2 (x-c).(y-c)/ell) (operators with gauss_split set).
 constexpr int kGaussSplit = 4;
+// Internal kernel variant of the symmetric FP64 nearfield: the Matern kernel of an operator whose
+// nearfield distances keep every exponent s log2(e) within 1000 (matern_in_range), evaluated
+// without the underflow clamp.
+constexpr int kMaternInRange = 5;
+template <int KIND>
+constexpr bool is_matern() { return KIND == 0 || KIND == kMaternInRange; }
 constexpr int kSymSeg = 256;  // owned blocks per column-stream segment (= threads per workgroup)
 // Row stride of the FP32 tile coordinates in LDS: a wave reads rows 4kc + g (g = 0..3) at 16
 // consecutive columns; with 16 floats of padding the rows g and g + 1 fall on the two halves
@@ -702,7 +720,11 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
                     if constexpr (DIAG) {
                         if (16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
                     }
-                    kv = kernel_fast<KIND>(r2, inv_ell);
+                    // Matern: the coordinates carry sqrt(3) / ell, so r2 is s^2
+                    if constexpr (is_matern<KIND>())
+                        kv = matern_s2<KIND == 0>(r2);
+                    else
+                        kv = kernel_fast<KIND>(r2, inv_ell);
                 }
                 racc[u][v] = fma(kv, qb, racc[u][v]);
                 if constexpr (!DIAG) cacc = fma(kv, rQ[u][v], cacc);
@@ -737,11 +759,15 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
 
     const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // the wave index is uniform: its row-tile tests below branch on scalars
+    const int tid = threadIdx.x, lane = tid & 63, w = __builtin_amdgcn_readfirstlane(tid >> 6);
     const int li = lane & 15, lg = lane >> 4;
     const int n = T.n;
     const double inv_ell = 1.0 / O.ell;
     const int ntiles = (nt + 15) / 16;
+    // Matern: shifted coordinates are scaled by sqrt(3) / ell, so the Gram tile gives s^2 = 3 r^2 / ell^2
+    constexpr bool kMat = is_matern<KIND>();
+    const double csc = kMat ? 1.7320508075688772 * inv_ell : 1.0;
 
     if (nt == 0) return;  // an empty leaf owns no block (uniform over the workgroup)
     // Coordinate rows k in [d, DK) are stored as zeros and cen[k] = 0 there, so every load
@@ -763,7 +789,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < DK; ++k) {
-            const double v = xv[k] - cen[k];
+            const double v = kMat ? csc * (xv[k] - cen[k]) : xv[k] - cen[k];
             s = fma(v, v, s);
         }
         const double q = O.xt[ii];
@@ -783,7 +809,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         const int i = 16 * rt[u] + li;
         const bool ok = i < nt;
         const int ii = cb + (ok ? i : nt - 1);
-        const double scale = KIND == kGaussSplit ? 2.0 * 1.4426950408889634 * inv_ell : -2.0;
+        const double scale = KIND == kGaussSplit ? 2.0 * 1.4426950408889634 * inv_ell : (kMat ? -2.0 * csc : -2.0);
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) {
             const int k = 4 * kc + lg;
@@ -812,7 +838,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k < DK; ++k) {
-            const double v = ok ? xv[k] - cen[k] : 0.0;
+            const double v = ok ? (kMat ? csc * (xv[k] - cen[k]) : xv[k] - cen[k]) : 0.0;
             sX[k * kSymLeaf + j] = v;
             s = fma(v, v, s);
         }
@@ -911,13 +937,16 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         }
 }
 
-// Waves per SIMD (also for the batched variant): four for the split Gaussian up to d = 20 (128
-// registers; the few spills sit outside the tile loop, and the extra wave beats the third by
-// ~2%), three for the other kinds up to d = 20 (four were slower there), else what the
-// registers allow.
+// Waves per SIMD (also for the batched variant): four for the split Gaussian and the Matern kernel
+// up to d = 20 (128 registers; the few spills sit outside the tile loop; the extra wave beats the
+// third by ~2% for both), three for the exponential kernel up to d = 20 (four were slower there),
+// else what the registers allow.
+template <int KIND, int DK>
+constexpr int sym_waves() { return (KIND == kGaussSplit || is_matern<KIND>()) && DK <= 20 ? 4 : (DK <= 20 || (KIND != kGaussSplit && DK <= 24) ? 3 : 1); }
+
 template <int KIND, int DK>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(KIND == kGaussSplit && DK <= 20 ? 4 : (DK <= 20 || (KIND != kGaussSplit && DK <= 24) ? 3 : 1), 8)))
+__attribute__((amdgpu_waves_per_eu(sym_waves<KIND, DK>(), 8)))
 void p2p_sym_kernel(DevTree T, DevOp O)
 {
     p2p_sym_body<KIND, DK>(T, O, xcd_leaf(blockIdx.x, T.nleaf));
@@ -2333,7 +2362,7 @@ __global__ __launch_bounds__(256) void m2l32_batch_kernel(const BatchItem *items
 
 template <int KIND, int DK, bool FP32>
 __global__ __launch_bounds__(256)
-__attribute__((amdgpu_waves_per_eu(KIND == kGaussSplit && DK <= 20 ? 4 : (DK <= 20 || (KIND != kGaussSplit && DK <= 24) ? 3 : 1), 8)))
+__attribute__((amdgpu_waves_per_eu(FP32 ? (KIND == kGaussSplit && DK <= 20 ? 4 : (DK <= 20 || (KIND != kGaussSplit && DK <= 24) ? 3 : 1)) : sym_waves<KIND, DK>(), 8)))
 void p2p_sym_batch_kernel(const BatchItem *items, const int2 *work)
 {
     const int2 wk = work[blockIdx.x];
@@ -2806,7 +2835,7 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
     if (sym) {
         if (near && precision == 0) {
             switch (O.kind) {
-            case 0: e = launch_sym_k<0>(T, O, st); break;
+            case 0: e = O.matern_in_range ? launch_sym_k<kMaternInRange>(T, O, st) : launch_sym_k<0>(T, O, st); break;
             case 1: e = O.gauss_split ? launch_sym_k<kGaussSplit>(T, O, st) : launch_sym_k<1>(T, O, st); break;
             default: e = launch_sym_k<2>(T, O, st); break;
             }
@@ -2906,6 +2935,9 @@ hipError_t launch_batch_matvec(const BatchPlan &P, hipStream_t st, const StreamF
         case 1: lp ? launch_p2p_batch_k<1, true>(P, L, st) : launch_p2p_batch_k<1, false>(P, L, st); break;
         case kGaussSplit:
             lp ? launch_p2p_batch_k<kGaussSplit, true>(P, L, st) : launch_p2p_batch_k<kGaussSplit, false>(P, L, st);
+            break;
+        case kMaternInRange:  // FP64 only (the reduced-precision plan keys Matern as kind 0)
+            lp ? launch_p2p_batch_k<0, true>(P, L, st) : launch_p2p_batch_k<kMaternInRange, false>(P, L, st);
             break;
         default: lp ? launch_p2p_batch_k<2, true>(P, L, st) : launch_p2p_batch_k<2, false>(P, L, st); break;
         }
