@@ -346,6 +346,7 @@ def served_vs_plain(reqs, lam: float, rtol: float, maxit: int, budget_gb: int, m
             log(f"[serve] served: {len(done)}/{len(reqs)} done, {active} active, {queued} queued "
                 f"({last_log - t0:.0f} s)")
     t_served = time.perf_counter() - t0
+    host = srv.stats()
     srv.close()
     log(f"[serve] served: {len(reqs)} requests in {t_served:.2f} s")
     lat_s = np.array([done[k][0] - reqs[k]["t"] for k in range(len(reqs))])
@@ -386,7 +387,8 @@ def served_vs_plain(reqs, lam: float, rtol: float, maxit: int, budget_gb: int, m
         "server": {"solves_per_s": round(len(reqs) / t_served, 3), "makespan_s": round(t_served, 3),
                    "latency": pct(lat_s), "queueing": pct(q_s), "preparation": pct(prep_s), "service": pct(svc_s),
                    "converged": conv(info_s), "cg_iterations": int(sum(i["iters"] for i in info_s)),
-                   "max_rel_res_true": float(max(i["rel_res_true"] for i in info_s))},
+                   "max_rel_res_true": float(max(i["rel_res_true"] for i in info_s)),
+                   "host": {k: (round(v, 3) if isinstance(v, float) else v) for k, v in host.items()}},
         "plain": {"solves_per_s": round(len(reqs) / t_plain, 3), "makespan_s": round(t_plain, 3),
                   "latency": pct(lat_p), "queueing": pct(q_p), "service": pct(svc_p),
                   "converged": conv(plain_info), "cg_iterations": int(sum(i["iters"] for i in plain_info))},

@@ -354,6 +354,11 @@ dwfmm_status dwfmm_server_result(dwfmm_server server, int64_t id, double *alpha,
 /* Requests finished and not yet collected by dwfmm_server_result: *count = their number,
  * ids[0 .. min(count, cap)) their ids (host array), in retirement order.  Errors: E_INVALID. */
 dwfmm_status dwfmm_server_finished(dwfmm_server server, int64_t *ids, int32_t cap, int32_t *count);
+/* Host-side accounting of the ticks so far: out[0..5] = ticks that ran work, batch-plan rebuilds,
+ * and the seconds the ticks spent rebuilding plans, launching their work, waiting for the
+ * device at checks, and retiring requests (residual, alpha to the host, release).  Host array
+ * of 6.  Errors: E_INVALID. */
+dwfmm_status dwfmm_server_stats(dwfmm_server server, double *out);
 /* Device bytes counted against the budget (requests being prepared or active). */
 size_t dwfmm_server_bytes(dwfmm_server server);
 void dwfmm_server_destroy(dwfmm_server server);

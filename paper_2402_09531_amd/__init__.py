@@ -72,7 +72,7 @@ EXPORTS = ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm
            "dwfmm_batch_m2l_shapes", "dwfmm_batch_m2l_layout", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
            "dwfmm_eval_info", "dwfmm_eval_tree_get", "dwfmm_eval_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
            "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy", "dwfmm_batch_solve", "dwfmm_op_bytes_for",
-           "dwfmm_server_finished"]
+           "dwfmm_server_finished", "dwfmm_server_stats"]
 
 
 def lib():
@@ -146,6 +146,8 @@ def lib():
             getattr(L, name).restype = C.c_int
         L.dwfmm_server_finished.argtypes = [vp, C.POINTER(C.c_int64), C.c_int32, C.POINTER(C.c_int32)]
         L.dwfmm_server_finished.restype = C.c_int
+        L.dwfmm_server_stats.argtypes = [vp, dp]
+        L.dwfmm_server_stats.restype = C.c_int
         L.dwfmm_server_bytes.argtypes = [vp]
         L.dwfmm_server_bytes.restype = C.c_size_t
         L.dwfmm_server_destroy.argtypes = [vp]
@@ -569,6 +571,13 @@ class Server:
         ids = (C.c_int64 * max(cnt.value, 1))()
         _check(lib().dwfmm_server_finished(self._h, ids, cnt.value, C.byref(cnt)))
         return [ids[i] for i in range(cnt.value)]
+
+    def stats(self) -> dict:
+        """Host-side accounting of the ticks (dwfmm_server_stats)."""
+        out = np.zeros(6)
+        _check(lib().dwfmm_server_stats(self._h, _f64p(out)))
+        return {"ticks": int(out[0]), "plan_rebuilds": int(out[1]), "rebuild_s": float(out[2]),
+                "launch_s": float(out[3]), "wait_s": float(out[4]), "retire_s": float(out[5])}
 
     def bytes_held(self) -> int:
         return int(lib().dwfmm_server_bytes(self._h))

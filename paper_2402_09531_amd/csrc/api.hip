@@ -1149,11 +1149,14 @@ struct dwfmm_batch_s {
     CgItem *d_cg = nullptr;           // solve: CG descriptors and status mirror, one per problem
     double *d_mirror = nullptr;
     StreamFork fork;                  // eager calls: the farfield beside the nearfield
+    bool own_fork = false;            // the fork was created for this batch (else a caller's, shared)
     ~dwfmm_batch_s()
     {
-        if (fork.forked) (void)hipEventDestroy(fork.forked);
-        if (fork.joined) (void)hipEventDestroy(fork.joined);
-        if (fork.side) (void)hipStreamDestroy(fork.side);
+        if (own_fork) {
+            if (fork.forked) (void)hipEventDestroy(fork.forked);
+            if (fork.joined) (void)hipEventDestroy(fork.joined);
+            if (fork.side) (void)hipStreamDestroy(fork.side);
+        }
         if (exec) (void)hipGraphExecDestroy(exec);
         if (graph) (void)hipGraphDestroy(graph);
     }
@@ -1172,7 +1175,7 @@ bool batch_eligible(dwfmm_op op)
 // Batch plan for a set of operators.  With sync == false the uploads stay queued on `st`
 // (their host sources live in the batch object), for callers that only use the batch on `st`.
 static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flags, hipStream_t st, bool sync,
-                                dwfmm_batch *out, int force_prec = -1);
+                                dwfmm_batch *out, int force_prec = -1, const StreamFork *shared_fork = nullptr);
 
 extern "C" dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, int32_t flags, void *stream,
                                            dwfmm_batch *out)
@@ -1181,7 +1184,7 @@ extern "C" dwfmm_status dwfmm_batch_create(const dwfmm_op *ops, int32_t count, i
 }
 
 static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flags, hipStream_t st, bool sync,
-                                dwfmm_batch *out, int force_prec)
+                                dwfmm_batch *out, int force_prec, const StreamFork *shared_fork)
 {
     if (!out) return fail(DWFMM_E_INVALID, "out is NULL");
     *out = nullptr;
@@ -1285,11 +1288,35 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
             std::stable_sort(lst.begin(), lst.end(), [&](const int2 &a, const int2 &b2) { return nfar(a) > nfar(b2); });
         }
         if (!far_list) {
-            // consecutive leaves on one XCD: block q is dealt to XCD q % 8
-            while (lst.size() % 8) lst.push_back(make_int2(-1, 0));
-            std::vector<int2> perm(lst.size());
-            const size_t chunk = lst.size() / 8;
-            for (size_t q = 0; q < lst.size(); ++q) perm[q] = lst[(q % 8) * chunk + q / 8];
+            // Workgroup q runs on XCD q % 8.  The list is cut into 8 contiguous segments of equal
+            // estimated work (consecutive leaves of a problem share source points in the XCD's
+            // L2), segment k dealt to XCD k in order and padded to the longest: the leaves of
+            // different problems differ several-fold in work, so equal counts per XCD would
+            // leave most XCDs idle while one finishes.  The estimate is half the leaf's
+            // nearfield entries (owners are balanced by block count) plus one 128-column chunk.
+            std::vector<double> wk(lst.size());
+            double total = 0.0;
+            for (size_t i = 0; i < lst.size(); ++i) {
+                const HostTree &H = *item_tree[lst[i].x];
+                const int64_t c = H.nleaf - 1 + lst[i].y;
+                const double nl = H.end[c] - H.begin[c];
+                double ns = 0.0;
+                for (int32_t q = H.Nptr[c]; q < H.Nptr[c + 1]; ++q) ns += H.end[H.Nsrc[q]] - H.begin[H.Nsrc[q]];
+                wk[i] = nl * (0.5 * ns + 128.0);
+                total += wk[i];
+            }
+            std::vector<size_t> cut(9, lst.size());
+            cut[0] = 0;
+            double acc = 0.0;
+            for (size_t i = 0, k = 1; i < lst.size() && k < 8; ++i) {
+                acc += wk[i];
+                while (k < 8 && acc >= total * k / 8.0) cut[k++] = i + 1;
+            }
+            size_t longest = 0;
+            for (int k = 0; k < 8; ++k) longest = std::max(longest, cut[k + 1] - cut[k]);
+            std::vector<int2> perm(8 * longest, make_int2(-1, 0));
+            for (int k = 0; k < 8; ++k)
+                for (size_t j = 0; j < cut[k + 1] - cut[k]; ++j) perm[8 * j + k] = lst[cut[k] + j];
             lst.swap(perm);
         }
         BatchLaunch L{k[0], k[1], k[2], k[3], (int)work.size(), (int)lst.size()};
@@ -1366,8 +1393,13 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
             return s;
         }
     }
-    if (!(flags & DWFMM_BATCH_GRAPH) && !b->items.empty() &&
-        ((e = hipStreamCreateWithFlags(&b->fork.side, hipStreamNonBlocking)) != hipSuccess ||
+    // eager batches run the farfield on a side stream: a caller's (plans rebuilt often share one)
+    // or one of their own
+    if (!(flags & DWFMM_BATCH_GRAPH) && !b->items.empty() && shared_fork && shared_fork->side)
+        b->fork = *shared_fork;
+    else if (!(flags & DWFMM_BATCH_GRAPH) && !b->items.empty() &&
+        (b->own_fork = true,
+         (e = hipStreamCreateWithFlags(&b->fork.side, hipStreamNonBlocking)) != hipSuccess ||
          (e = hipEventCreateWithFlags(&b->fork.forked, hipEventDisableTiming)) != hipSuccess ||
          (e = hipEventCreateWithFlags(&b->fork.joined, hipEventDisableTiming)) != hipSuccess)) {
         b->arena.release();
@@ -1494,7 +1526,7 @@ struct SolvePlan {
         for (int i : keep) ops.push_back(full->ops[i]);
         dwfmm_batch nb = nullptr;
         dwfmm_status rc = batch_build(ops.data(), (int)ops.size(), full->flags & DWFMM_BATCH_GRAPH, st, true, &nb,
-                                      full->force_prec);
+                                      full->force_prec, &full->fork);
         if (rc != DWFMM_OK) return rc;
         if (sub) dwfmm_batch_destroy(sub);
         sub = nb;
@@ -1660,7 +1692,8 @@ extern "C" dwfmm_status dwfmm_batch_solve(dwfmm_batch b, double lambda, const do
         // iterative refinement per problem, its outer steps taken together: FP64 residual on
         // the FP64 companion plan, inner CG on the batch's own (reduced) matvec, alpha += delta
         if (!b->b64) {
-            dwfmm_status rc = batch_build(b->ops.data(), P, b->flags & DWFMM_BATCH_GRAPH, st, true, &b->b64, DWFMM_FP64);
+            dwfmm_status rc =
+                batch_build(b->ops.data(), P, b->flags & DWFMM_BATCH_GRAPH, st, true, &b->b64, DWFMM_FP64, &b->fork);
             if (rc != DWFMM_OK) return rc;
         }
         full64 = b->b64;
@@ -1814,6 +1847,11 @@ struct dwfmm_server_s {
     std::vector<std::vector<CgItem>> old_cg;  // host sources of queued uploads, freed at the next synchronisation
     std::vector<double> h_mirror;
     int cg_nblocks = 0;
+    StreamFork fork;  // the batched farfield beside the nearfield, shared by every plan of the server
+    // host-side accounting: ticks, plan rebuilds, seconds rebuilding plans, launching a tick's
+    // work, waiting for the device at checks, retiring requests
+    int64_t n_rebuilds = 0;
+    double t_rebuild = 0, t_launch = 0, t_wait = 0, t_retire = 0;
     // preparation workers: each builds tree, operator and CG start on a stream of its own
     std::mutex mu;
     std::condition_variable cv_todo, cv_ready;
@@ -2049,6 +2087,9 @@ dwfmm_server_s::~dwfmm_server_s()
     for (hipStream_t w : worker_streams) (void)hipStreamDestroy(w);
     if (d_cg) (void)hipFree(d_cg);
     if (d_mirror) (void)hipFree(d_mirror);
+    if (fork.forked) (void)hipEventDestroy(fork.forked);
+    if (fork.joined) (void)hipEventDestroy(fork.joined);
+    if (fork.side) (void)hipStreamDestroy(fork.side);
 }
 
 extern "C" dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_active, int32_t check_every,
@@ -2067,6 +2108,9 @@ extern "C" dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_act
     hipError_t e = hipGetDevice(&s->device);
     if (e == hipSuccess) e = hipMalloc(&s->d_cg, sizeof(CgItem) * max_active);
     if (e == hipSuccess) e = hipMalloc(&s->d_mirror, sizeof(double) * 8 * max_active);
+    if (e == hipSuccess) e = hipStreamCreateWithFlags(&s->fork.side, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork.forked, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&s->fork.joined, hipEventDisableTiming);
     for (int w = 0; w < kServerWorkers && e == hipSuccess; ++w) {
         hipStream_t ws = nullptr;
         e = hipStreamCreateWithFlags(&ws, hipStreamNonBlocking);
@@ -2130,12 +2174,14 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
     admit_ready(s, s->active.empty() && s->preparing > 0);
     if (!s->active.empty()) {
         // one batched matvec q = K~ p over all active requests
+        double tm = s->now();
         if (s->dirty) {
+            s->n_rebuilds++;
             if (s->batch) s->old_batches.push_back(s->batch);
             s->batch = nullptr;
             std::vector<dwfmm_op> ops;
             for (ServerRequest *r : s->active) ops.push_back(r->op);
-            dwfmm_status rc = batch_build(ops.data(), (int)ops.size(), 0, st, false, &s->batch);
+            dwfmm_status rc = batch_build(ops.data(), (int)ops.size(), 0, st, false, &s->batch, -1, &s->fork);
             if (rc != DWFMM_OK) return rc;
             s->old_cg.push_back(std::move(s->h_cg));
             s->h_cg.clear();
@@ -2150,6 +2196,9 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
             HIP_TRY(hipMemcpyAsync(s->d_cg, s->h_cg.data(), sizeof(CgItem) * s->h_cg.size(), hipMemcpyHostToDevice,
                                    st));
             s->dirty = false;
+            const double t1 = s->now();
+            s->t_rebuild += t1 - tm;
+            tm = t1;
         }
         s->xs.clear();
         s->ys.clear();
@@ -2166,6 +2215,7 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
             HIP_TRY(launch_cg(step, s->d_cg, nact, s->cg_nblocks, s->h_cg[0], st));
         for (ServerRequest *r : s->active) r->iters++;
         s->ticks++;
+        s->t_launch += s->now() - tm;
         // every check_every ticks (and when a request reaches max_iter): retire finished requests.
         // This is the only place the tick waits for the device.
         bool due = s->ticks % s->check_every == 0;
@@ -2175,7 +2225,10 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
             HIP_TRY(launch_cg(CG_MIRROR, s->d_cg, nact, s->cg_nblocks, s->h_cg[0], st));
             HIP_TRY(hipMemcpyAsync(s->h_mirror.data(), s->d_mirror, sizeof(double) * 8 * nact, hipMemcpyDeviceToHost,
                                    st));
+            tm = s->now();
             HIP_TRY(hipStreamSynchronize(st));
+            const double tw = s->now();
+            s->t_wait += tw - tm;
             std::vector<int32_t> flags(nact);
             for (int i = 0; i < nact; ++i) flags[i] = (int32_t)s->h_mirror[8 * (size_t)i];
             for (dwfmm_batch b : s->old_batches) dwfmm_batch_destroy(b);
@@ -2195,6 +2248,7 @@ extern "C" dwfmm_status dwfmm_server_tick(dwfmm_server s, int32_t *n_active, int
             }
             s->active.swap(keep);
             hand_off(s);
+            s->t_retire += s->now() - tw;
         }
     }
     if (n_active) *n_active = (int32_t)s->active.size();
@@ -2231,6 +2285,18 @@ extern "C" dwfmm_status dwfmm_server_finished(dwfmm_server s, int64_t *ids, int3
     if (!s || !count || cap < 0 || (cap > 0 && !ids)) return fail(DWFMM_E_INVALID, "bad argument");
     *count = (int32_t)s->finished.size();
     for (int i = 0; i < std::min<int>(cap, (int)s->finished.size()); ++i) ids[i] = s->finished[i]->id;
+    return DWFMM_OK;
+}
+
+extern "C" dwfmm_status dwfmm_server_stats(dwfmm_server s, double *out)
+{
+    if (!s || !out) return fail(DWFMM_E_INVALID, "NULL argument");
+    out[0] = (double)s->ticks;
+    out[1] = (double)s->n_rebuilds;
+    out[2] = s->t_rebuild;
+    out[3] = s->t_launch;
+    out[4] = s->t_wait;
+    out[5] = s->t_retire;
     return DWFMM_OK;
 }
 
