@@ -84,7 +84,7 @@ int pad_dim(int d) { return d <= 32 ? (d + 3) / 4 * 4 : (d + 7) / 8 * 8; }
 // Host arrays of a tree built but not yet uploaded (the tree's device arrays, in upload order).
 struct TreeStage {
     std::vector<double> Xs, clo, csc, coff, center;
-    std::vector<int32_t> nsrc_local, nptr_leaf, own_ptr, own_src, inc_ptr, inc_blk;
+    std::vector<int32_t> nsrc_local, nptr_leaf, own_ptr, own_src, inc_ptr, inc_blk, leaf_order;
     int max_leaf = 0;
 };
 
@@ -261,6 +261,30 @@ static dwfmm_status tree_host(const std::vector<double> &pts, int64_t n, int32_t
         for (size_t b = 0; b < owned.size(); ++b)
             if (owned[b].first != owned[b].second) inc_blk[fill[owned[b].second]++] = (int32_t)b;
     }
+    {
+        // nearfield work of each owner leaf: the entries of its owned blocks plus one 128-column
+        // chunk; then 8 contiguous segments of equal work, segment k dealt to XCD k
+        auto sz = [&](int32_t leaf) { return (double)(H.end[lf + leaf] - H.begin[lf + leaf]); };
+        std::vector<double> lw(H.nleaf, 0.0);
+        double total = 0.0;
+        for (auto &op : owned) lw[op.first] += sz(op.first) * sz(op.second);
+        for (int64_t l = 0; l < H.nleaf; ++l) {
+            lw[l] += 128.0 * sz((int32_t)l);
+            total += lw[l];
+        }
+        std::vector<int64_t> cut(9, H.nleaf);
+        cut[0] = 0;
+        double acc = 0.0;
+        for (int64_t l = 0, k = 1; l < H.nleaf && k < 8; ++l) {
+            acc += lw[l];
+            while (k < 8 && acc >= total * k / 8.0) cut[k++] = l + 1;
+        }
+        int64_t longest = 0;
+        for (int k = 0; k < 8; ++k) longest = std::max(longest, cut[k + 1] - cut[k]);
+        S.leaf_order.assign(8 * longest, -1);
+        for (int k = 0; k < 8; ++k)
+            for (int64_t j = 0; j < cut[k + 1] - cut[k]; ++j) S.leaf_order[8 * j + k] = (int32_t)(cut[k] + j);
+    }
     std::vector<double> &center = S.center, rad(H.nleaf, 0.0);
     center.assign((size_t)H.nleaf * dp, 0.0);
     for (int64_t l = 0; l < H.nleaf; ++l) {
@@ -297,7 +321,7 @@ static size_t tree_stage_bytes(const dwfmm_tree t)
     size_t b = sizeof(double) * (S.Xs.size() + S.clo.size() + S.csc.size() + S.coff.size() + S.center.size());
     b += sizeof(int32_t) * (H.perm.size() + H.begin.size() + H.end.size() + H.Fptr.size() + H.Fsrc.size() +
                             S.nptr_leaf.size() + S.nsrc_local.size() + S.own_ptr.size() + S.own_src.size() +
-                            S.inc_ptr.size() + S.inc_blk.size());
+                            S.inc_ptr.size() + S.inc_blk.size() + S.leaf_order.size());
     return b;
 }
 
@@ -310,9 +334,10 @@ static dwfmm_status tree_upload(dwfmm_tree t, hipStream_t st)
     auto up = [&](auto **dst, const auto &v) { return t->arena.upload(dst, v, st); };
     hipError_t e = hipSuccess;
     double *dXs;
-    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs, *dop, *dos, *dip, *dib;
+    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs, *dop, *dos, *dip, *dib, *dlo;
     double *dcen;
     if ((e = up(&dXs, S.Xs)) != hipSuccess || (e = up(&dperm, H.perm)) != hipSuccess ||
+        (e = up(&dlo, S.leaf_order)) != hipSuccess ||
         (e = up(&dcb, H.begin)) != hipSuccess || (e = up(&dce, H.end)) != hipSuccess ||
         (e = up(&dFp, H.Fptr)) != hipSuccess || (e = up(&dFs, H.Fsrc)) != hipSuccess ||
         (e = up(&dNp, S.nptr_leaf)) != hipSuccess || (e = up(&dNs, S.nsrc_local)) != hipSuccess ||
@@ -348,6 +373,8 @@ static dwfmm_status tree_upload(dwfmm_tree t, hipStream_t st)
     D.inc_ptr = dip;
     D.inc_blk = dib;
     D.center = dcen;
+    D.leaf_order = dlo;
+    D.n_order = (int)S.leaf_order.size();
     t->stage.reset();
     return DWFMM_OK;
 }

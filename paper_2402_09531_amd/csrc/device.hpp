@@ -28,6 +28,11 @@ struct DevTree {
     int nblk;                     // number of owned blocks of the symmetric nearfield (self blocks included)
     const int32_t *own_ptr, *own_src, *inc_ptr, *inc_blk;
     const double *center;         // [nleaf][dpad] leaf box midpoints (coordinate shift)
+    // Order in which the symmetric nearfield launches take the owner leaves: workgroup q runs on
+    // XCD q % 8, and XCD k gets the k-th of 8 contiguous leaf segments of equal nearfield work,
+    // in leaf order; -1 pads the shorter segments.  NULL for trees without a symmetric nearfield.
+    const int32_t *leaf_order;
+    int n_order;
 };
 
 struct DevOp {

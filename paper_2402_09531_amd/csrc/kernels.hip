@@ -949,7 +949,9 @@ __global__ __launch_bounds__(256)
 __attribute__((amdgpu_waves_per_eu(sym_waves<KIND, DK>(), 8)))
 void p2p_sym_kernel(DevTree T, DevOp O)
 {
-    p2p_sym_body<KIND, DK>(T, O, xcd_leaf(blockIdx.x, T.nleaf));
+    const int l = T.leaf_order[blockIdx.x];
+    if (l < 0) return;  // padding of a shorter XCD segment
+    p2p_sym_body<KIND, DK>(T, O, l);
 }
 
 // ---------------------------------------------------------------- MFMA cross nearfield (new points, one rhs)
@@ -1469,7 +1471,7 @@ hipError_t launch_sym_k(const DevTree &T, const DevOp &O, hipStream_t st)
     const int dk = (T.d + 3) / 4 * 4;
     switch (dk) {
 #define DWFMM_SYM(D) \
-    case D: hipLaunchKernelGGL((p2p_sym_kernel<KIND, D>), dim3(T.nleaf), dim3(256), 0, st, T, O); break;
+    case D: hipLaunchKernelGGL((p2p_sym_kernel<KIND, D>), dim3(T.n_order), dim3(256), 0, st, T, O); break;
         DWFMM_SYM(4) DWFMM_SYM(8) DWFMM_SYM(12) DWFMM_SYM(16) DWFMM_SYM(20) DWFMM_SYM(24) DWFMM_SYM(28)
         DWFMM_SYM(32)
 #undef DWFMM_SYM
@@ -1731,7 +1733,9 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
 template <int KIND, int DK>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 12 ? 5 : 1, 8))) void p2p_sym32_kernel(DevTree T, DevOp O)
 {
-    p2p_sym32_body<KIND, DK>(T, O, xcd_leaf(blockIdx.x, T.nleaf));
+    const int l = T.leaf_order[blockIdx.x];
+    if (l < 0) return;  // padding of a shorter XCD segment
+    p2p_sym32_body<KIND, DK>(T, O, l);
 }
 
 template <int KIND>
@@ -1739,7 +1743,7 @@ hipError_t launch_sym32_k(const DevTree &T, const DevOp &O, hipStream_t st)
 {
     switch ((T.d + 3) / 4 * 4) {
 #define DWFMM_SYM(D) \
-    case D: hipLaunchKernelGGL((p2p_sym32_kernel<KIND, D>), dim3(T.nleaf), dim3(256), 0, st, T, O); break;
+    case D: hipLaunchKernelGGL((p2p_sym32_kernel<KIND, D>), dim3(T.n_order), dim3(256), 0, st, T, O); break;
         DWFMM_SYM(4) DWFMM_SYM(8) DWFMM_SYM(12) DWFMM_SYM(16) DWFMM_SYM(20) DWFMM_SYM(24) DWFMM_SYM(28)
         DWFMM_SYM(32)
 #undef DWFMM_SYM
