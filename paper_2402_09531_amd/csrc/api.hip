@@ -98,6 +98,7 @@ struct dwfmm_tree_s {
     // c the midpoint of a leaf box: bounds every squared shifted distance the nearfield forms
     double near_reach2 = 0.0;
     int64_t own_max = 0, own_total = 0, near_max = 0;  // symmetric-nearfield ownership statistics
+    std::vector<double> leaf_work;  // nearfield work of each owner leaf (entries of its owned blocks + 128 per point)
     int refs = 1;       // the caller's reference plus one per operator
     bool destroyed = false;
     int device = 0;
@@ -263,7 +264,8 @@ static dwfmm_status tree_host(const std::vector<double> &pts, int64_t n, int32_t
     }
     {
         // nearfield work of each owner leaf: the entries of its owned blocks plus one 128-column
-        // chunk; then 8 contiguous segments of equal work, segment k dealt to XCD k
+        // chunk; then 8 contiguous segments of equal work, segment k dealt to XCD k (so each
+        // XCD's L2 holds the sources of one region of the tree)
         auto sz = [&](int32_t leaf) { return (double)(H.end[lf + leaf] - H.begin[lf + leaf]); };
         std::vector<double> lw(H.nleaf, 0.0);
         double total = 0.0;
@@ -272,6 +274,7 @@ static dwfmm_status tree_host(const std::vector<double> &pts, int64_t n, int32_t
             lw[l] += 128.0 * sz((int32_t)l);
             total += lw[l];
         }
+        t->leaf_work = lw;
         std::vector<int64_t> cut(9, H.nleaf);
         cut[0] = 0;
         double acc = 0.0;
@@ -281,9 +284,14 @@ static dwfmm_status tree_host(const std::vector<double> &pts, int64_t n, int32_t
         }
         int64_t longest = 0;
         for (int k = 0; k < 8; ++k) longest = std::max(longest, cut[k + 1] - cut[k]);
+        // within a segment the costliest leaves go first, so the segment ends on short ones
         S.leaf_order.assign(8 * longest, -1);
-        for (int k = 0; k < 8; ++k)
-            for (int64_t j = 0; j < cut[k + 1] - cut[k]; ++j) S.leaf_order[8 * j + k] = (int32_t)(cut[k] + j);
+        for (int k = 0; k < 8; ++k) {
+            std::vector<int32_t> seg;
+            for (int64_t j = cut[k]; j < cut[k + 1]; ++j) seg.push_back((int32_t)j);
+            std::stable_sort(seg.begin(), seg.end(), [&](int32_t a, int32_t b) { return lw[a] > lw[b]; });
+            for (size_t j = 0; j < seg.size(); ++j) S.leaf_order[8 * j + k] = seg[j];
+        }
     }
     std::vector<double> &center = S.center, rad(H.nleaf, 0.0);
     center.assign((size_t)H.nleaf * dp, 0.0);
@@ -1230,6 +1238,7 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
     b->flags = flags;
     b->force_prec = force_prec;
     std::vector<const HostTree *> item_tree;  // host tree of each batch item
+    std::vector<const std::vector<double> *> item_work;  // nearfield work per leaf of each item
     for (int i = 0; i < count; ++i) {
         if (!batch_eligible(ops[i])) continue;
         const DevTree &T = ops[i]->tree->D;
@@ -1241,6 +1250,7 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
         b->item_of[i] = (int)b->items.size();
         b->items.push_back(it);
         item_tree.push_back(&ops[i]->tree->H);
+        item_work.push_back(&ops[i]->tree->leaf_work);
     }
     // work lists: leaves, per level M2M / L2L, and one slice per kernel variant for M2L and P2P
     std::vector<int2> work;
@@ -1316,20 +1326,14 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
         }
         if (!far_list) {
             // Workgroup q runs on XCD q % 8.  The list is cut into 8 contiguous segments of equal
-            // estimated work (consecutive leaves of a problem share source points in the XCD's
-            // L2), segment k dealt to XCD k in order and padded to the longest: the leaves of
-            // different problems differ several-fold in work, so equal counts per XCD would
-            // leave most XCDs idle while one finishes.  The estimate is half the leaf's
-            // nearfield entries (owners are balanced by block count) plus one 128-column chunk.
+            // nearfield work (consecutive leaves of a problem share source points in the XCD's
+            // L2), segment k dealt to XCD k and padded to the longest: the leaves of different
+            // problems differ several-fold in work, so equal counts per XCD would leave most
+            // XCDs idle while one finishes.  Work per leaf: its tree's owned-block entries.
             std::vector<double> wk(lst.size());
             double total = 0.0;
             for (size_t i = 0; i < lst.size(); ++i) {
-                const HostTree &H = *item_tree[lst[i].x];
-                const int64_t c = H.nleaf - 1 + lst[i].y;
-                const double nl = H.end[c] - H.begin[c];
-                double ns = 0.0;
-                for (int32_t q = H.Nptr[c]; q < H.Nptr[c + 1]; ++q) ns += H.end[H.Nsrc[q]] - H.begin[H.Nsrc[q]];
-                wk[i] = nl * (0.5 * ns + 128.0);
+                wk[i] = (*item_work[lst[i].x])[lst[i].y];
                 total += wk[i];
             }
             std::vector<size_t> cut(9, lst.size());
@@ -1342,8 +1346,13 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
             size_t longest = 0;
             for (int k = 0; k < 8; ++k) longest = std::max(longest, cut[k + 1] - cut[k]);
             std::vector<int2> perm(8 * longest, make_int2(-1, 0));
-            for (int k = 0; k < 8; ++k)
-                for (size_t j = 0; j < cut[k + 1] - cut[k]; ++j) perm[8 * j + k] = lst[cut[k] + j];
+            for (int k = 0; k < 8; ++k) {
+                // the costliest leaves of the segment first, so it ends on short ones
+                std::vector<size_t> seg;
+                for (size_t j = cut[k]; j < cut[k + 1]; ++j) seg.push_back(j);
+                std::stable_sort(seg.begin(), seg.end(), [&](size_t a, size_t b2) { return wk[a] > wk[b2]; });
+                for (size_t j = 0; j < seg.size(); ++j) perm[8 * j + k] = lst[seg[j]];
+            }
             lst.swap(perm);
         }
         BatchLaunch L{k[0], k[1], k[2], k[3], (int)work.size(), (int)lst.size()};
