@@ -1759,9 +1759,11 @@ hipError_t launch_sym32_k(const DevTree &T, const DevOp &O, hipStream_t st)
 // so Y(16 x 16 rhs) += K Q is one MFMA with FP32 accumulation.  FP32: element e is the A
 // operand of chunk e (sources 4g + e) of four v_mfma_f32_16x16x4f32.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-// bf16 charges stored [rhs][source]; a row of 132 elements puts the 16 lanes of a group on 16
-// different bank pairs for their 8-byte reads
-constexpr int kQtStride = kSymLeaf + 4;
+// bf16 charges stored [rhs][source] in rows of 136 elements (68 words): an 8-byte read of lane
+// (li, lg) starts at word 68 li + 2 lg (+ a constant) and the 32 lanes lg < 2 (lg >= 2) start at
+// 4 li + 2 lg mod 64, on 64 different banks; with 132-element rows the two lane groups overlapped
+// (2 li + 2 lg) and every charge read took two passes
+constexpr int kQtStride = kSymLeaf + 8;
 // FP32 charges stored [source][rhs]; rows of 16 RB + 4 floats put consecutive lane groups on
 // the two halves of the banks
 template <int RB>
@@ -1782,6 +1784,13 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
         float snv[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) snv[e] = sN[16 * ct + 4 * lg + e];
+        // the charge operands of this column tile serve both row tiles
+        bf16x4 Qb[BF16 ? RB : 1];
+        if constexpr (BF16) {
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+                Qb[rb] = *reinterpret_cast<const bf16x4 *>(&sQt[(16 * rb + li) * kQtStride + 16 * ct + 4 * lg]);
+        }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;
@@ -1800,10 +1809,7 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
             if constexpr (BF16) {
                 const bf16x4 Ka = {(__bf16)Kv[0], (__bf16)Kv[1], (__bf16)Kv[2], (__bf16)Kv[3]};
 #pragma unroll
-                for (int rb = 0; rb < RB; ++rb) {
-                    const bf16x4 Qb = *reinterpret_cast<const bf16x4 *>(&sQt[(16 * rb + li) * kQtStride + 16 * ct + 4 * lg]);
-                    Y[u][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ka, Qb, Y[u][rb], 0, 0, 0);
-                }
+                for (int rb = 0; rb < RB; ++rb) Y[u][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ka, Qb[rb], Y[u][rb], 0, 0, 0);
             } else {
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb)
@@ -1888,7 +1894,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
             }
             // as in the FP64 kernel: every charge load of the thread issued before the first store
             constexpr int QPT = kSymLeaf * 16 * RB / 256, G = 256 / (16 * RB);
-            const int r = tid % (16 * RB), j0 = tid / (16 * RB);
+            // FP32: r = tid mod 16 RB.  BF16 (the 8-byte transposed stores): a half-wave takes 16
+            // rhs x 2 column groups, so its stores start at words 68 r + 2 jl, on 64 different banks
+            const int r = BF16 ? (tid & 15) + 16 * ((tid >> 5) % RB) : tid % (16 * RB);
+            const int j0 = BF16 ? (((tid >> 5) / RB) << 1) + ((tid >> 4) & 1) : tid / (16 * RB);
             const int rr = r < nrhs ? r : 0;
             double qv[QPT];
             if constexpr (BF16) {
