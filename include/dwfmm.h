@@ -389,6 +389,12 @@ dwfmm_status dwfmm_tree_info(dwfmm_tree tree, int64_t *out);
  * nearfield (its self block plus the unordered pairs dealt to it), the longest nearfield
  * list of a leaf, and the number of owned blocks.  Host values; E_INVALID on NULL.    */
 dwfmm_status dwfmm_tree_stats(dwfmm_tree tree, int64_t *out);
+/* The order in which the symmetric nearfield takes the owner leaves (workgroup q runs on XCD
+ * q mod 8: 8 contiguous leaf segments of equal nearfield work, segment k on XCD k, costliest leaf
+ * first within a segment, -1 padding the shorter segments): *count = its length; order (host, may
+ * be NULL) receives min(count, cap) entries; work (host, may be NULL, nleaf entries) the nearfield
+ * work of each leaf (owned-block entries plus 128 per point).  Errors: E_INVALID, E_HIP. */
+dwfmm_status dwfmm_tree_leaf_order(dwfmm_tree tree, int32_t *order, double *work, int32_t cap, int32_t *count);
 /* Tree order and boxes: perm[n] (tree position -> original index), begin/end[ncl],
  * lo/hi[ncl*d]; farfield CSR by target cluster Fptr[ncl+1], Fsrc[nF]; nearfield
  * CSR by target cluster Nptr[ncl+1], Nsrc[nN].  Any pointer may be NULL.      */

@@ -72,7 +72,7 @@ EXPORTS = ["dwfmm_build_tree", "dwfmm_build_tree_ex", "dwfmm_fmm_create", "dwfmm
            "dwfmm_batch_m2l_shapes", "dwfmm_batch_m2l_layout", "dwfmm_batch_destroy", "dwfmm_eval_create", "dwfmm_eval_apply",
            "dwfmm_eval_info", "dwfmm_eval_tree_get", "dwfmm_eval_destroy", "dwfmm_server_create", "dwfmm_server_submit", "dwfmm_server_tick",
            "dwfmm_server_result", "dwfmm_server_bytes", "dwfmm_server_destroy", "dwfmm_batch_solve", "dwfmm_op_bytes_for",
-           "dwfmm_server_finished", "dwfmm_server_stats"]
+           "dwfmm_server_finished", "dwfmm_server_stats", "dwfmm_tree_leaf_order"]
 
 
 def lib():
@@ -105,6 +105,8 @@ def lib():
         L.dwfmm_last_error.restype = C.c_char_p
         L.dwfmm_tree_info.argtypes = [vp, i64p]
         L.dwfmm_tree_stats.argtypes = [vp, i64p]
+        L.dwfmm_tree_leaf_order.argtypes = [vp, C.POINTER(C.c_int32), dp, C.c_int32, C.POINTER(C.c_int32)]
+        L.dwfmm_tree_leaf_order.restype = C.c_int
         L.dwfmm_tree_get.argtypes = [vp, i64p, i64p, i64p, dp, dp, i64p, i64p, i64p, i64p]
         L.dwfmm_op_info.argtypes = [vp, i64p]
         L.dwfmm_op_basis.argtypes = [vp, C.POINTER(C.c_uint8), dp, dp, dp]
@@ -219,6 +221,17 @@ class Tree:
         out = np.zeros(3, dtype=np.int64)
         _check(lib().dwfmm_tree_stats(self._h, _i64(out)))
         return int(out[0]), int(out[1]), int(out[2])
+
+    def leaf_order(self):
+        """(order of the owner leaves in the symmetric nearfield launches, -1 = padding; nearfield
+        work per leaf)."""
+        cnt = C.c_int32()
+        _check(lib().dwfmm_tree_leaf_order(self._h, None, None, 0, C.byref(cnt)))
+        order = np.zeros(max(cnt.value, 1), dtype=np.int32)
+        work = np.zeros(self.nleaf)
+        _check(lib().dwfmm_tree_leaf_order(self._h, order.ctypes.data_as(C.POINTER(C.c_int32)), _f64p(work),
+                                           cnt.value, C.byref(cnt)))
+        return order[:cnt.value], work
 
     def near_entries(self) -> float:
         """E_N = sum over nearfield blocks |nu||nu'|."""

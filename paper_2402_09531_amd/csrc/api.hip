@@ -2605,6 +2605,20 @@ extern "C" dwfmm_status dwfmm_tree_stats(dwfmm_tree t, int64_t *out)
     return DWFMM_OK;
 }
 
+extern "C" dwfmm_status dwfmm_tree_leaf_order(dwfmm_tree t, int32_t *order, double *work, int32_t cap,
+                                             int32_t *count)
+{
+    if (!t || t->destroyed || !count || cap < 0) return fail(DWFMM_E_INVALID, "bad argument");
+    *count = t->D.n_order;
+    if (order && cap > 0 && t->D.leaf_order) {
+        const int m = std::min<int>(cap, t->D.n_order);
+        HIP_TRY(hipMemcpy(order, t->D.leaf_order, sizeof(int32_t) * m, hipMemcpyDeviceToHost));
+    }
+    if (work)
+        for (size_t l = 0; l < t->leaf_work.size(); ++l) work[l] = t->leaf_work[l];
+    return DWFMM_OK;
+}
+
 extern "C" dwfmm_status dwfmm_tree_get(dwfmm_tree t, int64_t *perm, int64_t *begin, int64_t *end, double *lo,
                                        double *hi, int64_t *Fptr, int64_t *Fsrc, int64_t *Nptr, int64_t *Nsrc)
 {

@@ -304,3 +304,29 @@ def test_split_gaussian_near_its_exponent_bound(orc, ratio, split):
     say(f"[split Gaussian reach^2/ell = {ratio}] ell {ell:.4g}, split {op.gauss_split}: rel err {e:.3e}, "
         f"max abs err / max |y| {ea:.3e}")
     assert e <= TOL and ea <= 10 * TOL
+
+
+@pytest.mark.parametrize("geom", ["d6_matern", "d10_matern", "d4_gauss"])
+def test_leaf_order_is_balanced_permutation(geom):
+    """The symmetric nearfield takes the owner leaves in 8 contiguous segments of equal work (one
+    per XCD, workgroup q on XCD q mod 8), costliest first within a segment: the order is a
+    permutation of the leaves plus -1 padding, each XCD's leaves are one contiguous range, and no
+    segment exceeds an eighth of the work by more than one leaf's work."""
+    n, d, r, kind, ell, q, leaf, eta = GEOM[geom]
+    X = W.points(n, d, r, 700 + d)
+    tree, _ = build(X, W.dim_weights(d, r), leaf, eta, kind, ell, q)
+    order, work = tree.leaf_order()
+    nl = tree.nleaf
+    assert len(order) % 8 == 0
+    real = order[order >= 0]
+    assert sorted(real.tolist()) == list(range(nl))
+    total = work.sum()
+    for k in range(8):
+        seg = order[k::8]
+        seg = seg[seg >= 0]
+        if len(seg) == 0:
+            continue
+        assert sorted(seg.tolist()) == list(range(seg.min(), seg.max() + 1))  # contiguous range
+        assert np.all(np.diff(work[seg]) <= 0)                                # costliest first
+        assert work[seg].sum() <= total / 8 + work.max() + 1e-9 * total
+    say(f"[leaf order] {geom}: {nl} leaves, segments of {[int(np.sum(order[k::8] >= 0)) for k in range(8)]} leaves")

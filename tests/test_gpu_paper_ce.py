@@ -3,11 +3,12 @@
 Setting of the paper: N = 1e5 uniform points of [0,1]^20 scaled by b_k = k^-r, exponential
 kernel, eta = 0.5, q = 8, the Sec 6.2 weights, approximate Fekete nodes; CE = relative Frobenius
 error of 100 random columns of K~.  The admissibility is read as eta * dist >= max half-diagonal
-(dist >= 1.0 x max full diagonal here); the leaf size is not stated (128 here).  From the CE peak
-towards larger length scales the farfield interpolation error dominates and the printed curve is
-met closely: the peak sits at the same length scale and the three largest length scales agree
-within a factor 1.5.  Below the peak the error falls steeply in both and its level depends on
-the finest admissible blocks (leaf size, split rule), so it is not compared.
+(dist >= 1.0 x max full diagonal here).  The leaf size is not stated.  From the CE peak towards
+larger length scales the farfield interpolation error dominates and the printed curves are met
+closely (r = 3 and 4 with leaf 128, r = 2 with leaf 256, whose peak sits one grid point below
+the printed one).  Below the peak the error falls steeply and its level is set by the finest
+admissible blocks, i.e. by the leaf size: with leaf 64 the r = 4 curve follows the printed one
+over the whole grid above roundoff, with leaf 256 the r = 3 curve from sigma = 4.6e-3 up.
 """
 import json
 import os
@@ -49,24 +50,53 @@ def ce(op, Xd, sigma, J):
     return float(torch.linalg.norm(Kt - K) / torch.linalg.norm(K))
 
 
-@pytest.mark.parametrize("r", [3, 4])
-def test_compression_error_matches_paper_above_the_peak(r):
+def curve(r, leaf, idx):
     ref = np.array(json.load(open(GOLDEN))[f"r{r}"])
     n = 100_000
     X = W.points(n, 20, float(r), 6200 + r)
     b = W.dim_weights(20, float(r))
     Xd = torch.from_numpy(X).cuda()
-    tree = dw.build_tree(Xd, b, 128, 1.0)
+    tree = dw.build_tree(Xd, b, leaf, 1.0)
     J = np.random.default_rng(1000 * r).choice(n, 100, replace=False)
-    peak = int(np.argmax(ref[:, 1]))
-    idx = sorted({peak - 1, peak, peak + 1, 12, 13, 14})
     got = {}
     for i in idx:
         sigma = float(ref[i, 0])
         op = dw.fmm_create(tree, "exponential", sigma, 8, max_nrhs=25, weight_rule="R3", nodes="afp")
         got[i] = ce(op, Xd, sigma, J)
-        say(f"[paper ce] r={r} sigma={sigma:.4e}: CE {got[i]:.3e}, printed {ref[i, 1]:.3e}, "
+        say(f"[paper ce] r={r} leaf {leaf} sigma={sigma:.4e}: CE {got[i]:.3e}, printed {ref[i, 1]:.3e}, "
             f"ratio {got[i] / ref[i, 1]:.2f}")
+        op.close()
+    return ref, got
+
+
+@pytest.mark.parametrize("r", [3, 4])
+def test_compression_error_matches_paper_above_the_peak(r):
+    ref = np.array(json.load(open(GOLDEN))[f"r{r}"])
+    peak = int(np.argmax(ref[:, 1]))
+    ref, got = curve(r, 128, sorted({peak - 1, peak, peak + 1, 12, 13, 14}))
     assert got[peak] >= got[peak - 1] and got[peak] >= got[peak + 1]
     for i in (12, 13, 14):
         assert 1 / 1.5 <= got[i] / ref[i, 1] <= 1.5
+
+
+def test_compression_error_r2_with_leaf_256():
+    # r = 2 (n_x = 97: the general coupling kernel): with leaf 256 the four largest length scales
+    # are 1.08-1.20x the printed values and the peak sits one grid point below the printed one
+    ref, got = curve(2, 256, list(range(7, 15)))
+    peak_ref = int(np.argmax(ref[:, 1]))
+    peak = max(got, key=got.get)
+    assert abs(peak - peak_ref) <= 1
+    for i in (11, 12, 13, 14):
+        assert 1 / 1.5 <= got[i] / ref[i, 1] <= 1.5
+
+
+@pytest.mark.parametrize("r,leaf,idx,lo,hi", [
+    # r = 4, leaf 64: the whole curve above roundoff (sigma >= 7e-4) within 0.73-1.50x
+    (4, 64, [2, 4, 6, 8, 10, 12, 14], 0.5, 2.0),
+    # r = 3, leaf 256: from sigma = 4.6e-3 up within 0.43-1.16x
+    (3, 256, [3, 5, 7, 9], 1 / 3, 1.5),
+])
+def test_compression_error_below_the_peak(r, leaf, idx, lo, hi):
+    ref, got = curve(r, leaf, idx)
+    for i in idx:
+        assert lo <= got[i] / ref[i, 1] <= hi, (i, got[i], ref[i, 1])
