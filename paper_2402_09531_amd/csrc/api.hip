@@ -84,7 +84,7 @@ int pad_dim(int d) { return d <= 32 ? (d + 3) / 4 * 4 : (d + 7) / 8 * 8; }
 // Host arrays of a tree built but not yet uploaded (the tree's device arrays, in upload order).
 struct TreeStage {
     std::vector<double> Xs, clo, csc, coff, center;
-    std::vector<int32_t> nsrc_local, nptr_leaf, own_ptr, own_src, inc_ptr, inc_blk, leaf_order;
+    std::vector<int32_t> nsrc_local, nptr_leaf, own_ptr, own_src, inc_ptr, inc_blk, leaf_order, near_order;
     int max_leaf = 0;
 };
 
@@ -182,6 +182,34 @@ extern "C" dwfmm_status dwfmm_build_tree_ex(const double *points, int64_t n, int
     return tree_from_host(pts, n, d, dim_weights, leaf_size, eta, st, out, (int)admissibility);
 }
 
+// Launch order of the leaves of a nearfield kernel with per-leaf work w: workgroup q runs on XCD
+// q mod 8, so the leaves are cut into 8 contiguous segments of equal work, segment k dealt to XCD
+// k (each XCD's L2 then holds the sources of one region of the tree), the costliest leaves first
+// within a segment (it ends on short ones); -1 pads the shorter segments.
+static std::vector<int32_t> xcd_order(const std::vector<double> &w)
+{
+    const int64_t nl = (int64_t)w.size();
+    double total = 0.0;
+    for (double v : w) total += v;
+    std::vector<int64_t> cut(9, nl);
+    cut[0] = 0;
+    double acc = 0.0;
+    for (int64_t l = 0, k = 1; l < nl && k < 8; ++l) {
+        acc += w[l];
+        while (k < 8 && acc >= total * k / 8.0) cut[k++] = l + 1;
+    }
+    int64_t longest = 0;
+    for (int k = 0; k < 8; ++k) longest = std::max(longest, cut[k + 1] - cut[k]);
+    std::vector<int32_t> order(8 * longest, -1);
+    for (int k = 0; k < 8; ++k) {
+        std::vector<int32_t> seg;
+        for (int64_t j = cut[k]; j < cut[k + 1]; ++j) seg.push_back((int32_t)j);
+        std::stable_sort(seg.begin(), seg.end(), [&](int32_t a, int32_t b) { return w[a] > w[b]; });
+        for (size_t j = 0; j < seg.size(); ++j) order[8 * j + k] = seg[j];
+    }
+    return order;
+}
+
 // Tree from host points (arguments already checked), in two phases: tree_host builds the tree,
 // the nearfield ownership and every array the device will hold, on the host only (so the
 // device bytes are known before anything is allocated); tree_upload allocates and uploads them.
@@ -263,35 +291,21 @@ static dwfmm_status tree_host(const std::vector<double> &pts, int64_t n, int32_t
             if (owned[b].first != owned[b].second) inc_blk[fill[owned[b].second]++] = (int32_t)b;
     }
     {
-        // nearfield work of each owner leaf: the entries of its owned blocks plus one 128-column
-        // chunk; then 8 contiguous segments of equal work, segment k dealt to XCD k (so each
-        // XCD's L2 holds the sources of one region of the tree)
+        // nearfield work of each owner leaf (the entries of its owned blocks) and of each target
+        // leaf of the several-rhs nearfield (the entries of its whole list), each plus one
+        // 128-column chunk; each gives a launch order of 8 work-balanced segments (xcd_order)
         auto sz = [&](int32_t leaf) { return (double)(H.end[lf + leaf] - H.begin[lf + leaf]); };
-        std::vector<double> lw(H.nleaf, 0.0);
-        double total = 0.0;
+        std::vector<double> lw(H.nleaf, 0.0), nw(H.nleaf, 0.0);
         for (auto &op : owned) lw[op.first] += sz(op.first) * sz(op.second);
-        for (int64_t l = 0; l < H.nleaf; ++l) {
-            lw[l] += 128.0 * sz((int32_t)l);
-            total += lw[l];
+        for (int32_t l = 0; l < (int32_t)H.nleaf; ++l) {
+            lw[l] += 128.0 * sz(l);
+            double ns = 0.0;
+            for (int32_t q = nptr_leaf[l]; q < nptr_leaf[l + 1]; ++q) ns += sz(nsrc_local[q]);
+            nw[l] = sz(l) * (ns + 128.0);
         }
         t->leaf_work = lw;
-        std::vector<int64_t> cut(9, H.nleaf);
-        cut[0] = 0;
-        double acc = 0.0;
-        for (int64_t l = 0, k = 1; l < H.nleaf && k < 8; ++l) {
-            acc += lw[l];
-            while (k < 8 && acc >= total * k / 8.0) cut[k++] = l + 1;
-        }
-        int64_t longest = 0;
-        for (int k = 0; k < 8; ++k) longest = std::max(longest, cut[k + 1] - cut[k]);
-        // within a segment the costliest leaves go first, so the segment ends on short ones
-        S.leaf_order.assign(8 * longest, -1);
-        for (int k = 0; k < 8; ++k) {
-            std::vector<int32_t> seg;
-            for (int64_t j = cut[k]; j < cut[k + 1]; ++j) seg.push_back((int32_t)j);
-            std::stable_sort(seg.begin(), seg.end(), [&](int32_t a, int32_t b) { return lw[a] > lw[b]; });
-            for (size_t j = 0; j < seg.size(); ++j) S.leaf_order[8 * j + k] = seg[j];
-        }
+        S.leaf_order = xcd_order(lw);
+        S.near_order = xcd_order(nw);
     }
     std::vector<double> &center = S.center, rad(H.nleaf, 0.0);
     center.assign((size_t)H.nleaf * dp, 0.0);
@@ -329,7 +343,7 @@ static size_t tree_stage_bytes(const dwfmm_tree t)
     size_t b = sizeof(double) * (S.Xs.size() + S.clo.size() + S.csc.size() + S.coff.size() + S.center.size());
     b += sizeof(int32_t) * (H.perm.size() + H.begin.size() + H.end.size() + H.Fptr.size() + H.Fsrc.size() +
                             S.nptr_leaf.size() + S.nsrc_local.size() + S.own_ptr.size() + S.own_src.size() +
-                            S.inc_ptr.size() + S.inc_blk.size() + S.leaf_order.size());
+                            S.inc_ptr.size() + S.inc_blk.size() + S.leaf_order.size() + S.near_order.size());
     return b;
 }
 
@@ -342,10 +356,10 @@ static dwfmm_status tree_upload(dwfmm_tree t, hipStream_t st)
     auto up = [&](auto **dst, const auto &v) { return t->arena.upload(dst, v, st); };
     hipError_t e = hipSuccess;
     double *dXs;
-    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs, *dop, *dos, *dip, *dib, *dlo;
+    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs, *dop, *dos, *dip, *dib, *dlo, *dno;
     double *dcen;
     if ((e = up(&dXs, S.Xs)) != hipSuccess || (e = up(&dperm, H.perm)) != hipSuccess ||
-        (e = up(&dlo, S.leaf_order)) != hipSuccess ||
+        (e = up(&dlo, S.leaf_order)) != hipSuccess || (e = up(&dno, S.near_order)) != hipSuccess ||
         (e = up(&dcb, H.begin)) != hipSuccess || (e = up(&dce, H.end)) != hipSuccess ||
         (e = up(&dFp, H.Fptr)) != hipSuccess || (e = up(&dFs, H.Fsrc)) != hipSuccess ||
         (e = up(&dNp, S.nptr_leaf)) != hipSuccess || (e = up(&dNs, S.nsrc_local)) != hipSuccess ||
@@ -383,6 +397,8 @@ static dwfmm_status tree_upload(dwfmm_tree t, hipStream_t st)
     D.center = dcen;
     D.leaf_order = dlo;
     D.n_order = (int)S.leaf_order.size();
+    D.near_order = dno;
+    D.n_near_order = (int)S.near_order.size();
     t->stage.reset();
     return DWFMM_OK;
 }
@@ -2395,6 +2411,18 @@ extern "C" dwfmm_status dwfmm_eval_create(dwfmm_op op, const double *targets, in
     for (size_t i = 0; i < H.Nsrc.size(); ++i) nsrc_local[i] = H.Nsrc[i] - lf;
     int max_leaf = 0;
     for (int64_t l = 0; l < H.nleaf; ++l) max_leaf = std::max(max_leaf, H.end[lf + l] - H.begin[lf + l]);
+    // launch order of the cross nearfield: 8 segments of equal work (target points x listed source
+    // points), costliest target leaf first within a segment
+    std::vector<int32_t> near_order;
+    {
+        std::vector<double> nw(H.nleaf, 0.0);
+        for (int64_t l = 0; l < H.nleaf; ++l) {
+            double ns = 0.0;
+            for (int32_t q = nptr_leaf[l]; q < nptr_leaf[l + 1]; ++q) ns += Hs.end[H.Nsrc[q]] - Hs.begin[H.Nsrc[q]];
+            nw[l] = (double)(H.end[lf + l] - H.begin[lf + l]) * (ns + 128.0);
+        }
+        near_order = xcd_order(nw);
+    }
     std::vector<double> nodes, nodes_p((size_t)H.ncl * nx * dp, 0.0), E;
     box_nodes(H, op->B, nodes);
     for (int64_t c = 0; c < H.ncl; ++c)
@@ -2419,9 +2447,10 @@ extern "C" dwfmm_status dwfmm_eval_create(dwfmm_op op, const double *targets, in
     auto up = [&](auto **dst, const auto &v) { return ev->arena.upload(dst, v, st); };
     hipError_t e = hipSuccess;
     double *dXs, *dclo, *dcsc, *dcoff, *dnodes, *dE, *dLb, *dL, *dnodesT = nullptr, *dnnorm = nullptr;
-    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs;
+    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs, *dno;
     const size_t R = (size_t)op->max_nrhs;
     if ((e = up(&dXs, Xs)) != hipSuccess || (e = up(&dperm, H.perm)) != hipSuccess ||
+        (e = up(&dno, near_order)) != hipSuccess ||
         (e = up(&dcb, H.begin)) != hipSuccess || (e = up(&dce, H.end)) != hipSuccess ||
         (e = up(&dFp, H.Fptr)) != hipSuccess || (e = up(&dFs, H.Fsrc)) != hipSuccess ||
         (e = up(&dNp, nptr_leaf)) != hipSuccess || (e = up(&dNs, nsrc_local)) != hipSuccess ||
@@ -2454,6 +2483,8 @@ extern "C" dwfmm_status dwfmm_eval_create(dwfmm_op op, const double *targets, in
     D.Fsrc = dFs;
     D.Nptr = dNp;
     D.Nsrc = dNs;
+    D.near_order = dno;
+    D.n_near_order = (int)near_order.size();
     DevOp &O = ev->O;
     O.kind = op->D.kind;
     O.ell = op->D.ell;

@@ -33,6 +33,10 @@ struct DevTree {
     // in leaf order; -1 pads the shorter segments.  NULL for trees without a symmetric nearfield.
     const int32_t *leaf_order;
     int n_order;
+    // The same for the several-rhs nearfield, which sweeps each target leaf's whole nearfield list:
+    // segments of equal list entries, costliest leaf first.
+    const int32_t *near_order;
+    int n_near_order;
 };
 
 struct DevOp {

@@ -738,12 +738,6 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
     }
 }
 
-// consecutive leaves (spatial neighbours) on the same XCD: blocks are dealt round-robin over 8 XCDs
-__device__ __forceinline__ int xcd_leaf(int bid, int nleaf)
-{
-    return (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
-}
-
 template <int KIND, int DK>
 __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, int l)
 {
@@ -1148,7 +1142,9 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(KIND == kGa
 void p2p_cross_mfma_kernel(DevTree T, DevOp O, DevTree Ts, const double *__restrict__ xs, double *__restrict__ y,
                            int do_far)
 {
-    p2p_cross_mfma_body<KIND, DK>(T, O, Ts, xs, y, do_far, xcd_leaf(blockIdx.x, T.nleaf));
+    const int l = T.near_order[blockIdx.x];
+    if (l < 0) return;  // padding of a shorter XCD segment
+    p2p_cross_mfma_body<KIND, DK>(T, O, Ts, xs, y, do_far, l);
 }
 
 template <int KIND>
@@ -1158,7 +1154,7 @@ hipError_t launch_cross_mfma_k(const DevTree &Tt, const DevOp &Ot, const DevTree
     switch (Tt.dpad) {
 #define DWFMM_XM(D)                                                                                        \
     case D:                                                                                                \
-        hipLaunchKernelGGL((p2p_cross_mfma_kernel<KIND, D>), dim3(Tt.nleaf), dim3(256), 0, st, Tt, Ot, Ts, xs, y, \
+        hipLaunchKernelGGL((p2p_cross_mfma_kernel<KIND, D>), dim3(Tt.n_near_order), dim3(256), 0, st, Tt, Ot, Ts, xs, y, \
                            do_far);                                                                        \
         break;
         DWFMM_XM(4) DWFMM_XM(8) DWFMM_XM(12) DWFMM_XM(16) DWFMM_XM(20) DWFMM_XM(24) DWFMM_XM(28) DWFMM_XM(32)
@@ -1232,9 +1228,8 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
     __shared__ double sQ[kSymLeaf * q_stride<RB>()];
     __shared__ double cen[DK];
     __shared__ int32_t sPre[kSymSeg + 1], sBeg[kSymSeg], colP[kSymLeaf], sDiag;
-    const int nleaf = T.nleaf;
-    const int bid = blockIdx.x;
-    const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
+    const int l = T.near_order[blockIdx.x];
+    if (l < 0) return;  // padding of a shorter XCD segment
     const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
     if (nt == 0) return;
@@ -1391,9 +1386,9 @@ template <int KIND, int DK>
 void launch_mrhs_d(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
 {
     if (nrhs <= 16)
-        hipLaunchKernelGGL((p2p_mrhs_kernel<KIND, DK, 1>), dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs, near, far);
+        hipLaunchKernelGGL((p2p_mrhs_kernel<KIND, DK, 1>), dim3(T.n_near_order), dim3(256), 0, st, T, O, y, nrhs, near, far);
     else
-        hipLaunchKernelGGL((p2p_mrhs_kernel<KIND, DK, 2>), dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs, near, far);
+        hipLaunchKernelGGL((p2p_mrhs_kernel<KIND, DK, 2>), dim3(T.n_near_order), dim3(256), 0, st, T, O, y, nrhs, near, far);
 }
 
 template <int KIND>
@@ -1833,9 +1828,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
     __shared__ __attribute__((aligned(16))) __bf16 sQt[BF16 ? 16 * RB * kQtStride : 8];
     __shared__ double cen[DK];
     __shared__ int32_t sPre[kSymSeg + 1], sBeg[kSymSeg], colP[kSymLeaf], sDiag;
-    const int nleaf = T.nleaf;
-    const int bid = blockIdx.x;
-    const int l = (nleaf % 8 == 0) ? (bid % 8) * (nleaf / 8) + bid / 8 : bid;
+    const int l = T.near_order[blockIdx.x];
+    if (l < 0) return;  // padding of a shorter XCD segment
     const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
     if (nt == 0) return;
@@ -2008,10 +2002,10 @@ template <int KIND, int DK, bool BF16>
 void launch_mrhs_lp_d(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
 {
     if (nrhs <= 16)
-        hipLaunchKernelGGL((p2p_mrhs_lp_kernel<KIND, DK, 1, BF16>), dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs,
+        hipLaunchKernelGGL((p2p_mrhs_lp_kernel<KIND, DK, 1, BF16>), dim3(T.n_near_order), dim3(256), 0, st, T, O, y, nrhs,
                            near, far);
     else
-        hipLaunchKernelGGL((p2p_mrhs_lp_kernel<KIND, DK, 2, BF16>), dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs,
+        hipLaunchKernelGGL((p2p_mrhs_lp_kernel<KIND, DK, 2, BF16>), dim3(T.n_near_order), dim3(256), 0, st, T, O, y, nrhs,
                            near, far);
 }
 
