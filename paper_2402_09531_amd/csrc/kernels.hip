@@ -10,6 +10,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <type_traits>
 
 #include "device.hpp"
 
@@ -46,14 +47,10 @@ __device__ __forceinline__ double exp_bounded(double x)
     return ldexp(p, (int)n);
 }
 
-// 2^t in FP64 for |t| <= 1020: t = n + f with n = rint(t) and f = t - n in [-1/2, 1/2]
-// (exact), then the degree-10 interpolant of 2^f at 11 first-kind Chebyshev points of
-// [-1/2, 1/2] (same generator; 2.9e-16 relative), scaled by 2^n.  Two operations fewer
-// than exp_bounded where the caller can fold log2(e) into its own operands.
-__device__ __forceinline__ double exp2_bounded(double t)
+// 2^f for f in [-1/2, 1/2]: the degree-10 interpolant of 2^f at 11 first-kind Chebyshev points
+// of [-1/2, 1/2] (csrc/gen_exp_coeffs.py; 2.9e-16 relative).
+__device__ __forceinline__ double exp2_frac(double f)
 {
-    const double n = rint(t);
-    const double f = t - n;
     double p = 7.072587226569927e-09;
     p = fma(p, f, 1.0208690586037056e-07);
     p = fma(p, f, 1.3215442576793237e-06);
@@ -64,8 +61,16 @@ __device__ __forceinline__ double exp2_bounded(double t)
     p = fma(p, f, 0.055504108664447695);
     p = fma(p, f, 0.24022650695910097);
     p = fma(p, f, 0.69314718055995);
-    p = fma(p, f, 1.0);
-    return ldexp(p, (int)n);
+    return fma(p, f, 1.0);
+}
+
+// 2^t in FP64 for |t| <= 1020: t = n + f with n = rint(t) and f = t - n in [-1/2, 1/2]
+// (exact), then 2^f by exp2_frac, scaled by 2^n.  Two operations fewer than exp_bounded
+// where the caller can fold log2(e) into its own operands.
+__device__ __forceinline__ double exp2_bounded(double t)
+{
+    const double n = rint(t);
+    return ldexp(exp2_frac(t - n), (int)n);
 }
 
 // 2^t for t <= 0: arguments below -1075 (where 2^t underflows to zero) are clamped.
@@ -107,14 +112,27 @@ __device__ __forceinline__ double kernel_fast(double r2, double inv_ell)
 
 // Matern-3/2 (1 + s) e^-s from s^2 = 3 r^2 / ell^2, for callers whose coordinates are already
 // scaled by sqrt(3) / ell: one multiplication fewer than kernel_fast<0>.  Without CLAMP the
-// caller guarantees s log2(e) <= 1000, so 2^-s log2(e) needs no underflow clamp.
+// caller guarantees s log2(e) <= 1000, and 2^(-s log2(e)) is split by the round-to-integer
+// constant 1.5 2^52: m = -s log2(e) + 1.5 2^52 rounded once (an FMA) has unit spacing, so
+// n = m - 1.5 2^52 is the nearest integer to -s log2(e) (exact subtraction), its two's complement
+// sits in the low 32 bits of m, and f = -s log2(e) - n lies in [-1/2, 1/2] -- the multiplication,
+// rounding and conversion of exp2_bounded in two operations.
 template <bool CLAMP>
 __device__ __forceinline__ double matern_s2(double s2)
 {
-    const double s = sqrt_pos(fmax(s2, 1e-300));
-    const double t = s * -1.4426950408889634;
-    const double e = CLAMP ? exp2_nonpos(t) : exp2_bounded(t);
-    return fma(s, e, e);
+    constexpr double kLog2e = 1.4426950408889634, kRound = 6755399441055744.0;  // 1.5 2^52
+    // |s2| + 1e-300 keeps the square root's argument positive (s2 may be a rounding below zero)
+    // in one addition, where a clamp by fmax would first canonicalise an MFMA result
+    const double s = sqrt_pos(fabs(s2) + 1e-300);
+    if constexpr (CLAMP) {
+        const double e = exp2_nonpos(s * -kLog2e);
+        return fma(s, e, e);
+    } else {
+        const double m = fma(s, -kLog2e, kRound);
+        const double n = m - kRound;
+        const double e = ldexp(exp2_frac(fma(s, -kLog2e, -n)), __double2loint(m));
+        return fma(s, e, e);
+    }
 }
 
 template <int KIND>
@@ -679,8 +697,10 @@ constexpr int kSymSeg = 256;  // owned blocks per column-stream segment (= threa
 constexpr int kSX32 = 128 + 16;
 
 // One leaf block, all 16x16 tiles of this wave's two row tiles.  DIAG: the block of a
-// leaf with itself (i == j forced to distance 0, no column sums).
-template <int KIND, int NKC, bool DIAG>
+// leaf with itself (i == j forced to distance 0, no column sums).  NK: the squared norms ride in
+// two padding rows of the Gram operands (row operand |x|^2 and 1, column operand 1 and |y|^2), so
+// the MFMA chain delivers the whole squared distance.
+template <int KIND, int NKC, bool DIAG, bool NK>
 __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const double (&rN)[2][4],
                                           const double (&rQ)[2][4], double (&racc)[2][4], const double *sX,
                                           const double *sN, const double *sQ, double *colpart, int ns, int ntiles,
@@ -690,7 +710,7 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
     const int nct = (ns + 15) / 16;
     for (int ct = 0; ct < nct; ++ct) {
         const int j = 16 * ct + li;
-        const double nb = KIND == kGaussSplit ? 0.0 : sN[j], qb = sQ[j];
+        const double nb = KIND == kGaussSplit || NK ? 0.0 : sN[j], qb = sQ[j];
         double Bf[NKC];
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) Bf[kc] = sX[(4 * kc + lg) * kSymLeaf + j];
@@ -704,7 +724,7 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
             // Split Gaussian: A holds (2 log2(e) / ell)(x - c) and the chain gives the base-2
             // exponent of the cross factor; the row and column factors sit in the charges.
             dbl4 G;
-            if constexpr (KIND == kGaussSplit)
+            if constexpr (KIND == kGaussSplit || NK)
                 G = dbl4{0.0, 0.0, 0.0, 0.0};
             else
                 G = dbl4{rN[u][0], rN[u][1], rN[u][2], rN[u][3]};
@@ -716,7 +736,7 @@ __device__ __forceinline__ void sym_block(const double (&A)[2][NKC], const doubl
                 if constexpr (KIND == kGaussSplit) {
                     kv = exp2_bounded(G[v]);  // the row operand carries log2(e)
                 } else {
-                    double r2 = G[v] + nb;
+                    double r2 = NK ? G[v] : G[v] + nb;
                     if constexpr (DIAG) {
                         if (16 * rt[u] + 4 * v + lg == j) r2 = 0.0;
                     }
@@ -812,6 +832,21 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         }
     }
     __syncthreads();
+    // Two padding rows free (d <= DK - 2): the squared norms go into the Gram operands
+    const bool nk = KIND != kGaussSplit && T.d <= DK - 2;
+    if (nk) {
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int i = 16 * rt[u] + li;
+            const bool ok = i < nt;
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) {
+                const int k = 4 * kc + lg;
+                if (k == T.d) A[u][kc] = ok ? tN[i] : 0.0;
+                else if (k == T.d + 1) A[u][kc] = ok ? 1.0 : 0.0;
+            }
+        }
+    }
     double rN[2][4], rQ[2][4], racc[2][4];
 #pragma unroll
     for (int u = 0; u < 2; ++u)
@@ -844,14 +879,29 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         } else {
             sN[j] = s;
             sQ[j] = ok ? q : 0.0;
+            if (nk) {
+                sX[T.d * kSymLeaf + j] = 1.0;
+                sX[(T.d + 1) * kSymLeaf + j] = s;
+            }
         }
+    };
+    // the tile loop with or without the norms in the Gram operands (uniform over the workgroup)
+    auto block = [&](auto diag, int ns) {
+        constexpr bool D = decltype(diag)::value;
+        if constexpr (KIND != kGaussSplit) {
+            if (nk) {
+                sym_block<KIND, NKC, D, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
+                return;
+            }
+        }
+        sym_block<KIND, NKC, D, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
     };
     // 1) the leaf with itself (sDiag was set before the barrier that precedes rN)
     if (sDiag) {
         __syncthreads();
         if (tid < kSymLeaf) stage(tid, cb + (tid < nt ? tid : nt - 1), tid < nt);
         __syncthreads();
-        sym_block<KIND, NKC, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, nt, ntiles, w, li, lg, inv_ell);
+        block(std::true_type{}, nt);
     }
     // 2) the other owned blocks as one stream of source points, kSymLeaf columns at a time: a
     //    16-wide column tile may span two source leaves, so only the stream's last tile is padded.
@@ -906,7 +956,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
                 colJ[j] = jl;
             }
             __syncthreads();
-            sym_block<KIND, NKC, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
+            block(std::false_type{}, ns);
             __syncthreads();
             if (tid < ns) {
                 double cs = ((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) +

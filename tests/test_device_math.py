@@ -7,12 +7,16 @@ generator derives, and the same operation sequence is replayed in numpy (each fu
 multiply-add formed in extended precision and rounded once to double) against numpy's exp.
 The square root (hardware reciprocal-square-root seed, then a two-term series correction
 g (1 + e/2 + 3e^2/8)) is replayed the same way from seeds carrying a relative error up to 2^-20.
+The Matern nearfield's 2^(-s log2(e)) splits off the nearest integer with the constant 1.5 2^52
+instead of a rounding instruction; that split is replayed bit for bit, including the integer
+read from the low 32 bits of the rounded sum.
 """
 import importlib.util
 import io
 import pathlib
 import re
 from contextlib import redirect_stdout
+from fractions import Fraction
 
 import numpy as np
 
@@ -90,10 +94,12 @@ def test_underflow_and_clamp():
 def device_constants2():
     src = (CSRC / "kernels.hip").read_text()
     body = src[src.index("double exp2_bounded(double t)"):]
-    body = body[:body.index("return ldexp")]
-    assert "const double n = rint(t);" in body and "const double f = t - n;" in body
-    top = float(re.search(r"double p = ([0-9.e+-]+);", body).group(1))
-    rest = [float(v) for v in re.findall(r"fma\(p, f, ([0-9.e+-]+)\)", body)]
+    body = body[:body.index("}")]
+    assert "const double n = rint(t);" in body and "return ldexp(exp2_frac(t - n), (int)n);" in body
+    poly = src[src.index("double exp2_frac(double f)"):]
+    poly = poly[:poly.index("}")]
+    top = float(re.search(r"double p = ([0-9.e+-]+);", poly).group(1))
+    rest = [float(v) for v in re.findall(r"fma\(p, f, ([0-9.e+-]+)\)", poly)]
     return [top] + rest
 
 
@@ -169,3 +175,55 @@ def test_sqrt_iteration_few_ulp():
     ref = np.sqrt(x.astype(np.longdouble))
     rel = np.abs((got - ref) / ref).astype(np.float64)
     assert rel.max() <= 3e-16, rel.max()
+
+
+def fma_exact(a, b, c):
+    """a b + c rounded once to double (exact rational arithmetic, correctly rounded)."""
+    return np.array([float(Fraction(x) * Fraction(y) + Fraction(z)) for x, y, z in
+                     np.broadcast(a, b, c)], dtype=np.float64)
+
+
+def test_matern_round_to_integer_split():
+    src = (CSRC / "kernels.hip").read_text()
+    body = src[src.index("__device__ __forceinline__ double matern_s2(double s2)"):]
+    body = body[:body.index("\n}\n")]
+    for frag in ("kRound = 6755399441055744.0", "const double m = fma(s, -kLog2e, kRound);",
+                 "const double n = m - kRound;",
+                 "ldexp(exp2_frac(fma(s, -kLog2e, -n)), __double2loint(m))", "return fma(s, e, e);"):
+        assert frag in body, frag
+    big = 6755399441055744.0
+    assert big == 1.5 * 2.0 ** 52
+    coef = device_constants2()
+    log2e = 1.4426950408889634
+    rng = np.random.default_rng(7)
+    # s log2(e) <= 1000 is the range the caller guarantees; the half-integer points are ties
+    s = np.concatenate([rng.random(12_000) * (1000.0 / log2e), rng.random(4_000) * 4.0,
+                        np.arange(0.0, 1000.0) / log2e, (np.arange(0.0, 1000.0) + 0.5) / log2e, [0.0, 1e-150]])
+    m = fma_exact(s, -log2e, big)
+    n = m - big
+    # n is an integer nearest the exact product -s log2(e), and the low word of m holds it
+    t_exact = [-Fraction(x) * Fraction(log2e) for x in s]
+    assert all(abs(t - Fraction(v)) <= Fraction(1, 2) for t, v in zip(t_exact, n))
+    assert np.array_equal(n, np.rint(n))
+    low = (m.view(np.int64) & 0xFFFFFFFF).astype(np.uint32).view(np.int32)
+    assert np.array_equal(low.astype(np.float64), n)
+    f = fma_exact(s, -log2e, -n)
+    assert np.all(np.abs(f) <= 0.5)
+    p = np.full_like(f, coef[0])
+    for c in coef[1:]:
+        p = fma(p, f, c)
+    e = np.ldexp(p, low.astype(np.int64))
+    ref = np.exp2(-(s.astype(np.longdouble) * np.longdouble(log2e)))
+    nz = ref > 1e-300
+    rel = np.abs((e[nz] - ref[nz]) / ref[nz]).astype(np.float64)
+    assert rel.max() <= 5e-16, rel.max()
+    # the kernel value (1 + s) 2^(-s log2(e)) with log2(e) rounded to double as in the source
+    # (that rounding, 2.0e-17, moves e^-s by at most s ln2 2.1e-17 relative), in extended precision
+    k = fma(s, e, e)
+    sl = s.astype(np.longdouble)
+    kref = (1 + sl) * ref
+    rk = np.abs((k[nz] - kref[nz]) / kref[nz]).astype(np.float64)
+    assert rk.max() <= 1e-15, rk.max()
+    kexp = (1 + sl) * np.exp(-sl)
+    rx = np.abs((k[nz] - kexp[nz]) / kexp[nz]).astype(np.float64)
+    assert np.all(rx <= 1e-15 + s[nz] * np.log(2.0) * 2.1e-17), rx.max()

@@ -68,6 +68,10 @@ CASES = [
     # Gaussian with a length scale so short that the split form's exponents would exceed 600:
     # the single-rhs nearfield keeps the direct form
     ("d6_gauss_short", 6000, 6, 1.0, "gaussian", 2e-4, 4, 64, 0.8, 1),
+    # the exponential kernel with two padding rows free for the squared norms (d = 5 in 8)
+    ("d5_exp", 7000, 5, 2.0, "exponential", 0.3, 5, 100, 0.5, 1),
+    # Matern with exponents beyond the unclamped variant's bound (s log2(e) > 1000 over the nearfield)
+    ("d2_matern_short", 20000, 2, 1.0, "matern32", 5e-5, 4, 64, 0.8, 1),
 ]
 
 
@@ -84,6 +88,14 @@ def test_matvec_parity_fp64(orc, case):
     assert op.nx == P.nx and tree.J == P.J and tree.nF == P.nF and tree.nN == P.nN
     # the split Gaussian nearfield runs wherever its exponents stay bounded
     assert op.gauss_split == (kind == "gaussian" and name != "d6_gauss_short")
+    if name == "d2_matern_short":
+        # a leaf's self block is nearfield, so its longest side bounds the nearfield reach from below:
+        # sqrt(3) reach log2(e) / ell is past the 1000 up to which the unclamped variant runs
+        h = tree.host()
+        lf = tree.nleaf - 1
+        side = max(np.ptp(X[h["perm"][h["begin"][c]:h["end"][c]]], axis=0).max()
+                   for c in range(lf, lf + tree.nleaf) if h["end"][c] > h["begin"][c])
+        assert np.sqrt(3.0) * side * np.log2(np.e) / ell > 1000.0
     y_ref = P.matvec(x)
     y = gpu_matvec(op, x)
     # parts separately (diagnostic and stronger: each part is itself within tolerance)
