@@ -26,12 +26,16 @@ KERNELS = {"matern32": MATERN32, "gaussian": GAUSSIAN, "exponential": EXPONENTIA
 W_R1, W_R2, W_R3, W_EXPLICIT, W_THM = 0, 1, 2, 3, 4
 
 
+def compile_source(src: str, out: str) -> None:
+    """gcc with the oracle's flags (FP64, no fast-math): C source -> shared library."""
+    subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11", "-o", out, src, "-lm"])
+
+
 def build(force: bool = False) -> str:
-    """Compile the oracle with gcc (FP64, no fast-math)."""
+    """Compile the oracle in place (when its source is newer than the library)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-std=c11",
-                               "-o", tmp, _SRC, "-lm"])
+        compile_source(_SRC, tmp)
         os.replace(tmp, _LIB)
     return _LIB
 
@@ -42,8 +46,9 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        build()
-        L = C.CDLL(_LIB)
+        # a test that plants a mistake in a copy of the C source names that copy's library here
+        path = os.environ.get("DWFMM_ORACLE_LIB") or build()
+        L = C.CDLL(path)
         dp = C.POINTER(C.c_double)
         lp = C.POINTER(C.c_long)
         up = C.POINTER(C.c_ubyte)
