@@ -906,6 +906,9 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
     // 2) the other owned blocks as one stream of source points, kSymLeaf columns at a time: a
     //    16-wide column tile may span two source leaves, so only the stream's last tile is padded.
     //    Owned blocks are taken kSymSeg at a time; sPre holds the prefix sums of their sizes.
+    // The staging and column-sum threads alternate between waves 0-1 and 2-3 from chunk to chunk
+    // (sid), so that the four SIMDs, which hold one wave of the workgroup each, share that work.
+    int chunk = 0;
     for (int fb = o0; fb < o1; fb += kSymSeg) {
         const int fe = min(fb + kSymSeg, o1);
         __syncthreads();  // the previous segment's table is no longer read
@@ -930,11 +933,12 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
             __syncthreads();
         }
         const int total = sPre[kSymSeg];
-        for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+        for (int c0 = 0; c0 < total; c0 += kSymLeaf, ++chunk) {
             const int ns = min(kSymLeaf, total - c0);
+            const int sid = tid ^ ((chunk & 1) << 7);
             __syncthreads();  // the previous chunk's tiles and column sums are consumed
-            if (tid < kSymLeaf) {
-                const int j = tid;
+            if (sid < kSymLeaf) {
+                const int j = sid;
                 const bool ok = j < ns;
                 int pidx = cb, fblk = 0, jl = 0;
                 if (ok) {
@@ -958,11 +962,11 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
             __syncthreads();
             block(std::false_type{}, ns);
             __syncthreads();
-            if (tid < ns) {
-                double cs = ((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) +
-                            colpart[3 * kSymLeaf + tid];
-                if constexpr (KIND == kGaussSplit) cs *= sN[tid];
-                O.colbuf[(size_t)colF[tid] * kSymLeaf + colJ[tid]] = cs;
+            if (sid < ns) {
+                double cs = ((colpart[sid] + colpart[kSymLeaf + sid]) + colpart[2 * kSymLeaf + sid]) +
+                            colpart[3 * kSymLeaf + sid];
+                if constexpr (KIND == kGaussSplit) cs *= sN[sid];
+                O.colbuf[(size_t)colF[sid] * kSymLeaf + colJ[sid]] = cs;
             }
         }
     }
@@ -1101,6 +1105,7 @@ __device__ __forceinline__ void p2p_cross_mfma_body(const DevTree &T, const DevO
             racc[u][v] = 0.0;
         }
     const int f0 = T.Nptr[l], f1 = T.Nptr[l + 1];
+    int chunk = 0;  // the staging threads alternate between waves 0-1 and 2-3 (as in the symmetric kernel)
     for (int fb = f0; fb < f1; fb += kSymSeg) {
         const int fe = min(fb + kSymSeg, f1);
         __syncthreads();  // the previous segment's table is no longer read
@@ -1124,11 +1129,12 @@ __device__ __forceinline__ void p2p_cross_mfma_body(const DevTree &T, const DevO
             __syncthreads();
         }
         const int total = sPre[kSymSeg];
-        for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+        for (int c0 = 0; c0 < total; c0 += kSymLeaf, ++chunk) {
             const int ns = min(kSymLeaf, total - c0);
+            const int sid = tid ^ ((chunk & 1) << 7);
             __syncthreads();  // the previous chunk's tiles are consumed
-            if (tid < kSymLeaf) {
-                const int j = tid;
+            if (sid < kSymLeaf) {
+                const int j = sid;
                 const bool ok = j < ns;
                 int pidx = 0;  // any valid source point for the padding columns
                 if (ok) {
@@ -1702,6 +1708,7 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
         __syncthreads();
         sym_block32<KIND, NKC, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, nt, ntiles, w, li, lg, inv_ell);
     }
+    int chunk = 0;  // staging and column sums alternate between waves 0-1 and 2-3 (as in FP64)
     for (int fb = o0; fb < o1; fb += kSymSeg) {
         const int fe = min(fb + kSymSeg, o1);
         __syncthreads();
@@ -1726,11 +1733,12 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
             __syncthreads();
         }
         const int total = sPre[kSymSeg];
-        for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+        for (int c0 = 0; c0 < total; c0 += kSymLeaf, ++chunk) {
             const int ns = min(kSymLeaf, total - c0);
+            const int sid = tid ^ ((chunk & 1) << 7);
             __syncthreads();
-            if (tid < kSymLeaf) {
-                const int j = tid;
+            if (sid < kSymLeaf) {
+                const int j = sid;
                 const bool ok = j < ns;
                 int pidx = cb, fblk = 0, jl = 0;
                 if (ok) {
@@ -1752,11 +1760,11 @@ __device__ __forceinline__ void p2p_sym32_body(const DevTree &T, const DevOp &O,
             __syncthreads();
             sym_block32<KIND, NKC, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
             __syncthreads();
-            if (tid < ns) {
-                float cs = ((colpart[tid] + colpart[kSymLeaf + tid]) + colpart[2 * kSymLeaf + tid]) +
-                           colpart[3 * kSymLeaf + tid];
-                if constexpr (KIND == kGaussSplit) cs *= sN[tid];
-                O.colbuf[(size_t)colF[tid] * kSymLeaf + colJ[tid]] = (double)cs;
+            if (sid < ns) {
+                float cs = ((colpart[sid] + colpart[kSymLeaf + sid]) + colpart[2 * kSymLeaf + sid]) +
+                           colpart[3 * kSymLeaf + sid];
+                if constexpr (KIND == kGaussSplit) cs *= sN[sid];
+                O.colbuf[(size_t)colF[sid] * kSymLeaf + colJ[sid]] = (double)cs;
             }
         }
     }
