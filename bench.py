@@ -47,14 +47,21 @@ def pairwise_dist(A, B, chunk_bytes: float = 2e9):
 
 
 def cpu_model() -> str:
-    """The host CPU's model name (/proc/cpuinfo)."""
+    """The host CPU's model name as lscpu shows it (/proc/cpuinfo), with its family, model and
+    stepping numbers (a virtual machine may show a generic name)."""
+    info = {}
     try:
         for line in open("/proc/cpuinfo"):
-            if line.startswith("model name"):
-                return line.split(":", 1)[1].strip()
+            if ":" in line:
+                k, v = (t.strip() for t in line.split(":", 1))
+                info.setdefault(k, v)
+            if not line.strip() and info:
+                break
     except OSError:
-        pass
-    return "unknown"
+        return "unknown"
+    name = info.get("model name", "unknown")
+    ids = [f"{k} {info[k]}" for k in ("cpu family", "model", "stepping") if k in info]
+    return f"{name} ({', '.join(ids)})" if ids else name
 
 
 def cpu_baseline(w, X, b, x, budget_leaves: int):
