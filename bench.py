@@ -1011,7 +1011,9 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else args.precision + "+f64",
+        # BF16 with one rhs runs the FP32 kernels (its products are not MFMA-shaped)
+        "dtype": ("f64" if args.precision == "fp64" else
+                  ("fp32" if args.precision == "bf16" and nrhs == 1 else args.precision) + "+f64"),
         "data": "synthetic",
         "config": {"workload": w.name, "N": n, "d": w.d, "box": f"b_k=k^-{w.r:g}", "kernel": w.kernel,
                    "ell": w.ell, "q": w.q, "leaf": w.leaf, "eta": w.eta, "nrhs": nrhs,
