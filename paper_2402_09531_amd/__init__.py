@@ -258,9 +258,9 @@ class Op:
     def __init__(self, handle, tree: Tree):
         self._h = handle
         self.tree = tree
-        info = np.zeros(5, dtype=np.int64)
+        info = np.zeros(6, dtype=np.int64)
         _check(lib().dwfmm_op_info(self._h, _i64(info)))
-        self.nx, self.max_nrhs, self.precision, self.bytes, self.gauss_split = (int(v) for v in info)
+        self.nx, self.max_nrhs, self.precision, self.bytes, self.gauss_split, self.gauss_split32 = (int(v) for v in info)
 
     def basis(self):
         d = self.tree.d

@@ -2675,6 +2675,7 @@ extern "C" dwfmm_status dwfmm_op_info(dwfmm_op op, int64_t *out)
     out[2] = op->precision;
     out[3] = (int64_t)dwfmm_op_bytes(op);
     out[4] = op->D.gauss_split;
+    out[5] = op->D.gauss_split32;
     return DWFMM_OK;
 }
 

@@ -1254,17 +1254,28 @@ __device__ __forceinline__ void mrhs_block(const double (&Bt)[2][DK / 4], const 
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;  // uniform over the wave
-            dbl4 G = {0.0, 0.0, 0.0, 0.0};
+            // Split Gaussian: the target operand carries (2 log2(e) / ell)(x - c) and the chain
+            // starts from the base-2 logarithm of each source's column factor (snv), so it delivers
+            // the whole base-2 exponent of the entry but for the row factor, applied to the sums
+            dbl4 G;
+            if constexpr (KIND == kGaussSplit)
+                G = dbl4{snv[0], snv[1], snv[2], snv[3]};
+            else
+                G = dbl4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f64_16x16x4f64(Af[kc], Bt[u][kc], G, 0, 0, 0);
             double Kv[4];
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
-                double r2 = fmax(fma(-2.0, G[v], tn[u] + snv[v]), 0.0);
-                if constexpr (DIAG) {
-                    if (16 * rt[u] + li == 16 * ct + 4 * v + lg) r2 = 0.0;
+                if constexpr (KIND == kGaussSplit) {
+                    Kv[v] = exp2_bounded(G[v]);
+                } else {
+                    double r2 = fmax(fma(-2.0, G[v], tn[u] + snv[v]), 0.0);
+                    if constexpr (DIAG) {
+                        if (16 * rt[u] + li == 16 * ct + 4 * v + lg) r2 = 0.0;
+                    }
+                    Kv[v] = kernel_fast<KIND>(r2, inv_ell);
                 }
-                Kv[v] = kernel_fast<KIND>(r2, inv_ell);
             }
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
@@ -1284,6 +1295,8 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
     __shared__ double sQ[kSymLeaf * q_stride<RB>()];
     __shared__ double cen[DK];
     __shared__ int32_t sPre[kSymSeg + 1], sBeg[kSymSeg], colP[kSymLeaf], sDiag;
+    constexpr bool kSplit = KIND == kGaussSplit;
+    __shared__ double tF[kSplit ? kSymLeaf : 1];  // split Gaussian: row factors exp(-|x - c|^2 / ell)
     const int l = T.near_order[blockIdx.x];
     if (l < 0) return;  // padding of a shorter XCD segment
     const int c = T.leaf_first + l;
@@ -1312,10 +1325,26 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
             s = fma(v, v, s);
         }
         tn[u] = s;
+        constexpr double kCross = 2.0 * 1.4426950408889634;
 #pragma unroll
-        for (int kc = 0; kc < NKC; ++kc) Bt[u][kc] = T.Xs[(size_t)(4 * kc + lg) * n + ii] - cen[4 * kc + lg];
+        for (int kc = 0; kc < NKC; ++kc) {
+            const double v = T.Xs[(size_t)(4 * kc + lg) * n + ii] - cen[4 * kc + lg];
+            Bt[u][kc] = kSplit ? (kCross * inv_ell) * v : v;
+        }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) Y[u][rb] = dbl4{0.0, 0.0, 0.0, 0.0};
+    }
+    if constexpr (kSplit) {
+        if (tid < kSymLeaf) {
+            const int ii = cb + (tid < nt ? tid : nt - 1);
+            double s = 0.0;
+#pragma unroll
+            for (int k = 0; k < DK; ++k) {
+                const double v = T.Xs[(size_t)k * n + ii] - cen[k];
+                s = fma(v, v, s);
+            }
+            tF[tid] = exp_bounded(-s * inv_ell);
+        }
     }
     if (do_near) {
         // the leaf's own block first (when listed), then the other source leaves as one stream of
@@ -1343,7 +1372,8 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
                     sX[k * kSymLeaf + j] = v;
                     s = fma(v, v, s);
                 }
-                sN[j] = s;
+                // split Gaussian: the base-2 logarithm of the column factor exp(-|y - c|^2 / ell)
+                sN[j] = kSplit ? s * (-1.4426950408889634 * inv_ell) : s;
             }
             // charges [j][r], zero beyond the stream and beyond nrhs: thread tid stages rhs
             // r = tid % 16RB of columns j0 + t * 256 / 16RB, every load issued before the first store
@@ -1413,6 +1443,7 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
             }
         }
     }
+    if constexpr (kSplit) __syncthreads();  // tF is complete
     // Y[u][rb] element v of lane (r + 16 g) is output (target 16 rt + 4 v + g, rhs 16 rb + r)
     const double *lc = O.L + (size_t)c * O.nx * nrhs;
 #pragma unroll
@@ -1425,6 +1456,7 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * rt[u] + 4 * v + lg;
                 double acc = Y[u][rb][v];
+                if constexpr (kSplit) acc *= tF[i];  // the row factor
                 if (do_far && i < nt && r < nrhs) {
                     // the farfield sum formed from zero and added once, as l2p_add_kernel does when
                     // the farfield ran beside this kernel: both orders give the same bits
@@ -1847,17 +1879,27 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;
-            flt4 G = {0.0f, 0.0f, 0.0f, 0.0f};
+            // split Gaussian as in the FP64 kernel: the chain starts from the sources' base-2 column
+            // factors and delivers the entry's exponent but for the row factor
+            flt4 G;
+            if constexpr (KIND == kGaussSplit)
+                G = flt4{snv[0], snv[1], snv[2], snv[3]};
+            else
+                G = flt4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[kc], Bt[u][kc], G, 0, 0, 0);
             float Kv[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                float r2 = fmaxf(fmaf(-2.0f, G[e], tn[u] + snv[e]), 0.0f);
-                if constexpr (DIAG) {
-                    if (16 * rt[u] + li == 16 * ct + 4 * lg + e) r2 = 0.0f;
+                if constexpr (KIND == kGaussSplit) {
+                    Kv[e] = __builtin_amdgcn_exp2f(G[e]);
+                } else {
+                    float r2 = fmaxf(fmaf(-2.0f, G[e], tn[u] + snv[e]), 0.0f);
+                    if constexpr (DIAG) {
+                        if (16 * rt[u] + li == 16 * ct + 4 * lg + e) r2 = 0.0f;
+                    }
+                    Kv[e] = kernel_f32<KIND>(r2, inv_ell);
                 }
-                Kv[e] = kernel_f32<KIND>(r2, inv_ell);
             }
             if constexpr (BF16) {
                 const bf16x4 Ka = {(__bf16)Kv[0], (__bf16)Kv[1], (__bf16)Kv[2], (__bf16)Kv[3]};
@@ -1886,6 +1928,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
     __shared__ __attribute__((aligned(16))) __bf16 sQt[BF16 ? 16 * RB * kQtStride : 8];
     __shared__ double cen[DK];
     __shared__ int32_t sPre[kSymSeg + 1], sBeg[kSymSeg], colP[kSymLeaf], sDiag;
+    constexpr bool kSplit = KIND == kGaussSplit;
+    __shared__ float tF[kSplit ? kSymLeaf : 1];  // split Gaussian: row factors exp(-|x - c|^2 / ell)
     const int l = T.near_order[blockIdx.x];
     if (l < 0) return;  // padding of a shorter XCD segment
     const int c = T.leaf_first + l;
@@ -1913,10 +1957,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
             s = fmaf(v, v, s);
         }
         tn[u] = s;
+        const double csc = kSplit ? 2.0 * 1.4426950408889634 / O.ell : 1.0;
 #pragma unroll
-        for (int kc = 0; kc < NKC; ++kc) Bt[u][kc] = (float)(T.Xs[(size_t)(4 * kc + lg) * n + ii] - cen[4 * kc + lg]);
+        for (int kc = 0; kc < NKC; ++kc) {
+            const double v = T.Xs[(size_t)(4 * kc + lg) * n + ii] - cen[4 * kc + lg];
+            Bt[u][kc] = (float)(kSplit ? csc * v : v);
+        }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) Y[u][rb] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+    }
+    if constexpr (kSplit) {
+        if (tid < kSymLeaf) {
+            const int ii = cb + (tid < nt ? tid : nt - 1);
+            float s = 0.0f;
+#pragma unroll
+            for (int k = 0; k < DK; ++k) {
+                const float v = (float)(T.Xs[(size_t)k * n + ii] - cen[k]);
+                s = fmaf(v, v, s);
+            }
+            tF[tid] = __builtin_amdgcn_exp2f(s * (inv_ell * -1.4426950408889634f));
+        }
     }
     if (do_near) {
         // the leaf's own block first (when listed), then the other source leaves as one stream of
@@ -1942,7 +2002,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
                     sX[k * kSX32 + j] = v;
                     s = fmaf(v, v, s);
                 }
-                sN[j] = s;
+                // split Gaussian: the base-2 logarithm of the column factor exp(-|y - c|^2 / ell)
+                sN[j] = kSplit ? s * (inv_ell * -1.4426950408889634f) : s;
             }
             // as in the FP64 kernel: every charge load of the thread issued before the first store
             constexpr int QPT = kSymLeaf * 16 * RB / 256, G = 256 / (16 * RB);
@@ -2031,6 +2092,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
             }
         }
     }
+    if constexpr (kSplit) __syncthreads();  // tF is complete
     // Y[u][rb] element v of lane (r + 16 g) is output (target 16 rt + 4 g + v, rhs 16 rb + r)
     const double *lc = O.L + (size_t)c * O.nx * nrhs;
 #pragma unroll
@@ -2042,7 +2104,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
 #pragma unroll
             for (int v = 0; v < 4; ++v) {
                 const int i = 16 * rt[u] + 4 * lg + v;
-                double acc = (double)Y[u][rb][v];
+                double acc = (double)(kSplit ? Y[u][rb][v] * tF[i] : Y[u][rb][v]);
                 if (do_far && i < nt && r < nrhs) {
                     // the farfield sum formed from zero and added once, as l2p_add_kernel does when
                     // the farfield ran beside this kernel: both orders give the same bits
@@ -2924,19 +2986,28 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
         if (precision == 0) {
             switch (O.kind) {
             case 0: e = launch_mrhs_k<0>(T, O, y, nrhs, near, nfar, st); break;
-            case 1: e = launch_mrhs_k<1>(T, O, y, nrhs, near, nfar, st); break;
+            case 1:
+                e = O.gauss_split ? launch_mrhs_k<kGaussSplit>(T, O, y, nrhs, near, nfar, st)
+                                  : launch_mrhs_k<1>(T, O, y, nrhs, near, nfar, st);
+                break;
             default: e = launch_mrhs_k<2>(T, O, y, nrhs, near, nfar, st); break;
             }
         } else if (precision == 1) {
             switch (O.kind) {
             case 0: e = launch_mrhs_lp_k<0, false>(T, O, y, nrhs, near, nfar, st); break;
-            case 1: e = launch_mrhs_lp_k<1, false>(T, O, y, nrhs, near, nfar, st); break;
+            case 1:
+                e = O.gauss_split32 ? launch_mrhs_lp_k<kGaussSplit, false>(T, O, y, nrhs, near, nfar, st)
+                                    : launch_mrhs_lp_k<1, false>(T, O, y, nrhs, near, nfar, st);
+                break;
             default: e = launch_mrhs_lp_k<2, false>(T, O, y, nrhs, near, nfar, st); break;
             }
         } else {
             switch (O.kind) {
             case 0: e = launch_mrhs_lp_k<0, true>(T, O, y, nrhs, near, nfar, st); break;
-            case 1: e = launch_mrhs_lp_k<1, true>(T, O, y, nrhs, near, nfar, st); break;
+            case 1:
+                e = O.gauss_split32 ? launch_mrhs_lp_k<kGaussSplit, true>(T, O, y, nrhs, near, nfar, st)
+                                    : launch_mrhs_lp_k<1, true>(T, O, y, nrhs, near, nfar, st);
+                break;
             default: e = launch_mrhs_lp_k<2, true>(T, O, y, nrhs, near, nfar, st); break;
             }
         }

@@ -283,25 +283,28 @@ def near_reach2(tree):
     return float((reach ** 2).max())
 
 
+@pytest.mark.parametrize("nrhs", [1, 5])
 @pytest.mark.parametrize("ratio,split", [(560.0, True), (598.0, True), (640.0, False)])
-def test_split_gaussian_near_its_exponent_bound(orc, ratio, split):
+def test_split_gaussian_near_its_exponent_bound(orc, ratio, split, nrhs):
     """The split Gaussian multiplies three exponentials whose exponents reach |x-c|^2/ell + |y-c|^2/ell
-    + 2(x-c).(y-c)/ell; up to the bound 600 on reach^2/ell the matvec must still meet 1e-12 (one
-    rhs; several rhs run the direct form); past it the direct form runs."""
+    + 2(x-c).(y-c)/ell; up to the bound 600 on reach^2/ell the matvec must still meet 1e-12 (one rhs:
+    the symmetric kernel with the row and column factors in the charges; several rhs: the exponent of
+    the column factor starts the Gram chain, the row factor scales the sums); past it the direct
+    form runs."""
     n, d = 20000, 6
     X = W.points(n, d, 2.0, 961)
     b = W.dim_weights(d, 2.0)
-    x = np.random.default_rng(962).standard_normal((n, 1))
+    x = np.random.default_rng(962).standard_normal((n, nrhs))
     tree0 = dw.build_tree(torch.from_numpy(X).cuda(), b, 64, 0.8)
     ell = near_reach2(tree0) / ratio
     del tree0
     P = orc.Plan(X, b, 64, 0.8, "gaussian", ell, 5)
-    tree, op = build(X, b, 64, 0.8, "gaussian", ell, 5)
+    tree, op = build(X, b, 64, 0.8, "gaussian", ell, 5, nrhs)
     assert op.gauss_split == split
     y, yr = matvec(op, x), P.matvec(x)
     e = rel(y, yr)
     ea = float(np.abs(y - yr).max() / np.abs(yr).max())
-    say(f"[split Gaussian reach^2/ell = {ratio}] ell {ell:.4g}, split {op.gauss_split}: rel err {e:.3e}, "
+    say(f"[split Gaussian reach^2/ell = {ratio}, {nrhs} rhs] ell {ell:.4g}, split {op.gauss_split}: rel err {e:.3e}, "
         f"max abs err / max |y| {ea:.3e}")
     assert e <= TOL and ea <= 10 * TOL
 

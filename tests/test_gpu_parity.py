@@ -68,6 +68,8 @@ CASES = [
     # Gaussian with a length scale so short that the split form's exponents would exceed 600:
     # the single-rhs nearfield keeps the direct form
     ("d6_gauss_short", 6000, 6, 1.0, "gaussian", 2e-4, 4, 64, 0.8, 1),
+    # ... and the several-rhs nearfield in the direct form (the split form runs for the other Gaussians)
+    ("d6_gauss_short_r5", 6000, 6, 1.0, "gaussian", 2e-4, 4, 64, 0.8, 5),
     # the exponential kernel with two padding rows free for the squared norms (d = 5 in 8)
     ("d5_exp", 7000, 5, 2.0, "exponential", 0.3, 5, 100, 0.5, 1),
     # Matern with exponents beyond the unclamped variant's bound (s log2(e) > 1000 over the nearfield)
@@ -87,7 +89,7 @@ def test_matvec_parity_fp64(orc, case):
     tree, op = gpu_op(X, b, leaf, eta, kind, ell, q, nrhs=nrhs)
     assert op.nx == P.nx and tree.J == P.J and tree.nF == P.nF and tree.nN == P.nN
     # the split Gaussian nearfield runs wherever its exponents stay bounded
-    assert op.gauss_split == (kind == "gaussian" and name != "d6_gauss_short")
+    assert op.gauss_split == (kind == "gaussian" and not name.startswith("d6_gauss_short"))
     if name == "d2_matern_short":
         # a leaf's self block is nearfield, so its longest side bounds the nearfield reach from below:
         # sqrt(3) reach log2(e) / ell is past the 1000 up to which the unclamped variant runs

@@ -23,6 +23,13 @@ from paper_2402_09531_amd import workloads as W  # noqa: E402
 
 NORM_BOUND = {("fp32", False): 5e-6, ("fp32", True): 6e-6, ("bf16", False): 5e-6, ("bf16", True): 6e-3}
 ROW_BOUND = {("fp32", False): 1.5e-7, ("fp32", True): 5e-7, ("bf16", False): 1.5e-7, ("bf16", True): 4e-4}
+# The direct form's FP32 squared distance |x-c|^2 + |y-c|^2 - 2 (x-c).(y-c) carries an absolute error of
+# about 2^-24 (|x-c|^2 + |y-c|^2), i.e. a relative error of that over ell in the kernel value: with
+# the short length scale (nearfield reach^2 / ell in the thousands) a row's error reaches 1.2e-5 of
+# its scale in FP32 (measured), so that case states its own row bound, three times that.  In BF16 its
+# rows are sums of a few terms, so the rounding of each product's operands to BF16 (2^-9 relative
+# each) is not averaged out: 3.9e-3 of the row scale measured, bound 1.2e-2.
+ROW_BOUND_CASE = {("d6_gauss_short_5rhs", "fp32"): 4e-5, ("d6_gauss_short_5rhs", "bf16"): 1.2e-2}
 
 
 def say(*a):
@@ -40,6 +47,8 @@ CASES = [
     ("d10_matern_1rhs", 20000, 10, 2.0, "matern32", 1.0, 6, 128, 0.8, 1),
     ("d20_gauss_32rhs", 12000, 20, 3.0, "gaussian", 0.5, 6, 128, 0.8, 32),
     ("d7_exp_5rhs", 6000, 7, 2.0, "exponential", 0.3, 5, 100, 0.5, 5),
+    # Gaussian whose nearfield exponents pass the split form's bound: the direct form
+    ("d6_gauss_short_5rhs", 6000, 6, 1.0, "gaussian", 2e-4, 4, 64, 0.8, 5),
 ]
 
 
@@ -54,6 +63,9 @@ def test_reduced_precision_matvec_error(orc, case, prec):
     P = orc.Plan(X, b, leaf, eta, kind, ell, q)
     tree = dw.build_tree(torch.from_numpy(X).cuda(), b, leaf, eta)
     op = dw.fmm_create(tree, kind, ell, q, max_nrhs=nrhs)
+    # the FP32 nearfield's split Gaussian (exponents within 80) for the d = 20 cases, the direct form
+    # for the short length scale
+    assert op.gauss_split32 == (kind == "gaussian" and ell > 1e-3)
     xd = torch.from_numpy(x).cuda()
     yd = torch.empty_like(xd)
     dw.fmm_matvec(op, xd, yd, precision=prec)
@@ -66,7 +78,7 @@ def test_reduced_precision_matvec_error(orc, case, prec):
     er = float(np.max(np.abs(y - y_ref) / ya))
     say(f"[{prec}] {name}: relative error vs FP64 oracle {e:.3e}, largest entry error / row scale {er:.3e}")
     assert e <= NORM_BOUND[(prec, nrhs > 1)]
-    assert er <= ROW_BOUND[(prec, nrhs > 1)]
+    assert er <= ROW_BOUND_CASE.get((name, prec), ROW_BOUND[(prec, nrhs > 1)])
     assert e > 1e-13  # the reduced path really ran
 
 
