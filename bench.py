@@ -558,6 +558,103 @@ def bench_paper_pe(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_paper_pe_grid(args):
+    """The Sec 6.2 prediction-error surface: for each r, the 15 printed length scales x 15 ridges
+    log-equispaced in [1e-6, 1e-1]; per ridge one batched FP64 CG solve over the 15 operators
+    (dwfmm_batch_solve, rtol 1e-6, at most --pe-max-iter iterations), then the exact interpolant at
+    1000 uniform points of the root box (five draws) against f.  The paper prints the surface only as
+    figures; its best point per r is compared."""
+    import torch
+    import paper_2402_09531_amd as dw
+    from paper_2402_09531_amd import workloads as W
+    with open(os.path.join(ROOT, "tests", "golden", "sec62_compression_error.json")) as fh:
+        ref = json.load(fh)
+    dev = torch.device("cuda:0")
+    n = args.ce_n
+    lams = [10.0 ** (-6 + 5 * i / 14) for i in range(15)]
+    out = {"metric": "prediction-error surface of Sec 6.2 (15 length scales x 15 ridges)",
+           "unit": "relative 2-norm error", "n_gpus": 1, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"N={n}, d=20, b_k=k^-r, exponential kernel, q=8, Sec 6.2 weights, AFP nodes, "
+                                  f"admissibility {args.ce_eta} x full diagonal, leaf {args.ce_leaf}, CG rtol 1e-6 "
+                                  f"(at most {args.pe_max_iter} iterations), 1000 test points x 5 draws",
+                      "lambdas": lams},
+           "results": {}}
+
+    def f_true(P):
+        r = torch.linalg.norm(P, dim=1)
+        return torch.sin(4 * np.pi * r) / (8 * np.pi * r)
+
+    for r in args.pe_r:
+        sig = [row[0] for row in ref[f"r{r}"]]
+        X = W.points(n, 20, float(r), 6200 + r)
+        b = W.dim_weights(20, float(r))
+        Xd = torch.from_numpy(X).to(dev)
+        tree = dw.build_tree(Xd, b, args.ce_leaf, args.ce_eta)
+        t0 = time.perf_counter()
+
+        def progress(it, rr):
+            if it % 128 == 0:
+                log(f"[pe-grid] r={r} CG iteration {it}: relative residual {rr[0]:.3e} ({time.perf_counter() - t0:.1f} s)")
+
+        ops = [dw.fmm_create(tree, "exponential", s_, 8, weight_rule="R3", nodes="afp", check_every=16,
+                             progress=progress) for s_ in sig]
+        log(f"[pe-grid] r={r}: n_x {ops[0].nx}, operators built ({time.perf_counter() - t0:.1f} s)")
+        # the batched kernels take n_x <= 64; above that each problem is solved on its own
+        batch = dw.batch_create(ops) if max(op.nx for op in ops) <= 64 else None
+        fd = f_true(Xd)[:, None].contiguous()
+        A = torch.zeros((len(sig), len(lams), n), dtype=torch.float64, device=dev)
+        infos = [[None] * len(lams) for _ in sig]
+        for j, lam in enumerate(lams):
+            als = [torch.zeros_like(fd) for _ in sig]
+            if batch is not None:
+                res = dw.batch_solve(batch, lam, [fd] * len(sig), als, 1e-6, args.pe_max_iter, check_every=16)
+            else:
+                res = [dw.fmm_solve(op, lam, fd, a_, 1e-6, args.pe_max_iter)[0] for op, a_ in zip(ops, als)]
+            for i in range(len(sig)):
+                A[i, j] = als[i][:, 0]
+                infos[i][j] = res[i]
+            nconv = sum(1 for x in res if x["status"] == 0)
+            log(f"[pe-grid] r={r} lambda={lam:.2e}: {nconv}/{len(sig)} converged, "
+                f"iterations {min(x['iters'] for x in res)}..{max(x['iters'] for x in res)} "
+                f"({time.perf_counter() - t0:.1f} s)")
+        torch.cuda.synchronize()
+        lo, hi = Xd.min(0).values, Xd.max(0).values
+        pe = np.zeros((len(sig), len(lams), 5))
+        for rep in range(5):
+            g = torch.Generator(device="cpu").manual_seed(7000 * r + rep)
+            T = (lo.cpu() + (hi - lo).cpu() * torch.rand((1000, 20), generator=g, dtype=torch.float64)).to(dev)
+            ft = f_true(T)
+            D = pairwise_dist(T, Xd)
+            for i, s_ in enumerate(sig):
+                S = torch.exp(-D / s_) @ A[i].T  # 1000 x 15 ridges
+                pe[i, :, rep] = (torch.linalg.norm(S - ft[:, None], dim=0) / torch.linalg.norm(ft)).cpu().numpy()
+            del D
+        pem = pe.mean(axis=2)
+        i0, j0 = np.unravel_index(np.argmin(pem), pem.shape)
+        sp, lp, pe_p, _ = PAPER_PE_BEST[r]
+        ip, jp = int(np.argmin(np.abs(np.log(np.array(sig) / sp)))), int(np.argmin(np.abs(np.log(np.array(lams) / lp))))
+        conv = np.array([[infos[i][j]["status"] == 0 for j in range(len(lams))] for i in range(len(sig))])
+        out["results"][f"r{r}"] = {
+            "sigmas": sig, "pe_mean": pem.tolist(), "converged": conv.astype(int).tolist(),
+            "iterations": [[infos[i][j]["iters"] for j in range(len(lams))] for i in range(len(sig))],
+            "best": {"sigma": sig[i0], "lambda": lams[j0], "pe": float(pem[i0, j0]), "converged": bool(conv[i0, j0])},
+            "at_paper_best": {"sigma": sig[ip], "lambda": lams[jp], "pe": float(pem[ip, jp]),
+                              "converged": bool(conv[ip, jp]), "paper_pe": pe_p},
+            "solve_s": round(time.perf_counter() - t0, 1)}
+        log(f"[pe-grid] r={r}: smallest PE {pem[i0, j0]:.3e} at sigma={sig[i0]:.3e}, lambda={lams[j0]:.2e} "
+            f"(CG {'converged' if conv[i0, j0] else 'capped'}); at the paper's best point "
+            f"(sigma={sig[ip]:.3e}, lambda={lams[jp]:.2e}) {pem[ip, jp]:.3e} against the printed {pe_p:.2e}; "
+            f"{int(conv.sum())}/{conv.size} solves converged")
+        if batch is not None:
+            batch.close()
+        for op in ops:
+            op.close()
+        tree.close()
+    out["value"] = float(np.exp(np.mean([np.log(v["best"]["pe"] / PAPER_PE_BEST[int(k[1:])][2])
+                                         for k, v in out["results"].items()])))
+    print(json.dumps(out), flush=True)
+
+
 def bench_index_compare(args):
     """Cost of the three index sets of Sec 6.1 on one problem: weighted total degree (R1
     weights), total degree (omega = 1) and tensor product, over a range of q.  For each: n_x,
@@ -837,6 +934,9 @@ def main():
     ap.add_argument("--paper-pe", action="store_true",
                     help="prediction error at the paper's best Sec 6.2 parameters (CG solves)")
     ap.add_argument("--pe-max-iter", type=int, default=4000, help="paper-pe: CG iteration limit")
+    ap.add_argument("--pe-grid", action="store_true",
+                    help="paper-pe: the whole 15 x 15 (length scale, ridge) surface, batched solves per ridge")
+    ap.add_argument("--pe-r", type=int, nargs="+", default=[2, 3, 4], help="paper-pe --pe-grid: the values of r")
     ap.add_argument("--lebesgue", action="store_true", help="sampled Lebesgue constants of both node rules")
     ap.add_argument("--solve", action="store_true", help="full-size CG solve (FP64, or reduced precision with IR)")
     ap.add_argument("--solve-max-iter", type=int, default=300)
@@ -886,7 +986,10 @@ def main():
         bench_paper_ce(args)
         return
     if args.paper_pe:
-        bench_paper_pe(args)
+        if args.pe_grid:
+            bench_paper_pe_grid(args)
+        else:
+            bench_paper_pe(args)
         return
     if args.lebesgue:
         bench_lebesgue(args)
