@@ -1357,9 +1357,10 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
         __syncthreads();
         // columns [c0, c0 + ns) of the current stream (or of the own block): colP holds each
         // column's point, set by the caller of stage_chunk before the barrier
-        auto stage_chunk = [&](int ns) {
-            if (tid < kSymLeaf) {
-                const int j = tid;
+        // sid: the 128 threads that stage the coordinates (waves 0-1 or 2-3, alternating by chunk)
+        auto stage_chunk = [&](int ns, int sid) {
+            if (sid < kSymLeaf) {
+                const int j = sid;
                 const bool ok = j < ns;
                 const int jj = colP[j];
                 double xv[DK];
@@ -1392,10 +1393,11 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
         if (sDiag) {
             if (tid < kSymLeaf) colP[tid] = cb + (tid < nt ? tid : nt - 1);
             __syncthreads();
-            stage_chunk(nt);
+            stage_chunk(nt, tid);
             __syncthreads();
             mrhs_block<KIND, DK, RB, true>(Bt, tn, Y, sX, sN, sQ, nt, ntiles, w, li, lg, inv_ell);
         }
+        int chunk = 0;  // the column search and coordinate staging alternate between waves 0-1 and 2-3
         for (int fb = f0; fb < f1; fb += kSymSeg) {
             const int fe = min(fb + kSymSeg, f1);
             __syncthreads();  // the previous tiles and table are consumed
@@ -1419,13 +1421,14 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
                 __syncthreads();
             }
             const int total = sPre[kSymSeg];
-            for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+            for (int c0 = 0; c0 < total; c0 += kSymLeaf, ++chunk) {
                 const int ns = min(kSymLeaf, total - c0);
+                const int sid = tid ^ ((chunk & 1) << 7);
                 __syncthreads();  // the previous chunk's tiles are consumed
-                if (tid < kSymLeaf) {
+                if (sid < kSymLeaf) {
                     int pidx = cb;  // any valid point for the padding columns
-                    if (tid < ns) {
-                        const int col = c0 + tid;  // the entry holding it: the largest k with sPre[k] <= col
+                    if (sid < ns) {
+                        const int col = c0 + sid;  // the entry holding it: the largest k with sPre[k] <= col
                         int lo = 0, hi = kSymSeg;
                         while (lo < hi) {
                             const int mid = (lo + hi + 1) >> 1;
@@ -1434,10 +1437,10 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
                         }
                         pidx = sBeg[lo] + (col - sPre[lo]);
                     }
-                    colP[tid] = pidx;
+                    colP[sid] = pidx;
                 }
                 __syncthreads();
-                stage_chunk(ns);
+                stage_chunk(ns, sid);
                 __syncthreads();
                 mrhs_block<KIND, DK, RB, false>(Bt, tn, Y, sX, sN, sQ, ns, ntiles, w, li, lg, inv_ell);
             }
@@ -1987,9 +1990,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
         for (int f = f0 + tid; f < f1; f += blockDim.x)
             if (T.Nsrc[f] == l) sDiag = 1;
         __syncthreads();
-        auto stage_chunk = [&](int ns) {  // columns of colP[0..kSymLeaf), the first ns real
-            if (tid < kSymLeaf) {
-                const int j = tid;
+        // sid: the 128 threads that stage the coordinates (waves 0-1 or 2-3, alternating by chunk)
+        auto stage_chunk = [&](int ns, int sid) {  // columns of colP[0..kSymLeaf), the first ns real
+            if (sid < kSymLeaf) {
+                const int j = sid;
                 const bool ok = j < ns;
                 const int jj = colP[j];
                 double xv[DK];
@@ -2041,10 +2045,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
         if (sDiag) {
             if (tid < kSymLeaf) colP[tid] = cb + (tid < nt ? tid : nt - 1);
             __syncthreads();
-            stage_chunk(nt);
+            stage_chunk(nt, tid);
             __syncthreads();
             mrhs_block_lp<KIND, DK, RB, BF16, true>(Bt, tn, Y, sX, sN, sQ, sQt, nt, ntiles, w, li, lg, inv_ell);
         }
+        int chunk = 0;  // the column search and coordinate staging alternate between waves 0-1 and 2-3
         for (int fb = f0; fb < f1; fb += kSymSeg) {
             const int fe = min(fb + kSymSeg, f1);
             __syncthreads();  // the previous tiles and table are consumed
@@ -2068,13 +2073,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
                 __syncthreads();
             }
             const int total = sPre[kSymSeg];
-            for (int c0 = 0; c0 < total; c0 += kSymLeaf) {
+            for (int c0 = 0; c0 < total; c0 += kSymLeaf, ++chunk) {
                 const int ns = min(kSymLeaf, total - c0);
+                const int sid = tid ^ ((chunk & 1) << 7);
                 __syncthreads();
-                if (tid < kSymLeaf) {
+                if (sid < kSymLeaf) {
                     int pidx = cb;
-                    if (tid < ns) {
-                        const int col = c0 + tid;
+                    if (sid < ns) {
+                        const int col = c0 + sid;
                         int lo = 0, hi = kSymSeg;
                         while (lo < hi) {
                             const int mid = (lo + hi + 1) >> 1;
@@ -2083,10 +2089,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
                         }
                         pidx = sBeg[lo] + (col - sPre[lo]);
                     }
-                    colP[tid] = pidx;
+                    colP[sid] = pidx;
                 }
                 __syncthreads();
-                stage_chunk(ns);
+                stage_chunk(ns, sid);
                 __syncthreads();
                 mrhs_block_lp<KIND, DK, RB, BF16, false>(Bt, tn, Y, sX, sN, sQ, sQt, ns, ntiles, w, li, lg, inv_ell);
             }
