@@ -335,7 +335,10 @@ typedef struct {
     double lambda;              /* >= 0 */
     double rtol;                /* > 0 */
     int32_t max_iter;           /* >= 0 */
-    int32_t precision;          /* dwfmm_precision of the matvec inside CG */
+    int32_t precision;          /* dwfmm_precision of the matvec inside CG (no refinement: a
+                                   reduced-precision request converges to its operator's accuracy and
+                                   is reported E_NOT_CONVERGED when its FP64 true residual stays above
+                                   rtol) */
 } dwfmm_request;
 dwfmm_status dwfmm_server_create(size_t budget_bytes, int32_t max_active, int32_t check_every, void *stream,
                                  dwfmm_server *out);

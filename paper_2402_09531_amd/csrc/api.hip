@@ -2108,6 +2108,10 @@ dwfmm_status retire(dwfmm_server s, ServerRequest *r, int32_t state)
     r->info.rel_res_recursive = std::sqrt(sc[0]) / den;
     r->info.rel_res_true = std::sqrt(res[0]) / den;
     r->info.status = state == 1 ? DWFMM_OK : (state == 2 ? DWFMM_E_BREAKDOWN : DWFMM_E_NOT_CONVERGED);
+    // a reduced-precision request converges on its own operator; it has met its tolerance only if the
+    // FP64 residual has too
+    if (r->info.status == DWFMM_OK && r->precision != DWFMM_FP64 && !(r->info.rel_res_true <= r->rtol))
+        r->info.status = DWFMM_E_NOT_CONVERGED;
     release_request(r, s->held);
     r->t_retired = s->now();
     return DWFMM_OK;

@@ -97,3 +97,32 @@ def test_server_tiny_budget_and_failed_request():
     for k in range(len(reqs)):
         status = results[k][1]["status"]
         assert status == (dw.E_NONFINITE if k == 2 else 0), (k, status)
+
+
+def test_server_reduced_precision_request_status(orc):
+    """An FP32 request runs CG on its FP32 operator without refinement: at a tolerance that operator
+    reaches, OK with the FP64 residual within it; at 1e-9, below the FP32 operator's accuracy, its
+    recursive residual may still get there, but the FP64 residual does not and the status says so."""
+    r = requests(count=1, seed=21)[0]
+    srv = dw.Server(1 << 40, max_active=4, check_every=1)
+    ids = [srv.submit(r["X"], r["b"], r["f"], r["leaf"], r["eta"], r["kernel"], r["ell"], r["q"], r["lam"], rtol,
+                      r["max_iter"], precision="fp32") for rtol in (1e-3, 1e-9)]
+    done, ticks = {}, 0
+    while len(done) < 2:
+        srv.tick()
+        ticks += 1
+        assert ticks < 100000
+        for rid in ids:
+            if rid not in done:
+                out = srv.result(rid)
+                if out is not None:
+                    done[rid] = out
+    (a1, i1), (a2, i2) = done[ids[0]], done[ids[1]]
+    say(f"[server fp32] rtol 1e-3: status {i1['status']} true {i1['rel_res_true']:.2e}; "
+        f"rtol 1e-9: status {i2['status']} recursive {i2['rel_res_recursive']:.2e} true {i2['rel_res_true']:.2e}")
+    assert i1["status"] == 0 and i1["rel_res_true"] <= 1e-3
+    assert i2["rel_res_true"] > 1e-9 and i2["status"] == dw.E_NOT_CONVERGED
+    # the reported FP64 residual is the oracle's
+    P = orc.Plan(r["X"], r["b"], r["leaf"], r["eta"], r["kernel"], r["ell"], r["q"])
+    res = np.linalg.norm(r["f"] - (P.matvec(a2) + r["lam"] * a2)) / np.linalg.norm(r["f"])
+    assert abs(res - i2["rel_res_true"]) <= 1e-3 * res
