@@ -361,6 +361,7 @@ def served_vs_plain(reqs, lam: float, rtol: float, maxit: int, budget_gb: int, m
     q_s, prep_s, svc_s = tm[:, 1] - tm[:, 0], tm[:, 2] - tm[:, 1], tm[:, 3] - tm[:, 2]
 
     t0 = time.perf_counter()
+    last_plain_log = t0
     start, fin, plain_info = [], [], []
     for k, r in enumerate(reqs):
         now = time.perf_counter() - t0
@@ -376,7 +377,8 @@ def served_vs_plain(reqs, lam: float, rtol: float, maxit: int, budget_gb: int, m
         op.close()
         tree.close()
         fin.append(time.perf_counter() - t0)
-        if k % 100 == 99:
+        if k % 100 == 99 or time.perf_counter() - last_plain_log > 10:
+            last_plain_log = time.perf_counter()
             log(f"[serve] plain: {k + 1}/{len(reqs)} done ({fin[-1]:.0f} s)")
     t_plain = time.perf_counter() - t0
     log(f"[serve] plain: {t_plain:.2f} s")
