@@ -1334,11 +1334,17 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
         if (far_list) {
             // longest farfield lists first (ties in list order): the costly clusters start early,
             // and a persistent grid striding over the list takes a balanced mix of them
-            auto nfar = [&](const int2 &w) {
-                const HostTree &H = *item_tree[w.x];
-                return H.Fptr[w.y + 1] - H.Fptr[w.y];
-            };
-            std::stable_sort(lst.begin(), lst.end(), [&](const int2 &a, const int2 &b2) { return nfar(a) > nfar(b2); });
+            // (the list lengths are gathered once: looking them up in the trees inside the sort's
+            // comparisons cost most of a plan rebuild)
+            std::vector<std::pair<int64_t, int64_t>> kv(lst.size());  // (-list length, position)
+            for (size_t i = 0; i < lst.size(); ++i) {
+                const HostTree &H = *item_tree[lst[i].x];
+                kv[i] = {-(int64_t)(H.Fptr[lst[i].y + 1] - H.Fptr[lst[i].y]), (int64_t)i};
+            }
+            std::sort(kv.begin(), kv.end());
+            std::vector<int2> sorted(lst.size());
+            for (size_t i = 0; i < lst.size(); ++i) sorted[i] = lst[kv[i].second];
+            lst.swap(sorted);
         }
         if (!far_list) {
             // Workgroup q runs on XCD q % 8.  The list is cut into 8 contiguous segments of equal
@@ -1363,11 +1369,11 @@ static dwfmm_status batch_build(const dwfmm_op *ops, int32_t count, int32_t flag
             for (int k = 0; k < 8; ++k) longest = std::max(longest, cut[k + 1] - cut[k]);
             std::vector<int2> perm(8 * longest, make_int2(-1, 0));
             for (int k = 0; k < 8; ++k) {
-                // the costliest leaves of the segment first, so it ends on short ones
-                std::vector<size_t> seg;
-                for (size_t j = cut[k]; j < cut[k + 1]; ++j) seg.push_back(j);
-                std::stable_sort(seg.begin(), seg.end(), [&](size_t a, size_t b2) { return wk[a] > wk[b2]; });
-                for (size_t j = 0; j < seg.size(); ++j) perm[8 * j + k] = lst[seg[j]];
+                // the costliest leaves of the segment first (ties in list order), so it ends on short ones
+                std::vector<std::pair<double, size_t>> seg;
+                for (size_t j = cut[k]; j < cut[k + 1]; ++j) seg.push_back({-wk[j], j});
+                std::sort(seg.begin(), seg.end());
+                for (size_t j = 0; j < seg.size(); ++j) perm[8 * j + k] = lst[seg[j].second];
             }
             lst.swap(perm);
         }
