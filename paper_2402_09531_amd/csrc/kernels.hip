@@ -1227,7 +1227,9 @@ hipError_t launch_cross_mfma_k(const DevTree &Tt, const DevOp &Ot, const DevTree
 // K[target i][source 4v + g], which is exactly the A operand of chunk v of
 //   Y(16 targets x 16 rhs) += K(16 x 16) Q(16 sources x 16 rhs),
 // so the kernel values feed the apply MFMAs without any lane exchange.  RB = number of
-// 16-wide rhs tiles.  L2P and the scatter to caller order are fused at the end.
+// 16-wide rhs tiles.  L2P and the scatter to caller order are fused at the end.  The split
+// Gaussian variant (KIND kGaussSplit) starts each Gram chain from the sources' base-2 column
+// factors and scales the finished sums by the targets' row factors.
 template <int RB>
 constexpr int q_stride() { return 16 * RB + 1; }  // padded row of the staged charges
 
