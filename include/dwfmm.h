@@ -106,6 +106,13 @@ typedef struct {
     int32_t index_rule;      /* dwfmm_index_rule, default WEIGHTED_TOTAL_DEGREE */
     int32_t ir_max_inner;    /* reduced precision: max inner CG iterations per refinement step
                                 (0 = up to the solve's remaining max_iter) */
+    int32_t cache_near;      /* 1: keep the BF16 kernel tiles of the several-rhs nearfield in device
+                                memory (2 bytes per nearfield entry, rows padded to 128: ~42 GB at
+                                N = 1e6, d = 20); the first BF16 matvec with nrhs > 1 writes them,
+                                later ones read them instead of recomputing (same results, bit for
+                                bit; not used inside a graph capture).  Needs precision BF16 and
+                                max_nrhs > 1 (else E_INVALID); kept only when leaves hold at most 128
+                                points and d <= 32.  Default 0. */
 } dwfmm_opts;
 
 /* Per right-hand-side result of dwfmm_fmm_solve. */

@@ -44,7 +44,7 @@ class _Opts(C.Structure):
                 ("max_nrhs", C.c_int32), ("check_every", C.c_int32), ("ir_inner_rtol", C.c_double),
                 ("ir_max_outer", C.c_int32), ("node_rule", C.c_int32), ("afp_candidates", C.c_int32),
                 ("progress", C.c_void_p), ("progress_ctx", C.c_void_p), ("index_rule", C.c_int32),
-                ("ir_max_inner", C.c_int32)]
+                ("ir_max_inner", C.c_int32), ("cache_near", C.c_int32)]
 
 
 # void (*)(void *ctx, int32_t iteration, int32_t nrhs, const double *rel_res)
@@ -324,10 +324,11 @@ def build_tree(points, dim_weights, leaf_size: int, eta: float, stream=None, adm
 def fmm_create(tree: Tree, kernel: str, ell: float, q: float, precision: str = "fp64", max_nrhs: int = 1,
                weight_rule: str = "R1", omega=None, check_every: int = 1, ir_inner_rtol: float = 0.0,
                ir_max_outer: int = 30, nodes: str = "cheb_leja", afp_candidates: int = 0, progress=None,
-               index_set: str = "weighted_total_degree", ir_max_inner: int = 0, stream=None) -> Op:
+               index_set: str = "weighted_total_degree", ir_max_inner: int = 0, cache_near: bool = False,
+               stream=None) -> Op:
     """dwfmm_fmm_create (nodes: "cheb_leja" or "afp", the approximate Fekete points; index_set:
     "weighted_total_degree" or "tensor"; progress: optional callable(iteration, rel_res list) run at
-    the solver's host convergence checks)."""
+    the solver's host convergence checks; cache_near: keep the BF16 several-rhs nearfield tiles)."""
     om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
     cb = None
     if progress is not None:
@@ -335,7 +336,7 @@ def fmm_create(tree: Tree, kernel: str, ell: float, q: float, precision: str = "
     opts = _Opts(WEIGHT_RULES[weight_rule], _f64p(om), PRECISIONS[precision], int(max_nrhs), int(check_every),
                  float(ir_inner_rtol), int(ir_max_outer), NODE_RULES[nodes], int(afp_candidates),
                  C.cast(cb, C.c_void_p) if cb is not None else None, None, INDEX_RULES[index_set],
-                 int(ir_max_inner))
+                 int(ir_max_inner), int(bool(cache_near)))
     h = C.c_void_p()
     _check(lib().dwfmm_fmm_create(tree._h, _Kernel(KERNELS[kernel], float(ell)), float(q), C.byref(opts),
                                   _stream(stream), C.byref(h)))
@@ -613,11 +614,12 @@ def op_bytes(op: Op) -> int:
 
 
 def op_bytes_for(tree: Tree, q: float, precision: str = "fp64", max_nrhs: int = 1, weight_rule: str = "R1",
-                 omega=None, nodes: str = "cheb_leja", index_set: str = "weighted_total_degree") -> int:
+                 omega=None, nodes: str = "cheb_leja", index_set: str = "weighted_total_degree",
+                 cache_near: bool = False) -> int:
     """dwfmm_op_bytes_for: the device bytes an operator with these options would hold on this tree."""
     om = None if omega is None else np.ascontiguousarray(omega, dtype=np.float64)
     opts = _Opts(WEIGHT_RULES[weight_rule], _f64p(om), PRECISIONS[precision], int(max_nrhs), 1, 0.0, 30,
-                 NODE_RULES[nodes], 0, None, None, INDEX_RULES[index_set], 0)
+                 NODE_RULES[nodes], 0, None, None, INDEX_RULES[index_set], 0, int(bool(cache_near)))
     return int(lib().dwfmm_op_bytes_for(tree._h, float(q), C.byref(opts)))
 
 

@@ -126,6 +126,7 @@ struct dwfmm_op_s {
     std::vector<KernelTimer> timers;
     size_t timers_used = 0;
     StreamFork fork;  // farfield beside the one-rhs nearfield
+    int near_filled = 0;  // the BF16 nearfield tile cache holds this operator's tiles
     ~dwfmm_op_s()
     {
         if (fork.forked) (void)hipEventDestroy(fork.forked);
@@ -426,6 +427,43 @@ extern "C" void dwfmm_tree_destroy(dwfmm_tree t)
 }
 
 // ============================================================== fmm_create
+// BF16 several-rhs nearfield tile cache (dwfmm_opts.cache_near): kept when asked for with BF16 and
+// max_nrhs > 1 on trees the several-rhs MFMA nearfield takes (leaves of at most 128 points, d <= 32).
+static bool near_cache_on(const HostTree &H, const dwfmm_opts &o)
+{
+    if (!o.cache_near || o.precision != DWFMM_BF16 || o.max_nrhs < 2 || H.d > 32) return false;
+    const int64_t lf = H.nleaf - 1;
+    for (int64_t l = 0; l < H.nleaf; ++l)
+        if (H.end[lf + l] - H.begin[lf + l] > 128) return false;
+    return true;
+}
+
+// Column tiles of each target leaf in the order the several-rhs nearfield streams its sources: the
+// leaf's own block when listed, then per list segment of 256 entries the other leaves' points back
+// to back, 16 columns a tile.  off[l] = first tile of leaf l, off[nleaf] = all tiles (4 KiB each).
+static std::vector<int64_t> near_tile_offsets(const HostTree &H)
+{
+    const int64_t lf = H.nleaf - 1;
+    std::vector<int64_t> off((size_t)H.nleaf + 1, 0);
+    for (int64_t l = 0; l < H.nleaf; ++l) {
+        const int64_t c = lf + l, nt = H.end[c] - H.begin[c], f0 = H.Nptr[c], f1 = H.Nptr[c + 1];
+        int64_t t = 0;
+        if (nt > 0) {
+            bool diag = false;
+            for (int64_t f = f0; f < f1; ++f) diag |= H.Nsrc[f] == c;
+            if (diag) t += (nt + 15) / 16;
+            for (int64_t fb = f0; fb < f1; fb += 256) {
+                int64_t total = 0;
+                for (int64_t f = fb; f < std::min<int64_t>(fb + 256, f1); ++f)
+                    if (H.Nsrc[f] != c) total += H.end[H.Nsrc[f]] - H.begin[H.Nsrc[f]];
+                t += (total + 15) / 16;
+            }
+        }
+        off[(size_t)l + 1] = off[(size_t)l] + t;
+    }
+    return off;
+}
+
 extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, double q, const dwfmm_opts *opts,
                                          void *stream, dwfmm_op *out)
 {
@@ -454,6 +492,8 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
         return fail(DWFMM_E_INVALID, "unknown node rule or negative candidate count");
     if (o.index_rule < 0 || o.index_rule > 1) return fail(DWFMM_E_INVALID, "unknown index rule");
     if (o.ir_max_inner < 0) return fail(DWFMM_E_INVALID, "ir_max_inner must be >= 0");
+    if (o.cache_near && (o.precision != DWFMM_BF16 || o.max_nrhs < 2))
+        return fail(DWFMM_E_INVALID, "cache_near needs BF16 precision and max_nrhs > 1");
     const HostTree &H = tree->H;
     hipStream_t st = (hipStream_t)stream;
 
@@ -561,6 +601,19 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
         return fail(e == hipErrorOutOfMemory ? DWFMM_E_NOMEM : DWFMM_E_HIP,
                     std::string("operator setup: ") + hipGetErrorString(e));
     }
+    if (near_cache_on(H, o)) {
+        const std::vector<int64_t> toff = near_tile_offsets(H);
+        int64_t *dtoff = nullptr;
+        if ((e = op->arena.alloc((void **)&op->D.near_tiles, 4096 * (size_t)toff.back())) != hipSuccess ||
+            (e = up(&dtoff, toff)) != hipSuccess || (e = hipStreamSynchronize(st)) != hipSuccess) {
+            op->arena.release();
+            delete op;
+            return fail(e == hipErrorOutOfMemory ? DWFMM_E_NOMEM : DWFMM_E_HIP,
+                        std::string("nearfield tile cache: ") + hipGetErrorString(e));
+        }
+        op->D.near_tile_off = dtoff;
+        op->D.near_filled = &op->near_filled;
+    }
     DevOp &D = op->D;
     D.kind = kernel.kind;
     D.ell = kernel.ell;
@@ -649,7 +702,9 @@ extern "C" size_t dwfmm_op_bytes_for(dwfmm_tree tree, double q, const dwfmm_opts
         return 0;
     const int64_t nblk = tree->stage ? (int64_t)tree->stage->own_src.size() : (int64_t)tree->D.nblk;
     const size_t tb = tree->stage ? tree_stage_bytes(tree) : tree->arena.total;
-    return tb + op_device_bytes(H, nblk, B, o.max_nrhs, o.precision);
+    size_t cache = 0;
+    if (near_cache_on(H, o)) cache = 4096 * (size_t)near_tile_offsets(H).back() + 8 * ((size_t)H.nleaf + 1);
+    return tb + op_device_bytes(H, nblk, B, o.max_nrhs, o.precision) + cache;
 }
 
 extern "C" void dwfmm_op_destroy(dwfmm_op op)

@@ -61,6 +61,15 @@ struct DevOp {
     // Matern only: sqrt(3) max|x - y| / ell log2(e) <= 1000 over the nearfield (from the host's reach
     // bound), so the FP64 nearfield's 2^-s log2(e) needs no underflow clamp
     int matern_in_range;
+    // Tile cache of the BF16 several-rhs nearfield (NULL when off): column tile t of target leaf l
+    // (16 stream columns x 8 row tiles of 16 targets, 64 lanes x 4 BF16 each, 4 KiB) sits at
+    // near_tiles + (near_tile_off[l] + t) * 512; near_filled points at a host flag set once a
+    // launch has written the tiles; near_cache_mode is chosen per launch (0 off, 1 compute and
+    // write, 2 read).
+    uint2 *near_tiles;
+    const int64_t *near_tile_off;
+    int *near_filled;
+    int near_cache_mode;
 };
 
 // Optional HIP events recorded around the nearfield (P2P) and coupling (M2L)

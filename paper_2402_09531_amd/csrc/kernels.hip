@@ -1859,19 +1859,63 @@ constexpr int kQtStride = kSymLeaf + 8;
 template <int RB>
 constexpr int q_stride32() { return 16 * RB + 4; }
 
-template <int KIND, int DK, int RB, bool BF16, bool DIAG>
+// A chunk's stored BF16 tiles for this wave (column tile ct, row tile w + 4u at tiles + ct * 512 +
+// (w + 4u) * 64 + lane: 8 bytes per lane, one coalesced 512-byte row per wave), all loads issued at
+// once so that they overlap each other and the chunk's charge staging; missing tiles read as zero.
+__device__ __forceinline__ void load_tiles(uint2 (&pre)[8][2], const uint2 *tiles, int64_t tcap, int ns, int ntiles,
+                                           int w, int lane)
+{
+    const int nct = (ns + 15) / 16;
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct)
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int rt = w + 4 * u;
+            pre[ct][u] = ct < nct && ct < tcap && rt < ntiles ? tiles[(size_t)ct * 512 + rt * 64 + lane]
+                                                              : make_uint2(0u, 0u);
+        }
+}
+
+// The apply of a chunk from its stored tiles: Y += K Q on the BF16 MFMA, charges from LDS.
+template <int RB>
+__device__ __forceinline__ void apply_tiles(const uint2 (&pre)[8][2], flt4 (&Y)[2][RB], const __bf16 *sQt, int ns,
+                                            int ntiles, int w, int li, int lg)
+{
+    const int nct = (ns + 15) / 16;
+#pragma unroll
+    for (int ct = 0; ct < 8; ++ct) {
+        if (ct >= nct) break;
+        bf16x4 Qb[RB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+            Qb[rb] = *reinterpret_cast<const bf16x4 *>(&sQt[(16 * rb + li) * kQtStride + 16 * ct + 4 * lg]);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            if (w + 4 * u >= ntiles) continue;
+            const bf16x4 Ka = __builtin_bit_cast(bf16x4, pre[ct][u]);
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb) Y[u][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ka, Qb[rb], Y[u][rb], 0, 0, 0);
+        }
+    }
+}
+
+// CM (BF16 only): 0 compute the kernel tiles, 1 compute them and also write them to `tiles`
+// (column tile ct of this call at tiles + ct * 512, at most `tcap` column tiles).
+template <int KIND, int DK, int RB, bool BF16, bool DIAG, int CM = 0>
 __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], const float (&tn)[2], flt4 (&Y)[2][RB],
                                               const float *sX, const float *sN, const float *sQ, const __bf16 *sQt,
-                                              int ns, int ntiles, int w, int li, int lg, float inv_ell)
+                                              int ns, int ntiles, int w, int li, int lg, float inv_ell,
+                                              uint2 *tiles = nullptr, int64_t tcap = 0)
 {
+    static_assert(CM == 0 || (CM == 1 && BF16), "the tile cache holds BF16 tiles");
     constexpr int NKC = DK / 4;
     const int rt[2] = {w, w + 4};
+    [[maybe_unused]] const int lane = li + 16 * lg;
     const int nct = (ns + 15) / 16;
     for (int ct = 0; ct < nct; ++ct) {
-        float Af[NKC];
+        float Af[NKC], snv[4];
 #pragma unroll
         for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSX32 + 16 * ct + li];
-        float snv[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) snv[e] = sN[16 * ct + 4 * lg + e];
         // the charge operands of this column tile serve both row tiles
@@ -1908,6 +1952,9 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
             }
             if constexpr (BF16) {
                 const bf16x4 Ka = {(__bf16)Kv[0], (__bf16)Kv[1], (__bf16)Kv[2], (__bf16)Kv[3]};
+                if constexpr (CM == 1) {
+                    if (ct < tcap) tiles[(size_t)ct * 512 + rt[u] * 64 + lane] = __builtin_bit_cast(uint2, Ka);
+                }
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) Y[u][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ka, Qb[rb], Y[u][rb], 0, 0, 0);
             } else {
@@ -1922,7 +1969,7 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
     }
 }
 
-template <int KIND, int DK, int RB, bool BF16>
+template <int KIND, int DK, int RB, bool BF16, int CM>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 4 : 1, 8))) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
                                                           int do_near, int do_far)
 {
@@ -1934,12 +1981,21 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
     __shared__ double cen[DK];
     __shared__ int32_t sPre[kSymSeg + 1], sBeg[kSymSeg], colP[kSymLeaf], sDiag;
     constexpr bool kSplit = KIND == kGaussSplit;
+    static_assert(CM == 0 || BF16, "the tile cache holds BF16 tiles");
     __shared__ float tF[kSplit ? kSymLeaf : 1];  // split Gaussian: row factors exp(-|x - c|^2 / ell)
     const int l = T.near_order[blockIdx.x];
     if (l < 0) return;  // padding of a shorter XCD segment
     const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
     if (nt == 0) return;
+    // the leaf's column tiles in the tile cache, taken in stream order (tb counts them)
+    uint2 *ltiles = nullptr;
+    int64_t lcount = 0, tb = 0;
+    uint2 pre[CM == 2 ? 8 : 1][2];  // reading: the current chunk's tiles of this wave
+    if constexpr (CM != 0) {
+        ltiles = O.near_tiles + O.near_tile_off[l] * 512;
+        lcount = O.near_tile_off[l + 1] - O.near_tile_off[l];
+    }
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lg = lane >> 4;
     const int n = T.n;
@@ -1994,7 +2050,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
         __syncthreads();
         // sid: the 128 threads that stage the coordinates (waves 0-1 or 2-3, alternating by chunk)
         auto stage_chunk = [&](int ns, int sid) {  // columns of colP[0..kSymLeaf), the first ns real
-            if (sid < kSymLeaf) {
+            if (CM != 2 && sid < kSymLeaf) {  // (the coordinates are not needed to read stored tiles)
                 const int j = sid;
                 const bool ok = j < ns;
                 const int jj = colP[j];
@@ -2045,11 +2101,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
             }
         };
         if (sDiag) {
+            if constexpr (CM == 2) load_tiles(pre, ltiles, lcount, nt, ntiles, w, lane);
             if (tid < kSymLeaf) colP[tid] = cb + (tid < nt ? tid : nt - 1);
             __syncthreads();
             stage_chunk(nt, tid);
             __syncthreads();
-            mrhs_block_lp<KIND, DK, RB, BF16, true>(Bt, tn, Y, sX, sN, sQ, sQt, nt, ntiles, w, li, lg, inv_ell);
+            if constexpr (CM == 2) {
+                apply_tiles<RB>(pre, Y, sQt, nt, ntiles, w, li, lg);
+            } else {
+                mrhs_block_lp<KIND, DK, RB, BF16, true, CM>(Bt, tn, Y, sX, sN, sQ, sQt, nt, ntiles, w, li, lg, inv_ell,
+                                                           ltiles + tb * 512, lcount - tb);
+            }
+            tb += (nt + 15) / 16;
         }
         int chunk = 0;  // the column search and coordinate staging alternate between waves 0-1 and 2-3
         for (int fb = f0; fb < f1; fb += kSymSeg) {
@@ -2078,6 +2141,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
             for (int c0 = 0; c0 < total; c0 += kSymLeaf, ++chunk) {
                 const int ns = min(kSymLeaf, total - c0);
                 const int sid = tid ^ ((chunk & 1) << 7);
+                if constexpr (CM == 2) load_tiles(pre, ltiles + tb * 512, lcount - tb, ns, ntiles, w, lane);
                 __syncthreads();
                 if (sid < kSymLeaf) {
                     int pidx = cb;
@@ -2096,7 +2160,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
                 __syncthreads();
                 stage_chunk(ns, sid);
                 __syncthreads();
-                mrhs_block_lp<KIND, DK, RB, BF16, false>(Bt, tn, Y, sX, sN, sQ, sQt, ns, ntiles, w, li, lg, inv_ell);
+                if constexpr (CM == 2) {
+                    apply_tiles<RB>(pre, Y, sQt, ns, ntiles, w, li, lg);
+                } else {
+                    mrhs_block_lp<KIND, DK, RB, BF16, false, CM>(Bt, tn, Y, sX, sN, sQ, sQt, ns, ntiles, w, li, lg,
+                                                                inv_ell, ltiles + tb * 512, lcount - tb);
+                }
+                tb += (ns + 15) / 16;
             }
         }
     }
@@ -2129,12 +2199,25 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
 template <int KIND, int DK, bool BF16>
 void launch_mrhs_lp_d(const DevTree &T, const DevOp &O, double *y, int nrhs, int near, int far, hipStream_t st)
 {
-    if (nrhs <= 16)
-        hipLaunchKernelGGL((p2p_mrhs_lp_kernel<KIND, DK, 1, BF16>), dim3(T.n_near_order), dim3(256), 0, st, T, O, y, nrhs,
-                           near, far);
-    else
-        hipLaunchKernelGGL((p2p_mrhs_lp_kernel<KIND, DK, 2, BF16>), dim3(T.n_near_order), dim3(256), 0, st, T, O, y, nrhs,
-                           near, far);
+#define DWFMM_LP(RB, CM)                                                                                   \
+    hipLaunchKernelGGL((p2p_mrhs_lp_kernel<KIND, DK, RB, BF16, CM>), dim3(T.n_near_order), dim3(256), 0, st, T, O, y, \
+                       nrhs, near, far)
+    [[maybe_unused]] const int cm = BF16 ? O.near_cache_mode : 0;
+    if constexpr (BF16) {
+        if (cm == 1) {
+            if (nrhs <= 16) DWFMM_LP(1, 1);
+            else DWFMM_LP(2, 1);
+            return;
+        }
+        if (cm == 2) {
+            if (nrhs <= 16) DWFMM_LP(1, 2);
+            else DWFMM_LP(2, 2);
+            return;
+        }
+    }
+    if (nrhs <= 16) DWFMM_LP(1, 0);
+    else DWFMM_LP(2, 0);
+#undef DWFMM_LP
 }
 
 template <int KIND, bool BF16>
@@ -3010,14 +3093,24 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
             default: e = launch_mrhs_lp_k<2, false>(T, O, y, nrhs, near, nfar, st); break;
             }
         } else {
-            switch (O.kind) {
-            case 0: e = launch_mrhs_lp_k<0, true>(T, O, y, nrhs, near, nfar, st); break;
-            case 1:
-                e = O.gauss_split32 ? launch_mrhs_lp_k<kGaussSplit, true>(T, O, y, nrhs, near, nfar, st)
-                                    : launch_mrhs_lp_k<1, true>(T, O, y, nrhs, near, nfar, st);
-                break;
-            default: e = launch_mrhs_lp_k<2, true>(T, O, y, nrhs, near, nfar, st); break;
+            // BF16 tile cache: the first nearfield launch writes the tiles, later ones read them (not
+            // inside a graph capture, whose launches run later than the host flag would say)
+            DevOp Oc = O;
+            Oc.near_cache_mode = 0;
+            if (O.near_tiles && near) {
+                hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+                if ((e = hipStreamIsCapturing(st, &cs)) != hipSuccess) return e;
+                if (cs == hipStreamCaptureStatusNone) Oc.near_cache_mode = *O.near_filled ? 2 : 1;
             }
+            switch (O.kind) {
+            case 0: e = launch_mrhs_lp_k<0, true>(T, Oc, y, nrhs, near, nfar, st); break;
+            case 1:
+                e = O.gauss_split32 ? launch_mrhs_lp_k<kGaussSplit, true>(T, Oc, y, nrhs, near, nfar, st)
+                                    : launch_mrhs_lp_k<1, true>(T, Oc, y, nrhs, near, nfar, st);
+                break;
+            default: e = launch_mrhs_lp_k<2, true>(T, Oc, y, nrhs, near, nfar, st); break;
+            }
+            if (e == hipSuccess && Oc.near_cache_mode == 1) *O.near_filled = 1;
         }
         if (timer) (void)hipEventRecord(timer->p2p_stop, st);
         if (e != hipSuccess || !split) return e;
