@@ -569,6 +569,7 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     auto up = [&](auto **dst, const auto &v) { return op->arena.upload(dst, v, st); };
     const size_t n = (size_t)H.n, R = (size_t)o.max_nrhs;
     double *dnodes, *dE, *dVinv, *dLb, *dxt, *dM, *dL;
+    __bf16 *dxtb = nullptr;
     int32_t *dlidx, *dla, *dld;
     hipError_t e = hipSuccess;
     double *dnodesT, *dnnorm;
@@ -578,6 +579,7 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
         (e = up(&dla, leg_axis)) != hipSuccess || (e = up(&dld, leg_deg)) != hipSuccess ||
         (e = op->arena.alloc((void **)&dLb, sizeof(double) * nx * n)) != hipSuccess ||
         (e = op->arena.alloc((void **)&dxt, sizeof(double) * n * R)) != hipSuccess ||
+        (R > 1 && (e = op->arena.alloc((void **)&dxtb, sizeof(__bf16) * n * R)) != hipSuccess) ||
         (e = op->arena.alloc((void **)&dM, sizeof(double) * H.ncl * nx * R)) != hipSuccess ||
         (e = op->arena.alloc((void **)&dL, sizeof(double) * H.ncl * nx * R)) != hipSuccess ||
         (e = op->arena.alloc((void **)&op->D.rowbuf, sizeof(double) * 128 * H.nleaf)) != hipSuccess ||
@@ -630,6 +632,7 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     D.E = dE;
     D.Lb = dLb;
     D.xt = dxt;
+    D.xtb = dxtb;
     D.M = dM;
     D.L = dL;
     op->precision = o.precision;
@@ -676,6 +679,7 @@ static size_t op_device_bytes(const HostTree &H, int64_t nblk, const HostBasis &
     size_t b = 8 * (ncl * nx * dp + ncl * nx * nx + ncl * dk * nxp + ncl * nxp + nx * nx);  // nodes, E, nodesT, norms, V^-1
     b += 4 * (nx * nnz_max + 2 * nleg);                                                     // Legendre slot tables
     b += 8 * (nx * n + n * R + 2 * ncl * nx * R);                                          // basis cache, xt, M, L
+    if (R > 1) b += 2 * n * R;                                                              // xtb
     b += 8 * 128 * ((size_t)H.nleaf + (size_t)nblk);                                       // row and column sums
     b += 8 * n * R * (precision != DWFMM_FP64 ? 5 : 3);                                    // r, p, q (, ir_r, ir_d)
     b += 8 * (2 * (size_t)kDotBlocks * R + 16 * (size_t)R) + 4 * 4 * (size_t)R;            // partial, scal, state
@@ -809,6 +813,7 @@ static size_t static_scratch_need(dwfmm_op op, int32_t nrhs)
     const DevTree &T = op->tree->D;
     const size_t n = (size_t)T.n, nx = (size_t)op->D.nx, r = (size_t)nrhs;
     size_t b = align256(sizeof(double) * n * r) + 2 * align256(sizeof(double) * (size_t)T.ncl * nx * r);
+    if (nrhs > 1) b += align256(sizeof(__bf16) * n * r);
     if (nrhs == 1) b += align256(sizeof(double) * 128 * (size_t)T.nleaf) + align256(sizeof(double) * 128 * (size_t)T.nblk);
     return b;
 }
@@ -839,6 +844,11 @@ extern "C" dwfmm_status dwfmm_fmm_matvec_static(dwfmm_op op, const double *x, do
     p += align256(sizeof(double) * (size_t)T.ncl * nx * r);
     O.L = (double *)p;
     p += align256(sizeof(double) * (size_t)T.ncl * nx * r);
+    O.xtb = nullptr;
+    if (nrhs > 1) {
+        O.xtb = (__bf16 *)p;
+        p += align256(sizeof(__bf16) * n * r);
+    }
     if (nrhs == 1) {
         O.rowbuf = (double *)p;
         p += align256(sizeof(double) * 128 * (size_t)T.nleaf);

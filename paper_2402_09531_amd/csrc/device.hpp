@@ -47,6 +47,7 @@ struct DevOp {
     const double *E;              // [ncl][nx][nx] Lagrange transfer matrices (row a, column b)
     const double *Lb;             // [nx][n] Lagrange basis l_a(a_leaf^-1 x_i), tree order
     double *xt;                   // [n][max_nrhs] x in tree order
+    __bf16 *xtb;                  // [n][nrhs] the same charges rounded to BF16 through FP32 (max_nrhs > 1)
     double *M, *L;                // [ncl][nx][max_nrhs] moments and locals
     int nxp;                      // nx rounded up to a multiple of 16
     const double *nodesT;         // [ncl][dk][nxp] nodes, axis-major, zero padded (dk = d rounded up to 4)

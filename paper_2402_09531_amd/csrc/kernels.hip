@@ -224,6 +224,7 @@ __device__ __forceinline__ void p2m_body(const DevTree &T, const DevOp &O, int l
             const double v = x[(size_t)T.perm[cb + i] * nrhs + r];
             xl[i] = v;
             O.xt[(size_t)(cb + i) * nrhs + r] = v;
+            if (O.xtb) O.xtb[(size_t)(cb + i) * nrhs + r] = (__bf16)(float)v;
         }
         __syncthreads();
         if (do_far) {
@@ -259,6 +260,7 @@ __global__ __launch_bounds__(256) void p2m_multi_kernel(DevTree T, DevOp O, cons
         const double v = x[(size_t)T.perm[cb + i] * nrhs + r];
         xl[e] = v;
         O.xt[(size_t)cb * nrhs + e] = v;
+        if (O.xtb) O.xtb[(size_t)cb * nrhs + e] = (__bf16)(float)v;
     }
     if (!do_far) return;  // uniform over the workgroup
     __syncthreads();
@@ -2074,23 +2076,26 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
             const int r = BF16 ? (tid & 15) + 16 * ((tid >> 5) % RB) : tid % (16 * RB);
             const int j0 = BF16 ? (((tid >> 5) / RB) << 1) + ((tid >> 4) & 1) : tid / (16 * RB);
             const int rr = r < nrhs ? r : 0;
-            double qv[QPT];
             if constexpr (BF16) {
-                // columns 4 (j0 + G t) + e, e < 4: one 8-byte store of four columns per t into the
-                // transposed tile (single 2-byte stores put rhs r and r + 16 on one bank)
+                // charges of the BF16 copy P2M wrote (the values this path rounds the FP64 ones to,
+                // a quarter of their bytes); columns 4 (j0 + G t) + e, e < 4: one 8-byte store of
+                // four columns per t into the transposed tile (single 2-byte stores put rhs r and
+                // r + 16 on one bank)
+                __bf16 qb[QPT];
 #pragma unroll
                 for (int t = 0; t < QPT / 4; ++t)
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) qv[4 * t + e] = O.xt[(size_t)colP[4 * (j0 + G * t) + e] * nrhs + rr];
+                    for (int e = 0; e < 4; ++e) qb[4 * t + e] = O.xtb[(size_t)colP[4 * (j0 + G * t) + e] * nrhs + rr];
 #pragma unroll
                 for (int t = 0; t < QPT / 4; ++t) {
                     const int j = 4 * (j0 + G * t);
                     bf16x4 v;
 #pragma unroll
-                    for (int e = 0; e < 4; ++e) v[e] = (__bf16)((j + e < ns && r < nrhs) ? (float)qv[4 * t + e] : 0.0f);
+                    for (int e = 0; e < 4; ++e) v[e] = (j + e < ns && r < nrhs) ? qb[4 * t + e] : (__bf16)0.0f;
                     *reinterpret_cast<bf16x4 *>(&sQt[r * kQtStride + j]) = v;
                 }
             } else {
+                double qv[QPT];
 #pragma unroll
                 for (int t = 0; t < QPT; ++t) qv[t] = O.xt[(size_t)colP[j0 + t * G] * nrhs + rr];
 #pragma unroll
@@ -3093,6 +3098,7 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
             default: e = launch_mrhs_lp_k<2, false>(T, O, y, nrhs, near, nfar, st); break;
             }
         } else {
+            if (near && !O.xtb) return hipErrorInvalidValue;  // the BF16 charges are staged from xtb
             // BF16 tile cache: the first nearfield launch writes the tiles, later ones read them (not
             // inside a graph capture, whose launches run later than the host flag would say)
             DevOp Oc = O;
