@@ -90,17 +90,27 @@ def cpu_baseline(w, X, b, x, budget_leaves: int):
     }
 
 
-COUNTERS_FILE = os.path.join(ROOT, "profiles", "p2p_sym_n1m_d20_counters.txt")
+# committed counter summaries with the calibrated HBM bytes of the nearfield kernel, by
+# (workload, N, nrhs, precision, stored tiles)
+COUNTERS_FILES = {
+    ("n1m_d20", 1_000_000, 1, "fp64", False): os.path.join(ROOT, "profiles", "p2p_sym_n1m_d20_counters.txt"),
+    ("n1m_d20", 1_000_000, 32, "bf16", True): os.path.join(ROOT, "profiles", "p2p_mrhs_lp_n1m_d20_r32_bf16_cached.txt"),
+}
 
 
-def recorded_traffic(workload: str, n: int, nrhs: int, precision: str):
+def counters_file(workload: str, n: int, nrhs: int, precision: str, cached: bool = False):
+    return COUNTERS_FILES.get((workload, n, nrhs, precision, bool(cached)))
+
+
+def recorded_traffic(workload: str, n: int, nrhs: int, precision: str, cached: bool = False):
     """HBM bytes per nearfield launch (FETCH_SIZE + WRITE_SIZE, calibrated) from the committed
-    counter summary, or None unless it was taken on this workload and on the kernel source as it
-    is now (its sha256 is recorded in the summary)."""
-    if (workload, n, nrhs, precision) != ("n1m_d20", 1_000_000, 1, "fp64") or not os.path.exists(COUNTERS_FILE):
+    counter summary, or None unless it was taken on this workload and mode and on the kernel source
+    as it is now (its sha256 is recorded in the summary)."""
+    path = counters_file(workload, n, nrhs, precision, cached)
+    if path is None or not os.path.exists(path):
         return None
     import hashlib
-    text = open(COUNTERS_FILE).read()
+    text = open(path).read()
     src = os.path.join(ROOT, "paper_2402_09531_amd", "csrc", "kernels.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
     if f"sha256 (paper_2402_09531_amd/csrc/kernels.hip): {sha}" not in text:
@@ -807,7 +817,7 @@ def bench_solve(args):
                 f"({time.perf_counter() - t_start[0]:.1f} s)")
 
     op = dw.fmm_create(tree, w.kernel, w.ell, w.q, precision=args.precision, max_nrhs=nrhs, check_every=16,
-                       progress=progress)
+                       progress=progress, cache_near=args.cache_near)
     fd = torch.from_numpy(f).to(dev).contiguous()
     ad = torch.zeros_like(fd)
     torch.cuda.synchronize()
@@ -822,7 +832,8 @@ def bench_solve(args):
            "dtype": "f64" if args.precision == "fp64" else args.precision + " inner, f64 outer",
            "data": "synthetic",
            "config": {"workload": w.name, "N": w.n, "d": w.d, "kernel": w.kernel, "q": w.q, "nrhs": nrhs,
-                      "lambda": lam, "rtol": 1e-8, "max_iter": args.solve_max_iter, "precision": args.precision},
+                      "lambda": lam, "rtol": 1e-8, "max_iter": args.solve_max_iter, "precision": args.precision,
+                      "cache_near": bool(args.cache_near)},
            "time_s": round(t, 3), "iterations": iters, "ms_per_iteration": round(1e3 * t / max(iters, 1), 3),
            "columns": [{"iters": i["iters"], "refine_steps": i["refine_steps"], "status": names.get(i["status"], i["status"]),
                         "neg_curvature_steps": i["neg_curvature_steps"], "rel_res_true": i["rel_res_true"]}
@@ -1145,7 +1156,7 @@ def main():
         # writing call is a warm-up step)
         tile_bytes = (dw.op_bytes_for(tree, w.q, precision=args.precision, max_nrhs=nrhs, cache_near=True) -
                       dw.op_bytes_for(tree, w.q, precision=args.precision, max_nrhs=nrhs))
-        nbytes = tile_bytes + 2 * 8 * n * nrhs
+        nbytes = tile_bytes + (2 + 8) * n * nrhs  # + the BF16 charges read and the FP64 sums written once
         gbs = nbytes / (p2p_avg * 1e-3) / 1e9
         result["config"]["cache_near"] = True
         result["roofline"] = {"kernel": "p2p (nearfield, stored BF16 tiles)", "bound": "hbm", "achieved": round(gbs, 1),
@@ -1166,10 +1177,11 @@ def main():
         err = float(torch.linalg.norm(yd - y64) / torch.linalg.norm(y64))
         result["rel_err_vs_fp64"] = err
         log(f"[bench] {args.precision} result: relative error {err:.3e} against the FP64 matvec")
-    traffic = recorded_traffic(w.name, n, nrhs, args.precision)
-    if traffic is not None:
+    traffic = recorded_traffic(w.name, n, nrhs, args.precision, args.cache_near)
+    if traffic is not None and result["roofline"] is not None:
         result["roofline"]["traffic"] = traffic
-        result["roofline"]["traffic_source"] = os.path.relpath(COUNTERS_FILE, ROOT)
+        result["roofline"]["traffic_source"] = os.path.relpath(
+            counters_file(w.name, n, nrhs, args.precision, args.cache_near), ROOT)
     if not args.no_cpu_baseline:
         log("[bench] timing the CPU oracle on a bounded sample")
         result["cpu_baseline"] = cpu_baseline(w, X, b, x, args.cpu_leaves)
