@@ -187,7 +187,8 @@ dwfmm_status dwfmm_fmm_matvec(dwfmm_op op, const double *x, double *y, int32_t n
 /* Allocation-free matvec, for callers that cannot allocate device memory: code under HIP
  * graph capture, tight serving loops, harnesses that forbid hipMalloc.  Computes the same
  * y = K~ x as dwfmm_fmm_matvec (same kernels, same bits) but takes the call's workspace --
- * charges in tree order, moments and locals, nearfield row and column sums -- from one static
+ * charges in tree order (and their BF16 copy with several rhs), moments and locals, nearfield
+ * row and column sums -- from one static
  * device array of DWFMM_STATIC_SCRATCH_BYTES that the library holds on each GPU it runs on
  * until the process ends, instead of the operator's buffers; it allocates nothing (the first
  * call on a device looks the array's address up once).  1 <= nrhs <= 32, independent of the
@@ -196,8 +197,9 @@ dwfmm_status dwfmm_fmm_matvec(dwfmm_op op, const double *x, double *y, int32_t n
  * (on different streams or host threads) race and must be ordered by the caller; nothing is
  * carried from one call to the next.  Asynchronous on `stream`.
  * The workspace is 8 N nrhs + 16 ncl n_x nrhs bytes, plus 1024 (nleaf + owned blocks) with one
- * rhs, each part rounded up to 256 bytes (ncl clusters, nleaf leaves, owned blocks as reported
- * by dwfmm_tree_info / dwfmm_tree_stats).
+ * rhs or 2 N nrhs with several, each part rounded up to 256 bytes (ncl clusters, nleaf leaves,
+ * owned blocks as reported by dwfmm_tree_info / dwfmm_tree_stats).  An operator's stored
+ * nearfield tiles (cache_near) are its own memory and are used as by dwfmm_fmm_matvec.
  * Errors: E_INVALID (NULL or equal x/y, nrhs out of range, another device current, or a
  * workspace above DWFMM_STATIC_SCRATCH_BYTES, with the sizes in the message), E_HIP.       */
 #define DWFMM_STATIC_SCRATCH_BYTES ((size_t)64 << 20)

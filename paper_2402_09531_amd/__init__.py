@@ -373,6 +373,8 @@ def static_scratch_bytes(op: Op, nrhs: int) -> int:
     need = a(8 * t.n * nrhs) + 2 * a(8 * t.ncl * op.nx * nrhs)
     if nrhs == 1:
         need += a(1024 * t.nleaf) + a(1024 * t.stats()[2])
+    else:
+        need += a(2 * t.n * nrhs)  # the charges in BF16
     return need
 
 
