@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 METRIC = "FMM matvec Mpoints/s at N=1M,d=20; served solves/s + p99 latency vs plain"
 PEAK_FP64_VALU_TFLOPS = 78.6      # 256 CU x 2.4 GHz x 128 FP64 flop/clk
 PEAK_FP32_TFLOPS = 157.3          # published FP32 vector / dense FP32 matrix peak
-PEAK_BF16_TFLOPS = 2500.0         # published dense BF16 MFMA peak
+PEAK_BF16_TFLOPS = 2500.0         # published dense BF16 (and FP16) MFMA peak
 PEAK_HBM_GBS = 8000.0             # published HBM3E bandwidth
 KERNEL_FLOPS = {"gaussian": 2, "matern32": 6, "exponential": 3, "poly": 4}
 
@@ -1111,15 +1111,20 @@ def main():
     p2p_flops = E_eval * (3 * w.d + KERNEL_FLOPS[w.kernel]) + EN * 2 * nrhs
     achieved = p2p_flops / (p2p_avg * 1e-3) / 1e12
     # FP64 mode: FP64 vector/matrix peak; FP32 mode: all of it is FP32 (MFMA + VALU), the FP32 peak
-    # bounds it; BF16 mode: the distance and kernel work is FP32 and the apply runs on BF16 MFMA, so
-    # the bound is the time the two parts take at their own peaks
+    # bounds it; BF16 mode: the bound is the time each part takes at the peak of the unit it runs
+    # on.  With several rhs (d >= 5) the distances run on FP16 MFMA as three products of split
+    # operands (2d flops each per entry), the kernel value on the FP32 VALU, and the apply on BF16
+    # MFMA; with one rhs (the FP32 kernels) or d < 5 distances and kernel values are FP32.
     if args.precision == "fp64":
         peak = PEAK_FP64_VALU_TFLOPS
     elif args.precision == "fp32":
         peak = PEAK_FP32_TFLOPS
     else:
-        f32_part, bf16_part = E_eval * (3 * w.d + KERNEL_FLOPS[w.kernel]), EN * 2 * nrhs
-        peak = round(p2p_flops / (f32_part / PEAK_FP32_TFLOPS + bf16_part / PEAK_BF16_TFLOPS), 3)
+        f16_gram = nrhs > 1 and w.d >= 5
+        t_eval = (3 * 2 * w.d / PEAK_BF16_TFLOPS + KERNEL_FLOPS[w.kernel] / PEAK_FP32_TFLOPS if f16_gram else
+                  (3 * w.d + KERNEL_FLOPS[w.kernel]) / PEAK_FP32_TFLOPS)
+        t_apply = 2 * nrhs / (PEAK_BF16_TFLOPS if nrhs > 1 else PEAK_FP32_TFLOPS)
+        peak = round(p2p_flops / (E_eval * t_eval + EN * t_apply), 3)
     result = {
         "metric": METRIC,
         "value": round(value, 3),

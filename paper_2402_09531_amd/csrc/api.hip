@@ -621,6 +621,13 @@ extern "C" dwfmm_status dwfmm_fmm_create(dwfmm_tree tree, dwfmm_kernel kernel, d
     D.ell = kernel.ell;
     D.gauss_split = kernel.kind == DWFMM_GAUSSIAN && tree->near_reach2 / kernel.ell <= 600.0;
     D.gauss_split32 = kernel.kind == DWFMM_GAUSSIAN && tree->near_reach2 / kernel.ell <= 80.0;
+    {
+        // every |x - c| and |y - c| of a nearfield entry is at most the reach (c the target leaf's midpoint)
+        const double reach = std::sqrt(tree->near_reach2);
+        // (the exponent held to [-60, 60] so that the kernel's 1 / hscale^2 stays a finite float)
+        const int e = reach > 0.0 && std::isfinite(reach) ? std::clamp((int)std::ceil(std::log2(reach)), -60, 60) : 0;
+        D.hscale = (float)std::ldexp(1.0, -e);
+    }
     D.matern_in_range = kernel.kind == DWFMM_MATERN32 &&
                         std::sqrt(tree->near_reach2) * (1.7320508075688772 * 1.4426950408889634) / kernel.ell <= 1000.0;
     D.nx = nx;

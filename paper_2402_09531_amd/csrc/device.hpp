@@ -62,6 +62,10 @@ struct DevOp {
     // Matern only: sqrt(3) max|x - y| / ell log2(e) <= 1000 over the nearfield (from the host's reach
     // bound), so the FP64 nearfield's 2^-s log2(e) needs no underflow clamp
     int matern_in_range;
+    // Power of two 2^-e with every centred nearfield coordinate (a point minus its target leaf's
+    // midpoint) at most 1 in magnitude after scaling (e from the host's reach bound): the BF16
+    // several-rhs nearfield forms its FP16 Gram operands from the scaled coordinates
+    float hscale;
     // Tile cache of the BF16 several-rhs nearfield (NULL when off): column tile t of target leaf l
     // (16 stream columns x 8 row tiles of 16 targets, 64 lanes x 4 BF16 each, 4 KiB) sits at
     // near_tiles + (near_tile_off[l] + t) * 512; near_filled points at a host flag set once a

@@ -1856,6 +1856,19 @@ typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
 // 4 li + 2 lg mod 64, on 64 different banks; with 132-element rows the two lane groups overlapped
 // (2 li + 2 lg) and every charge read took two passes
 constexpr int kQtStride = kSymLeaf + 8;
+// BF16 mode's distances: each centred coordinate v (scaled by the operator's power of two, so
+// |v| <= 1) is split into FP16 parts h = fp16(v) and l = fp16(2^11 (v - h)), and the Gram sum is
+// formed on v_mfma_f32_16x16x32_f16 (FP32 accumulation) as sum h_x h_y + 2^-11 sum (h_x l_y + l_x h_y):
+// three MFMAs of 16 cycles per 16 x 16 tile for up to 32 dimensions, against d / 4 of 32 cycles on
+// v_mfma_f32_16x16x4f32.  The dropped terms are about 2^-22 |x_k y_k| each, far below the BF16
+// rounding of the kernel values; the low parts carry the 2^11 so that they stay in FP16's normal
+// range.  Sources sit in LDS in rows of kHS halves, the 32 high parts then the 32 low parts: the
+// 16-byte read of lane (li, lg) starts at word 36 li + 4 lg, and the 16 lanes of one lg cover the
+// 64 banks once.
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+constexpr int kHS = 72;
+template <int DK, bool BF16>
+constexpr bool gram_f16() { return BF16 && DK >= 8; }
 // FP32 charges stored [source][rhs]; rows of 16 RB + 4 floats put consecutive lane groups on
 // the two halves of the banks
 template <int RB>
@@ -1903,21 +1916,32 @@ __device__ __forceinline__ void apply_tiles(const uint2 (&pre)[8][2], flt4 (&Y)[
 
 // CM (BF16 only): 0 compute the kernel tiles, 1 compute them and also write them to `tiles`
 // (column tile ct of this call at tiles + ct * 512, at most `tcap` column tiles).
+// FP16 Gram (gram_f16): Th, Tl the targets' high and low parts (lane (li, lg): target 16 rt + li,
+// dimensions 8 lg ... 8 lg + 7), sXh the sources' rows; the exponent (split Gaussian) or r^2 is
+// then gA G_hh + gB G_cross + (snv, or |x|^2 + |y|^2).
 template <int KIND, int DK, int RB, bool BF16, bool DIAG, int CM = 0>
 __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], const float (&tn)[2], flt4 (&Y)[2][RB],
                                               const float *sX, const float *sN, const float *sQ, const __bf16 *sQt,
                                               int ns, int ntiles, int w, int li, int lg, float inv_ell,
-                                              uint2 *tiles = nullptr, int64_t tcap = 0)
+                                              const f16x8 (&Th)[2], const f16x8 (&Tl)[2], const _Float16 *sXh,
+                                              float gA, float gB, uint2 *tiles = nullptr, int64_t tcap = 0)
 {
     static_assert(CM == 0 || (CM == 1 && BF16), "the tile cache holds BF16 tiles");
     constexpr int NKC = DK / 4;
+    constexpr bool kH = gram_f16<DK, BF16>();
     const int rt[2] = {w, w + 4};
     [[maybe_unused]] const int lane = li + 16 * lg;
     const int nct = (ns + 15) / 16;
     for (int ct = 0; ct < nct; ++ct) {
-        float Af[NKC], snv[4];
+        float Af[kH ? 1 : NKC], snv[4];
+        f16x8 Ah, Al;
+        if constexpr (kH) {
+            Ah = *reinterpret_cast<const f16x8 *>(&sXh[(16 * ct + li) * kHS + 8 * lg]);
+            Al = *reinterpret_cast<const f16x8 *>(&sXh[(16 * ct + li) * kHS + 32 + 8 * lg]);
+        } else {
 #pragma unroll
-        for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSX32 + 16 * ct + li];
+            for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSX32 + 16 * ct + li];
+        }
 #pragma unroll
         for (int e = 0; e < 4; ++e) snv[e] = sN[16 * ct + 4 * lg + e];
         // the charge operands of this column tile serve both row tiles
@@ -1932,20 +1956,29 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
             if (rt[u] >= ntiles) continue;
             // split Gaussian as in the FP64 kernel: the chain starts from the sources' base-2 column
             // factors and delivers the entry's exponent but for the row factor
-            flt4 G;
-            if constexpr (KIND == kGaussSplit)
-                G = flt4{snv[0], snv[1], snv[2], snv[3]};
-            else
+            flt4 G, C;
+            if constexpr (kH) {
                 G = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+                C = flt4{0.0f, 0.0f, 0.0f, 0.0f};
+                C = __builtin_amdgcn_mfma_f32_16x16x32_f16(Al, Th[u], C, 0, 0, 0);
+                C = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Tl[u], C, 0, 0, 0);
+                G = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Th[u], G, 0, 0, 0);
+            } else {
+                if constexpr (KIND == kGaussSplit)
+                    G = flt4{snv[0], snv[1], snv[2], snv[3]};
+                else
+                    G = flt4{0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-            for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[kc], Bt[u][kc], G, 0, 0, 0);
+                for (int kc = 0; kc < NKC; ++kc) G = __builtin_amdgcn_mfma_f32_16x16x4f32(Af[kc], Bt[u][kc], G, 0, 0, 0);
+            }
             float Kv[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if constexpr (KIND == kGaussSplit) {
-                    Kv[e] = __builtin_amdgcn_exp2f(G[e]);
+                    Kv[e] = __builtin_amdgcn_exp2f(kH ? fmaf(gA, G[e], fmaf(gB, C[e], snv[e])) : G[e]);
                 } else {
-                    float r2 = fmaxf(fmaf(-2.0f, G[e], tn[u] + snv[e]), 0.0f);
+                    float r2 = kH ? fmaf(gA, G[e], fmaf(gB, C[e], tn[u] + snv[e])) : fmaf(-2.0f, G[e], tn[u] + snv[e]);
+                    r2 = fmaxf(r2, 0.0f);
                     if constexpr (DIAG) {
                         if (16 * rt[u] + li == 16 * ct + 4 * lg + e) r2 = 0.0f;
                     }
@@ -1976,7 +2009,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
                                                           int do_near, int do_far)
 {
     constexpr int NKC = DK / 4;
-    __shared__ float sX[DK * kSX32];
+    constexpr bool kH = gram_f16<DK, BF16>();
+    // (reading stored tiles stages no coordinates)
+    __shared__ float sX[kH || CM == 2 ? 1 : DK * kSX32];
+    __shared__ __attribute__((aligned(16))) _Float16 sXh[kH && CM != 2 ? kSymLeaf * kHS : 8];
     __shared__ float sN[kSymLeaf];
     __shared__ float sQ[BF16 ? 1 : kSymLeaf * q_stride32<RB>()];
     __shared__ __attribute__((aligned(16))) __bf16 sQt[BF16 ? 16 * RB * kQtStride : 8];
@@ -2007,7 +2043,12 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
     __syncthreads();
     const int rt[2] = {w, w + 4};
     float Bt[2][NKC], tn[2];
+    f16x8 Th[2], Tl[2];
     flt4 Y[2][RB];
+    // FP16 Gram: the coordinates' power-of-two scale and the factors of its two sums
+    const float hs = O.hscale;
+    const float gA = kSplit ? (float)(2.0 * 1.4426950408889634 / O.ell) / (hs * hs) : -2.0f / (hs * hs);
+    const float gB = gA * 0x1p-11f;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int i = 16 * rt[u] + li;
@@ -2020,11 +2061,22 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
             s = fmaf(v, v, s);
         }
         tn[u] = s;
-        const double csc = kSplit ? 2.0 * 1.4426950408889634 / O.ell : 1.0;
+        if constexpr (kH) {
 #pragma unroll
-        for (int kc = 0; kc < NKC; ++kc) {
-            const double v = T.Xs[(size_t)(4 * kc + lg) * n + ii] - cen[4 * kc + lg];
-            Bt[u][kc] = (float)(kSplit ? csc * v : v);
+            for (int e = 0; e < 8; ++e) {
+                const int k = 8 * lg + e;
+                const float v = k < DK ? (float)(T.Xs[(size_t)k * n + ii] - cen[k]) * hs : 0.0f;
+                const _Float16 h = (_Float16)v;
+                Th[u][e] = h;
+                Tl[u][e] = (_Float16)((v - (float)h) * 2048.0f);
+            }
+        } else {
+            const double csc = kSplit ? 2.0 * 1.4426950408889634 / O.ell : 1.0;
+#pragma unroll
+            for (int kc = 0; kc < NKC; ++kc) {
+                const double v = T.Xs[(size_t)(4 * kc + lg) * n + ii] - cen[4 * kc + lg];
+                Bt[u][kc] = (float)(kSplit ? csc * v : v);
+            }
         }
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb) Y[u][rb] = flt4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -2052,7 +2104,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
         __syncthreads();
         // sid: the 128 threads that stage the coordinates (waves 0-1 or 2-3, alternating by chunk)
         auto stage_chunk = [&](int ns, int sid) {  // columns of colP[0..kSymLeaf), the first ns real
-            if (CM != 2 && sid < kSymLeaf) {  // (the coordinates are not needed to read stored tiles)
+            if constexpr (CM != 2) if (sid < kSymLeaf) {  // (the coordinates are not needed to read stored tiles)
                 const int j = sid;
                 const bool ok = j < ns;
                 const int jj = colP[j];
@@ -2063,8 +2115,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
 #pragma unroll
                 for (int k = 0; k < DK; ++k) {
                     const float v = ok ? (float)(xv[k] - cen[k]) : 0.0f;
-                    sX[k * kSX32 + j] = v;
+                    if constexpr (!kH) sX[k * kSX32 + j] = v;
                     s = fmaf(v, v, s);
+                }
+                if constexpr (kH) {
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        f16x8 hv, lv;
+#pragma unroll
+                        for (int e = 0; e < 8; ++e) {
+                            const int k = 8 * q + e;
+                            const float v = (k < DK && ok) ? (float)(xv[k < DK ? k : 0] - cen[k < DK ? k : 0]) * hs : 0.0f;
+                            const _Float16 h = (_Float16)v;
+                            hv[e] = h;
+                            lv[e] = (_Float16)((v - (float)h) * 2048.0f);
+                        }
+                        *reinterpret_cast<f16x8 *>(&sXh[j * kHS + 8 * q]) = hv;
+                        *reinterpret_cast<f16x8 *>(&sXh[j * kHS + 32 + 8 * q]) = lv;
+                    }
                 }
                 // split Gaussian: the base-2 logarithm of the column factor exp(-|y - c|^2 / ell)
                 sN[j] = kSplit ? s * (inv_ell * -1.4426950408889634f) : s;
@@ -2115,7 +2183,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
                 apply_tiles<RB>(pre, Y, sQt, nt, ntiles, w, li, lg);
             } else {
                 mrhs_block_lp<KIND, DK, RB, BF16, true, CM>(Bt, tn, Y, sX, sN, sQ, sQt, nt, ntiles, w, li, lg, inv_ell,
-                                                           ltiles + tb * 512, lcount - tb);
+                                                           Th, Tl, sXh, gA, gB, ltiles + tb * 512, lcount - tb);
             }
             tb += (nt + 15) / 16;
         }
@@ -2169,7 +2237,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 
                     apply_tiles<RB>(pre, Y, sQt, ns, ntiles, w, li, lg);
                 } else {
                     mrhs_block_lp<KIND, DK, RB, BF16, false, CM>(Bt, tn, Y, sX, sN, sQ, sQt, ns, ntiles, w, li, lg,
-                                                                inv_ell, ltiles + tb * 512, lcount - tb);
+                                                                inv_ell, Th, Tl, sXh, gA, gB, ltiles + tb * 512,
+                                                                lcount - tb);
                 }
                 tb += (ns + 15) / 16;
             }
