@@ -2004,8 +2004,11 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
     }
 }
 
+// Four waves per SIMD at d <= 20 (at most 128 VGPRs); reading stored tiles stages no coordinates,
+// fits in 96 VGPRs and runs five, with more tile loads in flight (computing kernels at five waves
+// spill in the staging and slow the farfield that runs beside them).
 template <int KIND, int DK, int RB, bool BF16, int CM>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(DK <= 20 ? 4 : 1, 8))) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && DK <= 20 ? 5 : DK <= 20 ? 4 : 1, 8))) void p2p_mrhs_lp_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs,
                                                           int do_near, int do_far)
 {
     constexpr int NKC = DK / 4;
