@@ -171,3 +171,53 @@ def test_reduced_precision_coupling_several_rhs(orc, case):
             f"largest entry error / row scale {er:.3e}")
         assert e <= FAR_NORM_BOUND[prec] and er <= FAR_ROW_BOUND[prec]
     assert not np.array_equal(ys["bf16"], ys["fp32"])  # the BF16 products really ran
+
+
+# kernel matrices unchanged when the points scale by s and the length scale with them
+SCALED_ELL = {"gaussian": lambda ell, s: ell * s * s, "matern32": lambda ell, s: ell * s,
+              "exponential": lambda ell, s: ell * s}
+SCALE_CASES = [
+    # name, n, d, r, kernel, ell, q, leaf, eta, nrhs
+    ("d20_gauss_32rhs", 12000, 20, 3.0, "gaussian", 0.5, 6, 128, 0.8, 32),
+    ("d10_matern_5rhs", 8000, 10, 2.0, "matern32", 1.0, 5, 128, 0.8, 5),
+]
+
+
+@pytest.mark.parametrize("s", [1e4, 1e-5])
+@pytest.mark.parametrize("case", SCALE_CASES, ids=[c[0] for c in SCALE_CASES])
+def test_bf16_several_rhs_point_scale(case, s):
+    """The BF16 several-rhs nearfield forms its distances from FP16 parts of the centred coordinates
+    after a power-of-two scale taken from the tree's reach: points scaled by 1e4 or 1e-5 (and the
+    length scale with them, so that the kernel matrix is the same) keep the BF16 error of the
+    unscaled problem against the FP64 result, and the FP64 results agree across the scales."""
+    name, n, d, r, kind, ell, q, leaf, eta, nrhs = case
+    rng = np.random.default_rng(11 + n)
+    X = W.points(n, d, r, n, rng)
+    b = W.dim_weights(d, r)
+    x = torch.from_numpy(rng.standard_normal((n, nrhs))).cuda()
+    out = {}
+    for sc in (1.0, s):
+        tree = dw.build_tree(torch.from_numpy(X * sc).cuda(), b * sc, leaf, eta)
+        op = dw.fmm_create(tree, kind, SCALED_ELL[kind](ell, sc), q, max_nrhs=nrhs)
+        for prec in ("fp64", "bf16"):
+            y = torch.empty_like(x)
+            dw.fmm_matvec(op, x, y, precision=prec)
+            torch.cuda.synchronize()
+            out[(sc, prec)] = y.cpu().numpy()
+        ya = torch.empty_like(x)
+        dw.fmm_matvec(op, x.abs(), ya, precision="fp64")
+        torch.cuda.synchronize()
+        out[(sc, "abs")] = ya.cpu().numpy()
+    e64 = rel(out[(s, "fp64")], out[(1.0, "fp64")])
+    errs = {}
+    for sc in (1.0, s):
+        y, y64, ya = out[(sc, "bf16")], out[(sc, "fp64")], out[(sc, "abs")]
+        errs[sc] = (rel(y, y64), float(np.max(np.abs(y - y64) / ya)))
+    say(f"[scale {s:g}] {name}: FP64 across scales {e64:.2e}; BF16 vs FP64 unscaled {errs[1.0][0]:.3e} "
+        f"(rows {errs[1.0][1]:.3e}), scaled {errs[s][0]:.3e} (rows {errs[s][1]:.3e})")
+    assert e64 <= 1e-10
+    for sc in (1.0, s):
+        assert errs[sc][0] <= NORM_BOUND[("bf16", True)]
+        assert errs[sc][1] <= ROW_BOUND[("bf16", True)]
+    # the scaled problem's BF16 error is that of the unscaled one, up to rounding differences
+    assert errs[s][0] <= 1.5 * errs[1.0][0]
