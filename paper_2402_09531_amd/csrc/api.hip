@@ -84,7 +84,8 @@ int pad_dim(int d) { return d <= 32 ? (d + 3) / 4 * 4 : (d + 7) / 8 * 8; }
 // Host arrays of a tree built but not yet uploaded (the tree's device arrays, in upload order).
 struct TreeStage {
     std::vector<double> Xs, clo, csc, coff, center;
-    std::vector<int32_t> nsrc_local, nptr_leaf, own_ptr, own_src, inc_ptr, inc_blk, leaf_order, near_order;
+    std::vector<int32_t> nsrc_local, nptr_leaf, own_ptr, own_src, inc_ptr, inc_blk, leaf_order, near_order,
+        near_order_seq;
     int max_leaf = 0;
 };
 
@@ -186,8 +187,10 @@ extern "C" dwfmm_status dwfmm_build_tree_ex(const double *points, int64_t n, int
 // Launch order of the leaves of a nearfield kernel with per-leaf work w: workgroup q runs on XCD
 // q mod 8, so the leaves are cut into 8 contiguous segments of equal work, segment k dealt to XCD
 // k (each XCD's L2 then holds the sources of one region of the tree), the costliest leaves first
-// within a segment (it ends on short ones); -1 pads the shorter segments.
-static std::vector<int32_t> xcd_order(const std::vector<double> &w)
+// within a segment (it ends on short ones) or, with by_cost false, in leaf order (neighbouring
+// leaves, which list mostly the same sources, then run at the same time); -1 pads the shorter
+// segments.
+static std::vector<int32_t> xcd_order(const std::vector<double> &w, bool by_cost = true)
 {
     const int64_t nl = (int64_t)w.size();
     double total = 0.0;
@@ -205,7 +208,7 @@ static std::vector<int32_t> xcd_order(const std::vector<double> &w)
     for (int k = 0; k < 8; ++k) {
         std::vector<int32_t> seg;
         for (int64_t j = cut[k]; j < cut[k + 1]; ++j) seg.push_back((int32_t)j);
-        std::stable_sort(seg.begin(), seg.end(), [&](int32_t a, int32_t b) { return w[a] > w[b]; });
+        if (by_cost) std::stable_sort(seg.begin(), seg.end(), [&](int32_t a, int32_t b) { return w[a] > w[b]; });
         for (size_t j = 0; j < seg.size(); ++j) order[8 * j + k] = seg[j];
     }
     return order;
@@ -307,6 +310,7 @@ static dwfmm_status tree_host(const std::vector<double> &pts, int64_t n, int32_t
         t->leaf_work = lw;
         S.leaf_order = xcd_order(lw);
         S.near_order = xcd_order(nw);
+        S.near_order_seq = xcd_order(nw, false);
     }
     std::vector<double> &center = S.center, rad(H.nleaf, 0.0);
     center.assign((size_t)H.nleaf * dp, 0.0);
@@ -344,7 +348,8 @@ static size_t tree_stage_bytes(const dwfmm_tree t)
     size_t b = sizeof(double) * (S.Xs.size() + S.clo.size() + S.csc.size() + S.coff.size() + S.center.size());
     b += sizeof(int32_t) * (H.perm.size() + H.begin.size() + H.end.size() + H.Fptr.size() + H.Fsrc.size() +
                             S.nptr_leaf.size() + S.nsrc_local.size() + S.own_ptr.size() + S.own_src.size() +
-                            S.inc_ptr.size() + S.inc_blk.size() + S.leaf_order.size() + S.near_order.size());
+                            S.inc_ptr.size() + S.inc_blk.size() + S.leaf_order.size() + S.near_order.size() +
+                            S.near_order_seq.size());
     return b;
 }
 
@@ -357,10 +362,11 @@ static dwfmm_status tree_upload(dwfmm_tree t, hipStream_t st)
     auto up = [&](auto **dst, const auto &v) { return t->arena.upload(dst, v, st); };
     hipError_t e = hipSuccess;
     double *dXs;
-    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs, *dop, *dos, *dip, *dib, *dlo, *dno;
+    int32_t *dperm, *dcb, *dce, *dFp, *dFs, *dNp, *dNs, *dop, *dos, *dip, *dib, *dlo, *dno, *dnq;
     double *dcen;
     if ((e = up(&dXs, S.Xs)) != hipSuccess || (e = up(&dperm, H.perm)) != hipSuccess ||
         (e = up(&dlo, S.leaf_order)) != hipSuccess || (e = up(&dno, S.near_order)) != hipSuccess ||
+        (e = up(&dnq, S.near_order_seq)) != hipSuccess ||
         (e = up(&dcb, H.begin)) != hipSuccess || (e = up(&dce, H.end)) != hipSuccess ||
         (e = up(&dFp, H.Fptr)) != hipSuccess || (e = up(&dFs, H.Fsrc)) != hipSuccess ||
         (e = up(&dNp, S.nptr_leaf)) != hipSuccess || (e = up(&dNs, S.nsrc_local)) != hipSuccess ||
@@ -399,6 +405,7 @@ static dwfmm_status tree_upload(dwfmm_tree t, hipStream_t st)
     D.leaf_order = dlo;
     D.n_order = (int)S.leaf_order.size();
     D.near_order = dno;
+    D.near_order_seq = dnq;
     D.n_near_order = (int)S.near_order.size();
     t->stage.reset();
     return DWFMM_OK;

@@ -30,12 +30,14 @@ struct DevTree {
     const double *center;         // [nleaf][dpad] leaf box midpoints (coordinate shift)
     // Order in which the symmetric nearfield launches take the owner leaves: workgroup q runs on
     // XCD q % 8, and XCD k gets the k-th of 8 contiguous leaf segments of equal nearfield work,
-    // in leaf order; -1 pads the shorter segments.  NULL for trees without a symmetric nearfield.
+    // costliest leaf first; -1 pads the shorter segments.  NULL for trees without a symmetric nearfield.
     const int32_t *leaf_order;
     int n_order;
     // The same for the several-rhs nearfield, which sweeps each target leaf's whole nearfield list:
-    // segments of equal list entries, costliest leaf first.
+    // segments of equal list entries, costliest leaf first; near_order_seq has the same segments in
+    // leaf order (the launches that read stored BF16 tiles, whose sources then stay in L2).
     const int32_t *near_order;
+    const int32_t *near_order_seq;
     int n_near_order;
 };
 

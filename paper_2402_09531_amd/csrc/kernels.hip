@@ -1886,8 +1886,11 @@ __device__ __forceinline__ void load_tiles(uint2 (&pre)[8][2], const uint2 *tile
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             const int rt = w + 4 * u;
-            pre[ct][u] = ct < nct && ct < tcap && rt < ntiles ? tiles[(size_t)ct * 512 + rt * 64 + lane]
-                                                              : make_uint2(0u, 0u);
+            // streamed once per apply: non-temporal, so that they do not push the charges out of L2
+            pre[ct][u] = ct < nct && ct < tcap && rt < ntiles
+                             ? __builtin_bit_cast(uint2, __builtin_nontemporal_load(reinterpret_cast<const uint64_t *>(
+                                                             tiles + (size_t)ct * 512 + rt * 64 + lane)))
+                             : make_uint2(0u, 0u);
         }
 }
 
@@ -1988,7 +1991,9 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
             if constexpr (BF16) {
                 const bf16x4 Ka = {(__bf16)Kv[0], (__bf16)Kv[1], (__bf16)Kv[2], (__bf16)Kv[3]};
                 if constexpr (CM == 1) {
-                    if (ct < tcap) tiles[(size_t)ct * 512 + rt[u] * 64 + lane] = __builtin_bit_cast(uint2, Ka);
+                    if (ct < tcap)
+                        __builtin_nontemporal_store(__builtin_bit_cast(uint64_t, Ka),
+                                                    reinterpret_cast<uint64_t *>(tiles + (size_t)ct * 512 + rt[u] * 64 + lane));
                 }
 #pragma unroll
                 for (int rb = 0; rb < RB; ++rb) Y[u][rb] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(Ka, Qb[rb], Y[u][rb], 0, 0, 0);
@@ -2024,7 +2029,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
     constexpr bool kSplit = KIND == kGaussSplit;
     static_assert(CM == 0 || BF16, "the tile cache holds BF16 tiles");
     __shared__ float tF[kSplit ? kSymLeaf : 1];  // split Gaussian: row factors exp(-|x - c|^2 / ell)
-    const int l = T.near_order[blockIdx.x];
+    const int l = (CM == 2 ? T.near_order_seq : T.near_order)[blockIdx.x];
     if (l < 0) return;  // padding of a shorter XCD segment
     const int c = T.leaf_first + l;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
