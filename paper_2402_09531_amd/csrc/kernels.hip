@@ -1851,6 +1851,18 @@ hipError_t launch_sym32_k(const DevTree &T, const DevOp &O, hipStream_t st)
 // so Y(16 x 16 rhs) += K Q is one MFMA with FP32 accumulation.  FP32: element e is the A
 // operand of chunk e (sources 4g + e) of four v_mfma_f32_16x16x4f32.
 typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef float flt2v __attribute__((ext_vector_type(2)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+// Four floats rounded to BF16 (to nearest even) by two v_cvt_pk_bf16_f32: the pairs are joined
+// through their 32-bit patterns (built element by element, a vector that feeds an MFMA compiles
+// to four one-value conversions and two permutes).
+__device__ __forceinline__ bf16x4 to_bf16x4(float a, float b, float c, float d)
+{
+    const uint32_t lo = __builtin_bit_cast(uint32_t, __builtin_convertvector(flt2v{a, b}, bf16x2));
+    const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(flt2v{c, d}, bf16x2));
+    return __builtin_bit_cast(bf16x4, u32x2{lo, hi});
+}
 // bf16 charges stored [rhs][source] in rows of 136 elements (68 words): an 8-byte read of lane
 // (li, lg) starts at word 68 li + 2 lg (+ a constant) and the 32 lanes lg < 2 (lg >= 2) start at
 // 4 li + 2 lg mod 64, on 64 different banks; with 132-element rows the two lane groups overlapped
@@ -1989,7 +2001,7 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
                 }
             }
             if constexpr (BF16) {
-                const bf16x4 Ka = {(__bf16)Kv[0], (__bf16)Kv[1], (__bf16)Kv[2], (__bf16)Kv[3]};
+                const bf16x4 Ka = to_bf16x4(Kv[0], Kv[1], Kv[2], Kv[3]);
                 if constexpr (CM == 1) {
                     if (ct < tcap)
                         __builtin_nontemporal_store(__builtin_bit_cast(uint64_t, Ka),
@@ -2338,11 +2350,11 @@ hipError_t launch_mrhs_lp_k(const DevTree &T, const DevOp &O, double *y, int nrh
 // v = hi + lo + O(2^-16 |v|) with hi, lo in BF16 (lo the BF16 rounding of v - hi)
 __device__ __forceinline__ void bf16_pair(const float (&v)[4], bf16x4 &hi, bf16x4 &lo)
 {
+    hi = to_bf16x4(v[0], v[1], v[2], v[3]);
+    float r[4];
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        hi[e] = (__bf16)v[e];
-        lo[e] = (__bf16)(v[e] - (float)hi[e]);
-    }
+    for (int e = 0; e < 4; ++e) r[e] = v[e] - (float)hi[e];
+    lo = to_bf16x4(r[0], r[1], r[2], r[3]);
 }
 
 template <int PREC>
