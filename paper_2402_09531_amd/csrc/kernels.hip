@@ -1869,14 +1869,15 @@ __device__ __forceinline__ bf16x4 to_bf16x4(float a, float b, float c, float d)
 // (2 li + 2 lg) and every charge read took two passes
 constexpr int kQtStride = kSymLeaf + 8;
 // BF16 mode's distances: each centred coordinate v (scaled by the operator's power of two, so
-// |v| <= 1) is split into FP16 parts h = fp16(v) and l = fp16(2^11 (v - h)), and the Gram sum is
-// formed on v_mfma_f32_16x16x32_f16 (FP32 accumulation) as sum h_x h_y + 2^-11 sum (h_x l_y + l_x h_y):
-// three MFMAs of 16 cycles per 16 x 16 tile for up to 32 dimensions, against d / 4 of 32 cycles on
-// v_mfma_f32_16x16x4f32.  The dropped terms are about 2^-22 |x_k y_k| each, far below the BF16
+// |v| <= 1) is split into FP16 parts h = fp16(v) and l = fp16(2^11 (v - h)), and 2^11 times the Gram
+// sum is formed on v_mfma_f32_16x16x32_f16 (FP32 accumulation) as sum h_x (2^11 h_y) + h_x l_y + l_x h_y
+// in one accumulator (2^11 h is exact in FP16): three MFMAs of 16 cycles per 16 x 16 tile for up to
+// 32 dimensions, against d / 4 of 32 cycles on v_mfma_f32_16x16x4f32.  The dropped terms are about 2^-22 |x_k y_k| each, far below the BF16
 // rounding of the kernel values; the low parts carry the 2^11 so that they stay in FP16's normal
 // range.  Sources sit in LDS in rows of kHS halves, the 32 high parts then the 32 low parts: the
-// 16-byte read of lane (li, lg) starts at word 36 li + 4 lg, and the 16 lanes of one lg cover the
-// 64 banks once.
+// 16-byte read of lane (li, lg) starts at word 36 li + 4 lg, so the 16 lanes of one lg cover the
+// 64 banks once (the counters still show about four conflict cycles per such read, some 2% of
+// the launch; two 8-byte reads at 36 li + 2 lg measured worse).
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 constexpr int kHS = 72;
 template <int DK, bool BF16>
@@ -1931,15 +1932,16 @@ __device__ __forceinline__ void apply_tiles(const uint2 (&pre)[8][2], flt4 (&Y)[
 
 // CM (BF16 only): 0 compute the kernel tiles, 1 compute them and also write them to `tiles`
 // (column tile ct of this call at tiles + ct * 512, at most `tcap` column tiles).
-// FP16 Gram (gram_f16): Th, Tl the targets' high and low parts (lane (li, lg): target 16 rt + li,
-// dimensions 8 lg ... 8 lg + 7), sXh the sources' rows; the exponent (split Gaussian) or r^2 is
-// then gA G_hh + gB G_cross + (snv, or |x|^2 + |y|^2).
+// FP16 Gram (gram_f16): Th, Tl the targets' high and low parts and Th2 = 2^11 Th (lane (li, lg):
+// target 16 rt + li, dimensions 8 lg ... 8 lg + 7), sXh the sources' rows; the exponent (split
+// Gaussian) or r^2 is then gA G + (snv, or |x|^2 + |y|^2) with G = 2^11 times the Gram sum.
 template <int KIND, int DK, int RB, bool BF16, bool DIAG, int CM = 0>
 __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], const float (&tn)[2], flt4 (&Y)[2][RB],
                                               const float *sX, const float *sN, const float *sQ, const __bf16 *sQt,
                                               int ns, int ntiles, int w, int li, int lg, float inv_ell,
-                                              const f16x8 (&Th)[2], const f16x8 (&Tl)[2], const _Float16 *sXh,
-                                              float gA, float gB, uint2 *tiles = nullptr, int64_t tcap = 0)
+                                              const f16x8 (&Th)[2], const f16x8 (&Tl)[2], const f16x8 (&Th2)[2],
+                                              const _Float16 *sXh, float gA, uint2 *tiles = nullptr,
+                                              int64_t tcap = 0)
 {
     static_assert(CM == 0 || (CM == 1 && BF16), "the tile cache holds BF16 tiles");
     constexpr int NKC = DK / 4;
@@ -1971,13 +1973,13 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
             if (rt[u] >= ntiles) continue;
             // split Gaussian as in the FP64 kernel: the chain starts from the sources' base-2 column
             // factors and delivers the entry's exponent but for the row factor
-            flt4 G, C;
+            flt4 G;
             if constexpr (kH) {
+                // the small cross terms first, then the high parts' product
                 G = flt4{0.0f, 0.0f, 0.0f, 0.0f};
-                C = flt4{0.0f, 0.0f, 0.0f, 0.0f};
-                C = __builtin_amdgcn_mfma_f32_16x16x32_f16(Al, Th[u], C, 0, 0, 0);
-                C = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Tl[u], C, 0, 0, 0);
-                G = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Th[u], G, 0, 0, 0);
+                G = __builtin_amdgcn_mfma_f32_16x16x32_f16(Al, Th[u], G, 0, 0, 0);
+                G = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Tl[u], G, 0, 0, 0);
+                G = __builtin_amdgcn_mfma_f32_16x16x32_f16(Ah, Th2[u], G, 0, 0, 0);
             } else {
                 if constexpr (KIND == kGaussSplit)
                     G = flt4{snv[0], snv[1], snv[2], snv[3]};
@@ -1990,9 +1992,9 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
                 if constexpr (KIND == kGaussSplit) {
-                    Kv[e] = __builtin_amdgcn_exp2f(kH ? fmaf(gA, G[e], fmaf(gB, C[e], snv[e])) : G[e]);
+                    Kv[e] = __builtin_amdgcn_exp2f(kH ? fmaf(gA, G[e], snv[e]) : G[e]);
                 } else {
-                    float r2 = kH ? fmaf(gA, G[e], fmaf(gB, C[e], tn[u] + snv[e])) : fmaf(-2.0f, G[e], tn[u] + snv[e]);
+                    float r2 = fmaf(kH ? gA : -2.0f, G[e], tn[u] + snv[e]);
                     r2 = fmaxf(r2, 0.0f);
                     if constexpr (DIAG) {
                         if (16 * rt[u] + li == 16 * ct + 4 * lg + e) r2 = 0.0f;
@@ -2063,12 +2065,11 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
     __syncthreads();
     const int rt[2] = {w, w + 4};
     float Bt[2][NKC], tn[2];
-    f16x8 Th[2], Tl[2];
+    f16x8 Th[2], Tl[2], Th2[2];
     flt4 Y[2][RB];
-    // FP16 Gram: the coordinates' power-of-two scale and the factors of its two sums
+    // FP16 Gram: the coordinates' power-of-two scale and the factor of its sum (which carries 2^11)
     const float hs = O.hscale;
-    const float gA = kSplit ? (float)(2.0 * 1.4426950408889634 / O.ell) / (hs * hs) : -2.0f / (hs * hs);
-    const float gB = gA * 0x1p-11f;
+    const float gA = (kSplit ? (float)(2.0 * 1.4426950408889634 / O.ell) / (hs * hs) : -2.0f / (hs * hs)) * 0x1p-11f;
 #pragma unroll
     for (int u = 0; u < 2; ++u) {
         const int i = 16 * rt[u] + li;
@@ -2088,6 +2089,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
                 const float v = k < DK ? (float)(T.Xs[(size_t)k * n + ii] - cen[k]) * hs : 0.0f;
                 const _Float16 h = (_Float16)v;
                 Th[u][e] = h;
+                Th2[u][e] = (_Float16)((float)h * 2048.0f);
                 Tl[u][e] = (_Float16)((v - (float)h) * 2048.0f);
             }
         } else {
@@ -2203,7 +2205,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
                 apply_tiles<RB>(pre, Y, sQt, nt, ntiles, w, li, lg);
             } else {
                 mrhs_block_lp<KIND, DK, RB, BF16, true, CM>(Bt, tn, Y, sX, sN, sQ, sQt, nt, ntiles, w, li, lg, inv_ell,
-                                                           Th, Tl, sXh, gA, gB, ltiles + tb * 512, lcount - tb);
+                                                           Th, Tl, Th2, sXh, gA, ltiles + tb * 512, lcount - tb);
             }
             tb += (nt + 15) / 16;
         }
@@ -2257,7 +2259,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
                     apply_tiles<RB>(pre, Y, sQt, ns, ntiles, w, li, lg);
                 } else {
                     mrhs_block_lp<KIND, DK, RB, BF16, false, CM>(Bt, tn, Y, sX, sN, sQ, sQt, ns, ntiles, w, li, lg,
-                                                                inv_ell, Th, Tl, sXh, gA, gB, ltiles + tb * 512,
+                                                                inv_ell, Th, Tl, Th2, sXh, gA, ltiles + tb * 512,
                                                                 lcount - tb);
                 }
                 tb += (ns + 15) / 16;
