@@ -1428,7 +1428,9 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
             for (int c0 = 0; c0 < total; c0 += kSymLeaf, ++chunk) {
                 const int ns = min(kSymLeaf, total - c0);
                 const int sid = tid ^ ((chunk & 1) << 7);
-                __syncthreads();  // the previous chunk's tiles are consumed
+                // no barrier here: the search writes only colP, which the previous chunk's tiles do not
+                // read (its staging, which does, ended at the barrier before them), and the barrier after
+                // the search keeps this chunk's staging behind every wave's previous tiles
                 if (sid < kSymLeaf) {
                     int pidx = cb;  // any valid point for the padding columns
                     if (sid < ns) {
@@ -2237,7 +2239,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
                 const int ns = min(kSymLeaf, total - c0);
                 const int sid = tid ^ ((chunk & 1) << 7);
                 if constexpr (CM == 2) load_tiles(pre, ltiles + tb * 512, lcount - tb, ns, ntiles, w, lane);
-                __syncthreads();
+                // no barrier here, as in the FP64 kernel: the search writes only colP, which the previous
+                // chunk's tiles do not read
                 if (sid < kSymLeaf) {
                     int pidx = cb;
                     if (sid < ns) {
