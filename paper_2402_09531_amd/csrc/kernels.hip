@@ -765,12 +765,14 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
 {
     constexpr int NKC = DK / 4;
     __shared__ double sX[DK * kSymLeaf];  // [k][j] shifted source coordinates
-    __shared__ double sN[kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf], tQ[kSymLeaf];
+    // sN, colF and colJ alternate between two halves from chunk to chunk (nb): the column sums of one
+    // chunk read them while the next chunk's staging writes the other half
+    __shared__ double sN[2 * kSymLeaf], sQ[kSymLeaf], tN[kSymLeaf], tQ[kSymLeaf];
     __shared__ double colpart[4 * kSymLeaf];
     __shared__ double cen[DK];
     __shared__ int32_t sPre[kSymSeg + 1], sBlk[kSymSeg];  // owned-block segment: size prefix, block ids
     __shared__ int32_t sBeg[kSymSeg];                     // first source point of each block
-    __shared__ int32_t colF[kSymLeaf], colJ[kSymLeaf];    // block and point of each stream column
+    __shared__ int32_t colF[2 * kSymLeaf], colJ[2 * kSymLeaf];  // block and point of each stream column
     __shared__ int32_t sDiag;                             // the leaf owns its self block
 
     const int c = T.leaf_first + l;
@@ -860,6 +862,7 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
             racc[u][v] = 0.0;
         }
 
+    int nb = 0;  // the half of sN, colF and colJ this chunk uses
     // Column j of the tile arrays: point pidx shifted to the owner's midpoint, its squared norm
     // (split Gaussian: its column factor) and its charge; columns past the data are zero.
     auto stage = [&](int j, int pidx, bool ok) {
@@ -876,10 +879,10 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         const double q = O.xt[pidx];
         if constexpr (KIND == kGaussSplit) {
             const double bfac = exp_bounded(-s * inv_ell);  // column factor
-            sN[j] = bfac;
+            sN[nb + j] = bfac;
             sQ[j] = ok ? q * bfac : 0.0;
         } else {
-            sN[j] = s;
+            sN[nb + j] = s;
             sQ[j] = ok ? q : 0.0;
             if (nk) {
                 sX[T.d * kSymLeaf + j] = 1.0;
@@ -892,11 +895,11 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         constexpr bool D = decltype(diag)::value;
         if constexpr (KIND != kGaussSplit) {
             if (nk) {
-                sym_block<KIND, NKC, D, true>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
+                sym_block<KIND, NKC, D, true>(A, rN, rQ, racc, sX, sN + nb, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
                 return;
             }
         }
-        sym_block<KIND, NKC, D, false>(A, rN, rQ, racc, sX, sN, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
+        sym_block<KIND, NKC, D, false>(A, rN, rQ, racc, sX, sN + nb, sQ, colpart, ns, ntiles, w, li, lg, inv_ell);
     };
     // 1) the leaf with itself (sDiag was set before the barrier that precedes rN)
     if (sDiag) {
@@ -938,7 +941,10 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
         for (int c0 = 0; c0 < total; c0 += kSymLeaf, ++chunk) {
             const int ns = min(kSymLeaf, total - c0);
             const int sid = tid ^ ((chunk & 1) << 7);
-            __syncthreads();  // the previous chunk's tiles and column sums are consumed
+            // no barrier here: the previous chunk's tiles ended at the barrier before its column sums,
+            // which read only colpart and the other half of sN, colF and colJ; the barrier after this
+            // staging keeps the next tiles (and colpart) behind every wave's column sums
+            nb = (chunk & 1) * kSymLeaf;
             if (sid < kSymLeaf) {
                 const int j = sid;
                 const bool ok = j < ns;
@@ -958,8 +964,8 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
                     pidx = sBeg[lo] + jl;  // from LDS: only the coordinates are loaded from memory
                 }
                 stage(j, pidx, ok);
-                colF[j] = fblk;
-                colJ[j] = jl;
+                colF[nb + j] = fblk;
+                colJ[nb + j] = jl;
             }
             __syncthreads();
             block(std::false_type{}, ns);
@@ -967,8 +973,8 @@ __device__ __forceinline__ void p2p_sym_body(const DevTree &T, const DevOp &O, i
             if (sid < ns) {
                 double cs = ((colpart[sid] + colpart[kSymLeaf + sid]) + colpart[2 * kSymLeaf + sid]) +
                             colpart[3 * kSymLeaf + sid];
-                if constexpr (KIND == kGaussSplit) cs *= sN[sid];
-                O.colbuf[(size_t)colF[sid] * kSymLeaf + colJ[sid]] = cs;
+                if constexpr (KIND == kGaussSplit) cs *= sN[nb + sid];
+                O.colbuf[(size_t)colF[nb + sid] * kSymLeaf + colJ[nb + sid]] = cs;
             }
         }
     }
