@@ -1549,16 +1549,24 @@ __global__ __launch_bounds__(kSymLeaf) void p2p_combine_kernel(DevTree T, DevOp 
 
 // Farfield evaluation (L2P) added to a several-rhs nearfield result that was computed beside the
 // farfield: y[perm i][r] += sum_a l_a(x_i) L_c[a][r] for the points i of leaf blockIdx.x (the sum
-// over a formed first, in order, then added once).
+// over a formed first, in order, then added once).  The leaf's locals sit in LDS (nx * nrhs
+// doubles, dynamic); thread t keeps rhs t mod nrhs and walks the points t / nrhs, t / nrhs + per,
+// ... (per = 256 / nrhs), so the nrhs threads of a point read one basis value and write one row.
 __global__ __launch_bounds__(256) void l2p_add_kernel(DevTree T, DevOp O, double *__restrict__ y, int nrhs)
 {
+    extern __shared__ double sL[];  // [nx][nrhs]
     const int c = T.leaf_first + blockIdx.x;
     const int cb = T.cbeg[c], nt = T.cend[c] - cb;
-    const double *lc = O.L + (size_t)c * O.nx * nrhs;
-    for (int e = threadIdx.x; e < nt * nrhs; e += blockDim.x) {
-        const int i = e / nrhs, r = e % nrhs;
+    const int nx = O.nx;
+    const double *lc = O.L + (size_t)c * nx * nrhs;
+    for (int e = threadIdx.x; e < nx * nrhs; e += blockDim.x) sL[e] = lc[e];
+    __syncthreads();
+    const int per = blockDim.x / nrhs;
+    const int r = threadIdx.x % nrhs, i0 = threadIdx.x / nrhs;
+    if (i0 >= per) return;  // (no barrier follows)
+    for (int i = i0; i < nt; i += per) {
         double acc = 0.0;
-        for (int a = 0; a < O.nx; ++a) acc = fma(O.Lb[(size_t)a * T.n + cb + i], lc[a * nrhs + r], acc);
+        for (int a = 0; a < nx; ++a) acc = fma(O.Lb[(size_t)a * T.n + cb + i], sL[a * nrhs + r], acc);
         y[(size_t)T.perm[cb + i] * nrhs + r] += acc;
     }
 }
@@ -3221,7 +3229,7 @@ hipError_t launch_matvec(const DevTree &T, const DevOp &O, const double *x, doub
         if (timer) (void)hipEventRecord(timer->p2p_stop, st);
         if (e != hipSuccess || !split) return e;
         if ((e = hipStreamWaitEvent(st, fork->joined, 0)) != hipSuccess) return e;
-        hipLaunchKernelGGL(l2p_add_kernel, dim3(T.nleaf), dim3(256), 0, st, T, O, y, nrhs);
+        hipLaunchKernelGGL(l2p_add_kernel, dim3(T.nleaf), dim3(256), sizeof(double) * O.nx * nrhs, st, T, O, y, nrhs);
         return hipGetLastError();
     }
     switch (O.kind) {
