@@ -412,9 +412,11 @@ dwfmm_status dwfmm_tree_leaf_order(dwfmm_tree tree, int32_t *order, double *work
  * CSR by target cluster Nptr[ncl+1], Nsrc[nN].  Any pointer may be NULL.      */
 dwfmm_status dwfmm_tree_get(dwfmm_tree tree, int64_t *perm, int64_t *begin, int64_t *end, double *lo, double *hi,
                             int64_t *Fptr, int64_t *Fsrc, int64_t *Nptr, int64_t *Nsrc);
-/* out[0..5] = n_x, max_nrhs, precision, bytes, then 1 when the FP64 Gaussian nearfield runs
+/* out[0..6] = n_x, max_nrhs, precision, bytes, then 1 when the FP64 Gaussian nearfield runs
  * split into row, column and cross factors (every nearfield exponent bounded by 600), and 1
- * when the FP32/BF16 one does (bounded by 80); else 0.  out: host, 6 values. */
+ * when the FP32/BF16 one does (bounded by 80), else 0; then the stored nearfield tiles
+ * (cache_near): 0 none, 1 allocated and not yet written (the next eager BF16 matvec with
+ * nrhs > 1 writes them), 2 written (later ones read them).  out: host, 7 values. */
 dwfmm_status dwfmm_op_info(dwfmm_op op, int64_t *out);
 /* Index set alpha[n_x*d] (uint8), reference nodes xi[n_x*d], Vinv[n_x*n_x], omega[d]. */
 dwfmm_status dwfmm_op_basis(dwfmm_op op, uint8_t *alpha, double *xi, double *Vinv, double *omega);

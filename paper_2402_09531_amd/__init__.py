@@ -258,9 +258,16 @@ class Op:
     def __init__(self, handle, tree: Tree):
         self._h = handle
         self.tree = tree
-        info = np.zeros(6, dtype=np.int64)
+        info = np.zeros(7, dtype=np.int64)
         _check(lib().dwfmm_op_info(self._h, _i64(info)))
-        self.nx, self.max_nrhs, self.precision, self.bytes, self.gauss_split, self.gauss_split32 = (int(v) for v in info)
+        self.nx, self.max_nrhs, self.precision, self.bytes, self.gauss_split, self.gauss_split32 = (int(v) for v in info[:6])
+
+    @property
+    def near_tiles_state(self) -> int:
+        """dwfmm_op_info's tile-cache state: 0 none, 1 allocated and unwritten, 2 written."""
+        info = np.zeros(7, dtype=np.int64)
+        _check(lib().dwfmm_op_info(self._h, _i64(info)))
+        return int(info[6])
 
     def basis(self):
         d = self.tree.d

@@ -2765,6 +2765,7 @@ extern "C" dwfmm_status dwfmm_op_info(dwfmm_op op, int64_t *out)
     out[3] = (int64_t)dwfmm_op_bytes(op);
     out[4] = op->D.gauss_split;
     out[5] = op->D.gauss_split32;
+    out[6] = !op->D.near_tiles ? 0 : op->near_filled ? 2 : 1;
     return DWFMM_OK;
 }
 

@@ -55,12 +55,14 @@ def test_cached_matvecs_bitwise_equal(name):
     _, op1, _ = setup(name, True)
     assert op1.bytes > op0.bytes
     assert op1.bytes == dw.op_bytes_for(op1.tree, GEOM[name][5], precision="bf16", max_nrhs=32, cache_near=True)
+    assert op0.near_tiles_state == 0 and op1.near_tiles_state == 1
     rng = np.random.default_rng(5)
     for nrhs in (32, 5, 17):
         x = torch.from_numpy(rng.standard_normal((n, nrhs))).cuda()
         y0 = mv(op0, x)
         for rep in range(2):   # the first 32-rhs call writes the tiles, every later one reads them
             y1 = mv(op1, x)
+            assert op1.near_tiles_state == 2
             say(f"[tile cache] {name} nrhs {nrhs} call {rep}: max |diff| {np.abs(y1 - y0).max():.3e}")
             assert np.array_equal(y1, y0)
 
@@ -80,7 +82,9 @@ def test_graph_capture_and_solve_with_cache():
         g.replay()
         torch.cuda.synchronize()
         assert np.array_equal(y.cpu().numpy(), y0)
+    assert op1.near_tiles_state == 1        # the captured launches did not write the tiles
     assert np.array_equal(mv(op1, x), y0)   # eager: writes the tiles
+    assert op1.near_tiles_state == 2
     assert np.array_equal(mv(op1, x), y0)   # reads them
     f = torch.from_numpy(np.sin(rng.random((n, 8)).sum(1, keepdims=True) + np.arange(8))).cuda().contiguous()
     a0, a1 = torch.zeros_like(f), torch.zeros_like(f)
