@@ -1879,23 +1879,25 @@ __device__ __forceinline__ bf16x4 to_bf16x4(float a, float b, float c, float d)
     const uint32_t hi = __builtin_bit_cast(uint32_t, __builtin_convertvector(flt2v{c, d}, bf16x2));
     return __builtin_bit_cast(bf16x4, u32x2{lo, hi});
 }
-// bf16 charges stored [rhs][source] in rows of 136 elements (68 words): an 8-byte read of lane
-// (li, lg) starts at word 68 li + 2 lg (+ a constant) and the 32 lanes lg < 2 (lg >= 2) start at
-// 4 li + 2 lg mod 64, on 64 different banks; with 132-element rows the two lane groups overlapped
-// (2 li + 2 lg) and every charge read took two passes
-constexpr int kQtStride = kSymLeaf + 8;
+// BF16 charges in the order the apply MFMA takes them: for column tile ct and rhs tile rb, lane
+// li + 16 lg's four values (sources 16 ct + 4 lg ... + 3 of rhs 16 rb + li) at halves
+// qt_slot = 4 (64 (RB ct + rb) + li + 16 lg): a wave reads 512 bytes in order, and a half-wave of
+// the staging (16 rhs x 2 column groups) writes 256 bytes in order.  (Rows of 136 halves per rhs,
+// read at words 68 li + 2 lg, still showed conflicts on about a sixth of the LDS cycles.)
+template <int RB>
+__device__ __forceinline__ int qt_slot(int ct, int rb, int lane) { return 4 * (64 * (RB * ct + rb) + lane); }
 // BF16 mode's distances: each centred coordinate v (scaled by the operator's power of two, so
 // |v| <= 1) is split into FP16 parts h = fp16(v) and l = fp16(2^11 (v - h)), and 2^11 times the Gram
 // sum is formed on v_mfma_f32_16x16x32_f16 (FP32 accumulation) as sum h_x (2^11 h_y) + h_x l_y + l_x h_y
 // in one accumulator (2^11 h is exact in FP16): three MFMAs of 16 cycles per 16 x 16 tile for up to
 // 32 dimensions, against d / 4 of 32 cycles on v_mfma_f32_16x16x4f32.  The dropped terms are about 2^-22 |x_k y_k| each, far below the BF16
 // rounding of the kernel values; the low parts carry the 2^11 so that they stay in FP16's normal
-// range.  Sources sit in LDS in rows of kHS halves, the 32 high parts then the 32 low parts: the
-// 16-byte read of lane (li, lg) starts at word 36 li + 4 lg, so the 16 lanes of one lg cover the
-// 64 banks once (the counters still show about four conflict cycles per such read, some 2% of
-// the launch; two 8-byte reads at 36 li + 2 lg measured worse).
+// range.  Sources sit in LDS in the order the MFMA takes them: for part p (0 high, 1 low) and
+// column tile ct, lane li + 16 lg's eight values (source 16 ct + li, dimensions 8 lg ... 8 lg + 7)
+// at halves 8 (64 (8 p + ct) + li + 16 lg), so a wave reads 1 KiB in order.  (Rows of 72 halves per
+// column, read at words 36 li + 4 lg, showed LDS bank conflicts on most of their 16-byte reads.)
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
-constexpr int kHS = 72;
+__device__ __forceinline__ int gram_slot(int part, int ct, int lane) { return 8 * (64 * (8 * part + ct) + lane); }
 template <int DK, bool BF16>
 constexpr bool gram_f16() { return BF16 && DK >= 8; }
 // FP32 charges stored [source][rhs]; rows of 16 RB + 4 floats put consecutive lane groups on
@@ -1935,7 +1937,7 @@ __device__ __forceinline__ void apply_tiles(const uint2 (&pre)[8][2], flt4 (&Y)[
         bf16x4 Qb[RB];
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
-            Qb[rb] = *reinterpret_cast<const bf16x4 *>(&sQt[(16 * rb + li) * kQtStride + 16 * ct + 4 * lg]);
+            Qb[rb] = *reinterpret_cast<const bf16x4 *>(&sQt[qt_slot<RB>(ct, rb, li + 16 * lg)]);
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (w + 4 * u >= ntiles) continue;
@@ -1969,8 +1971,8 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
         float Af[kH ? 1 : NKC], snv[4];
         f16x8 Ah, Al;
         if constexpr (kH) {
-            Ah = *reinterpret_cast<const f16x8 *>(&sXh[(16 * ct + li) * kHS + 8 * lg]);
-            Al = *reinterpret_cast<const f16x8 *>(&sXh[(16 * ct + li) * kHS + 32 + 8 * lg]);
+            Ah = *reinterpret_cast<const f16x8 *>(&sXh[gram_slot(0, ct, lane)]);
+            Al = *reinterpret_cast<const f16x8 *>(&sXh[gram_slot(1, ct, lane)]);
         } else {
 #pragma unroll
             for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSX32 + 16 * ct + li];
@@ -1982,7 +1984,7 @@ __device__ __forceinline__ void mrhs_block_lp(const float (&Bt)[2][DK / 4], cons
         if constexpr (BF16) {
 #pragma unroll
             for (int rb = 0; rb < RB; ++rb)
-                Qb[rb] = *reinterpret_cast<const bf16x4 *>(&sQt[(16 * rb + li) * kQtStride + 16 * ct + 4 * lg]);
+                Qb[rb] = *reinterpret_cast<const bf16x4 *>(&sQt[qt_slot<RB>(ct, rb, li + 16 * lg)]);
         }
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
@@ -2050,10 +2052,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
     constexpr bool kH = gram_f16<DK, BF16>();
     // (reading stored tiles stages no coordinates)
     __shared__ float sX[kH || CM == 2 ? 1 : DK * kSX32];
-    __shared__ __attribute__((aligned(16))) _Float16 sXh[kH && CM != 2 ? kSymLeaf * kHS : 8];
+    __shared__ __attribute__((aligned(16))) _Float16 sXh[kH && CM != 2 ? 2 * kSymLeaf * 32 : 8];
     __shared__ float sN[kSymLeaf];
     __shared__ float sQ[BF16 ? 1 : kSymLeaf * q_stride32<RB>()];
-    __shared__ __attribute__((aligned(16))) __bf16 sQt[BF16 ? 16 * RB * kQtStride : 8];
+    __shared__ __attribute__((aligned(16))) __bf16 sQt[BF16 ? 16 * RB * kSymLeaf : 8];
     __shared__ double cen[DK];
     __shared__ int32_t sPre[kSymSeg + 1], sBeg[kSymSeg], colP[kSymLeaf], sDiag;
     constexpr bool kSplit = KIND == kGaussSplit;
@@ -2168,8 +2170,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
                             hv[e] = h;
                             lv[e] = (_Float16)((v - (float)h) * 2048.0f);
                         }
-                        *reinterpret_cast<f16x8 *>(&sXh[j * kHS + 8 * q]) = hv;
-                        *reinterpret_cast<f16x8 *>(&sXh[j * kHS + 32 + 8 * q]) = lv;
+                        *reinterpret_cast<f16x8 *>(&sXh[gram_slot(0, j >> 4, (j & 15) + 16 * q)]) = hv;
+                        *reinterpret_cast<f16x8 *>(&sXh[gram_slot(1, j >> 4, (j & 15) + 16 * q)]) = lv;
                     }
                 }
                 // split Gaussian: the base-2 logarithm of the column factor exp(-|y - c|^2 / ell)
@@ -2177,8 +2179,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
             }
             // as in the FP64 kernel: every charge load of the thread issued before the first store
             constexpr int QPT = kSymLeaf * 16 * RB / 256, G = 256 / (16 * RB);
-            // FP32: r = tid mod 16 RB.  BF16 (the 8-byte transposed stores): a half-wave takes 16
-            // rhs x 2 column groups, so its stores start at words 68 r + 2 jl, on 64 different banks
+            // FP32: r = tid mod 16 RB.  BF16 (the 8-byte stores in the apply's order): a half-wave
+            // takes 16 rhs x 2 neighbouring column groups, 32 consecutive slots
             const int r = BF16 ? (tid & 15) + 16 * ((tid >> 5) % RB) : tid % (16 * RB);
             const int j0 = BF16 ? (((tid >> 5) / RB) << 1) + ((tid >> 4) & 1) : tid / (16 * RB);
             const int rr = r < nrhs ? r : 0;
@@ -2198,7 +2200,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CM == 2 && 
                     bf16x4 v;
 #pragma unroll
                     for (int e = 0; e < 4; ++e) v[e] = (j + e < ns && r < nrhs) ? qb[4 * t + e] : (__bf16)0.0f;
-                    *reinterpret_cast<bf16x4 *>(&sQt[r * kQtStride + j]) = v;
+                    *reinterpret_cast<bf16x4 *>(&sQt[qt_slot<RB>(j >> 4, r >> 4, (r & 15) + 16 * ((j & 15) >> 2))]) = v;
                 }
             } else {
                 double qv[QPT];
