@@ -67,7 +67,9 @@ typedef enum { DWFMM_W_R1 = 0, DWFMM_W_R2 = 1, DWFMM_W_R3 = 2, DWFMM_W_EXPLICIT 
  *   BF16  FP32 mode, and with several rhs the products on BF16 MFMA with FP32
  *         accumulation: the nearfield K Q with K and Q rounded to BF16, the
  *         coupling S m with S and m each carried as a pair of BF16 numbers
- *         (three products); with one rhs it is FP32 mode                    */
+ *         (three products); the nearfield's distances (d >= 5) on FP16 MFMA
+ *         from coordinates split into FP16 high and low parts (three
+ *         products, about 2^-22 of each term); with one rhs it is FP32 mode  */
 typedef enum { DWFMM_FP64 = 0, DWFMM_FP32 = 1, DWFMM_BF16 = 2 } dwfmm_precision;
 
 /* Interpolation nodes on the reference box (Sec 5.4 and the per-axis reading):
