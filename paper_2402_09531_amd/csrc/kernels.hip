@@ -1238,8 +1238,15 @@ hipError_t launch_cross_mfma_k(const DevTree &Tt, const DevOp &Ot, const DevTree
 // 16-wide rhs tiles.  L2P and the scatter to caller order are fused at the end.  The split
 // Gaussian variant (KIND kGaussSplit) starts each Gram chain from the sources' base-2 column
 // factors and scales the finished sums by the targets' row factors.
+// Staged charges [j][r] in rows of 16 RB doubles; with two rhs tiles the odd rows swap their
+// halves (r ^ 16), so that the two lane groups of a half-wave (rows j and j + 1 of a tile
+// column) read opposite halves of the 64 banks.  Coordinates [k][j] in rows of kSX64 doubles,
+// 16 past the leaf size for the same reason.
 template <int RB>
-constexpr int q_stride() { return 16 * RB + 1; }  // padded row of the staged charges
+constexpr int q_stride() { return 16 * RB; }
+template <int RB>
+__device__ __forceinline__ int q_col(int j, int r) { return RB == 2 ? r ^ ((j & 1) << 4) : r; }
+constexpr int kSX64 = kSymLeaf + 16;
 
 template <int KIND, int DK, int RB, bool DIAG>
 __device__ __forceinline__ void mrhs_block(const double (&Bt)[2][DK / 4], const double (&tn)[2], dbl4 (&Y)[2][RB],
@@ -1252,7 +1259,7 @@ __device__ __forceinline__ void mrhs_block(const double (&Bt)[2][DK / 4], const 
     for (int ct = 0; ct < nct; ++ct) {
         double Af[NKC];
 #pragma unroll
-        for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSymLeaf + 16 * ct + li];
+        for (int kc = 0; kc < NKC; ++kc) Af[kc] = sX[(4 * kc + lg) * kSX64 + 16 * ct + li];
         double snv[4];
 #pragma unroll
         for (int v = 0; v < 4; ++v) snv[v] = sN[16 * ct + 4 * v + lg];
@@ -1260,7 +1267,8 @@ __device__ __forceinline__ void mrhs_block(const double (&Bt)[2][DK / 4], const 
 #pragma unroll
         for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-            for (int v = 0; v < 4; ++v) Qf[rb][v] = sQ[(16 * ct + 4 * v + lg) * q_stride<RB>() + 16 * rb + li];
+            for (int v = 0; v < 4; ++v)
+                Qf[rb][v] = sQ[(16 * ct + 4 * v + lg) * q_stride<RB>() + q_col<RB>(lg, 16 * rb + li)];
 #pragma unroll
         for (int u = 0; u < 2; ++u) {
             if (rt[u] >= ntiles) continue;  // uniform over the wave
@@ -1300,7 +1308,7 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
                                                        int do_near, int do_far)
 {
     constexpr int NKC = DK / 4;
-    __shared__ double sX[DK * kSymLeaf];
+    __shared__ double sX[DK * kSX64];
     __shared__ double sN[kSymLeaf];
     __shared__ double sQ[kSymLeaf * q_stride<RB>()];
     __shared__ double cen[DK];
@@ -1380,7 +1388,7 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
 #pragma unroll
                 for (int k = 0; k < DK; ++k) {
                     const double v = ok ? xv[k] - cen[k] : 0.0;
-                    sX[k * kSymLeaf + j] = v;
+                    sX[k * kSX64 + j] = v;
                     s = fma(v, v, s);
                 }
                 // split Gaussian: the base-2 logarithm of the column factor exp(-|y - c|^2 / ell)
@@ -1397,7 +1405,7 @@ __global__ __launch_bounds__(256) void p2p_mrhs_kernel(DevTree T, DevOp O, doubl
 #pragma unroll
             for (int t = 0; t < QPT; ++t) {
                 const int j = j0 + t * (256 / (16 * RB));
-                sQ[j * q_stride<RB>() + r] = (j < ns && r < nrhs) ? qv[t] : 0.0;
+                sQ[j * q_stride<RB>() + q_col<RB>(j, r)] = (j < ns && r < nrhs) ? qv[t] : 0.0;
             }
         };
         if (sDiag) {
